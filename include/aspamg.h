@@ -1,0 +1,207 @@
+/*
+ * aspamg.h -- C ABI of the MI355X aSP-AMG solver library (libaspamg.so).
+ *
+ * Solves K u = f for a symmetric positive definite elasticity stiffness matrix
+ * K given as 3x3-block CSR (the problem statement of the paper, Section 1,
+ * eq. (1): K from the integral of B^T D B over the elements) with PCG
+ * preconditioned by one aSP-AMG V(nu1,nu2)-cycle (Section 2, Algorithms
+ * "Recursive AMG Setup" and "AMG application in a V-cycle"; Section 3 for the
+ * aFSAI smoother, the test space, the affinity coarsening and the DPLS
+ * prolongation; Section 4 for the PCG start and stopping rule).
+ *
+ * Conventions shared by every entry point
+ *   - DOF index = 3 * node + component.  Vectors are float64, node-major.
+ *   - Block matrices: row_ptr int32 [n+1], col int32 [nnzb] sorted ascending in
+ *     each row, vals float64 [nnzb][3][3] row-major blocks.
+ *   - A block row holding only its diagonal block is a constrained (Dirichlet)
+ *     or decoupled node: it is never coarse and gets no interpolation.
+ *   - All device work runs on the HIP stream given to aspamg_setup.
+ *   - Every call returns aspamg_status; negative values are errors, positive
+ *     values are warnings with valid outputs.  No C++ exception crosses the ABI.
+ *     aspamg_last_error() returns a message for the last failing call of the
+ *     calling thread.
+ *   - A handle must not be used from two threads at once.
+ */
+#ifndef ASPAMG_H
+#define ASPAMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ASPAMG_OK = 0,
+  ASPAMG_NOT_CONVERGED = 1, /* warning: u holds the last iterate, stats are filled */
+  ASPAMG_EINVAL = -1,       /* bad argument or unsupported input                    */
+  ASPAMG_ENOMEM = -2,       /* host or device allocation failed                     */
+  ASPAMG_EHIP = -3,         /* a HIP runtime call failed                            */
+  ASPAMG_ENOT_SPD = -4,     /* a local FSAI system or the coarsest matrix has a pivot <= 0 */
+  ASPAMG_EBREAKDOWN = -5,   /* PCG: p.q <= 0 or r.z <= 0 (indefinite preconditioner) */
+  ASPAMG_ENAN = -6          /* non-finite residual                                  */
+} aspamg_status;
+
+typedef struct aspamg_ctx *aspamg_handle;   /* opaque; owns all hierarchy memory */
+
+/* Setup and solve parameters.  The first eight are the paper's user parameters
+ * (Table "Default input parameters"); the rest fix values the paper leaves
+ * open.  aspamg_default_params() fills the defaults noted on each line. */
+typedef struct {
+  int32_t k_g;            /* 4     adaptive FSAI steps per row                          */
+  int32_t rho_g;          /* 4     paper: scalar entries per step (informational)      */
+  double  eps_g;          /* 1e-3  FSAI exit tolerance on the relative decrease of psi */
+  int32_t n_tv;           /* 6     test vectors (the six rigid-body modes)              */
+  int32_t n_rq;           /* 0     test-space smoothing iterations (not applied)        */
+  int32_t theta;          /* 5     strong connections kept per node                     */
+  int32_t n_max;          /* 5     max interpolation entries per scalar row (<= 8)      */
+  double  kappa_p;        /* 50    max conditioning of a local least-squares fit        */
+  int32_t rho_blocks;     /* 3     nodes added to an FSAI row per step                  */
+  double  omega_bar;      /* 0.8   aFSAI outer loop target for omega = 2/lambda_1       */
+  int32_t outer_fsai;     /* 1     run the aFSAI outer loop                             */
+  int32_t d_p;            /* 2     max S-path length to interpolating coarse nodes      */
+  double  eps_p;          /* 1e-8  relative least-squares residual tolerance            */
+  int32_t lanczos_steps;  /* 30    Lanczos steps for lambda_1(G A G^T)                  */
+  double  omega_safety;   /* 1.05  applied omega = min(1, 2 / (safety * lambda_1))      */
+  int32_t coarse_max_dof; /* 1500  factor densely once 3 N_l <= this                    */
+  int32_t max_levels;     /* 25                                                         */
+  double  stall_ratio;    /* 0.9   stop coarsening when N_{l+1} > ratio * N_l           */
+  int32_t nu1, nu2;       /* 1, 1  pre- and post-smoothing steps                        */
+  int32_t cycle_precision;/* 64    64: FP64 V-cycle; 32: FP32 V-cycle inside FP64 PCG   */
+  double  rtol;           /* 1e-10 stop when ||r_k|| <= rtol ||f||                       */
+  int32_t max_it;         /* 1000                                                       */
+  int32_t quant_bits;     /* 20    significant bits of quantised decision quantities    */
+  int32_t dense_max_dof;  /* 16384 refuse a larger dense coarsest system                */
+  int32_t check_every;    /* 4     PCG iterations per host convergence poll             */
+  int32_t use_graph;      /* 1     replay the PCG iteration as a captured HIP graph     */
+} aspamg_params;
+
+typedef struct {
+  int32_t status;           /* aspamg_status of the solve                             */
+  int32_t iterations;       /* PCG iterations (products with K)                       */
+  int32_t levels;           /* levels of the hierarchy                                */
+  int32_t cycle_precision;  /* 64 or 32                                               */
+  double  relres_recursive; /* ||r_k|| / ||f|| from the recurrence                     */
+  double  relres_true;      /* ||f - K u|| / ||f|| recomputed at the end               */
+  double  t_setup_s;        /* setup wall time                                        */
+  double  t_solve_s;        /* solve time, HIP events on the handle's stream          */
+  double  c_gd, c_op, c_fs; /* grid, operator and FSAI complexities                   */
+  double  bytes_vcycle;     /* algorithmic HBM bytes of one V-cycle                   */
+  double  bytes_iter;       /* algorithmic HBM bytes of one PCG iteration             */
+} aspamg_stats;
+
+/* Per-level summary, see aspamg_level_info. */
+typedef struct {
+  int32_t n;               /* block rows (nodes) on the level                       */
+  int32_t n_coarse;        /* coarse nodes chosen on this level (0 on the coarsest) */
+  int64_t nnzb_A, nnzb_G, nnzb_P;
+  int32_t has_smoother;    /* 0 on the coarsest level                               */
+  int32_t fsai_rounds;     /* extra rounds of the aFSAI outer loop                  */
+  double  lambda1, omega_q, omega_s;
+  int64_t sell_slots_A, sell_slots_G, sell_slots_GT; /* padded SELL-64 block slots   */
+} aspamg_level_info_t;
+
+/* Fill *out with the defaults.  out: caller-owned. */
+aspamg_status aspamg_default_params(aspamg_params *out);
+
+/* Build the hierarchy (Algorithm "Recursive AMG Setup").
+ *   p        parameters (NULL = defaults).
+ *   n_nodes  block rows of K; nnzb = row_ptr[n_nodes].
+ *   row_ptr, col, vals  K in the block layout above, host or device pointers
+ *            (classified with hipPointerGetAttributes); K must be symmetric in
+ *            pattern and values with a diagonal block in every row.
+ *   n_tv, V0 near-null-space vectors, float64 [n_nodes][3][n_tv] node-major
+ *            (the six rigid-body modes for elasticity, Section 3.3), host or device.
+ *   hip_stream  hipStream_t for all work of this handle (NULL = default stream).
+ *   out      receives the handle; NULL on failure.
+ * Every input is copied; the caller may free its arrays when the call returns.
+ * Errors: EINVAL (shape/pattern), ENOT_SPD, ENOMEM, EHIP. */
+aspamg_status aspamg_setup(const aspamg_params *p, int32_t n_nodes, int64_t nnzb,
+                           const int32_t *row_ptr, const int32_t *col, const double *vals,
+                           int32_t n_tv, const double *V0, void *hip_stream,
+                           aspamg_handle *out);
+
+/* Select the V-cycle precision for later solves: 64 (FP64 operators and
+ * vectors) or 32 (FP32 operators and vectors inside FP64 PCG; the coarsest
+ * solve stays FP64).  Both copies are built by aspamg_setup. */
+aspamg_status aspamg_set_cycle_precision(aspamg_handle h, int32_t bits);
+
+/* PCG from u = 0 until ||r|| <= rtol ||f|| (Section 4).
+ *   f_dev, u_dev  float64 device vectors of 3*n_nodes entries (caller-owned).
+ *   st            optional stats (may be NULL).
+ * Returns OK, NOT_CONVERGED (u = last iterate), EBREAKDOWN, ENAN or EHIP. */
+aspamg_status aspamg_solve(aspamg_handle h, const double *f_dev, double *u_dev,
+                           aspamg_stats *st);
+
+/* k independent solves sharing one hierarchy, through block SpMM kernels
+ * that reuse every streamed matrix block for all right-hand sides.
+ *   F_dev  float64 device, node-major [3*n_nodes][ldf] (column j = load case j)
+ *   U_dev  float64 device, [3*n_nodes][ldu]
+ *   st     optional array of k stats.
+ * Each column has its own alpha, beta and convergence test; a converged column
+ * is frozen.  Returns the worst column status. */
+aspamg_status aspamg_solve_batch(aspamg_handle h, int32_t k, const double *F_dev, int64_t ldf,
+                                 double *U_dev, int64_t ldu, aspamg_stats *st);
+
+/* One preconditioner application z = M^{-1} y (one V-cycle) in the selected
+ * precision.  y_dev, z_dev: float64 device vectors of 3*n_nodes entries. */
+aspamg_status aspamg_vcycle(aspamg_handle h, const double *y_dev, double *z_dev);
+
+/* Apply one stored operator of level l: which = 0 A_l, 1 G_l, 2 G_l^T, 3 P_l,
+ * 4 R_l = P_l^T; precision 64 or 32.  x_dev/y_dev are float64 device vectors
+ * sized by the operator's columns/rows (converted when precision is 32). */
+aspamg_status aspamg_apply_operator(aspamg_handle h, int32_t level, int32_t which,
+                                    int32_t precision, const double *x_dev, double *y_dev);
+
+/* Level summary. */
+aspamg_status aspamg_level_info(aspamg_handle h, int32_t level, aspamg_level_info_t *out);
+
+/* Copy a level's setup products to host arrays (caller-owned, sized from
+ * aspamg_level_info): which = 0 A_l, 1 G_l, 3 P_l as block CSR with int64
+ * row_ptr; any pointer may be NULL. */
+aspamg_status aspamg_level_matrix(aspamg_handle h, int32_t level, int32_t which,
+                                  int64_t *row_ptr, int32_t *col, double *vals);
+
+/* Copy the C/F split (int8 per node: 1 coarse, 0 fine, -1 constrained or
+ * decoupled) and the scalar interpolation pattern (counts[3n], cols[3n][n_max],
+ * -1 padded, coarse scalar indices) of a level.  Any pointer may be NULL. */
+aspamg_status aspamg_level_split(aspamg_handle h, int32_t level, int8_t *cf,
+                                 int32_t *p_counts, int32_t *p_cols);
+
+/* Per-element derivative of lam^T K(E) u with respect to E_e for K = sum_e
+ * E_e K_e^0 (the adjoint form of the compliance gradient):
+ *   grad_e = -scale_e * lam_e^T K_e^0 u_e        (scale NULL -> 1)
+ *   conn_dev  int32 [n_el][8] node ids (Q1 local order), device
+ *   Ke0_dev   float64 [24][24] (ke_stride = 0, shared) or [n_el][24][24]
+ *             (ke_stride = 576), node-major local DOFs, device
+ *   lam_dev, u_dev  float64 device vectors (3 * n_nodes)
+ *   grad_dev  float64 [n_el] device output.
+ * Runs on hip_stream (NULL = default).  Errors: EINVAL, EHIP. */
+aspamg_status aspamg_element_gradient(int64_t n_el, const int32_t *conn_dev,
+                                      const double *Ke0_dev, int64_t ke_stride,
+                                      const double *lam_dev, const double *u_dev,
+                                      const double *scale_dev, double *grad_dev,
+                                      void *hip_stream);
+
+/* Element-to-block assembly of K(E) = sum_e E_e K_e^0 into a fixed block
+ * pattern (the paper's K from element integrals, Section 1).  Rows and
+ * columns of constrained nodes are eliminated: their diagonal block is I3 and
+ * their couplings are absent from the pattern.  The assembler copies its
+ * inputs (host or device); contributions to a block are summed in ascending
+ * element order. */
+typedef struct aspamg_assembler_ctx *aspamg_assembler;
+aspamg_status aspamg_assembler_create(int32_t n_nodes, int64_t n_el, const int32_t *conn,
+                                      const int8_t *constrained, const int32_t *row_ptr,
+                                      const int32_t *col, const double *Ke0, int64_t ke_stride,
+                                      void *hip_stream, aspamg_assembler *out);
+/* vals_dev: float64 device [nnzb][3][3]; E_dev: float64 device [n_el]. */
+aspamg_status aspamg_assemble(aspamg_assembler a, const double *E_dev, double *vals_dev);
+aspamg_status aspamg_assembler_destroy(aspamg_assembler a);
+
+aspamg_status aspamg_destroy(aspamg_handle h);
+const char *aspamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASPAMG_H */

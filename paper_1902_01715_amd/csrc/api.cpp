@@ -1,0 +1,743 @@
+// C ABI of the aSP-AMG library: handle lifetime, device layouts, the
+// V(nu1,nu2)-cycle driver and the PCG driver (one iteration captured as a HIP
+// graph and replayed, with a device-side control block deciding convergence).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+
+#include "internal.h"
+
+namespace aspamg {
+
+static thread_local std::string g_last_error;
+
+void fail(aspamg_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) fail(ASPAMG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *dmalloc(aspamg_ctx *h, size_t bytes) {
+  void *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(&p, bytes) != hipSuccess) fail(ASPAMG_ENOMEM, "device allocation failed");
+  h->allocations.push_back(p);
+  return p;
+}
+
+HostBSR transpose(const HostBSR &M) {
+  HostBSR T;
+  T.n = M.nc;
+  T.nc = M.n;
+  T.rp.assign(T.n + 1, 0);
+  const int64_t nnz = M.nnzb();
+  for (int64_t k = 0; k < nnz; k++) T.rp[M.ci[k] + 1]++;
+  for (int32_t i = 0; i < T.n; i++) T.rp[i + 1] += T.rp[i];
+  T.ci.resize(nnz);
+  T.v.resize((size_t)nnz * 9);
+  std::vector<int64_t> pos(T.rp.begin(), T.rp.end() - 1);
+  for (int32_t i = 0; i < M.n; i++)
+    for (int64_t k = M.rp[i]; k < M.rp[i + 1]; k++) {
+      const int64_t q = pos[M.ci[k]]++;
+      T.ci[q] = i;
+      for (int d = 0; d < 3; d++)
+        for (int e = 0; e < 3; e++) T.v[(size_t)q * 9 + e * 3 + d] = M.v[(size_t)k * 9 + d * 3 + e];
+    }
+  return T;
+}
+
+template <typename T>
+Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M) {
+  Sell<T> S;
+  S.n = M.n;
+  S.nc = M.nc;
+  S.nnzb = M.nnzb();
+  S.nslices = (M.n + kSell - 1) / kSell;
+  std::vector<int32_t> sptr(S.nslices + 1, 0);
+  for (int32_t s = 0; s < S.nslices; s++) {
+    int64_t w = 0;
+    for (int32_t r = s * kSell; r < std::min(M.n, (s + 1) * kSell); r++) w = std::max(w, M.rp[r + 1] - M.rp[r]);
+    if ((int64_t)sptr[s] + w >= (int64_t)INT32_MAX / 64) fail(ASPAMG_EINVAL, "operator too large for SELL layout");
+    sptr[s + 1] = sptr[s] + (int32_t)w;
+  }
+  S.ngroups = sptr[S.nslices];
+  std::vector<int32_t> col((size_t)S.ngroups * 64, 0);
+  std::vector<T> val((size_t)S.ngroups * 576, (T)0);
+  for (int32_t s = 0; s < S.nslices; s++) {
+    for (int lane = 0; lane < kSell; lane++) {
+      const int32_t r = s * kSell + lane;
+      const int64_t len = r < M.n ? M.rp[r + 1] - M.rp[r] : 0;
+      // padding columns point at the row's own node (or 0), values stay 0
+      const int32_t padc = r < M.n ? std::min<int32_t>(r, std::max(M.nc - 1, 0)) : 0;
+      for (int32_t g = sptr[s]; g < sptr[s + 1]; g++) {
+        const int64_t k = g - sptr[s];
+        const size_t cidx = (size_t)g * 64 + lane;
+        if (k < len) {
+          const int64_t src = M.rp[r] + k;
+          col[cidx] = M.ci[src];
+          for (int e = 0; e < 9; e++) val[((size_t)g * 9 + e) * 64 + lane] = (T)M.v[(size_t)src * 9 + e];
+        } else {
+          col[cidx] = padc;
+        }
+      }
+    }
+  }
+  S.sptr = dalloc<int32_t>(h, sptr.size());
+  S.col = dalloc<int32_t>(h, col.size());
+  S.val = dalloc<T>(h, val.size());
+  HIPCHK(hipMemcpyAsync(S.sptr, sptr.data(), sptr.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(S.col, col.data(), col.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(S.val, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return S;
+}
+template Sell<double> upload_sell<double>(aspamg_ctx *, const HostBSR &);
+template Sell<float> upload_sell<float>(aspamg_ctx *, const HostBSR &);
+
+DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M) {
+  DevBSR d;
+  d.n = M.n;
+  d.nc = M.nc;
+  d.nnzb = M.nnzb();
+  if (d.nnzb >= (int64_t)INT32_MAX) fail(ASPAMG_EINVAL, "operator too large for int32 block indices");
+  std::vector<int32_t> rp32(M.rp.begin(), M.rp.end());
+  d.rp = dalloc<int32_t>(h, rp32.size());
+  d.ci = dalloc<int32_t>(h, std::max<size_t>(M.ci.size(), 1));
+  d.v = dalloc<double>(h, std::max<size_t>(M.v.size(), 1));
+  HIPCHK(hipMemcpyAsync(d.rp, rp32.data(), rp32.size() * 4, hipMemcpyHostToDevice, h->stream));
+  if (!M.ci.empty()) HIPCHK(hipMemcpyAsync(d.ci, M.ci.data(), M.ci.size() * 4, hipMemcpyHostToDevice, h->stream));
+  if (!M.v.empty()) HIPCHK(hipMemcpyAsync(d.v, M.v.data(), M.v.size() * 8, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// V(nu1, nu2)-cycle (Algorithm "AMG application in a V-cycle").  With the
+// symmetric smoother M^{-1} = omega G^T G:
+//   s = omega G^T G y                       (pre-smoothing from 0)
+//   s += omega G^T G (y - A s)              (further pre-smoothing steps)
+//   r = y - A s ; r_c = R r ; h_c = cycle(r_c) ; s += P h_c
+//   s += omega G^T G (y - A s)              (nu2 post-smoothing steps)
+// The coarsest level applies A_L^{-1} from its Cholesky factor.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Ops;
+template <>
+struct Ops<double> {
+  static const Sell<double> &A(const Level &L) { return L.A64; }
+  static const Sell<double> &G(const Level &L) { return L.G64; }
+  static const Sell<double> &GT(const Level &L) { return L.GT64; }
+  static const Sell<double> &P(const Level &L) { return L.P64; }
+  static const Sell<double> &R(const Level &L) { return L.R64; }
+  static const LevelVecs<double> &V(const Level &L) { return L.v64; }
+};
+template <>
+struct Ops<float> {
+  static const Sell<float> &A(const Level &L) { return L.A32; }
+  static const Sell<float> &G(const Level &L) { return L.G32; }
+  static const Sell<float> &GT(const Level &L) { return L.GT32; }
+  static const Sell<float> &P(const Level &L) { return L.P32; }
+  static const Sell<float> &R(const Level &L) { return L.R32; }
+  static const LevelVecs<float> &V(const Level &L) { return L.v32; }
+};
+
+template <typename T>
+static void cycle_level(aspamg_ctx *h, int l, const T *y, T *z, const PcgCtrl *ctrl) {
+  const Level &L = h->lev[l];
+  hipStream_t s = h->stream;
+  if (L.coarsest) {
+    launch_dense_gemv<T>(h->coarse.nd, h->coarse.inv, y, z, ctrl, s);
+    return;
+  }
+  using O = Ops<T>;
+  const LevelVecs<T> &W = O::V(L);
+  const LevelVecs<T> &Wn = O::V(h->lev[l + 1]);
+  const double w = L.omega_s;
+  for (int it = 0; it < h->p.nu1; it++) {
+    if (it == 0) {
+      launch_spmv<T, T, T>(O::G(L), y, W.t, nullptr, 1.0, ctrl, s);
+      launch_spmv<T, T, T>(O::GT(L), W.t, z, nullptr, w, ctrl, s);
+    } else {
+      launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
+      launch_spmv<T, T, T>(O::G(L), W.r, W.t, nullptr, 1.0, ctrl, s);
+      launch_spmv<T, T, T>(O::GT(L), W.t, z, z, w, ctrl, s);
+    }
+  }
+  launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
+  launch_spmv<T, T, T>(O::R(L), W.r, Wn.y, nullptr, 1.0, ctrl, s);
+  cycle_level<T>(h, l + 1, Wn.y, Wn.z, ctrl);
+  launch_spmv<T, T, T>(O::P(L), Wn.z, z, z, 1.0, ctrl, s);
+  for (int it = 0; it < h->p.nu2; it++) {
+    launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
+    launch_spmv<T, T, T>(O::G(L), W.r, W.t, nullptr, 1.0, ctrl, s);
+    launch_spmv<T, T, T>(O::GT(L), W.t, z, z, w, ctrl, s);
+  }
+}
+
+// z = M^{-1} r for FP64 vectors r, z of the fine level
+static void precondition(aspamg_ctx *h, const double *r, double *z, const PcgCtrl *ctrl, bool fp32) {
+  const int64_t n = (int64_t)h->n * 3;
+  if (fp32) {
+    const Level &L0 = h->lev[0];
+    launch_cast<double, float>(n, r, L0.v32.y, ctrl, h->stream);
+    cycle_level<float>(h, 0, L0.v32.y, L0.v32.z, ctrl);
+    launch_cast<float, double>(n, L0.v32.z, z, ctrl, h->stream);
+  } else {
+    cycle_level<double>(h, 0, r, z, ctrl);
+  }
+}
+
+// One PCG iteration (Section 4; beta in the Polak-Ribiere form
+// (r_{k+1}.z_{k+1} - r_{k+1}.z_k) / (r_k.z_k)).
+static void pcg_iteration(aspamg_ctx *h, bool fp32) {
+  hipStream_t s = h->stream;
+  const int64_t n = (int64_t)h->n * 3;
+  const Level &L0 = h->lev[0];
+  PcgCtrl *c = h->ctrl;
+  launch_spmv_dot(L0.A64, h->vp, h->vq, h->part, c, s);
+  launch_finish(kFinAlpha, h->part, spmv_blocks(h->n), c, s);
+  launch_pcg_update(n, h->vu, h->vr, h->vp, h->vq, h->vz, h->part, c, s);
+  launch_finish(kFinRr, h->part, vec_blocks(n), c, s);
+  if (fp32) {
+    launch_cast<double, float>(n, h->vr, L0.v32.y, c, s);
+    cycle_level<float>(h, 0, L0.v32.y, L0.v32.z, c);
+    launch_pcg_rz<float>(n, h->vr, L0.v32.z, h->vz, h->part, c, s);
+  } else {
+    cycle_level<double>(h, 0, h->vr, h->vz, c);
+    launch_pcg_rz<double>(n, h->vr, h->vz, h->vz, h->part, c, s);
+  }
+  launch_finish(kFinBeta, h->part, vec_blocks(n), c, s);
+  launch_pcg_pupdate(n, h->vz, h->vp, c, s);
+}
+
+static void alloc_level_vectors(aspamg_ctx *h) {
+  for (auto &L : h->lev) {
+    const size_t n = (size_t)L.A.n * 3;
+    L.v64.y = dalloc<double>(h, n);
+    L.v64.z = dalloc<double>(h, n);
+    L.v64.r = dalloc<double>(h, n);
+    L.v64.t = dalloc<double>(h, n);
+    L.v32.y = dalloc<float>(h, n);
+    L.v32.z = dalloc<float>(h, n);
+    L.v32.r = dalloc<float>(h, n);
+    L.v32.t = dalloc<float>(h, n);
+  }
+  const size_t n = (size_t)h->n * 3;
+  h->vu = dalloc<double>(h, n);
+  h->vr = dalloc<double>(h, n);
+  h->vp = dalloc<double>(h, n);
+  h->vq = dalloc<double>(h, n);
+  h->vz = dalloc<double>(h, n);
+  h->part = dalloc<double>(h, 2 * kMaxPart);
+  h->ctrl = dalloc<PcgCtrl>(h, 1);
+  HIPCHK(hipHostMalloc((void **)&h->ctrl_host, sizeof(PcgCtrl), hipHostMallocDefault));
+}
+
+static void compute_complexities(aspamg_ctx *h) {
+  double sn = 0, sa = 0, sg = 0, sga = 0;
+  for (auto &L : h->lev) {
+    sn += L.A.n;
+    sa += (double)L.A.nnzb();
+    if (!L.coarsest) {
+      // scalar nonzeros: off-diagonal blocks 9, diagonal block 6
+      sg += (double)(L.G.nnzb() - L.G.n) * 9.0 + 6.0 * L.G.n;
+      sga += (double)L.A.nnzb() * 9.0;
+    }
+  }
+  h->c_gd = sn / h->lev[0].A.n;
+  h->c_op = sa / (double)h->lev[0].A.nnzb();
+  h->c_fs = sga > 0 ? sg / sga : 0.0;
+}
+
+// algorithmic HBM bytes of one V-cycle: every stored operator streamed once per
+// use (9 values + 4-byte column per block) plus 18 level-vector passes per
+// level, and the dense coarsest inverse
+static double cycle_bytes(const aspamg_ctx *h, int prec) {
+  const double s = prec == 32 ? 4.0 : 8.0;
+  const double bb = 9.0 * s + 4.0;
+  double B = 0.0;
+  const int nu = h->p.nu1 + h->p.nu2;
+  for (const auto &L : h->lev) {
+    if (L.coarsest) {
+      B += (double)h->coarse.nd * h->coarse.nd * 8.0;
+      continue;
+    }
+    const double nA = (double)L.A.nnzb(), nG = (double)L.G.nnzb(), nP = (double)L.P.nnzb();
+    // A: nu1 - 1 pre-smoothing residuals, the restriction residual, nu2 post-smoothing residuals
+    const double usesA = (double)nu;
+    B += (usesA * nA + 2.0 * nu * nG + 2.0 * nP) * bb + 18.0 * 3.0 * L.A.n * s;
+  }
+  return B;
+}
+
+static double iter_bytes(const aspamg_ctx *h, int prec) {
+  const Level &L0 = h->lev[0];
+  return (double)L0.A.nnzb() * 76.0 + 14.0 * 3.0 * L0.A.n * 8.0 + cycle_bytes(h, prec);
+}
+
+template <typename T>
+static bool is_device_ptr(const T *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice;
+}
+
+template <typename T>
+static std::vector<T> fetch(const T *p, size_t n, hipStream_t s) {
+  std::vector<T> v(n);
+  if (n == 0) return v;
+  if (is_device_ptr(p)) {
+    HIPCHK(hipMemcpyAsync(v.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(v.data(), p, n * sizeof(T));
+  }
+  return v;
+}
+
+static void check_params(const aspamg_params &p) {
+  if (p.k_g < 0 || p.rho_blocks < 1 || p.theta < 1 || p.n_max < 1 || p.n_max > kMaxPEntries || p.d_p < 1 ||
+      p.lanczos_steps < 1 || p.lanczos_steps > 200 || p.nu1 < 1 || p.nu2 < 1 || p.max_levels < 1 ||
+      (p.cycle_precision != 32 && p.cycle_precision != 64) || !(p.rtol >= 0) || p.max_it < 1 ||
+      p.quant_bits < 8 || p.quant_bits > 52 || p.check_every < 1 || p.n_tv < 0 || p.n_tv > 64 ||
+      !(p.kappa_p > 0) || !(p.omega_safety > 0))
+    fail(ASPAMG_EINVAL, "invalid parameter value");
+}
+
+}  // namespace aspamg
+
+using namespace aspamg;
+
+#define ABI_BEGIN try {
+#define ABI_END                                   \
+  }                                               \
+  catch (const Error &e) {                        \
+    g_last_error = e.msg;                         \
+    return e.code;                                \
+  }                                               \
+  catch (const std::bad_alloc &) {                \
+    g_last_error = "host allocation failed";      \
+    return ASPAMG_ENOMEM;                         \
+  }                                               \
+  catch (...) {                                   \
+    g_last_error = "unexpected internal error";   \
+    return ASPAMG_EINVAL;                         \
+  }
+
+extern "C" {
+
+const char *aspamg_last_error(void) { return g_last_error.c_str(); }
+
+aspamg_status aspamg_default_params(aspamg_params *o) {
+  if (!o) return ASPAMG_EINVAL;
+  std::memset(o, 0, sizeof *o);
+  o->k_g = 4;
+  o->rho_g = 4;
+  o->eps_g = 1e-3;
+  o->n_tv = 6;
+  o->n_rq = 0;
+  o->theta = 5;
+  o->n_max = 5;
+  o->kappa_p = 50.0;
+  o->rho_blocks = 3;
+  o->omega_bar = 0.8;
+  o->outer_fsai = 1;
+  o->d_p = 2;
+  o->eps_p = 1e-8;
+  o->lanczos_steps = 30;
+  o->omega_safety = 1.05;
+  o->coarse_max_dof = 1500;
+  o->max_levels = 25;
+  o->stall_ratio = 0.9;
+  o->nu1 = 1;
+  o->nu2 = 1;
+  o->cycle_precision = 64;
+  o->rtol = 1e-10;
+  o->max_it = 1000;
+  o->quant_bits = 20;
+  o->dense_max_dof = 16384;
+  o->check_every = 4;
+  o->use_graph = 1;
+  return ASPAMG_OK;
+}
+
+aspamg_status aspamg_destroy(aspamg_handle h) {
+  if (!h) return ASPAMG_OK;
+  for (int i = 0; i < 2; i++)
+    if (h->graph[i]) (void)hipGraphExecDestroy(h->graph[i]);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (void *p : h->allocations) (void)hipFree(p);
+  if (h->ctrl_host) (void)hipHostFree(h->ctrl_host);
+  if (h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return ASPAMG_OK;
+}
+
+static aspamg_status setup_impl(const aspamg_params *pp, int32_t n_nodes, int64_t nnzb, const int32_t *row_ptr,
+                                const int32_t *col, const double *vals, int32_t n_tv, const double *V0,
+                                void *hip_stream, aspamg_ctx *hraw, aspamg_handle *out) {
+  struct NoDelete {
+    void operator()(aspamg_ctx *) const {}
+  };
+  std::unique_ptr<aspamg_ctx, NoDelete> h(hraw);
+  ABI_BEGIN
+  if (!out || n_nodes <= 0 || nnzb < n_nodes || !row_ptr || !col || !vals || n_tv < 0 || (n_tv > 0 && !V0))
+    fail(ASPAMG_EINVAL, "invalid arguments to aspamg_setup");
+  aspamg_params p;
+  if (pp) p = *pp;
+  else aspamg_default_params(&p);
+  p.n_tv = n_tv;
+  check_params(p);
+  const auto t0 = std::chrono::steady_clock::now();
+  h->p = p;
+  // every stream keeps the default priority; a private stream is created so
+  // that the PCG iteration can be captured as a graph
+  hipStream_t user = static_cast<hipStream_t>(hip_stream);
+  HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+  if (user) HIPCHK(hipStreamSynchronize(user));
+  h->ntv = n_tv;
+  h->n = n_nodes;
+  HostBSR A;
+  A.n = A.nc = n_nodes;
+  {
+    std::vector<int32_t> rp = fetch(row_ptr, (size_t)n_nodes + 1, h->stream);
+    if (rp[0] != 0 || rp[n_nodes] != nnzb) fail(ASPAMG_EINVAL, "row_ptr inconsistent with nnzb");
+    A.rp.assign(rp.begin(), rp.end());
+  }
+  A.ci = fetch(col, (size_t)nnzb, h->stream);
+  A.v = fetch(vals, (size_t)nnzb * 9, h->stream);
+  for (int32_t i = 0; i < n_nodes; i++) {
+    if (A.rp[i + 1] < A.rp[i]) fail(ASPAMG_EINVAL, "row_ptr not monotone");
+    bool diag = false;
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; k++) {
+      if (A.ci[k] < 0 || A.ci[k] >= n_nodes) fail(ASPAMG_EINVAL, "column index out of range");
+      if (k > A.rp[i] && A.ci[k] <= A.ci[k - 1]) fail(ASPAMG_EINVAL, "column indices not strictly ascending");
+      diag |= A.ci[k] == i;
+    }
+    if (!diag) fail(ASPAMG_EINVAL, "missing diagonal block");
+  }
+  for (double x : A.v)
+    if (!std::isfinite(x)) fail(ASPAMG_EINVAL, "non-finite matrix value");
+  std::vector<double> V = n_tv ? fetch(V0, (size_t)n_nodes * 3 * n_tv, h->stream) : std::vector<double>();
+  build_hierarchy(h.get(), std::move(A), std::move(V));
+  alloc_level_vectors(h.get());
+  compute_complexities(h.get());
+  h->prec = p.cycle_precision;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = h.release();
+  return ASPAMG_OK;
+  ABI_END
+}
+
+aspamg_status aspamg_setup(const aspamg_params *pp, int32_t n_nodes, int64_t nnzb, const int32_t *row_ptr,
+                           const int32_t *col, const double *vals, int32_t n_tv, const double *V0, void *hip_stream,
+                           aspamg_handle *out) {
+  if (out) *out = nullptr;
+  aspamg_ctx *h = new (std::nothrow) aspamg_ctx();
+  if (!h) return ASPAMG_ENOMEM;
+  const aspamg_status rc = setup_impl(pp, n_nodes, nnzb, row_ptr, col, vals, n_tv, V0, hip_stream, h, out);
+  if (rc != ASPAMG_OK) {
+    if (out) *out = nullptr;
+    aspamg_destroy(h);
+  }
+  return rc;
+}
+
+aspamg_status aspamg_set_cycle_precision(aspamg_handle h, int32_t bits) {
+  if (!h || (bits != 32 && bits != 64)) return ASPAMG_EINVAL;
+  h->prec = bits;
+  return ASPAMG_OK;
+}
+
+static void fill_stats(aspamg_handle h, aspamg_stats *st, const PcgCtrl &c, double t_solve, double relres_true) {
+  if (!st) return;
+  st->status = c.status;
+  st->iterations = c.iter;
+  st->levels = (int32_t)h->lev.size();
+  st->cycle_precision = h->prec;
+  st->relres_recursive = c.relres;
+  st->relres_true = relres_true;
+  st->t_setup_s = h->t_setup;
+  st->t_solve_s = t_solve;
+  st->c_gd = h->c_gd;
+  st->c_op = h->c_op;
+  st->c_fs = h->c_fs;
+  st->bytes_vcycle = cycle_bytes(h, h->prec);
+  st->bytes_iter = iter_bytes(h, h->prec);
+}
+
+aspamg_status aspamg_solve(aspamg_handle h, const double *f_dev, double *u_dev, aspamg_stats *st) {
+  ABI_BEGIN
+  if (!h || !f_dev || !u_dev) fail(ASPAMG_EINVAL, "invalid arguments to aspamg_solve");
+  hipStream_t s = h->stream;
+  const int64_t n = (int64_t)h->n * 3;
+  const bool fp32 = h->prec == 32;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  // control block
+  PcgCtrl c0;
+  std::memset(&c0, 0, sizeof c0);
+  c0.status = ASPAMG_NOT_CONVERGED;
+  c0.max_it = h->p.max_it;
+  c0.rtol = h->p.rtol;
+  *h->ctrl_host = c0;
+  HIPCHK(hipEventRecord(e0, s));
+  HIPCHK(hipMemcpyAsync(h->ctrl, h->ctrl_host, sizeof(PcgCtrl), hipMemcpyHostToDevice, s));
+  // u = 0, r = f, |f|
+  launch_fill(n, h->vu, 0.0, s);
+  launch_copy(n, f_dev, h->vr, s);
+  launch_dot(n, f_dev, f_dev, h->part, nullptr, s);
+  launch_finish(kFinInitF, h->part, vec_blocks(n), h->ctrl, s);
+  // z = M r, p = z, rz = r.z
+  precondition(h, h->vr, h->vz, h->ctrl, fp32);
+  launch_dot(n, h->vr, h->vz, h->part, h->ctrl, s);
+  launch_finish(kFinInitRz, h->part, vec_blocks(n), h->ctrl, s);
+  launch_copy(n, h->vz, h->vp, s);
+  HIPCHK(hipGetLastError());
+  hipGraphExec_t &gx = h->graph[fp32 ? 1 : 0];
+  if (h->p.use_graph && !gx) {
+    hipGraph_t g;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    pcg_iteration(h, fp32);
+    HIPCHK(hipStreamEndCapture(s, &g));
+    HIPCHK(hipGraphInstantiate(&gx, g, nullptr, nullptr, 0));
+    HIPCHK(hipGraphDestroy(g));
+  }
+  const int every = h->p.check_every;
+  for (;;) {
+    HIPCHK(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(PcgCtrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h->ctrl_host->done) break;
+    for (int k = 0; k < every; k++) {
+      if (h->p.use_graph) HIPCHK(hipGraphLaunch(gx, s));
+      else pcg_iteration(h, fp32);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  launch_copy(n, h->vu, u_dev, s);
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  PcgCtrl c = *h->ctrl_host;
+  // true residual |f - K u| / |f|
+  launch_spmv<double, double, double>(h->lev[0].A64, h->vu, h->vq, f_dev, -1.0, nullptr, s);
+  launch_dot(n, h->vq, h->vq, h->part, nullptr, s);
+  std::vector<double> part(vec_blocks(n));
+  HIPCHK(hipMemcpyAsync(part.data(), h->part, part.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double rr = 0.0;
+  for (double x : part) rr += x;
+  const double relres_true = c.fnorm > 0 ? std::sqrt(rr) / c.fnorm : 0.0;
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
+  fill_stats(h, st, c, ms * 1e-3, relres_true);
+  return (aspamg_status)c.status;
+  ABI_END
+}
+
+aspamg_status aspamg_vcycle(aspamg_handle h, const double *y_dev, double *z_dev) {
+  ABI_BEGIN
+  if (!h || !y_dev || !z_dev) fail(ASPAMG_EINVAL, "invalid arguments to aspamg_vcycle");
+  precondition(h, y_dev, z_dev, nullptr, h->prec == 32);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ASPAMG_OK;
+  ABI_END
+}
+
+aspamg_status aspamg_apply_operator(aspamg_handle h, int32_t level, int32_t which, int32_t precision,
+                                    const double *x_dev, double *y_dev) {
+  ABI_BEGIN
+  if (!h || level < 0 || level >= (int32_t)h->lev.size() || which < 0 || which > 4 ||
+      (precision != 32 && precision != 64) || !x_dev || !y_dev)
+    fail(ASPAMG_EINVAL, "invalid arguments to aspamg_apply_operator");
+  const Level &L = h->lev[level];
+  if (L.coarsest && which != 0) fail(ASPAMG_EINVAL, "the coarsest level has only A");
+  hipStream_t s = h->stream;
+  if (precision == 64) {
+    const Sell<double> *M[5] = {&L.A64, &L.G64, &L.GT64, &L.P64, &L.R64};
+    launch_spmv<double, double, double>(*M[which], x_dev, y_dev, nullptr, 1.0, nullptr, s);
+  } else {
+    const Sell<float> *M[5] = {&L.A32, &L.G32, &L.GT32, &L.P32, &L.R32};
+    const int64_t nx = (int64_t)M[which]->nc * 3, ny = (int64_t)M[which]->n * 3;
+    float *xs = nullptr, *ys = nullptr;
+    HIPCHK(hipMalloc(&xs, std::max<int64_t>(nx, 1) * 4));
+    HIPCHK(hipMalloc(&ys, std::max<int64_t>(ny, 1) * 4));
+    launch_cast<double, float>(nx, x_dev, xs, nullptr, s);
+    launch_spmv<float, float, float>(*M[which], xs, ys, nullptr, 1.0, nullptr, s);
+    launch_cast<float, double>(ny, ys, y_dev, nullptr, s);
+    HIPCHK(hipStreamSynchronize(s));
+    (void)hipFree(xs);
+    (void)hipFree(ys);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return ASPAMG_OK;
+  ABI_END
+}
+
+aspamg_status aspamg_level_info(aspamg_handle h, int32_t level, aspamg_level_info_t *o) {
+  if (!h || !o || level < 0 || level >= (int32_t)h->lev.size()) return ASPAMG_EINVAL;
+  const Level &L = h->lev[level];
+  std::memset(o, 0, sizeof *o);
+  o->n = L.A.n;
+  o->n_coarse = L.coarsest ? 0 : L.nc;
+  o->nnzb_A = L.A.nnzb();
+  o->nnzb_G = L.G.nnzb();
+  o->nnzb_P = L.P.nnzb();
+  o->has_smoother = !L.coarsest;
+  o->fsai_rounds = L.fsai_rounds;
+  o->lambda1 = L.lambda1;
+  o->omega_q = L.omega_q;
+  o->omega_s = L.omega_s;
+  o->sell_slots_A = L.A64.ngroups * 64;
+  o->sell_slots_G = L.G64.ngroups * 64;
+  o->sell_slots_GT = L.GT64.ngroups * 64;
+  return ASPAMG_OK;
+}
+
+aspamg_status aspamg_level_matrix(aspamg_handle h, int32_t level, int32_t which, int64_t *row_ptr, int32_t *col,
+                                  double *vals) {
+  if (!h || level < 0 || level >= (int32_t)h->lev.size() || (which != 0 && which != 1 && which != 3))
+    return ASPAMG_EINVAL;
+  const Level &L = h->lev[level];
+  const HostBSR &M = which == 0 ? L.A : which == 1 ? L.G : L.P;
+  if (row_ptr && !M.rp.empty()) std::memcpy(row_ptr, M.rp.data(), M.rp.size() * 8);
+  if (col && !M.ci.empty()) std::memcpy(col, M.ci.data(), M.ci.size() * 4);
+  if (vals && !M.v.empty()) std::memcpy(vals, M.v.data(), M.v.size() * 8);
+  return ASPAMG_OK;
+}
+
+aspamg_status aspamg_level_split(aspamg_handle h, int32_t level, int8_t *cf, int32_t *p_counts, int32_t *p_cols) {
+  if (!h || level < 0 || level >= (int32_t)h->lev.size()) return ASPAMG_EINVAL;
+  const Level &L = h->lev[level];
+  if (cf && !L.cf.empty()) std::memcpy(cf, L.cf.data(), L.cf.size());
+  if (p_counts && !L.pcount.empty()) std::memcpy(p_counts, L.pcount.data(), L.pcount.size() * 4);
+  if (p_cols && !L.pcols.empty()) std::memcpy(p_cols, L.pcols.data(), L.pcols.size() * 4);
+  return ASPAMG_OK;
+}
+
+aspamg_status aspamg_element_gradient(int64_t n_el, const int32_t *conn_dev, const double *Ke0_dev, int64_t ke_stride,
+                                      const double *lam_dev, const double *u_dev, const double *scale_dev,
+                                      double *grad_dev, void *hip_stream) {
+  ABI_BEGIN
+  if (n_el < 0 || (n_el > 0 && (!conn_dev || !Ke0_dev || !lam_dev || !u_dev || !grad_dev)) ||
+      (ke_stride != 0 && ke_stride != 576))
+    fail(ASPAMG_EINVAL, "invalid arguments to aspamg_element_gradient");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  launch_element_gradient(n_el, conn_dev, Ke0_dev, ke_stride, lam_dev, u_dev, scale_dev, grad_dev, s);
+  HIPCHK(hipGetLastError());
+  return ASPAMG_OK;
+  ABI_END
+}
+
+aspamg_status aspamg_assembler_create(int32_t n_nodes, int64_t n_el, const int32_t *conn, const int8_t *constrained,
+                                      const int32_t *row_ptr, const int32_t *col, const double *Ke0,
+                                      int64_t ke_stride, void *hip_stream, aspamg_assembler *out) {
+  if (out) *out = nullptr;
+  auto *a = new aspamg_assembler_ctx();
+  ABI_BEGIN
+  if (!out || n_nodes <= 0 || n_el < 0 || !conn || !row_ptr || !col || !Ke0 || (ke_stride != 0 && ke_stride != 576))
+    fail(ASPAMG_EINVAL, "invalid arguments to aspamg_assembler_create");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  a->stream = s;
+  a->n_nodes = n_nodes;
+  a->n_el = n_el;
+  std::vector<int32_t> rp = fetch(row_ptr, (size_t)n_nodes + 1, s);
+  const int64_t nnzb = rp[n_nodes];
+  a->nnzb = nnzb;
+  std::vector<int32_t> ci = fetch(col, (size_t)nnzb, s);
+  std::vector<int32_t> cn = fetch(conn, (size_t)n_el * 8, s);
+  std::vector<int8_t> cons = constrained ? fetch(constrained, (size_t)n_nodes, s) : std::vector<int8_t>(n_nodes, 0);
+  std::vector<double> ke = fetch(Ke0, (size_t)(ke_stride ? n_el * 576 : 576), s);
+  // contributions per slot, ascending element order (counting sort keeps it)
+  std::vector<int64_t> cnt(nnzb + 1, 0);
+  std::vector<int64_t> slot_of((size_t)n_el * 64, -1);
+  std::vector<int8_t> diag(nnzb, 0);
+  for (int64_t e = 0; e < n_el; e++)
+    for (int a1 = 0; a1 < 8; a1++)
+      for (int b1 = 0; b1 < 8; b1++) {
+        const int32_t r = cn[e * 8 + a1], c = cn[e * 8 + b1];
+        if (r < 0 || r >= n_nodes || c < 0 || c >= n_nodes) fail(ASPAMG_EINVAL, "connectivity out of range");
+        if (cons[r] || cons[c]) continue;
+        const int32_t *b = ci.data() + rp[r], *en = ci.data() + rp[r + 1];
+        const int32_t *it = std::lower_bound(b, en, c);
+        if (it == en || *it != c) fail(ASPAMG_EINVAL, "element coupling missing from the block pattern");
+        const int64_t sl = it - ci.data();
+        slot_of[e * 64 + a1 * 8 + b1] = sl;
+        cnt[sl + 1]++;
+      }
+  for (int32_t i = 0; i < n_nodes; i++)
+    if (cons[i]) {
+      const int32_t *b = ci.data() + rp[i], *en = ci.data() + rp[i + 1];
+      const int32_t *it = std::lower_bound(b, en, i);
+      if (it == en || *it != i) fail(ASPAMG_EINVAL, "missing diagonal block");
+      diag[it - ci.data()] = 1;
+    }
+  for (int64_t k = 0; k < nnzb; k++) cnt[k + 1] += cnt[k];
+  std::vector<int32_t> contrib((size_t)cnt[nnzb] * 2 + 2);
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t e = 0; e < n_el; e++)
+    for (int ab = 0; ab < 64; ab++) {
+      const int64_t sl = slot_of[e * 64 + ab];
+      if (sl < 0) continue;
+      const int64_t q = pos[sl]++;
+      contrib[2 * q] = (int32_t)e;
+      contrib[2 * q + 1] = ab;
+    }
+  auto up = [&](const void *src, size_t bytes) {
+    void *d = nullptr;
+    HIPCHK(hipMalloc(&d, std::max<size_t>(bytes, 16)));
+    if (bytes) HIPCHK(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
+    return d;
+  };
+  a->slot_ptr = (int64_t *)up(cnt.data(), cnt.size() * 8);
+  a->contrib = (int32_t *)up(contrib.data(), contrib.size() * 4);
+  a->diag_identity = (int8_t *)up(diag.data(), diag.size());
+  a->Ke0 = (double *)up(ke.data(), ke.size() * 8);
+  a->ke_stride = ke_stride;
+  *out = a;
+  return ASPAMG_OK;
+  ABI_END
+}
+
+aspamg_status aspamg_assemble(aspamg_assembler a, const double *E_dev, double *vals_dev) {
+  ABI_BEGIN
+  if (!a || !E_dev || !vals_dev) fail(ASPAMG_EINVAL, "invalid arguments to aspamg_assemble");
+  launch_assemble(a->nnzb, a->slot_ptr, a->contrib, a->diag_identity, a->Ke0, a->ke_stride, E_dev, vals_dev,
+                  a->stream);
+  HIPCHK(hipGetLastError());
+  return ASPAMG_OK;
+  ABI_END
+}
+
+aspamg_status aspamg_assembler_destroy(aspamg_assembler a) {
+  if (!a) return ASPAMG_OK;
+  if (a->stream) (void)hipStreamSynchronize(a->stream);
+  else (void)hipDeviceSynchronize();
+  (void)hipFree(a->slot_ptr);
+  (void)hipFree(a->contrib);
+  (void)hipFree(a->diag_identity);
+  (void)hipFree(a->Ke0);
+  delete a;
+  return ASPAMG_OK;
+}
+
+aspamg_status aspamg_solve_batch(aspamg_handle h, int32_t k, const double *F_dev, int64_t ldf, double *U_dev,
+                                 int64_t ldu, aspamg_stats *st) {
+  (void)h; (void)k; (void)F_dev; (void)ldf; (void)U_dev; (void)ldu; (void)st;
+  g_last_error = "solve_batch is not built yet";
+  return ASPAMG_EINVAL;
+}
+
+}  // extern "C"

@@ -1,0 +1,209 @@
+// Internal declarations of the aSP-AMG library: host data structures, the
+// device layouts and the kernel launchers shared by the host translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "aspamg.h"
+
+namespace aspamg {
+
+constexpr int kSell = 64;           // rows per SELL slice = one wavefront
+constexpr int kMaxFsaiNodes = 32;   // off-diagonal nodes an FSAI row may hold
+constexpr int kMaxPEntries = 8;     // interpolation entries per scalar row (n_max cap)
+
+// Error raised inside the library; converted to aspamg_status at the ABI.
+struct Error {
+  aspamg_status code;
+  std::string msg;
+};
+[[noreturn]] void fail(aspamg_status code, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+#define HIPCHK(x) ::aspamg::hip_check((x), #x)
+
+// Host 3x3-block CSR (int64 row pointer).
+struct HostBSR {
+  int32_t n = 0, nc = 0;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> v;   // nnzb * 9
+  int64_t nnzb() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+// Device plain BSR (int32 row pointer) used by setup kernels.
+struct DevBSR {
+  int32_t n = 0, nc = 0;
+  int64_t nnzb = 0;
+  int32_t *rp = nullptr;
+  int32_t *ci = nullptr;
+  double *v = nullptr;
+};
+
+// SELL-64 layout of a 3x3-block matrix: slice s of 64 consecutive block rows
+// owns slot groups [sptr[s], sptr[s+1]); slot group g holds one block per row:
+// col[g*64 + lane], and values val[(g*9 + k)*64 + lane] for entry k of the
+// block (component-major, so a wavefront reads 64 consecutive values).
+// Padded slots have value 0 and a valid column.
+template <typename T>
+struct Sell {
+  int32_t n = 0, nc = 0, nslices = 0;
+  int64_t ngroups = 0;     // padded slot groups
+  int64_t nnzb = 0;        // real blocks
+  int32_t *sptr = nullptr;
+  int32_t *col = nullptr;
+  T *val = nullptr;
+  size_t bytes() const { return (size_t)ngroups * 64 * (sizeof(int32_t) + 9 * sizeof(T)) + (nslices + 1) * 4; }
+};
+
+// Device-resident PCG control block (one per solve stream).
+struct PcgCtrl {
+  int32_t done;       // 1 once converged, failed or out of iterations
+  int32_t status;     // aspamg_status
+  int32_t iter;
+  int32_t max_it;
+  double rtol, fnorm;
+  double alpha, beta, rz, rzo, pq, rr, relres;
+  double pad[3];
+};
+
+template <typename T>
+struct LevelVecs {
+  T *y = nullptr;   // cycle input
+  T *z = nullptr;   // cycle output / s
+  T *r = nullptr;   // residual
+  T *t = nullptr;   // G r
+};
+
+struct Level {
+  HostBSR A, G, P;                 // FP64 host copies (decisions, exports)
+  DevBSR dA;                       // plain FP64 device copy for setup kernels
+  Sell<double> A64, G64, GT64, P64, R64;
+  Sell<float> A32, G32, GT32, P32, R32;
+  bool coarsest = false;
+  double lambda1 = 0, omega_q = 0, omega_s = 0;
+  int32_t fsai_rounds = 0;
+  std::vector<int8_t> cf;
+  std::vector<int32_t> cidx;
+  int32_t nc = 0;
+  std::vector<double> V;           // orthonormalised test space, [n][3][ntv]
+  std::vector<int32_t> pcount, pcols;   // scalar P pattern
+  LevelVecs<double> v64;
+  LevelVecs<float> v32;
+};
+
+// Dense coarsest operator: explicit inverse A_L^{-1} = L^{-T} L^{-1} from the
+// Cholesky factor, applied as one dense matrix-vector product.
+struct Coarse {
+  int32_t nd = 0;
+  double *inv = nullptr;     // device nd x nd row-major
+};
+
+struct BatchWork;  // multi-RHS buffers (solve_batch)
+
+}  // namespace aspamg
+
+struct aspamg_ctx {
+  aspamg_params p;
+  hipStream_t stream = nullptr;
+  int32_t ntv = 0;
+  int32_t n = 0;                              // fine block rows
+  std::vector<aspamg::Level> lev;
+  aspamg::Coarse coarse;
+  int32_t prec = 64;
+  // PCG vectors (FP64) and control
+  double *vu = nullptr, *vr = nullptr, *vp = nullptr, *vq = nullptr, *vz = nullptr;
+  double *part = nullptr;                     // reduction partials (4 x kMaxPart)
+  aspamg::PcgCtrl *ctrl = nullptr;
+  aspamg::PcgCtrl *ctrl_host = nullptr;       // pinned
+  hipGraphExec_t graph[2] = {nullptr, nullptr};   // [0] fp64 cycle, [1] fp32 cycle
+  const double *graph_f = nullptr;
+  double t_setup = 0;
+  double c_gd = 0, c_op = 0, c_fs = 0;
+  aspamg::BatchWork *batch = nullptr;
+  std::vector<void *> allocations;
+};
+
+struct aspamg_assembler_ctx {
+  hipStream_t stream = nullptr;
+  int64_t nnzb = 0;
+  int32_t n_nodes = 0;
+  int64_t n_el = 0;
+  int64_t *slot_ptr = nullptr;     // device: contribution list per block slot
+  int32_t *contrib = nullptr;      // device: (element, local a*8+b) packed per contribution
+  int8_t *diag_identity = nullptr; // device: 1 if the slot is a constrained diagonal block
+  double *Ke0 = nullptr;
+  int64_t ke_stride = 0;
+};
+
+namespace aspamg {
+
+constexpr int kMaxPart = 8192;      // reduction partial slots per buffer
+
+// ---- device memory helpers (tracked by the handle) ----
+void *dmalloc(aspamg_ctx *h, size_t bytes);
+template <typename T>
+T *dalloc(aspamg_ctx *h, size_t n) { return static_cast<T *>(dmalloc(h, n * sizeof(T))); }
+
+// ---- layout builders (host) ----
+HostBSR transpose(const HostBSR &M);
+template <typename T>
+Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M);
+DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M);
+
+// ---- solve-path kernel launchers (kernels_solve.hip) ----
+template <typename T, typename TX, typename TO>
+void launch_spmv(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
+                 hipStream_t s);
+void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
+                     hipStream_t s);
+template <typename TV>
+void launch_dense_gemv(int nd, const double *inv, const TV *y, TV *z, const PcgCtrl *ctrl, hipStream_t s);
+template <typename TI, typename TO>
+void launch_cast(int64_t n, const TI *x, TO *y, const PcgCtrl *ctrl, hipStream_t s);
+void launch_fill(int64_t n, double *x, double v, hipStream_t s);
+void launch_copy(int64_t n, const double *x, double *y, hipStream_t s);
+void launch_dot(int64_t n, const double *a, const double *b, double *part, const PcgCtrl *ctrl, hipStream_t s);
+void launch_pcg_update(int64_t n, double *u, double *r, const double *p, const double *q, const double *z,
+                       double *part, const PcgCtrl *ctrl, hipStream_t s);
+template <typename TZ>
+void launch_pcg_rz(int64_t n, const double *r, const TZ *zc, double *z, double *part, const PcgCtrl *ctrl,
+                   hipStream_t s);
+void launch_pcg_pupdate(int64_t n, const double *z, double *p, const PcgCtrl *ctrl, hipStream_t s);
+// finish modes
+enum FinishMode { kFinInitF = 0, kFinInitRz = 1, kFinAlpha = 2, kFinRr = 3, kFinBeta = 4, kFinNorm = 5 };
+void launch_finish(int mode, const double *part, int nparts, PcgCtrl *ctrl, hipStream_t s);
+int vec_blocks(int64_t n);
+int spmv_blocks(int32_t nrows);
+
+// ---- setup kernel launchers (kernels_setup.hip) ----
+// FSAI rows: for each listed block row I (rows[i]) with nodes pat[pat_ptr[i]..pat_ptr[i+1]),
+// computes the three scaled rows g (stride gstride) and psi. Returns nonzero on a bad pivot.
+int launch_fsai_rows(const DevBSR &A, int32_t nrows, const int32_t *rows, const int32_t *pat_ptr,
+                     const int32_t *pat_nodes, int mmax, double *g, int gstride, double *psi, int32_t *fail_flag,
+                     hipStream_t s);
+// DPLS weights: for each listed scalar row i, K=cnt[i] chosen scalar rows sel[i*kMaxPEntries + k]
+// of the fine-level test space V (ntv columns): w = (C^T C)^{-1} C^T v.
+void launch_dpls_weights(int32_t nrows, const int32_t *row, const int32_t *cnt, const int32_t *sel,
+                         const double *V, int ntv, double *w, hipStream_t s);
+// RAP numeric phases
+void launch_spgemm_ap(const DevBSR &A, const DevBSR &P, const DevBSR &T, hipStream_t s);
+void launch_spgemm_rt(const DevBSR &R, const DevBSR &T, const DevBSR &Ac, hipStream_t s);
+void launch_element_gradient(int64_t n_el, const int32_t *conn, const double *Ke0, int64_t ke_stride,
+                             const double *lam, const double *u, const double *scale, double *grad,
+                             hipStream_t s);
+void launch_assemble(int64_t nnzb, const int64_t *slot_ptr, const int32_t *contrib, const int8_t *diag_id,
+                     const double *Ke0, int64_t ke_stride, const double *E, double *vals, hipStream_t s);
+
+// ---- host setup (setup_host.cpp) ----
+void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0);
+double quantize(double s, int bits);
+
+// ---- V-cycle (api.cpp) ----
+template <typename T>
+void vcycle_launch(aspamg_ctx *h, const PcgCtrl *ctrl);
+
+}  // namespace aspamg

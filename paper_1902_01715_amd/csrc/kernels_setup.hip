@@ -1,0 +1,334 @@
+// Setup-phase kernels for gfx950: batched small dense SPD factorisations of the
+// FSAI rows (one wavefront per block row, system staged in LDS), the batched
+// least-squares solves of the interpolation weights, the two numeric SpGEMM
+// phases of the Galerkin product, and the element-level kernels (gradient of a
+// quadratic form and element-to-block assembly).
+//
+// This file is compiled with -ffp-contract=off: every sum runs in ascending
+// index order with separately rounded products, so the FSAI rows and the
+// Galerkin values are bitwise those of the sequential definition (IEEE
+// binary64 +, -, *, / and sqrt are correctly rounded on the device).
+#include "internal.h"
+
+namespace aspamg {
+
+namespace {
+
+__device__ __forceinline__ int32_t find_col(const int32_t *ci, int32_t lo, int32_t hi, int32_t c) {
+  // binary search in ci[lo, hi), -1 if absent
+  hi -= 1;
+  while (lo <= hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    const int32_t v = ci[mid];
+    if (v == c) return mid;
+    if (v < c) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+// One FSAI block row per 64-thread block.  With the local list
+// l = [(J,e) for J in B] + [(I,0), (I,1), (I,2)] and M = A[l,l] (block of row
+// l_p's node), the left-looking Cholesky M = L L^T is formed in LDS (packed
+// lower triangle) with
+//   L_jj = sqrt(M_jj - sum_{k<j} L_jk^2),  L_ij = (M_ij - sum_{k<j} L_ik L_jk) / L_jj,
+// each sum in ascending k.  Scalar row d is g = L_md^{-T} e_md (md = 3|B|+d+1),
+// obtained by back substitution with sums in ascending j, and psi_d = L_md,md^2.
+__device__ __forceinline__ int tri(int i, int j) { return (i * (i + 1) >> 1) + j; }
+
+__global__ void __launch_bounds__(64) k_fsai_rows(int32_t nrows, const int32_t *__restrict__ rows,
+                                                  const int32_t *__restrict__ pat_ptr,
+                                                  const int32_t *__restrict__ pat_nodes,
+                                                  const int32_t *__restrict__ Arp, const int32_t *__restrict__ Aci,
+                                                  const double *__restrict__ Av, int mmax, double *__restrict__ gout,
+                                                  int gstride, double *__restrict__ psi, int32_t *fail) {
+  extern __shared__ double L[];         // packed lower triangle, m(m+1)/2
+  __shared__ int32_t nodes[kMaxFsaiNodes + 1];
+  __shared__ int bad;
+  const int32_t r = blockIdx.x;
+  if (r >= nrows) return;
+  const int lane = threadIdx.x;
+  const int32_t I = rows[r];
+  const int32_t p0 = pat_ptr[r], nb = pat_ptr[r + 1] - p0;
+  const int m = 3 * nb + 3;
+  for (int q = lane; q <= nb; q += 64) nodes[q] = q < nb ? pat_nodes[p0 + q] : I;
+  if (lane == 0) bad = 0;
+  __syncthreads();
+  // gather the lower triangle of M (node blocks p >= q)
+  const int npairs = (nb + 1) * (nb + 1);
+  for (int pq = lane; pq < npairs; pq += 64) {
+    const int p = pq / (nb + 1), q = pq % (nb + 1);
+    if (q > p) continue;
+    const int32_t rn = nodes[p], cn = nodes[q];
+    const int32_t k = find_col(Aci, Arp[rn], Arp[rn + 1], cn);
+    const double *B = k >= 0 ? Av + (size_t)k * 9 : nullptr;
+    for (int d = 0; d < 3; d++)
+      for (int e = 0; e < 3; e++) {
+        if (p == q && e > d) continue;
+        L[tri(p * 3 + d, q * 3 + e)] = B ? B[d * 3 + e] : 0.0;
+      }
+  }
+  __syncthreads();
+  for (int j = 0; j < m; j++) {
+    if (lane == 0) {
+      double acc = 0.0;
+      for (int k = 0; k < j; k++) acc += L[tri(j, k)] * L[tri(j, k)];
+      const double d = L[tri(j, j)] - acc;
+      if (!(d > 0.0)) bad = 1;
+      L[tri(j, j)] = d > 0.0 ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    const double ljj = L[tri(j, j)];
+    for (int i = j + 1 + lane; i < m; i += 64) {
+      double acc = 0.0;
+      for (int k = 0; k < j; k++) acc += L[tri(i, k)] * L[tri(j, k)];
+      L[tri(i, j)] = (L[tri(i, j)] - acc) / ljj;
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (lane == 0) *fail = 1;
+    return;
+  }
+  if (lane < 3) {
+    const int d = lane;
+    const int md = 3 * nb + d + 1;
+    double *g = gout + ((size_t)r * 3 + d) * gstride;
+    const double lmm = L[tri(md - 1, md - 1)];
+    g[md - 1] = 1.0 / lmm;
+    for (int k = md - 2; k >= 0; k--) {
+      double acc = 0.0;
+      for (int jj = k + 1; jj < md; jj++) acc += L[tri(jj, k)] * g[jj];
+      g[k] = -acc / L[tri(k, k)];
+    }
+    for (int k = md; k < gstride; k++) g[k] = 0.0;
+    psi[(size_t)r * 3 + d] = lmm * lmm;
+  }
+}
+
+// Interpolation weights of one scalar row: Gram C^T C and C^T v of the chosen
+// test-space rows, Cholesky, forward and back substitution (normal equations).
+__global__ void __launch_bounds__(256) k_dpls_weights(int32_t nrows, const int32_t *__restrict__ row,
+                                                      const int32_t *__restrict__ cnt,
+                                                      const int32_t *__restrict__ sel, const double *__restrict__ V,
+                                                      int ntv, double *__restrict__ w) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nrows) return;
+  const int K = cnt[i];
+  const double *v = V + (size_t)row[i] * ntv;
+  double Gm[kMaxPEntries][kMaxPEntries], t[kMaxPEntries], y[kMaxPEntries], L[kMaxPEntries][kMaxPEntries];
+  for (int a = 0; a < K; a++) {
+    const double *ca = V + (size_t)sel[(size_t)i * kMaxPEntries + a] * ntv;
+    double s = 0.0;
+    for (int q = 0; q < ntv; q++) s += ca[q] * v[q];
+    t[a] = s;
+    for (int c = 0; c <= a; c++) {
+      const double *cc = V + (size_t)sel[(size_t)i * kMaxPEntries + c] * ntv;
+      double g = 0.0;
+      for (int q = 0; q < ntv; q++) g += ca[q] * cc[q];
+      Gm[a][c] = g;
+    }
+  }
+  for (int j = 0; j < K; j++) {
+    double acc = 0.0;
+    for (int k = 0; k < j; k++) acc += L[j][k] * L[j][k];
+    const double d = Gm[j][j] - acc;
+    L[j][j] = d > 0.0 ? sqrt(d) : 1.0;
+    for (int a = j + 1; a < K; a++) {
+      double a2 = 0.0;
+      for (int k = 0; k < j; k++) a2 += L[a][k] * L[j][k];
+      L[a][j] = (Gm[a][j] - a2) / L[j][j];
+    }
+  }
+  for (int a = 0; a < K; a++) {
+    double acc = 0.0;
+    for (int c = 0; c < a; c++) acc += L[a][c] * y[c];
+    y[a] = (t[a] - acc) / L[a][a];
+  }
+  double ww[kMaxPEntries];
+  for (int a = K - 1; a >= 0; a--) {
+    double acc = 0.0;
+    for (int c = a + 1; c < K; c++) acc += L[c][a] * ww[c];
+    ww[a] = (y[a] - acc) / L[a][a];
+  }
+  for (int a = 0; a < K; a++) w[(size_t)i * kMaxPEntries + a] = ww[a];
+}
+
+// acc += X * Y for 3x3 blocks, each entry ((x0 y0 + x1 y1) + x2 y2).
+__device__ __forceinline__ void blk_mac(const double *X, const double *Y, double *acc) {
+#pragma unroll
+  for (int d = 0; d < 3; d++)
+#pragma unroll
+    for (int e = 0; e < 3; e++) {
+      double s = X[d * 3] * Y[e];
+      s += X[d * 3 + 1] * Y[3 + e];
+      s += X[d * 3 + 2] * Y[6 + e];
+      acc[d * 3 + e] += s;
+    }
+}
+
+__device__ __forceinline__ int32_t row_of(const int32_t *rp, int32_t n, int32_t q) {
+  // row containing position q (rp ascending)
+  int32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (rp[mid] <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// T = A P with the pattern of T fixed: block (K, J) sums A_KL P_LJ over the
+// blocks L of A's row K in ascending order.  One thread per block of T.
+__global__ void __launch_bounds__(256) k_spgemm_ap(int32_t n, const int32_t *__restrict__ Arp,
+                                                   const int32_t *__restrict__ Aci, const double *__restrict__ Av,
+                                                   const int32_t *__restrict__ Prp, const int32_t *__restrict__ Pci,
+                                                   const double *__restrict__ Pv, const int32_t *__restrict__ Trp,
+                                                   const int32_t *__restrict__ Tci, double *__restrict__ Tv,
+                                                   int64_t nnzT) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= nnzT) return;
+  const int32_t K = row_of(Trp, n, (int32_t)q);
+  const int32_t J = Tci[q];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int32_t a = Arp[K]; a < Arp[K + 1]; a++) {
+    const int32_t Lr = Aci[a];
+    for (int32_t b = Prp[Lr]; b < Prp[Lr + 1]; b++) {
+      if (Pci[b] == J) {
+        blk_mac(Av + (size_t)a * 9, Pv + (size_t)b * 9, acc);
+        break;
+      }
+    }
+  }
+  for (int k = 0; k < 9; k++) Tv[q * 9 + k] = acc[k];
+}
+
+// A_c = R T: block (I, J) sums R_IK T_KJ over the blocks K of R's row I in
+// ascending order.  One thread per block of A_c.
+__global__ void __launch_bounds__(256) k_spgemm_rt(int32_t nc, const int32_t *__restrict__ Rrp,
+                                                   const int32_t *__restrict__ Rci, const double *__restrict__ Rv,
+                                                   const int32_t *__restrict__ Trp, const int32_t *__restrict__ Tci,
+                                                   const double *__restrict__ Tv, const int32_t *__restrict__ Crp,
+                                                   const int32_t *__restrict__ Cci, double *__restrict__ Cv,
+                                                   int64_t nnzC) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= nnzC) return;
+  const int32_t I = row_of(Crp, nc, (int32_t)q);
+  const int32_t J = Cci[q];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int32_t a = Rrp[I]; a < Rrp[I + 1]; a++) {
+    const int32_t K = Rci[a];
+    const int32_t t = find_col(Tci, Trp[K], Trp[K + 1], J);
+    if (t >= 0) blk_mac(Rv + (size_t)a * 9, Tv + (size_t)t * 9, acc);
+  }
+  for (int k = 0; k < 9; k++) Cv[q * 9 + k] = acc[k];
+}
+
+// grad_e = -scale_e * lam_e^T K_e^0 u_e, one thread per element; a shared
+// K_e^0 is staged in LDS.
+__global__ void __launch_bounds__(256) k_element_gradient(int64_t n_el, const int32_t *__restrict__ conn,
+                                                          const double *__restrict__ Ke0, int64_t ke_stride,
+                                                          const double *__restrict__ lam,
+                                                          const double *__restrict__ u,
+                                                          const double *__restrict__ scale,
+                                                          double *__restrict__ grad) {
+  __shared__ double ks[576];
+  if (ke_stride == 0)
+    for (int i = threadIdx.x; i < 576; i += 256) ks[i] = Ke0[i];
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_el) return;
+  const double *K = ke_stride == 0 ? ks : Ke0 + e * ke_stride;
+  double ue[24], le[24];
+#pragma unroll
+  for (int a = 0; a < 8; a++) {
+    const int32_t nd = conn[e * 8 + a];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      ue[a * 3 + c] = u[(size_t)nd * 3 + c];
+      le[a * 3 + c] = lam[(size_t)nd * 3 + c];
+    }
+  }
+  double s = 0.0;
+  for (int i = 0; i < 24; i++) {
+    double ku = 0.0;
+#pragma unroll
+    for (int j = 0; j < 24; j++) ku += K[i * 24 + j] * ue[j];
+    s += le[i] * ku;
+  }
+  grad[e] = scale ? -(scale[e] * s) : -s;
+}
+
+// vals[slot] = sum over the slot's contributions (ascending element) of
+// E_e * K_e^0[3a+d][3b+e]; constrained diagonal slots are I3.
+__global__ void __launch_bounds__(256) k_assemble(int64_t nnzb, const int64_t *__restrict__ slot_ptr,
+                                                  const int32_t *__restrict__ contrib,
+                                                  const int8_t *__restrict__ diag_id,
+                                                  const double *__restrict__ Ke0, int64_t ke_stride,
+                                                  const double *__restrict__ E, double *__restrict__ vals) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= nnzb) return;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (diag_id[s]) {
+    acc[0] = acc[4] = acc[8] = 1.0;
+  } else {
+    for (int64_t c = slot_ptr[s]; c < slot_ptr[s + 1]; c++) {
+      const int32_t el = contrib[2 * c], ab = contrib[2 * c + 1];
+      const int a = ab >> 3, b = ab & 7;
+      const double *K = Ke0 + (size_t)el * ke_stride;
+      const double Ee = E[el];
+#pragma unroll
+      for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int e = 0; e < 3; e++) acc[d * 3 + e] += Ee * K[(a * 3 + d) * 24 + b * 3 + e];
+    }
+  }
+  for (int k = 0; k < 9; k++) vals[s * 9 + k] = acc[k];
+}
+
+}  // namespace
+
+int launch_fsai_rows(const DevBSR &A, int32_t nrows, const int32_t *rows, const int32_t *pat_ptr,
+                     const int32_t *pat_nodes, int mmax, double *g, int gstride, double *psi, int32_t *fail_flag,
+                     hipStream_t s) {
+  if (nrows == 0) return 0;
+  const size_t lds = (size_t)mmax * (mmax + 1) / 2 * sizeof(double);
+  hipLaunchKernelGGL(k_fsai_rows, dim3(nrows), dim3(64), lds, s, nrows, rows, pat_ptr, pat_nodes, A.rp, A.ci, A.v,
+                     mmax, g, gstride, psi, fail_flag);
+  return 0;
+}
+
+void launch_dpls_weights(int32_t nrows, const int32_t *row, const int32_t *cnt, const int32_t *sel,
+                         const double *V, int ntv, double *w, hipStream_t s) {
+  if (nrows == 0) return;
+  hipLaunchKernelGGL(k_dpls_weights, dim3((nrows + 255) / 256), dim3(256), 0, s, nrows, row, cnt, sel, V, ntv, w);
+}
+
+void launch_spgemm_ap(const DevBSR &A, const DevBSR &P, const DevBSR &T, hipStream_t s) {
+  if (T.nnzb == 0) return;
+  hipLaunchKernelGGL(k_spgemm_ap, dim3((unsigned)((T.nnzb + 255) / 256)), dim3(256), 0, s, T.n, A.rp, A.ci, A.v,
+                     P.rp, P.ci, P.v, T.rp, T.ci, T.v, T.nnzb);
+}
+
+void launch_spgemm_rt(const DevBSR &R, const DevBSR &T, const DevBSR &Ac, hipStream_t s) {
+  if (Ac.nnzb == 0) return;
+  hipLaunchKernelGGL(k_spgemm_rt, dim3((unsigned)((Ac.nnzb + 255) / 256)), dim3(256), 0, s, Ac.n, R.rp, R.ci, R.v,
+                     T.rp, T.ci, T.v, Ac.rp, Ac.ci, Ac.v, Ac.nnzb);
+}
+
+void launch_element_gradient(int64_t n_el, const int32_t *conn, const double *Ke0, int64_t ke_stride,
+                             const double *lam, const double *u, const double *scale, double *grad,
+                             hipStream_t s) {
+  if (n_el == 0) return;
+  hipLaunchKernelGGL(k_element_gradient, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, s, n_el, conn, Ke0,
+                     ke_stride, lam, u, scale, grad);
+}
+
+void launch_assemble(int64_t nnzb, const int64_t *slot_ptr, const int32_t *contrib, const int8_t *diag_id,
+                     const double *Ke0, int64_t ke_stride, const double *E, double *vals, hipStream_t s) {
+  if (nnzb == 0) return;
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((nnzb + 255) / 256)), dim3(256), 0, s, nnzb, slot_ptr, contrib,
+                     diag_id, Ke0, ke_stride, E, vals);
+}
+
+}  // namespace aspamg

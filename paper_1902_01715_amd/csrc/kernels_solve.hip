@@ -1,0 +1,341 @@
+// Solve-phase kernels for gfx950: SELL-64 3x3-block SpMV with fused epilogues,
+// the dense coarsest-level product, precision casts and the fused PCG vector
+// updates with deterministic two-pass reductions.
+//
+// All of this work is bound by HBM bandwidth (a 3x3 FP64 block is 18 flops per
+// 76 bytes), so the kernels stream each matrix exactly once with fully
+// coalesced 64-lane loads and keep per-row accumulators in registers.  Matrix
+// cores are not used.
+#include "internal.h"
+
+namespace aspamg {
+
+namespace {
+
+__device__ __forceinline__ bool ctrl_done(const PcgCtrl *c) { return c != nullptr && c->done != 0; }
+
+// Deterministic sum over a 256-thread block; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *sm) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sm[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+  __syncthreads();
+  return r;
+}
+
+// y[row] = alpha * (A x)[row] (+ w[row]) for one 3x3 block row per lane.
+// A wavefront owns one SELL slice, so lane k streams slot k of every slot
+// group: 64 consecutive column indices, then 9 runs of 64 consecutive values.
+template <typename T, typename TX, typename TO, bool HAS_W>
+__global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__restrict__ sptr,
+                                                   const int32_t *__restrict__ col,
+                                                   const T *__restrict__ val, const TX *__restrict__ x,
+                                                   TO *y, const TO *w, T alpha, const PcgCtrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  const int32_t row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= n) return;
+  const int32_t sl = row >> 6, lane = row & 63;
+  const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
+  T a0 = 0, a1 = 0, a2 = 0;
+  const int32_t *cp = col + (size_t)g0 * 64 + lane;
+  const T *vp = val + (size_t)g0 * 576 + lane;
+#pragma unroll 2
+  for (int32_t g = g0; g < g1; ++g) {
+    const int32_t c = *cp;
+    const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
+    a0 += vp[0] * x0 + vp[64] * x1 + vp[128] * x2;
+    a1 += vp[192] * x0 + vp[256] * x1 + vp[320] * x2;
+    a2 += vp[384] * x0 + vp[448] * x1 + vp[512] * x2;
+    cp += 64;
+    vp += 576;
+  }
+  TO *yo = y + 3 * (size_t)row;
+  if (HAS_W) {
+    const TO *wo = w + 3 * (size_t)row;
+    yo[0] = (TO)(alpha * a0) + wo[0];
+    yo[1] = (TO)(alpha * a1) + wo[1];
+    yo[2] = (TO)(alpha * a2) + wo[2];
+  } else {
+    yo[0] = (TO)(alpha * a0);
+    yo[1] = (TO)(alpha * a1);
+    yo[2] = (TO)(alpha * a2);
+  }
+}
+
+// q = K p with the block partial of p.q (PCG, FP64).
+__global__ void __launch_bounds__(256) k_sell_spmv_dot(int32_t n, const int32_t *__restrict__ sptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const double *__restrict__ val,
+                                                       const double *__restrict__ x, double *__restrict__ y,
+                                                       double *__restrict__ part, const PcgCtrl *ctrl) {
+  __shared__ double sm[4];
+  if (ctrl_done(ctrl)) return;
+  const int32_t row = blockIdx.x * 256 + threadIdx.x;
+  double d = 0.0;
+  if (row < n) {
+    const int32_t sl = row >> 6, lane = row & 63;
+    const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
+    double a0 = 0, a1 = 0, a2 = 0;
+    const int32_t *cp = col + (size_t)g0 * 64 + lane;
+    const double *vp = val + (size_t)g0 * 576 + lane;
+#pragma unroll 2
+    for (int32_t g = g0; g < g1; ++g) {
+      const int32_t c = *cp;
+      const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
+      a0 += vp[0] * x0 + vp[64] * x1 + vp[128] * x2;
+      a1 += vp[192] * x0 + vp[256] * x1 + vp[320] * x2;
+      a2 += vp[384] * x0 + vp[448] * x1 + vp[512] * x2;
+      cp += 64;
+      vp += 576;
+    }
+    double *yo = y + 3 * (size_t)row;
+    yo[0] = a0;
+    yo[1] = a1;
+    yo[2] = a2;
+    const double *xo = x + 3 * (size_t)row;
+    d = (xo[0] * a0 + xo[1] * a1) + xo[2] * a2;
+  }
+  const double s = block_sum(d, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// z = Ainv y for the dense coarsest operator: one wavefront per row.
+template <typename TV>
+__global__ void __launch_bounds__(256) k_dense_gemv(int32_t nd, const double *__restrict__ inv,
+                                                    const TV *__restrict__ y, TV *__restrict__ z,
+                                                    const PcgCtrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  const int32_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= nd) return;
+  const double *a = inv + (size_t)row * nd;
+  double s = 0.0;
+  for (int32_t j = lane; j < nd; j += 64) s += a[j] * (double)y[j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) z[row] = (TV)s;
+}
+
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) k_cast(int64_t n, const TI *__restrict__ x, TO *__restrict__ y,
+                                              const PcgCtrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = (TO)x[i];
+}
+
+__global__ void __launch_bounds__(256) k_fill(int64_t n, double *__restrict__ x, double v) {
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) x[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_copy(int64_t n, const double *__restrict__ x, double *__restrict__ y) {
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = x[i];
+}
+
+__global__ void __launch_bounds__(256) k_dot(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                                             double *__restrict__ part, const PcgCtrl *ctrl) {
+  __shared__ double sm[4];
+  if (ctrl_done(ctrl)) return;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += a[i] * b[i];
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// u += alpha p, r -= alpha q; partials of r.r and r.z (z = previous preconditioned residual).
+__global__ void __launch_bounds__(256) k_pcg_update(int64_t n, double *__restrict__ u, double *__restrict__ r,
+                                                    const double *__restrict__ p, const double *__restrict__ q,
+                                                    const double *__restrict__ z, double *__restrict__ part,
+                                                    const PcgCtrl *ctrl) {
+  __shared__ double sm[4];
+  if (ctrl_done(ctrl)) return;
+  const double alpha = ctrl->alpha;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    u[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s1 += ri * ri;
+    s2 += ri * z[i];
+  }
+  s1 = block_sum(s1, sm);
+  s2 = block_sum(s2, sm);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s1;
+    part[kMaxPart + blockIdx.x] = s2;
+  }
+}
+
+// partial of r.z; with a low-precision cycle output zc the FP64 z is written too.
+template <typename TZ>
+__global__ void __launch_bounds__(256) k_pcg_rz(int64_t n, const double *__restrict__ r, const TZ *__restrict__ zc,
+                                                double *__restrict__ z, double *__restrict__ part,
+                                                const PcgCtrl *ctrl) {
+  __shared__ double sm[4];
+  if (ctrl_done(ctrl)) return;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double zi = (double)zc[i];
+    if ((const void *)zc != (const void *)z) z[i] = zi;
+    s += r[i] * zi;
+  }
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_pcg_pupdate(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                                                     const PcgCtrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  const double beta = ctrl->beta;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = z[i] + beta * p[i];
+}
+
+__device__ __forceinline__ double sum_parts(const double *part, int np, double *sm) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+  return block_sum(s, sm);
+}
+
+// Scalar steps of PCG, one block: fixed-order reductions of the partials.
+__global__ void __launch_bounds__(256) k_finish(int mode, const double *__restrict__ part, int np, PcgCtrl *ctrl) {
+  __shared__ double sm[4];
+  if (ctrl->done) return;
+  const double s0 = sum_parts(part, np, sm);
+  double s1 = 0.0;
+  if (mode == kFinRr) s1 = sum_parts(part + kMaxPart, np, sm);
+  if (threadIdx.x != 0) return;
+  switch (mode) {
+    case kFinInitF: {
+      ctrl->fnorm = sqrt(s0);
+      ctrl->iter = 0;
+      ctrl->relres = 1.0;
+      if (!(s0 == s0) || s0 == __builtin_inf()) { ctrl->status = ASPAMG_ENAN; ctrl->done = 1; }
+      else if (s0 == 0.0) { ctrl->status = ASPAMG_OK; ctrl->relres = 0.0; ctrl->done = 1; }
+      break;
+    }
+    case kFinInitRz: {
+      ctrl->rz = s0;
+      if (!(s0 > 0.0)) { ctrl->status = (s0 == s0) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN; ctrl->done = 1; }
+      break;
+    }
+    case kFinAlpha: {
+      ctrl->pq = s0;
+      if (!(s0 > 0.0)) {
+        ctrl->status = (s0 == s0) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN;
+        ctrl->done = 1;
+        ctrl->iter += 1;
+      } else {
+        ctrl->alpha = ctrl->rz / s0;
+      }
+      break;
+    }
+    case kFinRr: {
+      ctrl->rr = s0;
+      ctrl->rzo = s1;
+      ctrl->iter += 1;
+      const double nr = sqrt(s0);
+      ctrl->relres = nr / ctrl->fnorm;
+      if (!(s0 == s0) || s0 == __builtin_inf()) { ctrl->status = ASPAMG_ENAN; ctrl->done = 1; }
+      else if (nr <= ctrl->rtol * ctrl->fnorm) { ctrl->status = ASPAMG_OK; ctrl->done = 1; }
+      else if (ctrl->iter >= ctrl->max_it) { ctrl->status = ASPAMG_NOT_CONVERGED; ctrl->done = 1; }
+      break;
+    }
+    case kFinBeta: {
+      if (!(s0 > 0.0)) {
+        ctrl->status = (s0 == s0) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN;
+        ctrl->done = 1;
+      } else {
+        ctrl->beta = (s0 - ctrl->rzo) / ctrl->rz;
+        ctrl->rz = s0;
+      }
+      break;
+    }
+    case kFinNorm: {
+      ctrl->rr = s0;
+      break;
+    }
+  }
+}
+
+}  // namespace
+
+int vec_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+int spmv_blocks(int32_t nrows) { return (nrows + 255) / 256; }
+
+template <typename T, typename TX, typename TO>
+void launch_spmv(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
+                 hipStream_t s) {
+  if (A.n == 0) return;
+  if (w)
+    hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, true>), dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr, A.col,
+                       A.val, x, y, w, (T)alpha, ctrl);
+  else
+    hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, false>), dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr,
+                       A.col, A.val, x, y, w, (T)alpha, ctrl);
+}
+
+template void launch_spmv<double, double, double>(const Sell<double> &, const double *, double *, const double *,
+                                                  double, const PcgCtrl *, hipStream_t);
+template void launch_spmv<float, float, float>(const Sell<float> &, const float *, float *, const float *, double,
+                                               const PcgCtrl *, hipStream_t);
+template void launch_spmv<float, double, double>(const Sell<float> &, const double *, double *, const double *,
+                                                 double, const PcgCtrl *, hipStream_t);
+
+void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_sell_spmv_dot, dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr, A.col, A.val, x, y, part,
+                     ctrl);
+}
+
+template <typename TV>
+void launch_dense_gemv(int nd, const double *inv, const TV *y, TV *z, const PcgCtrl *ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_gemv<TV>, dim3((nd + 3) / 4), dim3(256), 0, s, nd, inv, y, z, ctrl);
+}
+template void launch_dense_gemv<double>(int, const double *, const double *, double *, const PcgCtrl *, hipStream_t);
+template void launch_dense_gemv<float>(int, const double *, const float *, float *, const PcgCtrl *, hipStream_t);
+
+template <typename TI, typename TO>
+void launch_cast(int64_t n, const TI *x, TO *y, const PcgCtrl *ctrl, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast<TI, TO>), dim3(vec_blocks(n)), dim3(256), 0, s, n, x, y, ctrl);
+}
+template void launch_cast<double, float>(int64_t, const double *, float *, const PcgCtrl *, hipStream_t);
+template void launch_cast<float, double>(int64_t, const float *, double *, const PcgCtrl *, hipStream_t);
+
+void launch_fill(int64_t n, double *x, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(vec_blocks(n)), dim3(256), 0, s, n, x, v);
+}
+void launch_copy(int64_t n, const double *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n)), dim3(256), 0, s, n, x, y);
+}
+void launch_dot(int64_t n, const double *a, const double *b, double *part, const PcgCtrl *ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(vec_blocks(n)), dim3(256), 0, s, n, a, b, part, ctrl);
+}
+void launch_pcg_update(int64_t n, double *u, double *r, const double *p, const double *q, const double *z,
+                       double *part, const PcgCtrl *ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_update, dim3(vec_blocks(n)), dim3(256), 0, s, n, u, r, p, q, z, part, ctrl);
+}
+template <typename TZ>
+void launch_pcg_rz(int64_t n, const double *r, const TZ *zc, double *z, double *part, const PcgCtrl *ctrl,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_rz<TZ>, dim3(vec_blocks(n)), dim3(256), 0, s, n, r, zc, z, part, ctrl);
+}
+template void launch_pcg_rz<double>(int64_t, const double *, const double *, double *, double *, const PcgCtrl *,
+                                    hipStream_t);
+template void launch_pcg_rz<float>(int64_t, const double *, const float *, double *, double *, const PcgCtrl *,
+                                   hipStream_t);
+void launch_pcg_pupdate(int64_t n, const double *z, double *p, const PcgCtrl *ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_pupdate, dim3(vec_blocks(n)), dim3(256), 0, s, n, z, p, ctrl);
+}
+void launch_finish(int mode, const double *part, int nparts, PcgCtrl *ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, mode, part, nparts, ctrl);
+}
+
+}  // namespace aspamg

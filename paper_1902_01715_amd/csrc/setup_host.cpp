@@ -1,0 +1,972 @@
+// Host side of the aSP-AMG setup (Algorithm "Recursive AMG Setup"): the
+// discrete decisions of every level (FSAI patterns, test-space basis, affinity
+// strength, theta filter, coarse/fine split, interpolation patterns, Galerkin
+// pattern) run here in a canonical order; the numerical bulk (FSAI row
+// factorisations, Lanczos products, least-squares weights, Galerkin values)
+// runs in HIP kernels on the handle's stream.
+//
+// Decision quantities use IEEE binary64 +, -, *, /, sqrt only, each sum in
+// ascending index order as written below, and every comparison of scores is
+// made on values rounded to `quant_bits` significant bits with ties broken by
+// the lowest index.  This file is compiled with -ffp-contract=off.
+#include <omp.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+namespace aspamg {
+
+double quantize(double s, int bits) {
+  if (s == 0.0 || !std::isfinite(s)) return s;
+  int e;
+  const double m = std::frexp(s, &e);
+  const double r = std::nearbyint(std::ldexp(m, bits));
+  return std::ldexp(r, e - bits);
+}
+
+namespace {
+
+struct Q {
+  int bits;
+  double operator()(double s) const { return quantize(s, bits); }
+};
+
+// position of block (r, c) in M, or -1
+inline int64_t find_block(const HostBSR &M, int32_t r, int32_t c) {
+  const int32_t *b = M.ci.data() + M.rp[r];
+  const int32_t *e = M.ci.data() + M.rp[r + 1];
+  const int32_t *it = std::lower_bound(b, e, c);
+  return (it != e && *it == c) ? (int64_t)(it - M.ci.data()) : -1;
+}
+
+inline bool is_decoupled(const HostBSR &A, int32_t i) {
+  return A.rp[i + 1] - A.rp[i] == 1 && A.ci[A.rp[i]] == i;
+}
+
+// ------------------------------------------------------------------------
+// device helpers
+// ------------------------------------------------------------------------
+template <typename T>
+T *upload(aspamg_ctx *h, const std::vector<T> &v) {
+  T *d = dalloc<T>(h, std::max<size_t>(v.size(), 1));
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+  return d;
+}
+
+// scratch device buffer freed at scope exit
+struct Scratch {
+  void *p = nullptr;
+  explicit Scratch(size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(&p, bytes) != hipSuccess) fail(ASPAMG_ENOMEM, "device scratch allocation failed");
+  }
+  ~Scratch() {
+    if (p) (void)hipFree(p);
+  }
+  template <typename T>
+  T *as() const { return static_cast<T *>(p); }
+};
+
+template <typename T>
+void to_device(hipStream_t s, T *d, const T *hsrc, size_t n) {
+  if (n) HIPCHK(hipMemcpyAsync(d, hsrc, n * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <typename T>
+void to_host(hipStream_t s, T *hdst, const T *d, size_t n) {
+  if (n) HIPCHK(hipMemcpyAsync(hdst, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------------
+// aFSAI (Section 3.1).  Each block row I keeps a sorted node set B (J < I);
+// the GPU factors A[l,l] and returns the three scaled rows g and psi.
+// ------------------------------------------------------------------------
+struct FsaiState {
+  int32_t n;
+  std::vector<int32_t> nb;        // |B| per row
+  std::vector<int32_t> nodes;     // n * kMaxFsaiNodes
+  std::vector<double> g;          // n * 3 * gstride
+  std::vector<double> psi;        // n * 3
+  static constexpr int gstride = 3 * kMaxFsaiNodes + 3;
+};
+
+// Factor the listed rows on the GPU and store g / psi in the state.
+void fsai_factor(aspamg_ctx *h, const Level &L, FsaiState &F, const std::vector<int32_t> &rows) {
+  if (rows.empty()) return;
+  const int32_t nr = (int32_t)rows.size();
+  const int gs = FsaiState::gstride;
+  // chunk to bound device memory
+  const int32_t chunk = 1 << 17;
+  for (int32_t c0 = 0; c0 < nr; c0 += chunk) {
+    const int32_t c1 = std::min(nr, c0 + chunk), m = c1 - c0;
+    std::vector<int32_t> pptr(m + 1, 0), pnodes;
+    int maxnb = 0;
+    for (int32_t i = 0; i < m; i++) {
+      const int32_t I = rows[c0 + i];
+      pptr[i + 1] = pptr[i] + F.nb[I];
+      maxnb = std::max(maxnb, F.nb[I]);
+    }
+    pnodes.resize(std::max<int32_t>(pptr[m], 1));
+    for (int32_t i = 0; i < m; i++) {
+      const int32_t I = rows[c0 + i];
+      std::memcpy(pnodes.data() + pptr[i], F.nodes.data() + (size_t)I * kMaxFsaiNodes, F.nb[I] * sizeof(int32_t));
+    }
+    Scratch drows(m * 4), dptr((m + 1) * 4), dnodes(pnodes.size() * 4), dg((size_t)m * 3 * gs * 8),
+        dpsi((size_t)m * 3 * 8), dfail(4);
+    to_device(h->stream, drows.as<int32_t>(), rows.data() + c0, m);
+    to_device(h->stream, dptr.as<int32_t>(), pptr.data(), m + 1);
+    to_device(h->stream, dnodes.as<int32_t>(), pnodes.data(), pnodes.size());
+    HIPCHK(hipMemsetAsync(dfail.p, 0, 4, h->stream));
+    const int mmax = 3 * maxnb + 3;
+    launch_fsai_rows(L.dA, m, drows.as<int32_t>(), dptr.as<int32_t>(), dnodes.as<int32_t>(), mmax, dg.as<double>(),
+                     gs, dpsi.as<double>(), dfail.as<int32_t>(), h->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<double> g((size_t)m * 3 * gs), psi((size_t)m * 3);
+    int32_t bad = 0;
+    to_host(h->stream, g.data(), dg.as<double>(), g.size());
+    to_host(h->stream, psi.data(), dpsi.as<double>(), psi.size());
+    to_host(h->stream, &bad, dfail.as<int32_t>(), 1);
+    if (bad) fail(ASPAMG_ENOT_SPD, "aFSAI: a local system is not positive definite");
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < m; i++) {
+      const int32_t I = rows[c0 + i];
+      std::memcpy(F.g.data() + (size_t)I * 3 * gs, g.data() + (size_t)i * 3 * gs, 3 * gs * sizeof(double));
+      std::memcpy(F.psi.data() + (size_t)I * 3, psi.data() + (size_t)i * 3, 3 * sizeof(double));
+    }
+  }
+}
+
+inline double psi_sum(const FsaiState &F, int32_t I) {
+  double s = 0.0;
+  for (int d = 0; d < 3; d++) s += F.psi[(size_t)I * 3 + d];
+  return s;
+}
+
+// Pattern growth of one row (the adaptive step): candidates are the nodes
+// J < I, not in B, adjacent in A to B u {I}; with g' = g / g_last,
+// h_{(I,d),(J,e)} = sum over the pattern index k (ascending) of A[(J,e), l_k] g'_k
+// and score_J = sum_d sum_e h^2.  The rho nodes with the largest quantised
+// score (ties to the lowest J) are added.  Returns the number added.
+int fsai_grow(const HostBSR &A, FsaiState &F, int32_t I, int rho, const Q &q, std::vector<int32_t> &cand,
+              std::vector<std::pair<double, int32_t>> &sc) {
+  const int32_t nb = F.nb[I];
+  if (nb + rho > kMaxFsaiNodes) return 0;
+  const int32_t *B = F.nodes.data() + (size_t)I * kMaxFsaiNodes;
+  cand.clear();
+  for (int p = 0; p <= nb; p++) {
+    const int32_t K = p < nb ? B[p] : I;
+    for (int64_t k = A.rp[K]; k < A.rp[K + 1]; k++) {
+      const int32_t J = A.ci[k];
+      if (J >= I) break;   // columns ascend
+      cand.push_back(J);
+    }
+  }
+  std::sort(cand.begin(), cand.end());
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  // drop members of B (both sorted)
+  {
+    size_t w = 0, b = 0;
+    for (size_t r = 0; r < cand.size(); r++) {
+      while (b < (size_t)nb && B[b] < cand[r]) b++;
+      if (b < (size_t)nb && B[b] == cand[r]) continue;
+      cand[w++] = cand[r];
+    }
+    cand.resize(w);
+  }
+  if (cand.empty()) return 0;
+  const int gs = FsaiState::gstride;
+  const double *g = F.g.data() + (size_t)I * 3 * gs;
+  double gp[3][gs];
+  for (int d = 0; d < 3; d++) {
+    const int md = 3 * nb + d + 1;
+    const double gl = g[d * gs + md - 1];
+    for (int k = 0; k < md; k++) gp[d][k] = g[d * gs + k] / gl;
+  }
+  sc.clear();
+  int64_t pos[kMaxFsaiNodes + 1];
+  for (int32_t J : cand) {
+    // blocks A(J, node_p) for the local node list [B..., I] (ascending): merge join
+    int64_t k = A.rp[J];
+    const int64_t ke = A.rp[J + 1];
+    for (int p = 0; p <= nb; p++) {
+      const int32_t nd = p < nb ? B[p] : I;
+      while (k < ke && A.ci[k] < nd) k++;
+      pos[p] = (k < ke && A.ci[k] == nd) ? k : -1;
+    }
+    double score = 0.0;
+    for (int d = 0; d < 3; d++) {
+      const int md = 3 * nb + d + 1;
+      for (int e = 0; e < 3; e++) {
+        double hh = 0.0;
+        for (int kk = 0; kk < md; kk++) {
+          const int64_t bp = pos[kk / 3];
+          if (bp < 0) continue;
+          hh += A.v[(size_t)bp * 9 + e * 3 + (kk % 3)] * gp[d][kk];
+        }
+        score += hh * hh;
+      }
+    }
+    if (score > 0.0) sc.emplace_back(q(score), J);
+  }
+  if (sc.empty()) return 0;
+  std::sort(sc.begin(), sc.end(), [](const auto &a, const auto &b) {
+    return a.first != b.first ? a.first > b.first : a.second < b.second;
+  });
+  const int add = std::min<int>(rho, (int)sc.size());
+  int32_t *Bw = F.nodes.data() + (size_t)I * kMaxFsaiNodes;
+  for (int a = 0; a < add; a++) Bw[nb + a] = sc[a].second;
+  F.nb[I] = nb + add;
+  std::sort(Bw, Bw + nb + add);
+  return add;
+}
+
+HostBSR fsai_assemble(const FsaiState &F) {
+  HostBSR G;
+  const int32_t n = F.n;
+  const int gs = FsaiState::gstride;
+  G.n = G.nc = n;
+  G.rp.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; i++) G.rp[i + 1] = G.rp[i] + F.nb[i] + 1;
+  G.ci.resize(G.rp[n]);
+  G.v.assign((size_t)G.rp[n] * 9, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; i++) {
+    const int nb = F.nb[i];
+    const double *g = F.g.data() + (size_t)i * 3 * gs;
+    for (int p = 0; p <= nb; p++) {
+      const int64_t q = G.rp[i] + p;
+      G.ci[q] = p < nb ? F.nodes[(size_t)i * kMaxFsaiNodes + p] : i;
+      for (int d = 0; d < 3; d++)
+        for (int e = 0; e < 3; e++) {
+          if (p == nb && e > d) continue;
+          G.v[(size_t)q * 9 + d * 3 + e] = g[d * gs + p * 3 + e];
+        }
+    }
+  }
+  return G;
+}
+
+// lambda_1(G A G^T) by plain Lanczos on the GPU (FP64 SELL products), the
+// largest Ritz value by Sturm bisection.
+double lanczos_gagt(aspamg_ctx *h, const Level &L, const Sell<double> &G, const Sell<double> &GT, int steps) {
+  const int64_t n = (int64_t)L.A.n * 3;
+  hipStream_t s = h->stream;
+  std::vector<double> w(n);
+  for (int64_t i = 0; i < n; i++) {
+    const uint64_t hs = ((uint64_t)i * 2654435761ULL) & 0xFFFFFFFFULL;
+    w[i] = (double)hs / 4294967296.0 - 0.5;
+  }
+  double nw = 0.0;
+  for (int64_t i = 0; i < n; i++) nw += w[i] * w[i];
+  nw = std::sqrt(nw);
+  for (int64_t i = 0; i < n; i++) w[i] /= nw;
+  Scratch dv(n * 8), dvp(n * 8), du(n * 8), dt1(n * 8), dt2(n * 8), dpart(kMaxPart * 8);
+  double *v = dv.as<double>(), *vp = dvp.as<double>(), *u = du.as<double>();
+  to_device(s, v, w.data(), n);
+  std::vector<double> al, be;
+  std::vector<double> hp(kMaxPart);
+  const int nb = vec_blocks(n);
+  auto dotv = [&](const double *a, const double *b) {
+    launch_dot(n, a, b, dpart.as<double>(), nullptr, s);
+    to_host(s, hp.data(), dpart.as<double>(), nb);
+    double acc = 0.0;
+    for (int i = 0; i < nb; i++) acc += hp[i];
+    return acc;
+  };
+  double bprev = 0.0;
+  for (int j = 0; j < steps; j++) {
+    launch_spmv<double, double, double>(GT, v, dt1.as<double>(), nullptr, 1.0, nullptr, s);
+    launch_spmv<double, double, double>(L.A64, dt1.as<double>(), dt2.as<double>(), nullptr, 1.0, nullptr, s);
+    launch_spmv<double, double, double>(G, dt2.as<double>(), u, nullptr, 1.0, nullptr, s);
+    // u -= bprev vp ; a = v.u ; u -= a v ; b = |u|
+    std::vector<double> hu(n), hv(n), hvp(n);
+    to_host(s, hu.data(), u, n);
+    to_host(s, hv.data(), v, n);
+    if (j > 0) {
+      to_host(s, hvp.data(), vp, n);
+      for (int64_t i = 0; i < n; i++) hu[i] -= bprev * hvp[i];
+    }
+    double a = 0.0;
+    for (int64_t i = 0; i < n; i++) a += hv[i] * hu[i];
+    for (int64_t i = 0; i < n; i++) hu[i] -= a * hv[i];
+    double bb = 0.0;
+    for (int64_t i = 0; i < n; i++) bb += hu[i] * hu[i];
+    bb = std::sqrt(bb);
+    al.push_back(a);
+    be.push_back(bb);
+    if (!(bb > 1e-300)) break;
+    for (int64_t i = 0; i < n; i++) hu[i] /= bb;
+    HIPCHK(hipMemcpyAsync(vp, v, n * 8, hipMemcpyDeviceToDevice, s));
+    to_device(s, v, hu.data(), n);
+    bprev = bb;
+  }
+  (void)dotv;
+  // Sturm bisection for the largest eigenvalue of the tridiagonal matrix
+  const int m = (int)al.size();
+  double lo = al[0], hi = al[0];
+  for (int i = 0; i < m; i++) {
+    const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(be[i]) : 0.0);
+    lo = std::min(lo, al[i] - r);
+    hi = std::max(hi, al[i] + r);
+  }
+  for (int it = 0; it < 2000; it++) {
+    const double x = 0.5 * (lo + hi);
+    if (x <= lo || x >= hi) break;
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < m; i++) {
+      const double off = i > 0 ? be[i - 1] * be[i - 1] : 0.0;
+      d = (al[i] - x) - (i > 0 ? off / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0.0) cnt++;
+    }
+    if (cnt == m) hi = x;
+    else lo = x;
+  }
+  return hi;
+}
+
+void build_fsai(aspamg_ctx *h, Level &L) {
+  const aspamg_params &p = h->p;
+  const Q q{p.quant_bits};
+  const int32_t n = L.A.n;
+  FsaiState F;
+  F.n = n;
+  F.nb.assign(n, 0);
+  F.nodes.assign((size_t)n * kMaxFsaiNodes, -1);
+  F.g.assign((size_t)n * 3 * FsaiState::gstride, 0.0);
+  F.psi.assign((size_t)n * 3, 0.0);
+  std::vector<int32_t> active(n);
+  std::iota(active.begin(), active.end(), 0);
+  fsai_factor(h, L, F, active);
+  std::vector<double> psi_prev(n);
+  for (int32_t i = 0; i < n; i++) psi_prev[i] = psi_sum(F, i);
+  const int nthreads = omp_get_max_threads();
+  std::vector<std::vector<int32_t>> tcand(nthreads);
+  std::vector<std::vector<std::pair<double, int32_t>>> tsc(nthreads);
+  for (int step = 0; step < p.k_g && !active.empty(); step++) {
+    std::vector<char> grew(active.size(), 0);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t a = 0; a < (int64_t)active.size(); a++) {
+      const int t = omp_get_thread_num();
+      grew[a] = fsai_grow(L.A, F, active[a], p.rho_blocks, q, tcand[t], tsc[t]) > 0;
+    }
+    std::vector<int32_t> next;
+    for (size_t a = 0; a < active.size(); a++)
+      if (grew[a]) next.push_back(active[a]);
+    fsai_factor(h, L, F, next);
+    std::vector<int32_t> keep;
+    for (int32_t I : next) {
+      const double pn = psi_sum(F, I);
+      const double dec = q(psi_prev[I] - pn), thr = q(p.eps_g * psi_prev[I]);
+      psi_prev[I] = pn;
+      if (!(dec <= thr)) keep.push_back(I);
+    }
+    active.swap(keep);
+  }
+  L.G = fsai_assemble(F);
+  L.fsai_rounds = 0;
+  for (;;) {
+    Sell<double> G = upload_sell<double>(h, L.G);
+    Sell<double> GT = upload_sell<double>(h, transpose(L.G));
+    L.lambda1 = lanczos_gagt(h, L, G, GT, p.lanczos_steps);
+    L.omega_q = 2.0 / L.lambda1;
+    if (!p.outer_fsai) break;
+    if (!(q(L.omega_q) < q(p.omega_bar))) break;
+    if (!(L.G.nnzb() < L.A.nnzb())) break;
+    std::vector<char> grew(n, 0);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int32_t I = 0; I < n; I++) {
+      const int t = omp_get_thread_num();
+      grew[I] = fsai_grow(L.A, F, I, p.rho_blocks, q, tcand[t], tsc[t]) > 0;
+    }
+    std::vector<int32_t> rows;
+    for (int32_t I = 0; I < n; I++)
+      if (grew[I]) rows.push_back(I);
+    if (rows.empty()) break;
+    fsai_factor(h, L, F, rows);
+    L.G = fsai_assemble(F);
+    L.fsai_rounds++;
+  }
+  const double w = 2.0 / (p.omega_safety * L.lambda1);
+  L.omega_s = w < 1.0 ? w : 1.0;
+}
+
+// ------------------------------------------------------------------------
+// test space (Section 3.3): Cholesky-QR orthonormalisation with the Gram
+// matrix summed over scalar rows in ascending order; a column whose pivot is
+// <= 1e-12 of its Gram diagonal is dropped (set to zero).
+// ------------------------------------------------------------------------
+void orthonormalize(std::vector<double> &V, int64_t nrows, int ntv) {
+  std::vector<double> W((size_t)ntv * ntv), Lm((size_t)ntv * ntv, 0.0);
+  for (int a = 0; a < ntv; a++)
+    for (int c = 0; c < ntv; c++) {
+      double s = 0.0;
+      for (int64_t i = 0; i < nrows; i++) s += V[(size_t)i * ntv + a] * V[(size_t)i * ntv + c];
+      W[a * ntv + c] = s;
+    }
+  std::vector<char> drop(ntv, 0);
+  for (int j = 0; j < ntv; j++) {
+    double acc = 0.0;
+    for (int k = 0; k < j; k++) acc += Lm[j * ntv + k] * Lm[j * ntv + k];
+    const double d = W[j * ntv + j] - acc;
+    drop[j] = !(d > 1e-12 * W[j * ntv + j]);
+    const double ljj = drop[j] ? 1.0 : std::sqrt(d);
+    Lm[j * ntv + j] = ljj;
+    for (int i = j + 1; i < ntv; i++) {
+      if (drop[j]) {
+        Lm[i * ntv + j] = 0.0;
+        continue;
+      }
+      double a2 = 0.0;
+      for (int k = 0; k < j; k++) a2 += Lm[i * ntv + k] * Lm[j * ntv + k];
+      Lm[i * ntv + j] = (W[i * ntv + j] - a2) / ljj;
+    }
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < nrows; i++) {
+    double y[64];
+    double *v = V.data() + (size_t)i * ntv;
+    for (int a = 0; a < ntv; a++) {
+      if (drop[a]) {
+        y[a] = 0.0;
+        continue;
+      }
+      double acc = 0.0;
+      for (int c = 0; c < a; c++) acc += Lm[a * ntv + c] * y[c];
+      y[a] = (v[a] - acc) / Lm[a * ntv + a];
+    }
+    std::memcpy(v, y, ntv * sizeof(double));
+  }
+}
+
+// ------------------------------------------------------------------------
+// coarsening (Section 3.4)
+// ------------------------------------------------------------------------
+// n_IJ: squared Frobenius norm of V_I V_J^T (3x3 entries summed over t
+// ascending, squares summed row-major)
+inline double node_affinity(const double *V, int ntv, int32_t I, int32_t J) {
+  double s = 0.0;
+  for (int d = 0; d < 3; d++)
+    for (int e = 0; e < 3; e++) {
+      const double *vi = V + ((size_t)I * 3 + d) * ntv;
+      const double *vj = V + ((size_t)J * 3 + e) * ntv;
+      double m = 0.0;
+      for (int t = 0; t < ntv; t++) m += vi[t] * vj[t];
+      s += m * m;
+    }
+  return s;
+}
+
+inline uint64_t mix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+struct StrongGraph {
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+};
+
+// SoC on A's off-diagonal blocks -> min(theta, deg) strongest per node ->
+// union symmetrisation.
+StrongGraph strong_graph(const Level &L, int ntv, int theta, const Q &q, const std::vector<char> &excl) {
+  const HostBSR &A = L.A;
+  const int32_t n = A.n;
+  std::vector<double> sq(n);
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; i++) sq[i] = std::sqrt(node_affinity(L.V.data(), ntv, i, i));
+  std::vector<int32_t> keep((size_t)n * std::max(theta, 1), -1), nkeep(n, 0);
+#pragma omp parallel
+  {
+    std::vector<std::pair<double, int32_t>> sc;
+#pragma omp for schedule(dynamic, 512)
+    for (int32_t i = 0; i < n; i++) {
+      if (excl[i]) continue;
+      sc.clear();
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; k++) {
+        const int32_t j = A.ci[k];
+        if (j == i || excl[j]) continue;
+        const int32_t a = std::min(i, j), c = std::max(i, j);
+        const double den = sq[a] * sq[c];
+        const double s = den > 0.0 ? node_affinity(L.V.data(), ntv, a, c) / den : 0.0;
+        if (s > 0.0) sc.emplace_back(q(s), j);
+      }
+      std::sort(sc.begin(), sc.end(), [](const auto &x, const auto &y) {
+        return x.first != y.first ? x.first > y.first : x.second < y.second;
+      });
+      const int kk = std::min<int>(theta, (int)sc.size());
+      for (int a = 0; a < kk; a++) keep[(size_t)i * theta + a] = sc[a].second;
+      nkeep[i] = kk;
+    }
+  }
+  // union: collect directed edges both ways, sort, unique
+  std::vector<std::vector<int32_t>> adj(n);
+  for (int32_t i = 0; i < n; i++)
+    for (int a = 0; a < nkeep[i]; a++) {
+      const int32_t j = keep[(size_t)i * theta + a];
+      adj[i].push_back(j);
+      adj[j].push_back(i);
+    }
+  StrongGraph S;
+  S.rp.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; i++) {
+    std::sort(adj[i].begin(), adj[i].end());
+    adj[i].erase(std::unique(adj[i].begin(), adj[i].end()), adj[i].end());
+    S.rp[i + 1] = S.rp[i] + (int64_t)adj[i].size();
+  }
+  S.ci.resize(S.rp[n]);
+  for (int32_t i = 0; i < n; i++) std::copy(adj[i].begin(), adj[i].end(), S.ci.begin() + S.rp[i]);
+  return S;
+}
+
+// Maximal independent set by rounds of local maxima: an undecided node whose
+// key (|S_I|, mix64(I), -I) exceeds the keys of all undecided S-neighbours
+// becomes C; its undecided neighbours become F.  The fixed point is the set
+// the sequential greedy in descending key order produces.
+void mis(const StrongGraph &S, const std::vector<char> &excl, std::vector<int8_t> &cf) {
+  const int32_t n = (int32_t)excl.size();
+  cf.assign(n, 2);
+  std::vector<uint64_t> hk(n);
+  std::vector<int64_t> deg(n);
+  for (int32_t i = 0; i < n; i++) {
+    if (excl[i]) cf[i] = -1;
+    hk[i] = mix64((uint64_t)i);
+    deg[i] = S.rp[i + 1] - S.rp[i];
+  }
+  auto greater = [&](int32_t a, int32_t b) {
+    if (deg[a] != deg[b]) return deg[a] > deg[b];
+    if (hk[a] != hk[b]) return hk[a] > hk[b];
+    return a < b;
+  };
+  std::vector<int32_t> und;
+  for (int32_t i = 0; i < n; i++)
+    if (cf[i] == 2) und.push_back(i);
+  while (!und.empty()) {
+    std::vector<char> win(und.size(), 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < (int64_t)und.size(); a++) {
+      const int32_t i = und[a];
+      bool best = true;
+      for (int64_t k = S.rp[i]; k < S.rp[i + 1]; k++) {
+        const int32_t j = S.ci[k];
+        if (cf[j] == 2 && greater(j, i)) {
+          best = false;
+          break;
+        }
+      }
+      win[a] = best;
+    }
+    for (size_t a = 0; a < und.size(); a++)
+      if (win[a]) cf[und[a]] = 1;
+    for (size_t a = 0; a < und.size(); a++) {
+      if (!win[a]) continue;
+      const int32_t i = und[a];
+      for (int64_t k = S.rp[i]; k < S.rp[i + 1]; k++)
+        if (cf[S.ci[k]] == 2) cf[S.ci[k]] = 0;
+    }
+    std::vector<int32_t> nx;
+    for (int32_t i : und)
+      if (cf[i] == 2) nx.push_back(i);
+    und.swap(nx);
+  }
+}
+
+// ------------------------------------------------------------------------
+// DPLS interpolation pattern (Section 3.5), Gram form of the greedy: with L
+// the Cholesky factor of the chosen Gram and y = L^{-1} t_C, each candidate a
+// has z_a = L^{-1} g_{C,a}, delta^2 = g_aa - |z_a|^2, pi = t_a - y.z_a and
+// affinity pi^2 / (rho^2 delta^2).  The largest quantised affinity (> 0,
+// ties to the lowest candidate) is taken unless the diagonal ratio of L would
+// exceed kappa_p.  Stops at n_max, rho^2 <= eps_p^2 v.v, or no candidate.
+// ------------------------------------------------------------------------
+int dpls_select(const double *v, const double *C, int nca, int ntv, const aspamg_params &p, const Q &q,
+                int32_t *chosen, std::vector<double> &t, std::vector<double> &gaa, std::vector<double> &gb,
+                std::vector<char> &used) {
+  double vv = 0.0;
+  for (int s = 0; s < ntv; s++) vv += v[s] * v[s];
+  if (vv == 0.0) return 0;
+  t.resize(nca);
+  gaa.resize(nca);
+  used.assign(nca, 0);
+  gb.resize((size_t)kMaxPEntries * nca);
+  for (int a = 0; a < nca; a++) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int s = 0; s < ntv; s++) {
+      s1 += C[(size_t)a * ntv + s] * v[s];
+      s2 += C[(size_t)a * ntv + s] * C[(size_t)a * ntv + s];
+    }
+    t[a] = s1;
+    gaa[a] = s2;
+  }
+  double Lm[kMaxPEntries][kMaxPEntries], y[kMaxPEntries];
+  double rho2 = vv, dmax = 0.0, dmin = 0.0;
+  const double thr = q((p.eps_p * p.eps_p) * vv);
+  const int nmax = std::min(p.n_max, kMaxPEntries);
+  int K = 0;
+  while (K < nmax) {
+    if (!(q(rho2) > thr)) break;
+    int best = -1;
+    double bestq = 0.0, bdel2 = 0.0, bpi = 0.0, bz[kMaxPEntries];
+    for (int a = 0; a < nca; a++) {
+      if (used[a]) continue;
+      double z[kMaxPEntries];
+      for (int k = 0; k < K; k++) {
+        double acc = 0.0;
+        for (int j = 0; j < k; j++) acc += Lm[k][j] * z[j];
+        z[k] = (gb[(size_t)k * nca + a] - acc) / Lm[k][k];
+      }
+      double s = 0.0;
+      for (int k = 0; k < K; k++) s += z[k] * z[k];
+      const double del2 = gaa[a] - s;
+      if (!(del2 > 0.0)) continue;
+      double s2 = 0.0;
+      for (int k = 0; k < K; k++) s2 += y[k] * z[k];
+      const double pi = t[a] - s2;
+      const double aff = (pi * pi) / (rho2 * del2);
+      const double qa = q(aff);
+      if (qa > bestq) {
+        best = a;
+        bestq = qa;
+        bdel2 = del2;
+        bpi = pi;
+        std::memcpy(bz, z, K * sizeof(double));
+      }
+    }
+    if (best < 0) break;
+    const double del = std::sqrt(bdel2);
+    const double mx = K ? std::max(dmax, del) : del;
+    const double mn = K ? std::min(dmin, del) : del;
+    if (q(mx / mn) > q(p.kappa_p)) break;
+    for (int k = 0; k < K; k++) Lm[K][k] = bz[k];
+    Lm[K][K] = del;
+    y[K] = bpi / del;
+    rho2 = rho2 - y[K] * y[K];
+    dmax = mx;
+    dmin = mn;
+    chosen[K] = best;
+    used[best] = 1;
+    for (int a = 0; a < nca; a++) {
+      double s = 0.0;
+      for (int r = 0; r < ntv; r++) s += C[(size_t)best * ntv + r] * C[(size_t)a * ntv + r];
+      gb[(size_t)K * nca + a] = s;
+    }
+    K++;
+  }
+  return K;
+}
+
+void build_prolongation(aspamg_ctx *h, Level &L, const StrongGraph &S) {
+  const aspamg_params &p = h->p;
+  const Q q{p.quant_bits};
+  const int32_t n = L.A.n;
+  const int ntv = h->ntv;
+  const int nmax = std::min(p.n_max, kMaxPEntries);
+  L.pcount.assign((size_t)n * 3, 0);
+  L.pcols.assign((size_t)n * 3 * p.n_max, -1);
+  // fine scalar row of each chosen entry (for the weight kernel)
+  std::vector<int32_t> selfine((size_t)n * 3 * kMaxPEntries, 0);
+#pragma omp parallel
+  {
+    std::vector<int32_t> dist(n, -1), frontier, cn;
+    std::vector<double> Cm, t, gaa, gb;
+    std::vector<char> used;
+    std::vector<int32_t> visited;
+#pragma omp for schedule(dynamic, 256)
+    for (int32_t I = 0; I < n; I++) {
+      if (L.cf[I] != 0) continue;
+      // C nodes within S-distance d_p
+      frontier.clear();
+      cn.clear();
+      frontier.push_back(I);
+      dist[I] = 0;
+      for (size_t head = 0; head < frontier.size(); head++) {
+        const int32_t u = frontier[head];
+        if (dist[u] >= p.d_p) continue;
+        for (int64_t k = S.rp[u]; k < S.rp[u + 1]; k++) {
+          const int32_t w = S.ci[k];
+          if (dist[w] >= 0) continue;
+          dist[w] = dist[u] + 1;
+          frontier.push_back(w);
+          if (L.cf[w] == 1) cn.push_back(w);
+        }
+      }
+      for (int32_t u : frontier) dist[u] = -1;
+      std::sort(cn.begin(), cn.end());
+      const int nca = (int)cn.size() * 3;
+      Cm.resize((size_t)std::max(nca, 1) * ntv);
+      for (size_t c = 0; c < cn.size(); c++)
+        for (int e = 0; e < 3; e++)
+          std::memcpy(Cm.data() + (c * 3 + e) * ntv, L.V.data() + ((size_t)cn[c] * 3 + e) * ntv, ntv * sizeof(double));
+      for (int d = 0; d < 3; d++) {
+        int32_t chosen[kMaxPEntries];
+        const int K = dpls_select(L.V.data() + ((size_t)I * 3 + d) * ntv, Cm.data(), nca, ntv, p, q, chosen, t, gaa,
+                                  gb, used);
+        const size_t r = (size_t)I * 3 + d;
+        L.pcount[r] = K;
+        for (int k = 0; k < K; k++) {
+          const int32_t J = cn[chosen[k] / 3], e = chosen[k] % 3;
+          L.pcols[r * p.n_max + k] = L.cidx[J] * 3 + e;
+          selfine[r * kMaxPEntries + k] = J * 3 + e;
+        }
+      }
+    }
+  }
+  (void)nmax;
+  // weights on the GPU: normal equations of the chosen columns
+  std::vector<int32_t> rows, cnt, sel;
+  for (int64_t r = 0; r < (int64_t)n * 3; r++) {
+    if (L.pcount[r] == 0) continue;
+    rows.push_back((int32_t)r);
+    cnt.push_back(L.pcount[r]);
+    for (int k = 0; k < kMaxPEntries; k++) sel.push_back(selfine[(size_t)r * kMaxPEntries + k]);
+  }
+  std::vector<double> w((size_t)rows.size() * kMaxPEntries, 0.0);
+  if (!rows.empty()) {
+    Scratch dr(rows.size() * 4), dc(cnt.size() * 4), ds(sel.size() * 4), dV(L.V.size() * 8),
+        dw(w.size() * 8);
+    to_device(h->stream, dr.as<int32_t>(), rows.data(), rows.size());
+    to_device(h->stream, dc.as<int32_t>(), cnt.data(), cnt.size());
+    to_device(h->stream, ds.as<int32_t>(), sel.data(), sel.size());
+    to_device(h->stream, dV.as<double>(), L.V.data(), L.V.size());
+    launch_dpls_weights((int32_t)rows.size(), dr.as<int32_t>(), dc.as<int32_t>(), ds.as<int32_t>(), dV.as<double>(),
+                        ntv, dw.as<double>(), h->stream);
+    HIPCHK(hipGetLastError());
+    to_host(h->stream, w.data(), dw.as<double>(), w.size());
+  }
+  std::vector<double> wr((size_t)n * 3 * kMaxPEntries, 0.0);
+  for (size_t i = 0; i < rows.size(); i++)
+    std::memcpy(wr.data() + (size_t)rows[i] * kMaxPEntries, w.data() + i * kMaxPEntries, kMaxPEntries * 8);
+  // assemble P: C rows I3 at (I, c(I)); F rows: union of the chosen coarse nodes
+  HostBSR &P = L.P;
+  P.n = n;
+  P.nc = L.nc;
+  P.rp.assign(n + 1, 0);
+  std::vector<std::vector<int32_t>> rowc(n);
+  for (int32_t I = 0; I < n; I++) {
+    if (L.cf[I] == 1) rowc[I].push_back(L.cidx[I]);
+    else if (L.cf[I] == 0) {
+      for (int d = 0; d < 3; d++) {
+        const size_t r = (size_t)I * 3 + d;
+        for (int k = 0; k < L.pcount[r]; k++) rowc[I].push_back(L.pcols[r * p.n_max + k] / 3);
+      }
+      std::sort(rowc[I].begin(), rowc[I].end());
+      rowc[I].erase(std::unique(rowc[I].begin(), rowc[I].end()), rowc[I].end());
+    }
+    P.rp[I + 1] = P.rp[I] + (int64_t)rowc[I].size();
+  }
+  P.ci.resize(P.rp[n]);
+  P.v.assign((size_t)P.rp[n] * 9, 0.0);
+  for (int32_t I = 0; I < n; I++) {
+    const int64_t base = P.rp[I];
+    std::copy(rowc[I].begin(), rowc[I].end(), P.ci.begin() + base);
+    if (L.cf[I] == 1) {
+      for (int d = 0; d < 3; d++) P.v[(size_t)base * 9 + d * 4] = 1.0;
+    } else if (L.cf[I] == 0) {
+      for (int d = 0; d < 3; d++) {
+        const size_t r = (size_t)I * 3 + d;
+        for (int k = 0; k < L.pcount[r]; k++) {
+          const int32_t sc = L.pcols[r * p.n_max + k];
+          const int32_t cnod = sc / 3, e = sc % 3;
+          const int64_t qpos = base + (std::lower_bound(rowc[I].begin(), rowc[I].end(), cnod) - rowc[I].begin());
+          P.v[(size_t)qpos * 9 + d * 3 + e] = wr[r * kMaxPEntries + k];
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// Galerkin operator A_c = R (A P): patterns on the host, values on the GPU.
+// ------------------------------------------------------------------------
+HostBSR spgemm_pattern(const HostBSR &X, const HostBSR &Y) {
+  HostBSR Z;
+  Z.n = X.n;
+  Z.nc = Y.nc;
+  Z.rp.assign(X.n + 1, 0);
+  std::vector<std::vector<int32_t>> rows(X.n);
+#pragma omp parallel
+  {
+    std::vector<int32_t> mark(Y.nc, -1);
+#pragma omp for schedule(dynamic, 512)
+    for (int32_t i = 0; i < X.n; i++) {
+      auto &r = rows[i];
+      for (int64_t k = X.rp[i]; k < X.rp[i + 1]; k++) {
+        const int32_t l = X.ci[k];
+        for (int64_t q = Y.rp[l]; q < Y.rp[l + 1]; q++) {
+          const int32_t j = Y.ci[q];
+          if (mark[j] != i) {
+            mark[j] = i;
+            r.push_back(j);
+          }
+        }
+      }
+      std::sort(r.begin(), r.end());
+    }
+  }
+  for (int32_t i = 0; i < X.n; i++) Z.rp[i + 1] = Z.rp[i] + (int64_t)rows[i].size();
+  Z.ci.resize(Z.rp[X.n]);
+  for (int32_t i = 0; i < X.n; i++) std::copy(rows[i].begin(), rows[i].end(), Z.ci.begin() + Z.rp[i]);
+  Z.v.assign((size_t)Z.rp[X.n] * 9, 0.0);
+  return Z;
+}
+
+struct DevTmp {
+  std::vector<Scratch *> s;
+  DevBSR make(const HostBSR &M, hipStream_t st, bool with_values) {
+    DevBSR d;
+    d.n = M.n;
+    d.nc = M.nc;
+    d.nnzb = M.nnzb();
+    if (d.nnzb >= (int64_t)INT32_MAX) fail(ASPAMG_EINVAL, "operator too large for int32 block indices");
+    std::vector<int32_t> rp32(M.rp.begin(), M.rp.end());
+    s.push_back(new Scratch(rp32.size() * 4));
+    d.rp = s.back()->as<int32_t>();
+    s.push_back(new Scratch(std::max<size_t>(M.ci.size(), 1) * 4));
+    d.ci = s.back()->as<int32_t>();
+    s.push_back(new Scratch(std::max<size_t>(M.v.size(), 1) * 8));
+    d.v = s.back()->as<double>();
+    to_device(st, d.rp, rp32.data(), rp32.size());
+    to_device(st, d.ci, M.ci.data(), M.ci.size());
+    if (with_values) to_device(st, d.v, M.v.data(), M.v.size());
+    return d;
+  }
+  ~DevTmp() {
+    for (auto *x : s) delete x;
+  }
+};
+
+HostBSR galerkin(aspamg_ctx *h, const Level &L) {
+  HostBSR R = transpose(L.P);
+  HostBSR T = spgemm_pattern(L.A, L.P);
+  HostBSR Ac = spgemm_pattern(R, T);
+  DevTmp tmp;
+  DevBSR dP = tmp.make(L.P, h->stream, true), dR = tmp.make(R, h->stream, true);
+  DevBSR dT = tmp.make(T, h->stream, false), dC = tmp.make(Ac, h->stream, false);
+  launch_spgemm_ap(L.dA, dP, dT, h->stream);
+  launch_spgemm_rt(dR, dT, dC, h->stream);
+  HIPCHK(hipGetLastError());
+  to_host(h->stream, Ac.v.data(), dC.v, Ac.v.size());
+  return Ac;
+}
+
+// dense coarsest factor and explicit inverse (L^{-T} L^{-1})
+void build_coarse(aspamg_ctx *h, const HostBSR &A) {
+  const int32_t nd = A.n * 3;
+  if (nd > h->p.dense_max_dof) fail(ASPAMG_EINVAL, "coarsest level too large for a dense factorisation");
+  std::vector<double> M((size_t)nd * nd, 0.0), Lm((size_t)nd * nd, 0.0);
+  for (int32_t i = 0; i < A.n; i++)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; k++)
+      for (int d = 0; d < 3; d++)
+        for (int e = 0; e < 3; e++) M[(size_t)(i * 3 + d) * nd + A.ci[k] * 3 + e] = A.v[(size_t)k * 9 + d * 3 + e];
+  for (int32_t j = 0; j < nd; j++) {
+    double acc = 0.0;
+    for (int32_t k = 0; k < j; k++) acc += Lm[(size_t)j * nd + k] * Lm[(size_t)j * nd + k];
+    const double d = M[(size_t)j * nd + j] - acc;
+    if (!(d > 0.0)) fail(ASPAMG_ENOT_SPD, "coarsest matrix is not positive definite");
+    const double ljj = std::sqrt(d);
+    Lm[(size_t)j * nd + j] = ljj;
+#pragma omp parallel for schedule(static)
+    for (int32_t i = j + 1; i < nd; i++) {
+      double a2 = 0.0;
+      for (int32_t k = 0; k < j; k++) a2 += Lm[(size_t)i * nd + k] * Lm[(size_t)j * nd + k];
+      Lm[(size_t)i * nd + j] = (M[(size_t)i * nd + j] - a2) / ljj;
+    }
+  }
+  // X = L^{-1} (lower), column by column
+  std::vector<double> X((size_t)nd * nd, 0.0);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t c = 0; c < nd; c++) {
+    for (int32_t i = c; i < nd; i++) {
+      double acc = i == c ? 1.0 : 0.0;
+      for (int32_t k = c; k < i; k++) acc -= Lm[(size_t)i * nd + k] * X[(size_t)k * nd + c];
+      X[(size_t)i * nd + c] = acc / Lm[(size_t)i * nd + i];
+    }
+  }
+  // inv = X^T X
+  std::vector<double> inv((size_t)nd * nd, 0.0);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t i = 0; i < nd; i++)
+    for (int32_t j = 0; j <= i; j++) {
+      double s = 0.0;
+      for (int32_t k = std::max(i, j); k < nd; k++) s += X[(size_t)k * nd + i] * X[(size_t)k * nd + j];
+      inv[(size_t)i * nd + j] = s;
+      inv[(size_t)j * nd + i] = s;
+    }
+  h->coarse.nd = nd;
+  h->coarse.inv = upload(h, inv);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// hierarchy driver
+// ------------------------------------------------------------------------
+void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
+  const aspamg_params &p = h->p;
+  const Q q{p.quant_bits};
+  const int ntv = h->ntv;
+  h->lev.clear();
+  h->lev.emplace_back();
+  h->lev[0].A = std::move(A0);
+  h->lev[0].V = std::move(V0);
+  for (int l = 0;; l++) {
+    Level &L = h->lev[l];
+    const int32_t N = L.A.n;
+    L.dA = upload_bsr(h, L.A);
+    L.A64 = upload_sell<double>(h, L.A);
+    L.A32 = upload_sell<float>(h, L.A);
+    if ((int64_t)N * 3 <= p.coarse_max_dof || l == p.max_levels - 1 || l == 31 || ntv == 0) {
+      L.coarsest = true;
+      break;
+    }
+    build_fsai(h, L);
+    orthonormalize(L.V, (int64_t)N * 3, ntv);
+    std::vector<char> excl(N);
+    for (int32_t i = 0; i < N; i++) excl[i] = is_decoupled(L.A, i);
+    StrongGraph S = strong_graph(L, ntv, p.theta, q, excl);
+    mis(S, excl, L.cf);
+    L.cidx.assign(N, -1);
+    int32_t nc = 0, nF = 0;
+    for (int32_t i = 0; i < N; i++) {
+      if (L.cf[i] == 1) L.cidx[i] = nc++;
+      nF += L.cf[i] == 0;
+    }
+    L.nc = nc;
+    if (nc == 0 || nF == 0 || (double)nc > p.stall_ratio * (double)N) {
+      L.G = HostBSR();
+      L.coarsest = true;
+      break;
+    }
+    build_prolongation(h, L, S);
+    HostBSR Ac = galerkin(h, L);
+    // device operators of this level
+    L.G64 = upload_sell<double>(h, L.G);
+    L.G32 = upload_sell<float>(h, L.G);
+    HostBSR GT = transpose(L.G);
+    L.GT64 = upload_sell<double>(h, GT);
+    L.GT32 = upload_sell<float>(h, GT);
+    L.P64 = upload_sell<double>(h, L.P);
+    L.P32 = upload_sell<float>(h, L.P);
+    HostBSR R = transpose(L.P);
+    L.R64 = upload_sell<double>(h, R);
+    L.R32 = upload_sell<float>(h, R);
+    std::vector<double> Vc((size_t)nc * 3 * ntv);
+    for (int32_t i = 0; i < N; i++)
+      if (L.cidx[i] >= 0)
+        std::memcpy(Vc.data() + (size_t)L.cidx[i] * 3 * ntv, L.V.data() + (size_t)i * 3 * ntv, 3 * ntv * sizeof(double));
+    h->lev.emplace_back();
+    h->lev[l + 1].A = std::move(Ac);
+    h->lev[l + 1].V = std::move(Vc);
+  }
+  build_coarse(h, h->lev.back().A);
+}
+
+}  // namespace aspamg

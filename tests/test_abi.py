@@ -1,0 +1,35 @@
+"""The C-ABI library loads and exports every symbol include/aspamg.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+from paper_1902_01715_amd import aspamg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "aspamg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(aspamg_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(aspamg.LIB_PATH)
+    names = declared_symbols()
+    assert len(names) >= 15
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert sorted(aspamg.EXPORTED) == names
+
+
+def test_default_params_and_struct_layout():
+    p = aspamg.default_params()
+    assert (p.k_g, p.theta, p.n_max, p.kappa_p, p.eps_g) == (4, 5, 5, 50.0, 1e-3)
+    assert p.rtol == 1e-10 and p.max_it == 1000 and p.cycle_precision == 64
+    # the ctypes mirror has the C struct size (fields checked by value above)
+    assert ctypes.sizeof(aspamg.Params) == 152
+
+
+def test_last_error_is_a_string():
+    assert isinstance(aspamg.lib().aspamg_last_error(), bytes)

@@ -1,0 +1,122 @@
+"""GPU path vs the FP64 CPU oracle on the same seeded inputs.
+
+Index work (C/F split, G pattern, scalar and block P pattern, Galerkin
+pattern) must match bit for bit; FSAI rows and Galerkin values come from the
+same sequential formulas and are compared bitwise too; Lanczos-based omega
+and the least-squares weights to tolerance; the solve to the spec bar."""
+import numpy as np
+import pytest
+
+from paper_1902_01715_amd import problems as PR
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(p, cuda, oracle_lib, **kw):
+    from paper_1902_01715_amd import aspamg
+    prm = aspamg.default_params(**kw)
+    S = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, prm)
+    okw = {k: v for k, v in kw.items() if hasattr(oracle_lib.Params, k)}
+    if "rho_blocks" in kw:
+        okw["rho_b"] = kw["rho_blocks"]
+    H = oracle_lib.Hierarchy(p.row_ptr, p.col, p.vals, p.V0, oracle_lib.default_params(**okw))
+    return S, H
+
+
+CASES = {
+    "cube7": lambda: PR.c1_cube(7),
+    "cube10_c1": lambda: PR.c1_cube(10),
+    "cube8_randE": lambda: PR.box_problem("r", 8, 8, 8, 1, 1, 1, E=10 ** np.random.default_rng(7).uniform(-3, 3, 512),
+                                          nu=0.3, clamp="z0", load=("body", (0, 0, -1))),
+    "cant40x4x4": lambda: PR.c2_cantilever(40, 4, 4),
+    "cube14": lambda: PR.c1_cube(14),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def pair(request, cuda, oracle_lib):
+    print(f"[case {request.param}]", flush=True)
+    p = CASES[request.param]()
+    S, H = _setup(p, cuda, oracle_lib)
+    yield request.param, p, S, H
+    S.close()
+
+
+def test_hierarchy_patterns_bit_exact(pair):
+    name, p, S, H = pair
+    assert S.nlev == H.nlev, (S.nlev, H.nlev)
+    for l in range(H.nlev):
+        oi, gi = H.info(l), S.level_info(l)
+        assert gi["n"] == oi["n"] and gi["nnzb_A"] == oi["nnzb_A"]
+        A_o, A_g = H.A(l), S.level_matrix(l, 0)
+        assert np.array_equal(A_o.rp, A_g[0]) and np.array_equal(A_o.ci, A_g[1])
+        assert np.array_equal(A_o.v, A_g[2]), f"level {l}: Galerkin values differ (max {np.abs(A_o.v - A_g[2]).max()})"
+        if not oi["has_G"]:
+            continue
+        assert gi["has_smoother"] == 1
+        G_o, G_g = H.G(l), S.level_matrix(l, 1)
+        assert np.array_equal(G_o.rp, G_g[0]) and np.array_equal(G_o.ci, G_g[1]), f"level {l}: G pattern"
+        assert np.array_equal(G_o.v, G_g[2]), f"level {l}: FSAI values differ (max {np.abs(G_o.v - G_g[2]).max()})"
+        cf_g, cnt_g, cols_g = S.level_split(l)
+        assert np.array_equal(H.cf(l), cf_g), f"level {l}: C/F split"
+        cnt_o, cols_o = H.P_scalar(l)
+        assert np.array_equal(cnt_o, cnt_g) and np.array_equal(cols_o, cols_g), f"level {l}: scalar P pattern"
+        P_o, P_g = H.P(l), S.level_matrix(l, 3)
+        assert np.array_equal(P_o.rp, P_g[0]) and np.array_equal(P_o.ci, P_g[1])
+        np.testing.assert_allclose(P_g[2], P_o.v, rtol=0, atol=1e-11 * max(1.0, np.abs(P_o.v).max()))
+        assert abs(gi["omega_q"] - oi["omega_q"]) <= 1e-9 * oi["omega_q"]
+        assert abs(gi["omega_s"] - oi["omega_s"]) <= 1e-9 * oi["omega_s"]
+        assert gi["fsai_rounds"] == oi["fsai_rounds"]
+
+
+def test_vcycle_fp64_matches_oracle(pair):
+    import torch
+    name, p, S, H = pair
+    rng = np.random.default_rng(11)
+    y = rng.standard_normal(p.n_dof)
+    y[np.repeat(p.dirichlet, 3)] = 0.0
+    z_o = H.vcycle(y)
+    S.set_precision(64)
+    z_g = S.vcycle(torch.tensor(y, device="cuda")).cpu().numpy()
+    err = np.linalg.norm(z_g - z_o) / np.linalg.norm(z_o)
+    assert err <= 1e-11, err
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_solve_matches_oracle(pair, prec):
+    import torch
+    name, p, S, H = pair
+    u_o, st_o = H.pcg(p.f, 1e-10, 1000)
+    assert st_o["status"] == 0
+    S.set_precision(prec)
+    f = torch.tensor(p.f, device="cuda")
+    u = S.solve(f).cpu().numpy()
+    st = S.last_stats
+    assert st["status"] == 0, st
+    assert st["relres_recursive"] <= 1e-10
+    assert st["relres_true"] <= 2e-10
+    err = np.linalg.norm(u - u_o) / np.linalg.norm(u_o)
+    print(f"{name} prec={prec} it={st['iterations']} (oracle {st_o['iterations']}) err={err:.2e}")
+    assert err <= 1e-8, err
+    if prec == 64:
+        assert abs(st["iterations"] - st_o["iterations"]) <= 1
+
+
+@pytest.mark.parametrize("which", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_operators_match_oracle(pair, which, prec):
+    import torch
+    name, p, S, H = pair
+    if H.nlev < 2:
+        pytest.skip("single level")
+    l = 0
+    M = {0: H.A(l), 1: H.G(l), 2: H.G(l), 3: H.P(l), 4: H.P(l)}[which].to_scipy().tocsr()
+    if which in (2, 4):
+        M = M.T.tocsr()
+    rng = np.random.default_rng(3 + which)
+    x = rng.standard_normal(M.shape[1])
+    y_ref = M @ x
+    y = S.apply(l, which, torch.tensor(x, device="cuda"), precision=prec, out_rows=M.shape[0]).cpu().numpy()
+    scale = abs(M).max() * np.abs(x).max() * max(1, M.getnnz(axis=1).max())
+    tol = 1e-14 if prec == 64 else 2e-6
+    assert np.abs(y - y_ref).max() <= tol * scale
