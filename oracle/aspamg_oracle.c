@@ -726,18 +726,23 @@ static int coarsen(ohier *h, olevel *L) {
 }
 
 /* ========================================================================= */
-/* DPLS prolongation (Section 3.5).  For scalar row (I,d) of an F node the    */
-/* target is v = V[(I,d)], the candidates are the scalar rows (J,e) of C      */
-/* nodes within S-distance d_p, ascending.  Greedy (Gram form of the          */
-/* Householder recursion): with L the Cholesky factor of the chosen Gram and  */
-/* y = L^{-1} t_C, rho^2 = v.v - |y|^2, each candidate a has                  */
-/* z_a = L^{-1} g_{C,a}, delta_a^2 = g_aa - |z_a|^2, pi_a = t_a - y.z_a and     */
-/* affinity pi_a^2 / (rho^2 delta_a^2): the squared cosine between the current */
-/* LS residual and the part of c_a orthogonal to the chosen columns (at step  */
-/* 0 the paper's affinity).  The argmax of the quantised affinity joins C_i   */
-/* unless the diagonal ratio of L, a lower bound of cond(V_{c,i}), would      */
-/* exceed kappa_p.  Stops at n_max entries, or rho^2 <= eps_p^2 v.v, or when  */
-/* no candidate has positive affinity.  Weights w = L^{-T} y.                  */
+/* DPLS prolongation (Section 3.5, Algorithm "Dynamic Pattern Least Squares  */
+/* Prolongation").  For scalar row (I,d) of an F node the target is           */
+/* v = V[(I,d)], the candidates are the scalar rows (J,e) of C nodes within   */
+/* S-distance d_p, ascending.  Householder form: after k accepted columns the */
+/* residual r and every candidate c_a have been reflected by H_{k-1}..H_0, so */
+/* their trailing parts (entries k..ntv-1) are their components orthogonal to */
+/* the chosen columns.  With rho^2 = |r_tail|^2, delta_a^2 = |c_a,tail|^2 and */
+/* pi_a = c_a,tail . r_tail, the affinity is pi_a^2 / (rho^2 delta_a^2) (at   */
+/* step 0 the paper's affinity).  The argmax of the quantised affinity (> 0,  */
+/* ties to the lowest candidate) is accepted unless max|R_kk| / min|R_kk|, a  */
+/* lower bound of cond(V_{c,i}), would exceed kappa_p.  Stops at n_max       */
+/* entries, or rho^2 <= eps_p^2 v.v, or when no candidate is eligible.        */
+/* Weights: R w = (Q v)_{0..k-1} by back substitution.                        */
+/* Reflection of column u at step k (sums ascending in t):                    */
+/*   delta = sqrt(sum_{t>=k} u_t^2), alpha = -delta if u_k >= 0 else delta,   */
+/*   h = u_tail with h_k = u_k - alpha, s = h_k^2 + sum_{t>k} u_t^2,           */
+/*   x_tail <- x_tail - (2 (h . x_tail) / s) h.                                */
 /* ========================================================================= */
 typedef struct {
   int k;
@@ -746,84 +751,81 @@ typedef struct {
 } dpls_out;
 
 static int dpls_row(ohier *h, const double *v, const double *C, int nca, int ntv, dpls_out *o,
-                    double *t, double *gaa, double *gbuf) {
+                    double *Cw, double *unused1, double *unused2) {
+  (void)unused1; (void)unused2;
   const oparams *p = &h->p;
   double vv = 0.0;
   for (int s = 0; s < ntv; s++) vv += v[s] * v[s];
   o->k = 0;
   if (vv == 0.0) return 0;
-  for (int a = 0; a < nca; a++) {
-    double s1 = 0.0, s2 = 0.0;
-    for (int s = 0; s < ntv; s++) { s1 += C[a * ntv + s] * v[s]; s2 += C[a * ntv + s] * C[a * ntv + s]; }
-    t[a] = s1; gaa[a] = s2;
-  }
-  double Lm[16][16], y[16], rho2 = vv, dmax = 0.0, dmin = 0.0;
-  int chosen[16];
-  int K = 0;
+  double r[64], Rm[16][16], hv[64];
+  memcpy(r, v, ntv * sizeof(double));
+  memcpy(Cw, C, (size_t)nca * ntv * sizeof(double));
   char *used = calloc(nca > 0 ? nca : 1, 1);
-  double thr = qz((p->eps_p * p->eps_p) * vv);
+  const double thr = qz((p->eps_p * p->eps_p) * vv);
   int nmax = p->n_max < 16 ? p->n_max : 16;
-  while (K < nmax) {
+  double dmax = 0.0, dmin = 0.0;
+  int K = 0;
+  while (K < nmax && K < ntv) {
+    double rho2 = 0.0;
+    for (int t = K; t < ntv; t++) rho2 += r[t] * r[t];
     if (!(qz(rho2) > thr)) break;
     int best = -1;
-    double bestq = 0.0, bz[16], bdel2 = 0.0, bpi = 0.0, secondq = -1.0;
+    double bestq = 0.0, bdel2 = 0.0, secondq = -1.0;
     for (int a = 0; a < nca; a++) {
       if (used[a]) continue;
-      double z[16];
-      for (int k = 0; k < K; k++) {
-        double acc = 0.0;
-        for (int j = 0; j < k; j++) acc += Lm[k][j] * z[j];
-        z[k] = (gbuf[(int64_t)k * nca + a] - acc) / Lm[k][k];
-      }
-      double s = 0.0;
-      for (int k = 0; k < K; k++) s += z[k] * z[k];
-      double del2 = gaa[a] - s;
+      const double *c = Cw + (size_t)a * ntv;
+      double del2 = 0.0, pi = 0.0;
+      for (int t = K; t < ntv; t++) del2 += c[t] * c[t];
       if (!(del2 > 0.0)) continue;
-      double s2 = 0.0;
-      for (int k = 0; k < K; k++) s2 += y[k] * z[k];
-      double pi = t[a] - s2;
-      double aff = (pi * pi) / (rho2 * del2);
-      double q = qz(aff);
+      for (int t = K; t < ntv; t++) pi += c[t] * r[t];
+      const double aff = (pi * pi) / (rho2 * del2);
+      const double q = qz(aff);
       if (q > bestq) {
         if (best >= 0 && bestq > secondq) secondq = bestq;
-        best = a; bestq = q; bdel2 = del2; bpi = pi;
-        memcpy(bz, z, K * sizeof(double));
+        best = a; bestq = q; bdel2 = del2;
       } else if (q > secondq) {
         secondq = q;
       }
     }
     if (best < 0) break;
     if (secondq > 0.0) note_margin(h, bestq, secondq);
-    double del = sqrt(bdel2);
-    double mx = K ? (dmax > del ? dmax : del) : del;
-    double mn = K ? (dmin < del ? dmin : del) : del;
-    double kap = mx / mn;
-    note_margin(h, kap, p->kappa_p);
-    if (qz(kap) > qz(p->kappa_p)) break;
-    for (int k = 0; k < K; k++) Lm[K][k] = bz[k];
-    Lm[K][K] = del;
-    y[K] = bpi / del;
-    rho2 = rho2 - y[K] * y[K];
-    dmax = mx; dmin = mn;
-    chosen[K] = best;
-    used[best] = 1;
-    /* Gram row of the new column against every candidate */
-    for (int a = 0; a < nca; a++) {
-      double s = 0.0;
-      for (int q = 0; q < ntv; q++) s += C[best * ntv + q] * C[a * ntv + q];
-      gbuf[(int64_t)K * nca + a] = s;
+    const double del = sqrt(bdel2);
+    const double mx = K ? (dmax > del ? dmax : del) : del;
+    const double mn = K ? (dmin < del ? dmin : del) : del;
+    note_margin(h, mx / mn, p->kappa_p);
+    if (qz(mx / mn) > qz(p->kappa_p)) break;
+    /* Householder reflection of the chosen column's trailing part */
+    double *u = Cw + (size_t)best * ntv;
+    const double alpha = u[K] >= 0.0 ? -del : del;
+    for (int t = K; t < ntv; t++) hv[t] = u[t];
+    hv[K] = u[K] - alpha;
+    double sh = hv[K] * hv[K];
+    for (int t = K + 1; t < ntv; t++) sh += hv[t] * hv[t];
+    for (int a = 0; a <= nca; a++) {          /* a == nca: the residual r */
+      if (a < nca && (used[a] || a == best)) continue;
+      double *x = a < nca ? Cw + (size_t)a * ntv : r;
+      double tau = 0.0;
+      for (int t = K; t < ntv; t++) tau += hv[t] * x[t];
+      const double fct = (2.0 * tau) / sh;
+      for (int t = K; t < ntv; t++) x[t] = x[t] - fct * hv[t];
     }
+    for (int i = 0; i < K; i++) Rm[i][K] = u[i];
+    Rm[K][K] = alpha;
+    dmax = mx; dmin = mn;
+    o->col[K] = best;
+    used[best] = 1;
     K++;
   }
-  /* w = L^{-T} y */
+  /* R w = (Q v)_{0..K-1} */
   double w[16];
-  for (int k = K - 1; k >= 0; k--) {
+  for (int j = K - 1; j >= 0; j--) {
     double acc = 0.0;
-    for (int j = k + 1; j < K; j++) acc += Lm[j][k] * w[j];
-    w[k] = (y[k] - acc) / Lm[k][k];
+    for (int i = j + 1; i < K; i++) acc += Rm[j][i] * w[i];
+    w[j] = (r[j] - acc) / Rm[j][j];
   }
   o->k = K;
-  for (int k = 0; k < K; k++) { o->col[k] = chosen[k]; o->w[k] = w[k]; }
+  for (int k = 0; k < K; k++) o->w[k] = w[k];
   free(used);
   return 0;
 }
@@ -848,7 +850,7 @@ static int build_P(ohier *h, olevel *L) {
   int cap = 1024;
   double *Cm = malloc((size_t)cap * b * ntv * sizeof(double));
   double *t = malloc((size_t)cap * b * sizeof(double)), *gaa = malloc((size_t)cap * b * sizeof(double));
-  double *gbuf = malloc((size_t)16 * cap * b * sizeof(double));
+  double *gbuf = malloc((size_t)cap * b * ntv * sizeof(double));
   int32_t *cnode = malloc((size_t)cap * b * sizeof(int32_t));
   int8_t *ccomp = malloc((size_t)cap * b);
   if (!wv || !Cm || !t || !gaa || !gbuf || !cnode || !ccomp) return O_ENOMEM;
@@ -874,7 +876,7 @@ static int build_P(ohier *h, olevel *L) {
       cap = ncn;
       Cm = realloc(Cm, (size_t)cap * b * ntv * sizeof(double));
       t = realloc(t, (size_t)cap * b * sizeof(double)); gaa = realloc(gaa, (size_t)cap * b * sizeof(double));
-      gbuf = realloc(gbuf, (size_t)16 * cap * b * sizeof(double));
+      gbuf = realloc(gbuf, (size_t)cap * b * ntv * sizeof(double));
       cnode = realloc(cnode, (size_t)cap * b * sizeof(int32_t)); ccomp = realloc(ccomp, (size_t)cap * b);
     }
     int nca = 0;
@@ -885,7 +887,7 @@ static int build_P(ohier *h, olevel *L) {
       }
     for (int d = 0; d < b; d++) {
       dpls_out o;
-      dpls_row(h, L->V + ((int64_t)I * b + d) * ntv, Cm, nca, ntv, &o, t, gaa, gbuf);
+      dpls_row(h, L->V + ((int64_t)I * b + d) * ntv, Cm, nca, ntv, &o, gbuf, t, gaa);
       int64_t r = (int64_t)I * b + d;
       L->pcount[r] = o.k;
       for (int k = 0; k < o.k; k++) {
@@ -1366,10 +1368,10 @@ double oracle_lanczos(int32_t n, int b, const int64_t *rp, const int32_t *ci, co
 int oracle_dpls_row(const oparams *p, const double *v, const double *C, int nca, int ntv,
                     int32_t *chosen, double *w) {
   ohier hh; memset(&hh, 0, sizeof hh); hh.p = *p; hh.min_margin = INFINITY; QB = p->quant_bits;
-  double *t = malloc((size_t)(nca ? nca : 1) * sizeof(double)), *gaa = malloc((size_t)(nca ? nca : 1) * sizeof(double));
-  double *gbuf = malloc((size_t)16 * (nca ? nca : 1) * sizeof(double));
+  double *t = NULL, *gaa = NULL;
+  double *gbuf = malloc((size_t)(nca ? nca : 1) * ntv * sizeof(double));
   dpls_out o;
-  dpls_row(&hh, v, C, nca, ntv, &o, t, gaa, gbuf);
+  dpls_row(&hh, v, C, nca, ntv, &o, gbuf, t, gaa);
   for (int k = 0; k < o.k; k++) { chosen[k] = o.col[k]; w[k] = o.w[k]; }
   free(t); free(gaa); free(gbuf);
   return o.k;

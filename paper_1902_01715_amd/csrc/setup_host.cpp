@@ -580,64 +580,48 @@ void mis(const StrongGraph &S, const std::vector<char> &excl, std::vector<int8_t
 }
 
 // ------------------------------------------------------------------------
-// DPLS interpolation pattern (Section 3.5), Gram form of the greedy: with L
-// the Cholesky factor of the chosen Gram and y = L^{-1} t_C, each candidate a
-// has z_a = L^{-1} g_{C,a}, delta^2 = g_aa - |z_a|^2, pi = t_a - y.z_a and
-// affinity pi^2 / (rho^2 delta^2).  The largest quantised affinity (> 0,
-// ties to the lowest candidate) is taken unless the diagonal ratio of L would
-// exceed kappa_p.  Stops at n_max, rho^2 <= eps_p^2 v.v, or no candidate.
+// DPLS interpolation pattern (Section 3.5), Householder form of the greedy:
+// after k accepted columns the residual r and the candidates have been
+// reflected k times, so entries k.. of each vector are its part orthogonal to
+// the chosen columns.  Affinity pi^2 / (rho^2 delta^2) with rho^2 = |r_tail|^2,
+// delta^2 = |c_tail|^2, pi = c_tail . r_tail; the largest quantised affinity
+// (> 0, ties to the lowest candidate) is taken unless max|R_kk| / min|R_kk|
+// would exceed kappa_p.  Stops at n_max, rho^2 <= eps_p^2 v.v, or when no
+// candidate is eligible.  Reflection at step k: alpha = -delta (u_k >= 0) or
+// +delta, h = u_tail with h_k -= alpha, x_tail -= (2 h.x_tail / h.h) h.
 // ------------------------------------------------------------------------
 int dpls_select(const double *v, const double *C, int nca, int ntv, const aspamg_params &p, const Q &q,
-                int32_t *chosen, std::vector<double> &t, std::vector<double> &gaa, std::vector<double> &gb,
-                std::vector<char> &used) {
+                int32_t *chosen, std::vector<double> &Cw, std::vector<char> &used) {
   double vv = 0.0;
-  for (int s = 0; s < ntv; s++) vv += v[s] * v[s];
+  for (int t = 0; t < ntv; t++) vv += v[t] * v[t];
   if (vv == 0.0) return 0;
-  t.resize(nca);
-  gaa.resize(nca);
+  double r[64], hv[64];
+  std::memcpy(r, v, ntv * sizeof(double));
+  Cw.assign(C, C + (size_t)nca * ntv);
   used.assign(nca, 0);
-  gb.resize((size_t)kMaxPEntries * nca);
-  for (int a = 0; a < nca; a++) {
-    double s1 = 0.0, s2 = 0.0;
-    for (int s = 0; s < ntv; s++) {
-      s1 += C[(size_t)a * ntv + s] * v[s];
-      s2 += C[(size_t)a * ntv + s] * C[(size_t)a * ntv + s];
-    }
-    t[a] = s1;
-    gaa[a] = s2;
-  }
-  double Lm[kMaxPEntries][kMaxPEntries], y[kMaxPEntries];
-  double rho2 = vv, dmax = 0.0, dmin = 0.0;
   const double thr = q((p.eps_p * p.eps_p) * vv);
   const int nmax = std::min(p.n_max, kMaxPEntries);
+  double dmax = 0.0, dmin = 0.0;
   int K = 0;
-  while (K < nmax) {
+  while (K < nmax && K < ntv) {
+    double rho2 = 0.0;
+    for (int t = K; t < ntv; t++) rho2 += r[t] * r[t];
     if (!(q(rho2) > thr)) break;
     int best = -1;
-    double bestq = 0.0, bdel2 = 0.0, bpi = 0.0, bz[kMaxPEntries];
+    double bestq = 0.0, bdel2 = 0.0;
     for (int a = 0; a < nca; a++) {
       if (used[a]) continue;
-      double z[kMaxPEntries];
-      for (int k = 0; k < K; k++) {
-        double acc = 0.0;
-        for (int j = 0; j < k; j++) acc += Lm[k][j] * z[j];
-        z[k] = (gb[(size_t)k * nca + a] - acc) / Lm[k][k];
-      }
-      double s = 0.0;
-      for (int k = 0; k < K; k++) s += z[k] * z[k];
-      const double del2 = gaa[a] - s;
+      const double *c = Cw.data() + (size_t)a * ntv;
+      double del2 = 0.0;
+      for (int t = K; t < ntv; t++) del2 += c[t] * c[t];
       if (!(del2 > 0.0)) continue;
-      double s2 = 0.0;
-      for (int k = 0; k < K; k++) s2 += y[k] * z[k];
-      const double pi = t[a] - s2;
-      const double aff = (pi * pi) / (rho2 * del2);
-      const double qa = q(aff);
+      double pi = 0.0;
+      for (int t = K; t < ntv; t++) pi += c[t] * r[t];
+      const double qa = q((pi * pi) / (rho2 * del2));
       if (qa > bestq) {
         best = a;
         bestq = qa;
         bdel2 = del2;
-        bpi = pi;
-        std::memcpy(bz, z, K * sizeof(double));
       }
     }
     if (best < 0) break;
@@ -645,19 +629,25 @@ int dpls_select(const double *v, const double *C, int nca, int ntv, const aspamg
     const double mx = K ? std::max(dmax, del) : del;
     const double mn = K ? std::min(dmin, del) : del;
     if (q(mx / mn) > q(p.kappa_p)) break;
-    for (int k = 0; k < K; k++) Lm[K][k] = bz[k];
-    Lm[K][K] = del;
-    y[K] = bpi / del;
-    rho2 = rho2 - y[K] * y[K];
+    const double *u = Cw.data() + (size_t)best * ntv;
+    const double alpha = u[K] >= 0.0 ? -del : del;
+    for (int t = K; t < ntv; t++) hv[t] = u[t];
+    hv[K] = u[K] - alpha;
+    double sh = hv[K] * hv[K];
+    for (int t = K + 1; t < ntv; t++) sh += hv[t] * hv[t];
+    auto reflect = [&](double *x) {
+      double tau = 0.0;
+      for (int t = K; t < ntv; t++) tau += hv[t] * x[t];
+      const double fct = (2.0 * tau) / sh;
+      for (int t = K; t < ntv; t++) x[t] = x[t] - fct * hv[t];
+    };
+    for (int a = 0; a < nca; a++)
+      if (!used[a] && a != best) reflect(Cw.data() + (size_t)a * ntv);
+    reflect(r);
     dmax = mx;
     dmin = mn;
     chosen[K] = best;
     used[best] = 1;
-    for (int a = 0; a < nca; a++) {
-      double s = 0.0;
-      for (int r = 0; r < ntv; r++) s += C[(size_t)best * ntv + r] * C[(size_t)a * ntv + r];
-      gb[(size_t)K * nca + a] = s;
-    }
     K++;
   }
   return K;
@@ -676,7 +666,7 @@ void build_prolongation(aspamg_ctx *h, Level &L, const StrongGraph &S) {
 #pragma omp parallel
   {
     std::vector<int32_t> dist(n, -1), frontier, cn;
-    std::vector<double> Cm, t, gaa, gb;
+    std::vector<double> Cm, Cw;
     std::vector<char> used;
     std::vector<int32_t> visited;
 #pragma omp for schedule(dynamic, 256)
@@ -707,8 +697,7 @@ void build_prolongation(aspamg_ctx *h, Level &L, const StrongGraph &S) {
           std::memcpy(Cm.data() + (c * 3 + e) * ntv, L.V.data() + ((size_t)cn[c] * 3 + e) * ntv, ntv * sizeof(double));
       for (int d = 0; d < 3; d++) {
         int32_t chosen[kMaxPEntries];
-        const int K = dpls_select(L.V.data() + ((size_t)I * 3 + d) * ntv, Cm.data(), nca, ntv, p, q, chosen, t, gaa,
-                                  gb, used);
+        const int K = dpls_select(L.V.data() + ((size_t)I * 3 + d) * ntv, Cm.data(), nca, ntv, p, q, chosen, Cw, used);
         const size_t r = (size_t)I * 3 + d;
         L.pcount[r] = K;
         for (int k = 0; k < K; k++) {
