@@ -1,0 +1,178 @@
+"""Benchmark of the aSP-AMG solve phase on one MI355X.
+
+Workload (default): the cantilever 320x32x32 Q1 hexes (1,048,707 DOF), element
+aspect ratio 10 along the axis, E log-uniform in [1e-3, 1e3] per element, nu
+uniform in [0.25, 0.45], clamped at x = 0, unit tip traction, seed 2.  A step
+is one PCG solve to ||r|| <= 1e-10 ||f|| (or the 1000-iteration cap) with the
+FP32 V-cycle inside FP64 PCG; the same number of solves with the FP64 V-cycle
+is timed beside it.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (rank 0): metric, value (FP32-cycle solve seconds), the
+FP64-cycle solve time, V-cycle HBM GB/s for both precisions, the roofline of
+the dominant kernel (PCG product q = K p, SELL-64 3x3-block SpMV) and the CPU
+oracle measured on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PCG-AMG solve s and V-cycle HBM GB/s at 1e-10 rel-res, FP32 vs FP64 cycle"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_problem(name):
+    from paper_1902_01715_amd import problems as PR
+    if name == "c2":
+        return PR.c2_cantilever(), "cantilever 320x32x32 Q1 (1,048,707 DOF), aspect 10, E=10^U[-3,3], nu=U[.25,.45]"
+    if name == "c3":
+        return PR.c3_layered_distorted(), "layered distorted block 128x128x64 Q1 (3,244,995 DOF), E=1/1e4 layers"
+    if name == "c5":
+        return PR.c5_simp(), "SIMP cube 48^3 Q1 (352,947 DOF), E=rho^3"
+    if name == "c1":
+        return PR.c1_cube(), "unit cube 10^3 Q1 (3,993 DOF)"
+    raise SystemExit(f"unknown config {name}")
+
+
+def cpu_baseline(problem_name, gpu_iters):
+    """The CPU oracle on a bounded sample of the workload: its own setup and a
+    fixed number of PCG iterations on the leading 20-element slab of the
+    cantilever (same cross-section, materials drawn the same way), scaled by
+    the DOF ratio and the GPU iteration count to seconds per solve."""
+    import numpy as np
+    import oracle
+    from paper_1902_01715_amd import problems as PR
+    oracle.build(force=False)
+    if problem_name != "c2":
+        return None
+    sample = PR.c2_cantilever(20, 32, 32)
+    H = oracle.Hierarchy(sample.row_ptr, sample.col, sample.vals, sample.V0)
+    its = min(gpu_iters, 400)
+    t0 = time.perf_counter()
+    u, st = H.pcg(sample.f, 0.0, its)                    # rtol 0: exactly `its` iterations
+    t = time.perf_counter() - t0
+    t_iter = t / max(st["iterations"], 1)
+    dof_ratio = 1048707.0 / sample.n_dof
+    return {"value": t_iter * dof_ratio * gpu_iters, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"{st['iterations']} PCG iterations (V(1,1) aSP-AMG, FP64) on the 20x32x32 leading slab "
+                      f"of the cantilever ({sample.n_dof} DOF, {t:.1f} s), scaled by the DOF ratio "
+                      f"{dof_ratio:.1f} and the GPU iteration count {gpu_iters}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-it", type=int, default=1000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1902_01715_amd import aspamg
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    aspamg.lib()
+    t0 = time.perf_counter()
+    p, desc = make_problem(args.config)
+    log(f"inputs {desc}: {time.perf_counter() - t0:.1f} s")
+    prm = aspamg.default_params(max_it=args.max_it)
+    t0 = time.perf_counter()
+    S = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, prm)
+    t_setup = time.perf_counter() - t0
+    levels = [S.level_info(l) for l in range(S.nlev)]
+    log(f"setup {t_setup:.1f} s, {len(levels)} levels: " + ", ".join(str(li["n"]) for li in levels))
+    f = torch.tensor(p.f if p.f.ndim == 1 else p.f[:, 0], device="cuda")
+    u = torch.empty_like(f)
+
+    def run(prec, n):
+        S.set_precision(prec)
+        ts, st = [], None
+        for _ in range(n):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            S.solve(f, u)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            st = S.last_stats
+        return ts, st
+
+    for prec in (32, 64):
+        run(prec, args.warmup)
+    log("warmup done")
+    ts32, st32 = run(32, args.steps)
+    log(f"fp32 cycle: {st32['iterations']} it, relres {st32['relres_recursive']:.2e} (true {st32['relres_true']:.2e}),"
+        f" {np.median(ts32):.4f} s")
+    u32 = u.clone()
+    ts64, st64 = run(64, args.steps)
+    log(f"fp64 cycle: {st64['iterations']} it, relres {st64['relres_recursive']:.2e} (true {st64['relres_true']:.2e}),"
+        f" {np.median(ts64):.4f} s")
+    err32 = float(torch.linalg.norm(u32 - u) / torch.linalg.norm(u))
+
+    # V-cycle bandwidth (M2) and the roofline of the dominant kernel
+    vc32_ms, vc32_b = S.time_kernel(3, 50)
+    vc64_ms, vc64_b = S.time_kernel(4, 50)
+    kp_ms, kp_b = S.time_kernel(0, 50)
+    r32_ms, r32_b = S.time_kernel(1, 50)
+    r64_ms, r64_b = S.time_kernel(2, 50)
+    kp_gbs = kp_b / (kp_ms * 1e-3) / 1e9
+    t32 = float(np.median(ts32))
+    t64 = float(np.median(ts64))
+    out = {
+        "metric": METRIC,
+        "value": t32,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t32 * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 V-cycle in f64 PCG",
+        "data": "synthetic",
+        "config": {"workload": desc, "config": args.config, "rtol": 1e-10, "max_it": args.max_it,
+                   "cycle": "V(1,1)", "levels": len(levels), "c_gd": st32["c_gd"], "c_op": st32["c_op"],
+                   "c_fs": st32["c_fs"], "setup_s": t_setup},
+        "fp32_cycle": {"solve_s": t32, "iterations": st32["iterations"], "status": st32["status"],
+                       "relres": st32["relres_recursive"], "relres_true": st32["relres_true"],
+                       "s_per_iter": t32 / max(st32["iterations"], 1), "err_vs_fp64_cycle": err32},
+        "fp64_cycle": {"solve_s": t64, "iterations": st64["iterations"], "status": st64["status"],
+                       "relres": st64["relres_recursive"], "relres_true": st64["relres_true"],
+                       "s_per_iter": t64 / max(st64["iterations"], 1)},
+        "speedup_fp64_over_fp32": t64 / t32,
+        "vcycle": {"fp32_ms": vc32_ms, "fp32_GBps": vc32_b / (vc32_ms * 1e-3) / 1e9,
+                   "fp64_ms": vc64_ms, "fp64_GBps": vc64_b / (vc64_ms * 1e-3) / 1e9,
+                   "fp32_bytes": vc32_b, "fp64_bytes": vc64_b},
+        "kernels": {"residual_fp32_GBps": r32_b / (r32_ms * 1e-3) / 1e9,
+                    "residual_fp64_GBps": r64_b / (r64_ms * 1e-3) / 1e9},
+        "levels": [{k: li[k] for k in ("n", "n_coarse", "nnzb_A", "nnzb_G", "nnzb_P", "sell_slots_A", "sell_slots_G",
+                                      "sell_slots_GT", "omega_s", "fsai_rounds")} for li in levels],
+        "roofline": {"bound": "hbm", "kernel": "k_sell_spmv_dot (q = K p, FP64 SELL-64)",
+                     "achieved": kp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kp_gbs / HBM_PEAK_GBS,
+                     "traffic": None, "avg_launch_ms": kp_ms, "alg_bytes_per_launch": kp_b},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(args.config, st32["iterations"])
+    S.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

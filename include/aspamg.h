@@ -15,7 +15,9 @@
  *     each row, vals float64 [nnzb][3][3] row-major blocks.
  *   - A block row holding only its diagonal block is a constrained (Dirichlet)
  *     or decoupled node: it is never coarse and gets no interpolation.
- *   - All device work runs on the HIP stream given to aspamg_setup.
+ *   - A handle runs its device work on a private non-blocking stream (default
+ *     priority) created by aspamg_setup, which first waits for the caller's
+ *     stream; solve, vcycle and apply calls return when their work is done.
  *   - Every call returns aspamg_status; negative values are errors, positive
  *     values are warnings with valid outputs.  No C++ exception crosses the ABI.
  *     aspamg_last_error() returns a message for the last failing call of the
@@ -112,7 +114,7 @@ aspamg_status aspamg_default_params(aspamg_params *out);
  *            pattern and values with a diagonal block in every row.
  *   n_tv, V0 near-null-space vectors, float64 [n_nodes][3][n_tv] node-major
  *            (the six rigid-body modes for elasticity, Section 3.3), host or device.
- *   hip_stream  hipStream_t for all work of this handle (NULL = default stream).
+ *   hip_stream  caller's hipStream_t whose pending work setup waits for (NULL = none).
  *   out      receives the handle; NULL on failure.
  * Every input is copied; the caller may free its arrays when the call returns.
  * Errors: EINVAL (shape/pattern), ENOT_SPD, ENOMEM, EHIP. */
@@ -197,6 +199,19 @@ aspamg_status aspamg_assembler_create(int32_t n_nodes, int64_t n_el, const int32
 /* vals_dev: float64 device [nnzb][3][3]; E_dev: float64 device [n_el]. */
 aspamg_status aspamg_assemble(aspamg_assembler a, const double *E_dev, double *vals_dev);
 aspamg_status aspamg_assembler_destroy(aspamg_assembler a);
+
+/* Measurement entry point: launch one kernel of the solve path `reps` times
+ * back to back on the handle's stream between two HIP events and report the
+ * average duration per launch and the algorithmic HBM bytes of one launch
+ * (every stored block, its column index and each vector entry counted once).
+ *   which = 0  PCG product q = K p with the fused p.q partials (FP64)
+ *           1  fine-level residual r = y - A s, FP32 operator and vectors
+ *           2  fine-level residual r = y - A s, FP64
+ *           3  one whole V-cycle in FP32 (all levels and the coarsest solve)
+ *           4  one whole V-cycle in FP64
+ *   avg_ms, alg_bytes: caller-owned outputs.  Errors: EINVAL, EHIP. */
+aspamg_status aspamg_time_kernel(aspamg_handle h, int32_t which, int32_t reps, double *avg_ms,
+                                 double *alg_bytes);
 
 aspamg_status aspamg_destroy(aspamg_handle h);
 const char *aspamg_last_error(void);

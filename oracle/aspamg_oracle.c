@@ -738,7 +738,8 @@ static int coarsen(ohier *h, olevel *L) {
 /* ties to the lowest candidate) is accepted unless max|R_kk| / min|R_kk|, a  */
 /* lower bound of cond(V_{c,i}), would exceed kappa_p.  Stops at n_max       */
 /* entries, or rho^2 <= eps_p^2 v.v, or when no candidate is eligible.        */
-/* Weights: R w = (Q v)_{0..k-1} by back substitution.                        */
+/* Weights: normal equations of the chosen columns by Cholesky (the SPD     */
+/* solve that defines them; equal to R^{-1} (Q v) in exact arithmetic).      */
 /* Reflection of column u at step k (sums ascending in t):                    */
 /*   delta = sqrt(sum_{t>=k} u_t^2), alpha = -delta if u_k >= 0 else delta,   */
 /*   h = u_tail with h_k = u_k - alpha, s = h_k^2 + sum_{t>k} u_t^2,           */
@@ -817,13 +818,44 @@ static int dpls_row(ohier *h, const double *v, const double *C, int nca, int ntv
     used[best] = 1;
     K++;
   }
-  /* R w = (Q v)_{0..K-1} */
-  double w[16];
-  for (int j = K - 1; j >= 0; j--) {
-    double acc = 0.0;
-    for (int i = j + 1; i < K; i++) acc += Rm[j][i] * w[i];
-    w[j] = (r[j] - acc) / Rm[j][j];
+  /* weights (the normal equations of the chosen columns, in the order chosen):
+   * t_a = c_a . v, Gram g_ac = c_a . c_c (c <= a), Cholesky g = L L^T,
+   * L y = t, L^T w = y; all sums ascending */
+  double Gm[16][16], Lc[16][16], tt[16], y[16], w[16];
+  for (int a = 0; a < K; a++) {
+    const double *ca = C + (size_t)o->col[a] * ntv;
+    double s1 = 0.0;
+    for (int q = 0; q < ntv; q++) s1 += ca[q] * v[q];
+    tt[a] = s1;
+    for (int c = 0; c <= a; c++) {
+      const double *cc = C + (size_t)o->col[c] * ntv;
+      double g = 0.0;
+      for (int q = 0; q < ntv; q++) g += ca[q] * cc[q];
+      Gm[a][c] = g;
+    }
   }
+  for (int j = 0; j < K; j++) {
+    double acc = 0.0;
+    for (int k = 0; k < j; k++) acc += Lc[j][k] * Lc[j][k];
+    const double dd = Gm[j][j] - acc;
+    Lc[j][j] = dd > 0.0 ? sqrt(dd) : 1.0;
+    for (int a = j + 1; a < K; a++) {
+      double a2 = 0.0;
+      for (int k = 0; k < j; k++) a2 += Lc[a][k] * Lc[j][k];
+      Lc[a][j] = (Gm[a][j] - a2) / Lc[j][j];
+    }
+  }
+  for (int a = 0; a < K; a++) {
+    double acc = 0.0;
+    for (int c = 0; c < a; c++) acc += Lc[a][c] * y[c];
+    y[a] = (tt[a] - acc) / Lc[a][a];
+  }
+  for (int a = K - 1; a >= 0; a--) {
+    double acc = 0.0;
+    for (int c = a + 1; c < K; c++) acc += Lc[c][a] * w[c];
+    w[a] = (y[a] - acc) / Lc[a][a];
+  }
+  (void)Rm;
   o->k = K;
   for (int k = 0; k < K; k++) o->w[k] = w[k];
   free(used);

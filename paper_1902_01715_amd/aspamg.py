@@ -24,7 +24,7 @@ EXPORTED = [
     "aspamg_default_params", "aspamg_setup", "aspamg_set_cycle_precision", "aspamg_solve",
     "aspamg_solve_batch", "aspamg_vcycle", "aspamg_apply_operator", "aspamg_level_info",
     "aspamg_level_matrix", "aspamg_level_split", "aspamg_element_gradient", "aspamg_assembler_create",
-    "aspamg_assemble", "aspamg_assembler_destroy", "aspamg_destroy", "aspamg_last_error",
+    "aspamg_assemble", "aspamg_assembler_destroy", "aspamg_time_kernel", "aspamg_destroy", "aspamg_last_error",
 ]
 
 
@@ -98,6 +98,7 @@ def lib():
                                               C.POINTER(C.c_void_p)]
         L.aspamg_assemble.argtypes = [P, P, P]
         L.aspamg_assembler_destroy.argtypes = [P]
+        L.aspamg_time_kernel.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.aspamg_destroy.argtypes = [P]
         L.aspamg_last_error.restype = C.c_char_p
         for nm in EXPORTED:
@@ -228,6 +229,13 @@ class Solver:
         self._stream.synchronize()
         _check(lib().aspamg_apply_operator(self.h, level, which, precision, _ptr(x.contiguous()), _ptr(y)))
         return y
+
+    def time_kernel(self, which, reps=20):
+        """(average ms per launch, algorithmic bytes per launch) of a solve-path kernel."""
+        ms, by = C.c_double(), C.c_double()
+        self._stream.synchronize()
+        _check(lib().aspamg_time_kernel(self.h, which, reps, C.byref(ms), C.byref(by)))
+        return ms.value, by.value
 
     @property
     def nlev(self):

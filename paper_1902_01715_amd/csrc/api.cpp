@@ -50,18 +50,40 @@ HostBSR transpose(const HostBSR &M) {
 }
 
 template <typename T>
-Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M) {
+Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, bool force_sell) {
   Sell<T> S;
   S.n = M.n;
   S.nc = M.nc;
   S.nnzb = M.nnzb();
   S.nslices = (M.n + kSell - 1) / kSell;
+  auto len = [&](int32_t r) { return M.rp[r + 1] - M.rp[r]; };
   std::vector<int32_t> sptr(S.nslices + 1, 0);
   for (int32_t s = 0; s < S.nslices; s++) {
     int64_t w = 0;
-    for (int32_t r = s * kSell; r < std::min(M.n, (s + 1) * kSell); r++) w = std::max(w, M.rp[r + 1] - M.rp[r]);
+    for (int32_t r = s * kSell; r < std::min(M.n, (s + 1) * kSell); r++) w = std::max(w, len(r));
     if ((int64_t)sptr[s] + w >= (int64_t)INT32_MAX / 64) fail(ASPAMG_EINVAL, "operator too large for SELL layout");
     sptr[s + 1] = sptr[s] + (int32_t)w;
+  }
+  const double padding = S.nnzb ? (double)sptr[S.nslices] * 64.0 / (double)S.nnzb : 1.0;
+  if (!force_sell && (M.n < kVecRows || padding > kMaxPadding)) {
+    // vector BSR: lanes per row ~ a quarter of the mean row length, power of two in [2, 64]
+    S.mode = 1;
+    S.nslices = 0;
+    const double avg = M.n ? (double)S.nnzb / M.n : 0.0;
+    int L = 2;
+    while (L < 64 && L * 4 < avg) L *= 2;
+    S.lanes = L;
+    std::vector<int32_t> rp32(M.rp.begin(), M.rp.end());
+    std::vector<T> val(std::max<size_t>(M.v.size(), 1));
+    for (size_t i = 0; i < M.v.size(); i++) val[i] = (T)M.v[i];
+    S.rp = dalloc<int32_t>(h, rp32.size());
+    S.col = dalloc<int32_t>(h, std::max<size_t>(M.ci.size(), 1));
+    S.val = dalloc<T>(h, val.size());
+    HIPCHK(hipMemcpyAsync(S.rp, rp32.data(), rp32.size() * 4, hipMemcpyHostToDevice, h->stream));
+    if (!M.ci.empty()) HIPCHK(hipMemcpyAsync(S.col, M.ci.data(), M.ci.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(S.val, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return S;
   }
   S.ngroups = sptr[S.nslices];
   std::vector<int32_t> col((size_t)S.ngroups * 64, 0);
@@ -69,13 +91,13 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M) {
   for (int32_t s = 0; s < S.nslices; s++) {
     for (int lane = 0; lane < kSell; lane++) {
       const int32_t r = s * kSell + lane;
-      const int64_t len = r < M.n ? M.rp[r + 1] - M.rp[r] : 0;
+      const int64_t ln = r < M.n ? len(r) : 0;
       // padding columns point at the row's own node (or 0), values stay 0
       const int32_t padc = r < M.n ? std::min<int32_t>(r, std::max(M.nc - 1, 0)) : 0;
       for (int32_t g = sptr[s]; g < sptr[s + 1]; g++) {
         const int64_t k = g - sptr[s];
         const size_t cidx = (size_t)g * 64 + lane;
-        if (k < len) {
+        if (k < ln) {
           const int64_t src = M.rp[r] + k;
           col[cidx] = M.ci[src];
           for (int e = 0; e < 9; e++) val[((size_t)g * 9 + e) * 64 + lane] = (T)M.v[(size_t)src * 9 + e];
@@ -94,8 +116,8 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M) {
   HIPCHK(hipStreamSynchronize(h->stream));
   return S;
 }
-template Sell<double> upload_sell<double>(aspamg_ctx *, const HostBSR &);
-template Sell<float> upload_sell<float>(aspamg_ctx *, const HostBSR &);
+template Sell<double> upload_sell<double>(aspamg_ctx *, const HostBSR &, bool);
+template Sell<float> upload_sell<float>(aspamg_ctx *, const HostBSR &, bool);
 
 DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M) {
   DevBSR d;
@@ -600,9 +622,9 @@ aspamg_status aspamg_level_info(aspamg_handle h, int32_t level, aspamg_level_inf
   o->lambda1 = L.lambda1;
   o->omega_q = L.omega_q;
   o->omega_s = L.omega_s;
-  o->sell_slots_A = L.A64.ngroups * 64;
-  o->sell_slots_G = L.G64.ngroups * 64;
-  o->sell_slots_GT = L.GT64.ngroups * 64;
+  o->sell_slots_A = L.A64.slots();
+  o->sell_slots_G = L.G64.slots();
+  o->sell_slots_GT = L.GT64.slots();
   return ASPAMG_OK;
 }
 
@@ -731,6 +753,62 @@ aspamg_status aspamg_assembler_destroy(aspamg_assembler a) {
   (void)hipFree(a->Ke0);
   delete a;
   return ASPAMG_OK;
+}
+
+aspamg_status aspamg_time_kernel(aspamg_handle h, int32_t which, int32_t reps, double *avg_ms, double *alg_bytes) {
+  ABI_BEGIN
+  if (!h || which < 0 || which > 4 || reps < 1 || !avg_ms || !alg_bytes)
+    fail(ASPAMG_EINVAL, "invalid arguments to aspamg_time_kernel");
+  hipStream_t s = h->stream;
+  const Level &L0 = h->lev[0];
+  const double N = (double)L0.A.n;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double bytes = 0.0;
+  auto run = [&]() {
+    switch (which) {
+      case 0:
+        launch_spmv_dot(L0.A64, h->vp, h->vq, h->part, nullptr, s);
+        break;
+      case 1:
+        launch_spmv<float, float, float>(L0.A32, L0.v32.z, L0.v32.r, L0.v32.y, -1.0, nullptr, s);
+        break;
+      case 2:
+        launch_spmv<double, double, double>(L0.A64, L0.v64.z, L0.v64.r, L0.v64.y, -1.0, nullptr, s);
+        break;
+      case 3:
+        cycle_level<float>(h, 0, L0.v32.y, L0.v32.z, nullptr);
+        break;
+      case 4:
+        cycle_level<double>(h, 0, L0.v64.y, L0.v64.z, nullptr);
+        break;
+    }
+  };
+  const double nb = (double)L0.A.nnzb();
+  switch (which) {
+    case 0: bytes = nb * 76.0 + N * 3.0 * 8.0 * 2.0; break;            // K, p, q
+    case 1: bytes = nb * 40.0 + N * 3.0 * 4.0 * 3.0; break;            // A32, s, y, r
+    case 2: bytes = nb * 76.0 + N * 3.0 * 8.0 * 3.0; break;
+    case 3: bytes = cycle_bytes(h, 32); break;
+    case 4: bytes = cycle_bytes(h, 64); break;
+  }
+  // inputs: zero-filled vectors are enough for timing (the bytes streamed do not depend on values)
+  run();
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; i++) run();
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
+  *avg_ms = (double)ms / reps;
+  *alg_bytes = bytes;
+  return ASPAMG_OK;
+  ABI_END
 }
 
 aspamg_status aspamg_solve_batch(aspamg_handle h, int32_t k, const double *F_dev, int64_t ldf, double *U_dev,

@@ -13,6 +13,8 @@
 namespace aspamg {
 
 constexpr int kSell = 64;           // rows per SELL slice = one wavefront
+constexpr double kMaxPadding = 1.25; // more SELL padding than this selects the vector BSR form
+constexpr int kVecRows = 100000;    // operators with fewer rows use the vector BSR form
 constexpr int kMaxFsaiNodes = 32;   // off-diagonal nodes an FSAI row may hold
 constexpr int kMaxPEntries = 8;     // interpolation entries per scalar row (n_max cap)
 
@@ -43,20 +45,30 @@ struct DevBSR {
   double *v = nullptr;
 };
 
-// SELL-64 layout of a 3x3-block matrix: slice s of 64 consecutive block rows
-// owns slot groups [sptr[s], sptr[s+1]); slot group g holds one block per row:
-// col[g*64 + lane], and values val[(g*9 + k)*64 + lane] for entry k of the
-// block (component-major, so a wavefront reads 64 consecutive values).
-// Padded slots have value 0 and a valid column.
+// Device layout of one stored 3x3-block operator, in one of two forms chosen
+// at setup from its shape:
+//  * SELL-64 (mode 0, operators with many rows of similar length): slice s of
+//    64 consecutive block rows owns slot groups [sptr[s], sptr[s+1]); slot
+//    group g holds one block per row: col[g*64+lane] and values
+//    val[(g*9 + k)*64 + lane] for entry k (component-major, so a wavefront
+//    reads 64 consecutive values).  Padded slots hold 0 and a valid column.
+//    perm (optional, unused by the setup) maps slot-row position -> row.
+//  * vector BSR (mode 1, operators with few or irregular rows): plain block
+//    CSR (rp, col, val[nnzb][9]); a group of L lanes shares one block row and
+//    reduces its three sums with a butterfly.
 template <typename T>
 struct Sell {
   int32_t n = 0, nc = 0, nslices = 0;
-  int64_t ngroups = 0;     // padded slot groups
+  int32_t mode = 0;        // 0 SELL-64, 1 vector BSR
+  int32_t lanes = 1;       // lanes per row (mode 1)
+  int64_t ngroups = 0;     // padded slot groups (mode 0)
   int64_t nnzb = 0;        // real blocks
   int32_t *sptr = nullptr;
   int32_t *col = nullptr;
   T *val = nullptr;
-  size_t bytes() const { return (size_t)ngroups * 64 * (sizeof(int32_t) + 9 * sizeof(T)) + (nslices + 1) * 4; }
+  int32_t *perm = nullptr;
+  int32_t *rp = nullptr;   // mode 1
+  int64_t slots() const { return mode == 0 ? ngroups * 64 : nnzb; }
 };
 
 // Device-resident PCG control block (one per solve stream).
@@ -151,7 +163,7 @@ T *dalloc(aspamg_ctx *h, size_t n) { return static_cast<T *>(dmalloc(h, n * size
 // ---- layout builders (host) ----
 HostBSR transpose(const HostBSR &M);
 template <typename T>
-Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M);
+Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, bool force_sell = false);
 DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M);
 
 // ---- solve-path kernel launchers (kernels_solve.hip) ----
