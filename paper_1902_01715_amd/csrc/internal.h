@@ -13,7 +13,7 @@
 namespace aspamg {
 
 constexpr int kSell = 64;           // rows per SELL slice = one wavefront
-constexpr double kMaxPadding = 1.25; // more SELL padding than this selects the vector BSR form
+constexpr double kMaxPadding = 2.5;  // more SELL padding than this selects the vector BSR form
 constexpr int kVecRows = 100000;    // operators with fewer rows use the vector BSR form
 constexpr int kMaxFsaiNodes = 32;   // off-diagonal nodes an FSAI row may hold
 constexpr int kMaxPEntries = 8;     // interpolation entries per scalar row (n_max cap)

@@ -14,6 +14,20 @@ namespace {
 
 __device__ __forceinline__ bool ctrl_done(const PcgCtrl *c) { return c != nullptr && c->done != 0; }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).  The
+// logical block index below gives every XCD one contiguous range of blocks,
+// so neighbouring rows, whose x-gathers overlap, share one L2.
+__device__ __forceinline__ int32_t xcd_block() {
+  const int32_t nb = gridDim.x, b = blockIdx.x;
+  const int32_t x = b & 7, per = nb >> 3, rem = nb & 7;
+  return x * per + (x < rem ? x : rem) + (b >> 3);
+}
+
+// matrix entries are streamed exactly once per product: keep them out of the
+// caches so that the gathered vector stays resident
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+
 // Deterministic sum over a 256-thread block; the result is valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double *sm) {
 #pragma unroll
@@ -38,7 +52,7 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
                                                    const TX *__restrict__ x, TO *y, const TO *w, T alpha,
                                                    const PcgCtrl *ctrl) {
   if (ctrl_done(ctrl)) return;
-  const int32_t q = blockIdx.x * 256 + threadIdx.x;
+  const int32_t q = xcd_block() * 256 + threadIdx.x;
   if (q >= n) return;
   const int32_t sl = q >> 6, lane = q & 63;
   const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
@@ -47,11 +61,11 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
   const T *vp = val + (size_t)g0 * 576 + lane;
 #pragma unroll 2
   for (int32_t g = g0; g < g1; ++g) {
-    const int32_t c = *cp;
+    const int32_t c = ld_stream(cp);
     const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
-    a0 += vp[0] * x0 + vp[64] * x1 + vp[128] * x2;
-    a1 += vp[192] * x0 + vp[256] * x1 + vp[320] * x2;
-    a2 += vp[384] * x0 + vp[448] * x1 + vp[512] * x2;
+    a0 += ld_stream(vp) * x0 + ld_stream(vp + 64) * x1 + ld_stream(vp + 128) * x2;
+    a1 += ld_stream(vp + 192) * x0 + ld_stream(vp + 256) * x1 + ld_stream(vp + 320) * x2;
+    a2 += ld_stream(vp + 384) * x0 + ld_stream(vp + 448) * x1 + ld_stream(vp + 512) * x2;
     cp += 64;
     vp += 576;
   }
@@ -78,13 +92,14 @@ __global__ void __launch_bounds__(256) k_bsr_vec(int32_t n, const int32_t *__res
                                                  const TX *__restrict__ x, TO *y, const TO *w, T alpha,
                                                  const PcgCtrl *ctrl) {
   if (ctrl_done(ctrl)) return;
-  const int32_t t = blockIdx.x * 256 + threadIdx.x;
+  const int32_t t = xcd_block() * 256 + threadIdx.x;
   const int32_t row = t / L;
   const int lane = t & (L - 1);
   if (row >= n) return;                 // whole groups leave together
   T a0 = 0, a1 = 0, a2 = 0;
   const int32_t b1 = rp[row + 1];
   for (int32_t b = rp[row] + lane; b < b1; b += L) {
+    // strided per-lane block reads rely on the caches: plain loads here
     const int32_t c = col[b];
     const T *v = val + (size_t)b * 9;
     const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
@@ -122,7 +137,7 @@ __global__ void __launch_bounds__(256) k_sell_spmv_dot(int32_t n, const int32_t 
                                                        double *__restrict__ part, const PcgCtrl *ctrl) {
   __shared__ double sm[4];
   if (ctrl_done(ctrl)) return;
-  const int32_t q = blockIdx.x * 256 + threadIdx.x;
+  const int32_t q = xcd_block() * 256 + threadIdx.x;
   double d = 0.0;
   if (q < n) {
     const int32_t sl = q >> 6, lane = q & 63;
@@ -133,11 +148,11 @@ __global__ void __launch_bounds__(256) k_sell_spmv_dot(int32_t n, const int32_t 
     const double *vp = val + (size_t)g0 * 576 + lane;
 #pragma unroll 2
     for (int32_t g = g0; g < g1; ++g) {
-      const int32_t c = *cp;
+      const int32_t c = ld_stream(cp);
       const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
-      a0 += vp[0] * x0 + vp[64] * x1 + vp[128] * x2;
-      a1 += vp[192] * x0 + vp[256] * x1 + vp[320] * x2;
-      a2 += vp[384] * x0 + vp[448] * x1 + vp[512] * x2;
+      a0 += ld_stream(vp) * x0 + ld_stream(vp + 64) * x1 + ld_stream(vp + 128) * x2;
+      a1 += ld_stream(vp + 192) * x0 + ld_stream(vp + 256) * x1 + ld_stream(vp + 320) * x2;
+      a2 += ld_stream(vp + 384) * x0 + ld_stream(vp + 448) * x1 + ld_stream(vp + 512) * x2;
       cp += 64;
       vp += 576;
     }
