@@ -90,6 +90,8 @@ typedef struct {
   double  c_gd, c_op, c_fs; /* grid, operator and FSAI complexities                   */
   double  bytes_vcycle;     /* algorithmic HBM bytes of one V-cycle                   */
   double  bytes_iter;       /* algorithmic HBM bytes of one PCG iteration             */
+  int32_t spmm_tile;        /* right-hand sides per SpMM tile (solve_batch), else 0   */
+  int32_t reserved;
 } aspamg_stats;
 
 /* Per-level summary, see aspamg_level_info. */

@@ -46,7 +46,8 @@ class Stats(C.Structure):
         ("status", C.c_int32), ("iterations", C.c_int32), ("levels", C.c_int32), ("cycle_precision", C.c_int32),
         ("relres_recursive", C.c_double), ("relres_true", C.c_double), ("t_setup_s", C.c_double),
         ("t_solve_s", C.c_double), ("c_gd", C.c_double), ("c_op", C.c_double), ("c_fs", C.c_double),
-        ("bytes_vcycle", C.c_double), ("bytes_iter", C.c_double),
+        ("bytes_vcycle", C.c_double), ("bytes_iter", C.c_double), ("spmm_tile", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
     def as_dict(self):
@@ -151,12 +152,16 @@ class Solver:
         self.params = params if params is not None else default_params()
         self.n = int(len(row_ptr) - 1)
         self.nnzb = int(row_ptr[-1])
-        if isinstance(row_ptr, np.ndarray):
-            row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
-            col = np.ascontiguousarray(col, dtype=np.int32)
-            vals = np.ascontiguousarray(vals, dtype=np.float64)
-        if isinstance(V0, np.ndarray):
-            V0 = np.ascontiguousarray(V0, dtype=np.float64)
+        def host_or_device(a, dtype, tdtype):
+            if isinstance(a, np.ndarray):
+                return np.ascontiguousarray(a, dtype=dtype)
+            assert a.dtype == tdtype, f"expected {tdtype}, got {a.dtype}"
+            return a.contiguous()
+
+        row_ptr = host_or_device(row_ptr, np.int32, torch.int32)
+        col = host_or_device(col, np.int32, torch.int32)
+        vals = host_or_device(vals, np.float64, torch.float64)
+        V0 = host_or_device(V0, np.float64, torch.float64)
         n_tv = int(V0.shape[-1])
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()

@@ -27,6 +27,8 @@ SOURCES = [
     # (file, is_device, extra flags)
     ("kernels_solve.hip", True, []),
     ("kernels_setup.hip", True, ["-ffp-contract=off"]),
+    ("kernels_batch.hip", True, []),
+    ("batch_api.cpp", False, []),
     ("setup_host.cpp", False, ["-ffp-contract=off", "-fopenmp"]),
     ("api.cpp", False, []),
 ]

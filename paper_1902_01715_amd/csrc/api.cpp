@@ -392,6 +392,9 @@ aspamg_status aspamg_default_params(aspamg_params *o) {
 
 aspamg_status aspamg_destroy(aspamg_handle h) {
   if (!h) return ASPAMG_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  destroy_batch(h->batch);
+  h->batch = nullptr;
   for (int i = 0; i < 2; i++)
     if (h->graph[i]) (void)hipGraphExecDestroy(h->graph[i]);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
@@ -813,9 +816,12 @@ aspamg_status aspamg_time_kernel(aspamg_handle h, int32_t which, int32_t reps, d
 
 aspamg_status aspamg_solve_batch(aspamg_handle h, int32_t k, const double *F_dev, int64_t ldf, double *U_dev,
                                  int64_t ldu, aspamg_stats *st) {
-  (void)h; (void)k; (void)F_dev; (void)ldf; (void)U_dev; (void)ldu; (void)st;
-  g_last_error = "solve_batch is not built yet";
-  return ASPAMG_EINVAL;
+  ABI_BEGIN
+  const aspamg_status r = solve_batch_impl(h, k, F_dev, ldf, U_dev, ldu, st);
+  if (st)
+    for (int j = 0; j < k; j++) st[j].spmm_tile = batch_tile(h, h->prec);
+  return r;
+  ABI_END
 }
 
 }  // extern "C"

@@ -214,8 +214,10 @@ void launch_assemble(int64_t nnzb, const int64_t *slot_ptr, const int32_t *contr
 void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0);
 double quantize(double s, int bits);
 
-// ---- V-cycle (api.cpp) ----
-template <typename T>
-void vcycle_launch(aspamg_ctx *h, const PcgCtrl *ctrl);
+// ---- multi-RHS solve (batch_api.cpp) ----
+aspamg_status solve_batch_impl(aspamg_ctx *h, int32_t k, const double *F, int64_t ldf, double *U, int64_t ldu,
+                               aspamg_stats *st);
+void destroy_batch(BatchWork *w);
+int batch_tile(const aspamg_ctx *h, int precision);
 
 }  // namespace aspamg

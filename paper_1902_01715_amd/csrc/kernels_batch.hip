@@ -1,0 +1,365 @@
+// Multi-right-hand-side kernels: block-CSR SpMM over a tile of KB columns and
+// the column-wise PCG vector operations with deterministic per-column
+// reductions.  Vectors are stored [dof][ld] (right-hand sides fastest), so the
+// KB lanes that share one block row read KB consecutive entries of every
+// gathered x row, and every matrix block is fetched once for the whole tile.
+#include "batch.h"
+
+namespace aspamg {
+
+namespace {
+
+__device__ __forceinline__ bool bdone(const BatchCtrl *c) { return c != nullptr && c->all_done != 0; }
+
+// Y[:, j] = alpha * (A X)[:, j] (+ W[:, j]) for the KB columns of tile blockIdx.y.
+template <typename T, bool HAS_W, int KB>
+__global__ void __launch_bounds__(256) k_bsr_spmm(int32_t n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                  const T *__restrict__ X, T *Y, const T *W, int32_t ld, T alpha,
+                                                  const BatchCtrl *ctrl) {
+  if (bdone(ctrl)) return;
+  const int32_t t = blockIdx.x * 256 + threadIdx.x;
+  const int32_t row = t / KB;
+  const int32_t j = blockIdx.y * KB + (t & (KB - 1));
+  if (row >= n) return;
+  T a0 = 0, a1 = 0, a2 = 0;
+  const int32_t b1 = rp[row + 1];
+  for (int32_t b = rp[row]; b < b1; ++b) {
+    const int32_t c = col[b];
+    const T *v = val + (size_t)b * 9;
+    const T x0 = X[(size_t)(3 * c) * ld + j], x1 = X[(size_t)(3 * c + 1) * ld + j], x2 = X[(size_t)(3 * c + 2) * ld + j];
+    a0 += v[0] * x0 + v[1] * x1 + v[2] * x2;
+    a1 += v[3] * x0 + v[4] * x1 + v[5] * x2;
+    a2 += v[6] * x0 + v[7] * x1 + v[8] * x2;
+  }
+  const size_t o = (size_t)(3 * row) * ld + j;
+  if (HAS_W) {
+    Y[o] = alpha * a0 + W[o];
+    Y[o + ld] = alpha * a1 + W[o + ld];
+    Y[o + 2 * ld] = alpha * a2 + W[o + 2 * ld];
+  } else {
+    Y[o] = alpha * a0;
+    Y[o + ld] = alpha * a1;
+    Y[o + 2 * ld] = alpha * a2;
+  }
+}
+
+// Q = K P and per-column partials of P.Q (FP64).  A fixed grid of at most
+// kBatchParts blocks walks the rows with a stride, so the partial count (and
+// the order of the final sums) does not depend on the problem size.
+template <int KB>
+__global__ void __launch_bounds__(256) k_bsr_spmm_dot(int32_t n, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col,
+                                                      const double *__restrict__ val, const double *__restrict__ X,
+                                                      double *__restrict__ Y, int32_t ld, double *__restrict__ part,
+                                                      const BatchCtrl *ctrl) {
+  __shared__ double sm[256];
+  if (bdone(ctrl)) return;
+  const int lane = threadIdx.x & (KB - 1);
+  const int32_t j = blockIdx.y * KB + lane;
+  const int32_t rstride = gridDim.x * (256 / KB);
+  double d = 0.0;
+  for (int32_t row = (blockIdx.x * 256 + threadIdx.x) / KB; row < n; row += rstride) {
+    double a0 = 0, a1 = 0, a2 = 0;
+    const int32_t b1 = rp[row + 1];
+    for (int32_t b = rp[row]; b < b1; ++b) {
+      const int32_t c = col[b];
+      const double *v = val + (size_t)b * 9;
+      const double x0 = X[(size_t)(3 * c) * ld + j], x1 = X[(size_t)(3 * c + 1) * ld + j],
+                   x2 = X[(size_t)(3 * c + 2) * ld + j];
+      a0 += v[0] * x0 + v[1] * x1 + v[2] * x2;
+      a1 += v[3] * x0 + v[4] * x1 + v[5] * x2;
+      a2 += v[6] * x0 + v[7] * x1 + v[8] * x2;
+    }
+    const size_t o = (size_t)(3 * row) * ld + j;
+    Y[o] = a0;
+    Y[o + ld] = a1;
+    Y[o + 2 * ld] = a2;
+    d += (X[o] * a0 + X[o + ld] * a1) + X[o + 2 * ld] * a2;
+  }
+  sm[threadIdx.x] = d;
+  __syncthreads();
+  if (threadIdx.x < KB) {
+    double s = 0.0;
+    for (int r = 0; r < 256 / KB; r++) s += sm[r * KB + threadIdx.x];
+    part[(size_t)blockIdx.x * ld + blockIdx.y * KB + threadIdx.x] = s;
+  }
+}
+
+// Z = Ainv Y for the dense coarsest operator, one thread per (row, column).
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_gemm(int32_t nd, const double *__restrict__ inv,
+                                                    const T *__restrict__ Y, T *__restrict__ Z, int32_t ld,
+                                                    const BatchCtrl *ctrl) {
+  if (bdone(ctrl)) return;
+  const int32_t t = blockIdx.x * 256 + threadIdx.x;
+  const int32_t row = t / ld, j = t % ld;
+  if (row >= nd) return;
+  const double *a = inv + (size_t)row * nd;
+  double s = 0.0;
+  for (int32_t i = 0; i < nd; i++) s += a[i] * (double)Y[(size_t)i * ld + j];
+  Z[(size_t)row * ld + j] = (T)s;
+}
+
+// Column-wise vector kernels: a 256-thread block is (256/ld) dof rows x ld
+// columns; every block walks dof rows with a grid stride and leaves one
+// partial per column, summed later in block order.
+__device__ __forceinline__ void col_partial(double v, double *sm, double *part, int32_t ld, int slot) {
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x < ld) {
+    double s = 0.0;
+    for (int r = 0; r < 256 / ld; r++) s += sm[r * ld + threadIdx.x];
+    part[((size_t)slot * gridDim.x + blockIdx.x) * ld + threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_col_dot(int64_t nrow, const double *__restrict__ A,
+                                                 const double *__restrict__ B, int32_t ld, double *__restrict__ part,
+                                                 const BatchCtrl *ctrl) {
+  __shared__ double sm[256];
+  if (bdone(ctrl)) return;
+  const int rpb = 256 / ld, r0 = threadIdx.x / ld, j = threadIdx.x % ld;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * rpb + r0; i < nrow; i += (int64_t)gridDim.x * rpb)
+    s += A[i * ld + j] * B[i * ld + j];
+  col_partial(s, sm, part, ld, 0);
+}
+
+__global__ void __launch_bounds__(256) k_col_update(int64_t nrow, double *__restrict__ U, double *__restrict__ R,
+                                                    const double *__restrict__ P, const double *__restrict__ Q,
+                                                    const double *__restrict__ Z, int32_t ld,
+                                                    double *__restrict__ part, const BatchCtrl *ctrl) {
+  __shared__ double sm[256];
+  if (bdone(ctrl)) return;
+  const int rpb = 256 / ld, r0 = threadIdx.x / ld, j = threadIdx.x % ld;
+  const double alpha = ctrl->alpha[j];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * rpb + r0; i < nrow; i += (int64_t)gridDim.x * rpb) {
+    const int64_t o = i * ld + j;
+    U[o] += alpha * P[o];
+    const double ri = R[o] - alpha * Q[o];
+    R[o] = ri;
+    s1 += ri * ri;
+    s2 += ri * Z[o];
+  }
+  col_partial(s1, sm, part, ld, 0);
+  col_partial(s2, sm, part, ld, 1);
+}
+
+template <typename TZ>
+__global__ void __launch_bounds__(256) k_col_rz(int64_t nrow, const double *__restrict__ R,
+                                                const TZ *__restrict__ Zc, double *__restrict__ Z, int32_t ld,
+                                                double *__restrict__ part, const BatchCtrl *ctrl) {
+  __shared__ double sm[256];
+  if (bdone(ctrl)) return;
+  const int rpb = 256 / ld, r0 = threadIdx.x / ld, j = threadIdx.x % ld;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * rpb + r0; i < nrow; i += (int64_t)gridDim.x * rpb) {
+    const int64_t o = i * ld + j;
+    const double zi = (double)Zc[o];
+    if ((const void *)Zc != (const void *)Z) Z[o] = zi;
+    s += R[o] * zi;
+  }
+  col_partial(s, sm, part, ld, 0);
+}
+
+__global__ void __launch_bounds__(256) k_col_pupdate(int64_t n, const double *__restrict__ Z, double *__restrict__ P,
+                                                     int32_t ld, const BatchCtrl *ctrl) {
+  if (bdone(ctrl)) return;
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < n; o += (int64_t)gridDim.x * 256)
+    P[o] = Z[o] + ctrl->beta[o % ld] * P[o];
+}
+
+// Per-column scalar steps; thread j owns column j.  A finished column gets
+// alpha = 0 (its iterate is frozen) and keeps the iteration count at which it
+// stopped.  all_done is raised when every column is finished.
+__global__ void __launch_bounds__(64) k_col_finish(int mode, const double *__restrict__ part, int nparts, int32_t ld,
+                                                   BatchCtrl *ctrl) {
+  __shared__ int32_t open[64];
+  if (ctrl->all_done) return;
+  const int j = threadIdx.x;
+  open[j] = 0;
+  if (j < ld) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = 0; b < nparts; b++) s0 += part[(size_t)b * ld + j];
+    if (mode == kFinRr)
+      for (int b = 0; b < nparts; b++) s1 += part[((size_t)nparts + b) * ld + j];
+    const bool dn = ctrl->done[j] != 0;
+    switch (mode) {
+      case kFinInitF:
+        ctrl->fnorm[j] = sqrt(s0);
+        ctrl->iter[j] = 0;
+        ctrl->relres[j] = 0.0;
+        if (!(s0 == s0)) { ctrl->status[j] = ASPAMG_ENAN; ctrl->done[j] = 1; }
+        else if (s0 == 0.0) { ctrl->status[j] = ASPAMG_OK; ctrl->done[j] = 1; }
+        else { ctrl->status[j] = ASPAMG_NOT_CONVERGED; ctrl->relres[j] = 1.0; }
+        break;
+      case kFinInitRz:
+        ctrl->rz[j] = s0;
+        if (!dn && !(s0 > 0.0)) { ctrl->status[j] = (s0 == s0) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN; ctrl->done[j] = 1; }
+        break;
+      case kFinAlpha:
+        if (dn) { ctrl->alpha[j] = 0.0; break; }
+        if (!(s0 > 0.0)) {
+          ctrl->status[j] = (s0 == s0) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN;
+          ctrl->done[j] = 1;
+          ctrl->alpha[j] = 0.0;
+        } else {
+          ctrl->alpha[j] = ctrl->rz[j] / s0;
+        }
+        break;
+      case kFinRr:
+        if (dn) break;
+        ctrl->rzo[j] = s1;
+        ctrl->iter[j] += 1;
+        ctrl->relres[j] = sqrt(s0) / ctrl->fnorm[j];
+        if (!(s0 == s0)) { ctrl->status[j] = ASPAMG_ENAN; ctrl->done[j] = 1; }
+        else if (sqrt(s0) <= ctrl->rtol * ctrl->fnorm[j]) { ctrl->status[j] = ASPAMG_OK; ctrl->done[j] = 1; }
+        else if (ctrl->iter[j] >= ctrl->max_it) { ctrl->done[j] = 1; }
+        break;
+      case kFinBeta:
+        if (dn) { ctrl->beta[j] = 0.0; break; }
+        if (!(s0 > 0.0)) {
+          ctrl->status[j] = (s0 == s0) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN;
+          ctrl->done[j] = 1;
+          ctrl->beta[j] = 0.0;
+        } else {
+          ctrl->beta[j] = (s0 - ctrl->rzo[j]) / ctrl->rz[j];
+          ctrl->rz[j] = s0;
+        }
+        break;
+    }
+    open[j] = ctrl->done[j] ? 0 : 1;
+  }
+  __syncthreads();
+  if (j == 0) {
+    int any = 0;
+    for (int q = 0; q < 64; q++) any += open[q];
+    if (any == 0) ctrl->all_done = 1;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_copy_cols(int64_t nrow, int32_t k, const double *__restrict__ src, int64_t lds,
+                                                   double *__restrict__ dst, int64_t ldd, int32_t kfill) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < nrow * kfill; t += (int64_t)gridDim.x * 256) {
+    const int64_t i = t / kfill, j = t % kfill;
+    dst[i * ldd + j] = j < k ? src[i * lds + j] : 0.0;
+  }
+}
+
+}  // namespace
+
+int batch_vec_blocks(int64_t nrow, int ld) {
+  const int64_t rpb = 256 / ld;
+  int64_t b = (nrow + rpb - 1) / rpb;
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <typename T, bool HAS_W, int KB>
+static void spmm_kb(const DevBSRT<T> &A, const T *X, T *Y, const T *W, int ld, double alpha, const BatchCtrl *c,
+                    hipStream_t s) {
+  const int64_t threads = (int64_t)A.n * KB;
+  dim3 grid((unsigned)((threads + 255) / 256), ld / KB);
+  hipLaunchKernelGGL((k_bsr_spmm<T, HAS_W, KB>), grid, dim3(256), 0, s, A.n, A.rp, A.ci, A.v, X, Y, W, ld, (T)alpha,
+                     c);
+}
+
+template <typename T>
+void launch_spmm(const DevBSRT<T> &A, const T *X, T *Y, const T *W, int ld, int kb, double alpha,
+                 const BatchCtrl *c, hipStream_t s) {
+  if (A.n == 0) return;
+  kb = kb > ld ? ld : kb;
+#define SPMM_CASE(K)                                                     \
+  case K:                                                                \
+    if (W) spmm_kb<T, true, K>(A, X, Y, W, ld, alpha, c, s);             \
+    else spmm_kb<T, false, K>(A, X, Y, W, ld, alpha, c, s);              \
+    break;
+  switch (kb) {
+    SPMM_CASE(4)
+    SPMM_CASE(8)
+    SPMM_CASE(16)
+    SPMM_CASE(32)
+    default: SPMM_CASE(1)
+  }
+#undef SPMM_CASE
+}
+template void launch_spmm<double>(const DevBSRT<double> &, const double *, double *, const double *, int, int, double,
+                                  const BatchCtrl *, hipStream_t);
+template void launch_spmm<float>(const DevBSRT<float> &, const float *, float *, const float *, int, int, double,
+                                 const BatchCtrl *, hipStream_t);
+
+void launch_spmm_dot(const DevBSRT<double> &A, const double *X, double *Y, int ld, int kb, double *part,
+                     const BatchCtrl *c, hipStream_t s) {
+  kb = kb > ld ? ld : kb;
+  dim3 grid((unsigned)spmm_dot_parts(A.n, ld, kb), ld / kb);
+#define DOT_CASE(K)                                                                                                \
+  case K:                                                                                                          \
+    hipLaunchKernelGGL(k_bsr_spmm_dot<K>, grid, dim3(256), 0, s, A.n, A.rp, A.ci, A.v, X, Y, ld, part, c); \
+    break;
+  switch (kb) {
+    DOT_CASE(4)
+    DOT_CASE(8)
+    DOT_CASE(16)
+    DOT_CASE(32)
+    default: DOT_CASE(1)
+  }
+#undef DOT_CASE
+}
+int spmm_dot_parts(int32_t n, int ld, int kb) {
+  kb = kb > ld ? ld : kb;
+  int64_t b = ((int64_t)n * kb + 255) / 256;
+  if (b > kBatchParts) b = kBatchParts;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <typename T>
+void launch_dense_gemm(int nd, const double *inv, const T *Y, T *Z, int ld, const BatchCtrl *c, hipStream_t s) {
+  const int64_t threads = (int64_t)nd * ld;
+  hipLaunchKernelGGL(k_dense_gemm<T>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, nd, inv, Y, Z, ld, c);
+}
+template void launch_dense_gemm<double>(int, const double *, const double *, double *, int, const BatchCtrl *,
+                                        hipStream_t);
+template void launch_dense_gemm<float>(int, const double *, const float *, float *, int, const BatchCtrl *,
+                                       hipStream_t);
+
+void launch_col_dot(int64_t nrow, const double *A, const double *B, int ld, double *part, const BatchCtrl *c,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_col_dot, dim3(batch_vec_blocks(nrow, ld)), dim3(256), 0, s, nrow, A, B, ld, part, c);
+}
+void launch_col_update(int64_t nrow, double *U, double *R, const double *P, const double *Q, const double *Z, int ld,
+                       double *part, const BatchCtrl *c, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_update, dim3(batch_vec_blocks(nrow, ld)), dim3(256), 0, s, nrow, U, R, P, Q, Z, ld, part,
+                     c);
+}
+template <typename TZ>
+void launch_col_rz(int64_t nrow, const double *R, const TZ *Zc, double *Z, int ld, double *part, const BatchCtrl *c,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_col_rz<TZ>, dim3(batch_vec_blocks(nrow, ld)), dim3(256), 0, s, nrow, R, Zc, Z, ld, part, c);
+}
+template void launch_col_rz<double>(int64_t, const double *, const double *, double *, int, double *,
+                                    const BatchCtrl *, hipStream_t);
+template void launch_col_rz<float>(int64_t, const double *, const float *, double *, int, double *,
+                                   const BatchCtrl *, hipStream_t);
+void launch_col_pupdate(int64_t nrow, const double *Z, double *P, int ld, const BatchCtrl *c, hipStream_t s) {
+  const int64_t n = nrow * ld;
+  int64_t b = (n + 255) / 256;
+  if (b > 2048) b = 2048;
+  hipLaunchKernelGGL(k_col_pupdate, dim3((unsigned)b), dim3(256), 0, s, n, Z, P, ld, c);
+}
+void launch_col_finish(int mode, const double *part, int nparts, int ld, BatchCtrl *c, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(64), 0, s, mode, part, nparts, ld, c);
+}
+void launch_copy_cols(int64_t nrow, int k, const double *src, int64_t lds, double *dst, int64_t ldd, int kfill,
+                      hipStream_t s) {
+  int64_t b = (nrow * kfill + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)b), dim3(256), 0, s, nrow, k, src, lds, dst, ldd, kfill);
+}
+
+}  // namespace aspamg
