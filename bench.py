@@ -27,6 +27,25 @@ METRIC = "PCG-AMG solve s and V-cycle HBM GB/s at 1e-10 rel-res, FP32 vs FP64 cy
 HBM_PEAK_GBS = 8000.0
 
 
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1902_01715_amd", "csrc", "kernels_solve.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of q = K p from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration), or
+    None when the kernel source changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_sell_spmv_dot_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernels_solve_sha256") != kernel_source_hash():
+        return None
+    return rec["bytes_per_launch"]
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -37,8 +56,10 @@ def make_problem(name):
         return PR.c2_cantilever(), "cantilever 320x32x32 Q1 (1,048,707 DOF), aspect 10, E=10^U[-3,3], nu=U[.25,.45]"
     if name == "c3":
         return PR.c3_layered_distorted(), "layered distorted block 128x128x64 Q1 (3,244,995 DOF), E=1/1e4 layers"
+    if name == "c4":
+        return PR.c4_multiload(), "cube 96^3 Q1 (2,738,019 DOF), 32 load cases"
     if name == "c5":
-        return PR.c5_simp(), "SIMP cube 48^3 Q1 (352,947 DOF), E=rho^3"
+        return PR.c5_simp(), "SIMP cube 48^3 Q1 (352,947 DOF), E=rho^3, compliance gradient"
     if name == "c1":
         return PR.c1_cube(), "unit cube 10^3 Q1 (3,993 DOF)"
     raise SystemExit(f"unknown config {name}")
@@ -69,6 +90,101 @@ def cpu_baseline(problem_name, gpu_iters):
                       f"{dof_ratio:.1f} and the GPU iteration count {gpu_iters}"}
 
 
+def bench_batch(args, p, desc, S, t_setup):
+    """32 load cases solved together (block SpMM V-cycle, tuned tile), FP32 and
+    FP64 cycles, graph replay vs eager launches."""
+    import numpy as np
+    import torch
+    F = torch.tensor(p.f, device="cuda")
+    out = {}
+    for prec in (32, 64):
+        S.set_precision(prec)
+        for _ in range(args.warmup):
+            S.solve_batch(F)
+        ts = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            U = S.solve_batch(F)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        st = S.last_stats
+        its = [s["iterations"] for s in st]
+        out[prec] = {"solve_s": float(np.median(ts)), "iterations_max": int(max(its)), "iterations_min": int(min(its)),
+                     "status": [s["status"] for s in st], "relres_true_max": max(s["relres_true"] for s in st),
+                     "spmm_tile": st[0]["spmm_tile"], "s_per_rhs": float(np.median(ts)) / F.shape[1]}
+        log(f"batch fp{prec}: {out[prec]['solve_s']:.4f} s for {F.shape[1]} RHS, its {min(its)}..{max(its)}, "
+            f"tile {st[0]['spmm_tile']}")
+    # eager launches (no graph) for comparison, FP32 cycle
+    S.params.use_graph = 0
+    from paper_1902_01715_amd import aspamg
+    prm = aspamg.default_params(max_it=args.max_it, use_graph=0)
+    Se = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, prm)
+    Se.set_precision(32)
+    Se.solve_batch(F)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Se.solve_batch(F)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t
+    Se.close()
+    # single-RHS reference: FP32 solve of column 0
+    S.set_precision(32)
+    f0 = F[:, 0].contiguous()
+    S.solve(f0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    S.solve(f0)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t
+    t32, t64 = out[32]["solve_s"], out[64]["solve_s"]
+    return {
+        "metric": METRIC, "value": t32, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t32 * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 V-cycle in f64 PCG", "data": "synthetic",
+        "config": {"workload": desc, "config": args.config, "rhs": int(F.shape[1]), "setup_s": t_setup},
+        "fp32_cycle": out[32], "fp64_cycle": out[64], "speedup_fp64_over_fp32": t64 / t32,
+        "graph_vs_eager_fp32": {"graph_s": t32, "eager_s": t_eager},
+        "single_rhs_fp32_s": t_single, "batch_speedup_per_rhs": t_single / out[32]["s_per_rhs"],
+    }
+
+
+def bench_adjoint(args, p, desc):
+    """Compliance C = f.u with E = rho^3 and its gradient: forward (GPU
+    assembly, setup, solve) and backward (adjoint solve, element gradient)."""
+    import numpy as np
+    import torch
+    from paper_1902_01715_amd import aspamg
+    from paper_1902_01715_amd.autograd import ElasticModel, elastic_solve
+    model = ElasticModel.from_problem(p, aspamg.default_params(max_it=args.max_it))
+    f = torch.tensor(p.f, device="cuda")
+    res = []
+    for it in range(args.warmup + args.steps):
+        rho = torch.tensor(p.extra["rho"], device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = elastic_solve(rho ** 3, f, model)
+        C = torch.dot(f, u)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        C.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if it >= args.warmup:
+            res.append((t1 - t0, t2 - t1))
+    g = rho.grad
+    euler = float(((rho.detach() * g).sum() + 3 * C.detach()).abs() / C.detach())
+    fw = float(np.median([r[0] for r in res]))
+    bw = float(np.median([r[1] for r in res]))
+    return {
+        "metric": METRIC, "value": fw + bw, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": (fw + bw) * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "config": args.config},
+        "forward_s": fw, "backward_s": bw, "euler_identity_rel_err": euler, "compliance": float(C),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,12 +207,20 @@ def main():
     t0 = time.perf_counter()
     p, desc = make_problem(args.config)
     log(f"inputs {desc}: {time.perf_counter() - t0:.1f} s")
+    if args.config == "c5":
+        print(json.dumps(bench_adjoint(args, p, desc)), flush=True)
+        return
     prm = aspamg.default_params(max_it=args.max_it)
     t0 = time.perf_counter()
     S = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, prm)
     t_setup = time.perf_counter() - t0
     levels = [S.level_info(l) for l in range(S.nlev)]
     log(f"setup {t_setup:.1f} s, {len(levels)} levels: " + ", ".join(str(li["n"]) for li in levels))
+    if args.config == "c4":
+        out = bench_batch(args, p, desc, S, t_setup)
+        S.close()
+        print(json.dumps(out), flush=True)
+        return
     f = torch.tensor(p.f if p.f.ndim == 1 else p.f[:, 0], device="cuda")
     u = torch.empty_like(f)
 
@@ -165,7 +289,8 @@ def main():
                                       "sell_slots_GT", "omega_s", "fsai_rounds")} for li in levels],
         "roofline": {"bound": "hbm", "kernel": "k_sell_spmv_dot (q = K p, FP64 SELL-64)",
                      "achieved": kp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kp_gbs / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_ms": kp_ms, "alg_bytes_per_launch": kp_b},
+                     "traffic": measured_traffic(args.config), "avg_launch_ms": kp_ms,
+                     "alg_bytes_per_launch": kp_b},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -49,58 +49,69 @@ HostBSR transpose(const HostBSR &M) {
   return T;
 }
 
+// slot groups of the sliced layout with L lanes per row
+static std::vector<int32_t> sliced_ptr(const HostBSR &M, int L) {
+  const int rps = kSell / L;
+  const int32_t ns = (M.n + rps - 1) / rps;
+  std::vector<int32_t> sptr(ns + 1, 0);
+  for (int32_t s = 0; s < ns; s++) {
+    int64_t w = 0;
+    for (int32_t r = s * rps; r < std::min(M.n, (s + 1) * rps); r++)
+      w = std::max<int64_t>(w, (M.rp[r + 1] - M.rp[r] + L - 1) / L);
+    if ((int64_t)sptr[s] + w >= (int64_t)INT32_MAX / 64) fail(ASPAMG_EINVAL, "operator too large for the sliced layout");
+    sptr[s + 1] = sptr[s] + (int32_t)w;
+  }
+  return sptr;
+}
+
 template <typename T>
-Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, bool force_sell) {
+Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes) {
   Sell<T> S;
   S.n = M.n;
   S.nc = M.nc;
   S.nnzb = M.nnzb();
-  S.nslices = (M.n + kSell - 1) / kSell;
-  auto len = [&](int32_t r) { return M.rp[r + 1] - M.rp[r]; };
-  std::vector<int32_t> sptr(S.nslices + 1, 0);
-  for (int32_t s = 0; s < S.nslices; s++) {
-    int64_t w = 0;
-    for (int32_t r = s * kSell; r < std::min(M.n, (s + 1) * kSell); r++) w = std::max(w, len(r));
-    if ((int64_t)sptr[s] + w >= (int64_t)INT32_MAX / 64) fail(ASPAMG_EINVAL, "operator too large for SELL layout");
-    sptr[s + 1] = sptr[s] + (int32_t)w;
+  // lanes per row: enough threads in flight, then little padding
+  int L = 1;
+  std::vector<int32_t> sptr;
+  if (force_lanes) {
+    L = force_lanes;
+    sptr = sliced_ptr(M, L);
+  } else {
+    // smallest L that keeps kMinThreads lanes busy, then the L (up to 64)
+    // with the fewest padded slots; a larger L must save at least 5%
+    int L0 = 1;
+    while (L0 < 64 && (int64_t)M.n * L0 < kMinThreads) L0 *= 2;
+    int64_t best = -1;
+    for (int c = L0; c <= 64; c *= 2) {
+      std::vector<int32_t> sp = sliced_ptr(M, c);
+      const int64_t slots = (int64_t)sp.back() * 64;
+      if (best < 0 || (double)slots < 0.95 * (double)best) {
+        best = slots;
+        L = c;
+        sptr.swap(sp);
+      }
+    }
   }
-  const double padding = S.nnzb ? (double)sptr[S.nslices] * 64.0 / (double)S.nnzb : 1.0;
-  if (!force_sell && (M.n < kVecRows || padding > kMaxPadding)) {
-    // vector BSR: lanes per row ~ a quarter of the mean row length, power of two in [2, 64]
-    S.mode = 1;
-    S.nslices = 0;
-    const double avg = M.n ? (double)S.nnzb / M.n : 0.0;
-    int L = 2;
-    while (L < 64 && L * 4 < avg) L *= 2;
-    S.lanes = L;
-    std::vector<int32_t> rp32(M.rp.begin(), M.rp.end());
-    std::vector<T> val(std::max<size_t>(M.v.size(), 1));
-    for (size_t i = 0; i < M.v.size(); i++) val[i] = (T)M.v[i];
-    S.rp = dalloc<int32_t>(h, rp32.size());
-    S.col = dalloc<int32_t>(h, std::max<size_t>(M.ci.size(), 1));
-    S.val = dalloc<T>(h, val.size());
-    HIPCHK(hipMemcpyAsync(S.rp, rp32.data(), rp32.size() * 4, hipMemcpyHostToDevice, h->stream));
-    if (!M.ci.empty()) HIPCHK(hipMemcpyAsync(S.col, M.ci.data(), M.ci.size() * 4, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipMemcpyAsync(S.val, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    return S;
-  }
-  S.ngroups = sptr[S.nslices];
+  S.lanes = L;
+  const int rps = kSell / L;
+  S.nslices = (int32_t)sptr.size() - 1;
+  S.ngroups = sptr.back();
   std::vector<int32_t> col((size_t)S.ngroups * 64, 0);
   std::vector<T> val((size_t)S.ngroups * 576, (T)0);
   for (int32_t s = 0; s < S.nslices; s++) {
-    for (int lane = 0; lane < kSell; lane++) {
-      const int32_t r = s * kSell + lane;
-      const int64_t ln = r < M.n ? len(r) : 0;
+    for (int e = 0; e < kSell; e++) {
+      const int32_t r = s * rps + e / L;
+      const int j = e % L;
+      const int64_t len = r < M.n ? M.rp[r + 1] - M.rp[r] : 0;
       // padding columns point at the row's own node (or 0), values stay 0
       const int32_t padc = r < M.n ? std::min<int32_t>(r, std::max(M.nc - 1, 0)) : 0;
       for (int32_t g = sptr[s]; g < sptr[s + 1]; g++) {
-        const int64_t k = g - sptr[s];
-        const size_t cidx = (size_t)g * 64 + lane;
-        if (k < ln) {
+        const int64_t k = (int64_t)(g - sptr[s]) * L + j;
+        const size_t cidx = (size_t)g * 64 + e;
+        if (k < len) {
           const int64_t src = M.rp[r] + k;
           col[cidx] = M.ci[src];
-          for (int e = 0; e < 9; e++) val[((size_t)g * 9 + e) * 64 + lane] = (T)M.v[(size_t)src * 9 + e];
+          for (int q = 0; q < 9; q++) val[((size_t)g * 9 + q) * 64 + e] = (T)M.v[(size_t)src * 9 + q];
         } else {
           col[cidx] = padc;
         }
@@ -116,8 +127,8 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, bool force_sell) {
   HIPCHK(hipStreamSynchronize(h->stream));
   return S;
 }
-template Sell<double> upload_sell<double>(aspamg_ctx *, const HostBSR &, bool);
-template Sell<float> upload_sell<float>(aspamg_ctx *, const HostBSR &, bool);
+template Sell<double> upload_sell<double>(aspamg_ctx *, const HostBSR &, int);
+template Sell<float> upload_sell<float>(aspamg_ctx *, const HostBSR &, int);
 
 DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M) {
   DevBSR d;

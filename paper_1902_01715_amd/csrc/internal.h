@@ -13,8 +13,7 @@
 namespace aspamg {
 
 constexpr int kSell = 64;           // rows per SELL slice = one wavefront
-constexpr double kMaxPadding = 2.5;  // more SELL padding than this selects the vector BSR form
-constexpr int kVecRows = 100000;    // operators with fewer rows use the vector BSR form
+constexpr int64_t kMinThreads = 262144;  // lanes per row grow until n * L reaches this
 constexpr int kMaxFsaiNodes = 32;   // off-diagonal nodes an FSAI row may hold
 constexpr int kMaxPEntries = 8;     // interpolation entries per scalar row (n_max cap)
 
@@ -45,30 +44,26 @@ struct DevBSR {
   double *v = nullptr;
 };
 
-// Device layout of one stored 3x3-block operator, in one of two forms chosen
-// at setup from its shape:
-//  * SELL-64 (mode 0, operators with many rows of similar length): slice s of
-//    64 consecutive block rows owns slot groups [sptr[s], sptr[s+1]); slot
-//    group g holds one block per row: col[g*64+lane] and values
-//    val[(g*9 + k)*64 + lane] for entry k (component-major, so a wavefront
-//    reads 64 consecutive values).  Padded slots hold 0 and a valid column.
-//    perm (optional, unused by the setup) maps slot-row position -> row.
-//  * vector BSR (mode 1, operators with few or irregular rows): plain block
-//    CSR (rp, col, val[nnzb][9]); a group of L lanes shares one block row and
-//    reduces its three sums with a butterfly.
+// Device layout of one stored 3x3-block operator: sliced ELL with L lanes
+// per block row (L a power of two, 1..64).  A slice is the 64/L consecutive
+// block rows one wavefront serves; lane j of row r in the slice takes the
+// row's blocks j, j+L, j+2L, ...  Slice s owns slot groups [sptr[s],
+// sptr[s+1]); within slot group g, entry e = r*L + j holds its column at
+// col[g*64 + e] and block entry k at val[(g*9 + k)*64 + e] (component-major,
+// so every load instruction of a wavefront covers 64 consecutive values).
+// Padded entries hold 0 and a valid column.  L = 1 is plain SELL-64; larger L
+// serve short, irregular or coarse operators (less padding per slice and more
+// threads in flight); the L partial sums of a row meet in a butterfly.
 template <typename T>
 struct Sell {
   int32_t n = 0, nc = 0, nslices = 0;
-  int32_t mode = 0;        // 0 SELL-64, 1 vector BSR
-  int32_t lanes = 1;       // lanes per row (mode 1)
-  int64_t ngroups = 0;     // padded slot groups (mode 0)
+  int32_t lanes = 1;       // L
+  int64_t ngroups = 0;     // slot groups (64 entries each)
   int64_t nnzb = 0;        // real blocks
   int32_t *sptr = nullptr;
   int32_t *col = nullptr;
   T *val = nullptr;
-  int32_t *perm = nullptr;
-  int32_t *rp = nullptr;   // mode 1
-  int64_t slots() const { return mode == 0 ? ngroups * 64 : nnzb; }
+  int64_t slots() const { return ngroups * 64; }
 };
 
 // Device-resident PCG control block (one per solve stream).
@@ -163,7 +158,7 @@ T *dalloc(aspamg_ctx *h, size_t n) { return static_cast<T *>(dmalloc(h, n * size
 // ---- layout builders (host) ----
 HostBSR transpose(const HostBSR &M);
 template <typename T>
-Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, bool force_sell = false);
+Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes = 0);
 DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M);
 
 // ---- solve-path kernel launchers (kernels_solve.hip) ----

@@ -41,24 +41,25 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
   return r;
 }
 
-// y[row] = alpha * (A x)[row] (+ w[row]) for one 3x3 block row per lane.
-// A wavefront owns one SELL slice, so lane k streams slot k of every slot
-// group: 64 consecutive column indices, then 9 runs of 64 consecutive values.
-// With a row permutation, slot-row q of the slice belongs to block row perm[q].
-template <typename T, typename TX, typename TO, bool HAS_W, bool PERM>
+// y[row] = alpha * (A x)[row] (+ w[row]) on the sliced layout with L lanes per
+// block row.  A wavefront owns one slice of 64/L rows; lane e = r*L + j streams
+// entry e of every slot group of the slice: 64 consecutive column indices,
+// then 9 runs of 64 consecutive values.  The L partial sums of a row meet in a
+// butterfly and lane j = 0 writes the row.
+template <typename T, typename TX, typename TO, bool HAS_W, int L>
 __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__restrict__ sptr,
                                                    const int32_t *__restrict__ col,
-                                                   const T *__restrict__ val, const int32_t *__restrict__ perm,
-                                                   const TX *__restrict__ x, TO *y, const TO *w, T alpha,
-                                                   const PcgCtrl *ctrl) {
+                                                   const T *__restrict__ val, const TX *__restrict__ x, TO *y,
+                                                   const TO *w, T alpha, const PcgCtrl *ctrl) {
   if (ctrl_done(ctrl)) return;
-  const int32_t q = xcd_block() * 256 + threadIdx.x;
-  if (q >= n) return;
-  const int32_t sl = q >> 6, lane = q & 63;
+  const int32_t t = xcd_block() * 256 + threadIdx.x;
+  const int32_t sl = t >> 6, e = t & 63;
+  const int32_t row = sl * (64 / L) + e / L;
+  if (row >= n) return;                 // whole lane groups leave together
   const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
   T a0 = 0, a1 = 0, a2 = 0;
-  const int32_t *cp = col + (size_t)g0 * 64 + lane;
-  const T *vp = val + (size_t)g0 * 576 + lane;
+  const int32_t *cp = col + (size_t)g0 * 64 + e;
+  const T *vp = val + (size_t)g0 * 576 + e;
 #pragma unroll 2
   for (int32_t g = g0; g < g1; ++g) {
     const int32_t c = ld_stream(cp);
@@ -69,7 +70,15 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
     cp += 64;
     vp += 576;
   }
-  const int32_t row = PERM ? perm[q] : q;
+  if (L > 1) {
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) {
+      a0 += __shfl_xor(a0, o, L);
+      a1 += __shfl_xor(a1, o, L);
+      a2 += __shfl_xor(a2, o, L);
+    }
+    if ((e & (L - 1)) != 0) return;
+  }
   TO *yo = y + 3 * (size_t)row;
   if (HAS_W) {
     const TO *wo = w + 3 * (size_t)row;
@@ -83,56 +92,10 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
   }
 }
 
-// Vector block-CSR product for operators with few, long rows: a group of L
-// lanes (L divides 64) owns one block row, lane j takes blocks j, j+L, ...,
-// and the three sums are combined by a butterfly inside the group.
-template <typename T, typename TX, typename TO, bool HAS_W, int L>
-__global__ void __launch_bounds__(256) k_bsr_vec(int32_t n, const int32_t *__restrict__ rp,
-                                                 const int32_t *__restrict__ col, const T *__restrict__ val,
-                                                 const TX *__restrict__ x, TO *y, const TO *w, T alpha,
-                                                 const PcgCtrl *ctrl) {
-  if (ctrl_done(ctrl)) return;
-  const int32_t t = xcd_block() * 256 + threadIdx.x;
-  const int32_t row = t / L;
-  const int lane = t & (L - 1);
-  if (row >= n) return;                 // whole groups leave together
-  T a0 = 0, a1 = 0, a2 = 0;
-  const int32_t b1 = rp[row + 1];
-  for (int32_t b = rp[row] + lane; b < b1; b += L) {
-    // strided per-lane block reads rely on the caches: plain loads here
-    const int32_t c = col[b];
-    const T *v = val + (size_t)b * 9;
-    const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
-    a0 += v[0] * x0 + v[1] * x1 + v[2] * x2;
-    a1 += v[3] * x0 + v[4] * x1 + v[5] * x2;
-    a2 += v[6] * x0 + v[7] * x1 + v[8] * x2;
-  }
-#pragma unroll
-  for (int o = L / 2; o > 0; o >>= 1) {
-    a0 += __shfl_xor(a0, o, L);
-    a1 += __shfl_xor(a1, o, L);
-    a2 += __shfl_xor(a2, o, L);
-  }
-  if (lane == 0) {
-    TO *yo = y + 3 * (size_t)row;
-    if (HAS_W) {
-      const TO *wo = w + 3 * (size_t)row;
-      yo[0] = (TO)(alpha * a0) + wo[0];
-      yo[1] = (TO)(alpha * a1) + wo[1];
-      yo[2] = (TO)(alpha * a2) + wo[2];
-    } else {
-      yo[0] = (TO)(alpha * a0);
-      yo[1] = (TO)(alpha * a1);
-      yo[2] = (TO)(alpha * a2);
-    }
-  }
-}
-
 // q = K p with the block partial of p.q (PCG, FP64).
 __global__ void __launch_bounds__(256) k_sell_spmv_dot(int32_t n, const int32_t *__restrict__ sptr,
                                                        const int32_t *__restrict__ col,
                                                        const double *__restrict__ val,
-                                                       const int32_t *__restrict__ perm,
                                                        const double *__restrict__ x, double *__restrict__ y,
                                                        double *__restrict__ part, const PcgCtrl *ctrl) {
   __shared__ double sm[4];
@@ -141,7 +104,7 @@ __global__ void __launch_bounds__(256) k_sell_spmv_dot(int32_t n, const int32_t 
   double d = 0.0;
   if (q < n) {
     const int32_t sl = q >> 6, lane = q & 63;
-    const int32_t row = perm ? perm[q] : q;
+    const int32_t row = q;
     const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
     double a0 = 0, a1 = 0, a2 = 0;
     const int32_t *cp = col + (size_t)g0 * 64 + lane;
@@ -335,33 +298,25 @@ int vec_blocks(int64_t n) {
 int spmv_blocks(int32_t nrows) { return (nrows + 255) / 256; }
 
 template <typename T, typename TX, typename TO, bool HAS_W, int L>
-static void launch_vec(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
-                       hipStream_t s) {
-  const int64_t threads = (int64_t)A.n * L;
-  hipLaunchKernelGGL((k_bsr_vec<T, TX, TO, HAS_W, L>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, A.n,
-                     A.rp, A.col, A.val, x, y, w, (T)alpha, ctrl);
+static void launch_l(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
+                     hipStream_t s) {
+  const int64_t threads = (int64_t)A.nslices * 64;
+  hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, HAS_W, L>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                     A.n, A.sptr, A.col, A.val, x, y, w, (T)alpha, ctrl);
 }
 
 template <typename T, typename TX, typename TO, bool HAS_W>
 static void launch_spmv_w(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
                           hipStream_t s) {
-  if (A.mode == 1) {
-    switch (A.lanes) {
-      case 2: launch_vec<T, TX, TO, HAS_W, 2>(A, x, y, w, alpha, ctrl, s); break;
-      case 4: launch_vec<T, TX, TO, HAS_W, 4>(A, x, y, w, alpha, ctrl, s); break;
-      case 8: launch_vec<T, TX, TO, HAS_W, 8>(A, x, y, w, alpha, ctrl, s); break;
-      case 16: launch_vec<T, TX, TO, HAS_W, 16>(A, x, y, w, alpha, ctrl, s); break;
-      case 32: launch_vec<T, TX, TO, HAS_W, 32>(A, x, y, w, alpha, ctrl, s); break;
-      default: launch_vec<T, TX, TO, HAS_W, 64>(A, x, y, w, alpha, ctrl, s); break;
-    }
-    return;
+  switch (A.lanes) {
+    case 1: launch_l<T, TX, TO, HAS_W, 1>(A, x, y, w, alpha, ctrl, s); break;
+    case 2: launch_l<T, TX, TO, HAS_W, 2>(A, x, y, w, alpha, ctrl, s); break;
+    case 4: launch_l<T, TX, TO, HAS_W, 4>(A, x, y, w, alpha, ctrl, s); break;
+    case 8: launch_l<T, TX, TO, HAS_W, 8>(A, x, y, w, alpha, ctrl, s); break;
+    case 16: launch_l<T, TX, TO, HAS_W, 16>(A, x, y, w, alpha, ctrl, s); break;
+    case 32: launch_l<T, TX, TO, HAS_W, 32>(A, x, y, w, alpha, ctrl, s); break;
+    default: launch_l<T, TX, TO, HAS_W, 64>(A, x, y, w, alpha, ctrl, s); break;
   }
-  if (A.perm)
-    hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, HAS_W, true>), dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr,
-                       A.col, A.val, A.perm, x, y, w, (T)alpha, ctrl);
-  else
-    hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, HAS_W, false>), dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr,
-                       A.col, A.val, A.perm, x, y, w, (T)alpha, ctrl);
 }
 
 template <typename T, typename TX, typename TO>
@@ -379,8 +334,9 @@ template void launch_spmv<float, float, float>(const Sell<float> &, const float 
 
 void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_sell_spmv_dot, dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr, A.col, A.val, A.perm, x, y,
-                     part, ctrl);
+  // one lane per row (the fine-level operator is stored with L = 1)
+  hipLaunchKernelGGL(k_sell_spmv_dot, dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr, A.col, A.val, x, y, part,
+                     ctrl);
 }
 
 template <typename TV>
