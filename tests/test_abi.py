@@ -33,3 +33,19 @@ def test_default_params_and_struct_layout():
 
 def test_last_error_is_a_string():
     assert isinstance(aspamg.lib().aspamg_last_error(), bytes)
+
+
+def test_setup_rejects_invalid_arguments_before_touching_a_device():
+    import numpy as np
+    L = aspamg.lib()
+    p = aspamg.default_params()
+    h = ctypes.c_void_p()
+    rp = np.zeros(1, dtype=np.int32)
+    rc = L.aspamg_setup(ctypes.byref(p), 0, 0, rp.ctypes.data_as(ctypes.c_void_p), None, None, 6, None, None,
+                        ctypes.byref(h))
+    assert rc == aspamg.EINVAL and not h.value
+    assert b"invalid" in L.aspamg_last_error()
+    # NULL handle arguments are rejected by every entry point
+    assert L.aspamg_set_cycle_precision(None, 32) == aspamg.EINVAL
+    assert L.aspamg_solve(None, None, None, None) == aspamg.EINVAL
+    assert L.aspamg_destroy(None) == aspamg.OK
