@@ -9,7 +9,7 @@ is timed beside it.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line (rank 0): metric, value (FP32-cycle solve seconds), the
 FP64-cycle solve time, V-cycle HBM GB/s for both precisions, the roofline of
-the dominant kernel (PCG product q = K p, SELL-64 3x3-block SpMV) and the CPU
+the dominant kernel (PCG product q = K p, 3x3-block sliced-ELL SpMV) and the CPU
 oracle measured on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -286,8 +286,9 @@ def main():
         "kernels": {"residual_fp32_GBps": r32_b / (r32_ms * 1e-3) / 1e9,
                     "residual_fp64_GBps": r64_b / (r64_ms * 1e-3) / 1e9},
         "levels": [{k: li[k] for k in ("n", "n_coarse", "nnzb_A", "nnzb_G", "nnzb_P", "sell_slots_A", "sell_slots_G",
-                                      "sell_slots_GT", "omega_s", "fsai_rounds")} for li in levels],
-        "roofline": {"bound": "hbm", "kernel": "k_sell_spmv_dot (q = K p, FP64 SELL-64)",
+                                      "sell_slots_GT", "sell_lanes64", "sell_lanes32", "omega_s", "fsai_rounds")}
+                   for li in levels],
+        "roofline": {"bound": "hbm", "kernel": "k_sell_spmv_dot (q = K p, FP64, sliced ELL with one lane per row)",
                      "achieved": kp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kp_gbs / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.config), "avg_launch_ms": kp_ms,
                      "alg_bytes_per_launch": kp_b},

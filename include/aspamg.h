@@ -102,7 +102,12 @@ typedef struct {
   int32_t has_smoother;    /* 0 on the coarsest level                               */
   int32_t fsai_rounds;     /* extra rounds of the aFSAI outer loop                  */
   double  lambda1, omega_q, omega_s;
-  int64_t sell_slots_A, sell_slots_G, sell_slots_GT; /* padded SELL-64 block slots   */
+  int64_t sell_slots_A, sell_slots_G, sell_slots_GT; /* stored block slots (padding incl.) */
+  /* device layout of the stored operators A, G, G^T, P, R (index = `which` of
+   * aspamg_apply_operator), FP64 and FP32 copies: L > 0 for the sliced layout
+   * with L lanes per row, -K for the row-packed layout with K slot groups per
+   * wavefront */
+  int32_t sell_lanes64[5], sell_lanes32[5];
 } aspamg_level_info_t;
 
 /* Fill *out with the defaults.  out: caller-owned. */

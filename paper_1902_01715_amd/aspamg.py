@@ -60,10 +60,15 @@ class LevelInfo(C.Structure):
         ("nnzb_P", C.c_int64), ("has_smoother", C.c_int32), ("fsai_rounds", C.c_int32),
         ("lambda1", C.c_double), ("omega_q", C.c_double), ("omega_s", C.c_double),
         ("sell_slots_A", C.c_int64), ("sell_slots_G", C.c_int64), ("sell_slots_GT", C.c_int64),
+        ("sell_lanes64", C.c_int32 * 5), ("sell_lanes32", C.c_int32 * 5),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if isinstance(v, C.Array) else v
+        return out
 
 
 class AspamgError(RuntimeError):

@@ -64,13 +64,91 @@ static std::vector<int32_t> sliced_ptr(const HostBSR &M, int L) {
   return sptr;
 }
 
+// Row-packed layout with K slot groups per wavefront: rows in matrix order,
+// max(1, ceil(len/K)) lanes each, a new wavefront whenever a row does not fit.
+// Returns the first row of every wavefront (plus n at the end), or an empty
+// vector when a row needs more than 64 lanes.
+static std::vector<int32_t> packed_waves(const HostBSR &M, int K) {
+  std::vector<int32_t> w0;
+  int used = 64;
+  for (int32_t r = 0; r < M.n; r++) {
+    const int64_t len = M.rp[r + 1] - M.rp[r];
+    const int64_t lr = std::max<int64_t>(1, (len + K - 1) / K);
+    if (lr > 64) return {};
+    if (used + lr > 64) {
+      w0.push_back(r);
+      used = 0;
+    }
+    used += (int)lr;
+  }
+  w0.push_back(M.n);
+  return w0;
+}
+
 template <typename T>
-Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes) {
+static void upload_arrays(aspamg_ctx *h, Sell<T> &S, const std::vector<int32_t> &sptr, const std::vector<int32_t> &col,
+                          const std::vector<T> &val, const std::vector<uint16_t> &meta) {
+  S.sptr = dalloc<int32_t>(h, sptr.size());
+  S.col = dalloc<int32_t>(h, col.size());
+  S.val = dalloc<T>(h, val.size());
+  HIPCHK(hipMemcpyAsync(S.sptr, sptr.data(), sptr.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(S.col, col.data(), col.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(S.val, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+  if (!meta.empty()) {
+    S.meta = dalloc<uint16_t>(h, meta.size());
+    HIPCHK(hipMemcpyAsync(S.meta, meta.data(), meta.size() * 2, hipMemcpyHostToDevice, h->stream));
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+}
+
+template <typename T>
+static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::vector<int32_t> &w0) {
   Sell<T> S;
   S.n = M.n;
   S.nc = M.nc;
   S.nnzb = M.nnzb();
-  // lanes per row: enough threads in flight, then little padding
+  S.lanes = 0;
+  S.pack = K;
+  S.nslices = (int32_t)w0.size() - 1;
+  S.ngroups = (int64_t)S.nslices * K;
+  std::vector<int32_t> col((size_t)S.ngroups * 64, 0);
+  std::vector<T> val((size_t)S.ngroups * 576, (T)0);
+  std::vector<uint16_t> meta((size_t)S.nslices * 64, 0x00FF);
+  for (int32_t s = 0; s < S.nslices; s++) {
+    int e = 0;
+    for (int32_t r = w0[s]; r < w0[s + 1]; r++) {
+      const int64_t len = M.rp[r + 1] - M.rp[r];
+      const int lr = (int)std::max<int64_t>(1, (len + K - 1) / K);
+      const int32_t padc = std::min<int32_t>(r, M.nc - 1);
+      for (int j = 0; j < lr; j++, e++) {
+        meta[(size_t)s * 64 + e] = (uint16_t)(((j == 0 ? lr : 0) << 8) | (r - w0[s]));
+        for (int k = 0; k < K; k++) {
+          const int64_t b = (int64_t)j * K + k;
+          const size_t g = (size_t)s * K + k;
+          if (b < len) {
+            const int64_t src = M.rp[r] + b;
+            col[g * 64 + e] = M.ci[src];
+            for (int q = 0; q < 9; q++) val[(g * 9 + q) * 64 + e] = (T)M.v[(size_t)src * 9 + q];
+          } else {
+            col[g * 64 + e] = padc;
+          }
+        }
+      }
+    }
+  }
+  upload_arrays(h, S, w0, col, val, meta);
+  return S;
+}
+
+// Sliced copy of M with L = force_lanes lanes per row, or the smallest L that
+// keeps kMinThreads lanes busy and then the L (up to 64) with the fewest padded
+// slots, a larger L having to save at least 5%.
+template <typename T>
+static Sell<T> upload_sliced(aspamg_ctx *h, const HostBSR &M, int force_lanes) {
+  Sell<T> S;
+  S.n = M.n;
+  S.nc = M.nc;
+  S.nnzb = M.nnzb();
   int L = 1;
   std::vector<int32_t> sptr;
   if (force_lanes) {
@@ -118,17 +196,112 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes) {
       }
     }
   }
-  S.sptr = dalloc<int32_t>(h, sptr.size());
-  S.col = dalloc<int32_t>(h, col.size());
-  S.val = dalloc<T>(h, val.size());
-  HIPCHK(hipMemcpyAsync(S.sptr, sptr.data(), sptr.size() * 4, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(S.col, col.data(), col.size() * 4, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(S.val, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
+  upload_arrays(h, S, sptr, col, val, {});
   return S;
 }
-template Sell<double> upload_sell<double>(aspamg_ctx *, const HostBSR &, int);
-template Sell<float> upload_sell<float>(aspamg_ctx *, const HostBSR &, int);
+
+void dfree(aspamg_ctx *h, void *p) {
+  if (!p) return;
+  auto it = std::find(h->allocations.begin(), h->allocations.end(), p);
+  if (it != h->allocations.end()) h->allocations.erase(it);
+  (void)hipFree(p);
+}
+
+template <typename T>
+void free_sell(aspamg_ctx *h, Sell<T> &S) {
+  dfree(h, S.sptr);
+  dfree(h, S.col);
+  dfree(h, S.val);
+  dfree(h, S.meta);
+  S = Sell<T>();
+}
+
+// Median times of y = S x and y = Q x over 7 launches each, the two
+// alternating (after one warm-up launch each), on the handle's stream.
+template <typename T>
+static void time_products(aspamg_ctx *h, const Sell<T> &S, const Sell<T> &Q, const T *x, T *y, float &ts,
+                          float &tq) {
+  hipEvent_t e[4];
+  for (auto &ev : e) HIPCHK(hipEventCreate(&ev));
+  constexpr int kReps = 7;
+  float a[kReps], b[kReps];
+  launch_spmv<T, T, T>(S, x, y, nullptr, 1.0, nullptr, h->stream);
+  launch_spmv<T, T, T>(Q, x, y, nullptr, 1.0, nullptr, h->stream);
+  for (int i = 0; i < kReps; i++) {
+    HIPCHK(hipEventRecord(e[0], h->stream));
+    launch_spmv<T, T, T>(S, x, y, nullptr, 1.0, nullptr, h->stream);
+    HIPCHK(hipEventRecord(e[1], h->stream));
+    launch_spmv<T, T, T>(Q, x, y, nullptr, 1.0, nullptr, h->stream);
+    HIPCHK(hipEventRecord(e[2], h->stream));
+    HIPCHK(hipEventSynchronize(e[2]));
+    HIPCHK(hipEventElapsedTime(&a[i], e[0], e[1]));
+    HIPCHK(hipEventElapsedTime(&b[i], e[1], e[2]));
+  }
+  for (auto &ev : e) (void)hipEventDestroy(ev);
+  std::sort(a, a + kReps);
+  std::sort(b, b + kReps);
+  ts = a[kReps / 2];
+  tq = b[kReps / 2];
+}
+
+// Device copy of M used by the products of the solve phase.  With
+// force_lanes the sliced layout with that many lanes per row; otherwise the
+// sliced layout and the row-packed one with the fewest slots (if it stores at
+// most 1.5 times the sliced slots) are both built and timed on this device,
+// and the faster one is kept (the row-packed one must win by 5%).  Operators
+// under kTimedSlots slots, or all of them without `timed`, keep the
+// row-packed layout when it stores 10% fewer slots.
+template <typename T>
+Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed) {
+  Sell<T> S = upload_sliced<T>(h, M, force_lanes);
+  if (force_lanes || M.n == 0 || M.nc == 0) return S;
+  int bestK = 0;
+  int64_t best = 0;
+  std::vector<int32_t> bestw;
+  for (int K : {1, 2, 4, 8}) {
+    std::vector<int32_t> w0 = packed_waves(M, K);
+    if (w0.empty()) continue;
+    const int64_t sl = (int64_t)(w0.size() - 1) * 64 * K;
+    if (!bestK || sl < best) {
+      best = sl;
+      bestK = K;
+      bestw.swap(w0);
+    }
+  }
+  const double ratio = bestK ? (double)best / (double)S.slots() : 1e30;
+  // small operators sit at the launch-latency floor either way: no timing
+  if (!timed || std::max<int64_t>(best, S.slots()) < kTimedSlots) {
+    if (ratio >= 0.9) return S;
+    free_sell(h, S);
+    return upload_packed<T>(h, M, bestK, bestw);
+  }
+  if (ratio > 1.5) return S;
+  Sell<T> Q = upload_packed<T>(h, M, bestK, bestw);
+  T *x = nullptr, *y = nullptr;
+  HIPCHK(hipMalloc(&x, sizeof(T) * 3 * (size_t)M.nc));
+  HIPCHK(hipMalloc(&y, sizeof(T) * 3 * (size_t)M.n));
+  HIPCHK(hipMemsetAsync(x, 0, sizeof(T) * 3 * (size_t)M.nc, h->stream));
+  float ts = 0, tq = 0;
+  try {
+    time_products(h, S, Q, x, y, ts, tq);
+  } catch (...) {
+    (void)hipFree(x);
+    (void)hipFree(y);
+    throw;
+  }
+  (void)hipFree(x);
+  (void)hipFree(y);
+  if (tq < 0.95f * ts) {
+    free_sell(h, S);
+    return Q;
+  }
+  free_sell(h, Q);
+  return S;
+}
+template Sell<double> upload_sell<double>(aspamg_ctx *, const HostBSR &, int, bool);
+template Sell<float> upload_sell<float>(aspamg_ctx *, const HostBSR &, int, bool);
+template void free_sell<double>(aspamg_ctx *, Sell<double> &);
+template void free_sell<float>(aspamg_ctx *, Sell<float> &);
 
 DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M) {
   DevBSR d;
@@ -639,6 +812,12 @@ aspamg_status aspamg_level_info(aspamg_handle h, int32_t level, aspamg_level_inf
   o->sell_slots_A = L.A64.slots();
   o->sell_slots_G = L.G64.slots();
   o->sell_slots_GT = L.GT64.slots();
+  const Sell<double> *M64[5] = {&L.A64, &L.G64, &L.GT64, &L.P64, &L.R64};
+  const Sell<float> *M32[5] = {&L.A32, &L.G32, &L.GT32, &L.P32, &L.R32};
+  for (int k = 0; k < 5; k++) {
+    o->sell_lanes64[k] = M64[k]->pack ? -M64[k]->pack : M64[k]->lanes;
+    o->sell_lanes32[k] = M32[k]->pack ? -M32[k]->pack : M32[k]->lanes;
+  }
   return ASPAMG_OK;
 }
 

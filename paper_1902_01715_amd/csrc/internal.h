@@ -14,6 +14,7 @@ namespace aspamg {
 
 constexpr int kSell = 64;           // rows per SELL slice = one wavefront
 constexpr int64_t kMinThreads = 262144;  // lanes per row grow until n * L reaches this
+constexpr int64_t kTimedSlots = 1 << 20;  // layouts of larger operators are chosen by timing
 constexpr int kMaxFsaiNodes = 32;   // off-diagonal nodes an FSAI row may hold
 constexpr int kMaxPEntries = 8;     // interpolation entries per scalar row (n_max cap)
 
@@ -44,25 +45,35 @@ struct DevBSR {
   double *v = nullptr;
 };
 
-// Device layout of one stored 3x3-block operator: sliced ELL with L lanes
-// per block row (L a power of two, 1..64).  A slice is the 64/L consecutive
-// block rows one wavefront serves; lane j of row r in the slice takes the
-// row's blocks j, j+L, j+2L, ...  Slice s owns slot groups [sptr[s],
-// sptr[s+1]); within slot group g, entry e = r*L + j holds its column at
-// col[g*64 + e] and block entry k at val[(g*9 + k)*64 + e] (component-major,
-// so every load instruction of a wavefront covers 64 consecutive values).
-// Padded entries hold 0 and a valid column.  L = 1 is plain SELL-64; larger L
-// serve short, irregular or coarse operators (less padding per slice and more
-// threads in flight); the L partial sums of a row meet in a butterfly.
+// Device layout of one stored 3x3-block operator, one of two forms.  In both,
+// slot group g holds 64 entries: entry e has its column at col[g*64 + e] and
+// block entry k at val[(g*9 + k)*64 + e] (component-major, so every load
+// instruction of a wavefront covers 64 consecutive values); padded entries
+// hold 0 and a valid column.
+//
+// Sliced ELL (pack == 0) with L lanes per block row (L a power of two,
+// 1..64): slice s is the 64/L consecutive rows one wavefront serves and owns
+// slot groups [sptr[s], sptr[s+1]); lane j of row r takes the row's blocks j,
+// j+L, j+2L, ... as entry e = r*L + j, and the L partial sums of a row meet
+// in a butterfly.  L = 1 suits long uniform rows (the fine-level operator).
+//
+// Row-packed (pack == K > 0): wavefront s owns the K slot groups [s*K, s*K+K)
+// and the rows [sptr[s], sptr[s+1]); a row of len blocks takes
+// max(1, ceil(len/K)) consecutive lanes, lane j holding its blocks
+// j*K .. j*K+K-1, so padding is per row rather than per slice.
+// meta[s*64 + e] = (lanes of the row << 8 on its first lane, else 0) | row
+// offset inside the wavefront, or 0x00FF for an idle lane.
 template <typename T>
 struct Sell {
-  int32_t n = 0, nc = 0, nslices = 0;
-  int32_t lanes = 1;       // L
+  int32_t n = 0, nc = 0, nslices = 0;  // nslices = wavefronts of the launch
+  int32_t lanes = 1;       // L (sliced)
+  int32_t pack = 0;        // K (row-packed), 0 for the sliced layout
   int64_t ngroups = 0;     // slot groups (64 entries each)
   int64_t nnzb = 0;        // real blocks
   int32_t *sptr = nullptr;
   int32_t *col = nullptr;
   T *val = nullptr;
+  uint16_t *meta = nullptr;
   int64_t slots() const { return ngroups * 64; }
 };
 
@@ -158,7 +169,9 @@ T *dalloc(aspamg_ctx *h, size_t n) { return static_cast<T *>(dmalloc(h, n * size
 // ---- layout builders (host) ----
 HostBSR transpose(const HostBSR &M);
 template <typename T>
-Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes = 0);
+Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes = 0, bool timed = true);
+template <typename T>
+void free_sell(aspamg_ctx *h, Sell<T> &S);   // releases the device arrays of S
 DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M);
 
 // ---- solve-path kernel launchers (kernels_solve.hip) ----

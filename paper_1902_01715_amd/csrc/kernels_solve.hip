@@ -1,4 +1,5 @@
-// Solve-phase kernels for gfx950: SELL-64 3x3-block SpMV with fused epilogues,
+// Solve-phase kernels for gfx950: 3x3-block SpMV on the sliced and row-packed
+// layouts with fused epilogues,
 // the dense coarsest-level product, precision casts and the fused PCG vector
 // updates with deterministic two-pass reductions.
 //
@@ -89,6 +90,62 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
     yo[0] = (TO)(alpha * a0);
     yo[1] = (TO)(alpha * a1);
     yo[2] = (TO)(alpha * a2);
+  }
+}
+
+// The same product on the row-packed layout: every lane streams its K slot
+// groups (fully unrolled), parks its three partial sums in LDS, and the first
+// lane of each row adds the row's lanes in lane order and writes the row.
+template <typename T, typename TX, typename TO, bool HAS_W, int K>
+__global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t *__restrict__ wrow,
+                                                   const uint16_t *__restrict__ meta,
+                                                   const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                   const TX *__restrict__ x, TO *y, const TO *w, T alpha,
+                                                   const PcgCtrl *ctrl) {
+  __shared__ T part[3][256];
+  if (ctrl_done(ctrl)) return;          // the same for every thread of the grid
+  const int32_t t = xcd_block() * 256 + threadIdx.x;
+  const int32_t wv = t >> 6, e = t & 63;
+  const bool live = wv < nwaves;        // whole wavefronts
+  uint32_t m = 0x00FF;
+  T a0 = 0, a1 = 0, a2 = 0;
+  if (live) {
+    m = meta[(size_t)wv * 64 + e];
+    const int32_t *cp = col + (size_t)wv * K * 64 + e;
+    const T *vp = val + (size_t)wv * K * 576 + e;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int32_t c = ld_stream(cp + 64 * k);
+      const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
+      const T *v = vp + 576 * k;
+      a0 += ld_stream(v) * x0 + ld_stream(v + 64) * x1 + ld_stream(v + 128) * x2;
+      a1 += ld_stream(v + 192) * x0 + ld_stream(v + 256) * x1 + ld_stream(v + 320) * x2;
+      a2 += ld_stream(v + 384) * x0 + ld_stream(v + 448) * x1 + ld_stream(v + 512) * x2;
+    }
+  }
+  part[0][threadIdx.x] = a0;
+  part[1][threadIdx.x] = a1;
+  part[2][threadIdx.x] = a2;
+  __syncthreads();
+  const int cnt = (int)(m >> 8);
+  if (!live || cnt == 0) return;
+  T s0 = 0, s1 = 0, s2 = 0;
+  for (int j = 0; j < cnt; ++j) {       // lanes of one row never leave the wavefront
+    s0 += part[0][threadIdx.x + j];
+    s1 += part[1][threadIdx.x + j];
+    s2 += part[2][threadIdx.x + j];
+  }
+  const int32_t row = wrow[wv] + (int32_t)(m & 0xFF);
+  TO *yo = y + 3 * (size_t)row;
+  if (HAS_W) {
+    const TO *wo = w + 3 * (size_t)row;
+    yo[0] = (TO)(alpha * s0) + wo[0];
+    yo[1] = (TO)(alpha * s1) + wo[1];
+    yo[2] = (TO)(alpha * s2) + wo[2];
+  } else {
+    yo[0] = (TO)(alpha * s0);
+    yo[1] = (TO)(alpha * s1);
+    yo[2] = (TO)(alpha * s2);
   }
 }
 
@@ -319,10 +376,35 @@ static void launch_spmv_w(const Sell<T> &A, const TX *x, TO *y, const TO *w, dou
   }
 }
 
+template <typename T, typename TX, typename TO, bool HAS_W, int K>
+static void launch_k(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
+                     hipStream_t s) {
+  const int64_t threads = (int64_t)A.nslices * 64;
+  hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, HAS_W, K>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                     A.nslices, A.sptr, A.meta, A.col, A.val, x, y, w, (T)alpha, ctrl);
+}
+
+template <typename T, typename TX, typename TO, bool HAS_W>
+static void launch_pack_w(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
+                          hipStream_t s) {
+  switch (A.pack) {
+    case 1: launch_k<T, TX, TO, HAS_W, 1>(A, x, y, w, alpha, ctrl, s); break;
+    case 2: launch_k<T, TX, TO, HAS_W, 2>(A, x, y, w, alpha, ctrl, s); break;
+    case 4: launch_k<T, TX, TO, HAS_W, 4>(A, x, y, w, alpha, ctrl, s); break;
+    case 8: launch_k<T, TX, TO, HAS_W, 8>(A, x, y, w, alpha, ctrl, s); break;
+    default: fail(ASPAMG_EINVAL, "row-packed layout with an unsupported group count");
+  }
+}
+
 template <typename T, typename TX, typename TO>
 void launch_spmv(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
                  hipStream_t s) {
   if (A.n == 0) return;
+  if (A.pack) {
+    if (w) launch_pack_w<T, TX, TO, true>(A, x, y, w, alpha, ctrl, s);
+    else launch_pack_w<T, TX, TO, false>(A, x, y, w, alpha, ctrl, s);
+    return;
+  }
   if (w) launch_spmv_w<T, TX, TO, true>(A, x, y, w, alpha, ctrl, s);
   else launch_spmv_w<T, TX, TO, false>(A, x, y, w, alpha, ctrl, s);
 }
@@ -334,7 +416,8 @@ template void launch_spmv<float, float, float>(const Sell<float> &, const float 
 
 void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
                      hipStream_t s) {
-  // one lane per row (the fine-level operator is stored with L = 1)
+  // one lane per row (the fine-level operator is stored so)
+  if (A.pack || A.lanes != 1) fail(ASPAMG_EINVAL, "q = K p needs the sliced layout with one lane per row");
   hipLaunchKernelGGL(k_sell_spmv_dot, dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr, A.col, A.val, x, y, part,
                      ctrl);
 }

@@ -14,6 +14,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -331,6 +333,20 @@ double lanczos_gagt(aspamg_ctx *h, const Level &L, const Sell<double> &G, const 
   return hi;
 }
 
+// Wall time of the setup phases per level, printed to stderr when the
+// environment variable ASPAMG_TRACE is set.
+struct PhaseClock {
+  bool on = std::getenv("ASPAMG_TRACE") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void tick(int level, const char *phase) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[aspamg] level %d %-12s %8.1f ms\n", level, phase,
+                 std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
+
 void build_fsai(aspamg_ctx *h, Level &L) {
   const aspamg_params &p = h->p;
   const Q q{p.quant_bits};
@@ -343,7 +359,9 @@ void build_fsai(aspamg_ctx *h, Level &L) {
   F.psi.assign((size_t)n * 3, 0.0);
   std::vector<int32_t> active(n);
   std::iota(active.begin(), active.end(), 0);
+  PhaseClock clk;
   fsai_factor(h, L, F, active);
+  clk.tick(-1, "fsai factor");
   std::vector<double> psi_prev(n);
   for (int32_t i = 0; i < n; i++) psi_prev[i] = psi_sum(F, i);
   const int nthreads = omp_get_max_threads();
@@ -359,7 +377,9 @@ void build_fsai(aspamg_ctx *h, Level &L) {
     std::vector<int32_t> next;
     for (size_t a = 0; a < active.size(); a++)
       if (grew[a]) next.push_back(active[a]);
+    clk.tick(-1, "fsai grow");
     fsai_factor(h, L, F, next);
+    clk.tick(-1, "fsai factor");
     std::vector<int32_t> keep;
     for (int32_t I : next) {
       const double pn = psi_sum(F, I);
@@ -370,11 +390,16 @@ void build_fsai(aspamg_ctx *h, Level &L) {
     active.swap(keep);
   }
   L.G = fsai_assemble(F);
+  clk.tick(-1, "fsai assemble");
   L.fsai_rounds = 0;
   for (;;) {
-    Sell<double> G = upload_sell<double>(h, L.G);
-    Sell<double> GT = upload_sell<double>(h, transpose(L.G));
+    Sell<double> G = upload_sell<double>(h, L.G, 0, false);
+    Sell<double> GT = upload_sell<double>(h, transpose(L.G), 0, false);
+    clk.tick(-1, "fsai G upload");
     L.lambda1 = lanczos_gagt(h, L, G, GT, p.lanczos_steps);
+    free_sell(h, G);
+    free_sell(h, GT);
+    clk.tick(-1, "lanczos");
     L.omega_q = 2.0 / L.lambda1;
     if (!p.outer_fsai) break;
     if (!(q(L.omega_q) < q(p.omega_bar))) break;
@@ -899,6 +924,7 @@ void build_coarse(aspamg_ctx *h, const HostBSR &A) {
 // hierarchy driver
 // ------------------------------------------------------------------------
 void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
+  PhaseClock clk;
   const aspamg_params &p = h->p;
   const Q q{p.quant_bits};
   const int ntv = h->ntv;
@@ -912,16 +938,19 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     L.dA = upload_bsr(h, L.A);
     L.A64 = upload_sell<double>(h, L.A, l == 0 ? 1 : 0);   // the PCG product runs one lane per fine row
     L.A32 = upload_sell<float>(h, L.A);
+    clk.tick(l, "upload A");
     if ((int64_t)N * 3 <= p.coarse_max_dof || l == p.max_levels - 1 || l == 31 || ntv == 0) {
       L.coarsest = true;
       break;
     }
     build_fsai(h, L);
+    clk.tick(l, "aFSAI");
     orthonormalize(L.V, (int64_t)N * 3, ntv);
     std::vector<char> excl(N);
     for (int32_t i = 0; i < N; i++) excl[i] = is_decoupled(L.A, i);
     StrongGraph S = strong_graph(L, ntv, p.theta, q, excl);
     mis(S, excl, L.cf);
+    clk.tick(l, "coarsening");
     L.cidx.assign(N, -1);
     int32_t nc = 0, nF = 0;
     for (int32_t i = 0; i < N; i++) {
@@ -935,7 +964,9 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
       break;
     }
     build_prolongation(h, L, S);
+    clk.tick(l, "DPLS");
     HostBSR Ac = galerkin(h, L);
+    clk.tick(l, "Galerkin");
     // device operators of this level
     L.G64 = upload_sell<double>(h, L.G);
     L.G32 = upload_sell<float>(h, L.G);
@@ -947,6 +978,7 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     HostBSR R = transpose(L.P);
     L.R64 = upload_sell<double>(h, R);
     L.R32 = upload_sell<float>(h, R);
+    clk.tick(l, "upload G P R");
     std::vector<double> Vc((size_t)nc * 3 * ntv);
     for (int32_t i = 0; i < N; i++)
       if (L.cidx[i] >= 0)
@@ -956,6 +988,7 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     h->lev[l + 1].V = std::move(Vc);
   }
   build_coarse(h, h->lev.back().A);
+  clk.tick((int)h->lev.size() - 1, "coarsest");
 }
 
 }  // namespace aspamg

@@ -5,9 +5,9 @@ The whole oracle hierarchy takes minutes on one core at this size, so the
 checks use what can be computed one by one or holds at any size:
   * FSAI rows of sampled block rows, recomputed by the oracle row by row
     (pattern and values bit for bit),
-  * every stored operator of every level applied by the GPU kernels (SELL-64,
-    length-sorted SELL-64 and vector block-CSR forms) against scipy on the
-    library's own exported matrices,
+  * every stored operator of every level applied by the GPU kernels (sliced
+    ELL with 1 to 64 lanes per row) against scipy on the library's own exported
+    matrices,
   * one V-cycle against the same sequence composed with scipy products,
   * the solve's recursive and true residuals."""
 import numpy as np
@@ -59,6 +59,8 @@ def test_all_operators_all_levels(c2, prec):
     import torch
     p, S = c2
     rng = np.random.default_rng(1)
+    li0 = S.level_info(0)
+    assert li0["sell_lanes64"][0] == 1       # q = K p runs one lane per row
     for l in range(S.nlev):
         li = S.level_info(l)
         ops = [0] if not li["has_smoother"] else [0, 1, 2, 3, 4]
