@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-it", type=int, default=1000)
+    ap.add_argument("--coarse-max-dof", type=int, default=1500,
+                    help="factor the coarsest level densely once it has at most this many DOF")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -210,7 +212,7 @@ def main():
     if args.config == "c5":
         print(json.dumps(bench_adjoint(args, p, desc)), flush=True)
         return
-    prm = aspamg.default_params(max_it=args.max_it)
+    prm = aspamg.default_params(max_it=args.max_it, coarse_max_dof=args.coarse_max_dof)
     t0 = time.perf_counter()
     S = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, prm)
     t_setup = time.perf_counter() - t0

@@ -403,20 +403,23 @@ static void pcg_iteration(aspamg_ctx *h, bool fp32) {
   const int64_t n = (int64_t)h->n * 3;
   const Level &L0 = h->lev[0];
   PcgCtrl *c = h->ctrl;
-  launch_spmv_dot(L0.A64, h->vp, h->vq, h->part, c, s);
-  launch_finish(kFinAlpha, h->part, spmv_blocks(h->n), c, s);
-  launch_pcg_update(n, h->vu, h->vr, h->vp, h->vq, h->vz, h->part, c, s);
-  launch_finish(kFinRr, h->part, vec_blocks(n), c, s);
+  // partial regions: [0] p.q, [1] r.r and [2] r.z_old (update), [3] r.z
+  double *pq_part = h->part, *rr_part = h->part + kMaxPart, *rz_part = h->part + 3 * kMaxPart;
+  launch_spmv_dot(L0.A64, h->vp, h->vq, pq_part, c, s);
   if (fp32) {
-    launch_cast<double, float>(n, h->vr, L0.v32.y, c, s);
+    launch_pcg_update<float>(n, h->vu, h->vr, h->vp, h->vq, h->vz, pq_part, spmv_blocks(h->n), rr_part, L0.v32.y, c,
+                             s);
+    launch_finish(kFinRr, rr_part, vec_blocks(n), c, s);
     cycle_level<float>(h, 0, L0.v32.y, L0.v32.z, c);
-    launch_pcg_rz<float>(n, h->vr, L0.v32.z, h->vz, h->part, c, s);
+    launch_pcg_rz<float>(n, h->vr, L0.v32.z, h->vz, rz_part, c, s);
   } else {
+    launch_pcg_update<double>(n, h->vu, h->vr, h->vp, h->vq, h->vz, pq_part, spmv_blocks(h->n), rr_part, nullptr, c,
+                              s);
+    launch_finish(kFinRr, rr_part, vec_blocks(n), c, s);
     cycle_level<double>(h, 0, h->vr, h->vz, c);
-    launch_pcg_rz<double>(n, h->vr, h->vz, h->vz, h->part, c, s);
+    launch_pcg_rz<double>(n, h->vr, h->vz, h->vz, rz_part, c, s);
   }
-  launch_finish(kFinBeta, h->part, vec_blocks(n), c, s);
-  launch_pcg_pupdate(n, h->vz, h->vp, c, s);
+  launch_pcg_pupdate(n, h->vz, h->vp, rz_part, vec_blocks(n), c, s);
 }
 
 static void alloc_level_vectors(aspamg_ctx *h) {
@@ -437,7 +440,7 @@ static void alloc_level_vectors(aspamg_ctx *h) {
   h->vp = dalloc<double>(h, n);
   h->vq = dalloc<double>(h, n);
   h->vz = dalloc<double>(h, n);
-  h->part = dalloc<double>(h, 2 * kMaxPart);
+  h->part = dalloc<double>(h, 4 * kMaxPart);
   h->ctrl = dalloc<PcgCtrl>(h, 1);
   HIPCHK(hipHostMalloc((void **)&h->ctrl_host, sizeof(PcgCtrl), hipHostMallocDefault));
 }

@@ -85,7 +85,8 @@ struct PcgCtrl {
   int32_t max_it;
   double rtol, fnorm;
   double alpha, beta, rz, rzo, pq, rr, relres;
-  double pad[3];
+  double rzk[2];      // r.z of iterate k in slot k & 1
+  double pad[1];
 };
 
 template <typename T>
@@ -134,7 +135,7 @@ struct aspamg_ctx {
   int32_t prec = 64;
   // PCG vectors (FP64) and control
   double *vu = nullptr, *vr = nullptr, *vp = nullptr, *vq = nullptr, *vz = nullptr;
-  double *part = nullptr;                     // reduction partials (4 x kMaxPart)
+  double *part = nullptr;                     // reduction partials (4 x kMaxPart): K p, r.r, r.z_old, r.z
   aspamg::PcgCtrl *ctrl = nullptr;
   aspamg::PcgCtrl *ctrl_host = nullptr;       // pinned
   hipGraphExec_t graph[2] = {nullptr, nullptr};   // [0] fp64 cycle, [1] fp32 cycle
@@ -187,12 +188,14 @@ void launch_cast(int64_t n, const TI *x, TO *y, const PcgCtrl *ctrl, hipStream_t
 void launch_fill(int64_t n, double *x, double v, hipStream_t s);
 void launch_copy(int64_t n, const double *x, double *y, hipStream_t s);
 void launch_dot(int64_t n, const double *a, const double *b, double *part, const PcgCtrl *ctrl, hipStream_t s);
+template <typename TC>
 void launch_pcg_update(int64_t n, double *u, double *r, const double *p, const double *q, const double *z,
-                       double *part, const PcgCtrl *ctrl, hipStream_t s);
+                       const double *pq_part, int npq, double *part, TC *rc, PcgCtrl *ctrl, hipStream_t s);
 template <typename TZ>
 void launch_pcg_rz(int64_t n, const double *r, const TZ *zc, double *z, double *part, const PcgCtrl *ctrl,
                    hipStream_t s);
-void launch_pcg_pupdate(int64_t n, const double *z, double *p, const PcgCtrl *ctrl, hipStream_t s);
+void launch_pcg_pupdate(int64_t n, const double *z, double *p, const double *rz_part, int nrz, PcgCtrl *ctrl,
+                        hipStream_t s);
 // finish modes
 enum FinishMode { kFinInitF = 0, kFinInitRz = 1, kFinAlpha = 2, kFinRr = 3, kFinBeta = 4, kFinNorm = 5 };
 void launch_finish(int mode, const double *part, int nparts, PcgCtrl *ctrl, hipStream_t s);

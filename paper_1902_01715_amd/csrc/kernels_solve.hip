@@ -230,18 +230,52 @@ __global__ void __launch_bounds__(256) k_dot(int64_t n, const double *__restrict
 }
 
 // u += alpha p, r -= alpha q; partials of r.r and r.z (z = previous preconditioned residual).
+// Fixed-order sum of np partials, the same in every block and returned to
+// every thread of the block.
+__device__ __forceinline__ double sum_parts_all(const double *part, int np, double *sm, double *bc) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) *bc = s;
+  __syncthreads();
+  return *bc;
+}
+
+// One PCG step on the iterate: alpha = rz_k / p.q (every block reduces the
+// product's partials itself, in the same order), u += alpha p, r -= alpha q,
+// and the partials of r.r and r.z_old (Polak-Ribiere); with rc, r is also
+// written in the cycle precision.  A non-positive p.q ends the solve.
+template <typename TC>
 __global__ void __launch_bounds__(256) k_pcg_update(int64_t n, double *__restrict__ u, double *__restrict__ r,
                                                     const double *__restrict__ p, const double *__restrict__ q,
-                                                    const double *__restrict__ z, double *__restrict__ part,
-                                                    const PcgCtrl *ctrl) {
-  __shared__ double sm[4];
+                                                    const double *__restrict__ z, const double *__restrict__ pq_part,
+                                                    int npq, double *__restrict__ part, TC *__restrict__ rc,
+                                                    PcgCtrl *ctrl) {
+  __shared__ double sm[4], bc;
   if (ctrl_done(ctrl)) return;
-  const double alpha = ctrl->alpha;
+  const int32_t it = ctrl->iter;
+  const double rz = ctrl->rzk[it & 1];
+  const double pq = sum_parts_all(pq_part, npq, sm, &bc);
+  if (!(pq > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctrl->pq = pq;
+      ctrl->status = (pq == pq) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN;
+      ctrl->iter = it + 1;
+      ctrl->done = 1;
+    }
+    return;
+  }
+  const double alpha = rz / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->pq = pq;
+    ctrl->alpha = alpha;
+  }
   double s1 = 0.0, s2 = 0.0;
   for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     u[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
+    if (rc) rc[i] = (TC)ri;
     s1 += ri * ri;
     s2 += ri * z[i];
   }
@@ -270,10 +304,30 @@ __global__ void __launch_bounds__(256) k_pcg_rz(int64_t n, const double *__restr
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// p = z + beta p with beta = (r.z - r.z_old) / rz_k (Polak-Ribiere); every
+// block reduces the r.z partials itself, and block 0 keeps r.z as rz_{k+1}
+// in the slot of the next iteration (the other slot is the one read here).
+// A non-positive r.z ends the solve.
 __global__ void __launch_bounds__(256) k_pcg_pupdate(int64_t n, const double *__restrict__ z, double *__restrict__ p,
-                                                     const PcgCtrl *ctrl) {
+                                                     const double *__restrict__ rz_part, int nrz, PcgCtrl *ctrl) {
+  __shared__ double sm[4], bc;
   if (ctrl_done(ctrl)) return;
-  const double beta = ctrl->beta;
+  const int32_t it = ctrl->iter;        // already k + 1
+  const double rz_old = ctrl->rzk[(it - 1) & 1], rzo = ctrl->rzo;
+  const double rz = sum_parts_all(rz_part, nrz, sm, &bc);
+  if (!(rz > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctrl->status = (rz == rz) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN;
+      ctrl->done = 1;
+    }
+    return;
+  }
+  const double beta = (rz - rzo) / rz_old;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->rzk[it & 1] = rz;
+    ctrl->rz = rz;
+    ctrl->beta = beta;
+  }
   for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = z[i] + beta * p[i];
 }
 
@@ -302,18 +356,8 @@ __global__ void __launch_bounds__(256) k_finish(int mode, const double *__restri
     }
     case kFinInitRz: {
       ctrl->rz = s0;
+      ctrl->rzk[0] = s0;
       if (!(s0 > 0.0)) { ctrl->status = (s0 == s0) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN; ctrl->done = 1; }
-      break;
-    }
-    case kFinAlpha: {
-      ctrl->pq = s0;
-      if (!(s0 > 0.0)) {
-        ctrl->status = (s0 == s0) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN;
-        ctrl->done = 1;
-        ctrl->iter += 1;
-      } else {
-        ctrl->alpha = ctrl->rz / s0;
-      }
       break;
     }
     case kFinRr: {
@@ -325,16 +369,6 @@ __global__ void __launch_bounds__(256) k_finish(int mode, const double *__restri
       if (!(s0 == s0) || s0 == __builtin_inf()) { ctrl->status = ASPAMG_ENAN; ctrl->done = 1; }
       else if (nr <= ctrl->rtol * ctrl->fnorm) { ctrl->status = ASPAMG_OK; ctrl->done = 1; }
       else if (ctrl->iter >= ctrl->max_it) { ctrl->status = ASPAMG_NOT_CONVERGED; ctrl->done = 1; }
-      break;
-    }
-    case kFinBeta: {
-      if (!(s0 > 0.0)) {
-        ctrl->status = (s0 == s0) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN;
-        ctrl->done = 1;
-      } else {
-        ctrl->beta = (s0 - ctrl->rzo) / ctrl->rz;
-        ctrl->rz = s0;
-      }
       break;
     }
     case kFinNorm: {
@@ -445,10 +479,16 @@ void launch_copy(int64_t n, const double *x, double *y, hipStream_t s) {
 void launch_dot(int64_t n, const double *a, const double *b, double *part, const PcgCtrl *ctrl, hipStream_t s) {
   hipLaunchKernelGGL(k_dot, dim3(vec_blocks(n)), dim3(256), 0, s, n, a, b, part, ctrl);
 }
+template <typename TC>
 void launch_pcg_update(int64_t n, double *u, double *r, const double *p, const double *q, const double *z,
-                       double *part, const PcgCtrl *ctrl, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_update, dim3(vec_blocks(n)), dim3(256), 0, s, n, u, r, p, q, z, part, ctrl);
+                       const double *pq_part, int npq, double *part, TC *rc, PcgCtrl *ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_update<TC>, dim3(vec_blocks(n)), dim3(256), 0, s, n, u, r, p, q, z, pq_part, npq, part, rc,
+                     ctrl);
 }
+template void launch_pcg_update<float>(int64_t, double *, double *, const double *, const double *, const double *,
+                                       const double *, int, double *, float *, PcgCtrl *, hipStream_t);
+template void launch_pcg_update<double>(int64_t, double *, double *, const double *, const double *, const double *,
+                                        const double *, int, double *, double *, PcgCtrl *, hipStream_t);
 template <typename TZ>
 void launch_pcg_rz(int64_t n, const double *r, const TZ *zc, double *z, double *part, const PcgCtrl *ctrl,
                    hipStream_t s) {
@@ -458,8 +498,9 @@ template void launch_pcg_rz<double>(int64_t, const double *, const double *, dou
                                     hipStream_t);
 template void launch_pcg_rz<float>(int64_t, const double *, const float *, double *, double *, const PcgCtrl *,
                                    hipStream_t);
-void launch_pcg_pupdate(int64_t n, const double *z, double *p, const PcgCtrl *ctrl, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_pupdate, dim3(vec_blocks(n)), dim3(256), 0, s, n, z, p, ctrl);
+void launch_pcg_pupdate(int64_t n, const double *z, double *p, const double *rz_part, int nrz, PcgCtrl *ctrl,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_pupdate, dim3(vec_blocks(n)), dim3(256), 0, s, n, z, p, rz_part, nrz, ctrl);
 }
 void launch_finish(int mode, const double *part, int nparts, PcgCtrl *ctrl, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, mode, part, nparts, ctrl);
