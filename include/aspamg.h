@@ -76,6 +76,14 @@ typedef struct {
   int32_t dense_max_dof;  /* 16384 refuse a larger dense coarsest system                */
   int32_t check_every;    /* 4     PCG iterations per host convergence poll             */
   int32_t use_graph;      /* 1     replay the PCG iteration as a captured HIP graph     */
+  int32_t layout;         /* 0     device layout of the stored operators: 0 time both
+                           *       layouts on the device for the larger operators; 1 pick
+                           *       by stored slots only (the same choice on every run); 2
+                           *       sliced ELL only; 3 row-packed only.  The fine-level FP64
+                           *       operator of q = K p is sliced with one lane per row in
+                           *       every case.  Results do not depend on the layout beyond
+                           *       the order of floating-point sums within a row. */
+  int32_t reserved;       /* 0                                                          */
 } aspamg_params;
 
 typedef struct {

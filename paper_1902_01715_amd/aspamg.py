@@ -37,7 +37,7 @@ class Params(C.Structure):
         ("coarse_max_dof", C.c_int32), ("max_levels", C.c_int32), ("stall_ratio", C.c_double),
         ("nu1", C.c_int32), ("nu2", C.c_int32), ("cycle_precision", C.c_int32), ("rtol", C.c_double),
         ("max_it", C.c_int32), ("quant_bits", C.c_int32), ("dense_max_dof", C.c_int32),
-        ("check_every", C.c_int32), ("use_graph", C.c_int32),
+        ("check_every", C.c_int32), ("use_graph", C.c_int32), ("layout", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

@@ -10,6 +10,11 @@
 
 #include "internal.h"
 
+// sizes mirrored by the Python binding
+static_assert(sizeof(aspamg_params) == 160, "aspamg_params layout changed");
+static_assert(sizeof(aspamg_stats) == 96, "aspamg_stats layout changed");
+static_assert(sizeof(aspamg_level_info_t) == 128, "aspamg_level_info_t layout changed");
+
 namespace aspamg {
 
 static thread_local std::string g_last_error;
@@ -253,8 +258,10 @@ static void time_products(aspamg_ctx *h, const Sell<T> &S, const Sell<T> &Q, con
 // row-packed layout when it stores 10% fewer slots.
 template <typename T>
 Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed) {
+  const int policy = h->p.layout;
   Sell<T> S = upload_sliced<T>(h, M, force_lanes);
-  if (force_lanes || M.n == 0 || M.nc == 0) return S;
+  if (force_lanes || M.n == 0 || M.nc == 0 || policy == 2) return S;
+  if (policy != 0) timed = false;
   int bestK = 0;
   int64_t best = 0;
   std::vector<int32_t> bestw;
@@ -268,7 +275,12 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
       bestw.swap(w0);
     }
   }
-  const double ratio = bestK ? (double)best / (double)S.slots() : 1e30;
+  if (!bestK) return S;                 // a row needs more than 64 lanes
+  if (policy == 3) {
+    free_sell(h, S);
+    return upload_packed<T>(h, M, bestK, bestw);
+  }
+  const double ratio = (double)best / (double)S.slots();
   // small operators sit at the launch-latency floor either way: no timing
   if (!timed || std::max<int64_t>(best, S.slots()) < kTimedSlots) {
     if (ratio >= 0.9) return S;
@@ -516,6 +528,7 @@ static void check_params(const aspamg_params &p) {
       p.lanczos_steps < 1 || p.lanczos_steps > 200 || p.nu1 < 1 || p.nu2 < 1 || p.max_levels < 1 ||
       (p.cycle_precision != 32 && p.cycle_precision != 64) || !(p.rtol >= 0) || p.max_it < 1 ||
       p.quant_bits < 8 || p.quant_bits > 52 || p.check_every < 1 || p.n_tv < 0 || p.n_tv > 64 ||
+      p.layout < 0 || p.layout > 3 ||
       !(p.kappa_p > 0) || !(p.omega_safety > 0))
     fail(ASPAMG_EINVAL, "invalid parameter value");
 }
@@ -574,6 +587,8 @@ aspamg_status aspamg_default_params(aspamg_params *o) {
   o->dense_max_dof = 16384;
   o->check_every = 4;
   o->use_graph = 1;
+  o->layout = 0;
+  o->reserved = 0;
   return ASPAMG_OK;
 }
 

@@ -27,8 +27,11 @@ def test_default_params_and_struct_layout():
     p = aspamg.default_params()
     assert (p.k_g, p.theta, p.n_max, p.kappa_p, p.eps_g) == (4, 5, 5, 50.0, 1e-3)
     assert p.rtol == 1e-10 and p.max_it == 1000 and p.cycle_precision == 64
-    # the ctypes mirror has the C struct size (fields checked by value above)
-    assert ctypes.sizeof(aspamg.Params) == 152
+    assert p.layout == 0 and p.use_graph == 1
+    # the ctypes mirrors have the C struct sizes (asserted at compile time in the library)
+    assert ctypes.sizeof(aspamg.Params) == 160
+    assert ctypes.sizeof(aspamg.Stats) == 96
+    assert ctypes.sizeof(aspamg.LevelInfo) == 128
 
 
 def test_last_error_is_a_string():
