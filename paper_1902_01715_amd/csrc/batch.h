@@ -21,6 +21,7 @@ struct BatchCtrl {
 template <typename T>
 struct DevBSRT {
   int32_t n = 0, nc = 0;
+  int32_t split = 1;       // lane groups per block row in the SpMM (1, 2, 4, 8)
   int64_t nnzb = 0;
   int32_t *rp = nullptr;
   int32_t *ci = nullptr;
@@ -49,7 +50,7 @@ struct BatchWork {
 };
 
 int batch_vec_blocks(int64_t nrow, int ld);
-int spmm_dot_parts(int32_t n, int ld, int kb);
+int spmm_dot_parts(const DevBSRT<double> &A, int ld, int kb);
 template <typename T>
 void launch_spmm(const DevBSRT<T> &A, const T *X, T *Y, const T *W, int ld, int kb, double alpha, const BatchCtrl *c,
                  hipStream_t s);

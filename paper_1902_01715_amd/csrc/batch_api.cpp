@@ -26,6 +26,10 @@ static DevBSRT<T> upload_plain(BatchWork *w, const HostBSR &M, hipStream_t s) {
   d.n = M.n;
   d.nc = M.nc;
   d.nnzb = M.nnzb();
+  // lane groups per row: long coarse-level rows are split (short rows run
+  // faster unsplit, with more rows sharing each staged chunk)
+  const double avg = M.n ? (double)d.nnzb / M.n : 0.0;
+  d.split = avg < 40.0 ? 1 : (avg < 80.0 ? 4 : 8);
   std::vector<int32_t> rp(M.rp.begin(), M.rp.end());
   std::vector<T> v(std::max<size_t>(M.v.size(), 1));
   for (size_t i = 0; i < M.v.size(); i++) v[i] = (T)M.v[i];
@@ -163,7 +167,7 @@ static void pcg_iteration_batch(aspamg_ctx *h, BatchWork *w, bool fp32) {
   BatchCtrl *c = w->ctrl;
   const BatchLevel &B0 = w->lev[0];
   launch_spmm_dot(B0.d.A, w->P, w->Q, ld, kb, w->part, c, s);
-  launch_col_finish(kFinAlpha, w->part, spmm_dot_parts(B0.d.A.n, ld, kb), ld, c, s);
+  launch_col_finish(kFinAlpha, w->part, spmm_dot_parts(B0.d.A, ld, kb), ld, c, s);
   launch_col_update(nrow, w->U, w->R, w->P, w->Q, w->Z, ld, w->part, c, s);
   launch_col_finish(kFinRr, w->part, batch_vec_blocks(nrow, ld), ld, c, s);
   if (fp32) {

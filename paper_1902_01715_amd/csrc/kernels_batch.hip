@@ -3,6 +3,8 @@
 // reductions.  Vectors are stored [dof][ld] (right-hand sides fastest), so the
 // KB lanes that share one block row read KB consecutive entries of every
 // gathered x row, and every matrix block is fetched once for the whole tile.
+#include <algorithm>
+
 #include "batch.h"
 
 namespace aspamg {
@@ -11,78 +13,103 @@ namespace {
 
 __device__ __forceinline__ bool bdone(const BatchCtrl *c) { return c != nullptr && c->all_done != 0; }
 
-// Y[:, j] = alpha * (A X)[:, j] (+ W[:, j]) for the KB columns of tile blockIdx.y.
-template <typename T, bool HAS_W, int KB>
+// Y[:, tile] = alpha * (A X)[:, tile] (+ W[:, tile]) for the KB columns of
+// tile blockIdx.y, and with DOT the per-column partials of X.Y.  A block row
+// is served by S lane groups of KB lanes (one lane per column of the tile);
+// group s takes the row's blocks s, s+S, s+2S, ..., and the S partial sums
+// meet in LDS in group order.  A row group is 256/(KB*S) consecutive rows.
+// The group's matrix
+// blocks (a contiguous range of the block CSR) are staged in LDS, 256 blocks
+// at a time, by coalesced loads; the lanes then read each block as an LDS
+// broadcast, so the global loads per block are the three x gathers of the
+// tile.
+template <typename T, bool HAS_W, bool DOT, int KB, int S>
 __global__ void __launch_bounds__(256) k_bsr_spmm(int32_t n, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ col, const T *__restrict__ val,
                                                   const T *__restrict__ X, T *Y, const T *W, int32_t ld, T alpha,
-                                                  const BatchCtrl *ctrl) {
-  if (bdone(ctrl)) return;
-  const int32_t t = blockIdx.x * 256 + threadIdx.x;
-  const int32_t row = t / KB;
-  const int32_t j = blockIdx.y * KB + (t & (KB - 1));
-  if (row >= n) return;
-  T a0 = 0, a1 = 0, a2 = 0;
-  const int32_t b1 = rp[row + 1];
-  for (int32_t b = rp[row]; b < b1; ++b) {
-    const int32_t c = col[b];
-    const T *v = val + (size_t)b * 9;
-    const T x0 = X[(size_t)(3 * c) * ld + j], x1 = X[(size_t)(3 * c + 1) * ld + j], x2 = X[(size_t)(3 * c + 2) * ld + j];
-    a0 += v[0] * x0 + v[1] * x1 + v[2] * x2;
-    a1 += v[3] * x0 + v[4] * x1 + v[5] * x2;
-    a2 += v[6] * x0 + v[7] * x1 + v[8] * x2;
-  }
-  const size_t o = (size_t)(3 * row) * ld + j;
-  if (HAS_W) {
-    Y[o] = alpha * a0 + W[o];
-    Y[o + ld] = alpha * a1 + W[o + ld];
-    Y[o + 2 * ld] = alpha * a2 + W[o + 2 * ld];
-  } else {
-    Y[o] = alpha * a0;
-    Y[o + ld] = alpha * a1;
-    Y[o + 2 * ld] = alpha * a2;
-  }
-}
-
-// Q = K P and per-column partials of P.Q (FP64).  A fixed grid of at most
-// kBatchParts blocks walks the rows with a stride, so the partial count (and
-// the order of the final sums) does not depend on the problem size.
-template <int KB>
-__global__ void __launch_bounds__(256) k_bsr_spmm_dot(int32_t n, const int32_t *__restrict__ rp,
-                                                      const int32_t *__restrict__ col,
-                                                      const double *__restrict__ val, const double *__restrict__ X,
-                                                      double *__restrict__ Y, int32_t ld, double *__restrict__ part,
-                                                      const BatchCtrl *ctrl) {
-  __shared__ double sm[256];
-  if (bdone(ctrl)) return;
-  const int lane = threadIdx.x & (KB - 1);
+                                                  double *__restrict__ part, const BatchCtrl *ctrl) {
+  constexpr int TPR = KB * S;
+  constexpr int RPG = 256 / TPR;
+  constexpr int CH = 256;
+  __shared__ T sv[CH * 9];
+  __shared__ int32_t sc[CH];
+  __shared__ T red[3][S > 1 ? 256 : 1];
+  __shared__ double sm[DOT ? 256 : 1];
+  if (bdone(ctrl)) return;              // the same for every thread of the grid
+  // XCD x (workgroups are dealt to the 8 XCDs round-robin) owns one contiguous
+  // range of row groups, and its workgroups take that range round-robin, so
+  // the groups in flight on one XCD are neighbours and share gathered x rows
+  // in its L2 and the MALL.
+  const int32_t ngroups = (n + RPG - 1) / RPG;
+  const int32_t nb = gridDim.x, xcd = blockIdx.x & 7, per = nb >> 3, rem = nb & 7;
+  const int32_t nwx = per + (xcd < rem ? 1 : 0), wi = blockIdx.x >> 3;
+  const int32_t gx0 = (int32_t)((int64_t)ngroups * xcd / 8), gx1 = (int32_t)((int64_t)ngroups * (xcd + 1) / 8);
+  const int32_t w = blockIdx.x;          // this workgroup's partial slot
+  const int lane = threadIdx.x % KB, sp = (threadIdx.x / KB) % S, lr = threadIdx.x / TPR;
   const int32_t j = blockIdx.y * KB + lane;
-  const int32_t rstride = gridDim.x * (256 / KB);
   double d = 0.0;
-  for (int32_t row = (blockIdx.x * 256 + threadIdx.x) / KB; row < n; row += rstride) {
-    double a0 = 0, a1 = 0, a2 = 0;
-    const int32_t b1 = rp[row + 1];
-    for (int32_t b = rp[row]; b < b1; ++b) {
-      const int32_t c = col[b];
-      const double *v = val + (size_t)b * 9;
-      const double x0 = X[(size_t)(3 * c) * ld + j], x1 = X[(size_t)(3 * c + 1) * ld + j],
-                   x2 = X[(size_t)(3 * c + 2) * ld + j];
-      a0 += v[0] * x0 + v[1] * x1 + v[2] * x2;
-      a1 += v[3] * x0 + v[4] * x1 + v[5] * x2;
-      a2 += v[6] * x0 + v[7] * x1 + v[8] * x2;
+  for (int32_t g = gx0 + wi; g < gx1; g += nwx) {
+    const int32_t r0 = g * RPG, row = r0 + lr;
+    const int32_t b0 = rp[r0], b1 = rp[min(r0 + RPG, n)];
+    const int32_t mb0 = row < n ? rp[row] : 0, mb1 = row < n ? rp[row + 1] : 0;
+    T a0 = 0, a1 = 0, a2 = 0;
+    for (int32_t cb = b0; cb < b1; cb += CH) {
+      const int32_t cn = min(CH, b1 - cb);
+      for (int i = threadIdx.x; i < cn * 9; i += 256) sv[i] = val[(size_t)cb * 9 + i];
+      if (threadIdx.x < cn) sc[threadIdx.x] = col[cb + threadIdx.x];
+      __syncthreads();
+      const int32_t lo = max(mb0, cb), hi = min(mb1, cb + cn);
+      // first block of this lane group's residue class at or after lo
+      const int32_t first = lo + (((sp - (lo - mb0)) % S) + S) % S;
+      for (int32_t b = first; b < hi; b += S) {
+        const int k = b - cb;
+        const int32_t c = sc[k];
+        const T *v = sv + k * 9;
+        const T x0 = X[(size_t)(3 * c) * ld + j], x1 = X[(size_t)(3 * c + 1) * ld + j],
+                x2 = X[(size_t)(3 * c + 2) * ld + j];
+        a0 += v[0] * x0 + v[1] * x1 + v[2] * x2;
+        a1 += v[3] * x0 + v[4] * x1 + v[5] * x2;
+        a2 += v[6] * x0 + v[7] * x1 + v[8] * x2;
+      }
+      __syncthreads();
     }
-    const size_t o = (size_t)(3 * row) * ld + j;
-    Y[o] = a0;
-    Y[o + ld] = a1;
-    Y[o + 2 * ld] = a2;
-    d += (X[o] * a0 + X[o + ld] * a1) + X[o + 2 * ld] * a2;
+    if (S > 1) {
+      red[0][threadIdx.x] = a0;
+      red[1][threadIdx.x] = a1;
+      red[2][threadIdx.x] = a2;
+      __syncthreads();
+      if (sp == 0) {
+        a0 = a1 = a2 = 0;
+        for (int q = 0; q < S; q++) {
+          a0 += red[0][threadIdx.x + q * KB];
+          a1 += red[1][threadIdx.x + q * KB];
+          a2 += red[2][threadIdx.x + q * KB];
+        }
+      }
+      __syncthreads();
+    }
+    if (row < n && sp == 0) {
+      const size_t o = (size_t)(3 * row) * ld + j;
+      if (HAS_W) {
+        Y[o] = alpha * a0 + W[o];
+        Y[o + ld] = alpha * a1 + W[o + ld];
+        Y[o + 2 * ld] = alpha * a2 + W[o + 2 * ld];
+      } else {
+        Y[o] = alpha * a0;
+        Y[o + ld] = alpha * a1;
+        Y[o + 2 * ld] = alpha * a2;
+      }
+      if (DOT) d += ((double)X[o] * a0 + (double)X[o + ld] * a1) + (double)X[o + 2 * ld] * a2;
+    }
   }
-  sm[threadIdx.x] = d;
-  __syncthreads();
-  if (threadIdx.x < KB) {
-    double s = 0.0;
-    for (int r = 0; r < 256 / KB; r++) s += sm[r * KB + threadIdx.x];
-    part[(size_t)blockIdx.x * ld + blockIdx.y * KB + threadIdx.x] = s;
+  if (DOT) {
+    sm[threadIdx.x] = d;                // zero on the lanes of groups s > 0
+    __syncthreads();
+    if (threadIdx.x < KB) {
+      double s = 0.0;
+      for (int r = 0; r < RPG; r++) s += sm[r * TPR + threadIdx.x];
+      part[(size_t)w * ld + blockIdx.y * KB + threadIdx.x] = s;
+    }
   }
 }
 
@@ -175,17 +202,32 @@ __global__ void __launch_bounds__(256) k_col_pupdate(int64_t n, const double *__
 // Per-column scalar steps; thread j owns column j.  A finished column gets
 // alpha = 0 (its iterate is frozen) and keeps the iteration count at which it
 // stopped.  all_done is raised when every column is finished.
-__global__ void __launch_bounds__(64) k_col_finish(int mode, const double *__restrict__ part, int nparts, int32_t ld,
-                                                   BatchCtrl *ctrl) {
+__global__ void __launch_bounds__(1024) k_col_finish(int mode, const double *__restrict__ part, int nparts,
+                                                     int32_t ld, BatchCtrl *ctrl) {
   __shared__ int32_t open[64];
+  __shared__ double t0[1024], t1[1024];
   if (ctrl->all_done) return;
-  const int j = threadIdx.x;
-  open[j] = 0;
+  // 1024/ld threads per column each sum a strided share of the partials, then
+  // thread j adds the shares of column j in order (ld divides 1024)
+  const int t = threadIdx.x, nr = 1024 / ld;
+  {
+    const int jj = t % ld, q0 = t / ld;
+    double a = 0.0, b = 0.0;
+    for (int q = q0; q < nparts; q += nr) a += part[(size_t)q * ld + jj];
+    if (mode == kFinRr)
+      for (int q = q0; q < nparts; q += nr) b += part[((size_t)nparts + q) * ld + jj];
+    t0[t] = a;
+    t1[t] = b;
+  }
+  if (t < 64) open[t] = 0;
+  __syncthreads();
+  const int j = t;
   if (j < ld) {
     double s0 = 0.0, s1 = 0.0;
-    for (int b = 0; b < nparts; b++) s0 += part[(size_t)b * ld + j];
-    if (mode == kFinRr)
-      for (int b = 0; b < nparts; b++) s1 += part[((size_t)nparts + b) * ld + j];
+    for (int q = 0; q < nr; q++) {
+      s0 += t0[q * ld + j];
+      s1 += t1[q * ld + j];
+    }
     const bool dn = ctrl->done[j] != 0;
     switch (mode) {
       case kFinInitF:
@@ -259,13 +301,43 @@ int batch_vec_blocks(int64_t nrow, int ld) {
   return (int)b;
 }
 
-template <typename T, bool HAS_W, int KB>
-static void spmm_kb(const DevBSRT<T> &A, const T *X, T *Y, const T *W, int ld, double alpha, const BatchCtrl *c,
-                    hipStream_t s) {
-  const int64_t threads = (int64_t)A.n * KB;
-  dim3 grid((unsigned)((threads + 255) / 256), ld / KB);
-  hipLaunchKernelGGL((k_bsr_spmm<T, HAS_W, KB>), grid, dim3(256), 0, s, A.n, A.rp, A.ci, A.v, X, Y, W, ld, (T)alpha,
-                     c);
+// workgroups of a product over n rows in row groups of 256/(kb*split): at most cap
+static int spmm_wgs(int32_t n, int kb, int split, int cap) {
+  const int rpg = 256 / (kb * split);
+  const int64_t groups = ((int64_t)n + rpg - 1) / rpg;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(groups, cap));
+}
+
+template <typename T, bool HAS_W, bool DOT, int KB, int S>
+static void spmm_ks(const DevBSRT<T> &A, const T *X, T *Y, const T *W, int ld, double alpha, double *part,
+                    const BatchCtrl *c, hipStream_t s) {
+  dim3 grid((unsigned)spmm_wgs(A.n, KB, S, DOT ? kBatchParts : 4096), ld / KB);
+  hipLaunchKernelGGL((k_bsr_spmm<T, HAS_W, DOT, KB, S>), grid, dim3(256), 0, s, A.n, A.rp, A.ci, A.v, X, Y, W, ld,
+                     (T)alpha, part, c);
+}
+
+template <typename T, bool HAS_W, bool DOT, int KB>
+static void spmm_k(const DevBSRT<T> &A, const T *X, T *Y, const T *W, int ld, double alpha, double *part,
+                   const BatchCtrl *c, hipStream_t s) {
+  switch (A.split) {
+    case 1: spmm_ks<T, HAS_W, DOT, KB, 1>(A, X, Y, W, ld, alpha, part, c, s); break;
+    case 2: spmm_ks<T, HAS_W, DOT, KB, 2>(A, X, Y, W, ld, alpha, part, c, s); break;
+    case 4: spmm_ks<T, HAS_W, DOT, KB, 4>(A, X, Y, W, ld, alpha, part, c, s); break;
+    case 8: spmm_ks<T, HAS_W, DOT, KB, 8>(A, X, Y, W, ld, alpha, part, c, s); break;
+    default: fail(ASPAMG_EINVAL, "SpMM row split must be 1, 2, 4 or 8");
+  }
+}
+
+template <typename T, bool HAS_W, bool DOT>
+static void spmm_any(const DevBSRT<T> &A, const T *X, T *Y, const T *W, int ld, int kb, double alpha, double *part,
+                     const BatchCtrl *c, hipStream_t s) {
+  switch (kb) {
+    case 4: spmm_k<T, HAS_W, DOT, 4>(A, X, Y, W, ld, alpha, part, c, s); break;
+    case 8: spmm_k<T, HAS_W, DOT, 8>(A, X, Y, W, ld, alpha, part, c, s); break;
+    case 16: spmm_k<T, HAS_W, DOT, 16>(A, X, Y, W, ld, alpha, part, c, s); break;
+    case 32: spmm_k<T, HAS_W, DOT, 32>(A, X, Y, W, ld, alpha, part, c, s); break;
+    default: fail(ASPAMG_EINVAL, "SpMM tile must be 4, 8, 16 or 32 columns");
+  }
 }
 
 template <typename T>
@@ -273,19 +345,8 @@ void launch_spmm(const DevBSRT<T> &A, const T *X, T *Y, const T *W, int ld, int 
                  const BatchCtrl *c, hipStream_t s) {
   if (A.n == 0) return;
   kb = kb > ld ? ld : kb;
-#define SPMM_CASE(K)                                                     \
-  case K:                                                                \
-    if (W) spmm_kb<T, true, K>(A, X, Y, W, ld, alpha, c, s);             \
-    else spmm_kb<T, false, K>(A, X, Y, W, ld, alpha, c, s);              \
-    break;
-  switch (kb) {
-    SPMM_CASE(4)
-    SPMM_CASE(8)
-    SPMM_CASE(16)
-    SPMM_CASE(32)
-    default: SPMM_CASE(1)
-  }
-#undef SPMM_CASE
+  if (W) spmm_any<T, true, false>(A, X, Y, W, ld, kb, alpha, nullptr, c, s);
+  else spmm_any<T, false, false>(A, X, Y, W, ld, kb, alpha, nullptr, c, s);
 }
 template void launch_spmm<double>(const DevBSRT<double> &, const double *, double *, const double *, int, int, double,
                                   const BatchCtrl *, hipStream_t);
@@ -295,26 +356,11 @@ template void launch_spmm<float>(const DevBSRT<float> &, const float *, float *,
 void launch_spmm_dot(const DevBSRT<double> &A, const double *X, double *Y, int ld, int kb, double *part,
                      const BatchCtrl *c, hipStream_t s) {
   kb = kb > ld ? ld : kb;
-  dim3 grid((unsigned)spmm_dot_parts(A.n, ld, kb), ld / kb);
-#define DOT_CASE(K)                                                                                                \
-  case K:                                                                                                          \
-    hipLaunchKernelGGL(k_bsr_spmm_dot<K>, grid, dim3(256), 0, s, A.n, A.rp, A.ci, A.v, X, Y, ld, part, c); \
-    break;
-  switch (kb) {
-    DOT_CASE(4)
-    DOT_CASE(8)
-    DOT_CASE(16)
-    DOT_CASE(32)
-    default: DOT_CASE(1)
-  }
-#undef DOT_CASE
+  spmm_any<double, false, true>(A, X, Y, nullptr, ld, kb, 1.0, part, c, s);
 }
-int spmm_dot_parts(int32_t n, int ld, int kb) {
+int spmm_dot_parts(const DevBSRT<double> &A, int ld, int kb) {
   kb = kb > ld ? ld : kb;
-  int64_t b = ((int64_t)n * kb + 255) / 256;
-  if (b > kBatchParts) b = kBatchParts;
-  if (b < 1) b = 1;
-  return (int)b;
+  return spmm_wgs(A.n, kb, A.split, kBatchParts);
 }
 
 template <typename T>
@@ -352,7 +398,8 @@ void launch_col_pupdate(int64_t nrow, const double *Z, double *P, int ld, const 
   hipLaunchKernelGGL(k_col_pupdate, dim3((unsigned)b), dim3(256), 0, s, n, Z, P, ld, c);
 }
 void launch_col_finish(int mode, const double *part, int nparts, int ld, BatchCtrl *c, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(64), 0, s, mode, part, nparts, ld, c);
+  if (ld < 1 || ld > 64 || 1024 % ld != 0) fail(ASPAMG_EINVAL, "column count must divide 1024");
+  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(1024), 0, s, mode, part, nparts, ld, c);
 }
 void launch_copy_cols(int64_t nrow, int k, const double *src, int64_t lds, double *dst, int64_t ldd, int kfill,
                       hipStream_t s) {
