@@ -350,6 +350,7 @@ struct Ops<double> {
   static const Sell<double> &GT(const Level &L) { return L.GT64; }
   static const Sell<double> &P(const Level &L) { return L.P64; }
   static const Sell<double> &R(const Level &L) { return L.R64; }
+  static const Sell<double> &PAP(const Level &L) { return L.PAP64; }
   static const LevelVecs<double> &V(const Level &L) { return L.v64; }
 };
 template <>
@@ -359,6 +360,7 @@ struct Ops<float> {
   static const Sell<float> &GT(const Level &L) { return L.GT32; }
   static const Sell<float> &P(const Level &L) { return L.P32; }
   static const Sell<float> &R(const Level &L) { return L.R32; }
+  static const Sell<float> &PAP(const Level &L) { return L.PAP32; }
   static const LevelVecs<float> &V(const Level &L) { return L.v32; }
 };
 
@@ -387,9 +389,11 @@ static void cycle_level(aspamg_ctx *h, int l, const T *y, T *z, const PcgCtrl *c
   launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
   launch_spmv<T, T, T>(O::R(L), W.r, Wn.y, nullptr, 1.0, ctrl, s);
   cycle_level<T>(h, l + 1, Wn.y, Wn.z, ctrl);
-  launch_spmv<T, T, T>(O::P(L), Wn.z, z, z, 1.0, ctrl, s);
+  // first post-smoothing step (nu2 >= 1): z += P e and r = (y - A z_pre) - (A P) e in one
+  // stacked product (W.r still holds the pre-smoothing residual)
+  launch_spmv_dual<T, T, T>(O::PAP(L), L.P.n, Wn.z, z, z, 1.0, W.r, W.r, -1.0, ctrl, s);
   for (int it = 0; it < h->p.nu2; it++) {
-    launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
+    if (it > 0) launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
     launch_spmv<T, T, T>(O::G(L), W.r, W.t, nullptr, 1.0, ctrl, s);
     launch_spmv<T, T, T>(O::GT(L), W.t, z, z, w, ctrl, s);
   }
@@ -487,9 +491,13 @@ static double cycle_bytes(const aspamg_ctx *h, int prec) {
       continue;
     }
     const double nA = (double)L.A.nnzb(), nG = (double)L.G.nnzb(), nP = (double)L.P.nnzb();
-    // A: nu1 - 1 pre-smoothing residuals, the restriction residual, nu2 post-smoothing residuals
-    const double usesA = (double)nu;
-    B += (usesA * nA + 2.0 * nu * nG + 2.0 * nP) * bb + 18.0 * 3.0 * L.A.n * s;
+    // A: nu1 - 1 pre-smoothing residuals, the restriction residual and nu2 - 1
+    // post-smoothing residuals; A P once (first post-smoothing residual); P
+    // for the restriction and the prolongation
+    const int nu2 = h->p.nu2;
+    const double usesA = (double)(h->p.nu1 + (nu2 > 0 ? nu2 - 1 : 0));
+    const double usesAP = nu2 > 0 ? (double)L.nnzb_AP : 0.0;
+    B += (usesA * nA + usesAP + 2.0 * nu * nG + 2.0 * nP) * bb + 18.0 * 3.0 * L.A.n * s;
   }
   return B;
 }

@@ -102,6 +102,11 @@ struct Level {
   DevBSR dA;                       // plain FP64 device copy for setup kernels
   Sell<double> A64, G64, GT64, P64, R64;
   Sell<float> A32, G32, GT32, P32, R32;
+  // [P; A P] stacked (2 N rows): the first post-smoothing step forms
+  // z + P e and r_pre - (A P) e in one product
+  Sell<double> PAP64;
+  Sell<float> PAP32;
+  int64_t nnzb_AP = 0;
   bool coarsest = false;
   double lambda1 = 0, omega_q = 0, omega_s = 0;
   int32_t fsai_rounds = 0;
@@ -179,6 +184,11 @@ DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M);
 template <typename T, typename TX, typename TO>
 void launch_spmv(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
                  hipStream_t s);
+// rows r < n1 of the stacked operator give y1[r] = a1 (S x)[r] + w1[r], rows
+// r >= n1 give y2[r - n1] = a2 (S x)[r] + w2[r - n1]
+template <typename T, typename TX, typename TO>
+void launch_spmv_dual(const Sell<T> &S, int32_t n1, const TX *x, TO *y1, const TO *w1, double a1, TO *y2,
+                      const TO *w2, double a2, const PcgCtrl *ctrl, hipStream_t s);
 void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
                      hipStream_t s);
 template <typename TV>

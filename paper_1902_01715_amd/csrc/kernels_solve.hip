@@ -47,11 +47,13 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
 // entry e of every slot group of the slice: 64 consecutive column indices,
 // then 9 runs of 64 consecutive values.  The L partial sums of a row meet in a
 // butterfly and lane j = 0 writes the row.
-template <typename T, typename TX, typename TO, bool HAS_W, int L>
+// With DUAL, rows r >= n1 write y2[r - n1] = alpha2 (A x)[r] + w2[r - n1].
+template <typename T, typename TX, typename TO, bool HAS_W, int L, bool DUAL = false>
 __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__restrict__ sptr,
                                                    const int32_t *__restrict__ col,
                                                    const T *__restrict__ val, const TX *__restrict__ x, TO *y,
-                                                   const TO *w, T alpha, const PcgCtrl *ctrl) {
+                                                   const TO *w, T alpha, const PcgCtrl *ctrl, int32_t n1 = 0,
+                                                   TO *y2 = nullptr, const TO *w2 = nullptr, T alpha2 = 0) {
   if (ctrl_done(ctrl)) return;
   const int32_t t = xcd_block() * 256 + threadIdx.x;
   const int32_t sl = t >> 6, e = t & 63;
@@ -80,9 +82,16 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
     }
     if ((e & (L - 1)) != 0) return;
   }
-  TO *yo = y + 3 * (size_t)row;
+  int32_t orow = row;
+  if (DUAL && row >= n1) {
+    orow = row - n1;
+    y = y2;
+    w = w2;
+    alpha = alpha2;
+  }
+  TO *yo = y + 3 * (size_t)orow;
   if (HAS_W) {
-    const TO *wo = w + 3 * (size_t)row;
+    const TO *wo = w + 3 * (size_t)orow;
     yo[0] = (TO)(alpha * a0) + wo[0];
     yo[1] = (TO)(alpha * a1) + wo[1];
     yo[2] = (TO)(alpha * a2) + wo[2];
@@ -96,12 +105,13 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
 // The same product on the row-packed layout: every lane streams its K slot
 // groups (fully unrolled), parks its three partial sums in LDS, and the first
 // lane of each row adds the row's lanes in lane order and writes the row.
-template <typename T, typename TX, typename TO, bool HAS_W, int K>
+template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL = false>
 __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t *__restrict__ wrow,
                                                    const uint16_t *__restrict__ meta,
                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
                                                    const TX *__restrict__ x, TO *y, const TO *w, T alpha,
-                                                   const PcgCtrl *ctrl) {
+                                                   const PcgCtrl *ctrl, int32_t n1 = 0, TO *y2 = nullptr,
+                                                   const TO *w2 = nullptr, T alpha2 = 0) {
   __shared__ T part[3][256];
   if (ctrl_done(ctrl)) return;          // the same for every thread of the grid
   const int32_t t = xcd_block() * 256 + threadIdx.x;
@@ -135,7 +145,13 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
     s1 += part[1][threadIdx.x + j];
     s2 += part[2][threadIdx.x + j];
   }
-  const int32_t row = wrow[wv] + (int32_t)(m & 0xFF);
+  int32_t row = wrow[wv] + (int32_t)(m & 0xFF);
+  if (DUAL && row >= n1) {
+    row -= n1;
+    y = y2;
+    w = w2;
+    alpha = alpha2;
+  }
   TO *yo = y + 3 * (size_t)row;
   if (HAS_W) {
     const TO *wo = w + 3 * (size_t)row;
@@ -442,6 +458,56 @@ void launch_spmv(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha
   if (w) launch_spmv_w<T, TX, TO, true>(A, x, y, w, alpha, ctrl, s);
   else launch_spmv_w<T, TX, TO, false>(A, x, y, w, alpha, ctrl, s);
 }
+
+template <typename T, typename TX, typename TO, int L>
+static void launch_dual_l(const Sell<T> &A, int32_t n1, const TX *x, TO *y1, const TO *w1, double a1, TO *y2,
+                          const TO *w2, double a2, const PcgCtrl *ctrl, hipStream_t s) {
+  const int64_t threads = (int64_t)A.nslices * 64;
+  hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, true, L, true>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                     s, A.n, A.sptr, A.col, A.val, x, y1, w1, (T)a1, ctrl, n1, y2, w2, (T)a2);
+}
+
+template <typename T, typename TX, typename TO, int K>
+static void launch_dual_k(const Sell<T> &A, int32_t n1, const TX *x, TO *y1, const TO *w1, double a1, TO *y2,
+                          const TO *w2, double a2, const PcgCtrl *ctrl, hipStream_t s) {
+  const int64_t threads = (int64_t)A.nslices * 64;
+  hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, true, K, true>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                     s, A.nslices, A.sptr, A.meta, A.col, A.val, x, y1, w1, (T)a1, ctrl, n1, y2, w2, (T)a2);
+}
+
+template <typename T, typename TX, typename TO>
+void launch_spmv_dual(const Sell<T> &A, int32_t n1, const TX *x, TO *y1, const TO *w1, double a1, TO *y2,
+                      const TO *w2, double a2, const PcgCtrl *ctrl, hipStream_t s) {
+  if (A.n == 0) return;
+  if (!w1 || !w2 || n1 < 0 || n1 > A.n) fail(ASPAMG_EINVAL, "stacked product needs both addends and 0 <= n1 <= n");
+#define DUAL_ARGS A, n1, x, y1, w1, a1, y2, w2, a2, ctrl, s
+  if (A.pack) {
+    switch (A.pack) {
+      case 1: launch_dual_k<T, TX, TO, 1>(DUAL_ARGS); break;
+      case 2: launch_dual_k<T, TX, TO, 2>(DUAL_ARGS); break;
+      case 4: launch_dual_k<T, TX, TO, 4>(DUAL_ARGS); break;
+      case 8: launch_dual_k<T, TX, TO, 8>(DUAL_ARGS); break;
+      default: fail(ASPAMG_EINVAL, "row-packed layout with an unsupported group count");
+    }
+  } else {
+    switch (A.lanes) {
+      case 1: launch_dual_l<T, TX, TO, 1>(DUAL_ARGS); break;
+      case 2: launch_dual_l<T, TX, TO, 2>(DUAL_ARGS); break;
+      case 4: launch_dual_l<T, TX, TO, 4>(DUAL_ARGS); break;
+      case 8: launch_dual_l<T, TX, TO, 8>(DUAL_ARGS); break;
+      case 16: launch_dual_l<T, TX, TO, 16>(DUAL_ARGS); break;
+      case 32: launch_dual_l<T, TX, TO, 32>(DUAL_ARGS); break;
+      default: launch_dual_l<T, TX, TO, 64>(DUAL_ARGS); break;
+    }
+  }
+#undef DUAL_ARGS
+}
+template void launch_spmv_dual<double, double, double>(const Sell<double> &, int32_t, const double *, double *,
+                                                       const double *, double, double *, const double *, double,
+                                                       const PcgCtrl *, hipStream_t);
+template void launch_spmv_dual<float, float, float>(const Sell<float> &, int32_t, const float *, float *,
+                                                    const float *, double, float *, const float *, double,
+                                                    const PcgCtrl *, hipStream_t);
 
 template void launch_spmv<double, double, double>(const Sell<double> &, const double *, double *, const double *,
                                                   double, const PcgCtrl *, hipStream_t);

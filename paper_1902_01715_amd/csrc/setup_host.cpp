@@ -857,7 +857,8 @@ struct DevTmp {
   }
 };
 
-HostBSR galerkin(aspamg_ctx *h, const Level &L) {
+// A_c = R (A P); the intermediate T = A P is returned in *AP.
+HostBSR galerkin(aspamg_ctx *h, const Level &L, HostBSR *AP) {
   HostBSR R = transpose(L.P);
   HostBSR T = spgemm_pattern(L.A, L.P);
   HostBSR Ac = spgemm_pattern(R, T);
@@ -868,7 +869,24 @@ HostBSR galerkin(aspamg_ctx *h, const Level &L) {
   launch_spgemm_rt(dR, dT, dC, h->stream);
   HIPCHK(hipGetLastError());
   to_host(h->stream, Ac.v.data(), dC.v, Ac.v.size());
+  to_host(h->stream, T.v.data(), dT.v, T.v.size());
+  *AP = std::move(T);
   return Ac;
+}
+
+// [P; A P]: the rows of P, then those of A P (same columns)
+HostBSR stack_rows(const HostBSR &P, const HostBSR &AP) {
+  HostBSR S;
+  S.n = P.n + AP.n;
+  S.nc = P.nc;
+  S.rp.resize((size_t)S.n + 1);
+  for (int32_t i = 0; i <= P.n; i++) S.rp[i] = P.rp[i];
+  for (int32_t i = 1; i <= AP.n; i++) S.rp[P.n + i] = P.rp[P.n] + AP.rp[i];
+  S.ci = P.ci;
+  S.ci.insert(S.ci.end(), AP.ci.begin(), AP.ci.end());
+  S.v = P.v;
+  S.v.insert(S.v.end(), AP.v.begin(), AP.v.end());
+  return S;
 }
 
 // dense coarsest factor and explicit inverse (L^{-T} L^{-1})
@@ -965,7 +983,8 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     }
     build_prolongation(h, L, S);
     clk.tick(l, "DPLS");
-    HostBSR Ac = galerkin(h, L);
+    HostBSR AP;
+    HostBSR Ac = galerkin(h, L, &AP);
     clk.tick(l, "Galerkin");
     // device operators of this level
     L.G64 = upload_sell<double>(h, L.G);
@@ -978,6 +997,13 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     HostBSR R = transpose(L.P);
     L.R64 = upload_sell<double>(h, R);
     L.R32 = upload_sell<float>(h, R);
+    {
+      L.nnzb_AP = AP.nnzb();
+      HostBSR PAP = stack_rows(L.P, AP);
+      AP = HostBSR();
+      L.PAP64 = upload_sell<double>(h, PAP);
+      L.PAP32 = upload_sell<float>(h, PAP);
+    }
     clk.tick(l, "upload G P R");
     std::vector<double> Vc((size_t)nc * 3 * ntv);
     for (int32_t i = 0; i < N; i++)
