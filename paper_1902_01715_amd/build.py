@@ -30,7 +30,7 @@ SOURCES = [
     ("kernels_batch.hip", True, []),
     ("batch_api.cpp", False, []),
     ("setup_host.cpp", False, ["-ffp-contract=off", "-fopenmp"]),
-    ("api.cpp", False, []),
+    ("api.cpp", False, ["-fopenmp"]),
 ]
 
 

@@ -119,6 +119,7 @@ static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::
   std::vector<int32_t> col((size_t)S.ngroups * 64, 0);
   std::vector<T> val((size_t)S.ngroups * 576, (T)0);
   std::vector<uint16_t> meta((size_t)S.nslices * 64, 0x00FF);
+#pragma omp parallel for schedule(dynamic, 64)
   for (int32_t s = 0; s < S.nslices; s++) {
     int e = 0;
     for (int32_t r = w0[s]; r < w0[s + 1]; r++) {
@@ -145,42 +146,43 @@ static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::
   return S;
 }
 
-// Sliced copy of M with L = force_lanes lanes per row, or the smallest L that
-// keeps kMinThreads lanes busy and then the L (up to 64) with the fewest padded
-// slots, a larger L having to save at least 5%.
+// Lanes per row of the sliced copy: force_lanes, or the smallest L that keeps
+// kMinThreads lanes busy and then the L (up to 64) with the fewest padded
+// slots, a larger L having to save at least 5%.  Returns L; *sptr receives
+// the slice pointers.
+static int sliced_plan(const HostBSR &M, int force_lanes, std::vector<int32_t> *sptr) {
+  if (force_lanes) {
+    *sptr = sliced_ptr(M, force_lanes);
+    return force_lanes;
+  }
+  int L0 = 1, L = 1;
+  while (L0 < 64 && (int64_t)M.n * L0 < kMinThreads) L0 *= 2;
+  int64_t best = -1;
+  for (int c = L0; c <= 64; c *= 2) {
+    std::vector<int32_t> sp = sliced_ptr(M, c);
+    const int64_t slots = (int64_t)sp.back() * 64;
+    if (best < 0 || (double)slots < 0.95 * (double)best) {
+      best = slots;
+      L = c;
+      sptr->swap(sp);
+    }
+  }
+  return L;
+}
+
 template <typename T>
-static Sell<T> upload_sliced(aspamg_ctx *h, const HostBSR &M, int force_lanes) {
+static Sell<T> upload_sliced(aspamg_ctx *h, const HostBSR &M, int L, const std::vector<int32_t> &sptr) {
   Sell<T> S;
   S.n = M.n;
   S.nc = M.nc;
   S.nnzb = M.nnzb();
-  int L = 1;
-  std::vector<int32_t> sptr;
-  if (force_lanes) {
-    L = force_lanes;
-    sptr = sliced_ptr(M, L);
-  } else {
-    // smallest L that keeps kMinThreads lanes busy, then the L (up to 64)
-    // with the fewest padded slots; a larger L must save at least 5%
-    int L0 = 1;
-    while (L0 < 64 && (int64_t)M.n * L0 < kMinThreads) L0 *= 2;
-    int64_t best = -1;
-    for (int c = L0; c <= 64; c *= 2) {
-      std::vector<int32_t> sp = sliced_ptr(M, c);
-      const int64_t slots = (int64_t)sp.back() * 64;
-      if (best < 0 || (double)slots < 0.95 * (double)best) {
-        best = slots;
-        L = c;
-        sptr.swap(sp);
-      }
-    }
-  }
   S.lanes = L;
   const int rps = kSell / L;
   S.nslices = (int32_t)sptr.size() - 1;
   S.ngroups = sptr.back();
   std::vector<int32_t> col((size_t)S.ngroups * 64, 0);
   std::vector<T> val((size_t)S.ngroups * 576, (T)0);
+#pragma omp parallel for schedule(dynamic, 64)
   for (int32_t s = 0; s < S.nslices; s++) {
     for (int e = 0; e < kSell; e++) {
       const int32_t r = s * rps + e / L;
@@ -259,8 +261,9 @@ static void time_products(aspamg_ctx *h, const Sell<T> &S, const Sell<T> &Q, con
 template <typename T>
 Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed) {
   const int policy = h->p.layout;
-  Sell<T> S = upload_sliced<T>(h, M, force_lanes);
-  if (force_lanes || M.n == 0 || M.nc == 0 || policy == 2) return S;
+  std::vector<int32_t> sptr;
+  const int L = sliced_plan(M, force_lanes, &sptr);
+  if (force_lanes || M.n == 0 || M.nc == 0 || policy == 2) return upload_sliced<T>(h, M, L, sptr);
   if (policy != 0) timed = false;
   int bestK = 0;
   int64_t best = 0;
@@ -275,19 +278,17 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
       bestw.swap(w0);
     }
   }
-  if (!bestK) return S;                 // a row needs more than 64 lanes
-  if (policy == 3) {
-    free_sell(h, S);
-    return upload_packed<T>(h, M, bestK, bestw);
-  }
-  const double ratio = (double)best / (double)S.slots();
+  if (!bestK) return upload_sliced<T>(h, M, L, sptr);   // a row needs more than 64 lanes
+  if (policy == 3) return upload_packed<T>(h, M, bestK, bestw);
+  const int64_t sliced = (int64_t)sptr.back() * 64;
+  const double ratio = (double)best / (double)sliced;
   // small operators sit at the launch-latency floor either way: no timing
-  if (!timed || std::max<int64_t>(best, S.slots()) < kTimedSlots) {
-    if (ratio >= 0.9) return S;
-    free_sell(h, S);
+  if (!timed || std::max<int64_t>(best, sliced) < kTimedSlots) {
+    if (ratio >= 0.9) return upload_sliced<T>(h, M, L, sptr);
     return upload_packed<T>(h, M, bestK, bestw);
   }
-  if (ratio > 1.5) return S;
+  if (ratio > 1.5) return upload_sliced<T>(h, M, L, sptr);
+  Sell<T> S = upload_sliced<T>(h, M, L, sptr);
   Sell<T> Q = upload_packed<T>(h, M, bestK, bestw);
   T *x = nullptr, *y = nullptr;
   HIPCHK(hipMalloc(&x, sizeof(T) * 3 * (size_t)M.nc));
@@ -610,6 +611,7 @@ aspamg_status aspamg_destroy(aspamg_handle h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (void *p : h->allocations) (void)hipFree(p);
   if (h->ctrl_host) (void)hipHostFree(h->ctrl_host);
+  if (h->staging) (void)hipHostFree(h->staging);
   if (h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return ASPAMG_OK;

@@ -149,6 +149,8 @@ struct aspamg_ctx {
   double c_gd = 0, c_op = 0, c_fs = 0;
   aspamg::BatchWork *batch = nullptr;
   std::vector<void *> allocations;
+  void *staging = nullptr;                    // pinned host staging for setup copies
+  size_t staging_bytes = 0;
 };
 
 struct aspamg_assembler_ctx {
@@ -216,7 +218,7 @@ int spmv_blocks(int32_t nrows);
 // FSAI rows: for each listed block row I (rows[i]) with nodes pat[pat_ptr[i]..pat_ptr[i+1]),
 // computes the three scaled rows g (stride gstride) and psi. Returns nonzero on a bad pivot.
 int launch_fsai_rows(const DevBSR &A, int32_t nrows, const int32_t *rows, const int32_t *pat_ptr,
-                     const int32_t *pat_nodes, int mmax, double *g, int gstride, double *psi, int32_t *fail_flag,
+                     const int32_t *pat_nodes, int mmax, double *g, double *psi, int32_t *fail_flag,
                      hipStream_t s);
 // DPLS weights: for each listed scalar row i, K=cnt[i] chosen scalar rows sel[i*kMaxPEntries + k]
 // of the fine-level test space V (ntv columns): w = (C^T C)^{-1} C^T v.

@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(64) k_fsai_rows(int32_t nrows, const int32_t *
                                                   const int32_t *__restrict__ pat_nodes,
                                                   const int32_t *__restrict__ Arp, const int32_t *__restrict__ Aci,
                                                   const double *__restrict__ Av, int mmax, double *__restrict__ gout,
-                                                  int gstride, double *__restrict__ psi, int32_t *fail) {
+                                                  double *__restrict__ psi, int32_t *fail) {
   extern __shared__ double L[];         // packed lower triangle, m(m+1)/2
   __shared__ int32_t nodes[kMaxFsaiNodes + 1];
   __shared__ int bad;
@@ -93,7 +93,10 @@ __global__ void __launch_bounds__(64) k_fsai_rows(int32_t nrows, const int32_t *
   if (lane < 3) {
     const int d = lane;
     const int md = 3 * nb + d + 1;
-    double *g = gout + ((size_t)r * 3 + d) * gstride;
+    // compact output: the scalar rows of chunk row r start at 3 (3 pat_ptr[r]
+    // + 3 r), each 3 nb + 3 entries long (md used, the rest zero)
+    const int rs = 3 * nb + 3;
+    double *g = gout + (size_t)3 * (3 * (size_t)p0 + 3 * (size_t)r) + (size_t)d * rs;
     const double lmm = L[tri(md - 1, md - 1)];
     g[md - 1] = 1.0 / lmm;
     for (int k = md - 2; k >= 0; k--) {
@@ -101,7 +104,7 @@ __global__ void __launch_bounds__(64) k_fsai_rows(int32_t nrows, const int32_t *
       for (int jj = k + 1; jj < md; jj++) acc += L[tri(jj, k)] * g[jj];
       g[k] = -acc / L[tri(k, k)];
     }
-    for (int k = md; k < gstride; k++) g[k] = 0.0;
+    for (int k = md; k < rs; k++) g[k] = 0.0;
     psi[(size_t)r * 3 + d] = lmm * lmm;
   }
 }
@@ -289,12 +292,12 @@ __global__ void __launch_bounds__(256) k_assemble(int64_t nnzb, const int64_t *_
 }  // namespace
 
 int launch_fsai_rows(const DevBSR &A, int32_t nrows, const int32_t *rows, const int32_t *pat_ptr,
-                     const int32_t *pat_nodes, int mmax, double *g, int gstride, double *psi, int32_t *fail_flag,
+                     const int32_t *pat_nodes, int mmax, double *g, double *psi, int32_t *fail_flag,
                      hipStream_t s) {
   if (nrows == 0) return 0;
   const size_t lds = (size_t)mmax * (mmax + 1) / 2 * sizeof(double);
   hipLaunchKernelGGL(k_fsai_rows, dim3(nrows), dim3(64), lds, s, nrows, rows, pat_ptr, pat_nodes, A.rp, A.ci, A.v,
-                     mmax, g, gstride, psi, fail_flag);
+                     mmax, g, psi, fail_flag);
   return 0;
 }
 

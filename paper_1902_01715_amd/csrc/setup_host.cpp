@@ -74,6 +74,20 @@ struct Scratch {
   T *as() const { return static_cast<T *>(p); }
 };
 
+// Pinned host buffer of at least `bytes`, kept by the handle across setup
+// steps (device-to-host copies into pinned memory run at full link speed).
+void *staging(aspamg_ctx *h, size_t bytes) {
+  if (bytes > h->staging_bytes) {
+    if (h->staging) (void)hipHostFree(h->staging);
+    h->staging = nullptr;
+    h->staging_bytes = 0;
+    if (hipHostMalloc(&h->staging, bytes, hipHostMallocDefault) != hipSuccess)
+      fail(ASPAMG_ENOMEM, "pinned staging allocation failed");
+    h->staging_bytes = bytes;
+  }
+  return h->staging;
+}
+
 template <typename T>
 void to_device(hipStream_t s, T *d, const T *hsrc, size_t n) {
   if (n) HIPCHK(hipMemcpyAsync(d, hsrc, n * sizeof(T), hipMemcpyHostToDevice, s));
@@ -118,26 +132,34 @@ void fsai_factor(aspamg_ctx *h, const Level &L, FsaiState &F, const std::vector<
       const int32_t I = rows[c0 + i];
       std::memcpy(pnodes.data() + pptr[i], F.nodes.data() + (size_t)I * kMaxFsaiNodes, F.nb[I] * sizeof(int32_t));
     }
-    Scratch drows(m * 4), dptr((m + 1) * 4), dnodes(pnodes.size() * 4), dg((size_t)m * 3 * gs * 8),
-        dpsi((size_t)m * 3 * 8), dfail(4);
+    const size_t gn = (size_t)3 * (3 * (size_t)pptr[m] + 3 * (size_t)m);   // compact g entries
+    Scratch drows(m * 4), dptr((m + 1) * 4), dnodes(pnodes.size() * 4), dg(gn * 8), dpsi((size_t)m * 3 * 8),
+        dfail(4);
     to_device(h->stream, drows.as<int32_t>(), rows.data() + c0, m);
     to_device(h->stream, dptr.as<int32_t>(), pptr.data(), m + 1);
     to_device(h->stream, dnodes.as<int32_t>(), pnodes.data(), pnodes.size());
     HIPCHK(hipMemsetAsync(dfail.p, 0, 4, h->stream));
     const int mmax = 3 * maxnb + 3;
     launch_fsai_rows(L.dA, m, drows.as<int32_t>(), dptr.as<int32_t>(), dnodes.as<int32_t>(), mmax, dg.as<double>(),
-                     gs, dpsi.as<double>(), dfail.as<int32_t>(), h->stream);
+                     dpsi.as<double>(), dfail.as<int32_t>(), h->stream);
     HIPCHK(hipGetLastError());
-    std::vector<double> g((size_t)m * 3 * gs), psi((size_t)m * 3);
+    double *g = static_cast<double *>(staging(h, gn * 8));
+    std::vector<double> psi((size_t)m * 3);
     int32_t bad = 0;
-    to_host(h->stream, g.data(), dg.as<double>(), g.size());
+    to_host(h->stream, g, dg.as<double>(), gn);
     to_host(h->stream, psi.data(), dpsi.as<double>(), psi.size());
     to_host(h->stream, &bad, dfail.as<int32_t>(), 1);
     if (bad) fail(ASPAMG_ENOT_SPD, "aFSAI: a local system is not positive definite");
 #pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < m; i++) {
       const int32_t I = rows[c0 + i];
-      std::memcpy(F.g.data() + (size_t)I * 3 * gs, g.data() + (size_t)i * 3 * gs, 3 * gs * sizeof(double));
+      const int rs = 3 * F.nb[I] + 3;
+      const double *src = g + (size_t)3 * (3 * (size_t)pptr[i] + 3 * (size_t)i);
+      for (int d = 0; d < 3; d++) {
+        double *dst = F.g.data() + ((size_t)I * 3 + d) * gs;
+        std::memcpy(dst, src + (size_t)d * rs, rs * sizeof(double));
+        std::memset(dst + rs, 0, (gs - rs) * sizeof(double));
+      }
       std::memcpy(F.psi.data() + (size_t)I * 3, psi.data() + (size_t)i * 3, 3 * sizeof(double));
     }
   }
@@ -200,18 +222,27 @@ int fsai_grow(const HostBSR &A, FsaiState &F, int32_t I, int rho, const Q &q, st
       while (k < ke && A.ci[k] < nd) k++;
       pos[p] = (k < ke && A.ci[k] == nd) ? k : -1;
     }
+    // h_{d,e} = sum over kk ascending (absent blocks skipped) of
+    // A[(J,e), l_kk] g'_d[kk]; the three e run side by side, each in that order
     double score = 0.0;
     for (int d = 0; d < 3; d++) {
       const int md = 3 * nb + d + 1;
-      for (int e = 0; e < 3; e++) {
-        double hh = 0.0;
-        for (int kk = 0; kk < md; kk++) {
-          const int64_t bp = pos[kk / 3];
-          if (bp < 0) continue;
-          hh += A.v[(size_t)bp * 9 + e * 3 + (kk % 3)] * gp[d][kk];
+      double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+      for (int pp = 0; pp <= nb; pp++) {
+        const int64_t bp = pos[pp];
+        if (bp < 0) continue;
+        const double *blk = A.v.data() + (size_t)bp * 9;
+        const int kend = std::min(3, md - 3 * pp);
+        for (int c = 0; c < kend; c++) {
+          const double gk = gp[d][3 * pp + c];
+          h0 += blk[c] * gk;
+          h1 += blk[3 + c] * gk;
+          h2 += blk[6 + c] * gk;
         }
-        score += hh * hh;
       }
+      score += h0 * h0;
+      score += h1 * h1;
+      score += h2 * h2;
     }
     if (score > 0.0) sc.emplace_back(q(score), J);
   }
