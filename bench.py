@@ -185,6 +185,34 @@ def bench_adjoint(args, p, desc):
     }
 
 
+def stream_reference():
+    """Streaming rates of PyTorch's own kernels on 2 GiB FP64 arrays (read-only
+    sum, write-only fill, two-read-one-write add, copy): the practical HBM
+    ceiling against which the solve kernels' GB/s are read."""
+    import torch
+    n = 1 << 28
+    a = torch.empty(n, dtype=torch.float64, device="cuda").normal_()
+    b = torch.empty_like(a)
+
+    def rate(f, nbytes, reps=20):
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+    out = {"stream_reference_GBps": {
+        "sum": rate(lambda: a.sum(), 8 * n),
+        "fill": rate(lambda: b.fill_(1.0), 8 * n),
+        "add_2r1w": rate(lambda: torch.add(a, b, out=b), 24 * n),
+        "copy": rate(lambda: b.copy_(a), 16 * n)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,7 +223,12 @@ def main():
     ap.add_argument("--max-it", type=int, default=1000)
     ap.add_argument("--coarse-max-dof", type=int, default=1500,
                     help="factor the coarsest level densely once it has at most this many DOF")
+    ap.add_argument("--stream-ref", action="store_true",
+                    help="only measure PyTorch's streaming rates on this device and exit")
     args = ap.parse_args()
+    if args.stream_ref:
+        stream_reference()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

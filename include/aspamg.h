@@ -116,6 +116,10 @@ typedef struct {
    * with L lanes per row, -K for the row-packed layout with K slot groups per
    * wavefront */
   int32_t sell_lanes64[5], sell_lanes32[5];
+  /* bit k (FP64 copy) and bit 5 + k (FP32 copy) set when operator k stores its
+   * columns as 16-bit offsets from a per-slice base */
+  int32_t sell_index16;
+  int32_t reserved;
 } aspamg_level_info_t;
 
 /* Fill *out with the defaults.  out: caller-owned. */

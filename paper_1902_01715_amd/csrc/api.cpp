@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <memory>
 
 #include "internal.h"
@@ -13,7 +14,7 @@
 // sizes mirrored by the Python binding
 static_assert(sizeof(aspamg_params) == 160, "aspamg_params layout changed");
 static_assert(sizeof(aspamg_stats) == 96, "aspamg_stats layout changed");
-static_assert(sizeof(aspamg_level_info_t) == 128, "aspamg_level_info_t layout changed");
+static_assert(sizeof(aspamg_level_info_t) == 136, "aspamg_level_info_t layout changed");
 
 namespace aspamg {
 
@@ -90,14 +91,57 @@ static std::vector<int32_t> packed_waves(const HostBSR &M, int K) {
   return w0;
 }
 
+// Padding entries (column -1 on entry) take the smallest real column of their
+// owner (slice or wavefront: entries [first[s]*64, first[s+1]*64)); returns the
+// per-owner bases when every owner spans at most 65,536 columns, else empty.
+static std::vector<int32_t> settle_columns(std::vector<int32_t> &col, int32_t nowners,
+                                           const std::function<int64_t(int32_t)> &first) {
+  std::vector<int32_t> base(nowners, 0);
+  bool fits = true;
+#pragma omp parallel for schedule(static) reduction(&& : fits)
+  for (int32_t s = 0; s < nowners; s++) {
+    int32_t lo = INT32_MAX, hi = -1;
+    for (int64_t i = first(s) * 64; i < first(s + 1) * 64; i++)
+      if (col[i] >= 0) {
+        lo = std::min(lo, col[i]);
+        hi = std::max(hi, col[i]);
+      }
+    if (hi < 0) lo = hi = 0;
+    for (int64_t i = first(s) * 64; i < first(s + 1) * 64; i++)
+      if (col[i] < 0) col[i] = lo;
+    base[s] = lo;
+    fits = fits && hi - lo <= 65535;
+  }
+  if (!fits) base.clear();
+  return base;
+}
+
 template <typename T>
 static void upload_arrays(aspamg_ctx *h, Sell<T> &S, const std::vector<int32_t> &sptr, const std::vector<int32_t> &col,
-                          const std::vector<T> &val, const std::vector<uint16_t> &meta) {
+                          const std::vector<int32_t> &base, const std::vector<T> &val,
+                          const std::vector<uint16_t> &meta) {
   S.sptr = dalloc<int32_t>(h, sptr.size());
-  S.col = dalloc<int32_t>(h, col.size());
-  S.val = dalloc<T>(h, val.size());
   HIPCHK(hipMemcpyAsync(S.sptr, sptr.data(), sptr.size() * 4, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(S.col, col.data(), col.size() * 4, hipMemcpyHostToDevice, h->stream));
+  std::vector<uint16_t> c16;
+  if (!base.empty()) {
+    // owner of slot group g: the slice (sliced) or wavefront (row-packed) it belongs to
+    c16.resize(col.size());
+    const int32_t nowners = (int32_t)base.size();
+#pragma omp parallel for schedule(static)
+    for (int32_t s = 0; s < nowners; s++) {
+      const int64_t g0 = S.pack ? (int64_t)s * S.pack : sptr[s];
+      const int64_t g1 = S.pack ? (int64_t)(s + 1) * S.pack : sptr[s + 1];
+      for (int64_t i = g0 * 64; i < g1 * 64; i++) c16[i] = (uint16_t)(col[i] - base[s]);
+    }
+    S.col16 = dalloc<uint16_t>(h, c16.size());
+    S.cbase = dalloc<int32_t>(h, base.size());
+    HIPCHK(hipMemcpyAsync(S.col16, c16.data(), c16.size() * 2, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(S.cbase, base.data(), base.size() * 4, hipMemcpyHostToDevice, h->stream));
+  } else {
+    S.col = dalloc<int32_t>(h, col.size());
+    HIPCHK(hipMemcpyAsync(S.col, col.data(), col.size() * 4, hipMemcpyHostToDevice, h->stream));
+  }
+  S.val = dalloc<T>(h, val.size());
   HIPCHK(hipMemcpyAsync(S.val, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
   if (!meta.empty()) {
     S.meta = dalloc<uint16_t>(h, meta.size());
@@ -116,7 +160,7 @@ static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::
   S.pack = K;
   S.nslices = (int32_t)w0.size() - 1;
   S.ngroups = (int64_t)S.nslices * K;
-  std::vector<int32_t> col((size_t)S.ngroups * 64, 0);
+  std::vector<int32_t> col((size_t)S.ngroups * 64, -1);
   std::vector<T> val((size_t)S.ngroups * 576, (T)0);
   std::vector<uint16_t> meta((size_t)S.nslices * 64, 0x00FF);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -125,7 +169,6 @@ static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::
     for (int32_t r = w0[s]; r < w0[s + 1]; r++) {
       const int64_t len = M.rp[r + 1] - M.rp[r];
       const int lr = (int)std::max<int64_t>(1, (len + K - 1) / K);
-      const int32_t padc = std::min<int32_t>(r, M.nc - 1);
       for (int j = 0; j < lr; j++, e++) {
         meta[(size_t)s * 64 + e] = (uint16_t)(((j == 0 ? lr : 0) << 8) | (r - w0[s]));
         for (int k = 0; k < K; k++) {
@@ -135,14 +178,14 @@ static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::
             const int64_t src = M.rp[r] + b;
             col[g * 64 + e] = M.ci[src];
             for (int q = 0; q < 9; q++) val[(g * 9 + q) * 64 + e] = (T)M.v[(size_t)src * 9 + q];
-          } else {
-            col[g * 64 + e] = padc;
           }
         }
       }
     }
   }
-  upload_arrays(h, S, w0, col, val, meta);
+  const int64_t Kp = K;
+  std::vector<int32_t> base = settle_columns(col, S.nslices, [Kp](int32_t s) { return (int64_t)s * Kp; });
+  upload_arrays(h, S, w0, col, base, val, meta);
   return S;
 }
 
@@ -180,7 +223,7 @@ static Sell<T> upload_sliced(aspamg_ctx *h, const HostBSR &M, int L, const std::
   const int rps = kSell / L;
   S.nslices = (int32_t)sptr.size() - 1;
   S.ngroups = sptr.back();
-  std::vector<int32_t> col((size_t)S.ngroups * 64, 0);
+  std::vector<int32_t> col((size_t)S.ngroups * 64, -1);
   std::vector<T> val((size_t)S.ngroups * 576, (T)0);
 #pragma omp parallel for schedule(dynamic, 64)
   for (int32_t s = 0; s < S.nslices; s++) {
@@ -188,22 +231,18 @@ static Sell<T> upload_sliced(aspamg_ctx *h, const HostBSR &M, int L, const std::
       const int32_t r = s * rps + e / L;
       const int j = e % L;
       const int64_t len = r < M.n ? M.rp[r + 1] - M.rp[r] : 0;
-      // padding columns point at the row's own node (or 0), values stay 0
-      const int32_t padc = r < M.n ? std::min<int32_t>(r, std::max(M.nc - 1, 0)) : 0;
       for (int32_t g = sptr[s]; g < sptr[s + 1]; g++) {
         const int64_t k = (int64_t)(g - sptr[s]) * L + j;
-        const size_t cidx = (size_t)g * 64 + e;
         if (k < len) {
           const int64_t src = M.rp[r] + k;
-          col[cidx] = M.ci[src];
+          col[(size_t)g * 64 + e] = M.ci[src];
           for (int q = 0; q < 9; q++) val[((size_t)g * 9 + q) * 64 + e] = (T)M.v[(size_t)src * 9 + q];
-        } else {
-          col[cidx] = padc;
         }
       }
     }
   }
-  upload_arrays(h, S, sptr, col, val, {});
+  std::vector<int32_t> base = settle_columns(col, S.nslices, [&sptr](int32_t s) { return (int64_t)sptr[s]; });
+  upload_arrays(h, S, sptr, col, base, val, {});
   return S;
 }
 
@@ -218,6 +257,8 @@ template <typename T>
 void free_sell(aspamg_ctx *h, Sell<T> &S) {
   dfree(h, S.sptr);
   dfree(h, S.col);
+  dfree(h, S.col16);
+  dfree(h, S.cbase);
   dfree(h, S.val);
   dfree(h, S.meta);
   S = Sell<T>();
@@ -481,31 +522,42 @@ static void compute_complexities(aspamg_ctx *h) {
 // algorithmic HBM bytes of one V-cycle: every stored operator streamed once per
 // use (9 values + 4-byte column per block) plus 18 level-vector passes per
 // level, and the dense coarsest inverse
+// Algorithmic bytes: each stored block once per use (9 values plus its column
+// index, 4 or 2 bytes as stored), 18 vector passes per level, the dense
+// coarsest inverse; one PCG iteration adds q = K p and 14 FP64 vector passes.
+template <typename T>
+static double block_bytes(const Sell<T> &S) {
+  return 9.0 * sizeof(T) + S.index_bytes();
+}
+
+template <typename T>
+static double level_bytes(const aspamg_ctx *h, const Level &L) {
+  using O = Ops<T>;
+  const double nA = (double)L.A.nnzb(), nG = (double)L.G.nnzb(), nP = (double)L.P.nnzb();
+  // A: nu1 - 1 pre-smoothing residuals, the restriction residual and nu2 - 1
+  // post-smoothing residuals; G and G^T once per smoothing step; R once; the
+  // stacked [P; A P] once (first post-smoothing step, nu2 >= 1)
+  const double usesA = (double)(h->p.nu1 + h->p.nu2 - 1);
+  const double nu = (double)(h->p.nu1 + h->p.nu2);
+  return usesA * nA * block_bytes(O::A(L)) + nu * nG * (block_bytes(O::G(L)) + block_bytes(O::GT(L))) +
+         nP * block_bytes(O::R(L)) + (nP + (double)L.nnzb_AP) * block_bytes(O::PAP(L)) +
+         18.0 * 3.0 * L.A.n * sizeof(T);
+}
+
 static double cycle_bytes(const aspamg_ctx *h, int prec) {
-  const double s = prec == 32 ? 4.0 : 8.0;
-  const double bb = 9.0 * s + 4.0;
   double B = 0.0;
-  const int nu = h->p.nu1 + h->p.nu2;
   for (const auto &L : h->lev) {
-    if (L.coarsest) {
-      B += (double)h->coarse.nd * h->coarse.nd * 8.0;
-      continue;
-    }
-    const double nA = (double)L.A.nnzb(), nG = (double)L.G.nnzb(), nP = (double)L.P.nnzb();
-    // A: nu1 - 1 pre-smoothing residuals, the restriction residual and nu2 - 1
-    // post-smoothing residuals; A P once (first post-smoothing residual); P
-    // for the restriction and the prolongation
-    const int nu2 = h->p.nu2;
-    const double usesA = (double)(h->p.nu1 + (nu2 > 0 ? nu2 - 1 : 0));
-    const double usesAP = nu2 > 0 ? (double)L.nnzb_AP : 0.0;
-    B += (usesA * nA + usesAP + 2.0 * nu * nG + 2.0 * nP) * bb + 18.0 * 3.0 * L.A.n * s;
+    if (L.coarsest) B += (double)h->coarse.nd * h->coarse.nd * 8.0;
+    else B += prec == 32 ? level_bytes<float>(h, L) : level_bytes<double>(h, L);
   }
   return B;
 }
 
+static double kp_block_bytes(const aspamg_ctx *h) { return 72.0 + h->lev[0].A64.index_bytes(); }
+
 static double iter_bytes(const aspamg_ctx *h, int prec) {
   const Level &L0 = h->lev[0];
-  return (double)L0.A.nnzb() * 76.0 + 14.0 * 3.0 * L0.A.n * 8.0 + cycle_bytes(h, prec);
+  return (double)L0.A.nnzb() * kp_block_bytes(h) + 14.0 * 3.0 * L0.A.n * 8.0 + cycle_bytes(h, prec);
 }
 
 template <typename T>
@@ -842,9 +894,13 @@ aspamg_status aspamg_level_info(aspamg_handle h, int32_t level, aspamg_level_inf
   o->sell_slots_GT = L.GT64.slots();
   const Sell<double> *M64[5] = {&L.A64, &L.G64, &L.GT64, &L.P64, &L.R64};
   const Sell<float> *M32[5] = {&L.A32, &L.G32, &L.GT32, &L.P32, &L.R32};
+  o->sell_index16 = 0;
+  o->reserved = 0;
   for (int k = 0; k < 5; k++) {
     o->sell_lanes64[k] = M64[k]->pack ? -M64[k]->pack : M64[k]->lanes;
     o->sell_lanes32[k] = M32[k]->pack ? -M32[k]->pack : M32[k]->lanes;
+    if (M64[k]->col16) o->sell_index16 |= 1 << k;
+    if (M32[k]->col16) o->sell_index16 |= 1 << (5 + k);
   }
   return ASPAMG_OK;
 }
@@ -1008,9 +1064,9 @@ aspamg_status aspamg_time_kernel(aspamg_handle h, int32_t which, int32_t reps, d
   };
   const double nb = (double)L0.A.nnzb();
   switch (which) {
-    case 0: bytes = nb * 76.0 + N * 3.0 * 8.0 * 2.0; break;            // K, p, q
-    case 1: bytes = nb * 40.0 + N * 3.0 * 4.0 * 3.0; break;            // A32, s, y, r
-    case 2: bytes = nb * 76.0 + N * 3.0 * 8.0 * 3.0; break;
+    case 0: bytes = nb * kp_block_bytes(h) + N * 3.0 * 8.0 * 2.0; break;                          // K, p, q
+    case 1: bytes = nb * (36.0 + h->lev[0].A32.index_bytes()) + N * 3.0 * 4.0 * 3.0; break;      // A32, s, y, r
+    case 2: bytes = nb * kp_block_bytes(h) + N * 3.0 * 8.0 * 3.0; break;
     case 3: bytes = cycle_bytes(h, 32); break;
     case 4: bytes = cycle_bytes(h, 64); break;
   }

@@ -71,10 +71,13 @@ struct Sell {
   int64_t ngroups = 0;     // slot groups (64 entries each)
   int64_t nnzb = 0;        // real blocks
   int32_t *sptr = nullptr;
-  int32_t *col = nullptr;
+  int32_t *col = nullptr;      // int32 columns, or null when col16 is used
+  uint16_t *col16 = nullptr;   // columns as offsets from cbase[s] of their slice / wavefront
+  int32_t *cbase = nullptr;
   T *val = nullptr;
   uint16_t *meta = nullptr;
   int64_t slots() const { return ngroups * 64; }
+  int index_bytes() const { return col16 ? 2 : 4; }
 };
 
 // Device-resident PCG control block (one per solve stream).

@@ -48,24 +48,26 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
 // then 9 runs of 64 consecutive values.  The L partial sums of a row meet in a
 // butterfly and lane j = 0 writes the row.
 // With DUAL, rows r >= n1 write y2[r - n1] = alpha2 (A x)[r] + w2[r - n1].
-template <typename T, typename TX, typename TO, bool HAS_W, int L, bool DUAL = false>
+// CI is the stored column type: int32, or uint16 offsets from cbase[slice].
+template <typename T, typename TX, typename TO, bool HAS_W, int L, bool DUAL, typename CI>
 __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__restrict__ sptr,
-                                                   const int32_t *__restrict__ col,
+                                                   const CI *__restrict__ col, const int32_t *__restrict__ cbase,
                                                    const T *__restrict__ val, const TX *__restrict__ x, TO *y,
-                                                   const TO *w, T alpha, const PcgCtrl *ctrl, int32_t n1 = 0,
-                                                   TO *y2 = nullptr, const TO *w2 = nullptr, T alpha2 = 0) {
+                                                   const TO *w, T alpha, const PcgCtrl *ctrl, int32_t n1,
+                                                   TO *y2, const TO *w2, T alpha2) {
   if (ctrl_done(ctrl)) return;
   const int32_t t = xcd_block() * 256 + threadIdx.x;
   const int32_t sl = t >> 6, e = t & 63;
   const int32_t row = sl * (64 / L) + e / L;
   if (row >= n) return;                 // whole lane groups leave together
   const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
+  const int32_t cb = sizeof(CI) == 2 ? cbase[sl] : 0;
   T a0 = 0, a1 = 0, a2 = 0;
-  const int32_t *cp = col + (size_t)g0 * 64 + e;
+  const CI *cp = col + (size_t)g0 * 64 + e;
   const T *vp = val + (size_t)g0 * 576 + e;
 #pragma unroll 2
   for (int32_t g = g0; g < g1; ++g) {
-    const int32_t c = ld_stream(cp);
+    const int32_t c = (int32_t)ld_stream(cp) + cb;
     const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
     a0 += ld_stream(vp) * x0 + ld_stream(vp + 64) * x1 + ld_stream(vp + 128) * x2;
     a1 += ld_stream(vp + 192) * x0 + ld_stream(vp + 256) * x1 + ld_stream(vp + 320) * x2;
@@ -105,13 +107,13 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
 // The same product on the row-packed layout: every lane streams its K slot
 // groups (fully unrolled), parks its three partial sums in LDS, and the first
 // lane of each row adds the row's lanes in lane order and writes the row.
-template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL = false>
+template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL, typename CI>
 __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t *__restrict__ wrow,
-                                                   const uint16_t *__restrict__ meta,
-                                                   const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                   const uint16_t *__restrict__ meta, const CI *__restrict__ col,
+                                                   const int32_t *__restrict__ cbase, const T *__restrict__ val,
                                                    const TX *__restrict__ x, TO *y, const TO *w, T alpha,
-                                                   const PcgCtrl *ctrl, int32_t n1 = 0, TO *y2 = nullptr,
-                                                   const TO *w2 = nullptr, T alpha2 = 0) {
+                                                   const PcgCtrl *ctrl, int32_t n1, TO *y2, const TO *w2,
+                                                   T alpha2) {
   __shared__ T part[3][256];
   if (ctrl_done(ctrl)) return;          // the same for every thread of the grid
   const int32_t t = xcd_block() * 256 + threadIdx.x;
@@ -121,11 +123,12 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
   T a0 = 0, a1 = 0, a2 = 0;
   if (live) {
     m = meta[(size_t)wv * 64 + e];
-    const int32_t *cp = col + (size_t)wv * K * 64 + e;
+    const int32_t cb = sizeof(CI) == 2 ? cbase[wv] : 0;
+    const CI *cp = col + (size_t)wv * K * 64 + e;
     const T *vp = val + (size_t)wv * K * 576 + e;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int32_t c = ld_stream(cp + 64 * k);
+      const int32_t c = (int32_t)ld_stream(cp + 64 * k) + cb;
       const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
       const T *v = vp + 576 * k;
       a0 += ld_stream(v) * x0 + ld_stream(v + 64) * x1 + ld_stream(v + 128) * x2;
@@ -166,8 +169,10 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
 }
 
 // q = K p with the block partial of p.q (PCG, FP64).
+template <typename CI>
 __global__ void __launch_bounds__(256) k_sell_spmv_dot(int32_t n, const int32_t *__restrict__ sptr,
-                                                       const int32_t *__restrict__ col,
+                                                       const CI *__restrict__ col,
+                                                       const int32_t *__restrict__ cbase,
                                                        const double *__restrict__ val,
                                                        const double *__restrict__ x, double *__restrict__ y,
                                                        double *__restrict__ part, const PcgCtrl *ctrl) {
@@ -179,12 +184,13 @@ __global__ void __launch_bounds__(256) k_sell_spmv_dot(int32_t n, const int32_t 
     const int32_t sl = q >> 6, lane = q & 63;
     const int32_t row = q;
     const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
+    const int32_t cb = sizeof(CI) == 2 ? cbase[sl] : 0;
     double a0 = 0, a1 = 0, a2 = 0;
-    const int32_t *cp = col + (size_t)g0 * 64 + lane;
+    const CI *cp = col + (size_t)g0 * 64 + lane;
     const double *vp = val + (size_t)g0 * 576 + lane;
 #pragma unroll 2
     for (int32_t g = g0; g < g1; ++g) {
-      const int32_t c = ld_stream(cp);
+      const int32_t c = (int32_t)ld_stream(cp) + cb;
       const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
       a0 += ld_stream(vp) * x0 + ld_stream(vp + 64) * x1 + ld_stream(vp + 128) * x2;
       a1 += ld_stream(vp + 192) * x0 + ld_stream(vp + 256) * x1 + ld_stream(vp + 320) * x2;
@@ -404,12 +410,17 @@ int vec_blocks(int64_t n) {
 }
 int spmv_blocks(int32_t nrows) { return (nrows + 255) / 256; }
 
-template <typename T, typename TX, typename TO, bool HAS_W, int L>
+template <typename T, typename TX, typename TO, bool HAS_W, int L, bool DUAL = false>
 static void launch_l(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
-                     hipStream_t s) {
+                     hipStream_t s, int32_t n1 = 0, TO *y2 = nullptr, const TO *w2 = nullptr, double alpha2 = 0) {
   const int64_t threads = (int64_t)A.nslices * 64;
-  hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, HAS_W, L>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
-                     A.n, A.sptr, A.col, A.val, x, y, w, (T)alpha, ctrl);
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  if (A.col16)
+    hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, HAS_W, L, DUAL, uint16_t>), grid, dim3(256), 0, s, A.n, A.sptr,
+                       A.col16, A.cbase, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
+  else
+    hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, HAS_W, L, DUAL, int32_t>), grid, dim3(256), 0, s, A.n, A.sptr, A.col,
+                       nullptr, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
 }
 
 template <typename T, typename TX, typename TO, bool HAS_W>
@@ -426,12 +437,17 @@ static void launch_spmv_w(const Sell<T> &A, const TX *x, TO *y, const TO *w, dou
   }
 }
 
-template <typename T, typename TX, typename TO, bool HAS_W, int K>
+template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL = false>
 static void launch_k(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
-                     hipStream_t s) {
+                     hipStream_t s, int32_t n1 = 0, TO *y2 = nullptr, const TO *w2 = nullptr, double alpha2 = 0) {
   const int64_t threads = (int64_t)A.nslices * 64;
-  hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, HAS_W, K>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
-                     A.nslices, A.sptr, A.meta, A.col, A.val, x, y, w, (T)alpha, ctrl);
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  if (A.col16)
+    hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, HAS_W, K, DUAL, uint16_t>), grid, dim3(256), 0, s, A.nslices, A.sptr,
+                       A.meta, A.col16, A.cbase, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
+  else
+    hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, HAS_W, K, DUAL, int32_t>), grid, dim3(256), 0, s, A.nslices, A.sptr,
+                       A.meta, A.col, nullptr, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
 }
 
 template <typename T, typename TX, typename TO, bool HAS_W>
@@ -459,45 +475,29 @@ void launch_spmv(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha
   else launch_spmv_w<T, TX, TO, false>(A, x, y, w, alpha, ctrl, s);
 }
 
-template <typename T, typename TX, typename TO, int L>
-static void launch_dual_l(const Sell<T> &A, int32_t n1, const TX *x, TO *y1, const TO *w1, double a1, TO *y2,
-                          const TO *w2, double a2, const PcgCtrl *ctrl, hipStream_t s) {
-  const int64_t threads = (int64_t)A.nslices * 64;
-  hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, true, L, true>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                     s, A.n, A.sptr, A.col, A.val, x, y1, w1, (T)a1, ctrl, n1, y2, w2, (T)a2);
-}
-
-template <typename T, typename TX, typename TO, int K>
-static void launch_dual_k(const Sell<T> &A, int32_t n1, const TX *x, TO *y1, const TO *w1, double a1, TO *y2,
-                          const TO *w2, double a2, const PcgCtrl *ctrl, hipStream_t s) {
-  const int64_t threads = (int64_t)A.nslices * 64;
-  hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, true, K, true>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                     s, A.nslices, A.sptr, A.meta, A.col, A.val, x, y1, w1, (T)a1, ctrl, n1, y2, w2, (T)a2);
-}
-
 template <typename T, typename TX, typename TO>
 void launch_spmv_dual(const Sell<T> &A, int32_t n1, const TX *x, TO *y1, const TO *w1, double a1, TO *y2,
                       const TO *w2, double a2, const PcgCtrl *ctrl, hipStream_t s) {
   if (A.n == 0) return;
   if (!w1 || !w2 || n1 < 0 || n1 > A.n) fail(ASPAMG_EINVAL, "stacked product needs both addends and 0 <= n1 <= n");
-#define DUAL_ARGS A, n1, x, y1, w1, a1, y2, w2, a2, ctrl, s
+#define DUAL_ARGS A, x, y1, w1, a1, ctrl, s, n1, y2, w2, a2
   if (A.pack) {
     switch (A.pack) {
-      case 1: launch_dual_k<T, TX, TO, 1>(DUAL_ARGS); break;
-      case 2: launch_dual_k<T, TX, TO, 2>(DUAL_ARGS); break;
-      case 4: launch_dual_k<T, TX, TO, 4>(DUAL_ARGS); break;
-      case 8: launch_dual_k<T, TX, TO, 8>(DUAL_ARGS); break;
+      case 1: launch_k<T, TX, TO, true, 1, true>(DUAL_ARGS); break;
+      case 2: launch_k<T, TX, TO, true, 2, true>(DUAL_ARGS); break;
+      case 4: launch_k<T, TX, TO, true, 4, true>(DUAL_ARGS); break;
+      case 8: launch_k<T, TX, TO, true, 8, true>(DUAL_ARGS); break;
       default: fail(ASPAMG_EINVAL, "row-packed layout with an unsupported group count");
     }
   } else {
     switch (A.lanes) {
-      case 1: launch_dual_l<T, TX, TO, 1>(DUAL_ARGS); break;
-      case 2: launch_dual_l<T, TX, TO, 2>(DUAL_ARGS); break;
-      case 4: launch_dual_l<T, TX, TO, 4>(DUAL_ARGS); break;
-      case 8: launch_dual_l<T, TX, TO, 8>(DUAL_ARGS); break;
-      case 16: launch_dual_l<T, TX, TO, 16>(DUAL_ARGS); break;
-      case 32: launch_dual_l<T, TX, TO, 32>(DUAL_ARGS); break;
-      default: launch_dual_l<T, TX, TO, 64>(DUAL_ARGS); break;
+      case 1: launch_l<T, TX, TO, true, 1, true>(DUAL_ARGS); break;
+      case 2: launch_l<T, TX, TO, true, 2, true>(DUAL_ARGS); break;
+      case 4: launch_l<T, TX, TO, true, 4, true>(DUAL_ARGS); break;
+      case 8: launch_l<T, TX, TO, true, 8, true>(DUAL_ARGS); break;
+      case 16: launch_l<T, TX, TO, true, 16, true>(DUAL_ARGS); break;
+      case 32: launch_l<T, TX, TO, true, 32, true>(DUAL_ARGS); break;
+      default: launch_l<T, TX, TO, true, 64, true>(DUAL_ARGS); break;
     }
   }
 #undef DUAL_ARGS
@@ -518,8 +518,12 @@ void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *
                      hipStream_t s) {
   // one lane per row (the fine-level operator is stored so)
   if (A.pack || A.lanes != 1) fail(ASPAMG_EINVAL, "q = K p needs the sliced layout with one lane per row");
-  hipLaunchKernelGGL(k_sell_spmv_dot, dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr, A.col, A.val, x, y, part,
-                     ctrl);
+  if (A.col16)
+    hipLaunchKernelGGL(k_sell_spmv_dot<uint16_t>, dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr, A.col16,
+                       A.cbase, A.val, x, y, part, ctrl);
+  else
+    hipLaunchKernelGGL(k_sell_spmv_dot<int32_t>, dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr, A.col, nullptr,
+                       A.val, x, y, part, ctrl);
 }
 
 template <typename TV>

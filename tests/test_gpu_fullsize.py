@@ -61,6 +61,9 @@ def test_all_operators_all_levels(c2, prec):
     rng = np.random.default_rng(1)
     li0 = S.level_info(0)
     assert li0["sell_lanes64"][0] == 1       # q = K p runs one lane per row
+    # the fine-level operators of the structured mesh span < 65,536 columns per
+    # slice: all of them (FP64 and FP32) store 16-bit column offsets
+    assert li0["sell_index16"] == (1 << 10) - 1
     for l in range(S.nlev):
         li = S.level_info(l)
         ops = [0] if not li["has_smoother"] else [0, 1, 2, 3, 4]

@@ -2,7 +2,8 @@
 and row-packed with K slot groups per wavefront), forced through the `layout`
 parameter: every operator of every level against the oracle's matrices, the
 solve against the oracle, and the slot-count policy giving the same layouts and
-bitwise the same solution on two setups."""
+bitwise the same solution on two setups.  A randomly renumbered mesh, whose
+slices span more than 65,536 columns, checks the 32-bit column fallback."""
 import numpy as np
 import pytest
 
@@ -80,3 +81,53 @@ def test_slot_policy_is_reproducible(cuda, problem):
         S.close()
     assert lays[0] == lays[1]
     assert np.array_equal(outs[0], outs[1])
+
+
+def _permuted(p, seed):
+    """The problem with its nodes renumbered by a random permutation."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    n = p.n_nodes
+    perm = rng.permutation(n)                 # old node -> new node
+    inv = np.argsort(perm)
+    rp = np.asarray(p.row_ptr, dtype=np.int64)
+    B = sp.bsr_matrix((p.vals, p.col, rp), shape=(3 * n, 3 * n)).tocsr()
+    P = sp.csr_matrix((np.ones(n), (perm, np.arange(n))), shape=(n, n))
+    P3 = sp.kron(P, sp.identity(3), format="csr")
+    Bp = (P3 @ B @ P3.T).tobsr(blocksize=(3, 3))
+    Bp.sort_indices()
+    V0 = np.ascontiguousarray(p.V0[inv])
+    f = np.ascontiguousarray(p.f.reshape(n, 3)[inv].reshape(-1))
+    return (Bp.indptr.astype(np.int32), Bp.indices.astype(np.int32), np.ascontiguousarray(Bp.data), V0, f, Bp.tocsr())
+
+
+def test_wide_column_spans_use_32bit_indices(cuda):
+    import scipy.sparse as sp
+    import torch
+    from paper_1902_01715_amd import aspamg
+    print("[case permuted cube 41^3]", flush=True)
+    p = PR.c1_cube(41)                         # 74,088 nodes
+    rp, ci, v, V0, f, K = _permuted(p, 5)
+    S = aspamg.Solver(rp, ci, v, V0)
+    li = S.level_info(0)
+    # randomly numbered rows: a slice spans more than 65,536 columns
+    assert not li["sell_index16"] & 1 and not li["sell_index16"] & (1 << 5)
+    n, nc = li["n"], li["n_coarse"]
+    r2, c2, v2 = S.level_matrix(0, 0)
+    A = sp.bsr_matrix((v2, c2, r2), shape=(3 * n, 3 * n)).tocsr()
+    r2, c2, v2 = S.level_matrix(0, 1)
+    G = sp.bsr_matrix((v2, c2, r2), shape=(3 * n, 3 * n)).tocsr()
+    r2, c2, v2 = S.level_matrix(0, 3)
+    P = sp.bsr_matrix((v2, c2, r2), shape=(3 * n, 3 * nc)).tocsr()
+    ops = [A, G, G.T.tocsr(), P, P.T.tocsr()]
+    rng = np.random.default_rng(2)
+    for prec in (64, 32):
+        for which, M in enumerate(ops):
+            x = rng.standard_normal(M.shape[1])
+            y = S.apply(0, which, torch.tensor(x, device="cuda"), precision=prec, out_rows=M.shape[0]).cpu().numpy()
+            tol = 1e-14 if prec == 64 else 3e-7
+            assert np.all(np.abs(y - M @ x) <= tol * (abs(M) @ np.abs(x)) + 1e-300), (which, prec)
+    u = S.solve(torch.tensor(f, device="cuda")).cpu().numpy()
+    assert S.last_stats["status"] == 0
+    assert np.linalg.norm(f - K @ u) <= 2e-10 * np.linalg.norm(f)
+    S.close()
