@@ -465,14 +465,14 @@ static void pcg_iteration(aspamg_ctx *h, bool fp32) {
   double *pq_part = h->part, *rr_part = h->part + kMaxPart, *rz_part = h->part + 3 * kMaxPart;
   launch_spmv_dot(L0.A64, h->vp, h->vq, pq_part, c, s);
   if (fp32) {
-    launch_pcg_update<float>(n, h->vu, h->vr, h->vp, h->vq, h->vz, pq_part, spmv_blocks(h->n), rr_part, L0.v32.y, c,
-                             s);
+    launch_pcg_update<float>(n, h->vu, h->vr, h->vp, h->vq, h->vz, pq_part, spmv_dot_blocks(L0.A64), rr_part,
+                             L0.v32.y, c, s);
     launch_finish(kFinRr, rr_part, vec_blocks(n), c, s);
     cycle_level<float>(h, 0, L0.v32.y, L0.v32.z, c);
     launch_pcg_rz<float>(n, h->vr, L0.v32.z, h->vz, rz_part, c, s);
   } else {
-    launch_pcg_update<double>(n, h->vu, h->vr, h->vp, h->vq, h->vz, pq_part, spmv_blocks(h->n), rr_part, nullptr, c,
-                              s);
+    launch_pcg_update<double>(n, h->vu, h->vr, h->vp, h->vq, h->vz, pq_part, spmv_dot_blocks(L0.A64), rr_part,
+                              nullptr, c, s);
     launch_finish(kFinRr, rr_part, vec_blocks(n), c, s);
     cycle_level<double>(h, 0, h->vr, h->vz, c);
     launch_pcg_rz<double>(n, h->vr, h->vz, h->vz, rz_part, c, s);

@@ -15,6 +15,18 @@ namespace aspamg {
 constexpr int kSell = 64;           // rows per SELL slice = one wavefront
 constexpr int64_t kMinThreads = 262144;  // lanes per row grow until n * L reaches this
 constexpr int64_t kTimedSlots = 1 << 20;  // layouts of larger operators are chosen by timing
+// q = K p: lanes per row of the fine-level FP64 copy and workgroup size (one
+// p.q partial per workgroup, each re-read by every block of the update
+// kernel).  Measured on the cantilever: 4 lanes make the product 3% faster,
+// but the 4x partial count costs the update kernel more than that.
+#ifndef ASPAMG_KP_LANES
+#define ASPAMG_KP_LANES 1
+#endif
+#ifndef ASPAMG_DOT_THREADS
+#define ASPAMG_DOT_THREADS 256
+#endif
+constexpr int kKpLanes = ASPAMG_KP_LANES;
+constexpr int kDotThreads = ASPAMG_DOT_THREADS;
 constexpr int kMaxFsaiNodes = 32;   // off-diagonal nodes an FSAI row may hold
 constexpr int kMaxPEntries = 8;     // interpolation entries per scalar row (n_max cap)
 
@@ -194,6 +206,7 @@ void launch_spmv(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha
 template <typename T, typename TX, typename TO>
 void launch_spmv_dual(const Sell<T> &S, int32_t n1, const TX *x, TO *y1, const TO *w1, double a1, TO *y2,
                       const TO *w2, double a2, const PcgCtrl *ctrl, hipStream_t s);
+int spmv_dot_blocks(const Sell<double> &A);   // partials written by launch_spmv_dot
 void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
                      hipStream_t s);
 template <typename TV>
@@ -215,7 +228,6 @@ void launch_pcg_pupdate(int64_t n, const double *z, double *p, const double *rz_
 enum FinishMode { kFinInitF = 0, kFinInitRz = 1, kFinAlpha = 2, kFinRr = 3, kFinBeta = 4, kFinNorm = 5 };
 void launch_finish(int mode, const double *part, int nparts, PcgCtrl *ctrl, hipStream_t s);
 int vec_blocks(int64_t n);
-int spmv_blocks(int32_t nrows);
 
 // ---- setup kernel launchers (kernels_setup.hip) ----
 // FSAI rows: for each listed block row I (rows[i]) with nodes pat[pat_ptr[i]..pat_ptr[i+1]),

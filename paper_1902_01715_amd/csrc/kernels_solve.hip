@@ -169,25 +169,47 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
 }
 
 // q = K p with the block partial of p.q (PCG, FP64).
-template <typename CI>
-__global__ void __launch_bounds__(256) k_sell_spmv_dot(int32_t n, const int32_t *__restrict__ sptr,
-                                                       const CI *__restrict__ col,
-                                                       const int32_t *__restrict__ cbase,
-                                                       const double *__restrict__ val,
-                                                       const double *__restrict__ x, double *__restrict__ y,
-                                                       double *__restrict__ part, const PcgCtrl *ctrl) {
-  __shared__ double sm[4];
+// Deterministic sum over an NT-thread block (NT = 256, 512 or 1024); the
+// result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum_n(double v, double *sm) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sm[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    constexpr int nw = NT / 64;
+    double h[nw / 4];
+    for (int q = 0; q < nw / 4; q++) h[q] = (sm[4 * q] + sm[4 * q + 1]) + (sm[4 * q + 2] + sm[4 * q + 3]);
+    for (int q = 0; q < nw / 4; q++) r += h[q];
+  }
+  __syncthreads();
+  return r;
+}
+
+// q = K p on the sliced layout with L lanes per row, and the p.q partial of
+// every kDotThreads-thread block.
+template <typename CI, int L>
+__global__ void __launch_bounds__(kDotThreads) k_sell_spmv_dot(int32_t n, const int32_t *__restrict__ sptr,
+                                                        const CI *__restrict__ col,
+                                                        const int32_t *__restrict__ cbase,
+                                                        const double *__restrict__ val,
+                                                        const double *__restrict__ x, double *__restrict__ y,
+                                                        double *__restrict__ part, const PcgCtrl *ctrl) {
+  __shared__ double sm[kDotThreads / 64];
   if (ctrl_done(ctrl)) return;
-  const int32_t q = xcd_block() * 256 + threadIdx.x;
+  const int32_t t = xcd_block() * kDotThreads + threadIdx.x;
+  const int32_t sl = t >> 6, e = t & 63;
+  const int32_t row = sl * (64 / L) + e / L;
   double d = 0.0;
-  if (q < n) {
-    const int32_t sl = q >> 6, lane = q & 63;
-    const int32_t row = q;
+  if (row < n) {                        // whole lane groups together
     const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
     const int32_t cb = sizeof(CI) == 2 ? cbase[sl] : 0;
     double a0 = 0, a1 = 0, a2 = 0;
-    const CI *cp = col + (size_t)g0 * 64 + lane;
-    const double *vp = val + (size_t)g0 * 576 + lane;
+    const CI *cp = col + (size_t)g0 * 64 + e;
+    const double *vp = val + (size_t)g0 * 576 + e;
 #pragma unroll 2
     for (int32_t g = g0; g < g1; ++g) {
       const int32_t c = (int32_t)ld_stream(cp) + cb;
@@ -198,14 +220,24 @@ __global__ void __launch_bounds__(256) k_sell_spmv_dot(int32_t n, const int32_t 
       cp += 64;
       vp += 576;
     }
-    double *yo = y + 3 * (size_t)row;
-    yo[0] = a0;
-    yo[1] = a1;
-    yo[2] = a2;
-    const double *xo = x + 3 * (size_t)row;
-    d = (xo[0] * a0 + xo[1] * a1) + xo[2] * a2;
+    if (L > 1) {
+#pragma unroll
+      for (int o = L / 2; o > 0; o >>= 1) {
+        a0 += __shfl_xor(a0, o, L);
+        a1 += __shfl_xor(a1, o, L);
+        a2 += __shfl_xor(a2, o, L);
+      }
+    }
+    if ((e & (L - 1)) == 0) {
+      double *yo = y + 3 * (size_t)row;
+      yo[0] = a0;
+      yo[1] = a1;
+      yo[2] = a2;
+      const double *xo = x + 3 * (size_t)row;
+      d = (xo[0] * a0 + xo[1] * a1) + xo[2] * a2;
+    }
   }
-  const double s = block_sum(d, sm);
+  const double s = block_sum_n<kDotThreads>(d, sm);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -408,7 +440,6 @@ int vec_blocks(int64_t n) {
   if (b < 1) b = 1;
   return (int)b;
 }
-int spmv_blocks(int32_t nrows) { return (nrows + 255) / 256; }
 
 template <typename T, typename TX, typename TO, bool HAS_W, int L, bool DUAL = false>
 static void launch_l(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
@@ -514,16 +545,32 @@ template void launch_spmv<double, double, double>(const Sell<double> &, const do
 template void launch_spmv<float, float, float>(const Sell<float> &, const float *, float *, const float *, double,
                                                const PcgCtrl *, hipStream_t);
 
+int spmv_dot_blocks(const Sell<double> &A) {
+  return (int)(((int64_t)A.nslices * 64 + kDotThreads - 1) / kDotThreads);
+}
+
+template <int L>
+static void launch_dot_l(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
+                         hipStream_t s) {
+  const dim3 grid((unsigned)spmv_dot_blocks(A));
+  if (A.col16)
+    hipLaunchKernelGGL((k_sell_spmv_dot<uint16_t, L>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col16, A.cbase, A.val, x,
+                       y, part, ctrl);
+  else
+    hipLaunchKernelGGL((k_sell_spmv_dot<int32_t, L>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col, nullptr, A.val, x, y,
+                       part, ctrl);
+}
+
 void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
                      hipStream_t s) {
-  // one lane per row (the fine-level operator is stored so)
-  if (A.pack || A.lanes != 1) fail(ASPAMG_EINVAL, "q = K p needs the sliced layout with one lane per row");
-  if (A.col16)
-    hipLaunchKernelGGL(k_sell_spmv_dot<uint16_t>, dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr, A.col16,
-                       A.cbase, A.val, x, y, part, ctrl);
-  else
-    hipLaunchKernelGGL(k_sell_spmv_dot<int32_t>, dim3(spmv_blocks(A.n)), dim3(256), 0, s, A.n, A.sptr, A.col, nullptr,
-                       A.val, x, y, part, ctrl);
+  if (A.pack) fail(ASPAMG_EINVAL, "q = K p needs the sliced layout");
+  if (spmv_dot_blocks(A) > kMaxPart) fail(ASPAMG_EINVAL, "q = K p: more partials than the reduction buffer holds");
+  switch (A.lanes) {
+    case 1: launch_dot_l<1>(A, x, y, part, ctrl, s); break;
+    case 2: launch_dot_l<2>(A, x, y, part, ctrl, s); break;
+    case 4: launch_dot_l<4>(A, x, y, part, ctrl, s); break;
+    default: fail(ASPAMG_EINVAL, "q = K p supports 1, 2 or 4 lanes per row");
+  }
 }
 
 template <typename TV>

@@ -985,7 +985,7 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     Level &L = h->lev[l];
     const int32_t N = L.A.n;
     L.dA = upload_bsr(h, L.A);
-    L.A64 = upload_sell<double>(h, L.A, l == 0 ? 1 : 0);   // the PCG product runs one lane per fine row
+    L.A64 = upload_sell<double>(h, L.A, l == 0 ? kKpLanes : 0);   // lanes per fine row of q = K p
     L.A32 = upload_sell<float>(h, L.A);
     clk.tick(l, "upload A");
     if ((int64_t)N * 3 <= p.coarse_max_dof || l == p.max_levels - 1 || l == 31 || ntv == 0) {

@@ -60,7 +60,7 @@ def test_all_operators_all_levels(c2, prec):
     p, S = c2
     rng = np.random.default_rng(1)
     li0 = S.level_info(0)
-    assert li0["sell_lanes64"][0] == 1       # q = K p runs one lane per row
+    assert li0["sell_lanes64"][0] == 1       # q = K p: sliced, one lane per row
     # the fine-level operators of the structured mesh span < 65,536 columns per
     # slice: all of them (FP64 and FP32) store 16-bit column offsets
     assert li0["sell_index16"] == (1 << 10) - 1
