@@ -381,7 +381,9 @@ DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M) {
 //   s += omega G^T G (y - A s)              (further pre-smoothing steps)
 //   r = y - A s ; r_c = R r ; h_c = cycle(r_c) ; s += P h_c
 //   s += omega G^T G (y - A s)              (nu2 post-smoothing steps)
-// The coarsest level applies A_L^{-1} from its Cholesky factor.
+// The first post-smoothing residual is formed as r - (A P) h_c, together with
+// s + P h_c, by one product with the stacked operator [P; A P].  The coarsest
+// level applies A_L^{-1} from its Cholesky factor.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Ops;
@@ -431,8 +433,8 @@ static void cycle_level(aspamg_ctx *h, int l, const T *y, T *z, const PcgCtrl *c
   launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
   launch_spmv<T, T, T>(O::R(L), W.r, Wn.y, nullptr, 1.0, ctrl, s);
   cycle_level<T>(h, l + 1, Wn.y, Wn.z, ctrl);
-  // first post-smoothing step (nu2 >= 1): z += P e and r = (y - A z_pre) - (A P) e in one
-  // stacked product (W.r still holds the pre-smoothing residual)
+  // first post-smoothing step (nu2 >= 1): z += P e and r = (y - A z_pre) - (A P) e
+  // in one stacked product (W.r still holds the pre-smoothing residual)
   launch_spmv_dual<T, T, T>(O::PAP(L), L.P.n, Wn.z, z, z, 1.0, W.r, W.r, -1.0, ctrl, s);
   for (int it = 0; it < h->p.nu2; it++) {
     if (it > 0) launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
@@ -519,9 +521,6 @@ static void compute_complexities(aspamg_ctx *h) {
   h->c_fs = sga > 0 ? sg / sga : 0.0;
 }
 
-// algorithmic HBM bytes of one V-cycle: every stored operator streamed once per
-// use (9 values + 4-byte column per block) plus 18 level-vector passes per
-// level, and the dense coarsest inverse
 // Algorithmic bytes: each stored block once per use (9 values plus its column
 // index, 4 or 2 bytes as stored), 18 vector passes per level, the dense
 // coarsest inverse; one PCG iteration adds q = K p and 14 FP64 vector passes.

@@ -1,12 +1,12 @@
 // Solve-phase kernels for gfx950: 3x3-block SpMV on the sliced and row-packed
-// layouts with fused epilogues,
-// the dense coarsest-level product, precision casts and the fused PCG vector
-// updates with deterministic two-pass reductions.
+// layouts with fused epilogues (axpy, the stacked [P; AP] product, the p.q
+// partial of the PCG product), the dense coarsest-level product, precision
+// casts and the PCG vector updates with deterministic reductions.
 //
 // All of this work is bound by HBM bandwidth (a 3x3 FP64 block is 18 flops per
-// 76 bytes), so the kernels stream each matrix exactly once with fully
-// coalesced 64-lane loads and keep per-row accumulators in registers.  Matrix
-// cores are not used.
+// 74 bytes with a 16-bit column offset), so the kernels stream each matrix
+// exactly once with fully coalesced 64-lane loads and keep per-row
+// accumulators in registers.  Matrix cores are not used.
 #include "internal.h"
 
 namespace aspamg {
@@ -44,7 +44,7 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
 
 // y[row] = alpha * (A x)[row] (+ w[row]) on the sliced layout with L lanes per
 // block row.  A wavefront owns one slice of 64/L rows; lane e = r*L + j streams
-// entry e of every slot group of the slice: 64 consecutive column indices,
+// entry e of every slot group of the slice: 64 consecutive column entries,
 // then 9 runs of 64 consecutive values.  The L partial sums of a row meet in a
 // butterfly and lane j = 0 writes the row.
 // With DUAL, rows r >= n1 write y2[r - n1] = alpha2 (A x)[r] + w2[r - n1].
