@@ -226,12 +226,12 @@ def main():
     ap.add_argument("--stream-ref", action="store_true",
                     help="only measure PyTorch's streaming rates on this device and exit")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
     if args.stream_ref:
         stream_reference()
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
 
     import numpy as np
     import torch
