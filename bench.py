@@ -181,7 +181,7 @@ def bench_adjoint(args, p, desc):
         "ms_per_step": (fw + bw) * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "config": args.config},
-        "forward_s": fw, "backward_s": bw, "euler_identity_rel_err": euler, "compliance": float(C),
+        "forward_s": fw, "backward_s": bw, "euler_identity_rel_err": euler, "compliance": float(C.detach()),
     }
 
 

@@ -352,6 +352,30 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
   free_sell(h, Q);
   return S;
 }
+// FP32 copy of S in the same layout: the index arrays are shared with S (so
+// the copy is never freed on its own), the values converted on the device.
+Sell<float> derive_fp32(aspamg_ctx *h, const Sell<double> &S) {
+  Sell<float> F;
+  F.n = S.n;
+  F.nc = S.nc;
+  F.nslices = S.nslices;
+  F.lanes = S.lanes;
+  F.pack = S.pack;
+  F.ngroups = S.ngroups;
+  F.nnzb = S.nnzb;
+  F.sptr = S.sptr;
+  F.col = S.col;
+  F.col16 = S.col16;
+  F.cbase = S.cbase;
+  F.meta = S.meta;
+  const int64_t nv = S.ngroups * 576;
+  F.val = dalloc<float>(h, (size_t)std::max<int64_t>(nv, 1));
+  if (nv > 0) launch_cast<double, float>(nv, S.val, F.val, nullptr, h->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return F;
+}
+
 template Sell<double> upload_sell<double>(aspamg_ctx *, const HostBSR &, int, bool);
 template Sell<float> upload_sell<float>(aspamg_ctx *, const HostBSR &, int, bool);
 template void free_sell<double>(aspamg_ctx *, Sell<double> &);

@@ -195,6 +195,8 @@ template <typename T>
 Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes = 0, bool timed = true);
 template <typename T>
 void free_sell(aspamg_ctx *h, Sell<T> &S);   // releases the device arrays of S
+// FP32 copy in the same layout, sharing S's index arrays (never freed on its own)
+Sell<float> derive_fp32(aspamg_ctx *h, const Sell<double> &S);
 DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M);
 
 // ---- solve-path kernel launchers (kernels_solve.hip) ----

@@ -424,12 +424,12 @@ void build_fsai(aspamg_ctx *h, Level &L) {
   clk.tick(-1, "fsai assemble");
   L.fsai_rounds = 0;
   for (;;) {
-    Sell<double> G = upload_sell<double>(h, L.G, 0, false);
-    Sell<double> GT = upload_sell<double>(h, transpose(L.G), 0, false);
+    // device copies of G and G^T (kept as the level's operators when the
+    // outer loop stops here)
+    L.G64 = upload_sell<double>(h, L.G);
+    L.GT64 = upload_sell<double>(h, transpose(L.G));
     clk.tick(-1, "fsai G upload");
-    L.lambda1 = lanczos_gagt(h, L, G, GT, p.lanczos_steps);
-    free_sell(h, G);
-    free_sell(h, GT);
+    L.lambda1 = lanczos_gagt(h, L, L.G64, L.GT64, p.lanczos_steps);
     clk.tick(-1, "lanczos");
     L.omega_q = 2.0 / L.lambda1;
     if (!p.outer_fsai) break;
@@ -444,7 +444,9 @@ void build_fsai(aspamg_ctx *h, Level &L) {
     std::vector<int32_t> rows;
     for (int32_t I = 0; I < n; I++)
       if (grew[I]) rows.push_back(I);
-    if (rows.empty()) break;
+    if (rows.empty()) break;            // G unchanged: its device copies stay
+    free_sell(h, L.G64);
+    free_sell(h, L.GT64);
     fsai_factor(h, L, F, rows);
     L.G = fsai_assemble(F);
     L.fsai_rounds++;
@@ -986,7 +988,7 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     const int32_t N = L.A.n;
     L.dA = upload_bsr(h, L.A);
     L.A64 = upload_sell<double>(h, L.A, l == 0 ? kKpLanes : 0);   // lanes per fine row of q = K p
-    L.A32 = upload_sell<float>(h, L.A);
+    L.A32 = derive_fp32(h, L.A64);
     clk.tick(l, "upload A");
     if ((int64_t)N * 3 <= p.coarse_max_dof || l == p.max_levels - 1 || l == 31 || ntv == 0) {
       L.coarsest = true;
@@ -1018,22 +1020,19 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     HostBSR Ac = galerkin(h, L, &AP);
     clk.tick(l, "Galerkin");
     // device operators of this level
-    L.G64 = upload_sell<double>(h, L.G);
-    L.G32 = upload_sell<float>(h, L.G);
-    HostBSR GT = transpose(L.G);
-    L.GT64 = upload_sell<double>(h, GT);
-    L.GT32 = upload_sell<float>(h, GT);
+    // (G64 and GT64 come from build_fsai); FP32 copies share the layouts
+    L.G32 = derive_fp32(h, L.G64);
+    L.GT32 = derive_fp32(h, L.GT64);
     L.P64 = upload_sell<double>(h, L.P);
-    L.P32 = upload_sell<float>(h, L.P);
-    HostBSR R = transpose(L.P);
-    L.R64 = upload_sell<double>(h, R);
-    L.R32 = upload_sell<float>(h, R);
+    L.P32 = derive_fp32(h, L.P64);
+    L.R64 = upload_sell<double>(h, transpose(L.P));
+    L.R32 = derive_fp32(h, L.R64);
     {
       L.nnzb_AP = AP.nnzb();
       HostBSR PAP = stack_rows(L.P, AP);
       AP = HostBSR();
       L.PAP64 = upload_sell<double>(h, PAP);
-      L.PAP32 = upload_sell<float>(h, PAP);
+      L.PAP32 = derive_fp32(h, L.PAP64);
     }
     clk.tick(l, "upload G P R");
     std::vector<double> Vc((size_t)nc * 3 * ntv);

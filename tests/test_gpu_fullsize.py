@@ -55,7 +55,7 @@ def test_sampled_fsai_rows_bit_exact(c2, oracle_lib):
 
 
 @pytest.mark.parametrize("prec", [64, 32])
-def test_all_operators_all_levels(c2, prec):
+def test_all_operators_all_levels(c2, prec, product_bound):
     import torch
     p, S = c2
     rng = np.random.default_rng(1)
@@ -81,9 +81,7 @@ def test_all_operators_all_levels(c2, prec):
             x = rng.standard_normal(M.shape[1])
             y_ref = M @ x
             y = S.apply(l, which, torch.tensor(x, device="cuda"), precision=prec, out_rows=M.shape[0]).cpu().numpy()
-            rowscale = abs(M) @ np.abs(x)
-            tol = 1e-14 if prec == 64 else 3e-7
-            assert np.all(np.abs(y - y_ref) <= tol * rowscale * 4 + 1e-300), (l, which, prec)
+            assert np.all(np.abs(y - y_ref) <= product_bound(M, x, prec)), (l, which, prec)
 
 
 def test_vcycle_matches_scipy_composition(c2):

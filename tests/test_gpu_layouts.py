@@ -22,7 +22,7 @@ def problem(oracle_lib):
 
 
 @pytest.mark.parametrize("form", list(POLICY))
-def test_forced_layout_operators_and_solve(cuda, problem, form):
+def test_forced_layout_operators_and_solve(cuda, problem, form, product_bound):
     import torch
     from paper_1902_01715_amd import aspamg
     p, H = problem
@@ -34,7 +34,7 @@ def test_forced_layout_operators_and_solve(cuda, problem, form):
         li = S.level_info(l)
         for prec, lanes in ((64, li["sell_lanes64"]), (32, li["sell_lanes32"])):
             for which in range(5):
-                fixed = l == 0 and which == 0 and prec == 64     # q = K p copy: sliced, one lane
+                fixed = l == 0 and which == 0     # q = K p copy (and its FP32 twin): sliced, one lane
                 if fixed:
                     assert lanes[which] == 1
                 elif form == "sliced":
@@ -47,9 +47,9 @@ def test_forced_layout_operators_and_solve(cuda, problem, form):
                 x = rng.standard_normal(M.shape[1])
                 y = S.apply(l, which, torch.tensor(x, device="cuda"), precision=prec,
                             out_rows=M.shape[0]).cpu().numpy()
-                scale = abs(M) @ np.abs(x)
-                tol = 1e-14 if prec == 64 else 3e-7
-                assert np.all(np.abs(y - M @ x) <= tol * scale + 1e-300), (l, which, prec)
+                # FP64: the oracle's matrices differ from the device's by setup rounding
+                bound = 1e-14 * (abs(M) @ np.abs(x)) + 1e-300 if prec == 64 else product_bound(M, x, 32)
+                assert np.all(np.abs(y - M @ x) <= bound), (l, which, prec)
     for prec in (64, 32):
         S.set_precision(prec)
         u = S.solve(torch.tensor(p.f, device="cuda"), check=False).cpu().numpy()
@@ -101,7 +101,7 @@ def _permuted(p, seed):
     return (Bp.indptr.astype(np.int32), Bp.indices.astype(np.int32), np.ascontiguousarray(Bp.data), V0, f, Bp.tocsr())
 
 
-def test_wide_column_spans_use_32bit_indices(cuda):
+def test_wide_column_spans_use_32bit_indices(cuda, product_bound):
     import scipy.sparse as sp
     import torch
     from paper_1902_01715_amd import aspamg
@@ -125,8 +125,7 @@ def test_wide_column_spans_use_32bit_indices(cuda):
         for which, M in enumerate(ops):
             x = rng.standard_normal(M.shape[1])
             y = S.apply(0, which, torch.tensor(x, device="cuda"), precision=prec, out_rows=M.shape[0]).cpu().numpy()
-            tol = 1e-14 if prec == 64 else 3e-7
-            assert np.all(np.abs(y - M @ x) <= tol * (abs(M) @ np.abs(x)) + 1e-300), (which, prec)
+            assert np.all(np.abs(y - M @ x) <= product_bound(M, x, prec)), (which, prec)
     u = S.solve(torch.tensor(f, device="cuda")).cpu().numpy()
     assert S.last_stats["status"] == 0
     assert np.linalg.norm(f - K @ u) <= 2e-10 * np.linalg.norm(f)

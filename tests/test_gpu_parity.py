@@ -119,7 +119,7 @@ def test_solve_matches_oracle(pair, prec):
 
 @pytest.mark.parametrize("which", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("prec", [64, 32])
-def test_operators_match_oracle(pair, which, prec):
+def test_operators_match_oracle(pair, which, prec, product_bound):
     import torch
     name, p, S, H = pair
     if H.nlev < 2:
@@ -132,6 +132,8 @@ def test_operators_match_oracle(pair, which, prec):
     x = rng.standard_normal(M.shape[1])
     y_ref = M @ x
     y = S.apply(l, which, torch.tensor(x, device="cuda"), precision=prec, out_rows=M.shape[0]).cpu().numpy()
-    scale = abs(M).max() * np.abs(x).max() * max(1, M.getnnz(axis=1).max())
-    tol = 1e-14 if prec == 64 else 2e-6
-    assert np.abs(y - y_ref).max() <= tol * scale
+    if prec == 64:     # the oracle's matrices differ from the device's by setup rounding
+        scale = abs(M).max() * np.abs(x).max() * max(1, M.getnnz(axis=1).max())
+        assert np.abs(y - y_ref).max() <= 1e-14 * scale
+    else:
+        assert np.all(np.abs(y - y_ref) <= product_bound(M, x, 32))
