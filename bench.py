@@ -321,7 +321,8 @@ def main():
         "kernels": {"residual_fp32_GBps": r32_b / (r32_ms * 1e-3) / 1e9,
                     "residual_fp64_GBps": r64_b / (r64_ms * 1e-3) / 1e9},
         "levels": [{k: li[k] for k in ("n", "n_coarse", "nnzb_A", "nnzb_G", "nnzb_P", "sell_slots_A", "sell_slots_G",
-                                      "sell_slots_GT", "sell_lanes64", "sell_lanes32", "omega_s", "fsai_rounds")}
+                                      "sell_slots_GT", "sell_lanes64", "sell_lanes32", "sell_stacked", "sell_index16",
+                                      "omega_s", "fsai_rounds")}
                    for li in levels],
         "roofline": {"bound": "hbm", "kernel": "k_sell_spmv_dot (q = K p, FP64, sliced ELL with one lane per row)",
                      "achieved": kp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kp_gbs / HBM_PEAK_GBS,

@@ -117,9 +117,12 @@ typedef struct {
    * wavefront */
   int32_t sell_lanes64[5], sell_lanes32[5];
   /* bit k (FP64 copy) and bit 5 + k (FP32 copy) set when operator k stores its
-   * columns as 16-bit offsets from a per-slice base */
+   * columns as 16-bit offsets from a per-slice base; bit 10 the same for the
+   * row-stacked [P; A P] operator of the coarse-grid correction */
   int32_t sell_index16;
-  int32_t reserved;
+  /* layout of the row-stacked [P; A P] operator (same encoding as sell_lanes64;
+   * its FP32 copy shares it); 0 on the coarsest level */
+  int32_t sell_stacked;
 } aspamg_level_info_t;
 
 /* Fill *out with the defaults.  out: caller-owned. */

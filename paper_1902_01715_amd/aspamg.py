@@ -61,7 +61,7 @@ class LevelInfo(C.Structure):
         ("lambda1", C.c_double), ("omega_q", C.c_double), ("omega_s", C.c_double),
         ("sell_slots_A", C.c_int64), ("sell_slots_G", C.c_int64), ("sell_slots_GT", C.c_int64),
         ("sell_lanes64", C.c_int32 * 5), ("sell_lanes32", C.c_int32 * 5),
-        ("sell_index16", C.c_int32), ("reserved", C.c_int32),
+        ("sell_index16", C.c_int32), ("sell_stacked", C.c_int32),
     ]
 
     def as_dict(self):

@@ -70,22 +70,50 @@ static std::vector<int32_t> sliced_ptr(const HostBSR &M, int L) {
   return sptr;
 }
 
+// Smallest and largest column of every row (-1, -1 for an empty row).
+static void row_spans(const HostBSR &M, std::vector<int32_t> &lo, std::vector<int32_t> &hi) {
+  lo.assign(M.n, -1);
+  hi.assign(M.n, -1);
+#pragma omp parallel for schedule(static)
+  for (int32_t r = 0; r < M.n; r++)
+    for (int64_t k = M.rp[r]; k < M.rp[r + 1]; k++) {
+      const int32_t c = M.ci[k];
+      if (lo[r] < 0 || c < lo[r]) lo[r] = c;
+      if (c > hi[r]) hi[r] = c;
+    }
+}
+
 // Row-packed layout with K slot groups per wavefront: rows in matrix order,
 // max(1, ceil(len/K)) lanes each, a new wavefront whenever a row does not fit.
-// Returns the first row of every wavefront (plus n at the end), or an empty
-// vector when a row needs more than 64 lanes.
-static std::vector<int32_t> packed_waves(const HostBSR &M, int K) {
+// When every row on its own spans at most 65,536 columns, a new wavefront also
+// starts where the next row would widen the wavefront's span beyond that, so
+// a jump in the column numbering (the seam of a row-stacked operator) does not
+// cost the whole operator its 16-bit column offsets.  Returns the first row of
+// every wavefront (plus n at the end), or an empty vector when a row needs
+// more than 64 lanes.
+static std::vector<int32_t> packed_waves(const HostBSR &M, int K, const std::vector<int32_t> &lo,
+                                         const std::vector<int32_t> &hi, bool span16) {
   std::vector<int32_t> w0;
   int used = 64;
+  int32_t wlo = INT32_MAX, whi = -1;
   for (int32_t r = 0; r < M.n; r++) {
     const int64_t len = M.rp[r + 1] - M.rp[r];
     const int64_t lr = std::max<int64_t>(1, (len + K - 1) / K);
     if (lr > 64) return {};
-    if (used + lr > 64) {
+    bool fresh = used + lr > 64;
+    if (!fresh && span16 && hi[r] >= 0 && whi >= 0)
+      fresh = (int64_t)std::max(whi, hi[r]) - std::min(wlo, lo[r]) > 65535;
+    if (fresh) {
       w0.push_back(r);
       used = 0;
+      wlo = INT32_MAX;
+      whi = -1;
     }
     used += (int)lr;
+    if (hi[r] >= 0) {
+      wlo = std::min(wlo, lo[r]);
+      whi = std::max(whi, hi[r]);
+    }
   }
   w0.push_back(M.n);
   return w0;
@@ -308,9 +336,12 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
   if (policy != 0) timed = false;
   int bestK = 0;
   int64_t best = 0;
-  std::vector<int32_t> bestw;
+  std::vector<int32_t> bestw, lo, hi;
+  row_spans(M, lo, hi);
+  bool span16 = true;
+  for (int32_t r = 0; r < M.n && span16; r++) span16 = hi[r] - lo[r] <= 65535;
   for (int K : {1, 2, 4, 8}) {
-    std::vector<int32_t> w0 = packed_waves(M, K);
+    std::vector<int32_t> w0 = packed_waves(M, K, lo, hi, span16);
     if (w0.empty()) continue;
     const int64_t sl = (int64_t)(w0.size() - 1) * 64 * K;
     if (!bestK || sl < best) {
@@ -481,7 +512,11 @@ static void precondition(aspamg_ctx *h, const double *r, double *z, const PcgCtr
 }
 
 // One PCG iteration (Section 4; beta in the Polak-Ribiere form
-// (r_{k+1}.z_{k+1} - r_{k+1}.z_k) / (r_k.z_k)).
+// (r_{k+1}.z_{k+1} - r_{k+1}.z_k) / (r_k.z_k)).  After convergence the kernels
+// that write u, r, p and the scalars are no-ops; the V-cycle kernels do not
+// read the flag (a dependent load at the head of each of their ~40 launches)
+// and recompute a z that no live kernel reads, for at most the rest of one
+// host polling window.
 static void pcg_iteration(aspamg_ctx *h, bool fp32) {
   hipStream_t s = h->stream;
   const int64_t n = (int64_t)h->n * 3;
@@ -494,13 +529,13 @@ static void pcg_iteration(aspamg_ctx *h, bool fp32) {
     launch_pcg_update<float>(n, h->vu, h->vr, h->vp, h->vq, h->vz, pq_part, spmv_dot_blocks(L0.A64), rr_part,
                              L0.v32.y, c, s);
     launch_finish(kFinRr, rr_part, vec_blocks(n), c, s);
-    cycle_level<float>(h, 0, L0.v32.y, L0.v32.z, c);
+    cycle_level<float>(h, 0, L0.v32.y, L0.v32.z, nullptr);
     launch_pcg_rz<float>(n, h->vr, L0.v32.z, h->vz, rz_part, c, s);
   } else {
     launch_pcg_update<double>(n, h->vu, h->vr, h->vp, h->vq, h->vz, pq_part, spmv_dot_blocks(L0.A64), rr_part,
                               nullptr, c, s);
     launch_finish(kFinRr, rr_part, vec_blocks(n), c, s);
-    cycle_level<double>(h, 0, h->vr, h->vz, c);
+    cycle_level<double>(h, 0, h->vr, h->vz, nullptr);
     launch_pcg_rz<double>(n, h->vr, h->vz, h->vz, rz_part, c, s);
   }
   launch_pcg_pupdate(n, h->vz, h->vp, rz_part, vec_blocks(n), c, s);
@@ -918,13 +953,14 @@ aspamg_status aspamg_level_info(aspamg_handle h, int32_t level, aspamg_level_inf
   const Sell<double> *M64[5] = {&L.A64, &L.G64, &L.GT64, &L.P64, &L.R64};
   const Sell<float> *M32[5] = {&L.A32, &L.G32, &L.GT32, &L.P32, &L.R32};
   o->sell_index16 = 0;
-  o->reserved = 0;
   for (int k = 0; k < 5; k++) {
     o->sell_lanes64[k] = M64[k]->pack ? -M64[k]->pack : M64[k]->lanes;
     o->sell_lanes32[k] = M32[k]->pack ? -M32[k]->pack : M32[k]->lanes;
     if (M64[k]->col16) o->sell_index16 |= 1 << k;
     if (M32[k]->col16) o->sell_index16 |= 1 << (5 + k);
   }
+  o->sell_stacked = L.PAP64.pack ? -L.PAP64.pack : L.PAP64.lanes;
+  if (L.PAP64.col16) o->sell_index16 |= 1 << 10;
   return ASPAMG_OK;
 }
 

@@ -32,6 +32,9 @@ def test_forced_layout_operators_and_solve(cuda, problem, form, product_bound):
     rng = np.random.default_rng(11)
     for l in range(H.nlev - 1):
         li = S.level_info(l)
+        assert (li["sell_stacked"] > 0) == (form == "sliced")
+        if form == "packed":    # the seam between P and A P starts a wavefront
+            assert li["sell_index16"] & (1 << 10)
         for prec, lanes in ((64, li["sell_lanes64"]), (32, li["sell_lanes32"])):
             for which in range(5):
                 fixed = l == 0 and which == 0     # q = K p copy (and its FP32 twin): sliced, one lane
@@ -75,7 +78,8 @@ def test_slot_policy_is_reproducible(cuda, problem):
     outs, lays = [], []
     for _ in range(2):
         S = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, aspamg.default_params(layout=1))
-        lays.append([(S.level_info(l)["sell_lanes64"], S.level_info(l)["sell_lanes32"]) for l in range(S.nlev)])
+        lays.append([(S.level_info(l)["sell_lanes64"], S.level_info(l)["sell_lanes32"], S.level_info(l)["sell_stacked"])
+                     for l in range(S.nlev)])
         S.set_precision(32)
         outs.append(S.solve(torch.tensor(p.f, device="cuda"), check=False).cpu().numpy())
         S.close()
