@@ -136,10 +136,14 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
       a2 += ld_stream(v + 384) * x0 + ld_stream(v + 448) * x1 + ld_stream(v + 512) * x2;
     }
   }
+  // the lanes of a row never leave their wavefront, whose LDS operations
+  // complete in order: a wavefront-scope barrier suffices
   part[0][threadIdx.x] = a0;
   part[1][threadIdx.x] = a1;
   part[2][threadIdx.x] = a2;
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int cnt = (int)(m >> 8);
   if (!live || cnt == 0) return;
   T s0 = 0, s1 = 0, s2 = 0;
