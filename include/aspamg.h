@@ -83,7 +83,12 @@ typedef struct {
                            *       operator of q = K p is sliced with one lane per row in
                            *       every case.  Results do not depend on the layout beyond
                            *       the order of floating-point sums within a row. */
-  int32_t reserved;       /* 0                                                          */
+  int32_t dense_tail_dof; /* 4096  the V-cycle from the highest level whose unknowns, and
+                           *       those of every level below it, number at most this
+                           *       (above the coarsest) is formed at setup as one dense FP64
+                           *       operator and applied as one product; 0 keeps every level
+                           *       sparse.  At most 8192.  The operator is the same; only the
+                           *       rounding differs. */
 } aspamg_params;
 
 typedef struct {
@@ -99,7 +104,7 @@ typedef struct {
   double  bytes_vcycle;     /* algorithmic HBM bytes of one V-cycle                   */
   double  bytes_iter;       /* algorithmic HBM bytes of one PCG iteration             */
   int32_t spmm_tile;        /* right-hand sides per SpMM tile (solve_batch), else 0   */
-  int32_t reserved;
+  int32_t tail_level;       /* level applied as the dense tail operator, -1 if none   */
 } aspamg_stats;
 
 /* Per-level summary, see aspamg_level_info. */

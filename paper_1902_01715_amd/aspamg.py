@@ -37,7 +37,7 @@ class Params(C.Structure):
         ("coarse_max_dof", C.c_int32), ("max_levels", C.c_int32), ("stall_ratio", C.c_double),
         ("nu1", C.c_int32), ("nu2", C.c_int32), ("cycle_precision", C.c_int32), ("rtol", C.c_double),
         ("max_it", C.c_int32), ("quant_bits", C.c_int32), ("dense_max_dof", C.c_int32),
-        ("check_every", C.c_int32), ("use_graph", C.c_int32), ("layout", C.c_int32), ("reserved", C.c_int32),
+        ("check_every", C.c_int32), ("use_graph", C.c_int32), ("layout", C.c_int32), ("dense_tail_dof", C.c_int32),
     ]
 
 
@@ -47,7 +47,7 @@ class Stats(C.Structure):
         ("relres_recursive", C.c_double), ("relres_true", C.c_double), ("t_setup_s", C.c_double),
         ("t_solve_s", C.c_double), ("c_gd", C.c_double), ("c_op", C.c_double), ("c_fs", C.c_double),
         ("bytes_vcycle", C.c_double), ("bytes_iter", C.c_double), ("spmm_tile", C.c_int32),
-        ("reserved", C.c_int32),
+        ("tail_level", C.c_int32),
     ]
 
     def as_dict(self):

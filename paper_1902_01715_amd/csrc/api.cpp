@@ -467,6 +467,10 @@ template <typename T>
 static void cycle_level(aspamg_ctx *h, int l, const T *y, T *z, const PcgCtrl *ctrl) {
   const Level &L = h->lev[l];
   hipStream_t s = h->stream;
+  if (l == h->tail.level) {
+    launch_dense_gemv<T>(h->tail.nd, h->tail.v, y, z, ctrl, s);
+    return;
+  }
   if (L.coarsest) {
     launch_dense_gemv<T>(h->coarse.nd, h->coarse.inv, y, z, ctrl, s);
     return;
@@ -496,6 +500,96 @@ static void cycle_level(aspamg_ctx *h, int l, const T *y, T *z, const PcgCtrl *c
     launch_spmv<T, T, T>(O::G(L), W.r, W.t, nullptr, 1.0, ctrl, s);
     launch_spmv<T, T, T>(O::GT(L), W.t, z, z, w, ctrl, s);
   }
+}
+
+// The same cycle in FP64 on the nb columns of a row-major multi-vector
+// ([3 n_l][nb]), with plain block-CSR products: forms the dense tail operator.
+struct ColumnLevel {
+  DevBSR A, G, GT, P, R;
+  double *y = nullptr, *z = nullptr, *r = nullptr, *t = nullptr;
+};
+
+static void cycle_columns(aspamg_ctx *h, std::vector<ColumnLevel> &C, int l0, int l, const double *y, double *z,
+                          int32_t nb) {
+  const Level &L = h->lev[l];
+  hipStream_t s = h->stream;
+  if (L.coarsest) {
+    launch_dense_mm(h->coarse.nd, h->coarse.inv, y, z, nb, s);
+    return;
+  }
+  ColumnLevel &W = C[l - l0], &Wn = C[l + 1 - l0];
+  const double w = L.omega_s;
+  for (int it = 0; it < h->p.nu1; it++) {
+    if (it == 0) {
+      launch_bsr_mm(W.G, y, W.t, nullptr, 1.0, nb, s);
+      launch_bsr_mm(W.GT, W.t, z, nullptr, w, nb, s);
+    } else {
+      launch_bsr_mm(W.A, z, W.r, y, -1.0, nb, s);
+      launch_bsr_mm(W.G, W.r, W.t, nullptr, 1.0, nb, s);
+      launch_bsr_mm(W.GT, W.t, z, z, w, nb, s);
+    }
+  }
+  launch_bsr_mm(W.A, z, W.r, y, -1.0, nb, s);
+  launch_bsr_mm(W.R, W.r, Wn.y, nullptr, 1.0, nb, s);
+  cycle_columns(h, C, l0, l + 1, Wn.y, Wn.z, nb);
+  launch_bsr_mm(W.P, Wn.z, z, z, 1.0, nb, s);
+  for (int it = 0; it < h->p.nu2; it++) {
+    launch_bsr_mm(W.A, z, W.r, y, -1.0, nb, s);
+    launch_bsr_mm(W.G, W.r, W.t, nullptr, 1.0, nb, s);
+    launch_bsr_mm(W.GT, W.t, z, z, w, nb, s);
+  }
+}
+
+// Dense tail: the highest level t above the coarsest such that every level
+// from t down has at most dense_tail_dof unknowns.  Its cycle maps y to z
+// linearly; applying it to the columns of the identity gives that operator's
+// columns, stored row by row (column c of the result is V e_c, so row r of
+// the row-major result is row r of V).  The cycle then reads one dense FP64
+// matrix at level t in place of the launches of levels t and below, each of
+// which costs a dependent round trip on these small levels.
+static void build_tail(aspamg_ctx *h) {
+  const int lc = (int)h->lev.size() - 1;
+  if (h->p.dense_tail_dof <= 0 || lc < 1) return;
+  int t = lc;
+  while (t > 0 && 3 * (int64_t)h->lev[t - 1].A.n <= h->p.dense_tail_dof) t--;
+  if (t == lc) return;
+  const int32_t nd = 3 * h->lev[t].A.n;
+  std::vector<ColumnLevel> C(lc - t + 1);
+  std::vector<void *> tmp;
+  auto vec = [&](int32_t rows) {
+    double *p = dalloc<double>(h, (size_t)rows * nd);
+    tmp.push_back(p);
+    return p;
+  };
+  auto keep = [&](const DevBSR &d) {
+    tmp.push_back(d.rp);
+    tmp.push_back(d.ci);
+    tmp.push_back(d.v);
+  };
+  for (int l = t; l <= lc; l++) {
+    const Level &L = h->lev[l];
+    ColumnLevel &W = C[l - t];
+    const int32_t rows = 3 * L.A.n;
+    W.y = vec(rows);
+    W.z = vec(rows);
+    if (L.coarsest) continue;
+    W.r = vec(rows);
+    W.t = vec(rows);
+    W.A = upload_bsr(h, L.A);
+    W.G = upload_bsr(h, L.G);
+    W.GT = upload_bsr(h, transpose(L.G));
+    W.P = upload_bsr(h, L.P);
+    W.R = upload_bsr(h, transpose(L.P));
+    for (const DevBSR *d : {&W.A, &W.G, &W.GT, &W.P, &W.R}) keep(*d);
+  }
+  h->tail.v = dalloc<double>(h, (size_t)nd * nd);
+  launch_eye(nd, C[0].y, h->stream);
+  cycle_columns(h, C, t, t, C[0].y, h->tail.v, nd);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (void *p : tmp) dfree(h, p);
+  h->tail.level = t;
+  h->tail.nd = nd;
 }
 
 // z = M^{-1} r for FP64 vectors r, z of the fine level
@@ -604,7 +698,13 @@ static double level_bytes(const aspamg_ctx *h, const Level &L) {
 
 static double cycle_bytes(const aspamg_ctx *h, int prec) {
   double B = 0.0;
-  for (const auto &L : h->lev) {
+  for (int l = 0; l < (int)h->lev.size(); l++) {
+    const Level &L = h->lev[l];
+    if (l == h->tail.level) {
+      const double nd = h->tail.nd;
+      B += nd * nd * 8.0 + 2.0 * nd * (prec == 32 ? 4.0 : 8.0);
+      break;
+    }
     if (L.coarsest) B += (double)h->coarse.nd * h->coarse.nd * 8.0;
     else B += prec == 32 ? level_bytes<float>(h, L) : level_bytes<double>(h, L);
   }
@@ -647,7 +747,7 @@ static void check_params(const aspamg_params &p) {
       p.lanczos_steps < 1 || p.lanczos_steps > 200 || p.nu1 < 1 || p.nu2 < 1 || p.max_levels < 1 ||
       (p.cycle_precision != 32 && p.cycle_precision != 64) || !(p.rtol >= 0) || p.max_it < 1 ||
       p.quant_bits < 8 || p.quant_bits > 52 || p.check_every < 1 || p.n_tv < 0 || p.n_tv > 64 ||
-      p.layout < 0 || p.layout > 3 ||
+      p.layout < 0 || p.layout > 3 || p.dense_tail_dof < 0 || p.dense_tail_dof > kMaxTailDof ||
       !(p.kappa_p > 0) || !(p.omega_safety > 0))
     fail(ASPAMG_EINVAL, "invalid parameter value");
 }
@@ -707,7 +807,7 @@ aspamg_status aspamg_default_params(aspamg_params *o) {
   o->check_every = 4;
   o->use_graph = 1;
   o->layout = 0;
-  o->reserved = 0;
+  o->dense_tail_dof = 4096;
   return ASPAMG_OK;
 }
 
@@ -775,6 +875,7 @@ static aspamg_status setup_impl(const aspamg_params *pp, int32_t n_nodes, int64_
   std::vector<double> V = n_tv ? fetch(V0, (size_t)n_nodes * 3 * n_tv, h->stream) : std::vector<double>();
   build_hierarchy(h.get(), std::move(A), std::move(V));
   alloc_level_vectors(h.get());
+  build_tail(h.get());
   compute_complexities(h.get());
   h->prec = p.cycle_precision;
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -819,6 +920,7 @@ static void fill_stats(aspamg_handle h, aspamg_stats *st, const PcgCtrl &c, doub
   st->c_fs = h->c_fs;
   st->bytes_vcycle = cycle_bytes(h, h->prec);
   st->bytes_iter = iter_bytes(h, h->prec);
+  st->tail_level = h->tail.level;
 }
 
 aspamg_status aspamg_solve(aspamg_handle h, const double *f_dev, double *u_dev, aspamg_stats *st) {

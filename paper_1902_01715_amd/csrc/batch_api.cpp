@@ -118,6 +118,10 @@ static void cycle_batch(aspamg_ctx *h, BatchWork *w, int l, const T *y, T *z, in
   hipStream_t s = h->stream;
   const int ld = w->kpad;
   const Level &L = h->lev[l];
+  if (l == h->tail.level) {
+    launch_dense_gemm<T>(h->tail.nd, h->tail.v, y, z, ld, c, s);
+    return;
+  }
   if (L.coarsest) {
     launch_dense_gemm<T>(h->coarse.nd, h->coarse.inv, y, z, ld, c, s);
     return;
@@ -306,6 +310,7 @@ static aspamg_status solve_chunk(aspamg_ctx *h, int k, const double *F, int64_t 
       o.c_gd = h->c_gd;
       o.c_op = h->c_op;
       o.c_fs = h->c_fs;
+      o.tail_level = h->tail.level;
     }
   }
   return worst;

@@ -141,6 +141,15 @@ struct Coarse {
   double *inv = nullptr;     // device nd x nd row-major
 };
 
+// Dense tail: the V-cycle from `level` down (its smoothing, transfers and the
+// coarsest solve), a fixed linear operator, formed once as a dense nd x nd
+// row-major FP64 matrix and applied as one product.  level = -1: none.
+struct DenseTail {
+  int32_t level = -1;
+  int32_t nd = 0;
+  double *v = nullptr;
+};
+
 struct BatchWork;  // multi-RHS buffers (solve_batch)
 
 }  // namespace aspamg
@@ -152,6 +161,7 @@ struct aspamg_ctx {
   int32_t n = 0;                              // fine block rows
   std::vector<aspamg::Level> lev;
   aspamg::Coarse coarse;
+  aspamg::DenseTail tail;
   int32_t prec = 64;
   // PCG vectors (FP64) and control
   double *vu = nullptr, *vr = nullptr, *vp = nullptr, *vq = nullptr, *vz = nullptr;
@@ -183,6 +193,7 @@ struct aspamg_assembler_ctx {
 namespace aspamg {
 
 constexpr int kMaxPart = 8192;      // reduction partial slots per buffer
+constexpr int kMaxTailDof = 8192;   // largest dense tail operator (512 MB in FP64)
 
 // ---- device memory helpers (tracked by the handle) ----
 void *dmalloc(aspamg_ctx *h, size_t bytes);
@@ -244,6 +255,11 @@ void launch_dpls_weights(int32_t nrows, const int32_t *row, const int32_t *cnt, 
 // RAP numeric phases
 void launch_spgemm_ap(const DevBSR &A, const DevBSR &P, const DevBSR &T, hipStream_t s);
 void launch_spgemm_rt(const DevBSR &R, const DevBSR &T, const DevBSR &Ac, hipStream_t s);
+// setup-only products on row-major multi-vectors with nb columns (the dense tail operator)
+void launch_bsr_mm(const DevBSR &M, const double *X, double *Y, const double *W, double alpha, int32_t nb,
+                   hipStream_t s);
+void launch_dense_mm(int32_t nd, const double *D, const double *X, double *Y, int32_t nb, hipStream_t s);
+void launch_eye(int32_t nd, double *X, hipStream_t s);
 void launch_element_gradient(int64_t n_el, const int32_t *conn, const double *Ke0, int64_t ke_stride,
                              const double *lam, const double *u, const double *scale, double *grad,
                              hipStream_t s);

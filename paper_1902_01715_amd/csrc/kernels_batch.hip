@@ -113,7 +113,10 @@ __global__ void __launch_bounds__(256) k_bsr_spmm(int32_t n, const int32_t *__re
   }
 }
 
-// Z = Ainv Y for the dense coarsest operator, one thread per (row, column).
+// Z = D Y for a dense row-major FP64 operator (the coarsest inverse or the
+// dense tail), one thread per (row, column); the 256 / ld rows of a block share
+// Y through the cache.  Four independent partial sums keep four loads of D and
+// Y in flight per thread instead of one dependent chain of nd.
 template <typename T>
 __global__ void __launch_bounds__(256) k_dense_gemm(int32_t nd, const double *__restrict__ inv,
                                                     const T *__restrict__ Y, T *__restrict__ Z, int32_t ld,
@@ -123,9 +126,17 @@ __global__ void __launch_bounds__(256) k_dense_gemm(int32_t nd, const double *__
   const int32_t row = t / ld, j = t % ld;
   if (row >= nd) return;
   const double *a = inv + (size_t)row * nd;
-  double s = 0.0;
-  for (int32_t i = 0; i < nd; i++) s += a[i] * (double)Y[(size_t)i * ld + j];
-  Z[(size_t)row * ld + j] = (T)s;
+  const T *y = Y + j;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int32_t i = 0;
+  for (; i + 3 < nd; i += 4) {
+    s0 += a[i] * (double)y[(size_t)i * ld];
+    s1 += a[i + 1] * (double)y[(size_t)(i + 1) * ld];
+    s2 += a[i + 2] * (double)y[(size_t)(i + 2) * ld];
+    s3 += a[i + 3] * (double)y[(size_t)(i + 3) * ld];
+  }
+  for (; i < nd; i++) s0 += a[i] * (double)y[(size_t)i * ld];
+  Z[(size_t)row * ld + j] = (T)((s0 + s1) + (s2 + s3));
 }
 
 // Column-wise vector kernels: a 256-thread block is (256/ld) dof rows x ld

@@ -289,7 +289,68 @@ __global__ void __launch_bounds__(256) k_assemble(int64_t nnzb, const int64_t *_
   for (int k = 0; k < 9; k++) vals[s * 9 + k] = acc[k];
 }
 
+// Y = alpha (M X) + W for a block-sparse M (row-major 3x3 blocks, block CSR)
+// and row-major multi-vectors with nb columns ([3 rows][nb]); one thread per
+// block row and column, blocks summed in stored order.  W may alias Y.
+__global__ void __launch_bounds__(256) k_bsr_mm(int32_t n, const int32_t *__restrict__ rp,
+                                                const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                const double *__restrict__ X, double *Y, const double *W,
+                                                double alpha, int32_t nb) {
+  const int32_t c = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+  if (c >= nb || i >= n) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+    const double *b = v + (size_t)k * 9;
+    const double *xj = X + (size_t)3 * ci[k] * nb + c;
+    const double x0 = xj[0], x1 = xj[nb], x2 = xj[2 * (size_t)nb];
+    a0 += b[0] * x0 + b[1] * x1 + b[2] * x2;
+    a1 += b[3] * x0 + b[4] * x1 + b[5] * x2;
+    a2 += b[6] * x0 + b[7] * x1 + b[8] * x2;
+  }
+  double *yi = Y + (size_t)3 * i * nb + c;
+  const double *wi = W ? W + (size_t)3 * i * nb + c : nullptr;
+  yi[0] = alpha * a0 + (wi ? wi[0] : 0.0);
+  yi[nb] = alpha * a1 + (wi ? wi[nb] : 0.0);
+  yi[2 * (size_t)nb] = alpha * a2 + (wi ? wi[2 * (size_t)nb] : 0.0);
+}
+
+// Y = D X for a dense row-major nd x nd matrix D and [nd][nb] multi-vectors.
+__global__ void __launch_bounds__(256) k_dense_mm(int32_t nd, const double *__restrict__ D,
+                                                  const double *__restrict__ X, double *__restrict__ Y, int32_t nb) {
+  const int32_t c = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
+  if (c >= nb || r >= nd) return;
+  const double *d = D + (size_t)r * nd;
+  double a = 0.0;
+  for (int32_t k = 0; k < nd; k++) a += d[k] * X[(size_t)k * nb + c];
+  Y[(size_t)r * nb + c] = a;
+}
+
+// X = the nd x nd identity, row-major
+__global__ void __launch_bounds__(256) k_eye(int64_t nd, double *__restrict__ X) {
+  const int64_t n = nd * nd;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    X[i] = (i / nd == i % nd) ? 1.0 : 0.0;
+}
+
 }  // namespace
+
+void launch_bsr_mm(const DevBSR &M, const double *X, double *Y, const double *W, double alpha, int32_t nb,
+                   hipStream_t s) {
+  if (M.n == 0 || nb == 0) return;
+  hipLaunchKernelGGL(k_bsr_mm, dim3((unsigned)((nb + 255) / 256), (unsigned)M.n), dim3(256), 0, s, M.n, M.rp, M.ci,
+                     M.v, X, Y, W, alpha, nb);
+}
+
+void launch_dense_mm(int32_t nd, const double *D, const double *X, double *Y, int32_t nb, hipStream_t s) {
+  if (nd == 0 || nb == 0) return;
+  hipLaunchKernelGGL(k_dense_mm, dim3((unsigned)((nb + 255) / 256), (unsigned)nd), dim3(256), 0, s, nd, D, X, Y, nb);
+}
+
+void launch_eye(int32_t nd, double *X, hipStream_t s) {
+  const int64_t n = (int64_t)nd * nd;
+  const int64_t b = std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096);
+  hipLaunchKernelGGL(k_eye, dim3((unsigned)b), dim3(256), 0, s, (int64_t)nd, X);
+}
 
 int launch_fsai_rows(const DevBSR &A, int32_t nrows, const int32_t *rows, const int32_t *pat_ptr,
                      const int32_t *pat_nodes, int mmax, double *g, double *psi, int32_t *fail_flag,

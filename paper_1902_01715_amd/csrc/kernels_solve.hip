@@ -245,7 +245,10 @@ __global__ void __launch_bounds__(kDotThreads) k_sell_spmv_dot(int32_t n, const 
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// z = Ainv y for the dense coarsest operator: one wavefront per row.
+// z = D y for a dense row-major FP64 operator (the coarsest inverse, or the
+// dense tail of the V-cycle): one wavefront per row, four independent partial
+// sums per lane so that four 512-byte row segments are in flight, the matrix
+// streamed past the caches (y stays resident).
 template <typename TV>
 __global__ void __launch_bounds__(256) k_dense_gemv(int32_t nd, const double *__restrict__ inv,
                                                     const TV *__restrict__ y, TV *__restrict__ z,
@@ -255,8 +258,16 @@ __global__ void __launch_bounds__(256) k_dense_gemv(int32_t nd, const double *__
   const int lane = threadIdx.x & 63;
   if (row >= nd) return;
   const double *a = inv + (size_t)row * nd;
-  double s = 0.0;
-  for (int32_t j = lane; j < nd; j += 64) s += a[j] * (double)y[j];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int32_t j = lane;
+  for (; j + 192 < nd; j += 256) {
+    s0 += ld_stream(a + j) * (double)y[j];
+    s1 += ld_stream(a + j + 64) * (double)y[j + 64];
+    s2 += ld_stream(a + j + 128) * (double)y[j + 128];
+    s3 += ld_stream(a + j + 192) * (double)y[j + 192];
+  }
+  for (; j < nd; j += 64) s0 += ld_stream(a + j) * (double)y[j];
+  double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (lane == 0) z[row] = (TV)s;

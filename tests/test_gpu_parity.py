@@ -33,12 +33,16 @@ CASES = {
 }
 
 
-@pytest.fixture(scope="module", params=list(CASES))
+# every case with all levels sparse, and with the V-cycle's small levels
+# folded into the dense tail operator (the default)
+@pytest.fixture(scope="module", params=[(c, t) for c in CASES for t in ("sparse", "tail")],
+                ids=lambda ct: f"{ct[0]}-{ct[1]}")
 def pair(request, cuda, oracle_lib):
-    print(f"[case {request.param}]", flush=True)
-    p = CASES[request.param]()
-    S, H = _setup(p, cuda, oracle_lib)
-    yield request.param, p, S, H
+    name, tail = request.param
+    print(f"[case {name} {tail}]", flush=True)
+    p = CASES[name]()
+    S, H = _setup(p, cuda, oracle_lib, **({"dense_tail_dof": 0} if tail == "sparse" else {}))
+    yield name, p, S, H
     S.close()
 
 

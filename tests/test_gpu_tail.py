@@ -1,0 +1,106 @@
+"""The dense tail: the V-cycle from the highest level whose unknowns, and those
+of every level below it, number at most `dense_tail_dof` is formed at setup as
+one dense FP64 operator.  It is the same linear operator as the sparse cycle
+of those levels, so the V-cycle, the solve and the iteration counts must agree
+with the all-sparse cycle and the oracle up to rounding; the V-cycle stays
+symmetric (symmetric smoother, Galerkin coarse operators, nu1 = nu2)."""
+import numpy as np
+import pytest
+
+from paper_1902_01715_amd import problems as PR
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def layered(cuda, oracle_lib):
+    from paper_1902_01715_amd import aspamg
+    p = PR.c3_layered_distorted(32, 32, 16)   # 55,539 DOF, 4 levels
+    print("[case layered 32x32x16 tail/sparse]", flush=True)
+    St = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0)
+    Ss = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, aspamg.default_params(dense_tail_dof=0))
+    H = oracle_lib.Hierarchy(p.row_ptr, p.col, p.vals, p.V0)
+    yield p, St, Ss, H
+    St.close()
+    Ss.close()
+
+
+def _expected_tail(S, dof):
+    sizes = [3 * S.level_info(l)["n"] for l in range(S.nlev)]
+    t = S.nlev - 1
+    while t > 0 and sizes[t - 1] <= dof:
+        t -= 1
+    return -1 if t == S.nlev - 1 else t
+
+
+def test_tail_level(layered):
+    import torch
+    p, St, Ss, _ = layered
+    f = torch.tensor(p.f, device="cuda")
+    St.solve(f, check=False)
+    Ss.solve(f, check=False)
+    t = St.last_stats["tail_level"]
+    assert t == _expected_tail(St, 4096) and 0 < t < St.nlev - 1, t
+    assert Ss.last_stats["tail_level"] == -1
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_tail_cycle_matches_sparse_cycle(layered, prec):
+    import torch
+    p, St, Ss, H = layered
+    rng = np.random.default_rng(21)
+    y = rng.standard_normal(3 * St.level_info(0)["n"])
+    St.set_precision(prec)
+    Ss.set_precision(prec)
+    zt = St.vcycle(torch.tensor(y, device="cuda")).cpu().numpy()
+    zs = Ss.vcycle(torch.tensor(y, device="cuda")).cpu().numpy()
+    zo = H.vcycle(y)
+    d_ts = np.linalg.norm(zt - zs) / np.linalg.norm(zs)
+    d_to = np.linalg.norm(zt - zo) / np.linalg.norm(zo)
+    print(f"prec {prec}: tail vs sparse {d_ts:.2e}, tail vs oracle {d_to:.2e}", flush=True)
+    # FP64: both are the oracle's operator to rounding; FP32: the sparse cycle
+    # rounds levels t.. in FP32, the tail applies them in FP64
+    bar = 1e-11 if prec == 64 else 1e-4
+    assert d_ts <= bar and d_to <= bar
+    St.set_precision(64)
+    Ss.set_precision(64)
+
+
+def test_tail_cycle_is_symmetric(layered):
+    import torch
+    _, St, _, _ = layered
+    n = 3 * St.level_info(0)["n"]
+    rng = np.random.default_rng(5)
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    St.set_precision(64)
+    Bx = St.vcycle(torch.tensor(x, device="cuda")).cpu().numpy()
+    By = St.vcycle(torch.tensor(y, device="cuda")).cpu().numpy()
+    a, b = y @ Bx, x @ By
+    assert abs(a - b) <= 1e-11 * np.sqrt(abs(x @ Bx) * abs(y @ By))
+
+
+def test_tail_solve_matches_oracle(layered):
+    import torch
+    p, St, Ss, H = layered
+    uo, sto = H.pcg(p.f, 1e-10, 1000)
+    for S in (St, Ss):
+        for prec in (64, 32):
+            S.set_precision(prec)
+            u = S.solve(torch.tensor(p.f, device="cuda"), check=False).cpu().numpy()
+            st = S.last_stats
+            err = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+            print(f"tail {st['tail_level']} prec {prec}: it {st['iterations']} (oracle {sto['iterations']}) "
+                  f"err {err:.2e}", flush=True)
+            assert st["status"] == 0 and err <= 1e-8
+            if prec == 64:
+                assert abs(st["iterations"] - sto["iterations"]) <= 1
+        S.set_precision(64)
+
+
+def test_tail_parameter_bounds(cuda):
+    from paper_1902_01715_amd import aspamg
+    p = PR.c1_cube(5)
+    with pytest.raises(aspamg.AspamgError):
+        aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, aspamg.default_params(dense_tail_dof=8193))
+    with pytest.raises(aspamg.AspamgError):
+        aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, aspamg.default_params(dense_tail_dof=-1))
