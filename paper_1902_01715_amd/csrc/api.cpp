@@ -619,20 +619,21 @@ static void pcg_iteration(aspamg_ctx *h, bool fp32) {
   // partial regions: [0] p.q, [1] r.r and [2] r.z_old (update), [3] r.z
   double *pq_part = h->part, *rr_part = h->part + kMaxPart, *rz_part = h->part + 3 * kMaxPart;
   launch_spmv_dot(L0.A64, h->vp, h->vq, pq_part, c, s);
+  const int nv = vec_blocks(n);
   if (fp32) {
-    launch_pcg_update<float>(n, h->vu, h->vr, h->vp, h->vq, h->vz, pq_part, spmv_dot_blocks(L0.A64), rr_part,
+    // z (and z_old) stay in FP32: the update, r.z and p = z + beta p read them as they are
+    launch_pcg_update<float>(n, h->vu, h->vr, h->vp, h->vq, L0.v32.z, pq_part, spmv_dot_blocks(L0.A64), rr_part,
                              L0.v32.y, c, s);
-    launch_finish(kFinRr, rr_part, vec_blocks(n), c, s);
     cycle_level<float>(h, 0, L0.v32.y, L0.v32.z, nullptr);
-    launch_pcg_rz<float>(n, h->vr, L0.v32.z, h->vz, rz_part, c, s);
+    launch_pcg_rz<float>(n, h->vr, L0.v32.z, rz_part, rr_part, nv, c, s);
+    launch_pcg_pupdate<float>(n, L0.v32.z, h->vp, rz_part, nv, c, s);
   } else {
     launch_pcg_update<double>(n, h->vu, h->vr, h->vp, h->vq, h->vz, pq_part, spmv_dot_blocks(L0.A64), rr_part,
                               nullptr, c, s);
-    launch_finish(kFinRr, rr_part, vec_blocks(n), c, s);
     cycle_level<double>(h, 0, h->vr, h->vz, nullptr);
-    launch_pcg_rz<double>(n, h->vr, h->vz, h->vz, rz_part, c, s);
+    launch_pcg_rz<double>(n, h->vr, h->vz, rz_part, rr_part, nv, c, s);
+    launch_pcg_pupdate<double>(n, h->vz, h->vp, rz_part, nv, c, s);
   }
-  launch_pcg_pupdate(n, h->vz, h->vp, rz_part, vec_blocks(n), c, s);
 }
 
 static void alloc_level_vectors(aspamg_ctx *h) {
@@ -675,8 +676,12 @@ static void compute_complexities(aspamg_ctx *h) {
 }
 
 // Algorithmic bytes: each stored block once per use (9 values plus its column
-// index, 4 or 2 bytes as stored), 18 vector passes per level, the dense
-// coarsest inverse; one PCG iteration adds q = K p and 14 FP64 vector passes.
+// index, 4 or 2 bytes as stored), 18 vector passes per level, the dense tail
+// or coarsest operator; one PCG iteration adds q = K p (p read, q written) and
+// the vector kernels: the update reads u, r, p, q (FP64) and z and writes u, r
+// (FP64) and r in the cycle precision s when s = 4; r.z reads r and z; the
+// direction update reads z and p and writes p.  That is 96 B per unknown with
+// an FP64 cycle and 88 B with an FP32 one.
 template <typename T>
 static double block_bytes(const Sell<T> &S) {
   return 9.0 * sizeof(T) + S.index_bytes();
@@ -715,7 +720,8 @@ static double kp_block_bytes(const aspamg_ctx *h) { return 72.0 + h->lev[0].A64.
 
 static double iter_bytes(const aspamg_ctx *h, int prec) {
   const Level &L0 = h->lev[0];
-  return (double)L0.A.nnzb() * kp_block_bytes(h) + 14.0 * 3.0 * L0.A.n * 8.0 + cycle_bytes(h, prec);
+  const double per_dof = prec == 32 ? 88.0 : 96.0;
+  return (double)L0.A.nnzb() * kp_block_bytes(h) + 3.0 * L0.A.n * (16.0 + per_dof) + cycle_bytes(h, prec);
 }
 
 template <typename T>

@@ -229,15 +229,20 @@ void launch_cast(int64_t n, const TI *x, TO *y, const PcgCtrl *ctrl, hipStream_t
 void launch_fill(int64_t n, double *x, double v, hipStream_t s);
 void launch_copy(int64_t n, const double *x, double *y, hipStream_t s);
 void launch_dot(int64_t n, const double *a, const double *b, double *part, const PcgCtrl *ctrl, hipStream_t s);
+// z in the cycle precision TC; rc (optional) receives r in that precision
 template <typename TC>
-void launch_pcg_update(int64_t n, double *u, double *r, const double *p, const double *q, const double *z,
+void launch_pcg_update(int64_t n, double *u, double *r, const double *p, const double *q, const TC *z,
                        const double *pq_part, int npq, double *part, TC *rc, PcgCtrl *ctrl, hipStream_t s);
+// r.z partials, and the convergence test on the update's r.r / r.z_old partials
 template <typename TZ>
-void launch_pcg_rz(int64_t n, const double *r, const TZ *zc, double *z, double *part, const PcgCtrl *ctrl,
-                   hipStream_t s);
-void launch_pcg_pupdate(int64_t n, const double *z, double *p, const double *rz_part, int nrz, PcgCtrl *ctrl,
+void launch_pcg_rz(int64_t n, const double *r, const TZ *z, double *part, const double *rr_part, int nrr,
+                   PcgCtrl *ctrl, hipStream_t s);
+template <typename TZ>
+void launch_pcg_pupdate(int64_t n, const TZ *z, double *p, const double *rz_part, int nrz, PcgCtrl *ctrl,
                         hipStream_t s);
 // finish modes
+// (kFinRr and the batch modes are used by the multi-RHS column finisher; the
+// single-RHS iteration tests convergence inside k_pcg_rz)
 enum FinishMode { kFinInitF = 0, kFinInitRz = 1, kFinAlpha = 2, kFinRr = 3, kFinBeta = 4, kFinNorm = 5 };
 void launch_finish(int mode, const double *part, int nparts, PcgCtrl *ctrl, hipStream_t s);
 int vec_blocks(int64_t n);

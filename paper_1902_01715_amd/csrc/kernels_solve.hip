@@ -301,6 +301,11 @@ __global__ void __launch_bounds__(256) k_dot(int64_t n, const double *__restrict
 // u += alpha p, r -= alpha q; partials of r.r and r.z (z = previous preconditioned residual).
 // Fixed-order sum of np partials, the same in every block and returned to
 // every thread of the block.
+__device__ __forceinline__ double sum_parts(const double *part, int np, double *sm) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+  return block_sum(s, sm);
+}
 __device__ __forceinline__ double sum_parts_all(const double *part, int np, double *sm, double *bc) {
   double s = 0.0;
   for (int i = threadIdx.x; i < np; i += 256) s += part[i];
@@ -317,7 +322,7 @@ __device__ __forceinline__ double sum_parts_all(const double *part, int np, doub
 template <typename TC>
 __global__ void __launch_bounds__(256) k_pcg_update(int64_t n, double *__restrict__ u, double *__restrict__ r,
                                                     const double *__restrict__ p, const double *__restrict__ q,
-                                                    const double *__restrict__ z, const double *__restrict__ pq_part,
+                                                    const TC *__restrict__ z, const double *__restrict__ pq_part,
                                                     int npq, double *__restrict__ part, TC *__restrict__ rc,
                                                     PcgCtrl *ctrl) {
   __shared__ double sm[4], bc;
@@ -346,7 +351,7 @@ __global__ void __launch_bounds__(256) k_pcg_update(int64_t n, double *__restric
     r[i] = ri;
     if (rc) rc[i] = (TC)ri;
     s1 += ri * ri;
-    s2 += ri * z[i];
+    s2 += ri * (double)z[i];
   }
   s1 = block_sum(s1, sm);
   s2 = block_sum(s2, sm);
@@ -356,28 +361,44 @@ __global__ void __launch_bounds__(256) k_pcg_update(int64_t n, double *__restric
   }
 }
 
-// partial of r.z; with a low-precision cycle output zc the FP64 z is written too.
+// Convergence test after the update of iterate k + 1 (one thread): r.r and
+// r.z_old from their block partials, the iteration count and the stop flag.
+__device__ void finish_iteration(PcgCtrl *ctrl, double rr, double rzo) {
+  ctrl->rr = rr;
+  ctrl->rzo = rzo;
+  ctrl->iter += 1;
+  const double nr = sqrt(rr);
+  ctrl->relres = nr / ctrl->fnorm;
+  if (!(rr == rr) || rr == __builtin_inf()) { ctrl->status = ASPAMG_ENAN; ctrl->done = 1; }
+  else if (nr <= ctrl->rtol * ctrl->fnorm) { ctrl->status = ASPAMG_OK; ctrl->done = 1; }
+  else if (ctrl->iter >= ctrl->max_it) { ctrl->status = ASPAMG_NOT_CONVERGED; ctrl->done = 1; }
+}
+
+// Partials of r.z for the cycle output z (in the cycle precision).  Block 0
+// also runs the convergence test on the r.r and r.z_old partials that the
+// update left (it is the only writer of the flag in this launch, and the
+// other blocks do not read it: their partials are unused once it is set).
 template <typename TZ>
-__global__ void __launch_bounds__(256) k_pcg_rz(int64_t n, const double *__restrict__ r, const TZ *__restrict__ zc,
-                                                double *__restrict__ z, double *__restrict__ part,
-                                                const PcgCtrl *ctrl) {
+__global__ void __launch_bounds__(256) k_pcg_rz(int64_t n, const double *__restrict__ r, const TZ *__restrict__ z,
+                                                double *__restrict__ part, const double *__restrict__ rr_part,
+                                                int nrr, PcgCtrl *ctrl) {
   __shared__ double sm[4];
-  if (ctrl_done(ctrl)) return;
   double s = 0.0;
-  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const double zi = (double)zc[i];
-    if ((const void *)zc != (const void *)z) z[i] = zi;
-    s += r[i] * zi;
-  }
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += r[i] * (double)z[i];
   s = block_sum(s, sm);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (blockIdx.x != 0 || ctrl->done) return;     // uniform within block 0
+  const double rr = sum_parts(rr_part, nrr, sm);
+  const double rzo = sum_parts(rr_part + kMaxPart, nrr, sm);
+  if (threadIdx.x == 0) finish_iteration(ctrl, rr, rzo);
 }
 
 // p = z + beta p with beta = (r.z - r.z_old) / rz_k (Polak-Ribiere); every
 // block reduces the r.z partials itself, and block 0 keeps r.z as rz_{k+1}
 // in the slot of the next iteration (the other slot is the one read here).
 // A non-positive r.z ends the solve.
-__global__ void __launch_bounds__(256) k_pcg_pupdate(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+template <typename TZ>
+__global__ void __launch_bounds__(256) k_pcg_pupdate(int64_t n, const TZ *__restrict__ z, double *__restrict__ p,
                                                      const double *__restrict__ rz_part, int nrz, PcgCtrl *ctrl) {
   __shared__ double sm[4], bc;
   if (ctrl_done(ctrl)) return;
@@ -397,22 +418,16 @@ __global__ void __launch_bounds__(256) k_pcg_pupdate(int64_t n, const double *__
     ctrl->rz = rz;
     ctrl->beta = beta;
   }
-  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = z[i] + beta * p[i];
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = (double)z[i] + beta * p[i];
 }
 
-__device__ __forceinline__ double sum_parts(const double *part, int np, double *sm) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < np; i += 256) s += part[i];
-  return block_sum(s, sm);
-}
 
 // Scalar steps of PCG, one block: fixed-order reductions of the partials.
 __global__ void __launch_bounds__(256) k_finish(int mode, const double *__restrict__ part, int np, PcgCtrl *ctrl) {
   __shared__ double sm[4];
   if (ctrl->done) return;
   const double s0 = sum_parts(part, np, sm);
-  double s1 = 0.0;
-  if (mode == kFinRr) s1 = sum_parts(part + kMaxPart, np, sm);
   if (threadIdx.x != 0) return;
   switch (mode) {
     case kFinInitF: {
@@ -427,17 +442,6 @@ __global__ void __launch_bounds__(256) k_finish(int mode, const double *__restri
       ctrl->rz = s0;
       ctrl->rzk[0] = s0;
       if (!(s0 > 0.0)) { ctrl->status = (s0 == s0) ? ASPAMG_EBREAKDOWN : ASPAMG_ENAN; ctrl->done = 1; }
-      break;
-    }
-    case kFinRr: {
-      ctrl->rr = s0;
-      ctrl->rzo = s1;
-      ctrl->iter += 1;
-      const double nr = sqrt(s0);
-      ctrl->relres = nr / ctrl->fnorm;
-      if (!(s0 == s0) || s0 == __builtin_inf()) { ctrl->status = ASPAMG_ENAN; ctrl->done = 1; }
-      else if (nr <= ctrl->rtol * ctrl->fnorm) { ctrl->status = ASPAMG_OK; ctrl->done = 1; }
-      else if (ctrl->iter >= ctrl->max_it) { ctrl->status = ASPAMG_NOT_CONVERGED; ctrl->done = 1; }
       break;
     }
     case kFinNorm: {
@@ -612,28 +616,33 @@ void launch_dot(int64_t n, const double *a, const double *b, double *part, const
   hipLaunchKernelGGL(k_dot, dim3(vec_blocks(n)), dim3(256), 0, s, n, a, b, part, ctrl);
 }
 template <typename TC>
-void launch_pcg_update(int64_t n, double *u, double *r, const double *p, const double *q, const double *z,
+void launch_pcg_update(int64_t n, double *u, double *r, const double *p, const double *q, const TC *z,
                        const double *pq_part, int npq, double *part, TC *rc, PcgCtrl *ctrl, hipStream_t s) {
   hipLaunchKernelGGL(k_pcg_update<TC>, dim3(vec_blocks(n)), dim3(256), 0, s, n, u, r, p, q, z, pq_part, npq, part, rc,
                      ctrl);
 }
-template void launch_pcg_update<float>(int64_t, double *, double *, const double *, const double *, const double *,
+template void launch_pcg_update<float>(int64_t, double *, double *, const double *, const double *, const float *,
                                        const double *, int, double *, float *, PcgCtrl *, hipStream_t);
 template void launch_pcg_update<double>(int64_t, double *, double *, const double *, const double *, const double *,
                                         const double *, int, double *, double *, PcgCtrl *, hipStream_t);
 template <typename TZ>
-void launch_pcg_rz(int64_t n, const double *r, const TZ *zc, double *z, double *part, const PcgCtrl *ctrl,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_rz<TZ>, dim3(vec_blocks(n)), dim3(256), 0, s, n, r, zc, z, part, ctrl);
+void launch_pcg_rz(int64_t n, const double *r, const TZ *z, double *part, const double *rr_part, int nrr,
+                   PcgCtrl *ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_rz<TZ>, dim3(vec_blocks(n)), dim3(256), 0, s, n, r, z, part, rr_part, nrr, ctrl);
 }
-template void launch_pcg_rz<double>(int64_t, const double *, const double *, double *, double *, const PcgCtrl *,
+template void launch_pcg_rz<double>(int64_t, const double *, const double *, double *, const double *, int, PcgCtrl *,
                                     hipStream_t);
-template void launch_pcg_rz<float>(int64_t, const double *, const float *, double *, double *, const PcgCtrl *,
+template void launch_pcg_rz<float>(int64_t, const double *, const float *, double *, const double *, int, PcgCtrl *,
                                    hipStream_t);
-void launch_pcg_pupdate(int64_t n, const double *z, double *p, const double *rz_part, int nrz, PcgCtrl *ctrl,
+template <typename TZ>
+void launch_pcg_pupdate(int64_t n, const TZ *z, double *p, const double *rz_part, int nrz, PcgCtrl *ctrl,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_pupdate, dim3(vec_blocks(n)), dim3(256), 0, s, n, z, p, rz_part, nrz, ctrl);
+  hipLaunchKernelGGL(k_pcg_pupdate<TZ>, dim3(vec_blocks(n)), dim3(256), 0, s, n, z, p, rz_part, nrz, ctrl);
 }
+template void launch_pcg_pupdate<double>(int64_t, const double *, double *, const double *, int, PcgCtrl *,
+                                         hipStream_t);
+template void launch_pcg_pupdate<float>(int64_t, const float *, double *, const double *, int, PcgCtrl *,
+                                        hipStream_t);
 void launch_finish(int mode, const double *part, int nparts, PcgCtrl *ctrl, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, mode, part, nparts, ctrl);
 }
