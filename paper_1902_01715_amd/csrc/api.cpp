@@ -144,9 +144,13 @@ static std::vector<int32_t> settle_columns(std::vector<int32_t> &col, int32_t no
   return base;
 }
 
+// Device arrays of a layout: slice/wavefront pointers, columns (16-bit
+// offsets when `base` is not empty), the lane metadata of the row-packed
+// layout, and the values, scattered on the device from the block values `dv`
+// of the source matrix (device copy) by the per-slot source map.
 template <typename T>
 static void upload_arrays(aspamg_ctx *h, Sell<T> &S, const std::vector<int32_t> &sptr, const std::vector<int32_t> &col,
-                          const std::vector<int32_t> &base, const std::vector<T> &val,
+                          const std::vector<int32_t> &base, const std::vector<int32_t> &map, const double *dv,
                           const std::vector<uint16_t> &meta) {
   S.sptr = dalloc<int32_t>(h, sptr.size());
   HIPCHK(hipMemcpyAsync(S.sptr, sptr.data(), sptr.size() * 4, hipMemcpyHostToDevice, h->stream));
@@ -169,17 +173,23 @@ static void upload_arrays(aspamg_ctx *h, Sell<T> &S, const std::vector<int32_t> 
     S.col = dalloc<int32_t>(h, col.size());
     HIPCHK(hipMemcpyAsync(S.col, col.data(), col.size() * 4, hipMemcpyHostToDevice, h->stream));
   }
-  S.val = dalloc<T>(h, val.size());
-  HIPCHK(hipMemcpyAsync(S.val, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
   if (!meta.empty()) {
     S.meta = dalloc<uint16_t>(h, meta.size());
     HIPCHK(hipMemcpyAsync(S.meta, meta.data(), meta.size() * 2, hipMemcpyHostToDevice, h->stream));
   }
+  const int64_t nslots = (int64_t)map.size();
+  S.val = dalloc<T>(h, (size_t)S.ngroups * 576);
+  int32_t *dmap = dalloc<int32_t>(h, std::max<size_t>(map.size(), 1));
+  HIPCHK(hipMemcpyAsync(dmap, map.data(), map.size() * 4, hipMemcpyHostToDevice, h->stream));
+  launch_scatter_values<T>(nslots, dmap, dv, S.val, h->stream);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(h->stream));
+  dfree(h, dmap);
 }
 
 template <typename T>
-static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::vector<int32_t> &w0) {
+static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::vector<int32_t> &w0,
+                             const double *dv) {
   Sell<T> S;
   S.n = M.n;
   S.nc = M.nc;
@@ -188,32 +198,43 @@ static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::
   S.pack = K;
   S.nslices = (int32_t)w0.size() - 1;
   S.ngroups = (int64_t)S.nslices * K;
-  std::vector<int32_t> col((size_t)S.ngroups * 64, -1);
-  std::vector<T> val((size_t)S.ngroups * 576, (T)0);
-  std::vector<uint16_t> meta((size_t)S.nslices * 64, 0x00FF);
+  std::vector<int32_t> col((size_t)S.ngroups * 64), map((size_t)S.ngroups * 64);
+  std::vector<uint16_t> meta((size_t)S.nslices * 64);
 #pragma omp parallel for schedule(dynamic, 64)
   for (int32_t s = 0; s < S.nslices; s++) {
+    // lane e of wavefront s serves blocks j K .. j K + K - 1 of row lrow[e]
+    int32_t lrow[64], lj[64];
     int e = 0;
     for (int32_t r = w0[s]; r < w0[s + 1]; r++) {
       const int64_t len = M.rp[r + 1] - M.rp[r];
       const int lr = (int)std::max<int64_t>(1, (len + K - 1) / K);
       for (int j = 0; j < lr; j++, e++) {
         meta[(size_t)s * 64 + e] = (uint16_t)(((j == 0 ? lr : 0) << 8) | (r - w0[s]));
-        for (int k = 0; k < K; k++) {
-          const int64_t b = (int64_t)j * K + k;
-          const size_t g = (size_t)s * K + k;
-          if (b < len) {
-            const int64_t src = M.rp[r] + b;
-            col[g * 64 + e] = M.ci[src];
-            for (int q = 0; q < 9; q++) val[(g * 9 + q) * 64 + e] = (T)M.v[(size_t)src * 9 + q];
-          }
+        lrow[e] = r;
+        lj[e] = j;
+      }
+    }
+    for (int f = e; f < 64; f++) {
+      meta[(size_t)s * 64 + f] = 0x00FF;
+      lrow[f] = -1;
+      lj[f] = 0;
+    }
+    for (int k = 0; k < K; k++) {
+      const size_t g = (size_t)s * K + k;
+      for (int f = 0; f < 64; f++) {
+        int32_t src = -1;
+        if (lrow[f] >= 0) {
+          const int64_t b = (int64_t)lj[f] * K + k;
+          if (b < M.rp[lrow[f] + 1] - M.rp[lrow[f]]) src = (int32_t)(M.rp[lrow[f]] + b);
         }
+        map[g * 64 + f] = src;
+        col[g * 64 + f] = src >= 0 ? M.ci[src] : -1;
       }
     }
   }
   const int64_t Kp = K;
   std::vector<int32_t> base = settle_columns(col, S.nslices, [Kp](int32_t s) { return (int64_t)s * Kp; });
-  upload_arrays(h, S, w0, col, base, val, meta);
+  upload_arrays(h, S, w0, col, base, map, dv, meta);
   return S;
 }
 
@@ -242,7 +263,8 @@ static int sliced_plan(const HostBSR &M, int force_lanes, std::vector<int32_t> *
 }
 
 template <typename T>
-static Sell<T> upload_sliced(aspamg_ctx *h, const HostBSR &M, int L, const std::vector<int32_t> &sptr) {
+static Sell<T> upload_sliced(aspamg_ctx *h, const HostBSR &M, int L, const std::vector<int32_t> &sptr,
+                             const double *dv) {
   Sell<T> S;
   S.n = M.n;
   S.nc = M.nc;
@@ -251,26 +273,22 @@ static Sell<T> upload_sliced(aspamg_ctx *h, const HostBSR &M, int L, const std::
   const int rps = kSell / L;
   S.nslices = (int32_t)sptr.size() - 1;
   S.ngroups = sptr.back();
-  std::vector<int32_t> col((size_t)S.ngroups * 64, -1);
-  std::vector<T> val((size_t)S.ngroups * 576, (T)0);
+  std::vector<int32_t> col((size_t)S.ngroups * 64), map((size_t)S.ngroups * 64);
 #pragma omp parallel for schedule(dynamic, 64)
   for (int32_t s = 0; s < S.nslices; s++) {
-    for (int e = 0; e < kSell; e++) {
-      const int32_t r = s * rps + e / L;
-      const int j = e % L;
-      const int64_t len = r < M.n ? M.rp[r + 1] - M.rp[r] : 0;
-      for (int32_t g = sptr[s]; g < sptr[s + 1]; g++) {
-        const int64_t k = (int64_t)(g - sptr[s]) * L + j;
-        if (k < len) {
-          const int64_t src = M.rp[r] + k;
-          col[(size_t)g * 64 + e] = M.ci[src];
-          for (int q = 0; q < 9; q++) val[((size_t)g * 9 + q) * 64 + e] = (T)M.v[(size_t)src * 9 + q];
-        }
+    for (int32_t g = sptr[s]; g < sptr[s + 1]; g++) {
+      for (int e = 0; e < kSell; e++) {
+        const int32_t r = s * rps + e / L;
+        const int64_t k = (int64_t)(g - sptr[s]) * L + e % L;
+        const int64_t len = r < M.n ? M.rp[r + 1] - M.rp[r] : 0;
+        const int32_t src = k < len ? (int32_t)(M.rp[r] + k) : -1;
+        map[(size_t)g * 64 + e] = src;
+        col[(size_t)g * 64 + e] = src >= 0 ? M.ci[src] : -1;
       }
     }
   }
   std::vector<int32_t> base = settle_columns(col, S.nslices, [&sptr](int32_t s) { return (int64_t)sptr[s]; });
-  upload_arrays(h, S, sptr, col, base, val, {});
+  upload_arrays(h, S, sptr, col, base, map, dv, {});
   return S;
 }
 
@@ -330,9 +348,18 @@ static void time_products(aspamg_ctx *h, const Sell<T> &S, const Sell<T> &Q, con
 template <typename T>
 Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed) {
   const int policy = h->p.layout;
+  if (M.nnzb() >= (int64_t)INT32_MAX) fail(ASPAMG_EINVAL, "operator too large for int32 block indices");
   std::vector<int32_t> sptr;
   const int L = sliced_plan(M, force_lanes, &sptr);
-  if (force_lanes || M.n == 0 || M.nc == 0 || policy == 2) return upload_sliced<T>(h, M, L, sptr);
+  // the block values on the device once; every layout built below scatters from them
+  struct Values {
+    aspamg_ctx *h;
+    double *v;
+    ~Values() { dfree(h, v); }
+  } dv{h, dalloc<double>(h, std::max<size_t>(M.v.size(), 1))};
+  if (!M.v.empty())
+    HIPCHK(hipMemcpyAsync(dv.v, M.v.data(), M.v.size() * 8, hipMemcpyHostToDevice, h->stream));
+  if (force_lanes || M.n == 0 || M.nc == 0 || policy == 2) return upload_sliced<T>(h, M, L, sptr, dv.v);
   if (policy != 0) timed = false;
   int bestK = 0;
   int64_t best = 0;
@@ -350,18 +377,18 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
       bestw.swap(w0);
     }
   }
-  if (!bestK) return upload_sliced<T>(h, M, L, sptr);   // a row needs more than 64 lanes
-  if (policy == 3) return upload_packed<T>(h, M, bestK, bestw);
+  if (!bestK) return upload_sliced<T>(h, M, L, sptr, dv.v);   // a row needs more than 64 lanes
+  if (policy == 3) return upload_packed<T>(h, M, bestK, bestw, dv.v);
   const int64_t sliced = (int64_t)sptr.back() * 64;
   const double ratio = (double)best / (double)sliced;
   // small operators sit at the launch-latency floor either way: no timing
   if (!timed || std::max<int64_t>(best, sliced) < kTimedSlots) {
-    if (ratio >= 0.9) return upload_sliced<T>(h, M, L, sptr);
-    return upload_packed<T>(h, M, bestK, bestw);
+    if (ratio >= 0.9) return upload_sliced<T>(h, M, L, sptr, dv.v);
+    return upload_packed<T>(h, M, bestK, bestw, dv.v);
   }
-  if (ratio > 1.5) return upload_sliced<T>(h, M, L, sptr);
-  Sell<T> S = upload_sliced<T>(h, M, L, sptr);
-  Sell<T> Q = upload_packed<T>(h, M, bestK, bestw);
+  if (ratio > 1.5) return upload_sliced<T>(h, M, L, sptr, dv.v);
+  Sell<T> S = upload_sliced<T>(h, M, L, sptr, dv.v);
+  Sell<T> Q = upload_packed<T>(h, M, bestK, bestw, dv.v);
   T *x = nullptr, *y = nullptr;
   HIPCHK(hipMalloc(&x, sizeof(T) * 3 * (size_t)M.nc));
   HIPCHK(hipMalloc(&y, sizeof(T) * 3 * (size_t)M.n));

@@ -199,6 +199,7 @@ constexpr int kMaxTailDof = 8192;   // largest dense tail operator (512 MB in FP
 void *dmalloc(aspamg_ctx *h, size_t bytes);
 template <typename T>
 T *dalloc(aspamg_ctx *h, size_t n) { return static_cast<T *>(dmalloc(h, n * sizeof(T))); }
+void dfree(aspamg_ctx *h, void *p);   // releases one dmalloc'd pointer early
 
 // ---- layout builders (host) ----
 HostBSR transpose(const HostBSR &M);
@@ -265,6 +266,9 @@ void launch_bsr_mm(const DevBSR &M, const double *X, double *Y, const double *W,
                    hipStream_t s);
 void launch_dense_mm(int32_t nd, const double *D, const double *X, double *Y, int32_t nb, hipStream_t s);
 void launch_eye(int32_t nd, double *X, hipStream_t s);
+// layout values: slot i takes the 9 values of block map[i] of v (zeros when map[i] < 0)
+template <typename T>
+void launch_scatter_values(int64_t nslots, const int32_t *map, const double *v, T *val, hipStream_t s);
 void launch_element_gradient(int64_t n_el, const int32_t *conn, const double *Ke0, int64_t ke_stride,
                              const double *lam, const double *u, const double *scale, double *grad,
                              hipStream_t s);

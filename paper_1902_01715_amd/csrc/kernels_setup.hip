@@ -325,6 +325,26 @@ __global__ void __launch_bounds__(256) k_dense_mm(int32_t nd, const double *__re
   Y[(size_t)r * nb + c] = a;
 }
 
+// Layout values from the block values of the source matrix: slot i (slot
+// group i / 64, lane i % 64) takes block src = map[i] (its 9 values into the
+// group's nine 64-entry runs), or zeros when src < 0.
+template <typename T>
+__global__ void __launch_bounds__(256) k_scatter_values(int64_t nslots, const int32_t *__restrict__ map,
+                                                        const double *__restrict__ v, T *__restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nslots) return;
+  const int32_t src = map[i];
+  T *o = val + (i >> 6) * 576 + (i & 63);
+  if (src >= 0) {
+    const double *b = v + (int64_t)src * 9;
+#pragma unroll
+    for (int q = 0; q < 9; q++) o[q * 64] = (T)b[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 9; q++) o[q * 64] = (T)0;
+  }
+}
+
 // X = the nd x nd identity, row-major
 __global__ void __launch_bounds__(256) k_eye(int64_t nd, double *__restrict__ X) {
   const int64_t n = nd * nd;
@@ -345,6 +365,15 @@ void launch_dense_mm(int32_t nd, const double *D, const double *X, double *Y, in
   if (nd == 0 || nb == 0) return;
   hipLaunchKernelGGL(k_dense_mm, dim3((unsigned)((nb + 255) / 256), (unsigned)nd), dim3(256), 0, s, nd, D, X, Y, nb);
 }
+
+template <typename T>
+void launch_scatter_values(int64_t nslots, const int32_t *map, const double *v, T *val, hipStream_t s) {
+  if (nslots == 0) return;
+  hipLaunchKernelGGL(k_scatter_values<T>, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s, nslots, map, v,
+                     val);
+}
+template void launch_scatter_values<double>(int64_t, const int32_t *, const double *, double *, hipStream_t);
+template void launch_scatter_values<float>(int64_t, const int32_t *, const double *, float *, hipStream_t);
 
 void launch_eye(int32_t nd, double *X, hipStream_t s) {
   const int64_t n = (int64_t)nd * nd;
