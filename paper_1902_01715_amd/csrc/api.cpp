@@ -43,15 +43,19 @@ HostBSR transpose(const HostBSR &M) {
   for (int64_t k = 0; k < nnz; k++) T.rp[M.ci[k] + 1]++;
   for (int32_t i = 0; i < T.n; i++) T.rp[i + 1] += T.rp[i];
   T.ci.resize(nnz);
-  T.v.resize((size_t)nnz * 9);
+  std::vector<int64_t> src(nnz);
   std::vector<int64_t> pos(T.rp.begin(), T.rp.end() - 1);
   for (int32_t i = 0; i < M.n; i++)
     for (int64_t k = M.rp[i]; k < M.rp[i + 1]; k++) {
       const int64_t q = pos[M.ci[k]]++;
       T.ci[q] = i;
-      for (int d = 0; d < 3; d++)
-        for (int e = 0; e < 3; e++) T.v[(size_t)q * 9 + e * 3 + d] = M.v[(size_t)k * 9 + d * 3 + e];
+      src[q] = k;
     }
+  T.v.resize((size_t)nnz * 9);
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < nnz; q++)
+    for (int d = 0; d < 3; d++)
+      for (int e = 0; e < 3; e++) T.v[(size_t)q * 9 + e * 3 + d] = M.v[(size_t)src[q] * 9 + d * 3 + e];
   return T;
 }
 
@@ -346,7 +350,7 @@ static void time_products(aspamg_ctx *h, const Sell<T> &S, const Sell<T> &Q, con
 // under kTimedSlots slots, or all of them without `timed`, keep the
 // row-packed layout when it stores 10% fewer slots.
 template <typename T>
-Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed) {
+Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed, const double *dvals) {
   const int policy = h->p.layout;
   if (M.nnzb() >= (int64_t)INT32_MAX) fail(ASPAMG_EINVAL, "operator too large for int32 block indices");
   std::vector<int32_t> sptr;
@@ -355,10 +359,16 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
   struct Values {
     aspamg_ctx *h;
     double *v;
-    ~Values() { dfree(h, v); }
-  } dv{h, dalloc<double>(h, std::max<size_t>(M.v.size(), 1))};
-  if (!M.v.empty())
-    HIPCHK(hipMemcpyAsync(dv.v, M.v.data(), M.v.size() * 8, hipMemcpyHostToDevice, h->stream));
+    bool own;
+    ~Values() {
+      if (own) dfree(h, v);
+    }
+  } dv{h, const_cast<double *>(dvals), dvals == nullptr};
+  if (!dvals) {
+    dv.v = dalloc<double>(h, std::max<size_t>(M.v.size(), 1));
+    if (!M.v.empty())
+      HIPCHK(hipMemcpyAsync(dv.v, M.v.data(), M.v.size() * 8, hipMemcpyHostToDevice, h->stream));
+  }
   if (force_lanes || M.n == 0 || M.nc == 0 || policy == 2) return upload_sliced<T>(h, M, L, sptr, dv.v);
   if (policy != 0) timed = false;
   int bestK = 0;
@@ -434,8 +444,8 @@ Sell<float> derive_fp32(aspamg_ctx *h, const Sell<double> &S) {
   return F;
 }
 
-template Sell<double> upload_sell<double>(aspamg_ctx *, const HostBSR &, int, bool);
-template Sell<float> upload_sell<float>(aspamg_ctx *, const HostBSR &, int, bool);
+template Sell<double> upload_sell<double>(aspamg_ctx *, const HostBSR &, int, bool, const double *);
+template Sell<float> upload_sell<float>(aspamg_ctx *, const HostBSR &, int, bool, const double *);
 template void free_sell<double>(aspamg_ctx *, Sell<double> &);
 template void free_sell<float>(aspamg_ctx *, Sell<float> &);
 

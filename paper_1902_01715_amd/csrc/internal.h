@@ -203,8 +203,10 @@ void dfree(aspamg_ctx *h, void *p);   // releases one dmalloc'd pointer early
 
 // ---- layout builders (host) ----
 HostBSR transpose(const HostBSR &M);
+// dvals: M's block values already on the device (then M.v is not read)
 template <typename T>
-Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes = 0, bool timed = true);
+Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes = 0, bool timed = true,
+                    const double *dvals = nullptr);
 template <typename T>
 void free_sell(aspamg_ctx *h, Sell<T> &S);   // releases the device arrays of S
 // FP32 copy in the same layout, sharing S's index arrays (never freed on its own)

@@ -171,38 +171,49 @@ inline double psi_sum(const FsaiState &F, int32_t I) {
   return s;
 }
 
+// Column view of A: for every column K the rows J with a block (J, K), in
+// ascending order, and that block's position in A.
+struct ColumnView {
+  std::vector<int64_t> cp;
+  std::vector<int32_t> row;
+  std::vector<int64_t> pos;
+  explicit ColumnView(const HostBSR &A) : cp((size_t)A.nc + 1, 0), row(A.ci.size()), pos(A.ci.size()) {
+    for (int32_t c : A.ci) cp[(size_t)c + 1]++;
+    for (int32_t c = 0; c < A.nc; c++) cp[(size_t)c + 1] += cp[c];
+    std::vector<int64_t> next(cp.begin(), cp.end() - 1);
+    for (int32_t r = 0; r < A.n; r++)
+      for (int64_t k = A.rp[r]; k < A.rp[r + 1]; k++) {
+        const int64_t at = next[A.ci[k]]++;
+        row[at] = r;
+        pos[at] = k;
+      }
+  }
+};
+
+// Per-thread work space of fsai_grow: mark[J] is the accumulator slot of
+// candidate J, -2 for a member of the row's pattern, -1 otherwise (restored
+// after every row).
+struct GrowScratch {
+  std::vector<int32_t> mark, cand;
+  std::vector<double> h;
+  std::vector<std::pair<double, int32_t>> sc;
+  explicit GrowScratch(int32_t n) : mark(n, -1) {}
+};
+
 // Pattern growth of one row (the adaptive step): candidates are the nodes
 // J < I, not in B, adjacent in A to B u {I}; with g' = g / g_last,
 // h_{(I,d),(J,e)} = sum over the pattern index k (ascending) of A[(J,e), l_k] g'_k
 // and score_J = sum_d sum_e h^2.  The rho nodes with the largest quantised
 // score (ties to the lowest J) are added.  Returns the number added.
-int fsai_grow(const HostBSR &A, FsaiState &F, int32_t I, int rho, const Q &q, std::vector<int32_t> &cand,
-              std::vector<std::pair<double, int32_t>> &sc) {
+// The pattern nodes are walked in ascending order and, for each, the rows J
+// of its column in A, so every candidate's h receives its terms in the
+// ascending order of k above (A's pattern is symmetric, so the column of a
+// pattern node lists exactly the candidates adjacent to it).
+int fsai_grow(const HostBSR &A, const ColumnView &C, FsaiState &F, int32_t I, int rho, const Q &q,
+              GrowScratch &W) {
   const int32_t nb = F.nb[I];
   if (nb + rho > kMaxFsaiNodes) return 0;
   const int32_t *B = F.nodes.data() + (size_t)I * kMaxFsaiNodes;
-  cand.clear();
-  for (int p = 0; p <= nb; p++) {
-    const int32_t K = p < nb ? B[p] : I;
-    for (int64_t k = A.rp[K]; k < A.rp[K + 1]; k++) {
-      const int32_t J = A.ci[k];
-      if (J >= I) break;   // columns ascend
-      cand.push_back(J);
-    }
-  }
-  std::sort(cand.begin(), cand.end());
-  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-  // drop members of B (both sorted)
-  {
-    size_t w = 0, b = 0;
-    for (size_t r = 0; r < cand.size(); r++) {
-      while (b < (size_t)nb && B[b] < cand[r]) b++;
-      if (b < (size_t)nb && B[b] == cand[r]) continue;
-      cand[w++] = cand[r];
-    }
-    cand.resize(w);
-  }
-  if (cand.empty()) return 0;
   const int gs = FsaiState::gstride;
   const double *g = F.g.data() + (size_t)I * 3 * gs;
   double gp[3][gs];
@@ -211,48 +222,57 @@ int fsai_grow(const HostBSR &A, FsaiState &F, int32_t I, int rho, const Q &q, st
     const double gl = g[d * gs + md - 1];
     for (int k = 0; k < md; k++) gp[d][k] = g[d * gs + k] / gl;
   }
-  sc.clear();
-  int64_t pos[kMaxFsaiNodes + 1];
-  for (int32_t J : cand) {
-    // blocks A(J, node_p) for the local node list [B..., I] (ascending): merge join
-    int64_t k = A.rp[J];
-    const int64_t ke = A.rp[J + 1];
-    for (int p = 0; p <= nb; p++) {
-      const int32_t nd = p < nb ? B[p] : I;
-      while (k < ke && A.ci[k] < nd) k++;
-      pos[p] = (k < ke && A.ci[k] == nd) ? k : -1;
-    }
-    // h_{d,e} = sum over kk ascending (absent blocks skipped) of
-    // A[(J,e), l_kk] g'_d[kk]; the three e run side by side, each in that order
-    double score = 0.0;
-    for (int d = 0; d < 3; d++) {
-      const int md = 3 * nb + d + 1;
-      double h0 = 0.0, h1 = 0.0, h2 = 0.0;
-      for (int pp = 0; pp <= nb; pp++) {
-        const int64_t bp = pos[pp];
-        if (bp < 0) continue;
-        const double *blk = A.v.data() + (size_t)bp * 9;
-        const int kend = std::min(3, md - 3 * pp);
+  for (int b = 0; b < nb; b++) W.mark[B[b]] = -2;
+  W.cand.clear();
+  W.h.clear();
+  for (int p = 0; p <= nb; p++) {
+    const int32_t K = p < nb ? B[p] : I;
+    for (int64_t k = C.cp[K]; k < C.cp[(size_t)K + 1]; k++) {
+      const int32_t J = C.row[k];
+      if (J >= I) break;   // rows ascend
+      int32_t slot = W.mark[J];
+      if (slot == -2) continue;
+      if (slot < 0) {
+        slot = (int32_t)W.cand.size();
+        W.mark[J] = slot;
+        W.cand.push_back(J);
+        W.h.resize(W.h.size() + 9, 0.0);
+      }
+      const double *blk = A.v.data() + (size_t)C.pos[k] * 9;   // block (J, K)
+      double *hj = W.h.data() + (size_t)slot * 9;
+      for (int d = 0; d < 3; d++) {
+        const int kend = std::min(3, 3 * nb + d + 1 - 3 * p);
         for (int c = 0; c < kend; c++) {
-          const double gk = gp[d][3 * pp + c];
-          h0 += blk[c] * gk;
-          h1 += blk[3 + c] * gk;
-          h2 += blk[6 + c] * gk;
+          const double gk = gp[d][3 * p + c];
+          hj[d * 3 + 0] += blk[c] * gk;
+          hj[d * 3 + 1] += blk[3 + c] * gk;
+          hj[d * 3 + 2] += blk[6 + c] * gk;
         }
       }
-      score += h0 * h0;
-      score += h1 * h1;
-      score += h2 * h2;
     }
-    if (score > 0.0) sc.emplace_back(q(score), J);
   }
-  if (sc.empty()) return 0;
-  std::sort(sc.begin(), sc.end(), [](const auto &a, const auto &b) {
+  W.sc.clear();
+  for (size_t j = 0; j < W.cand.size(); j++) {
+    const double *hj = W.h.data() + j * 9;
+    double score = 0.0;
+    for (int d = 0; d < 3; d++) {
+      score += hj[d * 3 + 0] * hj[d * 3 + 0];
+      score += hj[d * 3 + 1] * hj[d * 3 + 1];
+      score += hj[d * 3 + 2] * hj[d * 3 + 2];
+    }
+    if (score > 0.0) W.sc.emplace_back(q(score), W.cand[j]);
+    W.mark[W.cand[j]] = -1;
+  }
+  for (int b = 0; b < nb; b++) W.mark[B[b]] = -1;
+  if (W.sc.empty()) return 0;
+  // the rho first in the order (score descending, J ascending): a total order,
+  // so the selection is that of a full sort
+  const int add = std::min<int>(rho, (int)W.sc.size());
+  std::partial_sort(W.sc.begin(), W.sc.begin() + add, W.sc.end(), [](const auto &a, const auto &b) {
     return a.first != b.first ? a.first > b.first : a.second < b.second;
   });
-  const int add = std::min<int>(rho, (int)sc.size());
   int32_t *Bw = F.nodes.data() + (size_t)I * kMaxFsaiNodes;
-  for (int a = 0; a < add; a++) Bw[nb + a] = sc[a].second;
+  for (int a = 0; a < add; a++) Bw[nb + a] = W.sc[a].second;
   F.nb[I] = nb + add;
   std::sort(Bw, Bw + nb + add);
   return add;
@@ -396,14 +416,14 @@ void build_fsai(aspamg_ctx *h, Level &L) {
   std::vector<double> psi_prev(n);
   for (int32_t i = 0; i < n; i++) psi_prev[i] = psi_sum(F, i);
   const int nthreads = omp_get_max_threads();
-  std::vector<std::vector<int32_t>> tcand(nthreads);
-  std::vector<std::vector<std::pair<double, int32_t>>> tsc(nthreads);
+  const ColumnView cols(L.A);
+  std::vector<GrowScratch> work(nthreads, GrowScratch(n));
   for (int step = 0; step < p.k_g && !active.empty(); step++) {
     std::vector<char> grew(active.size(), 0);
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t a = 0; a < (int64_t)active.size(); a++) {
       const int t = omp_get_thread_num();
-      grew[a] = fsai_grow(L.A, F, active[a], p.rho_blocks, q, tcand[t], tsc[t]) > 0;
+      grew[a] = fsai_grow(L.A, cols, F, active[a], p.rho_blocks, q, work[t]) > 0;
     }
     std::vector<int32_t> next;
     for (size_t a = 0; a < active.size(); a++)
@@ -439,7 +459,7 @@ void build_fsai(aspamg_ctx *h, Level &L) {
 #pragma omp parallel for schedule(dynamic, 256)
     for (int32_t I = 0; I < n; I++) {
       const int t = omp_get_thread_num();
-      grew[I] = fsai_grow(L.A, F, I, p.rho_blocks, q, tcand[t], tsc[t]) > 0;
+      grew[I] = fsai_grow(L.A, cols, F, I, p.rho_blocks, q, work[t]) > 0;
     }
     std::vector<int32_t> rows;
     for (int32_t I = 0; I < n; I++)
@@ -833,7 +853,7 @@ void build_prolongation(aspamg_ctx *h, Level &L, const StrongGraph &S) {
 // ------------------------------------------------------------------------
 // Galerkin operator A_c = R (A P): patterns on the host, values on the GPU.
 // ------------------------------------------------------------------------
-HostBSR spgemm_pattern(const HostBSR &X, const HostBSR &Y) {
+HostBSR spgemm_pattern(const HostBSR &X, const HostBSR &Y, bool host_values = true) {
   HostBSR Z;
   Z.n = X.n;
   Z.nc = Y.nc;
@@ -861,7 +881,7 @@ HostBSR spgemm_pattern(const HostBSR &X, const HostBSR &Y) {
   for (int32_t i = 0; i < X.n; i++) Z.rp[i + 1] = Z.rp[i] + (int64_t)rows[i].size();
   Z.ci.resize(Z.rp[X.n]);
   for (int32_t i = 0; i < X.n; i++) std::copy(rows[i].begin(), rows[i].end(), Z.ci.begin() + Z.rp[i]);
-  Z.v.assign((size_t)Z.rp[X.n] * 9, 0.0);
+  if (host_values) Z.v.assign((size_t)Z.rp[X.n] * 9, 0.0);
   return Z;
 }
 
@@ -890,24 +910,32 @@ struct DevTmp {
   }
 };
 
-// A_c = R (A P); the intermediate T = A P is returned in *AP.
-HostBSR galerkin(aspamg_ctx *h, const Level &L, HostBSR *AP) {
+// A_c = R (A P).  The pattern of the intermediate T = A P is returned in *AP
+// (no host values); its values stay on the device, in *dPAP = [P values;
+// T values] (dalloc'd, the caller frees it), the block values of the stacked
+// operator [P; A P].
+HostBSR galerkin(aspamg_ctx *h, const Level &L, HostBSR *AP, double **dPAP) {
   HostBSR R = transpose(L.P);
-  HostBSR T = spgemm_pattern(L.A, L.P);
+  HostBSR T = spgemm_pattern(L.A, L.P, false);
   HostBSR Ac = spgemm_pattern(R, T);
+  const int64_t nP = L.P.nnzb(), nT = T.nnzb();
+  double *stack = dalloc<double>(h, (size_t)std::max<int64_t>(nP + nT, 1) * 9);
   DevTmp tmp;
   DevBSR dP = tmp.make(L.P, h->stream, true), dR = tmp.make(R, h->stream, true);
   DevBSR dT = tmp.make(T, h->stream, false), dC = tmp.make(Ac, h->stream, false);
+  dT.v = stack + (size_t)nP * 9;
+  if (nP > 0) HIPCHK(hipMemcpyAsync(stack, dP.v, (size_t)nP * 72, hipMemcpyDeviceToDevice, h->stream));
   launch_spgemm_ap(L.dA, dP, dT, h->stream);
   launch_spgemm_rt(dR, dT, dC, h->stream);
   HIPCHK(hipGetLastError());
   to_host(h->stream, Ac.v.data(), dC.v, Ac.v.size());
-  to_host(h->stream, T.v.data(), dT.v, T.v.size());
   *AP = std::move(T);
+  *dPAP = stack;
   return Ac;
 }
 
-// [P; A P]: the rows of P, then those of A P (same columns)
+// Pattern of [P; A P]: the rows of P, then those of A P (same columns); the
+// block values are numbered in the same order (P's, then A P's)
 HostBSR stack_rows(const HostBSR &P, const HostBSR &AP) {
   HostBSR S;
   S.n = P.n + AP.n;
@@ -917,8 +945,6 @@ HostBSR stack_rows(const HostBSR &P, const HostBSR &AP) {
   for (int32_t i = 1; i <= AP.n; i++) S.rp[P.n + i] = P.rp[P.n] + AP.rp[i];
   S.ci = P.ci;
   S.ci.insert(S.ci.end(), AP.ci.begin(), AP.ci.end());
-  S.v = P.v;
-  S.v.insert(S.v.end(), AP.v.begin(), AP.v.end());
   return S;
 }
 
@@ -1016,8 +1042,9 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     }
     build_prolongation(h, L, S);
     clk.tick(l, "DPLS");
-    HostBSR AP;
-    HostBSR Ac = galerkin(h, L, &AP);
+    HostBSR AP;              // pattern of A P
+    double *dPAP = nullptr;  // [P; A P] block values, on the device
+    HostBSR Ac = galerkin(h, L, &AP, &dPAP);
     clk.tick(l, "Galerkin");
     // device operators of this level
     // (G64 and GT64 come from build_fsai); FP32 copies share the layouts
@@ -1031,7 +1058,8 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
       L.nnzb_AP = AP.nnzb();
       HostBSR PAP = stack_rows(L.P, AP);
       AP = HostBSR();
-      L.PAP64 = upload_sell<double>(h, PAP);
+      L.PAP64 = upload_sell<double>(h, PAP, 0, true, dPAP);
+      dfree(h, dPAP);
       L.PAP32 = derive_fp32(h, L.PAP64);
     }
     clk.tick(l, "upload G P R");
