@@ -23,12 +23,29 @@
 
 namespace aspamg {
 
+// s rounded to `bits` significant bits (round to nearest, ties to even).  A
+// normal double keeps the top bits of its 53-bit significand, rounding the
+// dropped ones (a carry may step the exponent); zero, subnormal and
+// non-finite values take the frexp / ldexp form of the same rounding.
 double quantize(double s, int bits) {
-  if (s == 0.0 || !std::isfinite(s)) return s;
-  int e;
-  const double m = std::frexp(s, &e);
-  const double r = std::nearbyint(std::ldexp(m, bits));
-  return std::ldexp(r, e - bits);
+  uint64_t u;
+  std::memcpy(&u, &s, 8);
+  const uint64_t ex = (u >> 52) & 0x7FF;
+  if (ex == 0 || ex == 0x7FF) {
+    if (s == 0.0 || !std::isfinite(s)) return s;
+    int e;
+    const double m = std::frexp(s, &e);
+    const double r = std::nearbyint(std::ldexp(m, bits));
+    return std::ldexp(r, e - bits);
+  }
+  const int drop = 53 - bits;
+  const uint64_t mask = (1ULL << drop) - 1, half = 1ULL << (drop - 1);
+  const uint64_t rem = u & mask;
+  u &= ~mask;
+  if (rem > half || (rem == half && ((u >> drop) & 1))) u += 1ULL << drop;
+  double r;
+  std::memcpy(&r, &u, 8);
+  return r;
 }
 
 namespace {
