@@ -3,7 +3,7 @@
 Index work (C/F split, G pattern, scalar and block P pattern, Galerkin
 pattern) must match bit for bit; FSAI rows and Galerkin values come from the
 same sequential formulas and are compared bitwise too; Lanczos-based omega
-and the least-squares weights to tolerance; the solve to the spec bar."""
+and the least-squares weights to tolerance; the solve to 1e-8 of the oracle's u."""
 import numpy as np
 import pytest
 
