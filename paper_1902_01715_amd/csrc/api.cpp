@@ -438,7 +438,7 @@ Sell<float> derive_fp32(aspamg_ctx *h, const Sell<double> &S) {
   F.meta = S.meta;
   const int64_t nv = S.ngroups * 576;
   F.val = dalloc<float>(h, (size_t)std::max<int64_t>(nv, 1));
-  if (nv > 0) launch_cast<double, float>(nv, S.val, F.val, nullptr, h->stream);
+  if (nv > 0) launch_narrow_values(S.ngroups * 64, S.val, F.val, h->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(h->stream));
   return F;

@@ -59,9 +59,11 @@ struct DevBSR {
 
 // Device layout of one stored 3x3-block operator, one of two forms.  In both,
 // slot group g holds 64 entries: entry e has its column at col[g*64 + e] and
-// block entry k at val[(g*9 + k)*64 + e] (component-major, so every load
-// instruction of a wavefront covers 64 consecutive values); padded entries
-// hold 0 and a valid column.
+// its block values in the group's 576 values val[g*576 ...]: with W = 16 /
+// sizeof(T) values per 16-byte chunk, block entry k < 8 at
+// (k / W)*64*W + e*W + k % W and entry 8 at 512 + e.  Every load instruction of
+// a wavefront then reads 64 lane-consecutive 16-byte chunks (or 64 consecutive
+// entries 8); padded entries hold 0 and a valid column.
 //
 // Sliced ELL (pack == 0) with L lanes per block row (L a power of two,
 // 1..64): slice s is the 64/L consecutive rows one wavefront serves and owns
@@ -271,6 +273,8 @@ void launch_eye(int32_t nd, double *X, hipStream_t s);
 // layout values: slot i takes the 9 values of block map[i] of v (zeros when map[i] < 0)
 template <typename T>
 void launch_scatter_values(int64_t nslots, const int32_t *map, const double *v, T *val, hipStream_t s);
+// FP32 layout values from FP64 ones (same slots)
+void launch_narrow_values(int64_t nslots, const double *v64, float *v32, hipStream_t s);
 void launch_element_gradient(int64_t n_el, const int32_t *conn, const double *Ke0, int64_t ke_stride,
                              const double *lam, const double *u, const double *scale, double *grad,
                              hipStream_t s);

@@ -326,23 +326,36 @@ __global__ void __launch_bounds__(256) k_dense_mm(int32_t nd, const double *__re
 }
 
 // Layout values from the block values of the source matrix: slot i (slot
-// group i / 64, lane i % 64) takes block src = map[i] (its 9 values into the
-// group's nine 64-entry runs), or zeros when src < 0.
+// group i / 64, lane i % 64) takes block src = map[i] (its 9 values at the
+// lane's places in the group's 16-byte chunk rows and final run), or zeros
+// when src < 0.
 template <typename T>
 __global__ void __launch_bounds__(256) k_scatter_values(int64_t nslots, const int32_t *__restrict__ map,
                                                         const double *__restrict__ v, T *__restrict__ val) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= nslots) return;
   const int32_t src = map[i];
-  T *o = val + (i >> 6) * 576 + (i & 63);
-  if (src >= 0) {
-    const double *b = v + (int64_t)src * 9;
+  constexpr int W = 16 / sizeof(T);   // values per 16-byte chunk
+  T *g = val + (i >> 6) * 576;
+  const int e = (int)(i & 63);
+  const double *b = src >= 0 ? v + (int64_t)src * 9 : nullptr;
 #pragma unroll
-    for (int q = 0; q < 9; q++) o[q * 64] = (T)b[q];
-  } else {
+  for (int q = 0; q < 8; q++) g[(q / W) * 64 * W + e * W + (q % W)] = b ? (T)b[q] : (T)0;
+  g[512 + e] = b ? (T)b[8] : (T)0;
+}
+
+// FP32 copy of FP64 layout values: the same slots, each value rounded, moved
+// from the FP64 chunk order (pairs) to the FP32 one (quads).
+__global__ void __launch_bounds__(256) k_narrow_values(int64_t nslots, const double *__restrict__ v64,
+                                                       float *__restrict__ v32) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nslots) return;
+  const double *g = v64 + (i >> 6) * 576;
+  float *o = v32 + (i >> 6) * 576;
+  const int e = (int)(i & 63);
 #pragma unroll
-    for (int q = 0; q < 9; q++) o[q * 64] = (T)0;
-  }
+  for (int q = 0; q < 8; q++) o[(q / 4) * 256 + e * 4 + (q % 4)] = (float)g[(q / 2) * 128 + e * 2 + (q % 2)];
+  o[512 + e] = (float)g[512 + e];
 }
 
 // X = the nd x nd identity, row-major
@@ -374,6 +387,11 @@ void launch_scatter_values(int64_t nslots, const int32_t *map, const double *v, 
 }
 template void launch_scatter_values<double>(int64_t, const int32_t *, const double *, double *, hipStream_t);
 template void launch_scatter_values<float>(int64_t, const int32_t *, const double *, float *, hipStream_t);
+
+void launch_narrow_values(int64_t nslots, const double *v64, float *v32, hipStream_t s) {
+  if (nslots == 0) return;
+  hipLaunchKernelGGL(k_narrow_values, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s, nslots, v64, v32);
+}
 
 void launch_eye(int32_t nd, double *X, hipStream_t s) {
   const int64_t n = (int64_t)nd * nd;

@@ -29,6 +29,34 @@ __device__ __forceinline__ int32_t xcd_block() {
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
 
+typedef double wide_f64 __attribute__((ext_vector_type(2)));
+typedef float wide_f32 __attribute__((ext_vector_type(4)));
+
+// One slot's 3x3 block times (x0, x1, x2), accumulated into a0..a2; g is the
+// slot group (576 values), e the lane.  The first eight values of each lane
+// lie in 16-byte chunks, 64 lanes side by side per chunk row: FP64 pairs
+// (v0 v1)(v2 v3)(v4 v5)(v6 v7) at 128-entry strides, FP32 quads (v0..v3)(v4..v7)
+// at a 256-entry stride; v8 of the 64 lanes follows at 512.
+__device__ __forceinline__ void blk_fma(const double *g, int e, double x0, double x1, double x2, double &a0,
+                                        double &a1, double &a2) {
+  const wide_f64 *p = reinterpret_cast<const wide_f64 *>(g) + e;
+  const wide_f64 c0 = __builtin_nontemporal_load(p), c1 = __builtin_nontemporal_load(p + 64),
+                 c2 = __builtin_nontemporal_load(p + 128), c3 = __builtin_nontemporal_load(p + 192);
+  const double v8 = __builtin_nontemporal_load(g + 512 + e);
+  a0 += c0.x * x0 + c0.y * x1 + c1.x * x2;
+  a1 += c1.y * x0 + c2.x * x1 + c2.y * x2;
+  a2 += c3.x * x0 + c3.y * x1 + v8 * x2;
+}
+__device__ __forceinline__ void blk_fma(const float *g, int e, float x0, float x1, float x2, float &a0, float &a1,
+                                        float &a2) {
+  const wide_f32 *p = reinterpret_cast<const wide_f32 *>(g) + e;
+  const wide_f32 c0 = __builtin_nontemporal_load(p), c1 = __builtin_nontemporal_load(p + 64);
+  const float v8 = __builtin_nontemporal_load(g + 512 + e);
+  a0 += c0.x * x0 + c0.y * x1 + c0.z * x2;
+  a1 += c0.w * x0 + c1.x * x1 + c1.y * x2;
+  a2 += c1.z * x0 + c1.w * x1 + v8 * x2;
+}
+
 // Deterministic sum over a 256-thread block; the result is valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double *sm) {
 #pragma unroll
@@ -45,8 +73,8 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
 // y[row] = alpha * (A x)[row] (+ w[row]) on the sliced layout with L lanes per
 // block row.  A wavefront owns one slice of 64/L rows; lane e = r*L + j streams
 // entry e of every slot group of the slice: 64 consecutive column entries,
-// then 9 runs of 64 consecutive values.  The L partial sums of a row meet in a
-// butterfly and lane j = 0 writes the row.
+// then the group's values in 16-byte chunks (blk_fma).  The L partial sums of
+// a row meet in a butterfly and lane j = 0 writes the row.
 // With DUAL, rows r >= n1 write y2[r - n1] = alpha2 (A x)[r] + w2[r - n1].
 // CI is the stored column type: int32, or uint16 offsets from cbase[slice].
 template <typename T, typename TX, typename TO, bool HAS_W, int L, bool DUAL, typename CI>
@@ -64,14 +92,12 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
   const int32_t cb = sizeof(CI) == 2 ? cbase[sl] : 0;
   T a0 = 0, a1 = 0, a2 = 0;
   const CI *cp = col + (size_t)g0 * 64 + e;
-  const T *vp = val + (size_t)g0 * 576 + e;
+  const T *vp = val + (size_t)g0 * 576;
 #pragma unroll 2
   for (int32_t g = g0; g < g1; ++g) {
     const int32_t c = (int32_t)ld_stream(cp) + cb;
     const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
-    a0 += ld_stream(vp) * x0 + ld_stream(vp + 64) * x1 + ld_stream(vp + 128) * x2;
-    a1 += ld_stream(vp + 192) * x0 + ld_stream(vp + 256) * x1 + ld_stream(vp + 320) * x2;
-    a2 += ld_stream(vp + 384) * x0 + ld_stream(vp + 448) * x1 + ld_stream(vp + 512) * x2;
+    blk_fma(vp, e, x0, x1, x2, a0, a1, a2);
     cp += 64;
     vp += 576;
   }
@@ -125,15 +151,12 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
     m = meta[(size_t)wv * 64 + e];
     const int32_t cb = sizeof(CI) == 2 ? cbase[wv] : 0;
     const CI *cp = col + (size_t)wv * K * 64 + e;
-    const T *vp = val + (size_t)wv * K * 576 + e;
+    const T *vp = val + (size_t)wv * K * 576;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int32_t c = (int32_t)ld_stream(cp + 64 * k) + cb;
       const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
-      const T *v = vp + 576 * k;
-      a0 += ld_stream(v) * x0 + ld_stream(v + 64) * x1 + ld_stream(v + 128) * x2;
-      a1 += ld_stream(v + 192) * x0 + ld_stream(v + 256) * x1 + ld_stream(v + 320) * x2;
-      a2 += ld_stream(v + 384) * x0 + ld_stream(v + 448) * x1 + ld_stream(v + 512) * x2;
+      blk_fma(vp + 576 * k, e, x0, x1, x2, a0, a1, a2);
     }
   }
   // the lanes of a row never leave their wavefront, whose LDS operations
@@ -213,14 +236,12 @@ __global__ void __launch_bounds__(kDotThreads) k_sell_spmv_dot(int32_t n, const 
     const int32_t cb = sizeof(CI) == 2 ? cbase[sl] : 0;
     double a0 = 0, a1 = 0, a2 = 0;
     const CI *cp = col + (size_t)g0 * 64 + e;
-    const double *vp = val + (size_t)g0 * 576 + e;
+    const double *vp = val + (size_t)g0 * 576;
 #pragma unroll 2
     for (int32_t g = g0; g < g1; ++g) {
       const int32_t c = (int32_t)ld_stream(cp) + cb;
       const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
-      a0 += ld_stream(vp) * x0 + ld_stream(vp + 64) * x1 + ld_stream(vp + 128) * x2;
-      a1 += ld_stream(vp + 192) * x0 + ld_stream(vp + 256) * x1 + ld_stream(vp + 320) * x2;
-      a2 += ld_stream(vp + 384) * x0 + ld_stream(vp + 448) * x1 + ld_stream(vp + 512) * x2;
+      blk_fma(vp, e, x0, x1, x2, a0, a1, a2);
       cp += 64;
       vp += 576;
     }
