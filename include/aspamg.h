@@ -128,6 +128,10 @@ typedef struct {
   /* layout of the row-stacked [P; A P] operator (same encoding as sell_lanes64;
    * its FP32 copy shares it); 0 on the coarsest level */
   int32_t sell_stacked;
+  /* blocks of M = G^T G when the FP32 cycle's smoothing applies it as one
+   * stored operator (small levels above the dense tail), else 0 (G, then G^T;
+   * the FP64 cycle always applies G, then G^T) */
+  int64_t nnzb_M;
 } aspamg_level_info_t;
 
 /* Fill *out with the defaults.  out: caller-owned. */
@@ -177,7 +181,7 @@ aspamg_status aspamg_solve_batch(aspamg_handle h, int32_t k, const double *F_dev
 aspamg_status aspamg_vcycle(aspamg_handle h, const double *y_dev, double *z_dev);
 
 /* Apply one stored operator of level l: which = 0 A_l, 1 G_l, 2 G_l^T, 3 P_l,
- * 4 R_l = P_l^T; precision 64 or 32.  x_dev/y_dev are float64 device vectors
+ * 4 R_l = P_l^T, 5 M_l = G_l^T G_l (only where nnzb_M > 0); precision 64 or 32.  x_dev/y_dev are float64 device vectors
  * sized by the operator's columns/rows (converted when precision is 32). */
 aspamg_status aspamg_apply_operator(aspamg_handle h, int32_t level, int32_t which,
                                     int32_t precision, const double *x_dev, double *y_dev);

@@ -61,7 +61,7 @@ class LevelInfo(C.Structure):
         ("lambda1", C.c_double), ("omega_q", C.c_double), ("omega_s", C.c_double),
         ("sell_slots_A", C.c_int64), ("sell_slots_G", C.c_int64), ("sell_slots_GT", C.c_int64),
         ("sell_lanes64", C.c_int32 * 5), ("sell_lanes32", C.c_int32 * 5),
-        ("sell_index16", C.c_int32), ("sell_stacked", C.c_int32),
+        ("sell_index16", C.c_int32), ("sell_stacked", C.c_int32), ("nnzb_M", C.c_int64),
     ]
 
     def as_dict(self):
@@ -231,7 +231,7 @@ class Solver:
         return z
 
     def apply(self, level, which, x, precision=64, out_rows=None):
-        """Apply A (0), G (1), G^T (2), P (3) or R (4) of a level to x."""
+        """Apply A (0), G (1), G^T (2), P (3), R (4) or the merged G^T G (5) of a level to x."""
         import torch
         info = self.level_info(level)
         if out_rows is None:

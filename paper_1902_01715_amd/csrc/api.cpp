@@ -1,6 +1,7 @@
 // C ABI of the aSP-AMG library: handle lifetime, device layouts, the
 // V(nu1,nu2)-cycle driver and the PCG driver (one iteration captured as a HIP
 // graph and replayed, with a device-side control block deciding convergence).
+#include <type_traits>
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -14,7 +15,7 @@
 // sizes mirrored by the Python binding
 static_assert(sizeof(aspamg_params) == 160, "aspamg_params layout changed");
 static_assert(sizeof(aspamg_stats) == 96, "aspamg_stats layout changed");
-static_assert(sizeof(aspamg_level_info_t) == 136, "aspamg_level_info_t layout changed");
+static_assert(sizeof(aspamg_level_info_t) == 144, "aspamg_level_info_t layout changed");
 
 namespace aspamg {
 
@@ -487,6 +488,7 @@ struct Ops<double> {
   static const Sell<double> &P(const Level &L) { return L.P64; }
   static const Sell<double> &R(const Level &L) { return L.R64; }
   static const Sell<double> &PAP(const Level &L) { return L.PAP64; }
+  static const Sell<double> &M(const Level &L) { return L.M64; }
   static const LevelVecs<double> &V(const Level &L) { return L.v64; }
 };
 template <>
@@ -497,6 +499,7 @@ struct Ops<float> {
   static const Sell<float> &P(const Level &L) { return L.P32; }
   static const Sell<float> &R(const Level &L) { return L.R32; }
   static const Sell<float> &PAP(const Level &L) { return L.PAP32; }
+  static const Sell<float> &M(const Level &L) { return L.M32; }
   static const LevelVecs<float> &V(const Level &L) { return L.v32; }
 };
 
@@ -516,14 +519,26 @@ static void cycle_level(aspamg_ctx *h, int l, const T *y, T *z, const PcgCtrl *c
   const LevelVecs<T> &W = O::V(L);
   const LevelVecs<T> &Wn = O::V(h->lev[l + 1]);
   const double w = L.omega_s;
+  // z = w G^T G x (+ z).  The FP32 cycle uses the merged M on small levels:
+  // one launch, and one rounding of the FP64 product G^T G instead of an FP32
+  // intermediate G x (the FP64 cycle keeps G and G^T, whose two launches cost
+  // no more than M's larger FP64 copy there)
+  constexpr bool kMergedFp32 = std::is_same<T, float>::value;
+  const bool merged = kMergedFp32 && L.nnzb_M > 0;
+  auto smooth = [&](const T *x, const T *add) {
+    if (merged) {
+      launch_spmv<T, T, T>(O::M(L), x, z, add, w, ctrl, s);
+    } else {
+      launch_spmv<T, T, T>(O::G(L), x, W.t, nullptr, 1.0, ctrl, s);
+      launch_spmv<T, T, T>(O::GT(L), W.t, z, add, w, ctrl, s);
+    }
+  };
   for (int it = 0; it < h->p.nu1; it++) {
     if (it == 0) {
-      launch_spmv<T, T, T>(O::G(L), y, W.t, nullptr, 1.0, ctrl, s);
-      launch_spmv<T, T, T>(O::GT(L), W.t, z, nullptr, w, ctrl, s);
+      smooth(y, nullptr);
     } else {
       launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
-      launch_spmv<T, T, T>(O::G(L), W.r, W.t, nullptr, 1.0, ctrl, s);
-      launch_spmv<T, T, T>(O::GT(L), W.t, z, z, w, ctrl, s);
+      smooth(W.r, z);
     }
   }
   launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
@@ -534,8 +549,7 @@ static void cycle_level(aspamg_ctx *h, int l, const T *y, T *z, const PcgCtrl *c
   launch_spmv_dual<T, T, T>(O::PAP(L), L.P.n, Wn.z, z, z, 1.0, W.r, W.r, -1.0, ctrl, s);
   for (int it = 0; it < h->p.nu2; it++) {
     if (it > 0) launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
-    launch_spmv<T, T, T>(O::G(L), W.r, W.t, nullptr, 1.0, ctrl, s);
-    launch_spmv<T, T, T>(O::GT(L), W.t, z, z, w, ctrl, s);
+    smooth(W.r, z);
   }
 }
 
@@ -733,7 +747,10 @@ static double level_bytes(const aspamg_ctx *h, const Level &L) {
   // stacked [P; A P] once (first post-smoothing step, nu2 >= 1)
   const double usesA = (double)(h->p.nu1 + h->p.nu2 - 1);
   const double nu = (double)(h->p.nu1 + h->p.nu2);
-  return usesA * nA * block_bytes(O::A(L)) + nu * nG * (block_bytes(O::G(L)) + block_bytes(O::GT(L))) +
+  const bool merged = std::is_same<T, float>::value && L.nnzb_M > 0;
+  const double smooth = merged ? (double)L.nnzb_M * block_bytes(O::M(L))
+                               : nG * (block_bytes(O::G(L)) + block_bytes(O::GT(L)));
+  return usesA * nA * block_bytes(O::A(L)) + nu * smooth +
          nP * block_bytes(O::R(L)) + (nP + (double)L.nnzb_AP) * block_bytes(O::PAP(L)) +
          18.0 * 3.0 * L.A.n * sizeof(T);
 }
@@ -919,6 +936,7 @@ static aspamg_status setup_impl(const aspamg_params *pp, int32_t n_nodes, int64_
   build_hierarchy(h.get(), std::move(A), std::move(V));
   alloc_level_vectors(h.get());
   build_tail(h.get());
+  merge_smoothers(h.get());
   compute_complexities(h.get());
   h->prec = p.cycle_precision;
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -1050,17 +1068,18 @@ aspamg_status aspamg_vcycle(aspamg_handle h, const double *y_dev, double *z_dev)
 aspamg_status aspamg_apply_operator(aspamg_handle h, int32_t level, int32_t which, int32_t precision,
                                     const double *x_dev, double *y_dev) {
   ABI_BEGIN
-  if (!h || level < 0 || level >= (int32_t)h->lev.size() || which < 0 || which > 4 ||
+  if (!h || level < 0 || level >= (int32_t)h->lev.size() || which < 0 || which > 5 ||
       (precision != 32 && precision != 64) || !x_dev || !y_dev)
     fail(ASPAMG_EINVAL, "invalid arguments to aspamg_apply_operator");
   const Level &L = h->lev[level];
   if (L.coarsest && which != 0) fail(ASPAMG_EINVAL, "the coarsest level has only A");
+  if (which == 5 && L.nnzb_M == 0) fail(ASPAMG_EINVAL, "this level applies G and G^T (no merged G^T G)");
   hipStream_t s = h->stream;
   if (precision == 64) {
-    const Sell<double> *M[5] = {&L.A64, &L.G64, &L.GT64, &L.P64, &L.R64};
+    const Sell<double> *M[6] = {&L.A64, &L.G64, &L.GT64, &L.P64, &L.R64, &L.M64};
     launch_spmv<double, double, double>(*M[which], x_dev, y_dev, nullptr, 1.0, nullptr, s);
   } else {
-    const Sell<float> *M[5] = {&L.A32, &L.G32, &L.GT32, &L.P32, &L.R32};
+    const Sell<float> *M[6] = {&L.A32, &L.G32, &L.GT32, &L.P32, &L.R32, &L.M32};
     const int64_t nx = (int64_t)M[which]->nc * 3, ny = (int64_t)M[which]->n * 3;
     float *xs = nullptr, *ys = nullptr;
     HIPCHK(hipMalloc(&xs, std::max<int64_t>(nx, 1) * 4));
@@ -1105,6 +1124,7 @@ aspamg_status aspamg_level_info(aspamg_handle h, int32_t level, aspamg_level_inf
     if (M32[k]->col16) o->sell_index16 |= 1 << (5 + k);
   }
   o->sell_stacked = L.PAP64.pack ? -L.PAP64.pack : L.PAP64.lanes;
+  o->nnzb_M = L.nnzb_M;
   if (L.PAP64.col16) o->sell_index16 |= 1 << 10;
   return ASPAMG_OK;
 }

@@ -124,6 +124,12 @@ struct Level {
   Sell<double> PAP64;
   Sell<float> PAP32;
   int64_t nnzb_AP = 0;
+  // M = G^T G as one stored operator on small levels (nnzb_M > 0): each
+  // smoothing step of the FP32 cycle is then one product instead of G
+  // followed by G^T
+  Sell<double> M64;
+  Sell<float> M32;
+  int64_t nnzb_M = 0;
   bool coarsest = false;
   double lambda1 = 0, omega_q = 0, omega_s = 0;
   int32_t fsai_rounds = 0;
@@ -196,6 +202,8 @@ namespace aspamg {
 
 constexpr int kMaxPart = 8192;      // reduction partial slots per buffer
 constexpr int kMaxTailDof = 8192;   // largest dense tail operator (512 MB in FP64)
+constexpr int32_t kMergeMaxNodes = 10922;           // levels considered for M = G^T G
+constexpr double kMergeMaxBytes = 16.0 * (1 << 20);  // ... kept when its FP32 copy is at most this
 
 // ---- device memory helpers (tracked by the handle) ----
 void *dmalloc(aspamg_ctx *h, size_t bytes);
@@ -283,6 +291,8 @@ void launch_assemble(int64_t nnzb, const int64_t *slot_ptr, const int32_t *contr
 
 // ---- host setup (setup_host.cpp) ----
 void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0);
+// M = G^T G on the small smoothed levels above the dense tail
+void merge_smoothers(aspamg_ctx *h);
 double quantize(double s, int bits);
 
 // ---- multi-RHS solve (batch_api.cpp) ----

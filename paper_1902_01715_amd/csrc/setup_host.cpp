@@ -1012,7 +1012,40 @@ void build_coarse(aspamg_ctx *h, const HostBSR &A) {
   h->coarse.inv = upload(h, inv);
 }
 
+// M = G^T G for one level, numeric product on the device (the Galerkin
+// product's kernel with G^T and G as its operands), kept when its FP32 copy
+// is small: there every product costs about one dependent memory round trip,
+// so one launch of M replaces the launches of G and G^T in each smoothing step.
+void merge_smoother(aspamg_ctx *h, Level &L) {
+  const HostBSR GT = transpose(L.G);
+  HostBSR M = spgemm_pattern(GT, L.G, false);
+  if ((double)M.nnzb() * 38.0 > kMergeMaxBytes) return;
+  double *dM = dalloc<double>(h, (size_t)std::max<int64_t>(M.nnzb(), 1) * 9);
+  {
+    DevTmp tmp;
+    DevBSR dGT = tmp.make(GT, h->stream, true), dG = tmp.make(L.G, h->stream, true);
+    DevBSR dMb = tmp.make(M, h->stream, false);
+    dMb.v = dM;
+    launch_spgemm_ap(dGT, dG, dMb, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  L.M64 = upload_sell<double>(h, M, 0, true, dM);
+  dfree(h, dM);
+  L.M32 = derive_fp32(h, L.M64);
+  L.nnzb_M = M.nnzb();
+}
+
 }  // namespace
+
+void merge_smoothers(aspamg_ctx *h) {
+  const int end = h->tail.level >= 0 ? h->tail.level : (int)h->lev.size() - 1;
+  for (int l = 0; l < end; l++) {
+    Level &L = h->lev[l];
+    if (L.coarsest || L.A.n > kMergeMaxNodes) continue;
+    merge_smoother(h, L);
+  }
+}
 
 // ------------------------------------------------------------------------
 // hierarchy driver

@@ -31,7 +31,7 @@ def test_default_params_and_struct_layout():
     # the ctypes mirrors have the C struct sizes (asserted at compile time in the library)
     assert ctypes.sizeof(aspamg.Params) == 160
     assert ctypes.sizeof(aspamg.Stats) == 96
-    assert ctypes.sizeof(aspamg.LevelInfo) == 136
+    assert ctypes.sizeof(aspamg.LevelInfo) == 144
 
 
 def test_last_error_is_a_string():

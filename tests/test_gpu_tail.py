@@ -1,9 +1,10 @@
-"""The dense tail: the V-cycle from the highest level whose unknowns, and those
-of every level below it, number at most `dense_tail_dof` is formed at setup as
-one dense FP64 operator.  It is the same linear operator as the sparse cycle
+"""The small levels of the V-cycle.  The dense tail: the V-cycle from the
+highest level whose unknowns, and those of every level below it, number at
+most `dense_tail_dof` is formed at setup as one dense FP64 operator.  It is the same linear operator as the sparse cycle
 of those levels, so the V-cycle, the solve and the iteration counts must agree
 with the all-sparse cycle and the oracle up to rounding; the V-cycle stays
-symmetric (symmetric smoother, Galerkin coarse operators, nu1 = nu2)."""
+symmetric (symmetric smoother, Galerkin coarse operators, nu1 = nu2).  Small
+smoothed levels above the tail store M = G^T G and apply it in one product."""
 import numpy as np
 import pytest
 
@@ -104,3 +105,26 @@ def test_tail_parameter_bounds(cuda):
         aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, aspamg.default_params(dense_tail_dof=8193))
     with pytest.raises(aspamg.AspamgError):
         aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, aspamg.default_params(dense_tail_dof=-1))
+
+
+def test_merged_smoother_is_gtg(layered, product_bound):
+    import scipy.sparse as sp
+    import torch
+    _, St, Ss, _ = layered
+    merged = [l for l in range(St.nlev) if St.level_info(l)["nnzb_M"] > 0]
+    # the 4,131-node level 1 of the layered block merges; the 18,513-node fine level does not
+    assert merged == [1] and Ss.level_info(1)["nnzb_M"] > 0 and St.level_info(0)["nnzb_M"] == 0
+    li = St.level_info(1)
+    rp, ci, v = St.level_matrix(1, 1)
+    G = sp.bsr_matrix((v, ci, rp), shape=(3 * li["n"], 3 * li["n"])).tocsr()
+    # blocks of G^T G: the node pattern of G (ones) squared, no cancellation possible
+    Gn = sp.csr_matrix((np.ones(len(ci)), ci, rp), shape=(li["n"], li["n"]))
+    assert li["nnzb_M"] == (Gn.T @ Gn).nnz
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(3 * li["n"])
+    ref = G.T @ (G @ x)
+    for prec in (64, 32):
+        y = St.apply(1, 5, torch.tensor(x, device="cuda"), precision=prec).cpu().numpy()
+        # M's entries are sums over G's blocks: bound the two-stage product
+        bound = product_bound(abs(G).T @ abs(G), np.abs(x), prec) * 4
+        assert np.all(np.abs(y - ref) <= bound + 1e-300), prec
