@@ -156,7 +156,8 @@ aspamg_status aspamg_setup(const aspamg_params *p, int32_t n_nodes, int64_t nnzb
 
 /* Select the V-cycle precision for later solves: 64 (FP64 operators and
  * vectors) or 32 (FP32 operators and vectors inside FP64 PCG; the coarsest
- * solve stays FP64).  Both copies are built by aspamg_setup. */
+ * solve, and the dense tail operator that contains it, stay FP64).  Both
+ * copies are built by aspamg_setup. */
 aspamg_status aspamg_set_cycle_precision(aspamg_handle h, int32_t bits);
 
 /* PCG from u = 0 until ||r|| <= rtol ||f|| (Section 4).
@@ -181,8 +182,10 @@ aspamg_status aspamg_solve_batch(aspamg_handle h, int32_t k, const double *F_dev
 aspamg_status aspamg_vcycle(aspamg_handle h, const double *y_dev, double *z_dev);
 
 /* Apply one stored operator of level l: which = 0 A_l, 1 G_l, 2 G_l^T, 3 P_l,
- * 4 R_l = P_l^T, 5 M_l = G_l^T G_l (only where nnzb_M > 0); precision 64 or 32.  x_dev/y_dev are float64 device vectors
- * sized by the operator's columns/rows (converted when precision is 32). */
+ * 4 R_l = P_l^T, 5 M_l = G_l^T G_l (only where nnzb_M > 0); precision 64 or
+ * 32.  x_dev/y_dev are float64 device vectors sized by the operator's
+ * columns/rows (converted when precision is 32; that path allocates two
+ * staging vectors). */
 aspamg_status aspamg_apply_operator(aspamg_handle h, int32_t level, int32_t which,
                                     int32_t precision, const double *x_dev, double *y_dev);
 
@@ -238,7 +241,8 @@ aspamg_status aspamg_assembler_destroy(aspamg_assembler a);
  *   which = 0  PCG product q = K p with the fused p.q partials (FP64)
  *           1  fine-level residual r = y - A s, FP32 operator and vectors
  *           2  fine-level residual r = y - A s, FP64
- *           3  one whole V-cycle in FP32 (all levels and the coarsest solve)
+ *           3  one whole V-cycle in FP32 (every level; the dense tail or the
+ *              coarsest solve included)
  *           4  one whole V-cycle in FP64
  *   avg_ms, alg_bytes: caller-owned outputs.  Errors: EINVAL, EHIP. */
 aspamg_status aspamg_time_kernel(aspamg_handle h, int32_t which, int32_t reps, double *avg_ms,
