@@ -60,12 +60,15 @@ template <typename T>
 void launch_dense_gemm(int nd, const double *inv, const T *Y, T *Z, int ld, const BatchCtrl *c, hipStream_t s);
 void launch_col_dot(int64_t nrow, const double *A, const double *B, int ld, double *part, const BatchCtrl *c,
                     hipStream_t s);
-void launch_col_update(int64_t nrow, double *U, double *R, const double *P, const double *Q, const double *Z, int ld,
-                       double *part, const BatchCtrl *c, hipStream_t s);
+// z in the cycle precision TC; Rc (optional) receives r in that precision
+template <typename TC>
+void launch_col_update(int64_t nrow, double *U, double *R, const double *P, const double *Q, const TC *Z, TC *Rc,
+                       int ld, double *part, const BatchCtrl *c, hipStream_t s);
 template <typename TZ>
-void launch_col_rz(int64_t nrow, const double *R, const TZ *Zc, double *Z, int ld, double *part, const BatchCtrl *c,
+void launch_col_rz(int64_t nrow, const double *R, const TZ *Z, int ld, double *part, const BatchCtrl *c,
                    hipStream_t s);
-void launch_col_pupdate(int64_t nrow, const double *Z, double *P, int ld, const BatchCtrl *c, hipStream_t s);
+template <typename TZ>
+void launch_col_pupdate(int64_t nrow, const TZ *Z, double *P, int ld, const BatchCtrl *c, hipStream_t s);
 void launch_col_finish(int mode, const double *part, int nparts, int ld, BatchCtrl *c, hipStream_t s);
 void launch_copy_cols(int64_t nrow, int k, const double *src, int64_t lds, double *dst, int64_t ldd, int kfill,
                       hipStream_t s);

@@ -172,18 +172,22 @@ static void pcg_iteration_batch(aspamg_ctx *h, BatchWork *w, bool fp32) {
   const BatchLevel &B0 = w->lev[0];
   launch_spmm_dot(B0.d.A, w->P, w->Q, ld, kb, w->part, c, s);
   launch_col_finish(kFinAlpha, w->part, spmm_dot_parts(B0.d.A, ld, kb), ld, c, s);
-  launch_col_update(nrow, w->U, w->R, w->P, w->Q, w->Z, ld, w->part, c, s);
-  launch_col_finish(kFinRr, w->part, batch_vec_blocks(nrow, ld), ld, c, s);
   if (fp32) {
-    launch_cast<double, float>(nrow * ld, w->R, B0.f.y, nullptr, s);
+    // z (and z_old) stay in FP32; the update writes the cycle input r in FP32
+    launch_col_update<float>(nrow, w->U, w->R, w->P, w->Q, B0.f.z, B0.f.y, ld, w->part, c, s);
+    launch_col_finish(kFinRr, w->part, batch_vec_blocks(nrow, ld), ld, c, s);
     cycle_batch<float>(h, w, 0, B0.f.y, B0.f.z, kb, c);
-    launch_col_rz<float>(nrow, w->R, B0.f.z, w->Z, ld, w->part, c, s);
+    launch_col_rz<float>(nrow, w->R, B0.f.z, ld, w->part, c, s);
+    launch_col_finish(kFinBeta, w->part, batch_vec_blocks(nrow, ld), ld, c, s);
+    launch_col_pupdate<float>(nrow, B0.f.z, w->P, ld, c, s);
   } else {
+    launch_col_update<double>(nrow, w->U, w->R, w->P, w->Q, w->Z, nullptr, ld, w->part, c, s);
+    launch_col_finish(kFinRr, w->part, batch_vec_blocks(nrow, ld), ld, c, s);
     cycle_batch<double>(h, w, 0, w->R, w->Z, kb, c);
-    launch_col_rz<double>(nrow, w->R, w->Z, w->Z, ld, w->part, c, s);
+    launch_col_rz<double>(nrow, w->R, w->Z, ld, w->part, c, s);
+    launch_col_finish(kFinBeta, w->part, batch_vec_blocks(nrow, ld), ld, c, s);
+    launch_col_pupdate<double>(nrow, w->Z, w->P, ld, c, s);
   }
-  launch_col_finish(kFinBeta, w->part, batch_vec_blocks(nrow, ld), ld, c, s);
-  launch_col_pupdate(nrow, w->Z, w->P, ld, c, s);
 }
 
 // SpMM tile per precision: time one cycle for each candidate, keep the fastest

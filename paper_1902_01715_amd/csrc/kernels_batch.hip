@@ -165,9 +165,12 @@ __global__ void __launch_bounds__(256) k_col_dot(int64_t nrow, const double *__r
   col_partial(s, sm, part, ld, 0);
 }
 
+// z (z_old here) is read in the cycle precision TC; Rc (optional) receives r
+// in that precision, the next cycle's input.
+template <typename TC>
 __global__ void __launch_bounds__(256) k_col_update(int64_t nrow, double *__restrict__ U, double *__restrict__ R,
                                                     const double *__restrict__ P, const double *__restrict__ Q,
-                                                    const double *__restrict__ Z, int32_t ld,
+                                                    const TC *__restrict__ Z, TC *__restrict__ Rc, int32_t ld,
                                                     double *__restrict__ part, const BatchCtrl *ctrl) {
   __shared__ double sm[256];
   if (bdone(ctrl)) return;
@@ -179,35 +182,36 @@ __global__ void __launch_bounds__(256) k_col_update(int64_t nrow, double *__rest
     U[o] += alpha * P[o];
     const double ri = R[o] - alpha * Q[o];
     R[o] = ri;
+    if (Rc) Rc[o] = (TC)ri;
     s1 += ri * ri;
-    s2 += ri * Z[o];
+    s2 += ri * (double)Z[o];
   }
   col_partial(s1, sm, part, ld, 0);
   col_partial(s2, sm, part, ld, 1);
 }
 
+// r.z partials per column, z in the cycle precision
 template <typename TZ>
 __global__ void __launch_bounds__(256) k_col_rz(int64_t nrow, const double *__restrict__ R,
-                                                const TZ *__restrict__ Zc, double *__restrict__ Z, int32_t ld,
-                                                double *__restrict__ part, const BatchCtrl *ctrl) {
+                                                const TZ *__restrict__ Z, int32_t ld, double *__restrict__ part,
+                                                const BatchCtrl *ctrl) {
   __shared__ double sm[256];
   if (bdone(ctrl)) return;
   const int rpb = 256 / ld, r0 = threadIdx.x / ld, j = threadIdx.x % ld;
   double s = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * rpb + r0; i < nrow; i += (int64_t)gridDim.x * rpb) {
     const int64_t o = i * ld + j;
-    const double zi = (double)Zc[o];
-    if ((const void *)Zc != (const void *)Z) Z[o] = zi;
-    s += R[o] * zi;
+    s += R[o] * (double)Z[o];
   }
   col_partial(s, sm, part, ld, 0);
 }
 
-__global__ void __launch_bounds__(256) k_col_pupdate(int64_t n, const double *__restrict__ Z, double *__restrict__ P,
+template <typename TZ>
+__global__ void __launch_bounds__(256) k_col_pupdate(int64_t n, const TZ *__restrict__ Z, double *__restrict__ P,
                                                      int32_t ld, const BatchCtrl *ctrl) {
   if (bdone(ctrl)) return;
   for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < n; o += (int64_t)gridDim.x * 256)
-    P[o] = Z[o] + ctrl->beta[o % ld] * P[o];
+    P[o] = (double)Z[o] + ctrl->beta[o % ld] * P[o];
 }
 
 // Per-column scalar steps; thread j owns column j.  A finished column gets
@@ -388,26 +392,34 @@ void launch_col_dot(int64_t nrow, const double *A, const double *B, int ld, doub
                     hipStream_t s) {
   hipLaunchKernelGGL(k_col_dot, dim3(batch_vec_blocks(nrow, ld)), dim3(256), 0, s, nrow, A, B, ld, part, c);
 }
-void launch_col_update(int64_t nrow, double *U, double *R, const double *P, const double *Q, const double *Z, int ld,
-                       double *part, const BatchCtrl *c, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_update, dim3(batch_vec_blocks(nrow, ld)), dim3(256), 0, s, nrow, U, R, P, Q, Z, ld, part,
-                     c);
+template <typename TC>
+void launch_col_update(int64_t nrow, double *U, double *R, const double *P, const double *Q, const TC *Z, TC *Rc,
+                       int ld, double *part, const BatchCtrl *c, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_update<TC>, dim3(batch_vec_blocks(nrow, ld)), dim3(256), 0, s, nrow, U, R, P, Q, Z, Rc,
+                     ld, part, c);
 }
+template void launch_col_update<double>(int64_t, double *, double *, const double *, const double *, const double *,
+                                        double *, int, double *, const BatchCtrl *, hipStream_t);
+template void launch_col_update<float>(int64_t, double *, double *, const double *, const double *, const float *,
+                                       float *, int, double *, const BatchCtrl *, hipStream_t);
 template <typename TZ>
-void launch_col_rz(int64_t nrow, const double *R, const TZ *Zc, double *Z, int ld, double *part, const BatchCtrl *c,
+void launch_col_rz(int64_t nrow, const double *R, const TZ *Z, int ld, double *part, const BatchCtrl *c,
                    hipStream_t s) {
-  hipLaunchKernelGGL(k_col_rz<TZ>, dim3(batch_vec_blocks(nrow, ld)), dim3(256), 0, s, nrow, R, Zc, Z, ld, part, c);
+  hipLaunchKernelGGL(k_col_rz<TZ>, dim3(batch_vec_blocks(nrow, ld)), dim3(256), 0, s, nrow, R, Z, ld, part, c);
 }
-template void launch_col_rz<double>(int64_t, const double *, const double *, double *, int, double *,
-                                    const BatchCtrl *, hipStream_t);
-template void launch_col_rz<float>(int64_t, const double *, const float *, double *, int, double *,
-                                   const BatchCtrl *, hipStream_t);
-void launch_col_pupdate(int64_t nrow, const double *Z, double *P, int ld, const BatchCtrl *c, hipStream_t s) {
+template void launch_col_rz<double>(int64_t, const double *, const double *, int, double *, const BatchCtrl *,
+                                    hipStream_t);
+template void launch_col_rz<float>(int64_t, const double *, const float *, int, double *, const BatchCtrl *,
+                                   hipStream_t);
+template <typename TZ>
+void launch_col_pupdate(int64_t nrow, const TZ *Z, double *P, int ld, const BatchCtrl *c, hipStream_t s) {
   const int64_t n = nrow * ld;
   int64_t b = (n + 255) / 256;
   if (b > 2048) b = 2048;
-  hipLaunchKernelGGL(k_col_pupdate, dim3((unsigned)b), dim3(256), 0, s, n, Z, P, ld, c);
+  hipLaunchKernelGGL(k_col_pupdate<TZ>, dim3((unsigned)b), dim3(256), 0, s, n, Z, P, ld, c);
 }
+template void launch_col_pupdate<double>(int64_t, const double *, double *, int, const BatchCtrl *, hipStream_t);
+template void launch_col_pupdate<float>(int64_t, const float *, double *, int, const BatchCtrl *, hipStream_t);
 void launch_col_finish(int mode, const double *part, int nparts, int ld, BatchCtrl *c, hipStream_t s) {
   if (ld < 1 || ld > 64 || 1024 % ld != 0) fail(ASPAMG_EINVAL, "column count must divide 1024");
   hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(1024), 0, s, mode, part, nparts, ld, c);
