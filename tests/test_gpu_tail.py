@@ -128,3 +128,32 @@ def test_merged_smoother_is_gtg(layered, product_bound):
         # M's entries are sums over G's blocks: bound the two-stage product
         bound = product_bound(abs(G).T @ abs(G), np.abs(x), prec) * 4
         assert np.all(np.abs(y - ref) <= bound + 1e-300), prec
+
+
+def test_tail_over_two_smoothed_levels(cuda, oracle_lib):
+    """dense_tail_dof = 8192 on the 12^3 cube (6,591 / 2,019 / 441 DOF) folds the
+    whole cycle, two smoothed levels and the coarsest, into one dense operator."""
+    import torch
+    from paper_1902_01715_amd import aspamg
+    p = PR.c1_cube(12)
+    print("[case cube 12^3 tail 8192]", flush=True)
+    S8 = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, aspamg.default_params(dense_tail_dof=8192))
+    S0 = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, aspamg.default_params(dense_tail_dof=0))
+    H = oracle_lib.Hierarchy(p.row_ptr, p.col, p.vals, p.V0)
+    assert S8.nlev == H.nlev == 3
+    f = torch.tensor(p.f, device="cuda")
+    rng = np.random.default_rng(12)
+    y = rng.standard_normal(p.f.shape[0])
+    z8 = S8.vcycle(torch.tensor(y, device="cuda")).cpu().numpy()
+    z0 = S0.vcycle(torch.tensor(y, device="cuda")).cpu().numpy()
+    zo = H.vcycle(y)
+    assert np.linalg.norm(z8 - z0) <= 1e-11 * np.linalg.norm(z0)
+    assert np.linalg.norm(z8 - zo) <= 1e-11 * np.linalg.norm(zo)
+    uo, sto = H.pcg(p.f, 1e-10, 1000)
+    u = S8.solve(f, check=False).cpu().numpy()
+    st = S8.last_stats
+    assert st["tail_level"] == 0 and st["status"] == 0
+    assert abs(st["iterations"] - sto["iterations"]) <= 1
+    assert np.linalg.norm(u - uo) <= 1e-8 * np.linalg.norm(uo)
+    S8.close()
+    S0.close()
