@@ -278,6 +278,8 @@ void launch_bsr_mm(const DevBSR &M, const double *X, double *Y, const double *W,
                    hipStream_t s);
 void launch_dense_mm(int32_t nd, const double *D, const double *X, double *Y, int32_t nb, hipStream_t s);
 void launch_eye(int32_t nd, double *X, hipStream_t s);
+void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);     // y += a x
+void launch_divided(int64_t n, double a, const double *x, double *y, hipStream_t s);  // y = x / a
 // layout values: slot i takes the 9 values of block map[i] of v (zeros when map[i] < 0)
 template <typename T>
 void launch_scatter_values(int64_t nslots, const int32_t *map, const double *v, T *val, hipStream_t s);

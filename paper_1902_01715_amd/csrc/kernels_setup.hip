@@ -358,6 +358,16 @@ __global__ void __launch_bounds__(256) k_narrow_values(int64_t nslots, const dou
   o[512 + e] = (float)g[512 + e];
 }
 
+// y += a x and y = x / a (the Lanczos recurrence of the aFSAI set-up)
+__global__ void __launch_bounds__(256) k_axpy(int64_t n, double a, const double *__restrict__ x,
+                                              double *__restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] += a * x[i];
+}
+__global__ void __launch_bounds__(256) k_divided(int64_t n, double a, const double *__restrict__ x,
+                                                 double *__restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = x[i] / a;
+}
+
 // X = the nd x nd identity, row-major
 __global__ void __launch_bounds__(256) k_eye(int64_t nd, double *__restrict__ X) {
   const int64_t n = nd * nd;
@@ -391,6 +401,17 @@ template void launch_scatter_values<float>(int64_t, const int32_t *, const doubl
 void launch_narrow_values(int64_t nslots, const double *v64, float *v32, hipStream_t s) {
   if (nslots == 0) return;
   hipLaunchKernelGGL(k_narrow_values, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s, nslots, v64, v32);
+}
+
+static unsigned setup_vec_blocks(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)std::min<int64_t>(std::max<int64_t>(b, 1), 2048);
+}
+void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(setup_vec_blocks(n)), dim3(256), 0, s, n, a, x, y);
+}
+void launch_divided(int64_t n, double a, const double *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_divided, dim3(setup_vec_blocks(n)), dim3(256), 0, s, n, a, x, y);
 }
 
 void launch_eye(int32_t nd, double *X, hipStream_t s) {

@@ -348,34 +348,26 @@ double lanczos_gagt(aspamg_ctx *h, const Level &L, const Sell<double> &G, const 
     for (int i = 0; i < nb; i++) acc += hp[i];
     return acc;
   };
+  // the recurrence on the device; the two inner products per step are summed
+  // from their block partials in block order on the host
   double bprev = 0.0;
   for (int j = 0; j < steps; j++) {
     launch_spmv<double, double, double>(GT, v, dt1.as<double>(), nullptr, 1.0, nullptr, s);
     launch_spmv<double, double, double>(L.A64, dt1.as<double>(), dt2.as<double>(), nullptr, 1.0, nullptr, s);
     launch_spmv<double, double, double>(G, dt2.as<double>(), u, nullptr, 1.0, nullptr, s);
     // u -= bprev vp ; a = v.u ; u -= a v ; b = |u|
-    std::vector<double> hu(n), hv(n), hvp(n);
-    to_host(s, hu.data(), u, n);
-    to_host(s, hv.data(), v, n);
-    if (j > 0) {
-      to_host(s, hvp.data(), vp, n);
-      for (int64_t i = 0; i < n; i++) hu[i] -= bprev * hvp[i];
-    }
-    double a = 0.0;
-    for (int64_t i = 0; i < n; i++) a += hv[i] * hu[i];
-    for (int64_t i = 0; i < n; i++) hu[i] -= a * hv[i];
-    double bb = 0.0;
-    for (int64_t i = 0; i < n; i++) bb += hu[i] * hu[i];
-    bb = std::sqrt(bb);
+    if (j > 0) launch_axpy(n, -bprev, vp, u, s);
+    const double a = dotv(v, u);
+    launch_axpy(n, -a, v, u, s);
+    const double bb = std::sqrt(dotv(u, u));
     al.push_back(a);
     be.push_back(bb);
     if (!(bb > 1e-300)) break;
-    for (int64_t i = 0; i < n; i++) hu[i] /= bb;
     HIPCHK(hipMemcpyAsync(vp, v, n * 8, hipMemcpyDeviceToDevice, s));
-    to_device(s, v, hu.data(), n);
+    launch_divided(n, bb, u, v, s);
     bprev = bb;
   }
-  (void)dotv;
+  HIPCHK(hipGetLastError());
   // Sturm bisection for the largest eigenvalue of the tridiagonal matrix
   const int m = (int)al.size();
   double lo = al[0], hi = al[0];
@@ -974,37 +966,48 @@ void build_coarse(aspamg_ctx *h, const HostBSR &A) {
     for (int64_t k = A.rp[i]; k < A.rp[i + 1]; k++)
       for (int d = 0; d < 3; d++)
         for (int e = 0; e < 3; e++) M[(size_t)(i * 3 + d) * nd + A.ci[k] * 3 + e] = A.v[(size_t)k * 9 + d * 3 + e];
-  for (int32_t j = 0; j < nd; j++) {
-    double acc = 0.0;
-    for (int32_t k = 0; k < j; k++) acc += Lm[(size_t)j * nd + k] * Lm[(size_t)j * nd + k];
-    const double d = M[(size_t)j * nd + j] - acc;
-    if (!(d > 0.0)) fail(ASPAMG_ENOT_SPD, "coarsest matrix is not positive definite");
-    const double ljj = std::sqrt(d);
-    Lm[(size_t)j * nd + j] = ljj;
-#pragma omp parallel for schedule(static)
+  // left-looking Cholesky, column by column, in one parallel region
+  bool spd = true;
+#pragma omp parallel
+  for (int32_t j = 0; j < nd && spd; j++) {
+#pragma omp single
+    {
+      double acc = 0.0;
+      for (int32_t k = 0; k < j; k++) acc += Lm[(size_t)j * nd + k] * Lm[(size_t)j * nd + k];
+      const double d = M[(size_t)j * nd + j] - acc;
+      if (!(d > 0.0)) spd = false;
+      else Lm[(size_t)j * nd + j] = std::sqrt(d);
+    }   // implicit barrier: every thread sees spd and the pivot
+    if (!spd) break;
+    const double ljj = Lm[(size_t)j * nd + j];
+#pragma omp for schedule(static)
     for (int32_t i = j + 1; i < nd; i++) {
       double a2 = 0.0;
       for (int32_t k = 0; k < j; k++) a2 += Lm[(size_t)i * nd + k] * Lm[(size_t)j * nd + k];
       Lm[(size_t)i * nd + j] = (M[(size_t)i * nd + j] - a2) / ljj;
     }
   }
-  // X = L^{-1} (lower), column by column
-  std::vector<double> X((size_t)nd * nd, 0.0);
+  if (!spd) fail(ASPAMG_ENOT_SPD, "coarsest matrix is not positive definite");
+  // X = L^{-1} (lower), column by column; row c of Xt holds column c of X so
+  // that both products below read contiguous memory
+  std::vector<double> Xt((size_t)nd * nd, 0.0);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int32_t c = 0; c < nd; c++) {
+    double *xc = Xt.data() + (size_t)c * nd;
     for (int32_t i = c; i < nd; i++) {
       double acc = i == c ? 1.0 : 0.0;
-      for (int32_t k = c; k < i; k++) acc -= Lm[(size_t)i * nd + k] * X[(size_t)k * nd + c];
-      X[(size_t)i * nd + c] = acc / Lm[(size_t)i * nd + i];
+      for (int32_t k = c; k < i; k++) acc -= Lm[(size_t)i * nd + k] * xc[k];
+      xc[i] = acc / Lm[(size_t)i * nd + i];
     }
   }
-  // inv = X^T X
+  // inv = X^T X: inv[i][j] = sum over k >= max(i, j) of X[k][i] X[k][j]
   std::vector<double> inv((size_t)nd * nd, 0.0);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int32_t i = 0; i < nd; i++)
     for (int32_t j = 0; j <= i; j++) {
+      const double *xi = Xt.data() + (size_t)i * nd, *xj = Xt.data() + (size_t)j * nd;
       double s = 0.0;
-      for (int32_t k = std::max(i, j); k < nd; k++) s += X[(size_t)k * nd + i] * X[(size_t)k * nd + j];
+      for (int32_t k = std::max(i, j); k < nd; k++) s += xi[k] * xj[k];
       inv[(size_t)i * nd + j] = s;
       inv[(size_t)j * nd + i] = s;
     }
