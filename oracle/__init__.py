@@ -36,7 +36,7 @@ class Params(C.Structure):
         ("eps_p", C.c_double), ("lanczos_steps", C.c_int32), ("omega_safety", C.c_double),
         ("coarse_max_dof", C.c_int32), ("max_levels", C.c_int32), ("stall_ratio", C.c_double),
         ("nu1", C.c_int32), ("nu2", C.c_int32), ("quant_bits", C.c_int32),
-        ("dense_max_dof", C.c_int32),
+        ("dense_max_dof", C.c_int32), ("n_rq", C.c_int32), ("k_ritz", C.c_int32),
     ]
 
 
@@ -76,6 +76,8 @@ def lib():
         L.oracle_fsai_rows.argtypes = [C.POINTER(Params), C.c_int32, P, P, P, C.c_int32, P, P, P, P, P]
         L.oracle_lanczos.restype = C.c_double
         L.oracle_lanczos.argtypes = [C.c_int32, C.c_int, P, P, P, P, P, P, C.c_int]
+        L.oracle_srqcg.restype = C.c_int
+        L.oracle_srqcg.argtypes = [C.c_int32, C.c_int, P, P, P, P, P, P, C.c_int, P, C.c_int, C.c_int, P]
         L.oracle_dpls_row.restype = C.c_int
         L.oracle_dpls_row.argtypes = [C.POINTER(Params), P, P, C.c_int, C.c_int, P, P]
         L.oracle_rap.restype = C.c_int
@@ -294,6 +296,21 @@ def lanczos(rp, ci, v, G: BSR, steps=30, b=3):
     n = rp.shape[0] - 1
     grp, gci, gv = _bsr_args(G.rp, G.ci, G.v)
     return lib().oracle_lanczos(n, b, _p(rp), _p(ci), _p(v), _p(grp), _p(gci), _p(gv), steps)
+
+
+def srqcg(rp, ci, v, G: BSR, V0, kmax, kritz=1, b=3):
+    """Test space by SRQCG on S = G A G^T; V0 [n*b, nt].  Returns (G^T Z, the
+    final Rayleigh quotients of the columns of Z)."""
+    rp, ci, v = _bsr_args(rp, ci, v)
+    n = rp.shape[0] - 1
+    grp, gci, gv = _bsr_args(G.rp, G.ci, G.v)
+    V = np.array(V0, dtype=np.float64, order="C", copy=True).reshape(n * b, -1)
+    nt = V.shape[1]
+    rq = np.zeros(nt)
+    rc = lib().oracle_srqcg(n, b, _p(rp), _p(ci), _p(v), _p(grp), _p(gci), _p(gv), nt, _p(V), kmax, kritz, _p(rq))
+    if rc != 0:
+        raise RuntimeError(f"srqcg failed {rc}")
+    return V, rq
 
 
 def dpls_row(params, v, Cm):

@@ -14,7 +14,8 @@
  *                                eqs. (2)-(4) (pre-/post-smoothing, coarse correction)
  *   aFSAI smoother ............. Section 3.1, S = I - omega G^T G A, and the
  *                                Algorithm "aFSAI Smoother Set-up"
- *   test space ................. Section 3.3 (rigid-body modes as V0, orthonormalised)
+ *   test space ................. Section 3.3 (V0 given; optional SRQCG smoothing by the
+ *                                Algorithm "Test Space generation by SRQCG"; orthonormalised)
  *   affinity SoC + theta + MIS . Section 3.4, eq. (SoC)
  *   DPLS prolongation .......... Section 3.5, eq. (minDPLS) and the Algorithm
  *                                "Dynamic Pattern Least Squares Prolongation"
@@ -60,6 +61,8 @@ typedef struct {
   int32_t nu1, nu2;       /* pre / post smoothing steps                        */
   int32_t quant_bits;     /* significant bits of decision quantisation         */
   int32_t dense_max_dof;  /* refuse a dense coarsest system larger than this   */
+  int32_t n_rq;           /* SRQCG iterations on each level's test space (0: none) */
+  int32_t k_ritz;         /* Ritz projection every k_ritz SRQCG iterations     */
 } oparams;
 
 /* status codes */
@@ -117,7 +120,7 @@ void oracle_default_params(oparams *p) {
   p->kappa_p = 50.0; p->omega_bar = 0.8; p->outer_fsai = 1; p->d_p = 2; p->eps_p = 1e-8;
   p->lanczos_steps = 30; p->omega_safety = 1.05; p->coarse_max_dof = 1500;
   p->max_levels = 25; p->stall_ratio = 0.9; p->nu1 = 1; p->nu2 = 1; p->quant_bits = 20;
-  p->dense_max_dof = 16384;
+  p->dense_max_dof = 16384; p->n_rq = 0; p->k_ritz = 1;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -575,6 +578,252 @@ static int orthonormalize(double *V, int64_t nrows, int ntv) {
     memcpy(v, y, ntv * sizeof(double));
   }
   return O_OK;
+}
+
+/* ========================================================================= */
+/* test space by SRQCG (Section 3.3, Algorithm "Test Space generation by      */
+/* SRQCG"): simultaneous minimisation of the Rayleigh quotients of the columns */
+/* of Z for S = G A G^T by conjugate gradients, with a Ritz projection every   */
+/* k_ritz iterations, then V = G^T Z.  Readings where the algorithm is terse:  */
+/*   - q is the Rayleigh quotient z^T S z / z^T z; f_i starts at 1 and is set   */
+/*     to z_i^T z_i after each update of column i (not after a projection);     */
+/*   - S Z is formed by products at every projection and then carried:         */
+/*     S z_i <- S z_i + alpha S p_i after an update, S Z <- (S Z) U after a     */
+/*     projection;                                                             */
+/*   - the projection solves (Z^T S Z) U = (Z^T Z) U Lambda through the         */
+/*     Cholesky factor of Z^T Z and Jacobi rotations, eigenvalues ascending,    */
+/*     each eigenvector with its largest-magnitude entry positive (the first    */
+/*     such entry on ties); it is skipped when Z^T Z is not positive definite;  */
+/*   - a column update with 2(bc - ad) = 0 or Delta < 0 is skipped;            */
+/*   - exactly k_max iterations run (no early exit).                           */
+/* Z and V are row-major [nrows][nt] like the test space.                      */
+/* ========================================================================= */
+
+/* S x = G (A (G^T x)) */
+static void apply_gagt(const obsr *A, const obsr *G, const obsr *GT, const double *x, double *y, double *t1,
+                       double *t2) {
+  bsr_mv(GT, x, t1);
+  bsr_mv(A, t1, t2);
+  bsr_mv(G, t2, y);
+}
+
+/* symmetric m x m matrix C (destroyed): C = X diag(w) X^T by cyclic Jacobi
+ * sweeps (Golub and Van Loan, "Matrix Computations", Section 8.5); w ascending,
+ * eigenvectors in the columns of X */
+static void jacobi_eigen(double *C, int m, double *w, double *X) {
+  for (int i = 0; i < m; i++)
+    for (int j = 0; j < m; j++) X[i * m + j] = i == j ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 100; sweep++) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < m; i++)
+      for (int j = 0; j < m; j++) {
+        tot += C[i * m + j] * C[i * m + j];
+        if (i != j) off += C[i * m + j] * C[i * m + j];
+      }
+    if (!(off > 1e-32 * tot)) break;
+    for (int p = 0; p < m - 1; p++)
+      for (int q = p + 1; q < m; q++) {
+        double apq = C[p * m + q];
+        if (apq == 0.0) continue;
+        /* rotation that zeroes C[p][q]: tan t = sign(theta) / (|theta| + sqrt(theta^2 + 1)) */
+        double theta = (C[q * m + q] - C[p * m + p]) / (2.0 * apq);
+        double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < m; k++) {      /* columns p, q: C <- C J */
+          double ckp = C[k * m + p], ckq = C[k * m + q];
+          C[k * m + p] = c * ckp - s * ckq;
+          C[k * m + q] = s * ckp + c * ckq;
+        }
+        for (int k = 0; k < m; k++) {      /* rows p, q: C <- J^T C */
+          double cpk = C[p * m + k], cqk = C[q * m + k];
+          C[p * m + k] = c * cpk - s * cqk;
+          C[q * m + k] = s * cpk + c * cqk;
+        }
+        for (int k = 0; k < m; k++) {      /* X <- X J */
+          double xkp = X[k * m + p], xkq = X[k * m + q];
+          X[k * m + p] = c * xkp - s * xkq;
+          X[k * m + q] = s * xkp + c * xkq;
+        }
+      }
+  }
+  for (int i = 0; i < m; i++) w[i] = C[i * m + i];
+  /* selection sort, ascending eigenvalues (stable for equal values) */
+  for (int i = 0; i < m; i++) {
+    int k = i;
+    for (int j = i + 1; j < m; j++)
+      if (w[j] < w[k]) k = j;
+    if (k != i) {
+      double tw = w[i]; w[i] = w[k]; w[k] = tw;
+      for (int r = 0; r < m; r++) { double tx = X[r * m + i]; X[r * m + i] = X[r * m + k]; X[r * m + k] = tx; }
+    }
+  }
+}
+
+/* Ritz step: U with (Z^T S Z) U = (Z^T Z) U Lambda; returns -1 when Z^T Z is not SPD */
+static int ritz_vectors(const double *Z, const double *SZ, int64_t nr, int nt, double *U) {
+  double Ms[64 * 64], Mz[64 * 64], L[64 * 64], C[64 * 64], T[64 * 64], X[64 * 64], w[64];
+  for (int a = 0; a < nt; a++)
+    for (int c = 0; c < nt; c++) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int64_t i = 0; i < nr; i++) {
+        s1 += Z[i * nt + a] * SZ[i * nt + c];
+        s2 += Z[i * nt + a] * Z[i * nt + c];
+      }
+      Ms[a * nt + c] = s1;
+      Mz[a * nt + c] = s2;
+    }
+  for (int a = 0; a < nt; a++)          /* symmetric parts */
+    for (int c = 0; c < a; c++) {
+      double s = 0.5 * (Ms[a * nt + c] + Ms[c * nt + a]);
+      Ms[a * nt + c] = Ms[c * nt + a] = s;
+    }
+  if (chol_small(Mz, L, nt)) return -1;
+  /* T = L^{-1} Ms (forward substitution column by column), C = T L^{-T} */
+  for (int c = 0; c < nt; c++)
+    for (int i = 0; i < nt; i++) {
+      double acc = Ms[i * nt + c];
+      for (int k = 0; k < i; k++) acc -= L[i * nt + k] * T[k * nt + c];
+      T[i * nt + c] = acc / L[i * nt + i];
+    }
+  for (int r = 0; r < nt; r++)
+    for (int i = 0; i < nt; i++) {
+      double acc = T[r * nt + i];
+      for (int k = 0; k < i; k++) acc -= L[i * nt + k] * C[r * nt + k];
+      C[r * nt + i] = acc / L[i * nt + i];
+    }
+  for (int a = 0; a < nt; a++)
+    for (int c = 0; c < a; c++) {
+      double s = 0.5 * (C[a * nt + c] + C[c * nt + a]);
+      C[a * nt + c] = C[c * nt + a] = s;
+    }
+  jacobi_eigen(C, nt, w, X);
+  /* U = L^{-T} X (back substitution), then the sign rule */
+  for (int c = 0; c < nt; c++) {
+    for (int i = nt - 1; i >= 0; i--) {
+      double acc = X[i * nt + c];
+      for (int k = i + 1; k < nt; k++) acc -= L[k * nt + i] * U[k * nt + c];
+      U[i * nt + c] = acc / L[i * nt + i];
+    }
+    int imax = 0;
+    for (int i = 1; i < nt; i++)
+      if (fabs(U[i * nt + c]) > fabs(U[imax * nt + c])) imax = i;
+    if (U[imax * nt + c] < 0.0)
+      for (int i = 0; i < nt; i++) U[i * nt + c] = -U[i * nt + c];
+  }
+  return 0;
+}
+
+/* V (row-major [nr][nt], in: V0, out: G^T Z); rq (optional, nt entries):
+ * the Rayleigh quotients of the columns of Z at the end */
+static int srqcg(const obsr *A, const obsr *G, double *V, int nt, int kmax, int kritz, double *rq) {
+  int64_t nr = (int64_t)A->n * A->b;
+  if (nt < 1 || nt > 64 || kritz < 1 || kmax < 0) return O_EINVAL;
+  obsr GT = {0};
+  int rc = bsr_transpose(G, &GT);
+  double *Z = malloc((size_t)nr * nt * sizeof(double)), *SZ = malloc((size_t)nr * nt * sizeof(double));
+  double *Pd = malloc((size_t)nr * nt * sizeof(double));
+  double *x = malloc((size_t)nr * sizeof(double)), *y = malloc((size_t)nr * sizeof(double));
+  double *t1 = malloc((size_t)nr * sizeof(double)), *t2 = malloc((size_t)nr * sizeof(double));
+  double *sp = malloc((size_t)nr * sizeof(double)), *g = malloc((size_t)nr * sizeof(double));
+  double f[64], U[64 * 64];
+  if (rc || !Z || !SZ || !Pd || !x || !y || !t1 || !t2 || !sp || !g) { rc = O_ENOMEM; goto done; }
+  /* Z0 = (I - S) V0, orthonormalised */
+  for (int c = 0; c < nt; c++) {
+    for (int64_t i = 0; i < nr; i++) x[i] = V[i * nt + c];
+    apply_gagt(A, G, &GT, x, y, t1, t2);
+    for (int64_t i = 0; i < nr; i++) Z[i * nt + c] = x[i] - y[i];
+  }
+  if ((rc = orthonormalize(Z, nr, nt))) goto done;
+  /* initial residuals and search directions */
+  for (int c = 0; c < nt; c++) {
+    for (int64_t i = 0; i < nr; i++) x[i] = Z[i * nt + c];
+    apply_gagt(A, G, &GT, x, y, t1, t2);
+    double e = dot(x, y, nr), ff = dot(x, x, nr);
+    double q = ff > 0.0 ? e / ff : 0.0;
+    for (int64_t i = 0; i < nr; i++) {
+      SZ[i * nt + c] = y[i];
+      Pd[i * nt + c] = 2.0 * (y[i] - q * x[i]);
+    }
+    f[c] = 1.0;
+  }
+  for (int k = 1; k <= kmax; k++) {
+    if (k % kritz == 0) {
+      for (int c = 0; c < nt; c++) {         /* S Z by products */
+        for (int64_t i = 0; i < nr; i++) x[i] = Z[i * nt + c];
+        apply_gagt(A, G, &GT, x, y, t1, t2);
+        for (int64_t i = 0; i < nr; i++) SZ[i * nt + c] = y[i];
+      }
+      if (ritz_vectors(Z, SZ, nr, nt, U) == 0)
+        for (int64_t i = 0; i < nr; i++) {   /* Z <- Z U, S Z <- (S Z) U, row by row */
+          double zr[64], sr[64];
+          for (int c = 0; c < nt; c++) {
+            double s1 = 0.0, s2 = 0.0;
+            for (int j = 0; j < nt; j++) {
+              s1 += Z[i * nt + j] * U[j * nt + c];
+              s2 += SZ[i * nt + j] * U[j * nt + c];
+            }
+            zr[c] = s1;
+            sr[c] = s2;
+          }
+          memcpy(Z + i * nt, zr, nt * sizeof(double));
+          memcpy(SZ + i * nt, sr, nt * sizeof(double));
+        }
+    }
+    for (int c = 0; c < nt; c++) {
+      /* column c: z = Z_c, p = P_c, sz = (S Z)_c, sp = S p */
+      for (int64_t i = 0; i < nr; i++) x[i] = Pd[i * nt + c];
+      apply_gagt(A, G, &GT, x, sp, t1, t2);
+      double a = 0.0, b = 0.0, cc = 0.0, d = 0.0, e = 0.0;
+      for (int64_t i = 0; i < nr; i++) {
+        const double pi = Pd[i * nt + c], zi = Z[i * nt + c], szi = SZ[i * nt + c];
+        a += pi * szi;
+        b += pi * sp[i];
+        cc += pi * zi;
+        d += pi * pi;
+        e += zi * szi;
+      }
+      const double fi = f[c];
+      const double den = 2.0 * (b * cc - a * d);
+      const double u1 = d * e - b * fi;
+      const double delta = u1 * u1 - 4.0 * (b * cc - a * d) * (a * fi - cc * e);
+      if (!(den != 0.0) || !(delta >= 0.0)) continue;
+      const double alpha = (u1 + sqrt(delta)) / den;   /* minimiser of the quotient on z + alpha p */
+      double zz = 0.0, zsz = 0.0;
+      for (int64_t i = 0; i < nr; i++) {
+        Z[i * nt + c] += alpha * Pd[i * nt + c];
+        SZ[i * nt + c] += alpha * sp[i];
+      }
+      for (int64_t i = 0; i < nr; i++) {
+        zz += Z[i * nt + c] * Z[i * nt + c];
+        zsz += Z[i * nt + c] * SZ[i * nt + c];
+      }
+      f[c] = zz;
+      const double q = zsz / zz;
+      /* gradient of the quotient, g = 2 (S z - q z) / f, and the new direction */
+      for (int64_t i = 0; i < nr; i++) g[i] = 2.0 * (SZ[i * nt + c] - q * Z[i * nt + c]) / zz;
+      const double beta = -dot(g, sp, nr) / b;
+      for (int64_t i = 0; i < nr; i++) Pd[i * nt + c] = g[i] + beta * Pd[i * nt + c];
+    }
+  }
+  if (rq)
+    for (int c = 0; c < nt; c++) {
+      double zz = 0.0, zsz = 0.0;
+      for (int64_t i = 0; i < nr; i++) {
+        zz += Z[i * nt + c] * Z[i * nt + c];
+        zsz += Z[i * nt + c] * SZ[i * nt + c];
+      }
+      rq[c] = zz > 0.0 ? zsz / zz : 0.0;
+    }
+  /* V = G^T Z */
+  for (int c = 0; c < nt; c++) {
+    for (int64_t i = 0; i < nr; i++) x[i] = Z[i * nt + c];
+    bsr_mv(&GT, x, y);
+    for (int64_t i = 0; i < nr; i++) V[i * nt + c] = y[i];
+  }
+done:
+  free(Z); free(SZ); free(Pd); free(x); free(y); free(t1); free(t2); free(sp); free(g);
+  bsr_free(&GT);
+  return rc;
 }
 
 /* ========================================================================= */
@@ -1112,6 +1361,7 @@ int oracle_setup(const oparams *p, int32_t n, const int64_t *rp, const int32_t *
     int32_t N = L->A.n;
     if ((int64_t)N * b <= p->coarse_max_dof || l == p->max_levels - 1 || l == OMAXLEV - 1 || ntv == 0) break;
     if ((rc = fsai_build(h, L))) goto fail;
+    if (p->n_rq > 0 && (rc = srqcg(&L->A, &L->G, L->V, ntv, p->n_rq, p->k_ritz, NULL))) goto fail;
     if ((rc = orthonormalize(L->V, (int64_t)N * b, ntv))) goto fail;
     if ((rc = coarsen(h, L))) goto fail;
     int32_t nF = 0;
@@ -1292,6 +1542,7 @@ void oracle_level_info(const ohier *h, int l, int64_t *info, double *dinfo) {
 }
 
 static void export_bsr(const obsr *M, int64_t *rp, int32_t *ci, double *v) {
+  if (!M->rp) return;   /* not formed on this level (G, P of the coarsest) */
   if (rp) memcpy(rp, M->rp, ((size_t)M->n + 1) * sizeof(int64_t));
   if (ci) memcpy(ci, M->ci, (size_t)M->nnzb * sizeof(int32_t));
   if (v) memcpy(v, M->v, (size_t)M->nnzb * M->b * M->b * sizeof(double));
@@ -1382,6 +1633,21 @@ int oracle_fsai_rows(const oparams *p, int32_t n, const int64_t *rp, const int32
 }
 
 int oracle_max_nb(void) { return OMAXNB; }
+
+/* SRQCG on a standalone matrix A (BSR, n block rows of size b) and factor G;
+ * V is row-major [n*b][nt], V0 in and G^T Z out; rq receives the final
+ * Rayleigh quotients of the columns of Z */
+int oracle_srqcg(int32_t n, int b, const int64_t *rp, const int32_t *ci, const double *v, const int64_t *grp,
+                 const int32_t *gci, const double *gv, int nt, double *V, int kmax, int kritz, double *rq) {
+  obsr A = {0}, G = {0};
+  int rc = copy_bsr_in(&A, n, b, rp, ci, v);
+  if (rc) return rc;
+  G.n = n; G.nc = n; G.b = b; G.nnzb = grp[n];
+  G.rp = (int64_t *)grp; G.ci = (int32_t *)gci; G.v = (double *)gv;
+  rc = srqcg(&A, &G, V, nt, kmax, kritz, rq);
+  bsr_free(&A);
+  return rc;
+}
 
 double oracle_lanczos(int32_t n, int b, const int64_t *rp, const int32_t *ci, const double *v,
                       const int64_t *grp, const int32_t *gci, const double *gv, int steps) {

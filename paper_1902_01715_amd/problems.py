@@ -314,6 +314,17 @@ def rigid_body_modes(coords):
     return V
 
 
+def initial_test_space(p, n_tv, seed):
+    """Initial test space [N, 3, n_tv]: the six rigid-body modes of p, then
+    n_tv - 6 columns of seeded standard normal entries (the random padding of
+    the test space is an input)."""
+    if n_tv < 6:
+        raise ValueError("n_tv must be at least 6")
+    N = p.n_nodes
+    extra = np.random.default_rng(seed).standard_normal((N, 3, n_tv - 6))
+    return np.ascontiguousarray(np.concatenate([p.V0, extra], axis=2))
+
+
 def body_force(coords, conn, b, chunk=65536):
     """Consistent nodal loads of a uniform body force b (per unit volume)."""
     N = coords.shape[0]
