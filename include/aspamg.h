@@ -54,7 +54,10 @@ typedef struct {
   int32_t rho_g;          /* 4     paper: scalar entries per step (informational)      */
   double  eps_g;          /* 1e-3  FSAI exit tolerance on the relative decrease of psi */
   int32_t n_tv;           /* 6     test vectors (the six rigid-body modes)              */
-  int32_t n_rq;           /* 0     test-space smoothing iterations (not applied)        */
+  int32_t n_rq;           /* 0     SRQCG iterations on each level's test space before its
+                           *       coarsening (Section 3.3, Algorithm "Test Space generation
+                           *       by SRQCG", Ritz projection every iteration); 0 uses V0 as
+                           *       given.  The paper's default is 10, with n_tv = 10.  0..1000 */
   int32_t theta;          /* 5     strong connections kept per node                     */
   int32_t n_max;          /* 5     max interpolation entries per scalar row (<= 8)      */
   double  kappa_p;        /* 50    max conditioning of a local least-squares fit        */
@@ -203,6 +206,13 @@ aspamg_status aspamg_level_matrix(aspamg_handle h, int32_t level, int32_t which,
  * -1 padded, coarse scalar indices) of a level.  Any pointer may be NULL. */
 aspamg_status aspamg_level_split(aspamg_handle h, int32_t level, int8_t *cf,
                                  int32_t *p_counts, int32_t *p_cols);
+
+/* Copy a level's orthonormalised test space, float64 [n][3][n_tv] node-major
+ * (host array, caller-owned): the rows the affinity SoC and the least-squares
+ * interpolation of that level used (Section 3.3; after n_rq SRQCG iterations
+ * when n_rq > 0).  The coarsest level keeps the restricted rows, not
+ * orthonormalised. */
+aspamg_status aspamg_level_test_space(aspamg_handle h, int32_t level, double *V);
 
 /* Per-element derivative of lam^T K(E) u with respect to E_e for K = sum_e
  * E_e K_e^0 (the adjoint form of the compliance gradient):

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EH
 EXPORTED = [
     "aspamg_default_params", "aspamg_setup", "aspamg_set_cycle_precision", "aspamg_solve",
     "aspamg_solve_batch", "aspamg_vcycle", "aspamg_apply_operator", "aspamg_level_info",
-    "aspamg_level_matrix", "aspamg_level_split", "aspamg_element_gradient", "aspamg_assembler_create",
+    "aspamg_level_matrix", "aspamg_level_split", "aspamg_level_test_space", "aspamg_element_gradient", "aspamg_assembler_create",
     "aspamg_assemble", "aspamg_assembler_destroy", "aspamg_time_kernel", "aspamg_destroy", "aspamg_last_error",
 ]
 
@@ -100,6 +100,7 @@ def lib():
         L.aspamg_level_info.argtypes = [P, C.c_int32, C.POINTER(LevelInfo)]
         L.aspamg_level_matrix.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
         L.aspamg_level_split.argtypes = [P, C.c_int32, P, P, P]
+        L.aspamg_level_test_space.argtypes = [P, C.c_int32, P]
         L.aspamg_element_gradient.argtypes = [C.c_int64, P, P, C.c_int64, P, P, P, P, P]
         L.aspamg_assembler_create.argtypes = [C.c_int32, C.c_int64, P, P, P, P, P, C.c_int64, P,
                                               C.POINTER(C.c_void_p)]
@@ -174,6 +175,7 @@ class Solver:
         _check(lib().aspamg_setup(C.byref(self.params), self.n, self.nnzb, _ptr(row_ptr), _ptr(col), _ptr(vals),
                                   n_tv, _ptr(V0), _stream_ptr(self._stream), C.byref(h)))
         self.h = h
+        self.n_tv = n_tv
         self.precision = int(self.params.cycle_precision)
         self.last_stats = None
 
@@ -280,6 +282,13 @@ class Solver:
         cols = np.zeros((3 * n, self.params.n_max), dtype=np.int32)
         _check(lib().aspamg_level_split(self.h, level, _ptr(cf), _ptr(cnt), _ptr(cols)))
         return cf, cnt, cols
+
+    def level_test_space(self, level):
+        """The level's orthonormalised test space, [n, 3, n_tv]."""
+        n = self.level_info(level)["n"]
+        V = np.zeros((n, 3, self.n_tv))
+        _check(lib().aspamg_level_test_space(self.h, level, _ptr(V)))
+        return V
 
 
 def element_gradient(conn, Ke0, lam, u, scale=None, stream=None):

@@ -807,6 +807,7 @@ static void check_params(const aspamg_params &p) {
       p.lanczos_steps < 1 || p.lanczos_steps > 200 || p.nu1 < 1 || p.nu2 < 1 || p.max_levels < 1 ||
       (p.cycle_precision != 32 && p.cycle_precision != 64) || !(p.rtol >= 0) || p.max_it < 1 ||
       p.quant_bits < 8 || p.quant_bits > 52 || p.check_every < 1 || p.n_tv < 0 || p.n_tv > 64 ||
+      p.n_rq < 0 || p.n_rq > 1000 ||
       p.layout < 0 || p.layout > 3 || p.dense_tail_dof < 0 || p.dense_tail_dof > kMaxTailDof ||
       !(p.kappa_p > 0) || !(p.omega_safety > 0))
     fail(ASPAMG_EINVAL, "invalid parameter value");
@@ -1147,6 +1148,13 @@ aspamg_status aspamg_level_split(aspamg_handle h, int32_t level, int8_t *cf, int
   if (cf && !L.cf.empty()) std::memcpy(cf, L.cf.data(), L.cf.size());
   if (p_counts && !L.pcount.empty()) std::memcpy(p_counts, L.pcount.data(), L.pcount.size() * 4);
   if (p_cols && !L.pcols.empty()) std::memcpy(p_cols, L.pcols.data(), L.pcols.size() * 4);
+  return ASPAMG_OK;
+}
+
+aspamg_status aspamg_level_test_space(aspamg_handle h, int32_t level, double *V) {
+  if (!h || level < 0 || level >= (int32_t)h->lev.size() || !V) return ASPAMG_EINVAL;
+  const Level &L = h->lev[level];
+  if (!L.V.empty()) std::memcpy(V, L.V.data(), L.V.size() * 8);
   return ASPAMG_OK;
 }
 

@@ -280,6 +280,10 @@ void launch_dense_mm(int32_t nd, const double *D, const double *X, double *Y, in
 void launch_eye(int32_t nd, double *X, hipStream_t s);
 void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);     // y += a x
 void launch_divided(int64_t n, double a, const double *x, double *y, hipStream_t s);  // y = x / a
+// test-space iteration: out = 2 (sz - q z) / f; y = x + b y; Y = X U (columns of n entries, U nt x nt row-major)
+void launch_rq_gradient(int64_t n, double q, double f, const double *sz, const double *z, double *out, hipStream_t s);
+void launch_xpby(int64_t n, const double *x, double b, double *y, hipStream_t s);
+void launch_combine_columns(int64_t n, int nt, const double *X, const double *U, double *Y, hipStream_t s);
 // layout values: slot i takes the 9 values of block map[i] of v (zeros when map[i] < 0)
 template <typename T>
 void launch_scatter_values(int64_t nslots, const int32_t *map, const double *v, T *val, hipStream_t s);

@@ -368,6 +368,29 @@ __global__ void __launch_bounds__(256) k_divided(int64_t n, double a, const doub
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = x[i] / a;
 }
 
+// Test-space iteration (SRQCG): columns stored one after another, n entries each.
+// out = 2 (sz - q z) / f, the gradient of the Rayleigh quotient of z
+__global__ void __launch_bounds__(256) k_rq_gradient(int64_t n, double q, double f, const double *__restrict__ sz,
+                                                     const double *__restrict__ z, double *__restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    out[i] = 2.0 * (sz[i] - q * z[i]) / f;
+}
+// y = x + b y
+__global__ void __launch_bounds__(256) k_xpby(int64_t n, const double *__restrict__ x, double b,
+                                              double *__restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = x[i] + b * y[i];
+}
+// Y[:, c] = sum over j ascending of X[:, j] U[j][c] (U row-major nt x nt)
+__global__ void __launch_bounds__(256) k_combine_columns(int64_t n, int nt, const double *__restrict__ X,
+                                                         const double *__restrict__ U, double *__restrict__ Y) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    for (int c = 0; c < nt; c++) {
+      double s = 0.0;
+      for (int j = 0; j < nt; j++) s += X[(size_t)j * n + i] * U[j * nt + c];
+      Y[(size_t)c * n + i] = s;
+    }
+}
+
 // X = the nd x nd identity, row-major
 __global__ void __launch_bounds__(256) k_eye(int64_t nd, double *__restrict__ X) {
   const int64_t n = nd * nd;
@@ -412,6 +435,17 @@ void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s)
 }
 void launch_divided(int64_t n, double a, const double *x, double *y, hipStream_t s) {
   hipLaunchKernelGGL(k_divided, dim3(setup_vec_blocks(n)), dim3(256), 0, s, n, a, x, y);
+}
+
+void launch_rq_gradient(int64_t n, double q, double f, const double *sz, const double *z, double *out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_rq_gradient, dim3(setup_vec_blocks(n)), dim3(256), 0, s, n, q, f, sz, z, out);
+}
+void launch_xpby(int64_t n, const double *x, double b, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_xpby, dim3(setup_vec_blocks(n)), dim3(256), 0, s, n, x, b, y);
+}
+void launch_combine_columns(int64_t n, int nt, const double *X, const double *U, double *Y, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine_columns, dim3(setup_vec_blocks(n)), dim3(256), 0, s, n, nt, X, U, Y);
 }
 
 void launch_eye(int32_t nd, double *X, hipStream_t s) {

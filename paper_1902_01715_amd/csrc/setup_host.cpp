@@ -533,6 +533,241 @@ void orthonormalize(std::vector<double> &V, int64_t nrows, int ntv) {
 }
 
 // ------------------------------------------------------------------------
+// test space by SRQCG (Section 3.3, Algorithm "Test Space generation by
+// SRQCG"): the columns of Z minimise their Rayleigh quotients for
+// S = G A G^T by conjugate gradients, with a Ritz projection every
+// iteration (k_ritz = 1, as in the paper's experiments), then V = G^T Z.
+//   - q is the Rayleigh quotient z^T S z / z^T z; f_i starts at 1 and is
+//     z_i^T z_i after each update of column i (kept across a projection);
+//   - S Z is formed by products at every projection and then carried
+//     (S z_i += alpha S p_i; S Z <- (S Z) U);
+//   - the projection solves (Z^T S Z) U = (Z^T Z) U Lambda through the
+//     Cholesky factor of Z^T Z and Jacobi rotations, eigenvalues ascending,
+//     each eigenvector with its largest-magnitude entry positive (the first
+//     on ties); it is skipped when Z^T Z is not positive definite;
+//   - a column update with 2(bc - ad) = 0 or a negative discriminant is
+//     skipped; exactly n_rq iterations run.
+// Products, vector updates and inner products run on the device (FP64 SELL
+// products; inner products summed from block partials in block order); the
+// nt x nt eigenproblems on the host.
+// ------------------------------------------------------------------------
+
+// C (symmetric m x m, row-major, destroyed) = X diag(w) X^T by cyclic Jacobi
+// rotations; w ascending, eigenvectors in the columns of X.
+void jacobi_sym(std::vector<double> &C, int m, std::vector<double> &w, std::vector<double> &X) {
+  auto at = [m](std::vector<double> &M, int i, int j) -> double & { return M[(size_t)i * m + j]; };
+  X.assign((size_t)m * m, 0.0);
+  for (int i = 0; i < m; i++) at(X, i, i) = 1.0;
+  for (int sweep = 0; sweep < 100; sweep++) {
+    double off = 0.0, all = 0.0;
+    for (int i = 0; i < m; i++)
+      for (int j = 0; j < m; j++) {
+        const double c2 = at(C, i, j) * at(C, i, j);
+        all += c2;
+        if (i != j) off += c2;
+      }
+    if (!(off > 1e-32 * all)) break;
+    for (int p = 0; p + 1 < m; p++)
+      for (int q = p + 1; q < m; q++) {
+        const double apq = at(C, p, q);
+        if (apq == 0.0) continue;
+        // the rotation angle t = tan(phi) zeroing C[p][q], the smaller root
+        const double th = (at(C, q, q) - at(C, p, p)) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < m; k++) {
+          const double a = at(C, k, p), b = at(C, k, q);
+          at(C, k, p) = c * a - sn * b;
+          at(C, k, q) = sn * a + c * b;
+        }
+        for (int k = 0; k < m; k++) {
+          const double a = at(C, p, k), b = at(C, q, k);
+          at(C, p, k) = c * a - sn * b;
+          at(C, q, k) = sn * a + c * b;
+        }
+        for (int k = 0; k < m; k++) {
+          const double a = at(X, k, p), b = at(X, k, q);
+          at(X, k, p) = c * a - sn * b;
+          at(X, k, q) = sn * a + c * b;
+        }
+      }
+  }
+  w.resize(m);
+  for (int i = 0; i < m; i++) w[i] = at(C, i, i);
+  for (int i = 0; i < m; i++) {   // ascending; the first smallest moves first
+    int k = i;
+    for (int j = i + 1; j < m; j++)
+      if (w[j] < w[k]) k = j;
+    if (k == i) continue;
+    std::swap(w[i], w[k]);
+    for (int r = 0; r < m; r++) std::swap(at(X, r, i), at(X, r, k));
+  }
+}
+
+// U with (Z^T S Z) U = (Z^T Z) U Lambda from Ms = Z^T S Z (symmetrised) and
+// Mz = Z^T Z; false when Mz is not positive definite.
+bool ritz_basis(const std::vector<double> &Ms, const std::vector<double> &Mz, int m, std::vector<double> &U) {
+  std::vector<double> L((size_t)m * m, 0.0), T((size_t)m * m), C((size_t)m * m), X, w;
+  for (int j = 0; j < m; j++) {   // Mz = L L^T, left-looking
+    double acc = 0.0;
+    for (int k = 0; k < j; k++) acc += L[j * m + k] * L[j * m + k];
+    const double d = Mz[j * m + j] - acc;
+    if (!(d > 0.0)) return false;
+    L[j * m + j] = std::sqrt(d);
+    for (int i = j + 1; i < m; i++) {
+      double a2 = 0.0;
+      for (int k = 0; k < j; k++) a2 += L[i * m + k] * L[j * m + k];
+      L[i * m + j] = (Mz[i * m + j] - a2) / L[j * m + j];
+    }
+  }
+  for (int c = 0; c < m; c++)     // T = L^{-1} Ms
+    for (int i = 0; i < m; i++) {
+      double acc = Ms[i * m + c];
+      for (int k = 0; k < i; k++) acc -= L[i * m + k] * T[k * m + c];
+      T[i * m + c] = acc / L[i * m + i];
+    }
+  for (int r = 0; r < m; r++)     // C = T L^{-T}
+    for (int i = 0; i < m; i++) {
+      double acc = T[r * m + i];
+      for (int k = 0; k < i; k++) acc -= L[i * m + k] * C[r * m + k];
+      C[r * m + i] = acc / L[i * m + i];
+    }
+  for (int a = 0; a < m; a++)
+    for (int c = 0; c < a; c++) C[a * m + c] = C[c * m + a] = 0.5 * (C[a * m + c] + C[c * m + a]);
+  jacobi_sym(C, m, w, X);
+  U.assign((size_t)m * m, 0.0);
+  for (int c = 0; c < m; c++) {   // U = L^{-T} X, then the sign rule
+    for (int i = m - 1; i >= 0; i--) {
+      double acc = X[i * m + c];
+      for (int k = i + 1; k < m; k++) acc -= L[k * m + i] * U[k * m + c];
+      U[i * m + c] = acc / L[i * m + i];
+    }
+    int big = 0;
+    for (int i = 1; i < m; i++)
+      if (std::fabs(U[i * m + c]) > std::fabs(U[big * m + c])) big = i;
+    if (U[big * m + c] < 0.0)
+      for (int i = 0; i < m; i++) U[i * m + c] = -U[i * m + c];
+  }
+  return true;
+}
+
+// L.V ([n][nt], in: the level's V0) <- G^T Z after kmax SRQCG iterations
+void srqcg(aspamg_ctx *h, Level &L, int nt, int kmax) {
+  const int64_t n = (int64_t)L.A.n * 3;
+  const size_t cols = (size_t)n * nt;
+  hipStream_t s = h->stream;
+  const int nb = vec_blocks(n);
+  Scratch dZ(cols * 8), dSZ(cols * 8), dP(cols * 8), dW(cols * 8), dsp(n * 8), dg(n * 8), dt1(n * 8), dt2(n * 8),
+      dU((size_t)nt * nt * 8), dpart((size_t)nb * 2 * nt * nt * 8);
+  double *Z = dZ.as<double>(), *SZ = dSZ.as<double>(), *Pd = dP.as<double>(), *W = dW.as<double>();
+  double *sp = dsp.as<double>(), *g = dg.as<double>(), *part = dpart.as<double>();
+  auto C = [n](double *M, int c) { return M + (size_t)c * n; };
+  auto apply_s = [&](const double *x, double *y) {
+    launch_spmv<double, double, double>(L.GT64, x, dt1.as<double>(), nullptr, 1.0, nullptr, s);
+    launch_spmv<double, double, double>(L.A64, dt1.as<double>(), dt2.as<double>(), nullptr, 1.0, nullptr, s);
+    launch_spmv<double, double, double>(L.G64, dt2.as<double>(), y, nullptr, 1.0, nullptr, s);
+  };
+  std::vector<double> hp;
+  using Pair = std::pair<const double *, const double *>;
+  auto dots = [&](const std::vector<Pair> &pr) {
+    for (size_t k = 0; k < pr.size(); k++) launch_dot(n, pr[k].first, pr[k].second, part + k * nb, nullptr, s);
+    HIPCHK(hipGetLastError());
+    hp.resize(pr.size() * nb);
+    to_host(s, hp.data(), part, pr.size() * nb);
+    std::vector<double> out(pr.size(), 0.0);
+    for (size_t k = 0; k < pr.size(); k++)
+      for (int i = 0; i < nb; i++) out[k] += hp[k * nb + i];
+    return out;
+  };
+  auto to_columns = [&](const std::vector<double> &rows, double *dst) {
+    std::vector<double> cm(cols);
+    for (int64_t i = 0; i < n; i++)
+      for (int c = 0; c < nt; c++) cm[(size_t)c * n + i] = rows[(size_t)i * nt + c];
+    to_device(s, dst, cm.data(), cols);
+    HIPCHK(hipStreamSynchronize(s));
+  };
+  auto to_rows = [&](const double *src, std::vector<double> &rows) {
+    std::vector<double> cm(cols);
+    to_host(s, cm.data(), src, cols);
+    rows.resize(cols);
+    for (int64_t i = 0; i < n; i++)
+      for (int c = 0; c < nt; c++) rows[(size_t)i * nt + c] = cm[(size_t)c * n + i];
+  };
+  // Z0 = (I - S) V0, orthonormalised
+  to_columns(L.V, W);
+  for (int c = 0; c < nt; c++) {
+    apply_s(C(W, c), C(SZ, c));
+    HIPCHK(hipMemcpyAsync(C(Z, c), C(W, c), n * 8, hipMemcpyDeviceToDevice, s));
+    launch_axpy(n, -1.0, C(SZ, c), C(Z, c), s);
+  }
+  HIPCHK(hipGetLastError());
+  {
+    std::vector<double> rows;
+    to_rows(Z, rows);
+    orthonormalize(rows, n, nt);
+    to_columns(rows, Z);
+  }
+  // initial residuals and search directions
+  std::vector<double> f(nt, 1.0);
+  for (int c = 0; c < nt; c++) {
+    apply_s(C(Z, c), C(SZ, c));
+    const std::vector<double> ef = dots({{C(Z, c), C(SZ, c)}, {C(Z, c), C(Z, c)}});
+    const double q = ef[1] > 0.0 ? ef[0] / ef[1] : 0.0;
+    launch_rq_gradient(n, q, 1.0, C(SZ, c), C(Z, c), C(Pd, c), s);
+  }
+  std::vector<double> Ms((size_t)nt * nt), Mz((size_t)nt * nt), U;
+  for (int k = 1; k <= kmax; k++) {
+    // Ritz projection
+    for (int c = 0; c < nt; c++) apply_s(C(Z, c), C(SZ, c));
+    std::vector<Pair> pr;
+    for (int a = 0; a < nt; a++)
+      for (int c = 0; c < nt; c++) pr.push_back({C(Z, a), C(SZ, c)});
+    for (int a = 0; a < nt; a++)
+      for (int c = 0; c <= a; c++) pr.push_back({C(Z, a), C(Z, c)});
+    const std::vector<double> m = dots(pr);
+    size_t t = 0;
+    for (int a = 0; a < nt; a++)
+      for (int c = 0; c < nt; c++) Ms[a * nt + c] = m[t++];
+    for (int a = 0; a < nt; a++)
+      for (int c = 0; c <= a; c++) Mz[a * nt + c] = Mz[c * nt + a] = m[t++];
+    for (int a = 0; a < nt; a++)
+      for (int c = 0; c < a; c++) Ms[a * nt + c] = Ms[c * nt + a] = 0.5 * (Ms[a * nt + c] + Ms[c * nt + a]);
+    if (ritz_basis(Ms, Mz, nt, U)) {
+      to_device(s, dU.as<double>(), U.data(), U.size());
+      launch_combine_columns(n, nt, Z, dU.as<double>(), W, s);
+      std::swap(Z, W);
+      launch_combine_columns(n, nt, SZ, dU.as<double>(), W, s);
+      std::swap(SZ, W);
+      HIPCHK(hipGetLastError());
+    }
+    // one conjugate-gradient step per column
+    for (int c = 0; c < nt; c++) {
+      double *z = C(Z, c), *p = C(Pd, c), *sz = C(SZ, c);
+      apply_s(p, sp);
+      const std::vector<double> v = dots({{p, sz}, {p, sp}, {p, z}, {p, p}, {z, sz}});
+      const double a = v[0], b = v[1], cc = v[2], d = v[3], e = v[4], fi = f[c];
+      const double den = 2.0 * (b * cc - a * d);
+      const double u1 = d * e - b * fi;
+      const double delta = u1 * u1 - 4.0 * (b * cc - a * d) * (a * fi - cc * e);
+      if (!(den != 0.0) || !(delta >= 0.0)) continue;
+      const double alpha = (u1 + std::sqrt(delta)) / den;
+      launch_axpy(n, alpha, p, z, s);
+      launch_axpy(n, alpha, sp, sz, s);
+      const std::vector<double> zq = dots({{z, z}, {z, sz}});
+      f[c] = zq[0];
+      const double q = zq[1] / zq[0];
+      launch_rq_gradient(n, q, zq[0], sz, z, g, s);
+      const double beta = -dots({{g, sp}})[0] / b;
+      launch_xpby(n, g, beta, p, s);
+    }
+  }
+  // V = G^T Z
+  for (int c = 0; c < nt; c++) launch_spmv<double, double, double>(L.GT64, C(Z, c), C(W, c), nullptr, 1.0, nullptr, s);
+  HIPCHK(hipGetLastError());
+  to_rows(W, L.V);
+}
+
+// ------------------------------------------------------------------------
 // coarsening (Section 3.4)
 // ------------------------------------------------------------------------
 // n_IJ: squared Frobenius norm of V_I V_J^T (3x3 entries summed over t
@@ -1075,6 +1310,10 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     }
     build_fsai(h, L);
     clk.tick(l, "aFSAI");
+    if (p.n_rq > 0) {
+      srqcg(h, L, ntv, p.n_rq);
+      clk.tick(l, "test space");
+    }
     orthonormalize(L.V, (int64_t)N * 3, ntv);
     std::vector<char> excl(N);
     for (int32_t i = 0; i < N; i++) excl[i] = is_decoupled(L.A, i);

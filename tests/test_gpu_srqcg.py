@@ -1,0 +1,89 @@
+"""GPU set-up with the SRQCG test space (Section 3.3, Algorithm "Test Space
+generation by SRQCG"; n_tv = 10, n_rq = 10, a Ritz projection every
+iteration) against the oracle on the same seeded inputs.
+
+The iteration takes inner products in a different order on the two sides (block
+partials on the device, sequential sums in the oracle), so the test spaces
+agree to rounding amplified by the iteration, not bit for bit.  What is unique
+is compared: the subspace spanned by each level's orthonormalised test space,
+the C/F split and interpolation pattern it leads to, and the solution."""
+import numpy as np
+import pytest
+
+from paper_1902_01715_amd import problems as PR
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "cube8": lambda: PR.c1_cube(8),
+    "cube8_randE": lambda: PR.box_problem("r", 8, 8, 8, 1, 1, 1, E=10 ** np.random.default_rng(7).uniform(-3, 3, 512),
+                                          nu=0.3, clamp="z0", load=("body", (0, 0, -1))),
+    "cube12": lambda: PR.c1_cube(12),
+    "cube16": lambda: PR.c1_cube(16),
+}
+
+# Both sides fix the order and signs of the Ritz vectors the same way, so the
+# test spaces agree column by column (measured: 7e-15 of max |V| on these
+# meshes); the entrywise bar leaves a margin of 10^5 for the amplification of
+# rounding through ten iterations.  The subspace bar is the sine of the largest
+# principal angle, whose computation itself has a floor near 1.5e-8.
+ENTRY_TOL = 1e-9
+SUBSPACE_TOL = 1e-6
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def srq_pair(request, cuda, oracle_lib):
+    from paper_1902_01715_amd import aspamg
+    name = request.param
+    print(f"[srqcg case {name}]", flush=True)
+    p = CASES[name]()
+    V0 = PR.initial_test_space(p, 10, 11)
+    S = aspamg.Solver(p.row_ptr, p.col, p.vals, V0, aspamg.default_params(n_rq=10))
+    H = oracle_lib.Hierarchy(p.row_ptr, p.col, p.vals, V0, oracle_lib.default_params(n_rq=10))
+    yield name, p, S, H
+    S.close()
+
+
+def _sin_max_angle(A, B):
+    keep_a = np.abs(A).max(axis=0) > 0
+    keep_b = np.abs(B).max(axis=0) > 0
+    if keep_a.sum() != keep_b.sum():
+        return 1.0
+    Qa = np.linalg.qr(A[:, keep_a])[0]
+    Qb = np.linalg.qr(B[:, keep_b])[0]
+    c = np.linalg.svd(Qa.T @ Qb, compute_uv=False).min()
+    return float(np.sqrt(max(0.0, 1.0 - c * c)))
+
+
+def test_srqcg_test_space_and_split(srq_pair):
+    name, p, S, H = srq_pair
+    assert S.nlev == H.nlev, (S.nlev, H.nlev)
+    for l in range(H.nlev - 1):
+        Vg = S.level_test_space(l).reshape(-1, 10)
+        Vo = H.V(l).reshape(-1, 10)
+        ang = _sin_max_angle(Vg, Vo)
+        cf_g, cnt_g, cols_g = S.level_split(l)
+        cf_o = H.cf(l)
+        print(f"{name} level {l}: sin(angle) {ang:.2e}, |V_g - V_o|max {np.abs(Vg - Vo).max():.2e}, "
+              f"C/F differ at {int((cf_g != cf_o).sum())} of {cf_o.size} nodes")
+        assert ang <= SUBSPACE_TOL, (l, ang)
+        assert np.abs(Vg - Vo).max() <= ENTRY_TOL * np.abs(Vo).max(), l
+        assert np.array_equal(cf_g, cf_o), l
+        assert np.array_equal(S.level_matrix(l, 3)[1], H.P(l).ci), l
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_srqcg_solve_matches_oracle(srq_pair, prec):
+    import torch
+    name, p, S, H = srq_pair
+    u_o, st_o = H.pcg(p.f, 1e-10, 1000)
+    assert st_o["status"] == 0
+    S.set_precision(prec)
+    u = S.solve(torch.tensor(p.f, device="cuda")).cpu().numpy()
+    st = S.last_stats
+    err = np.linalg.norm(u - u_o) / np.linalg.norm(u_o)
+    print(f"{name} prec={prec} it={st['iterations']} (oracle {st_o['iterations']}) err={err:.2e} "
+          f"true res {st['relres_true']:.2e}")
+    assert st["status"] == 0, st
+    assert st["relres_true"] <= 2e-10
+    assert err <= 1e-8, err
