@@ -65,7 +65,7 @@ def make_problem(name):
     raise SystemExit(f"unknown config {name}")
 
 
-def cpu_baseline(problem_name, gpu_iters):
+def cpu_baseline(problem_name, gpu_iters, n_rq=0):
     """The CPU oracle on a bounded sample of the workload: its own setup and a
     fixed number of PCG iterations on the leading 20-element slab of the
     cantilever (same cross-section, materials drawn the same way), scaled by
@@ -77,7 +77,8 @@ def cpu_baseline(problem_name, gpu_iters):
     if problem_name != "c2":
         return None
     sample = PR.c2_cantilever(20, 32, 32)
-    H = oracle.Hierarchy(sample.row_ptr, sample.col, sample.vals, sample.V0)
+    V0 = sample.V0 if n_rq == 0 else PR.initial_test_space(sample, 10, 11)
+    H = oracle.Hierarchy(sample.row_ptr, sample.col, sample.vals, V0, oracle.default_params(n_rq=n_rq))
     its = min(gpu_iters, 400)
     t0 = time.perf_counter()
     u, st = H.pcg(sample.f, 0.0, its)                    # rtol 0: exactly `its` iterations
@@ -88,6 +89,12 @@ def cpu_baseline(problem_name, gpu_iters):
             "sample": f"{st['iterations']} PCG iterations (V(1,1) aSP-AMG, FP64) on the 20x32x32 leading slab "
                       f"of the cantilever ({sample.n_dof} DOF, {t:.1f} s), scaled by the DOF ratio "
                       f"{dof_ratio:.1f} and the GPU iteration count {gpu_iters}"}
+
+
+def test_space_label(args):
+    if args.n_rq == 0:
+        return "rigid-body modes (n_tv = 6)"
+    return f"SRQCG, n_tv = 10 (rigid-body modes + 4 seeded random), n_rq = {args.n_rq}"
 
 
 def bench_batch(args, p, desc, S, t_setup):
@@ -142,7 +149,8 @@ def bench_batch(args, p, desc, S, t_setup):
         "metric": METRIC, "value": t32, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": t32 * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 V-cycle in f64 PCG", "data": "synthetic",
-        "config": {"workload": desc, "config": args.config, "rhs": int(F.shape[1]), "setup_s": t_setup},
+        "config": {"workload": desc, "config": args.config, "rhs": int(F.shape[1]), "setup_s": t_setup,
+                   "test_space": test_space_label(args)},
         "fp32_cycle": out[32], "fp64_cycle": out[64], "speedup_fp64_over_fp32": t64 / t32,
         "graph_vs_eager_fp32": {"graph_s": t32, "eager_s": t_eager},
         "single_rhs_fp32_s": t_single, "batch_speedup_per_rhs": t_single / out[32]["s_per_rhs"],
@@ -223,6 +231,9 @@ def main():
     ap.add_argument("--max-it", type=int, default=1000)
     ap.add_argument("--coarse-max-dof", type=int, default=1500,
                     help="factor the coarsest level densely once it has at most this many DOF")
+    ap.add_argument("--n-rq", type=int, default=0,
+                    help="SRQCG iterations on each level's test space (then n_tv = 10: the rigid-body modes "
+                         "and four seeded random columns); 0 keeps the six rigid-body modes (c2, c3, c4)")
     ap.add_argument("--stream-ref", action="store_true",
                     help="only measure PyTorch's streaming rates on this device and exit")
     args = ap.parse_args()
@@ -237,6 +248,8 @@ def main():
     import torch
     from paper_1902_01715_amd import aspamg
 
+    from paper_1902_01715_amd import problems as PR
+
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     aspamg.lib()
     t0 = time.perf_counter()
@@ -245,9 +258,10 @@ def main():
     if args.config == "c5":
         print(json.dumps(bench_adjoint(args, p, desc)), flush=True)
         return
-    prm = aspamg.default_params(max_it=args.max_it, coarse_max_dof=args.coarse_max_dof)
+    prm = aspamg.default_params(max_it=args.max_it, coarse_max_dof=args.coarse_max_dof, n_rq=args.n_rq)
+    V0 = p.V0 if args.n_rq == 0 else PR.initial_test_space(p, 10, 11)
     t0 = time.perf_counter()
-    S = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, prm)
+    S = aspamg.Solver(p.row_ptr, p.col, p.vals, V0, prm)
     t_setup = time.perf_counter() - t0
     levels = [S.level_info(l) for l in range(S.nlev)]
     log(f"setup {t_setup:.1f} s, {len(levels)} levels: " + ", ".join(str(li["n"]) for li in levels))
@@ -305,7 +319,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 V-cycle in f64 PCG",
         "data": "synthetic",
-        "config": {"workload": desc, "config": args.config, "rtol": 1e-10, "max_it": args.max_it,
+        "config": {"workload": desc, "config": args.config, "test_space": test_space_label(args),
+                   "rtol": 1e-10, "max_it": args.max_it,
                    "cycle": "V(1,1)", "levels": len(levels), "c_gd": st32["c_gd"], "c_op": st32["c_op"],
                    "c_fs": st32["c_fs"], "setup_s": t_setup},
         "fp32_cycle": {"solve_s": t32, "iterations": st32["iterations"], "status": st32["status"],
@@ -331,7 +346,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(args.config, st32["iterations"])
+        out["cpu_baseline"] = cpu_baseline(args.config, st32["iterations"], args.n_rq)
     S.close()
     print(json.dumps(out), flush=True)
 
