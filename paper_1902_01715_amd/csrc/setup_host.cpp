@@ -658,7 +658,7 @@ void srqcg(aspamg_ctx *h, Level &L, int nt, int kmax) {
   hipStream_t s = h->stream;
   const int nb = vec_blocks(n);
   Scratch dZ(cols * 8), dSZ(cols * 8), dP(cols * 8), dW(cols * 8), dsp(n * 8), dg(n * 8), dt1(n * 8), dt2(n * 8),
-      dU((size_t)nt * nt * 8), dpart((size_t)nb * 2 * nt * nt * 8);
+      dU((size_t)nt * nt * 8), dpart((size_t)nb * std::max(5, 2 * nt * nt) * 8);
   double *Z = dZ.as<double>(), *SZ = dSZ.as<double>(), *Pd = dP.as<double>(), *W = dW.as<double>();
   double *sp = dsp.as<double>(), *g = dg.as<double>(), *part = dpart.as<double>();
   auto C = [n](double *M, int c) { return M + (size_t)c * n; };
@@ -669,7 +669,9 @@ void srqcg(aspamg_ctx *h, Level &L, int nt, int kmax) {
   };
   std::vector<double> hp;
   using Pair = std::pair<const double *, const double *>;
+  const size_t max_pairs = (size_t)std::max(5, 2 * nt * nt);
   auto dots = [&](const std::vector<Pair> &pr) {
+    if (pr.size() > max_pairs) fail(ASPAMG_EINVAL, "srqcg: too many inner products in one batch");
     for (size_t k = 0; k < pr.size(); k++) launch_dot(n, pr[k].first, pr[k].second, part + k * nb, nullptr, s);
     HIPCHK(hipGetLastError());
     hp.resize(pr.size() * nb);

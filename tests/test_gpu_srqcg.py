@@ -87,3 +87,26 @@ def test_srqcg_solve_matches_oracle(srq_pair, prec):
     assert st["status"] == 0, st
     assert st["relres_true"] <= 2e-10
     assert err <= 1e-8, err
+
+
+@pytest.mark.parametrize("n_tv,n_rq", [(1, 3), (6, 5)])
+def test_srqcg_few_test_vectors(n_tv, n_rq, cuda, oracle_lib):
+    """One test vector (a single column: the smallest batch of inner products
+    is the column update's five) and the six rigid-body modes without padding."""
+    import torch
+    from paper_1902_01715_amd import aspamg
+    p = PR.c1_cube(8)
+    V0 = np.ascontiguousarray(p.V0[:, :, :n_tv])
+    S = aspamg.Solver(p.row_ptr, p.col, p.vals, V0, aspamg.default_params(n_rq=n_rq))
+    H = oracle_lib.Hierarchy(p.row_ptr, p.col, p.vals, V0, oracle_lib.default_params(n_rq=n_rq))
+    try:
+        assert S.nlev == H.nlev
+        Vg, Vo = S.level_test_space(0).reshape(-1, n_tv), H.V(0).reshape(-1, n_tv)
+        assert np.abs(Vg - Vo).max() <= ENTRY_TOL * np.abs(Vo).max()
+        assert np.array_equal(S.level_split(0)[0], H.cf(0))
+        u_o, st_o = H.pcg(p.f, 1e-10, 1000)
+        u = S.solve(torch.tensor(p.f, device="cuda")).cpu().numpy()
+        assert S.last_stats["status"] == 0
+        assert np.linalg.norm(u - u_o) / np.linalg.norm(u_o) <= 1e-8
+    finally:
+        S.close()
