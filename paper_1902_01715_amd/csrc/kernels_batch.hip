@@ -14,27 +14,41 @@ namespace {
 __device__ __forceinline__ bool bdone(const BatchCtrl *c) { return c != nullptr && c->all_done != 0; }
 
 // Y[:, tile] = alpha * (A X)[:, tile] (+ W[:, tile]) for the KB columns of
-// tile blockIdx.y, and with DOT the per-column partials of X.Y.  A block row
-// is served by S lane groups of KB lanes (one lane per column of the tile);
-// group s takes the row's blocks s, s+S, s+2S, ..., and the S partial sums
-// meet in LDS in group order.  A row group is 256/(KB*S) consecutive rows.
-// The group's matrix
-// blocks (a contiguous range of the block CSR) are staged in LDS, 256 blocks
-// at a time, by coalesced loads; the lanes then read each block as an LDS
-// broadcast, so the global loads per block are the three x gathers of the
-// tile.
+// tile blockIdx.y, and with DOT the per-column partials of X.Y.  Each lane
+// takes CPT = 16 / sizeof(T) consecutive columns (one 16-byte load per
+// gathered x entry), so a block row is served by S lane groups of KB / CPT
+// lanes; group s takes the row's blocks s, s+S, s+2S, ..., and the S partial
+// sums meet in LDS in group order.  A row group is 256 CPT / (KB S)
+// consecutive rows.  The group's matrix blocks (a contiguous range of the
+// block CSR) are staged in LDS, 256 CPT blocks at a time, by coalesced loads;
+// the lanes read each block as an LDS broadcast and apply it to their CPT
+// columns, so LDS delivers every block once per CPT columns and the global
+// loads per block are the three x gathers of the tile.  Every column is
+// summed in the same order as with one column per lane.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+  using type = float __attribute__((ext_vector_type(4)));
+};
+template <> struct Vec16<double> {
+  using type = double __attribute__((ext_vector_type(2)));
+};
+
 template <typename T, bool HAS_W, bool DOT, int KB, int S>
 __global__ void __launch_bounds__(256) k_bsr_spmm(int32_t n, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ col, const T *__restrict__ val,
                                                   const T *__restrict__ X, T *Y, const T *W, int32_t ld, T alpha,
                                                   double *__restrict__ part, const BatchCtrl *ctrl) {
-  constexpr int TPR = KB * S;
+  using V = typename Vec16<T>::type;
+  constexpr int CPT = 16 / sizeof(T);
+  constexpr int LPR = KB / CPT;          // lanes per row and lane group
+  constexpr int TPR = LPR * S;
   constexpr int RPG = 256 / TPR;
-  constexpr int CH = 256;
+  constexpr int CH = 256 * CPT;
+  static_assert(KB % CPT == 0, "tile narrower than one lane");
   __shared__ T sv[CH * 9];
   __shared__ int32_t sc[CH];
-  __shared__ T red[3][S > 1 ? 256 : 1];
-  __shared__ double sm[DOT ? 256 : 1];
+  __shared__ V red[3][S > 1 ? 256 : 1];
+  __shared__ double sm[DOT ? CPT : 1][DOT ? 256 : 1];
   if (bdone(ctrl)) return;              // the same for every thread of the grid
   // XCD x (workgroups are dealt to the 8 XCDs round-robin) owns one contiguous
   // range of row groups, and its workgroups take that range round-robin, so
@@ -45,18 +59,20 @@ __global__ void __launch_bounds__(256) k_bsr_spmm(int32_t n, const int32_t *__re
   const int32_t nwx = per + (xcd < rem ? 1 : 0), wi = blockIdx.x >> 3;
   const int32_t gx0 = (int32_t)((int64_t)ngroups * xcd / 8), gx1 = (int32_t)((int64_t)ngroups * (xcd + 1) / 8);
   const int32_t w = blockIdx.x;          // this workgroup's partial slot
-  const int lane = threadIdx.x % KB, sp = (threadIdx.x / KB) % S, lr = threadIdx.x / TPR;
-  const int32_t j = blockIdx.y * KB + lane;
-  double d = 0.0;
+  const int lane = threadIdx.x % LPR, sp = (threadIdx.x / LPR) % S, lr = threadIdx.x / TPR;
+  const int32_t j = blockIdx.y * KB + lane * CPT;
+  double d[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; q++) d[q] = 0.0;
   for (int32_t g = gx0 + wi; g < gx1; g += nwx) {
     const int32_t r0 = g * RPG, row = r0 + lr;
     const int32_t b0 = rp[r0], b1 = rp[min(r0 + RPG, n)];
     const int32_t mb0 = row < n ? rp[row] : 0, mb1 = row < n ? rp[row + 1] : 0;
-    T a0 = 0, a1 = 0, a2 = 0;
+    V a0 = (V)0, a1 = (V)0, a2 = (V)0;
     for (int32_t cb = b0; cb < b1; cb += CH) {
       const int32_t cn = min(CH, b1 - cb);
       for (int i = threadIdx.x; i < cn * 9; i += 256) sv[i] = val[(size_t)cb * 9 + i];
-      if (threadIdx.x < cn) sc[threadIdx.x] = col[cb + threadIdx.x];
+      for (int i = threadIdx.x; i < cn; i += 256) sc[i] = col[cb + i];
       __syncthreads();
       const int32_t lo = max(mb0, cb), hi = min(mb1, cb + cn);
       // first block of this lane group's residue class at or after lo
@@ -65,11 +81,15 @@ __global__ void __launch_bounds__(256) k_bsr_spmm(int32_t n, const int32_t *__re
         const int k = b - cb;
         const int32_t c = sc[k];
         const T *v = sv + k * 9;
-        const T x0 = X[(size_t)(3 * c) * ld + j], x1 = X[(size_t)(3 * c + 1) * ld + j],
-                x2 = X[(size_t)(3 * c + 2) * ld + j];
-        a0 += v[0] * x0 + v[1] * x1 + v[2] * x2;
-        a1 += v[3] * x0 + v[4] * x1 + v[5] * x2;
-        a2 += v[6] * x0 + v[7] * x1 + v[8] * x2;
+        const V x0 = *(const V *)(X + (size_t)(3 * c) * ld + j);
+        const V x1 = *(const V *)(X + (size_t)(3 * c + 1) * ld + j);
+        const V x2 = *(const V *)(X + (size_t)(3 * c + 2) * ld + j);
+#pragma unroll
+        for (int q = 0; q < CPT; q++) {
+          a0[q] += v[0] * x0[q] + v[1] * x1[q] + v[2] * x2[q];
+          a1[q] += v[3] * x0[q] + v[4] * x1[q] + v[5] * x2[q];
+          a2[q] += v[6] * x0[q] + v[7] * x1[q] + v[8] * x2[q];
+        }
       }
       __syncthreads();
     }
@@ -79,35 +99,46 @@ __global__ void __launch_bounds__(256) k_bsr_spmm(int32_t n, const int32_t *__re
       red[2][threadIdx.x] = a2;
       __syncthreads();
       if (sp == 0) {
-        a0 = a1 = a2 = 0;
+        a0 = a1 = a2 = (V)0;
         for (int q = 0; q < S; q++) {
-          a0 += red[0][threadIdx.x + q * KB];
-          a1 += red[1][threadIdx.x + q * KB];
-          a2 += red[2][threadIdx.x + q * KB];
+          a0 += red[0][threadIdx.x + q * LPR];
+          a1 += red[1][threadIdx.x + q * LPR];
+          a2 += red[2][threadIdx.x + q * LPR];
         }
       }
       __syncthreads();
     }
     if (row < n && sp == 0) {
       const size_t o = (size_t)(3 * row) * ld + j;
+      V y0, y1, y2;
       if (HAS_W) {
-        Y[o] = alpha * a0 + W[o];
-        Y[o + ld] = alpha * a1 + W[o + ld];
-        Y[o + 2 * ld] = alpha * a2 + W[o + 2 * ld];
+        y0 = alpha * a0 + *(const V *)(W + o);
+        y1 = alpha * a1 + *(const V *)(W + o + ld);
+        y2 = alpha * a2 + *(const V *)(W + o + 2 * ld);
       } else {
-        Y[o] = alpha * a0;
-        Y[o + ld] = alpha * a1;
-        Y[o + 2 * ld] = alpha * a2;
+        y0 = alpha * a0;
+        y1 = alpha * a1;
+        y2 = alpha * a2;
       }
-      if (DOT) d += ((double)X[o] * a0 + (double)X[o + ld] * a1) + (double)X[o + 2 * ld] * a2;
+      *(V *)(Y + o) = y0;
+      *(V *)(Y + o + ld) = y1;
+      *(V *)(Y + o + 2 * ld) = y2;
+      if (DOT) {
+        const V x0 = *(const V *)(X + o), x1 = *(const V *)(X + o + ld), x2 = *(const V *)(X + o + 2 * ld);
+#pragma unroll
+        for (int q = 0; q < CPT; q++)
+          d[q] += ((double)x0[q] * a0[q] + (double)x1[q] * a1[q]) + (double)x2[q] * a2[q];
+      }
     }
   }
   if (DOT) {
-    sm[threadIdx.x] = d;                // zero on the lanes of groups s > 0
+#pragma unroll
+    for (int q = 0; q < CPT; q++) sm[q][threadIdx.x] = d[q];   // zero on the lanes of groups s > 0
     __syncthreads();
     if (threadIdx.x < KB) {
+      const int ln = threadIdx.x / CPT, q = threadIdx.x % CPT;
       double s = 0.0;
-      for (int r = 0; r < RPG; r++) s += sm[r * TPR + threadIdx.x];
+      for (int r = 0; r < RPG; r++) s += sm[q][r * TPR + ln];
       part[(size_t)w * ld + blockIdx.y * KB + threadIdx.x] = s;
     }
   }
@@ -316,9 +347,10 @@ int batch_vec_blocks(int64_t nrow, int ld) {
   return (int)b;
 }
 
-// workgroups of a product over n rows in row groups of 256/(kb*split): at most cap
-static int spmm_wgs(int32_t n, int kb, int split, int cap) {
-  const int rpg = 256 / (kb * split);
+// workgroups of a product over n rows in row groups of 256 cpt / (kb split)
+// (cpt columns per lane): at most cap
+static int spmm_wgs(int32_t n, int kb, int split, int cpt, int cap) {
+  const int rpg = 256 * cpt / (kb * split);
   const int64_t groups = ((int64_t)n + rpg - 1) / rpg;
   return (int)std::max<int64_t>(1, std::min<int64_t>(groups, cap));
 }
@@ -326,7 +358,11 @@ static int spmm_wgs(int32_t n, int kb, int split, int cap) {
 template <typename T, bool HAS_W, bool DOT, int KB, int S>
 static void spmm_ks(const DevBSRT<T> &A, const T *X, T *Y, const T *W, int ld, double alpha, double *part,
                     const BatchCtrl *c, hipStream_t s) {
-  dim3 grid((unsigned)spmm_wgs(A.n, KB, S, DOT ? kBatchParts : 4096), ld / KB);
+  constexpr int CPT = 16 / sizeof(T);
+  // every lane loads and stores CPT columns as one 16-byte vector
+  const uintptr_t mis = (uintptr_t)X | (uintptr_t)Y | (uintptr_t)W;
+  if ((mis & 15) != 0 || ld % CPT != 0) fail(ASPAMG_EINVAL, "SpMM operands must be 16-byte aligned column tiles");
+  dim3 grid((unsigned)spmm_wgs(A.n, KB, S, CPT, DOT ? kBatchParts : 4096), ld / KB);
   hipLaunchKernelGGL((k_bsr_spmm<T, HAS_W, DOT, KB, S>), grid, dim3(256), 0, s, A.n, A.rp, A.ci, A.v, X, Y, W, ld,
                      (T)alpha, part, c);
 }
@@ -375,7 +411,7 @@ void launch_spmm_dot(const DevBSRT<double> &A, const double *X, double *Y, int l
 }
 int spmm_dot_parts(const DevBSRT<double> &A, int ld, int kb) {
   kb = kb > ld ? ld : kb;
-  return spmm_wgs(A.n, kb, A.split, kBatchParts);
+  return spmm_wgs(A.n, kb, A.split, 16 / (int)sizeof(double), kBatchParts);
 }
 
 template <typename T>
