@@ -61,7 +61,7 @@ typedef struct {
   int32_t theta;          /* 5     strong connections kept per node                     */
   int32_t n_max;          /* 5     max interpolation entries per scalar row (<= 8)      */
   double  kappa_p;        /* 50    max conditioning of a local least-squares fit        */
-  int32_t rho_blocks;     /* 3     nodes added to an FSAI row per step                  */
+  int32_t rho_blocks;     /* 3     nodes added to an FSAI row per step (1..8)           */
   double  omega_bar;      /* 0.8   aFSAI outer loop target for omega = 2/lambda_1       */
   int32_t outer_fsai;     /* 1     run the aFSAI outer loop                             */
   int32_t d_p;            /* 2     max S-path length to interpolating coarse nodes      */

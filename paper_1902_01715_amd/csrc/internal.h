@@ -28,6 +28,7 @@ constexpr int64_t kTimedSlots = 1 << 20;  // layouts of larger operators are cho
 constexpr int kKpLanes = ASPAMG_KP_LANES;
 constexpr int kDotThreads = ASPAMG_DOT_THREADS;
 constexpr int kMaxFsaiNodes = 32;   // off-diagonal nodes an FSAI row may hold
+constexpr int kMaxGrowRho = 8;      // nodes one aFSAI growth step may add to a row
 constexpr int kMaxPEntries = 8;     // interpolation entries per scalar row (n_max cap)
 
 // Error raised inside the library; converted to aspamg_status at the ABI.
@@ -266,6 +267,10 @@ int vec_blocks(int64_t n);
 int launch_fsai_rows(const DevBSR &A, int32_t nrows, const int32_t *rows, const int32_t *pat_ptr,
                      const int32_t *pat_nodes, int mmax, double *g, double *psi, int32_t *fail_flag,
                      hipStream_t s);
+// aFSAI growth: for each listed block row (as for launch_fsai_rows, with the g it wrote) the
+// rho (<= kMaxGrowRho) nodes to add, add[i*rho ..] (-1 padded), chosen by quantised scores.
+void launch_fsai_grow(const DevBSR &A, int32_t nrows, const int32_t *rows, const int32_t *pat_ptr,
+                      const int32_t *pat_nodes, const double *g, int rho, int qbits, int32_t *add, hipStream_t s);
 // DPLS weights: for each listed scalar row i, K=cnt[i] chosen scalar rows sel[i*kMaxPEntries + k]
 // of the fine-level test space V (ntv columns): w = (C^T C)^{-1} C^T v.
 void launch_dpls_weights(int32_t nrows, const int32_t *row, const int32_t *cnt, const int32_t *sel,

@@ -368,6 +368,178 @@ __global__ void __launch_bounds__(256) k_divided(int64_t n, double a, const doub
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = x[i] / a;
 }
 
+// s rounded to `bits` significant bits, ties to even: the host quantiser of
+// the set-up decisions, for the device (normal values by integer operations on
+// the significand; zero, subnormal and non-finite values by frexp / ldexp).
+__device__ double quantize_dev(double s, int bits) {
+  uint64_t u = (uint64_t)__double_as_longlong(s);
+  const uint64_t ex = (u >> 52) & 0x7FF;
+  if (ex == 0 || ex == 0x7FF) {
+    if (s == 0.0 || !isfinite(s)) return s;
+    int e;
+    const double m = frexp(s, &e);
+    const double r = nearbyint(ldexp(m, bits));
+    return ldexp(r, e - bits);
+  }
+  const int drop = 53 - bits;
+  const uint64_t mask = (1ULL << drop) - 1, half = 1ULL << (drop - 1);
+  const uint64_t rem = u & mask;
+  u &= ~mask;
+  if (rem > half || (rem == half && ((u >> drop) & 1))) u += 1ULL << drop;
+  return __longlong_as_double((long long)u);
+}
+
+// position of column c in row r of A (columns ascending), or -1
+__device__ __forceinline__ int32_t find_col(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, int32_t r,
+                                            int32_t c) {
+  int32_t lo = rp[r], hi = rp[r + 1] - 1;
+  while (lo <= hi) {
+    const int32_t mid = (lo + hi) >> 1, cm = ci[mid];
+    if (cm == c) return mid;
+    if (cm < c) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+// (score, J) precedes (score', J') in the selection order: larger quantised
+// score first, then the lower node
+__device__ __forceinline__ bool grow_before(double a, int32_t ja, double b, int32_t jb) {
+  return a != b ? a > b : ja < jb;
+}
+
+// aFSAI pattern growth (Section 3.1, the adaptive step) for the listed block
+// rows, one wavefront per row, from the rows' current pattern B (ascending) and
+// the scaled rows g that k_fsai_rows wrote for it.  Candidates are the nodes
+// J < I outside B adjacent in A to B u {I}; with g' = g / g_last,
+//   h_{(I,d),(J,e)} = sum over the pattern index k of A[(J,e), l_k] g'_k
+// (k ascending, so every h gets its terms in the same order as the host walk),
+// score_J = sum_d sum_e h^2, quantised.  The rho first candidates in the order
+// (score descending, J ascending) are written to add[i*rho ..], -1 padded;
+// nothing is added when |B| + rho exceeds kMaxFsaiNodes.  A candidate reached
+// from several pattern nodes is scored once, by the pair of its first one.
+__global__ void __launch_bounds__(64) k_fsai_grow(int32_t nrows, const int32_t *__restrict__ rows,
+                                                  const int32_t *__restrict__ pat_ptr,
+                                                  const int32_t *__restrict__ pat_nodes, const double *__restrict__ g,
+                                                  const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                  const double *__restrict__ v, int rho, int qbits,
+                                                  int32_t *__restrict__ add) {
+  constexpr int GS = 3 * kMaxFsaiNodes + 3;
+  __shared__ int32_t K[kMaxFsaiNodes + 1];
+  __shared__ int32_t off[kMaxFsaiNodes + 2];
+  __shared__ double gp[3][GS];
+  const int32_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (i >= nrows) return;
+  const int32_t I = rows[i];
+  const int32_t p0 = pat_ptr[i], nb = pat_ptr[i + 1] - p0;
+  if (lane < rho) add[(size_t)i * rho + lane] = -1;
+  if (nb + rho > kMaxFsaiNodes) return;                 // uniform in the wavefront
+  // pattern nodes, then I; the candidate count of each (columns J < I of its row)
+  if (lane <= nb) {
+    const int32_t Kp = lane < nb ? pat_nodes[p0 + lane] : I;
+    K[lane] = Kp;
+    int32_t lo = rp[Kp], hi = rp[Kp + 1];
+    while (lo < hi) {                                    // first column >= I
+      const int32_t mid = (lo + hi) >> 1;
+      if (ci[mid] < I) lo = mid + 1;
+      else hi = mid;
+    }
+    off[lane + 1] = lo - rp[Kp];
+  }
+  // g' rows (compact layout of k_fsai_rows: rows of 3 nb + 3 entries)
+  const int rs = 3 * nb + 3;
+  const double *gi = g + (size_t)3 * (3 * (size_t)p0 + 3 * (size_t)i);
+  for (int t = lane; t < 3 * rs; t += 64) {
+    const int d = t / rs, k = t % rs, md = 3 * nb + d + 1;
+    if (k < md) gp[d][k] = gi[d * rs + k] / gi[d * rs + md - 1];
+  }
+  __syncthreads();
+  if (lane == 0) {
+    off[0] = 0;
+    for (int p = 0; p <= nb; p++) off[p + 1] += off[p];
+  }
+  __syncthreads();
+  const int32_t T = off[nb + 1];
+  // this lane's best candidates, in selection order
+  double bs[kMaxGrowRho];
+  int32_t bj[kMaxGrowRho];
+  int nbest = 0;
+  for (int32_t t = lane; t < T; t += 64) {
+    int p = 0;
+    while (off[p + 1] <= t) p++;
+    const int32_t J = ci[rp[K[p]] + (t - off[p])];
+    // outside B (B ascending)
+    int lo = 0, hi = nb - 1;
+    bool inB = false;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      if (K[mid] == J) { inB = true; break; }
+      if (K[mid] < J) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    if (inB) continue;
+    // scored by its first pattern node only
+    bool first = true;
+    for (int q = 0; q < p && first; q++) first = find_col(rp, ci, J, K[q]) < 0;
+    if (!first) continue;
+    double h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = p; q <= nb; q++) {
+      const int32_t pos = find_col(rp, ci, J, K[q]);    // block (J, K_q)
+      if (pos < 0) continue;
+      const double *blk = v + (size_t)pos * 9;
+      for (int d = 0; d < 3; d++) {
+        const int kend = min(3, 3 * nb + d + 1 - 3 * q);
+        for (int c = 0; c < kend; c++) {
+          const double gk = gp[d][3 * q + c];
+          h[d * 3 + 0] += blk[c] * gk;
+          h[d * 3 + 1] += blk[3 + c] * gk;
+          h[d * 3 + 2] += blk[6 + c] * gk;
+        }
+      }
+    }
+    double score = 0.0;
+    for (int d = 0; d < 3; d++) {
+      score += h[d * 3 + 0] * h[d * 3 + 0];
+      score += h[d * 3 + 1] * h[d * 3 + 1];
+      score += h[d * 3 + 2] * h[d * 3 + 2];
+    }
+    if (!(score > 0.0)) continue;
+    const double qs = quantize_dev(score, qbits);
+    // insert into this lane's sorted best list (at most rho kept)
+    int at = nbest;
+    while (at > 0 && grow_before(qs, J, bs[at - 1], bj[at - 1])) at--;
+    if (at >= rho) continue;
+    for (int m = min(nbest, rho - 1); m > at; m--) {
+      bs[m] = bs[m - 1];
+      bj[m] = bj[m - 1];
+    }
+    bs[at] = qs;
+    bj[at] = J;
+    if (nbest < rho) nbest++;
+  }
+  // rho rounds: the wavefront's first remaining candidate
+  int head = 0;
+  for (int r = 0; r < rho; r++) {
+    double s = head < nbest ? bs[head] : -1.0;
+    int32_t j = head < nbest ? bj[head] : 0x7FFFFFFF;
+    int src = lane;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double s2 = __shfl_xor(s, o, 64);
+      const int32_t j2 = __shfl_xor(j, o, 64);
+      const int src2 = __shfl_xor(src, o, 64);
+      if (grow_before(s2, j2, s, j)) {
+        s = s2;
+        j = j2;
+        src = src2;
+      }
+    }
+    if (s < 0.0) break;                                  // no candidate left (uniform)
+    if (lane == src) head++;
+    if (lane == 0) add[(size_t)i * rho + r] = j;
+  }
+}
+
 // Test-space iteration (SRQCG): columns stored one after another, n entries each.
 // out = 2 (sz - q z) / f, the gradient of the Rayleigh quotient of z
 __global__ void __launch_bounds__(256) k_rq_gradient(int64_t n, double q, double f, const double *__restrict__ sz,
@@ -462,6 +634,13 @@ int launch_fsai_rows(const DevBSR &A, int32_t nrows, const int32_t *rows, const 
   hipLaunchKernelGGL(k_fsai_rows, dim3(nrows), dim3(64), lds, s, nrows, rows, pat_ptr, pat_nodes, A.rp, A.ci, A.v,
                      mmax, g, psi, fail_flag);
   return 0;
+}
+
+void launch_fsai_grow(const DevBSR &A, int32_t nrows, const int32_t *rows, const int32_t *pat_ptr,
+                      const int32_t *pat_nodes, const double *g, int rho, int qbits, int32_t *add, hipStream_t s) {
+  if (nrows == 0) return;
+  hipLaunchKernelGGL(k_fsai_grow, dim3(nrows), dim3(64), 0, s, nrows, rows, pat_ptr, pat_nodes, g, A.rp, A.ci, A.v,
+                     rho, qbits, add);
 }
 
 void launch_dpls_weights(int32_t nrows, const int32_t *row, const int32_t *cnt, const int32_t *sel,

@@ -117,18 +117,21 @@ void to_host(hipStream_t s, T *hdst, const T *d, size_t n) {
 
 // ------------------------------------------------------------------------
 // aFSAI (Section 3.1).  Each block row I keeps a sorted node set B (J < I);
-// the GPU factors A[l,l] and returns the three scaled rows g and psi.
+// the GPU factors A[l,l] and returns the three scaled rows g and psi, and
+// from the same g the nodes the row's next growth step would add.
 // ------------------------------------------------------------------------
 struct FsaiState {
   int32_t n;
+  int rho;                        // nodes per growth step
   std::vector<int32_t> nb;        // |B| per row
   std::vector<int32_t> nodes;     // n * kMaxFsaiNodes
   std::vector<double> g;          // n * 3 * gstride
   std::vector<double> psi;        // n * 3
+  std::vector<int32_t> add;       // n * rho: the next growth of the row's current pattern, -1 padded
   static constexpr int gstride = 3 * kMaxFsaiNodes + 3;
 };
 
-// Factor the listed rows on the GPU and store g / psi in the state.
+// Factor the listed rows on the GPU; store g / psi and the next growth in the state.
 void fsai_factor(aspamg_ctx *h, const Level &L, FsaiState &F, const std::vector<int32_t> &rows) {
   if (rows.empty()) return;
   const int32_t nr = (int32_t)rows.size();
@@ -160,13 +163,19 @@ void fsai_factor(aspamg_ctx *h, const Level &L, FsaiState &F, const std::vector<
     launch_fsai_rows(L.dA, m, drows.as<int32_t>(), dptr.as<int32_t>(), dnodes.as<int32_t>(), mmax, dg.as<double>(),
                      dpsi.as<double>(), dfail.as<int32_t>(), h->stream);
     HIPCHK(hipGetLastError());
+    Scratch dadd((size_t)m * F.rho * 4);
+    launch_fsai_grow(L.dA, m, drows.as<int32_t>(), dptr.as<int32_t>(), dnodes.as<int32_t>(), dg.as<double>(), F.rho,
+                     h->p.quant_bits, dadd.as<int32_t>(), h->stream);
+    HIPCHK(hipGetLastError());
     double *g = static_cast<double *>(staging(h, gn * 8));
     std::vector<double> psi((size_t)m * 3);
+    std::vector<int32_t> add((size_t)m * F.rho);
     int32_t bad = 0;
-    to_host(h->stream, g, dg.as<double>(), gn);
-    to_host(h->stream, psi.data(), dpsi.as<double>(), psi.size());
     to_host(h->stream, &bad, dfail.as<int32_t>(), 1);
     if (bad) fail(ASPAMG_ENOT_SPD, "aFSAI: a local system is not positive definite");
+    to_host(h->stream, g, dg.as<double>(), gn);
+    to_host(h->stream, psi.data(), dpsi.as<double>(), psi.size());
+    to_host(h->stream, add.data(), dadd.as<int32_t>(), add.size());
 #pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < m; i++) {
       const int32_t I = rows[c0 + i];
@@ -178,6 +187,7 @@ void fsai_factor(aspamg_ctx *h, const Level &L, FsaiState &F, const std::vector<
         std::memset(dst + rs, 0, (gs - rs) * sizeof(double));
       }
       std::memcpy(F.psi.data() + (size_t)I * 3, psi.data() + (size_t)i * 3, 3 * sizeof(double));
+      std::memcpy(F.add.data() + (size_t)I * F.rho, add.data() + (size_t)i * F.rho, F.rho * sizeof(int32_t));
     }
   }
 }
@@ -188,111 +198,22 @@ inline double psi_sum(const FsaiState &F, int32_t I) {
   return s;
 }
 
-// Column view of A: for every column K the rows J with a block (J, K), in
-// ascending order, and that block's position in A.
-struct ColumnView {
-  std::vector<int64_t> cp;
-  std::vector<int32_t> row;
-  std::vector<int64_t> pos;
-  explicit ColumnView(const HostBSR &A) : cp((size_t)A.nc + 1, 0), row(A.ci.size()), pos(A.ci.size()) {
-    for (int32_t c : A.ci) cp[(size_t)c + 1]++;
-    for (int32_t c = 0; c < A.nc; c++) cp[(size_t)c + 1] += cp[c];
-    std::vector<int64_t> next(cp.begin(), cp.end() - 1);
-    for (int32_t r = 0; r < A.n; r++)
-      for (int64_t k = A.rp[r]; k < A.rp[r + 1]; k++) {
-        const int64_t at = next[A.ci[k]]++;
-        row[at] = r;
-        pos[at] = k;
-      }
-  }
-};
-
-// Per-thread work space of fsai_grow: mark[J] is the accumulator slot of
-// candidate J, -2 for a member of the row's pattern, -1 otherwise (restored
-// after every row).
-struct GrowScratch {
-  std::vector<int32_t> mark, cand;
-  std::vector<double> h;
-  std::vector<std::pair<double, int32_t>> sc;
-  explicit GrowScratch(int32_t n) : mark(n, -1) {}
-};
-
-// Pattern growth of one row (the adaptive step): candidates are the nodes
-// J < I, not in B, adjacent in A to B u {I}; with g' = g / g_last,
-// h_{(I,d),(J,e)} = sum over the pattern index k (ascending) of A[(J,e), l_k] g'_k
-// and score_J = sum_d sum_e h^2.  The rho nodes with the largest quantised
-// score (ties to the lowest J) are added.  Returns the number added.
-// The pattern nodes are walked in ascending order and, for each, the rows J
-// of its column in A, so every candidate's h receives its terms in the
-// ascending order of k above (A's pattern is symmetric, so the column of a
-// pattern node lists exactly the candidates adjacent to it).
-int fsai_grow(const HostBSR &A, const ColumnView &C, FsaiState &F, int32_t I, int rho, const Q &q,
-              GrowScratch &W) {
+// One growth step of row I (the adaptive step): the nodes the device chose
+// from the row's current pattern and g (scores h_{(I,d),(J,e)} over the
+// candidates J < I adjacent to B u {I}, the rho largest quantised, ties to the
+// lowest J) join B.  Returns the number added.
+int apply_growth(FsaiState &F, int32_t I) {
   const int32_t nb = F.nb[I];
-  if (nb + rho > kMaxFsaiNodes) return 0;
-  const int32_t *B = F.nodes.data() + (size_t)I * kMaxFsaiNodes;
-  const int gs = FsaiState::gstride;
-  const double *g = F.g.data() + (size_t)I * 3 * gs;
-  double gp[3][gs];
-  for (int d = 0; d < 3; d++) {
-    const int md = 3 * nb + d + 1;
-    const double gl = g[d * gs + md - 1];
-    for (int k = 0; k < md; k++) gp[d][k] = g[d * gs + k] / gl;
-  }
-  for (int b = 0; b < nb; b++) W.mark[B[b]] = -2;
-  W.cand.clear();
-  W.h.clear();
-  for (int p = 0; p <= nb; p++) {
-    const int32_t K = p < nb ? B[p] : I;
-    for (int64_t k = C.cp[K]; k < C.cp[(size_t)K + 1]; k++) {
-      const int32_t J = C.row[k];
-      if (J >= I) break;   // rows ascend
-      int32_t slot = W.mark[J];
-      if (slot == -2) continue;
-      if (slot < 0) {
-        slot = (int32_t)W.cand.size();
-        W.mark[J] = slot;
-        W.cand.push_back(J);
-        W.h.resize(W.h.size() + 9, 0.0);
-      }
-      const double *blk = A.v.data() + (size_t)C.pos[k] * 9;   // block (J, K)
-      double *hj = W.h.data() + (size_t)slot * 9;
-      for (int d = 0; d < 3; d++) {
-        const int kend = std::min(3, 3 * nb + d + 1 - 3 * p);
-        for (int c = 0; c < kend; c++) {
-          const double gk = gp[d][3 * p + c];
-          hj[d * 3 + 0] += blk[c] * gk;
-          hj[d * 3 + 1] += blk[3 + c] * gk;
-          hj[d * 3 + 2] += blk[6 + c] * gk;
-        }
-      }
-    }
-  }
-  W.sc.clear();
-  for (size_t j = 0; j < W.cand.size(); j++) {
-    const double *hj = W.h.data() + j * 9;
-    double score = 0.0;
-    for (int d = 0; d < 3; d++) {
-      score += hj[d * 3 + 0] * hj[d * 3 + 0];
-      score += hj[d * 3 + 1] * hj[d * 3 + 1];
-      score += hj[d * 3 + 2] * hj[d * 3 + 2];
-    }
-    if (score > 0.0) W.sc.emplace_back(q(score), W.cand[j]);
-    W.mark[W.cand[j]] = -1;
-  }
-  for (int b = 0; b < nb; b++) W.mark[B[b]] = -1;
-  if (W.sc.empty()) return 0;
-  // the rho first in the order (score descending, J ascending): a total order,
-  // so the selection is that of a full sort
-  const int add = std::min<int>(rho, (int)W.sc.size());
-  std::partial_sort(W.sc.begin(), W.sc.begin() + add, W.sc.end(), [](const auto &a, const auto &b) {
-    return a.first != b.first ? a.first > b.first : a.second < b.second;
-  });
-  int32_t *Bw = F.nodes.data() + (size_t)I * kMaxFsaiNodes;
-  for (int a = 0; a < add; a++) Bw[nb + a] = W.sc[a].second;
-  F.nb[I] = nb + add;
-  std::sort(Bw, Bw + nb + add);
-  return add;
+  const int32_t *a = F.add.data() + (size_t)I * F.rho;
+  int k = 0;
+  while (k < F.rho && a[k] >= 0) k++;
+  if (k == 0) return 0;
+  int32_t *B = F.nodes.data() + (size_t)I * kMaxFsaiNodes;
+  for (int j = 0; j < k; j++) B[nb + j] = a[j];
+  F.nb[I] = nb + k;
+  std::sort(B, B + nb + k);
+  std::fill(F.add.data() + (size_t)I * F.rho, F.add.data() + (size_t)(I + 1) * F.rho, -1);
+  return k;
 }
 
 HostBSR fsai_assemble(const FsaiState &F) {
@@ -417,6 +338,8 @@ void build_fsai(aspamg_ctx *h, Level &L) {
   F.nodes.assign((size_t)n * kMaxFsaiNodes, -1);
   F.g.assign((size_t)n * 3 * FsaiState::gstride, 0.0);
   F.psi.assign((size_t)n * 3, 0.0);
+  F.rho = p.rho_blocks;
+  F.add.assign((size_t)n * F.rho, -1);
   std::vector<int32_t> active(n);
   std::iota(active.begin(), active.end(), 0);
   PhaseClock clk;
@@ -424,16 +347,10 @@ void build_fsai(aspamg_ctx *h, Level &L) {
   clk.tick(-1, "fsai factor");
   std::vector<double> psi_prev(n);
   for (int32_t i = 0; i < n; i++) psi_prev[i] = psi_sum(F, i);
-  const int nthreads = omp_get_max_threads();
-  const ColumnView cols(L.A);
-  std::vector<GrowScratch> work(nthreads, GrowScratch(n));
   for (int step = 0; step < p.k_g && !active.empty(); step++) {
     std::vector<char> grew(active.size(), 0);
-#pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t a = 0; a < (int64_t)active.size(); a++) {
-      const int t = omp_get_thread_num();
-      grew[a] = fsai_grow(L.A, cols, F, active[a], p.rho_blocks, q, work[t]) > 0;
-    }
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < (int64_t)active.size(); a++) grew[a] = apply_growth(F, active[a]) > 0;
     std::vector<int32_t> next;
     for (size_t a = 0; a < active.size(); a++)
       if (grew[a]) next.push_back(active[a]);
@@ -465,11 +382,8 @@ void build_fsai(aspamg_ctx *h, Level &L) {
     if (!(q(L.omega_q) < q(p.omega_bar))) break;
     if (!(L.G.nnzb() < L.A.nnzb())) break;
     std::vector<char> grew(n, 0);
-#pragma omp parallel for schedule(dynamic, 256)
-    for (int32_t I = 0; I < n; I++) {
-      const int t = omp_get_thread_num();
-      grew[I] = fsai_grow(L.A, cols, F, I, p.rho_blocks, q, work[t]) > 0;
-    }
+#pragma omp parallel for schedule(static)
+    for (int32_t I = 0; I < n; I++) grew[I] = apply_growth(F, I) > 0;
     std::vector<int32_t> rows;
     for (int32_t I = 0; I < n; I++)
       if (grew[I]) rows.push_back(I);
