@@ -141,3 +141,28 @@ def test_operators_match_oracle(pair, which, prec, product_bound):
         assert np.abs(y - y_ref).max() <= 1e-14 * scale
     else:
         assert np.all(np.abs(y - y_ref) <= product_bound(M, x, 32))
+
+
+@pytest.mark.parametrize("name,kw", [("cant40x4x4", {"omega_bar": 0.95}),
+                                     ("cube8_randE", {"rho_blocks": 5, "k_g": 2}),
+                                     ("cube7", {"rho_blocks": 8, "k_g": 3})])
+def test_fsai_growth_variants_bit_exact(name, kw, cuda, oracle_lib):
+    """The aFSAI outer loop (omega_q below omega_bar: every row grows again
+    from its last choice) and other step sizes: G bit for bit the oracle's."""
+    print(f"[case {name} {kw}]", flush=True)
+    p = CASES[name]()
+    S, H = _setup(p, cuda, oracle_lib, **kw)
+    try:
+        rounds = []
+        for l in range(H.nlev - 1):
+            oi, gi = H.info(l), S.level_info(l)
+            rounds.append(oi["fsai_rounds"])
+            assert gi["fsai_rounds"] == oi["fsai_rounds"], l
+            G_o, G_g = H.G(l), S.level_matrix(l, 1)
+            assert np.array_equal(G_o.rp, G_g[0]) and np.array_equal(G_o.ci, G_g[1]), f"level {l}: G pattern"
+            assert np.array_equal(G_o.v, G_g[2]), f"level {l}: FSAI values"
+            assert abs(gi["omega_q"] - oi["omega_q"]) <= 1e-9 * oi["omega_q"]
+        if "omega_bar" in kw:
+            assert max(rounds) > 0, rounds          # the outer loop ran
+    finally:
+        S.close()
