@@ -1217,7 +1217,8 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     Level &L = h->lev[l];
     const int32_t N = L.A.n;
     L.dA = upload_bsr(h, L.A);
-    L.A64 = upload_sell<double>(h, L.A, l == 0 ? kKpLanes : 0);   // lanes per fine row of q = K p
+    // lanes per fine row of q = K p; the layouts scatter from the block values of dA
+    L.A64 = upload_sell<double>(h, L.A, l == 0 ? kKpLanes : 0, true, L.dA.v);
     L.A32 = derive_fp32(h, L.A64);
     clk.tick(l, "upload A");
     if ((int64_t)N * 3 <= p.coarse_max_dof || l == p.max_levels - 1 || l == 31 || ntv == 0) {
