@@ -405,12 +405,31 @@ void build_fsai(aspamg_ctx *h, Level &L) {
 // ------------------------------------------------------------------------
 void orthonormalize(std::vector<double> &V, int64_t nrows, int ntv) {
   std::vector<double> W((size_t)ntv * ntv), Lm((size_t)ntv * ntv, 0.0);
-  for (int a = 0; a < ntv; a++)
-    for (int c = 0; c < ntv; c++) {
-      double s = 0.0;
-      for (int64_t i = 0; i < nrows; i++) s += V[(size_t)i * ntv + a] * V[(size_t)i * ntv + c];
-      W[a * ntv + c] = s;
+  // Gram entries (a <= c; W_ca is the same sum): the pairs are dealt to the
+  // threads, and each thread streams the rows once for all its pairs, every
+  // entry still summed over the rows in ascending order
+  const int npairs = ntv * (ntv + 1) / 2;
+  std::vector<int> pa(npairs), pc(npairs);
+  for (int a = 0, k = 0; a < ntv; a++)
+    for (int c = a; c < ntv; c++, k++) {
+      pa[k] = a;
+      pc[k] = c;
     }
+#pragma omp parallel
+  {
+    const int t = omp_get_thread_num(), nt = omp_get_num_threads();
+    std::vector<int> mine;
+    for (int k = t; k < npairs; k += nt) mine.push_back(k);
+    std::vector<double> acc(mine.size(), 0.0);
+    for (int64_t i = 0; i < nrows; i++) {
+      const double *v = V.data() + (size_t)i * ntv;
+      for (size_t m = 0; m < mine.size(); m++) acc[m] += v[pa[mine[m]]] * v[pc[mine[m]]];
+    }
+    for (size_t m = 0; m < mine.size(); m++) {
+      W[pa[mine[m]] * ntv + pc[mine[m]]] = acc[m];
+      W[pc[mine[m]] * ntv + pa[mine[m]]] = acc[m];
+    }
+  }
   std::vector<char> drop(ntv, 0);
   for (int j = 0; j < ntv; j++) {
     double acc = 0.0;
