@@ -1037,29 +1037,48 @@ HostBSR spgemm_pattern(const HostBSR &X, const HostBSR &Y, bool host_values = tr
   Z.n = X.n;
   Z.nc = Y.nc;
   Z.rp.assign(X.n + 1, 0);
-  std::vector<std::vector<int32_t>> rows(X.n);
+  // two passes over the product structure: row lengths, then the columns of
+  // each row written in place and sorted
 #pragma omp parallel
   {
     std::vector<int32_t> mark(Y.nc, -1);
 #pragma omp for schedule(dynamic, 512)
     for (int32_t i = 0; i < X.n; i++) {
-      auto &r = rows[i];
+      int64_t cnt = 0;
       for (int64_t k = X.rp[i]; k < X.rp[i + 1]; k++) {
         const int32_t l = X.ci[k];
         for (int64_t q = Y.rp[l]; q < Y.rp[l + 1]; q++) {
           const int32_t j = Y.ci[q];
           if (mark[j] != i) {
             mark[j] = i;
-            r.push_back(j);
+            cnt++;
           }
         }
       }
-      std::sort(r.begin(), r.end());
+      Z.rp[i + 1] = cnt;
     }
   }
-  for (int32_t i = 0; i < X.n; i++) Z.rp[i + 1] = Z.rp[i] + (int64_t)rows[i].size();
+  for (int32_t i = 0; i < X.n; i++) Z.rp[i + 1] += Z.rp[i];
   Z.ci.resize(Z.rp[X.n]);
-  for (int32_t i = 0; i < X.n; i++) std::copy(rows[i].begin(), rows[i].end(), Z.ci.begin() + Z.rp[i]);
+#pragma omp parallel
+  {
+    std::vector<int32_t> mark(Y.nc, -1);
+#pragma omp for schedule(dynamic, 512)
+    for (int32_t i = 0; i < X.n; i++) {
+      int64_t at = Z.rp[i];
+      for (int64_t k = X.rp[i]; k < X.rp[i + 1]; k++) {
+        const int32_t l = X.ci[k];
+        for (int64_t q = Y.rp[l]; q < Y.rp[l + 1]; q++) {
+          const int32_t j = Y.ci[q];
+          if (mark[j] != i) {
+            mark[j] = i;
+            Z.ci[at++] = j;
+          }
+        }
+      }
+      std::sort(Z.ci.begin() + Z.rp[i], Z.ci.begin() + Z.rp[i + 1]);
+    }
+  }
   if (host_values) Z.v.assign((size_t)Z.rp[X.n] * 9, 0.0);
   return Z;
 }
