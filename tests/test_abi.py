@@ -52,3 +52,21 @@ def test_setup_rejects_invalid_arguments_before_touching_a_device():
     assert L.aspamg_set_cycle_precision(None, 32) == aspamg.EINVAL
     assert L.aspamg_solve(None, None, None, None) == aspamg.EINVAL
     assert L.aspamg_destroy(None) == aspamg.OK
+
+
+def test_setup_rejects_invalid_parameters_before_touching_a_device():
+    import numpy as np
+    L = aspamg.lib()
+    rp = np.array([0, 1], dtype=np.int32)
+    ci = np.array([0], dtype=np.int32)
+    v = np.eye(3).reshape(1, 3, 3).copy()
+    V0 = np.zeros((1, 3, 6))
+    for kw in ({"rho_blocks": 9}, {"rho_blocks": 0}, {"n_rq": -1}, {"n_rq": 1001}, {"dense_tail_dof": 8193},
+               {"cycle_precision": 16}):
+        p = aspamg.default_params(**kw)
+        h = ctypes.c_void_p()
+        rc = L.aspamg_setup(ctypes.byref(p), 1, 1, rp.ctypes.data_as(ctypes.c_void_p),
+                            ci.ctypes.data_as(ctypes.c_void_p), v.ctypes.data_as(ctypes.c_void_p), 6,
+                            V0.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(h))
+        assert rc == aspamg.EINVAL and not h.value, kw
+        assert b"invalid parameter" in L.aspamg_last_error(), kw
