@@ -413,7 +413,7 @@ __device__ __forceinline__ bool grow_before(double a, int32_t ja, double b, int3
 // the scaled rows g that k_fsai_rows wrote for it.  Candidates are the nodes
 // J < I outside B adjacent in A to B u {I}; with g' = g / g_last,
 //   h_{(I,d),(J,e)} = sum over the pattern index k of A[(J,e), l_k] g'_k
-// (k ascending, so every h gets its terms in the same order as the host walk),
+// (summed over k ascending, whichever pattern node found the candidate),
 // score_J = sum_d sum_e h^2, quantised.  The rho first candidates in the order
 // (score descending, J ascending) are written to add[i*rho ..], -1 padded;
 // nothing is added when |B| + rho exceeds kMaxFsaiNodes.  A candidate reached
