@@ -764,23 +764,38 @@ StrongGraph strong_graph(const Level &L, int ntv, int theta, const Q &q, const s
       nkeep[i] = kk;
     }
   }
-  // union: collect directed edges both ways, sort, unique
-  std::vector<std::vector<int32_t>> adj(n);
+  // union: every kept edge both ways, bucketed by row (counts, then a fill in
+  // row order), each row sorted and deduplicated, then compacted
+  std::vector<int64_t> bp((size_t)n + 1, 0);
   for (int32_t i = 0; i < n; i++)
     for (int a = 0; a < nkeep[i]; a++) {
-      const int32_t j = keep[(size_t)i * theta + a];
-      adj[i].push_back(j);
-      adj[j].push_back(i);
+      bp[(size_t)i + 1]++;
+      bp[(size_t)keep[(size_t)i * theta + a] + 1]++;
     }
+  for (int32_t i = 0; i < n; i++) bp[(size_t)i + 1] += bp[i];
+  std::vector<int32_t> both(bp[n]);
+  {
+    std::vector<int64_t> at(bp.begin(), bp.end() - 1);
+    for (int32_t i = 0; i < n; i++)
+      for (int a = 0; a < nkeep[i]; a++) {
+        const int32_t j = keep[(size_t)i * theta + a];
+        both[at[i]++] = j;
+        both[at[j]++] = i;
+      }
+  }
+  std::vector<int64_t> len(n);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int32_t i = 0; i < n; i++) {
+    auto b = both.begin() + bp[i], e = both.begin() + bp[(size_t)i + 1];
+    std::sort(b, e);
+    len[i] = std::unique(b, e) - b;
+  }
   StrongGraph S;
   S.rp.assign(n + 1, 0);
-  for (int32_t i = 0; i < n; i++) {
-    std::sort(adj[i].begin(), adj[i].end());
-    adj[i].erase(std::unique(adj[i].begin(), adj[i].end()), adj[i].end());
-    S.rp[i + 1] = S.rp[i] + (int64_t)adj[i].size();
-  }
+  for (int32_t i = 0; i < n; i++) S.rp[i + 1] = S.rp[i] + len[i];
   S.ci.resize(S.rp[n]);
-  for (int32_t i = 0; i < n; i++) std::copy(adj[i].begin(), adj[i].end(), S.ci.begin() + S.rp[i]);
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; i++) std::copy(both.begin() + bp[i], both.begin() + bp[i] + len[i], S.ci.begin() + S.rp[i]);
   return S;
 }
 
