@@ -1010,24 +1010,32 @@ void build_prolongation(aspamg_ctx *h, Level &L, const StrongGraph &S) {
   P.n = n;
   P.nc = L.nc;
   P.rp.assign(n + 1, 0);
-  std::vector<std::vector<int32_t>> rowc(n);
+  // coarse nodes of each row, sorted and unique (at most 3 kMaxPEntries)
+  constexpr int kRowMax = 3 * kMaxPEntries;
+  std::vector<int32_t> rowc((size_t)n * kRowMax), nrc(n, 0);
+#pragma omp parallel for schedule(static)
   for (int32_t I = 0; I < n; I++) {
-    if (L.cf[I] == 1) rowc[I].push_back(L.cidx[I]);
+    int32_t *rc = rowc.data() + (size_t)I * kRowMax;
+    int m = 0;
+    if (L.cf[I] == 1) rc[m++] = L.cidx[I];
     else if (L.cf[I] == 0) {
       for (int d = 0; d < 3; d++) {
         const size_t r = (size_t)I * 3 + d;
-        for (int k = 0; k < L.pcount[r]; k++) rowc[I].push_back(L.pcols[r * p.n_max + k] / 3);
+        for (int k = 0; k < L.pcount[r]; k++) rc[m++] = L.pcols[r * p.n_max + k] / 3;
       }
-      std::sort(rowc[I].begin(), rowc[I].end());
-      rowc[I].erase(std::unique(rowc[I].begin(), rowc[I].end()), rowc[I].end());
+      std::sort(rc, rc + m);
+      m = (int)(std::unique(rc, rc + m) - rc);
     }
-    P.rp[I + 1] = P.rp[I] + (int64_t)rowc[I].size();
+    nrc[I] = m;
   }
+  for (int32_t I = 0; I < n; I++) P.rp[I + 1] = P.rp[I] + nrc[I];
   P.ci.resize(P.rp[n]);
   P.v.assign((size_t)P.rp[n] * 9, 0.0);
+#pragma omp parallel for schedule(static)
   for (int32_t I = 0; I < n; I++) {
     const int64_t base = P.rp[I];
-    std::copy(rowc[I].begin(), rowc[I].end(), P.ci.begin() + base);
+    const int32_t *rc = rowc.data() + (size_t)I * kRowMax;
+    std::copy(rc, rc + nrc[I], P.ci.begin() + base);
     if (L.cf[I] == 1) {
       for (int d = 0; d < 3; d++) P.v[(size_t)base * 9 + d * 4] = 1.0;
     } else if (L.cf[I] == 0) {
@@ -1036,7 +1044,7 @@ void build_prolongation(aspamg_ctx *h, Level &L, const StrongGraph &S) {
         for (int k = 0; k < L.pcount[r]; k++) {
           const int32_t sc = L.pcols[r * p.n_max + k];
           const int32_t cnod = sc / 3, e = sc % 3;
-          const int64_t qpos = base + (std::lower_bound(rowc[I].begin(), rowc[I].end(), cnod) - rowc[I].begin());
+          const int64_t qpos = base + (std::lower_bound(rc, rc + nrc[I], cnod) - rc);
           P.v[(size_t)qpos * 9 + d * 3 + e] = wr[r * kMaxPEntries + k];
         }
       }
