@@ -119,3 +119,22 @@ def test_srqcg_hierarchy_solves(mk, oracle_lib):
         Vm = V.reshape(-1, V.shape[-1])
         keep = np.abs(Vm).max(axis=0) > 0
         assert np.allclose(Vm[:, keep].T @ Vm[:, keep], np.eye(keep.sum()), atol=1e-10)
+
+
+def test_srqcg_converges_on_elasticity(oracle_lib):
+    """On the 7^3 elasticity cube with its own aFSAI factor G (b = 3), the
+    columns converge to the four smallest eigenpairs of S = G A G^T computed
+    by a dense symmetric eigensolver: Ritz values to 1e-11 and V = G^T Z
+    spanning G^T of the eigenvectors."""
+    p = PR.c1_cube(7)
+    H = O.Hierarchy(p.row_ptr, p.col, p.vals, p.V0)
+    G = H.G(0)
+    Gd, A = G.to_dense(), p.to_scipy().toarray()
+    S = Gd @ A @ Gd.T
+    w, X = np.linalg.eigh((S + S.T) / 2)
+    V0 = np.random.default_rng(3).standard_normal((p.n_dof, 4))
+    V, rq = O.srqcg(p.row_ptr, p.col, p.vals, G, V0, 100, 1)
+    assert np.max(np.abs(rq - w[:4]) / w[:4]) < 1e-11
+    Qv = np.linalg.qr(V)[0]
+    Qe = np.linalg.qr(Gd.T @ X[:, :4])[0]
+    assert np.linalg.svd(Qv.T @ Qe, compute_uv=False).min() > 1 - 1e-8
