@@ -18,13 +18,19 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 OK, NOT_CONVERGED, EINVAL, ENOMEM, ENOTSPD, EBREAK, ENAN = 0, 1, -1, -2, -4, -5, -6
 
 
+def compile_source(src: str, out: str) -> str:
+    """gcc build of one oracle source file (no fast-math, no FP contraction)."""
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                           "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no fast-math, no FP contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+        compile_source(_SRC, _LIB)
     return _LIB
 
 
@@ -41,14 +47,28 @@ class Params(C.Structure):
 
 
 _lib = None
+# None: the built liboracle.so; else another compiled copy of the source (see
+# use_library; ORACLE_LIBRARY in the environment sets it for a whole process)
+_lib_path = os.environ.get("ORACLE_LIBRARY") or None
+
+
+def use_library(path):
+    """Load the oracle from another compiled copy of its source (or, with None,
+    the built one again).  The mutation tests use it to run the pins against
+    copies with a planted mistake."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        path = _lib_path
+        if path is None:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        L = C.CDLL(path)
         P = C.c_void_p
         L.oracle_setup.restype = C.c_int
         L.oracle_setup.argtypes = [C.POINTER(Params), C.c_int32, P, P, P, C.c_int32, P, C.POINTER(C.c_void_p)]
@@ -65,6 +85,8 @@ def lib():
         L.oracle_level_S.argtypes = [C.c_void_p, C.c_int, P, P]
         L.oracle_level_soc.argtypes = [C.c_void_p, C.c_int, P]
         L.oracle_level_Pscalar.argtypes = [C.c_void_p, C.c_int, P, P]
+        L.oracle_level_candidates.restype = C.c_int64
+        L.oracle_level_candidates.argtypes = [C.c_void_p, C.c_int, P, P]
         L.oracle_coarse_factor.argtypes = [C.c_void_p, P]
         L.oracle_vcycle.argtypes = [C.c_void_p, P, P]
         L.oracle_pcg.restype = C.c_int
@@ -229,6 +251,15 @@ class Hierarchy:
         lib().oracle_level_Pscalar(self.h, l, _p(cnt), _p(cols))
         return cnt, cols
 
+    def candidates(self, l):
+        """Interpolation candidates (C nodes within S-distance d_p) of each F node: (rp, ci)."""
+        n = self.info(l)["n"]
+        rp = np.zeros(n + 1, dtype=np.int64)
+        tot = lib().oracle_level_candidates(self.h, l, _p(rp), None)
+        ci = np.zeros(max(tot, 1), dtype=np.int32)
+        lib().oracle_level_candidates(self.h, l, _p(rp), _p(ci))
+        return rp, ci[:tot]
+
     def coarse_factor(self):
         nd = lib().oracle_coarse_order(self.h)
         L = np.zeros((nd, nd))
@@ -320,6 +351,8 @@ def dpls_row(params, v, Cm):
     chosen = np.zeros(16, dtype=np.int32)
     w = np.zeros(16)
     k = lib().oracle_dpls_row(C.byref(params), _p(v), _p(Cm), nca, ntv, _p(chosen), _p(w))
+    if k < 0:
+        raise RuntimeError(f"dpls_row failed ({k}): {lib().oracle_last_error().decode()}")
     return chosen[:k].copy(), w[:k].copy()
 
 

@@ -987,8 +987,10 @@ static int coarsen(ohier *h, olevel *L) {
 /* ties to the lowest candidate) is accepted unless max|R_kk| / min|R_kk|, a  */
 /* lower bound of cond(V_{c,i}), would exceed kappa_p.  Stops at n_max       */
 /* entries, or rho^2 <= eps_p^2 v.v, or when no candidate is eligible.        */
-/* Weights: normal equations of the chosen columns by Cholesky (the SPD     */
-/* solve that defines them; equal to R^{-1} (Q v) in exact arithmetic).      */
+/* Weights: the least-squares fit V_c w = v of eq. (minDPLS) through its     */
+/* normal equations (C^T C) w = C^T v, by Cholesky: equal in exact arithmetic */
+/* to the back substitution w = R^{-1} (Q^T v) of the algorithm, and          */
+/* well-conditioned because the kappa guard bounds cond(C^T C) by kappa_p^2.  */
 /* Reflection of column u at step k (sums ascending in t):                    */
 /*   delta = sqrt(sum_{t>=k} u_t^2), alpha = -delta if u_k >= 0 else delta,   */
 /*   h = u_tail with h_k = u_k - alpha, s = h_k^2 + sum_{t>k} u_t^2,           */
@@ -1087,7 +1089,10 @@ static int dpls_row(ohier *h, const double *v, const double *C, int nca, int ntv
     double acc = 0.0;
     for (int k = 0; k < j; k++) acc += Lc[j][k] * Lc[j][k];
     const double dd = Gm[j][j] - acc;
-    Lc[j][j] = dd > 0.0 ? sqrt(dd) : 1.0;
+    /* the kappa guard bounds cond(C^T C) by kappa_p^2, so a non-positive
+     * pivot means the chosen columns are dependent: an error, not a fit */
+    if (!(dd > 0.0)) { free(used); seterr("DPLS: weight Gram matrix not positive definite"); return O_ENOTSPD; }
+    Lc[j][j] = sqrt(dd);
     for (int a = j + 1; a < K; a++) {
       double a2 = 0.0;
       for (int k = 0; k < j; k++) a2 += Lc[a][k] * Lc[j][k];
@@ -1109,6 +1114,30 @@ static int dpls_row(ohier *h, const double *v, const double *C, int nca, int ntv
   for (int k = 0; k < K; k++) o->w[k] = w[k];
   free(used);
   return 0;
+}
+
+/* interpolation candidates of node I (R-P1): the C nodes joined to I by a
+ * path of at most d_p edges of the strong graph S, ascending.  Breadth-first
+ * search; mark and dist hold -1 for every node on entry and on exit (mark is
+ * set to I while the search runs). */
+static int candidate_nodes(const olevel *L, int32_t I, int d_p, int32_t *mark, int32_t *frontier, int32_t *dist,
+                           int32_t *cn) {
+  int nf = 0, ncn = 0;
+  frontier[nf++] = I; dist[I] = 0; mark[I] = I;
+  for (int head = 0; head < nf; head++) {
+    int32_t u = frontier[head];
+    if (dist[u] >= d_p) continue;
+    for (int64_t k = L->srp[u]; k < L->srp[u + 1]; k++) {
+      int32_t w = L->sci[k];
+      if (mark[w] == I) continue;
+      mark[w] = I; dist[w] = dist[u] + 1;
+      frontier[nf++] = w;
+      if (L->cf[w] == 1) cn[ncn++] = w;
+    }
+  }
+  for (int q = 0; q < nf; q++) { dist[frontier[q]] = -1; mark[frontier[q]] = -1; }
+  qsort(cn, ncn, sizeof(int32_t), cmp_i32);
+  return ncn;
 }
 
 static int build_P(ohier *h, olevel *L) {
@@ -1137,22 +1166,7 @@ static int build_P(ohier *h, olevel *L) {
   if (!wv || !Cm || !t || !gaa || !gbuf || !cnode || !ccomp) return O_ENOMEM;
   for (int32_t I = 0; I < n; I++) {
     if (L->cf[I] != 0) continue;
-    /* breadth-first search to depth d_p on S, collecting C nodes */
-    int nf = 0, ncn = 0;
-    frontier[nf++] = I; dist[I] = 0; mark[I] = I;
-    for (int head = 0; head < nf; head++) {
-      int32_t u = frontier[head];
-      if (dist[u] >= h->p.d_p) continue;
-      for (int64_t k = L->srp[u]; k < L->srp[u + 1]; k++) {
-        int32_t w = L->sci[k];
-        if (mark[w] == I) continue;
-        mark[w] = I; dist[w] = dist[u] + 1;
-        frontier[nf++] = w;
-        if (L->cf[w] == 1) cn[ncn++] = w;
-      }
-    }
-    for (int q = 0; q < nf; q++) dist[frontier[q]] = -1;
-    qsort(cn, ncn, sizeof(int32_t), cmp_i32);
+    int ncn = candidate_nodes(L, I, h->p.d_p, mark, frontier, dist, cn);
     if (ncn > cap) {
       cap = ncn;
       Cm = realloc(Cm, (size_t)cap * b * ntv * sizeof(double));
@@ -1168,7 +1182,8 @@ static int build_P(ohier *h, olevel *L) {
       }
     for (int d = 0; d < b; d++) {
       dpls_out o;
-      dpls_row(h, L->V + ((int64_t)I * b + d) * ntv, Cm, nca, ntv, &o, gbuf, t, gaa);
+      int rc = dpls_row(h, L->V + ((int64_t)I * b + d) * ntv, Cm, nca, ntv, &o, gbuf, t, gaa);
+      if (rc) return rc;
       int64_t r = (int64_t)I * b + d;
       L->pcount[r] = o.k;
       for (int k = 0; k < o.k; k++) {
@@ -1566,6 +1581,26 @@ void oracle_level_Pscalar(const ohier *h, int l, int32_t *cnt, int32_t *cols) {
   memcpy(cnt, L->pcount, (size_t)L->A.n * L->A.b * sizeof(int32_t));
   memcpy(cols, L->pcols, (size_t)L->A.n * L->A.b * h->p.n_max * sizeof(int32_t));
 }
+/* interpolation candidates (C nodes within S-distance d_p) of every F node of
+ * level l, CSR by node (C and decoupled nodes: empty); returns the total count
+ * and fills ci only when it is not NULL */
+int64_t oracle_level_candidates(const ohier *h, int l, int64_t *rp, int32_t *ci) {
+  const olevel *L = &h->lev[l];
+  int32_t n = L->A.n;
+  int32_t *mark = malloc((size_t)n * sizeof(int32_t)), *frontier = malloc((size_t)n * sizeof(int32_t));
+  int32_t *dist = malloc((size_t)n * sizeof(int32_t)), *cn = malloc((size_t)n * sizeof(int32_t));
+  for (int32_t i = 0; i < n; i++) { mark[i] = -1; dist[i] = -1; }
+  int64_t tot = 0;
+  rp[0] = 0;
+  for (int32_t I = 0; I < n; I++) {
+    int ncn = L->cf && L->cf[I] == 0 ? candidate_nodes(L, I, h->p.d_p, mark, frontier, dist, cn) : 0;
+    if (ci) memcpy(ci + tot, cn, (size_t)ncn * sizeof(int32_t));
+    tot += ncn;
+    rp[I + 1] = tot;
+  }
+  free(mark); free(frontier); free(dist); free(cn);
+  return tot;
+}
 void oracle_coarse_factor(const ohier *h, double *Ld) { memcpy(Ld, h->Ld, (size_t)h->nd * h->nd * sizeof(double)); }
 
 /* ---- unit exports used by the pins ---- */
@@ -1669,9 +1704,10 @@ int oracle_dpls_row(const oparams *p, const double *v, const double *C, int nca,
   double *t = NULL, *gaa = NULL;
   double *gbuf = malloc((size_t)(nca ? nca : 1) * ntv * sizeof(double));
   dpls_out o;
-  dpls_row(&hh, v, C, nca, ntv, &o, gbuf, t, gaa);
-  for (int k = 0; k < o.k; k++) { chosen[k] = o.col[k]; w[k] = o.w[k]; }
+  int rc = dpls_row(&hh, v, C, nca, ntv, &o, gbuf, t, gaa);
   free(t); free(gaa); free(gbuf);
+  if (rc) return rc;
+  for (int k = 0; k < o.k; k++) { chosen[k] = o.col[k]; w[k] = o.w[k]; }
   return o.k;
 }
 

@@ -136,7 +136,13 @@ __global__ void __launch_bounds__(256) k_dpls_weights(int32_t nrows, const int32
     double acc = 0.0;
     for (int k = 0; k < j; k++) acc += L[j][k] * L[j][k];
     const double d = Gm[j][j] - acc;
-    L[j][j] = d > 0.0 ? sqrt(d) : 1.0;
+    if (!(d > 0.0)) {
+      // dependent columns (the kappa guard bounds cond(C^T C) by kappa_p^2, so
+      // this is an error): NaN weights, which the host turns into a status
+      for (int a = 0; a < K; a++) w[(size_t)i * kMaxPEntries + a] = __builtin_nan("");
+      return;
+    }
+    L[j][j] = sqrt(d);
     for (int a = j + 1; a < K; a++) {
       double a2 = 0.0;
       for (int k = 0; k < j; k++) a2 += L[a][k] * L[j][k];

@@ -1001,6 +1001,9 @@ void build_prolongation(aspamg_ctx *h, Level &L, const StrongGraph &S) {
                         ntv, dw.as<double>(), h->stream);
     HIPCHK(hipGetLastError());
     to_host(h->stream, w.data(), dw.as<double>(), w.size());
+    for (size_t i = 0; i < rows.size(); i++)
+      for (int k = 0; k < cnt[i]; k++)
+        if (std::isnan(w[i * kMaxPEntries + k])) fail(ASPAMG_ENOT_SPD, "DPLS: weight Gram matrix not positive definite");
   }
   std::vector<double> wr((size_t)n * 3 * kMaxPEntries, 0.0);
   for (size_t i = 0; i < rows.size(); i++)
@@ -1178,10 +1181,12 @@ void build_coarse(aspamg_ctx *h, const HostBSR &A) {
     for (int64_t k = A.rp[i]; k < A.rp[i + 1]; k++)
       for (int d = 0; d < 3; d++)
         for (int e = 0; e < 3; e++) M[(size_t)(i * 3 + d) * nd + A.ci[k] * 3 + e] = A.v[(size_t)k * 9 + d * 3 + e];
-  // left-looking Cholesky, column by column, in one parallel region
+  // left-looking Cholesky, column by column, in one parallel region.  spd is
+  // written only inside the single and read only after its barrier, so every
+  // thread leaves the loop at the same column.
   bool spd = true;
 #pragma omp parallel
-  for (int32_t j = 0; j < nd && spd; j++) {
+  for (int32_t j = 0; j < nd; j++) {
 #pragma omp single
     {
       double acc = 0.0;
