@@ -585,6 +585,12 @@ static int orthonormalize(double *V, int64_t nrows, int ntv) {
 /* SRQCG"): simultaneous minimisation of the Rayleigh quotients of the columns */
 /* of Z for S = G A G^T by conjugate gradients, with a Ritz projection every   */
 /* k_ritz iterations, then V = G^T Z.  Readings where the algorithm is terse:  */
+/*   - the iterates live in the variable of S: A v = lambda (G^T G)^{-1} v      */
+/*     becomes S z = lambda z with v = G^T z, which is why the algorithm ends   */
+/*     with V = G^T Z.  V0 approximates the near kernel of A (v variable), so   */
+/*     it enters as G^{-T} V0: Z0 = (I - S) G^{-T} V0.  On an unconstrained K   */
+/*     with V0 the rigid-body modes, S G^{-T} V0 = G A V0 = 0 and the modes      */
+/*     come back unchanged;                                                    */
 /*   - q is the Rayleigh quotient z^T S z / z^T z; f_i starts at 1 and is set   */
 /*     to z_i^T z_i after each update of column i (not after a projection);     */
 /*   - S Z is formed by products at every projection and then carried:         */
@@ -598,6 +604,24 @@ static int orthonormalize(double *V, int64_t nrows, int ntv) {
 /*   - exactly k_max iterations run (no early exit).                           */
 /* Z and V are row-major [nrows][nt] like the test space.                      */
 /* ========================================================================= */
+
+/* x <- G^{-T} x: back substitution with the rows of the lower triangular G,  */
+/* scalar rows from the last to the first; x_r is divided by g_rr and then     */
+/* g_rk x_r is subtracted from every x_k, k < r, of row r                      */
+static void gt_solve(const obsr *G, double *x) {
+  const int b = G->b;
+  for (int64_t r = (int64_t)G->n * b - 1; r >= 0; r--) {
+    const int32_t I = (int32_t)(r / b);
+    const int d = (int)(r % b);
+    const double *dg = bsr_block(G, I, I);
+    x[r] /= dg[d * b + d];
+    for (int64_t k = G->rp[I]; k < G->rp[I + 1]; k++) {
+      const int32_t J = G->ci[k];
+      const int ne = J < I ? b : d;          /* the diagonal block: columns e < d */
+      for (int e = 0; e < ne; e++) x[(int64_t)J * b + e] -= G->v[k * b * b + d * b + e] * x[r];
+    }
+  }
+}
 
 /* S x = G (A (G^T x)) */
 static void apply_gagt(const obsr *A, const obsr *G, const obsr *GT, const double *x, double *y, double *t1,
@@ -727,9 +751,10 @@ static int srqcg(const obsr *A, const obsr *G, double *V, int nt, int kmax, int 
   double *sp = malloc((size_t)nr * sizeof(double)), *g = malloc((size_t)nr * sizeof(double));
   double f[64], U[64 * 64];
   if (rc || !Z || !SZ || !Pd || !x || !y || !t1 || !t2 || !sp || !g) { rc = O_ENOMEM; goto done; }
-  /* Z0 = (I - S) V0, orthonormalised */
+  /* Z0 = (I - S) G^{-T} V0, orthonormalised */
   for (int c = 0; c < nt; c++) {
     for (int64_t i = 0; i < nr; i++) x[i] = V[i * nt + c];
+    gt_solve(G, x);
     apply_gagt(A, G, &GT, x, y, t1, t2);
     for (int64_t i = 0; i < nr; i++) Z[i * nt + c] = x[i] - y[i];
   }

@@ -584,7 +584,40 @@ bool ritz_basis(const std::vector<double> &Ms, const std::vector<double> &Mz, in
   return true;
 }
 
-// L.V ([n][nt], in: the level's V0) <- G^T Z after kmax SRQCG iterations
+// V ([n*3][nt] row-major) <- G^{-T} V: back substitution with the rows of the
+// block lower triangular G, scalar rows from the last to the first.  x_r is
+// divided by g_rr, then g_rk x_r is subtracted from x_k for every k < r of row
+// r; each column sees exactly that sequence of operations.
+static void gt_solve(const HostBSR &G, std::vector<double> &V, int nt) {
+  const int64_t nr = (int64_t)G.n * 3;
+  std::vector<int64_t> diag(G.n);
+  for (int32_t I = 0; I < G.n; I++) {
+    int64_t kd = G.rp[I + 1] - 1;
+    while (kd >= G.rp[I] && G.ci[kd] != I) kd--;
+    if (kd < G.rp[I]) fail(ASPAMG_EINVAL, "srqcg: FSAI factor without a diagonal block");
+    diag[I] = kd;
+  }
+#pragma omp parallel for schedule(static, 1)
+  for (int c = 0; c < nt; c++) {
+    double *x = V.data() + c;
+    for (int64_t r = nr - 1; r >= 0; r--) {
+      const int32_t I = (int32_t)(r / 3);
+      const int d = (int)(r % 3);
+      const double xr = x[r * nt] / G.v[diag[I] * 9 + d * 3 + d];
+      x[r * nt] = xr;
+      for (int64_t k = G.rp[I]; k < G.rp[I + 1]; k++) {
+        const int32_t J = G.ci[k];
+        const int ne = J < I ? 3 : d;     // in the diagonal block only the columns e < d
+        for (int e = 0; e < ne; e++) x[((int64_t)J * 3 + e) * nt] -= G.v[k * 9 + d * 3 + e] * xr;
+      }
+    }
+  }
+}
+
+// L.V ([n][nt], in: the level's V0) <- G^T Z after kmax SRQCG iterations.  The
+// iterates live in the variable of S = G A G^T (A v = lambda (G^T G)^{-1} v is
+// S z = lambda z with v = G^T z, hence V = G^T Z at the end); V0 approximates
+// the near kernel of A, so it enters as G^{-T} V0: Z0 = (I - S) G^{-T} V0.
 void srqcg(aspamg_ctx *h, Level &L, int nt, int kmax) {
   const int64_t n = (int64_t)L.A.n * 3;
   const size_t cols = (size_t)n * nt;
@@ -628,7 +661,8 @@ void srqcg(aspamg_ctx *h, Level &L, int nt, int kmax) {
     for (int64_t i = 0; i < n; i++)
       for (int c = 0; c < nt; c++) rows[(size_t)i * nt + c] = cm[(size_t)c * n + i];
   };
-  // Z0 = (I - S) V0, orthonormalised
+  // Z0 = (I - S) G^{-T} V0, orthonormalised
+  gt_solve(L.G, L.V, nt);
   to_columns(L.V, W);
   for (int c = 0; c < nt; c++) {
     apply_s(C(W, c), C(SZ, c));

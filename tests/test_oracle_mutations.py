@@ -5,8 +5,8 @@ rule), compiles the copy and runs the pin that should catch it in a child
 pytest process that loads the copy (ORACLE_LIBRARY).  The case passes when that
 pin fails.  The mistakes are the ones a reader could plausibly make in the
 aFSAI growth rule, its eps_g stop and outer loop (Section 3.1, Algorithm "aFSAI
-Smoother Set-up"), the theta filter (Section 3.4) and the interpolation
-candidates (Section 3.5)."""
+Smoother Set-up"), the start of the SRQCG test-space iteration (Section 3.3),
+the theta filter (Section 3.4) and the interpolation candidates (Section 3.5)."""
 import os
 import subprocess
 import sys
@@ -64,6 +64,9 @@ MUTATIONS = [
     ("candidates_depth_one_long",
      [("if (dist[u] >= d_p) continue;", "if (dist[u] > d_p) continue;")],
      "test_interpolation_candidates_replay"),
+    ("srqcg_start_not_in_the_variable_of_S",
+     [("    gt_solve(G, x);\n    apply_gagt", "    apply_gagt")],
+     "test_oracle_srqcg.py::test_srqcg_keeps_the_rigid_body_modes_of_a_free_body"),
 ]
 
 
@@ -78,7 +81,8 @@ def test_pin_catches_planted_mistake(name, edits, pin, tmp_path, oracle_lib):
     path.write_text(src)
     lib = O.compile_source(str(path), str(tmp_path / "libmutant.so"))
     env = dict(os.environ, ORACLE_LIBRARY=lib)
+    fname, _, sel = pin.rpartition("::")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(HERE, "test_oracle_replays.py"), "-k", pin],
+                        os.path.join(HERE, fname or "test_oracle_replays.py"), "-k", sel],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"{name}: pin {pin} did not fail (rc {r.returncode})\n{r.stdout[-2000:]}"

@@ -67,7 +67,8 @@ def test_srqcg_step_is_the_line_minimum(seed, oracle_lib):
     S = Gd @ A @ Gd.T
     v0 = rng.standard_normal((n, 1))
     V, rq = O.srqcg(rp, ci, A.reshape(-1, 1, 1), G, v0, 1, 10 ** 6, b=1)
-    z0 = v0[:, 0] - S @ v0[:, 0]
+    x0 = np.linalg.solve(Gd.T, v0[:, 0])          # V0 enters in the variable of S
+    z0 = x0 - S @ x0
     z0 /= np.linalg.norm(z0)
     p0 = 2 * (S @ z0 - (z0 @ S @ z0) * z0)
     W = np.stack([z0, p0], axis=1)
@@ -80,7 +81,8 @@ def test_srqcg_step_is_the_line_minimum(seed, oracle_lib):
 
 
 def test_srqcg_zero_iterations_is_the_smoothed_start(oracle_lib):
-    """With k_max = 0 the result is G^T times the orthonormalised (I - S) V0."""
+    """With k_max = 0 the result is G^T times the orthonormalised (I - S) X0,
+    X0 = G^{-T} V0 the start vectors in the variable of S (dense solve)."""
     p = PR.c1_cube(7)
     H = O.Hierarchy(p.row_ptr, p.col, p.vals, p.V0)
     assert H.nlev == 2
@@ -88,7 +90,8 @@ def test_srqcg_zero_iterations_is_the_smoothed_start(oracle_lib):
     V0 = PR.initial_test_space(p, 8, 7).reshape(p.n_dof, 8)
     V, _ = O.srqcg(p.row_ptr, p.col, p.vals, G, V0, 0, 1)
     Gd, A = G.to_dense(), p.to_scipy().toarray()
-    Z0 = V0 - Gd @ A @ Gd.T @ V0
+    X0 = np.linalg.solve(Gd.T, V0)
+    Z0 = X0 - Gd @ A @ Gd.T @ X0
     Q = np.linalg.qr(Z0)[0]
     # the oracle orthonormalises by Cholesky-QR: the same columns up to signs
     # fixed by a positive triangular factor, i.e. Q with R's diagonal positive
@@ -138,3 +141,26 @@ def test_srqcg_converges_on_elasticity(oracle_lib):
     Qv = np.linalg.qr(V)[0]
     Qe = np.linalg.qr(Gd.T @ X[:, :4])[0]
     assert np.linalg.svd(Qv.T @ Qe, compute_uv=False).min() > 1 - 1e-8
+
+
+@pytest.mark.parametrize("kmax", [0, 6])
+def test_srqcg_keeps_the_rigid_body_modes_of_a_free_body(kmax, oracle_lib):
+    """On an unconstrained (singular) elasticity K the rigid-body modes span its
+    kernel.  Entering in the variable of S as G^{-T} V0, they lie in the kernel
+    of S = G A G^T (S G^{-T} V0 = G A V0 = 0), so neither the smoothing step nor
+    the Rayleigh-quotient iteration moves them: V = G^T Z spans the modes
+    again.  G is the FSAI factor on the lower block pattern of K."""
+    p = PR.unconstrained_box(4, 4, 3, jitter=0.2, seed=1)
+    n = p.n_nodes
+    brp, bci = [0], []
+    for i in range(n):
+        row = p.col[p.row_ptr[i]:p.row_ptr[i + 1]]
+        bci.extend(int(j) for j in row if j < i)
+        brp.append(len(bci))
+    G, _ = O.fsai_fixed(p.row_ptr, p.col, p.vals, np.array(brp), np.array(bci, dtype=np.int32))
+    R = p.V0.reshape(p.n_dof, 6)
+    V, rq = O.srqcg(p.row_ptr, p.col, p.vals, G, R, kmax, 1)
+    Q = np.linalg.qr(R)[0]
+    resid = V - Q @ (Q.T @ V)
+    assert np.linalg.norm(resid) <= 1e-9 * np.linalg.norm(V)
+    assert np.linalg.matrix_rank(V, tol=1e-8 * np.abs(V).max()) == 6
