@@ -53,7 +53,10 @@ typedef struct {
   int32_t k_g;            /* 4     adaptive FSAI steps per row                          */
   int32_t rho_g;          /* 4     paper: scalar entries per step (informational)      */
   double  eps_g;          /* 1e-3  FSAI exit tolerance on the relative decrease of psi */
-  int32_t n_tv;           /* 6     test vectors (the six rigid-body modes)              */
+  int32_t n_tv;           /* 0     test vectors: 0 takes the n_tv argument of aspamg_setup
+                           *       (the columns of V0); > 0 must equal it (EINVAL
+                           *       otherwise).  The paper's default is 10: the six
+                           *       rigid-body modes padded with random vectors.       */
   int32_t n_rq;           /* 0     SRQCG iterations on each level's test space before its
                            *       coarsening (Section 3.3, Algorithm "Test Space generation
                            *       by SRQCG", Ritz projection every iteration); 0 uses V0 as
@@ -101,6 +104,10 @@ typedef struct {
   int32_t cycle_precision;  /* 64 or 32                                               */
   double  relres_recursive; /* ||r_k|| / ||f|| from the recurrence                     */
   double  relres_true;      /* ||f - K u|| / ||f|| recomputed at the end               */
+  double  relres_floor;     /* gamma_{m+1} || |f| + |K| |u| || / ||f||: the rounding bound
+                             * of that recomputation in FP64 (m = longest scalar row of
+                             * K; Higham, "Accuracy and Stability of Numerical
+                             * Algorithms", Sec. 3.5).  relres_true below it is noise. */
   double  t_setup_s;        /* setup wall time                                        */
   double  t_solve_s;        /* solve time, HIP events on the handle's stream          */
   double  c_gd, c_op, c_fs; /* grid, operator and FSAI complexities                   */
@@ -163,10 +170,16 @@ aspamg_status aspamg_setup(const aspamg_params *p, int32_t n_nodes, int64_t nnzb
  * copies are built by aspamg_setup. */
 aspamg_status aspamg_set_cycle_precision(aspamg_handle h, int32_t bits);
 
-/* PCG from u = 0 until ||r|| <= rtol ||f|| (Section 4).
+/* PCG from u = 0 until ||r|| <= rtol ||f|| (Section 4: the recursive residual
+ * of the iteration).
  *   f_dev, u_dev  float64 device vectors of 3*n_nodes entries (caller-owned).
  *   st            optional stats (may be NULL).
- * Returns OK, NOT_CONVERGED (u = last iterate), EBREAKDOWN, ENAN or EHIP. */
+ * After the iteration the residual f - K u is recomputed.  OK requires both
+ * the recursive test and relres_true <= max(rtol, relres_floor): the
+ * recomputed residual is at most rtol, or within the rounding bound of its own
+ * evaluation.  Otherwise NOT_CONVERGED (u = last iterate).  Also EBREAKDOWN,
+ * ENAN or EHIP.  The stats carry no separate V-cycle time: the iteration runs
+ * as one captured graph; aspamg_time_kernel (which = 3, 4) times the cycle. */
 aspamg_status aspamg_solve(aspamg_handle h, const double *f_dev, double *u_dev,
                            aspamg_stats *st);
 

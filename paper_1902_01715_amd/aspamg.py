@@ -44,7 +44,8 @@ class Params(C.Structure):
 class Stats(C.Structure):
     _fields_ = [
         ("status", C.c_int32), ("iterations", C.c_int32), ("levels", C.c_int32), ("cycle_precision", C.c_int32),
-        ("relres_recursive", C.c_double), ("relres_true", C.c_double), ("t_setup_s", C.c_double),
+        ("relres_recursive", C.c_double), ("relres_true", C.c_double), ("relres_floor", C.c_double),
+        ("t_setup_s", C.c_double),
         ("t_solve_s", C.c_double), ("c_gd", C.c_double), ("c_op", C.c_double), ("c_fs", C.c_double),
         ("bytes_vcycle", C.c_double), ("bytes_iter", C.c_double), ("spmm_tile", C.c_int32),
         ("tail_level", C.c_int32),

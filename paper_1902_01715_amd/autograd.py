@@ -4,9 +4,16 @@ Forward assembles K(E) on the GPU (element-to-block kernel), builds the aSP-AMG
 hierarchy and solves with PCG.  K is symmetric, so the backward pass is one
 more solve with the same hierarchy, lam = K^{-1} g_u (the adjoint), followed by
 the element-gradient kernel dL/dE_e = -lam_e^T K_e^0 u_e; dL/df = lam.
-All numerical work runs in libaspamg.so; this module only wires tensors.
+Constrained DOFs are decoupled identity rows of K (u_c = f_c, no coupling to
+the free DOFs), so dL/df_c = dL/du_c there and the element gradient sees u with
+its constrained entries zeroed (K(E) holds no free-constrained couplings).
+A solve that does not reach its tolerance raises (strict models, the default)
+or warns.  All numerical work runs in libaspamg.so; this module only wires
+tensors.
 """
 from __future__ import annotations
+
+import warnings
 
 import numpy as np
 import torch
@@ -19,7 +26,8 @@ class ElasticModel:
     element matrix K_e^0 (shared, 24x24, or per element), the block pattern of
     K with its constrained nodes, and the near-null space for the setup."""
 
-    def __init__(self, n_nodes, conn, Ke0, row_ptr, col, constrained, V0, params=None, device="cuda"):
+    def __init__(self, n_nodes, conn, Ke0, row_ptr, col, constrained, V0, params=None, device="cuda", strict=True):
+        self.strict = bool(strict)
         self.n_nodes = int(n_nodes)
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
         self.col = np.ascontiguousarray(col, dtype=np.int32)
@@ -42,12 +50,24 @@ class ElasticModel:
         torch.cuda.current_stream().synchronize()
         return aspamg.Solver(self.row_ptr, self.col, vals, self.V0, self.params)
 
+    def checked_solve(self, S, rhs, what):
+        x = S.solve(rhs)
+        st = S.last_stats
+        if st["status"] != aspamg.OK:
+            msg = (f"{what} solve did not converge: status {st['status']}, {st['iterations']} iterations, "
+                   f"relres {st['relres_recursive']:.2e} (recomputed {st['relres_true']:.2e})")
+            if self.strict:
+                S.close()
+                raise RuntimeError(msg)
+            warnings.warn(msg, RuntimeWarning, stacklevel=3)
+        return x
+
 
 class ElasticSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, E, f, model: ElasticModel):
         S = model.solver(E)
-        u = S.solve(f.detach().contiguous())
+        u = model.checked_solve(S, f.detach().contiguous(), "forward")
         ctx.solver = S
         ctx.model = model
         ctx.save_for_backward(u)
@@ -60,9 +80,16 @@ class ElasticSolve(torch.autograd.Function):
         S, model = ctx.solver, ctx.model
         g = g_u.contiguous().clone()
         g[model.constrained] = 0.0
-        lam = S.solve(g)
-        grad_E = aspamg.element_gradient(model.conn, model.Ke0, lam, u) if ctx.needs_input_grad[0] else None
-        grad_f = lam if ctx.needs_input_grad[1] else None
+        lam = model.checked_solve(S, g, "adjoint")
+        grad_E = None
+        if ctx.needs_input_grad[0]:
+            uf = u.clone()
+            uf[model.constrained] = 0.0
+            grad_E = aspamg.element_gradient(model.conn, model.Ke0, lam, uf)
+        grad_f = None
+        if ctx.needs_input_grad[1]:
+            grad_f = lam.clone()
+            grad_f[model.constrained] = g_u[model.constrained]
         S.close()
         return grad_E, grad_f, None
 

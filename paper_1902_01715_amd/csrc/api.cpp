@@ -14,7 +14,7 @@
 
 // sizes mirrored by the Python binding
 static_assert(sizeof(aspamg_params) == 160, "aspamg_params layout changed");
-static_assert(sizeof(aspamg_stats) == 96, "aspamg_stats layout changed");
+static_assert(sizeof(aspamg_stats) == 104, "aspamg_stats layout changed");
 static_assert(sizeof(aspamg_level_info_t) == 144, "aspamg_level_info_t layout changed");
 
 namespace aspamg {
@@ -813,6 +813,18 @@ static void check_params(const aspamg_params &p) {
     fail(ASPAMG_EINVAL, "invalid parameter value");
 }
 
+// gamma_{m+1} = (m+1) u / (1 - (m+1) u) for the longest scalar row of K (m
+// stored entries): |fl(f - K u) - (f - K u)| <= gamma_{m+1} (|f| + |K| |u|)
+// componentwise (Higham, "Accuracy and Stability of Numerical Algorithms",
+// Sec. 3.5), whatever the order of the row's sums
+double residual_gamma(const aspamg_ctx *h) {
+  const HostBSR &A = h->lev[0].A;
+  int64_t m = 0;
+  for (int32_t i = 0; i < A.n; i++) m = std::max(m, A.rp[i + 1] - A.rp[i]);
+  const double k = (double)(3 * m + 1), u = std::ldexp(1.0, -53);
+  return k * u / (1.0 - k * u);
+}
+
 }  // namespace aspamg
 
 using namespace aspamg;
@@ -843,7 +855,7 @@ aspamg_status aspamg_default_params(aspamg_params *o) {
   o->k_g = 4;
   o->rho_g = 4;
   o->eps_g = 1e-3;
-  o->n_tv = 6;
+  o->n_tv = 0;
   o->n_rq = 0;
   o->theta = 5;
   o->n_max = 5;
@@ -901,6 +913,9 @@ static aspamg_status setup_impl(const aspamg_params *pp, int32_t n_nodes, int64_
   aspamg_params p;
   if (pp) p = *pp;
   else aspamg_default_params(&p);
+  if (p.n_tv != 0 && p.n_tv != n_tv)
+    fail(ASPAMG_EINVAL, "params.n_tv (" + std::to_string(p.n_tv) + ") differs from the columns of V0 (" +
+                            std::to_string(n_tv) + ")");
   p.n_tv = n_tv;
   check_params(p);
   const auto t0 = std::chrono::steady_clock::now();
@@ -967,7 +982,8 @@ aspamg_status aspamg_set_cycle_precision(aspamg_handle h, int32_t bits) {
   return ASPAMG_OK;
 }
 
-static void fill_stats(aspamg_handle h, aspamg_stats *st, const PcgCtrl &c, double t_solve, double relres_true) {
+static void fill_stats(aspamg_handle h, aspamg_stats *st, const PcgCtrl &c, double t_solve, double relres_true,
+                       double relres_floor) {
   if (!st) return;
   st->status = c.status;
   st->iterations = c.iter;
@@ -975,6 +991,7 @@ static void fill_stats(aspamg_handle h, aspamg_stats *st, const PcgCtrl &c, doub
   st->cycle_precision = h->prec;
   st->relres_recursive = c.relres;
   st->relres_true = relres_true;
+  st->relres_floor = relres_floor;
   st->t_setup_s = h->t_setup;
   st->t_solve_s = t_solve;
   st->c_gd = h->c_gd;
@@ -1018,7 +1035,14 @@ aspamg_status aspamg_solve(aspamg_handle h, const double *f_dev, double *u_dev, 
   if (h->p.use_graph && !gx) {
     hipGraph_t g;
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    pcg_iteration(h, fp32);
+    try {
+      pcg_iteration(h, fp32);
+    } catch (...) {   // leave the stream out of capture mode before reporting
+      hipGraph_t dead = nullptr;
+      (void)hipStreamEndCapture(s, &dead);
+      if (dead) (void)hipGraphDestroy(dead);
+      throw;
+    }
     HIPCHK(hipStreamEndCapture(s, &g));
     HIPCHK(hipGraphInstantiate(&gx, g, nullptr, nullptr, 0));
     HIPCHK(hipGraphDestroy(g));
@@ -1040,18 +1064,27 @@ aspamg_status aspamg_solve(aspamg_handle h, const double *f_dev, double *u_dev, 
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   PcgCtrl c = *h->ctrl_host;
-  // true residual |f - K u| / |f|
+  // true residual |f - K u| / |f|, and the rounding bound of evaluating it
   launch_spmv<double, double, double>(h->lev[0].A64, h->vu, h->vq, f_dev, -1.0, nullptr, s);
   launch_dot(n, h->vq, h->vq, h->part, nullptr, s);
-  std::vector<double> part(vec_blocks(n));
+  const int nbnd = spmv_dot_blocks(h->lev[0].A64);
+  launch_abs_bound(h->lev[0].A64, h->vu, f_dev, h->part + kMaxPart, s);
+  std::vector<double> part(vec_blocks(n)), bpart(nbnd);
   HIPCHK(hipMemcpyAsync(part.data(), h->part, part.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(bpart.data(), h->part + kMaxPart, bpart.size() * 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  double rr = 0.0;
+  double rr = 0.0, bb = 0.0;
   for (double x : part) rr += x;
+  for (double x : bpart) bb += x;
   const double relres_true = c.fnorm > 0 ? std::sqrt(rr) / c.fnorm : 0.0;
+  const double bound = c.fnorm > 0 ? residual_gamma(h) * std::sqrt(bb) / c.fnorm : 0.0;
+  // converged (Section 4: the recursive residual) only when the recomputed
+  // residual agrees: at most rtol, or within the rounding bound of its own
+  // evaluation in FP64
+  if (c.status == ASPAMG_OK && !(relres_true <= std::max(c.rtol, bound))) c.status = ASPAMG_NOT_CONVERGED;
   HIPCHK(hipEventDestroy(e0));
   HIPCHK(hipEventDestroy(e1));
-  fill_stats(h, st, c, ms * 1e-3, relres_true);
+  fill_stats(h, st, c, ms * 1e-3, relres_true, bound);
   return (aspamg_status)c.status;
   ABI_END
 }

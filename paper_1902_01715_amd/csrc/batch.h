@@ -70,6 +70,9 @@ void launch_col_rz(int64_t nrow, const double *R, const TZ *Z, int ld, double *p
 template <typename TZ>
 void launch_col_pupdate(int64_t nrow, const TZ *Z, double *P, int ld, const BatchCtrl *c, hipStream_t s);
 void launch_col_finish(int mode, const double *part, int nparts, int ld, BatchCtrl *c, hipStream_t s);
+// S = |F| + |A| |U| on the first k columns (rounding bound of F - A U)
+void launch_abs_bound_cols(const DevBSRT<double> &A, const double *U, const double *F, int ld, int k, double *S,
+                           hipStream_t s);
 void launch_copy_cols(int64_t nrow, int k, const double *src, int64_t lds, double *dst, int64_t ldd, int kfill,
                       hipStream_t s);
 

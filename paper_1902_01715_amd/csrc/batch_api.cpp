@@ -288,16 +288,26 @@ static aspamg_status solve_chunk(aspamg_ctx *h, int k, const double *F, int64_t 
   launch_spmm<double>(w->lev[0].d.A, w->U, w->Q, w->F, ld, w->kb[0], -1.0, nullptr, s);
   launch_col_dot(nrow, w->Q, w->Q, ld, w->part, nullptr, s);
   const int nb = batch_vec_blocks(nrow, ld);
-  std::vector<double> part((size_t)nb * ld);
+  std::vector<double> part((size_t)nb * ld), bpart((size_t)nb * ld);
   HIPCHK(hipMemcpyAsync(part.data(), w->part, part.size() * 8, hipMemcpyDeviceToHost, s));
+  // and the rounding bound of evaluating it, column by column
+  launch_abs_bound_cols(w->lev[0].d.A, w->U, w->F, ld, k, w->Q, s);
+  launch_col_dot(nrow, w->Q, w->Q, ld, w->part, nullptr, s);
+  HIPCHK(hipMemcpyAsync(bpart.data(), w->part, bpart.size() * 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  const double gam = residual_gamma(h);
   HIPCHK(hipEventDestroy(e0));
   HIPCHK(hipEventDestroy(e1));
   aspamg_status worst = ASPAMG_OK;
   for (int j = 0; j < k; j++) {
-    double rr = 0.0;
+    double rr = 0.0, bb = 0.0;
     for (int b = 0; b < nb; b++) rr += part[(size_t)b * ld + j];
-    const aspamg_status sj = (aspamg_status)c.status[j];
+    for (int b = 0; b < nb; b++) bb += bpart[(size_t)b * ld + j];
+    const double rel = c.fnorm[j] > 0 ? std::sqrt(rr) / c.fnorm[j] : 0.0;
+    const double bound = c.fnorm[j] > 0 ? gam * std::sqrt(bb) / c.fnorm[j] : 0.0;
+    aspamg_status sj = (aspamg_status)c.status[j];
+    // converged only when the recomputed residual agrees (as for one column)
+    if (sj == ASPAMG_OK && !(rel <= std::max(c.rtol, bound))) sj = ASPAMG_NOT_CONVERGED;
     if (sj < 0 && (worst >= 0 || sj < worst)) worst = sj;
     else if (worst == ASPAMG_OK && sj > 0) worst = sj;
     if (st) {
@@ -308,7 +318,8 @@ static aspamg_status solve_chunk(aspamg_ctx *h, int k, const double *F, int64_t 
       o.levels = (int32_t)h->lev.size();
       o.cycle_precision = h->prec;
       o.relres_recursive = c.relres[j];
-      o.relres_true = c.fnorm[j] > 0 ? std::sqrt(rr) / c.fnorm[j] : 0.0;
+      o.relres_true = rel;
+      o.relres_floor = bound;
       o.t_setup_s = h->t_setup;
       o.t_solve_s = ms * 1e-3;
       o.c_gd = h->c_gd;

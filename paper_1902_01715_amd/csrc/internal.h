@@ -233,9 +233,11 @@ void launch_spmv(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha
 template <typename T, typename TX, typename TO>
 void launch_spmv_dual(const Sell<T> &S, int32_t n1, const TX *x, TO *y1, const TO *w1, double a1, TO *y2,
                       const TO *w2, double a2, const PcgCtrl *ctrl, hipStream_t s);
-int spmv_dot_blocks(const Sell<double> &A);   // partials written by launch_spmv_dot
+int spmv_dot_blocks(const Sell<double> &A);   // partials written by launch_spmv_dot (<= kMaxPart)
 void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
                      hipStream_t s);
+// partials (spmv_dot_blocks of them) of sum_i s_i^2, s_i = |f_i| + (|K| |u|)_i
+void launch_abs_bound(const Sell<double> &A, const double *u, const double *f, double *part, hipStream_t s);
 template <typename TV>
 void launch_dense_gemv(int nd, const double *inv, const TV *y, TV *z, const PcgCtrl *ctrl, hipStream_t s);
 template <typename TI, typename TO>
@@ -305,6 +307,10 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0);
 // M = G^T G on the small smoothed levels above the dense tail
 void merge_smoothers(aspamg_ctx *h);
 double quantize(double s, int bits);
+
+// gamma_{m+1} of the longest scalar row of the fine-level K: the relative
+// rounding bound of recomputing a residual f - K u in FP64
+double residual_gamma(const aspamg_ctx *h);
 
 // ---- multi-RHS solve (batch_api.cpp) ----
 aspamg_status solve_batch_impl(aspamg_ctx *h, int32_t k, const double *F, int64_t ldf, double *U, int64_t ldu,

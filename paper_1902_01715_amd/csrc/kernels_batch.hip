@@ -337,6 +337,31 @@ __global__ void __launch_bounds__(256) k_copy_cols(int64_t nrow, int32_t k, cons
   }
 }
 
+// S[i][j] = |F[i][j]| + sum_k |A_ik| |U[k][j]| for the k columns (the
+// componentwise bound of evaluating F - A U; rounding floor of the true
+// residual).  One thread per (scalar row, column); the row's blocks are read
+// by the k threads of the row from cache.
+__global__ void __launch_bounds__(256) k_abs_bound_cols(int32_t n, const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci,
+                                                        const double *__restrict__ v,
+                                                        const double *__restrict__ U, const double *__restrict__ F,
+                                                        int32_t ld, int32_t k, double *__restrict__ S) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = t / k;
+  const int32_t j = (int32_t)(t % k);
+  if (i >= (int64_t)n * 3) return;
+  const int32_t I = (int32_t)(i / 3);
+  const int d = (int)(i % 3);
+  double a = 0.0;
+  for (int32_t b = rp[I]; b < rp[I + 1]; b++) {
+    const int32_t c = ci[b];
+    const double *blk = v + (size_t)b * 9 + d * 3;
+    a += fabs(blk[0]) * fabs(U[(size_t)(3 * c) * ld + j]) + fabs(blk[1]) * fabs(U[(size_t)(3 * c + 1) * ld + j]) +
+         fabs(blk[2]) * fabs(U[(size_t)(3 * c + 2) * ld + j]);
+  }
+  S[(size_t)i * ld + j] = fabs(F[(size_t)i * ld + j]) + a;
+}
+
 }  // namespace
 
 int batch_vec_blocks(int64_t nrow, int ld) {
@@ -466,6 +491,13 @@ void launch_copy_cols(int64_t nrow, int k, const double *src, int64_t lds, doubl
   if (b > 4096) b = 4096;
   if (b < 1) b = 1;
   hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)b), dim3(256), 0, s, nrow, k, src, lds, dst, ldd, kfill);
+}
+
+void launch_abs_bound_cols(const DevBSRT<double> &A, const double *U, const double *F, int ld, int k, double *S,
+                           hipStream_t s) {
+  const int64_t nt = (int64_t)A.n * 3 * k;
+  hipLaunchKernelGGL(k_abs_bound_cols, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, A.n, A.rp, A.ci, A.v, U, F,
+                     ld, k, S);
 }
 
 }  // namespace aspamg

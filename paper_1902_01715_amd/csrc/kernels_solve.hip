@@ -217,33 +217,91 @@ __device__ __forceinline__ double block_sum_n(double v, double *sm) {
 }
 
 // q = K p on the sliced layout with L lanes per row, and the p.q partial of
-// every kDotThreads-thread block.
+// every kDotThreads-thread block.  Block b serves the `per` consecutive groups
+// of kDotThreads lanes b*per .. b*per+per-1 (per = 1 up to kMaxPart blocks; a
+// larger operator keeps kMaxPart partials and gives each block more rows).
 template <typename CI, int L>
 __global__ void __launch_bounds__(kDotThreads) k_sell_spmv_dot(int32_t n, const int32_t *__restrict__ sptr,
                                                         const CI *__restrict__ col,
                                                         const int32_t *__restrict__ cbase,
                                                         const double *__restrict__ val,
                                                         const double *__restrict__ x, double *__restrict__ y,
-                                                        double *__restrict__ part, const PcgCtrl *ctrl) {
+                                                        double *__restrict__ part, const PcgCtrl *ctrl,
+                                                        int32_t per) {
   __shared__ double sm[kDotThreads / 64];
   if (ctrl_done(ctrl)) return;
-  const int32_t t = xcd_block() * kDotThreads + threadIdx.x;
-  const int32_t sl = t >> 6, e = t & 63;
-  const int32_t row = sl * (64 / L) + e / L;
   double d = 0.0;
-  if (row < n) {                        // whole lane groups together
+  for (int32_t it = 0; it < per; ++it) {
+    const int32_t t = (xcd_block() * per + it) * kDotThreads + threadIdx.x;
+    const int32_t sl = t >> 6, e = t & 63;
+    const int32_t row = sl * (64 / L) + e / L;
+    if (row < n) {                        // whole lane groups together
+      const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
+      const int32_t cb = sizeof(CI) == 2 ? cbase[sl] : 0;
+      double a0 = 0, a1 = 0, a2 = 0;
+      const CI *cp = col + (size_t)g0 * 64 + e;
+      const double *vp = val + (size_t)g0 * 576;
+#pragma unroll 2
+      for (int32_t g = g0; g < g1; ++g) {
+        const int32_t c = (int32_t)ld_stream(cp) + cb;
+        const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
+        blk_fma(vp, e, x0, x1, x2, a0, a1, a2);
+        cp += 64;
+        vp += 576;
+      }
+      if (L > 1) {
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1) {
+          a0 += __shfl_xor(a0, o, L);
+          a1 += __shfl_xor(a1, o, L);
+          a2 += __shfl_xor(a2, o, L);
+        }
+      }
+      if ((e & (L - 1)) == 0) {
+        double *yo = y + 3 * (size_t)row;
+        yo[0] = a0;
+        yo[1] = a1;
+        yo[2] = a2;
+        const double *xo = x + 3 * (size_t)row;
+        d += (xo[0] * a0 + xo[1] * a1) + xo[2] * a2;
+      }
+    }
+  }
+  const double s = block_sum_n<kDotThreads>(d, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Rounding floor of the recomputed residual: per scalar row
+// s_i = |f_i| + sum_j |K_ij| |u_j| (the componentwise bound of evaluating
+// f - K u, Higham, "Accuracy and Stability of Numerical Algorithms", Sec. 3.5),
+// and the block partials of sum s_i^2.  Same layout and row mapping as
+// k_sell_spmv_dot.
+template <typename CI, int L>
+__global__ void __launch_bounds__(kDotThreads) k_sell_abs_bound(int32_t n, const int32_t *__restrict__ sptr,
+                                                         const CI *__restrict__ col,
+                                                         const int32_t *__restrict__ cbase,
+                                                         const double *__restrict__ val,
+                                                         const double *__restrict__ u, const double *__restrict__ f,
+                                                         double *__restrict__ part, int32_t per) {
+  __shared__ double sm[kDotThreads / 64];
+  double d = 0.0;
+  for (int32_t it = 0; it < per; ++it) {
+    const int32_t t = (xcd_block() * per + it) * kDotThreads + threadIdx.x;
+    const int32_t sl = t >> 6, e = t & 63;
+    const int32_t row = sl * (64 / L) + e / L;
+    if (row >= n) continue;
     const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
     const int32_t cb = sizeof(CI) == 2 ? cbase[sl] : 0;
     double a0 = 0, a1 = 0, a2 = 0;
-    const CI *cp = col + (size_t)g0 * 64 + e;
-    const double *vp = val + (size_t)g0 * 576;
-#pragma unroll 2
     for (int32_t g = g0; g < g1; ++g) {
-      const int32_t c = (int32_t)ld_stream(cp) + cb;
-      const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
-      blk_fma(vp, e, x0, x1, x2, a0, a1, a2);
-      cp += 64;
-      vp += 576;
+      const int32_t c = (int32_t)col[(size_t)g * 64 + e] + cb;
+      const double x0 = fabs(u[3 * c]), x1 = fabs(u[3 * c + 1]), x2 = fabs(u[3 * c + 2]);
+      const wide_f64 *p = reinterpret_cast<const wide_f64 *>(val + (size_t)g * 576) + e;
+      const wide_f64 c0 = p[0], c1 = p[64], c2 = p[128], c3 = p[192];
+      const double v8 = val[(size_t)g * 576 + 512 + e];
+      a0 += fabs(c0.x) * x0 + fabs(c0.y) * x1 + fabs(c1.x) * x2;
+      a1 += fabs(c1.y) * x0 + fabs(c2.x) * x1 + fabs(c2.y) * x2;
+      a2 += fabs(c3.x) * x0 + fabs(c3.y) * x1 + fabs(v8) * x2;
     }
     if (L > 1) {
 #pragma unroll
@@ -254,12 +312,9 @@ __global__ void __launch_bounds__(kDotThreads) k_sell_spmv_dot(int32_t n, const 
       }
     }
     if ((e & (L - 1)) == 0) {
-      double *yo = y + 3 * (size_t)row;
-      yo[0] = a0;
-      yo[1] = a1;
-      yo[2] = a2;
-      const double *xo = x + 3 * (size_t)row;
-      d = (xo[0] * a0 + xo[1] * a1) + xo[2] * a2;
+      const double *fo = f + 3 * (size_t)row;
+      const double s0 = fabs(fo[0]) + a0, s1 = fabs(fo[1]) + a1, s2 = fabs(fo[2]) + a2;
+      d += (s0 * s0 + s1 * s1) + s2 * s2;
     }
   }
   const double s = block_sum_n<kDotThreads>(d, sm);
@@ -585,31 +640,62 @@ template void launch_spmv<double, double, double>(const Sell<double> &, const do
 template void launch_spmv<float, float, float>(const Sell<float> &, const float *, float *, const float *, double,
                                                const PcgCtrl *, hipStream_t);
 
+// groups of kDotThreads lanes of the sliced operator, and the groups each
+// block of the fused product serves so that at most kMaxPart blocks run
+static int64_t dot_groups(const Sell<double> &A) {
+  return ((int64_t)A.nslices * 64 + kDotThreads - 1) / kDotThreads;
+}
+static int32_t dot_per_block(const Sell<double> &A) {
+  return (int32_t)((dot_groups(A) + kMaxPart - 1) / kMaxPart);
+}
 int spmv_dot_blocks(const Sell<double> &A) {
-  return (int)(((int64_t)A.nslices * 64 + kDotThreads - 1) / kDotThreads);
+  const int64_t per = dot_per_block(A);
+  return (int)((dot_groups(A) + per - 1) / per);
 }
 
 template <int L>
 static void launch_dot_l(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
                          hipStream_t s) {
   const dim3 grid((unsigned)spmv_dot_blocks(A));
+  const int32_t per = dot_per_block(A);
   if (A.col16)
     hipLaunchKernelGGL((k_sell_spmv_dot<uint16_t, L>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col16, A.cbase, A.val, x,
-                       y, part, ctrl);
+                       y, part, ctrl, per);
   else
     hipLaunchKernelGGL((k_sell_spmv_dot<int32_t, L>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col, nullptr, A.val, x, y,
-                       part, ctrl);
+                       part, ctrl, per);
 }
 
 void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
                      hipStream_t s) {
   if (A.pack) fail(ASPAMG_EINVAL, "q = K p needs the sliced layout");
-  if (spmv_dot_blocks(A) > kMaxPart) fail(ASPAMG_EINVAL, "q = K p: more partials than the reduction buffer holds");
   switch (A.lanes) {
     case 1: launch_dot_l<1>(A, x, y, part, ctrl, s); break;
     case 2: launch_dot_l<2>(A, x, y, part, ctrl, s); break;
     case 4: launch_dot_l<4>(A, x, y, part, ctrl, s); break;
     default: fail(ASPAMG_EINVAL, "q = K p supports 1, 2 or 4 lanes per row");
+  }
+}
+
+template <int L>
+static void launch_abs_l(const Sell<double> &A, const double *u, const double *f, double *part, hipStream_t s) {
+  const dim3 grid((unsigned)spmv_dot_blocks(A));
+  const int32_t per = dot_per_block(A);
+  if (A.col16)
+    hipLaunchKernelGGL((k_sell_abs_bound<uint16_t, L>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col16, A.cbase,
+                       A.val, u, f, part, per);
+  else
+    hipLaunchKernelGGL((k_sell_abs_bound<int32_t, L>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col, nullptr,
+                       A.val, u, f, part, per);
+}
+
+void launch_abs_bound(const Sell<double> &A, const double *u, const double *f, double *part, hipStream_t s) {
+  if (A.pack) fail(ASPAMG_EINVAL, "residual bound needs the sliced layout of K");
+  switch (A.lanes) {
+    case 1: launch_abs_l<1>(A, u, f, part, s); break;
+    case 2: launch_abs_l<2>(A, u, f, part, s); break;
+    case 4: launch_abs_l<4>(A, u, f, part, s); break;
+    default: fail(ASPAMG_EINVAL, "residual bound supports 1, 2 or 4 lanes per row");
   }
 }
 

@@ -28,9 +28,10 @@ def test_default_params_and_struct_layout():
     assert (p.k_g, p.theta, p.n_max, p.kappa_p, p.eps_g) == (4, 5, 5, 50.0, 1e-3)
     assert p.rtol == 1e-10 and p.max_it == 1000 and p.cycle_precision == 64
     assert p.layout == 0 and p.use_graph == 1
+    assert p.n_tv == 0       # the test space is sized by the columns of V0
     # the ctypes mirrors have the C struct sizes (asserted at compile time in the library)
     assert ctypes.sizeof(aspamg.Params) == 160
-    assert ctypes.sizeof(aspamg.Stats) == 96
+    assert ctypes.sizeof(aspamg.Stats) == 104
     assert ctypes.sizeof(aspamg.LevelInfo) == 144
 
 
@@ -70,3 +71,20 @@ def test_setup_rejects_invalid_parameters_before_touching_a_device():
                             V0.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(h))
         assert rc == aspamg.EINVAL and not h.value, kw
         assert b"invalid parameter" in L.aspamg_last_error(), kw
+
+
+def test_setup_rejects_a_test_space_size_other_than_v0s():
+    """params.n_tv, when set, must equal the column count passed with V0."""
+    import numpy as np
+    L = aspamg.lib()
+    rp = np.array([0, 1], dtype=np.int32)
+    ci = np.array([0], dtype=np.int32)
+    v = np.eye(3).reshape(1, 3, 3).copy()
+    V0 = np.zeros((1, 3, 6))
+    p = aspamg.default_params(n_tv=10)
+    h = ctypes.c_void_p()
+    rc = L.aspamg_setup(ctypes.byref(p), 1, 1, rp.ctypes.data_as(ctypes.c_void_p), ci.ctypes.data_as(ctypes.c_void_p),
+                        v.ctypes.data_as(ctypes.c_void_p), 6, V0.ctypes.data_as(ctypes.c_void_p), None,
+                        ctypes.byref(h))
+    assert rc == aspamg.EINVAL and not h.value
+    assert b"n_tv" in L.aspamg_last_error()

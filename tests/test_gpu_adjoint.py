@@ -80,3 +80,48 @@ def test_compliance_gradient(simp, oracle_lib):
             S.close()
         fd = (cs[0] - cs[1]) / (2 * h)
         assert abs(fd - g[e]) <= 1e-3 * abs(g[e]) + 1e-9 * Cv / g.size, (e, fd, g[e])
+
+
+def test_load_gradient_and_clamped_loads(cuda):
+    """L = w . u with loads also on clamped nodes (there u_c = f_c: decoupled
+    identity rows).  dL/df against exact central differences (L is linear in
+    f), dL/dE against central differences on sampled elements, both through
+    the autograd function; the clamped loads must not leak into dL/dE."""
+    import torch
+    from paper_1902_01715_amd import aspamg
+    from paper_1902_01715_amd.autograd import ElasticModel, elastic_solve
+    print("[case clamped loads simp 6^3]", flush=True)
+    p = PR.c5_simp(6, seed=7, n_fd=6)
+    model = ElasticModel.from_problem(p, aspamg.default_params(rtol=1e-12))
+    rng = np.random.default_rng(1)
+    f0 = p.f.copy()
+    cdof = np.repeat(p.dirichlet, 3)
+    f0[cdof] = rng.standard_normal(cdof.sum())
+    w = torch.tensor(rng.standard_normal(p.n_dof), device="cuda")
+    E0 = p.extra["rho"] ** 3
+
+    def loss(E, f):
+        u = elastic_solve(torch.tensor(E, device="cuda"), torch.tensor(f, device="cuda"), model)
+        return torch.dot(w, u).item()
+
+    E = torch.tensor(E0, device="cuda", requires_grad=True)
+    f = torch.tensor(f0, device="cuda", requires_grad=True)
+    L = torch.dot(w, elastic_solve(E, f, model))
+    L.backward()
+    gE, gf = E.grad.cpu().numpy(), f.grad.cpu().numpy()
+    # constrained DOFs: u_c = f_c, so dL/df_c = w_c exactly
+    assert np.abs(gf[cdof] - w.cpu().numpy()[cdof]).max() == 0.0
+    free = np.flatnonzero(~cdof)
+    for i in list(rng.choice(free, 4, replace=False)) + list(np.flatnonzero(cdof)[:2]):
+        fp, fm = f0.copy(), f0.copy()
+        fp[i] += 1.0
+        fm[i] -= 1.0
+        fd = (loss(E0, fp) - loss(E0, fm)) / 2.0
+        assert abs(fd - gf[i]) <= 1e-9 * np.abs(gf).max(), (i, fd, gf[i])
+    h = 1e-6
+    for e in p.extra["fd_elems"]:
+        Ep, Em = E0.copy(), E0.copy()
+        Ep[e] *= 1 + h
+        Em[e] *= 1 - h
+        fd = (loss(Ep, f0) - loss(Em, f0)) / (2 * h * E0[e])
+        assert abs(fd - gE[e]) <= 1e-3 * np.abs(gE).max(), (e, fd, gE[e])
