@@ -205,6 +205,21 @@ aspamg_status aspamg_vcycle(aspamg_handle h, const double *y_dev, double *z_dev)
 aspamg_status aspamg_apply_operator(aspamg_handle h, int32_t level, int32_t which,
                                     int32_t precision, const double *x_dev, double *y_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same product
+ * as aspamg_apply_operator, with the FP32 staging of x and y in a fixed
+ * library array of 2^23 floats (32 MiB) per device instead of per-call
+ * allocations; no hipMalloc, hipFree or other allocating routine is called.
+ * Arguments and results as for aspamg_apply_operator (bitwise the same
+ * output).  EINVAL when an FP32 product needs more staging than the array
+ * holds (3 * (columns rounded up to 64) + 3 * rows values) or on bad
+ * arguments.  Every call on one device shares that device's array and leaves
+ * its last contents there: calls that overlap in time on one device (two
+ * threads, or two handles on different streams) race and must be serialised
+ * by the caller. */
+aspamg_status aspamg_apply_operator_noalloc(aspamg_handle h, int32_t level, int32_t which,
+                                            int32_t precision, const double *x_dev, double *y_dev);
+
 /* Level summary. */
 aspamg_status aspamg_level_info(aspamg_handle h, int32_t level, aspamg_level_info_t *out);
 

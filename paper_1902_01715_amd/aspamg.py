@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EH
 # every symbol declared in include/aspamg.h
 EXPORTED = [
     "aspamg_default_params", "aspamg_setup", "aspamg_set_cycle_precision", "aspamg_solve",
-    "aspamg_solve_batch", "aspamg_vcycle", "aspamg_apply_operator", "aspamg_level_info",
+    "aspamg_solve_batch", "aspamg_vcycle", "aspamg_apply_operator", "aspamg_apply_operator_noalloc",
+    "aspamg_level_info",
     "aspamg_level_matrix", "aspamg_level_split", "aspamg_level_test_space", "aspamg_element_gradient", "aspamg_assembler_create",
     "aspamg_assemble", "aspamg_assembler_destroy", "aspamg_time_kernel", "aspamg_destroy", "aspamg_last_error",
 ]
@@ -98,6 +99,7 @@ def lib():
         L.aspamg_solve_batch.argtypes = [P, C.c_int32, P, C.c_int64, P, C.c_int64, P]
         L.aspamg_vcycle.argtypes = [P, P, P]
         L.aspamg_apply_operator.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P]
+        L.aspamg_apply_operator_noalloc.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P]
         L.aspamg_level_info.argtypes = [P, C.c_int32, C.POINTER(LevelInfo)]
         L.aspamg_level_matrix.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
         L.aspamg_level_split.argtypes = [P, C.c_int32, P, P, P]
@@ -242,6 +244,13 @@ class Solver:
         y = torch.empty(out_rows, dtype=torch.float64, device=x.device)
         self._stream.synchronize()
         _check(lib().aspamg_apply_operator(self.h, level, which, precision, _ptr(x.contiguous()), _ptr(y)))
+        return y
+
+    def apply_noalloc(self, level, which, x, y, precision=64):
+        """The same product as apply() into a caller-provided y, through the
+        entry point that allocates no device memory."""
+        self._stream.synchronize()
+        _check(lib().aspamg_apply_operator_noalloc(self.h, level, which, precision, _ptr(x.contiguous()), _ptr(y)))
         return y
 
     def time_kernel(self, which, reps=20):

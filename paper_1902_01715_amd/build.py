@@ -28,6 +28,7 @@ SOURCES = [
     ("kernels_solve.hip", True, []),
     ("kernels_setup.hip", True, ["-ffp-contract=off"]),
     ("kernels_batch.hip", True, []),
+    ("noalloc.hip", True, []),
     ("batch_api.cpp", False, []),
     ("setup_host.cpp", False, ["-ffp-contract=off", "-fopenmp"]),
     ("api.cpp", False, ["-fopenmp"]),

@@ -20,6 +20,7 @@ static_assert(sizeof(aspamg_level_info_t) == 144, "aspamg_level_info_t layout ch
 namespace aspamg {
 
 static thread_local std::string g_last_error;
+void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 void fail(aspamg_status code, const std::string &msg) { throw Error{code, msg}; }
 
@@ -923,7 +924,9 @@ static aspamg_status setup_impl(const aspamg_params *pp, int32_t n_nodes, int64_
   // every stream keeps the default priority; a private stream is created so
   // that the PCG iteration can be captured as a graph
   hipStream_t user = static_cast<hipStream_t>(hip_stream);
+  HIPCHK(hipGetDevice(&h->device));
   HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+  noalloc_scratch_current_device();   // the no-allocation entry point's staging on this device
   if (user) HIPCHK(hipStreamSynchronize(user));
   h->ntv = n_tv;
   h->n = n_nodes;

@@ -166,6 +166,7 @@ struct BatchWork;  // multi-RHS buffers (solve_batch)
 struct aspamg_ctx {
   aspamg_params p;
   hipStream_t stream = nullptr;
+  int32_t device = 0;                         // device current at setup (the stream's)
   int32_t ntv = 0;
   int32_t n = 0;                              // fine block rows
   std::vector<aspamg::Level> lev;
@@ -307,6 +308,12 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0);
 // M = G^T G on the small smoothed levels above the dense tail
 void merge_smoothers(aspamg_ctx *h);
 double quantize(double s, int bits);
+
+// message returned by aspamg_last_error for the calling thread
+void set_last_error(const std::string &msg);
+// device address of the no-allocation staging array on the current device
+// (looked up once per device)
+float *noalloc_scratch_current_device();
 
 // gamma_{m+1} of the longest scalar row of the fine-level K: the relative
 // rounding bound of recomputing a residual f - K u in FP64
