@@ -195,6 +195,36 @@ def bench_adjoint(args, p, desc):
     }
 
 
+OP_NAMES = {0: "residual A", 1: "G", 2: "G^T", 3: "restriction R", 4: "merged G^T G", 5: "stacked [P; AP]",
+            6: "dense", 7: "prolongation P"}
+
+
+def level_table(S, levels, reps=50):
+    """Every product of the V-cycle per level and precision: average launch
+    time (HIP events, 50 launches), algorithmic bytes and GB/s, and how many
+    times one cycle launches it (V(1,1): A once, G and G^T twice, R and the
+    stacked product once, or P once and A twice on a level without the stacked
+    product; merged G^T G twice where the FP32 cycle uses it)."""
+    rows = []
+    tail = S.last_stats["tail_level"]
+    for l, li in enumerate(levels):
+        dense = li["n_coarse"] == 0 or l == tail
+        for prec in (32, 64):
+            if dense:
+                ops = [6]
+            else:
+                ops = [0, 4] if prec == 32 and li["nnzb_M"] > 0 else [0, 1, 2]
+                ops += [3, 5] if li["sell_stacked"] != 0 else [3, 7]
+            for op in ops:
+                ms, by = S.time_operator(l, op, prec, reps)
+                per_cycle = {0: 1 if li["sell_stacked"] != 0 else 2, 1: 2, 2: 2, 3: 1, 4: 2, 5: 1, 6: 1, 7: 1}[op]
+                rows.append({"level": l, "prec": prec, "op": OP_NAMES[op], "per_cycle": per_cycle, "ms": ms,
+                             "bytes": by, "GBps": by / (ms * 1e-3) / 1e9})
+        if dense:
+            break
+    return rows
+
+
 def stream_reference():
     """Streaming rates of PyTorch's own kernels on 2 GiB FP64 arrays (read-only
     sum, write-only fill, two-read-one-write add, copy): the practical HBM
@@ -237,6 +267,9 @@ def main():
                     help="SRQCG iterations on each level's test space, n_tv = 10 (the rigid-body modes and four "
                          "seeded random columns): the paper's defaults; 0 keeps the six rigid-body modes alone "
                          "(c2, c3, c4)")
+    ap.add_argument("--level-table", action="store_true",
+                    help="also time every V-cycle product per level and precision (aspamg_time_operator) and add "
+                         "the table to the JSON line")
     ap.add_argument("--stream-ref", action="store_true",
                     help="only measure PyTorch's streaming rates on this device and exit")
     args = ap.parse_args()
@@ -349,6 +382,8 @@ def main():
                      "traffic": measured_traffic(args.config), "avg_launch_ms": kp_ms,
                      "alg_bytes_per_launch": kp_b},
     }
+    if args.level_table:
+        out["level_table"] = level_table(S, levels)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.config, st32["iterations"], args.n_rq)

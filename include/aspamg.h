@@ -136,7 +136,8 @@ typedef struct {
    * row-stacked [P; A P] operator of the coarse-grid correction */
   int32_t sell_index16;
   /* layout of the row-stacked [P; A P] operator (same encoding as sell_lanes64;
-   * its FP32 copy shares it); 0 on the coarsest level */
+   * its FP32 copy shares it); 0 on the coarsest level and where A P has more
+   * blocks than A (there the first post-smoothing step applies P, then A) */
   int32_t sell_stacked;
   /* blocks of M = G^T G when the FP32 cycle's smoothing applies it as one
    * stored operator (small levels above the dense tail), else 0 (G, then G^T;
@@ -285,6 +286,20 @@ aspamg_status aspamg_assembler_destroy(aspamg_assembler a);
  *   avg_ms, alg_bytes: caller-owned outputs.  Errors: EINVAL, EHIP. */
 aspamg_status aspamg_time_kernel(aspamg_handle h, int32_t which, int32_t reps, double *avg_ms,
                                  double *alg_bytes);
+
+/* Measurement entry point: one product of the V-cycle on one level, launched
+ * `reps` times back to back on the handle's stream between two HIP events,
+ * as in aspamg_time_kernel (average ms per launch and algorithmic bytes of
+ * one launch: each stored block with its column index once, each vector
+ * entry read or written once).
+ *   op = 0  residual r = y - A z          3  restriction r_c = R r
+ *        1  t = G r                        4  z += w (G^T G) r, merged (FP32, where stored)
+ *        2  z += w G^T t                   5  stacked [P; A P] e (first post-smoothing step)
+ *        6  the dense operator of the tail level or of the coarsest level (only there)
+ *        7  prolongation z += P e (where the level has no stacked [P; A P])
+ *   precision 64 or 32.  Errors: EINVAL (level / op / precision), EHIP. */
+aspamg_status aspamg_time_operator(aspamg_handle h, int32_t level, int32_t op, int32_t precision,
+                                   int32_t reps, double *avg_ms, double *alg_bytes);
 
 aspamg_status aspamg_destroy(aspamg_handle h);
 const char *aspamg_last_error(void);

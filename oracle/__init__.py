@@ -18,11 +18,12 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 OK, NOT_CONVERGED, EINVAL, ENOMEM, ENOTSPD, EBREAK, ENAN = 0, 1, -1, -2, -4, -5, -6
 
 
-def compile_source(src: str, out: str) -> str:
-    """gcc build of one oracle source file (no fast-math, no FP contraction)."""
+def compile_source(src: str, out: str, openmp: bool = False) -> str:
+    """gcc build of one oracle source file (no fast-math, no FP contraction);
+    openmp=True builds the timing variant whose row loops run on all cores."""
     tmp = out + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                           "-o", tmp, src, "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+                          + (["-fopenmp"] if openmp else []) + ["-o", tmp, src, "-lm"])
     os.replace(tmp, out)
     return out
 
@@ -115,6 +116,8 @@ def lib():
         L.oracle_last_error.restype = C.c_char_p
         L.oracle_default_params.argtypes = [C.POINTER(Params)]
         L.oracle_max_nb.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -418,3 +421,9 @@ def element_gradient(conn, Ke0, lam, u, ke_stride=0):
 def problem_rp(problem):
     """int64 row pointer of a Problem's K (the oracle's index width)."""
     return np.asarray(problem.row_ptr, dtype=np.int64)
+
+
+def set_threads(n):
+    """Threads of the OpenMP timing build (no effect on the default build)."""
+    lib().oracle_set_threads(int(n))
+    return lib().oracle_threads()

@@ -27,12 +27,19 @@
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math: every decision
  * quantity is plain IEEE binary64 +, -, *, /, sqrt in the order written here).
+ * The row loops of the block product and the vector updates of the cycle and
+ * of PCG carry OpenMP pragmas for a timing build with -fopenmp (rows are
+ * independent, so results are bitwise those of the sequential build); the
+ * default build ignores them.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OMAXLEV 32
 #define OMAXB 3
@@ -165,6 +172,7 @@ static const double *bsr_block(const obsr *M, int32_t r, int32_t c) {
 /* y = M x (scalar vectors of length n*b / nc*b); sums in stored block order */
 static void bsr_mv(const obsr *M, const double *x, double *y) {
   int b = M->b;
+#pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < M->n; i++) {
     double acc[OMAXB] = {0, 0, 0};
     for (int64_t k = M->rp[i]; k < M->rp[i + 1]; k++) {
@@ -1460,6 +1468,7 @@ static void smooth(const olevel *L, const double *y, double *s, int from_zero, d
   if (from_zero) memcpy(r, y, n * sizeof(double));
   else {
     bsr_mv(&L->A, s, r);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) r[i] = y[i] - r[i];
   }
   bsr_mv(&L->G, r, t);
@@ -1473,6 +1482,7 @@ static void smooth(const olevel *L, const double *y, double *s, int from_zero, d
       for (int d = 0; d < b; d++)
         for (int e = 0; e < b; e++) u[(int64_t)j * b + e] += B[d * b + e] * t[(int64_t)i * b + d];
     }
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; i++) s[i] = from_zero ? L->omega_s * u[i] : s[i] + L->omega_s * u[i];
 }
 
@@ -1485,10 +1495,12 @@ static void vcycle(const ohier *h, int l, const double *y, double *z) {
   double *rc = Ln->work[3], *hc = Ln->work[4];
   for (int it = 0; it < h->p.nu1; it++) smooth(L, y, s, it == 0, r, t, u);
   bsr_mv(&L->A, s, r);
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; i++) r[i] = y[i] - r[i];
   bsr_mv(&L->R, r, rc);
   vcycle(h, l + 1, rc, hc);
   bsr_mv(&L->P, hc, t);
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; i++) s[i] += t[i];
   for (int it = 0; it < h->p.nu2; it++) smooth(L, y, s, 0, r, t, u);
 }
@@ -1522,6 +1534,7 @@ int oracle_pcg(const ohier *h, const double *f, double *u, double rtol, int max_
     double pq = dot(p, q, n);
     if (!(pq > 0.0)) { rc = isfinite(pq) ? O_EBREAK : O_ENAN; *iters = k; break; }
     double alpha = rz / pq;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) { u[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
     double rr = dot(r, r, n);
     *iters = k;
@@ -1533,6 +1546,7 @@ int oracle_pcg(const ohier *h, const double *f, double *u, double rtol, int max_
     double rzn = dot(r, z, n), rzo = dot(r, zo, n);
     if (!(rzn > 0.0)) { rc = isfinite(rzn) ? O_EBREAK : O_ENAN; break; }
     double beta = (rzn - rzo) / rz;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
     rz = rzn;
   }
@@ -1568,6 +1582,22 @@ void oracle_element_gradient(int64_t n_el, const int32_t *conn, const double *Ke
 /* ========================================================================= */
 /* inspection exports for the tests                                           */
 /* ========================================================================= */
+/* threads of the OpenMP timing build (1 in the default build) */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int oracle_num_levels(const ohier *h) { return h->nlev; }
 double oracle_min_margin(const ohier *h) { return h->min_margin; }
 int oracle_coarse_order(const ohier *h) { return h->nd; }

@@ -1,0 +1,170 @@
+"""TEST INFRASTRUCTURE: the oracle on a full-size workload, run once on a CPU host.
+
+    python -m oracle.fullsize_run c2            # six rigid-body modes, every value bitwise
+    python -m oracle.fullsize_run c3 --n-rq 10  # the paper's default test space
+
+Writes
+  tests/golden/<name>_hierarchy.json  per-level fingerprints of the oracle's
+      hierarchy: SHA-256 of the C/F split, the scalar interpolation pattern and
+      the block patterns of A, G and P; of the block values of A, G and P when
+      both implementations compute them in the same order (n_rq = 0); with the
+      SRQCG test space (inner products summed in different orders on the two
+      sides) the values of 48 seeded sampled block rows per level instead;
+  profiles/oracle_<name>_fullsize.json  the oracle's setup time and the time of
+      its PCG iterations on this hierarchy, single-threaded and with its OpenMP
+      row loops on every host core (host CPU, core count, git revision).
+Only oracle/ and the seeded input generator are called; nothing here reads a
+GPU result.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import subprocess
+import sys
+import tempfile
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_SAMPLE_ROWS = 48
+
+
+def sha(*arrays) -> str:
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def sample_rows(n: int, level: int) -> np.ndarray:
+    rng = np.random.default_rng(1000 + level)
+    return np.sort(rng.choice(n, size=min(n, N_SAMPLE_ROWS), replace=False))
+
+
+def row_values(M, rows):
+    return [M.v[M.rp[i]:M.rp[i + 1]].reshape(-1).tolist() for i in rows]
+
+
+def fingerprint(H, bitwise_values: bool) -> list:
+    out = []
+    for l in range(H.nlev):
+        info = H.info(l)
+        A = H.A(l)
+        rec = {"level": l, "n": info["n"], "nnzb_A": info["nnzb_A"], "A_pattern": sha(A.rp, A.ci)}
+        if bitwise_values:
+            rec["A_values"] = sha(A.v)
+        if info["has_G"]:
+            G, P = H.G(l), H.P(l)
+            cnt, cols = H.P_scalar(l)
+            rec.update({"nnzb_G": info["nnzb_G"], "nnzb_P": info["nnzb_P"], "n_coarse": info["nc"],
+                        "cf": sha(H.cf(l)), "P_scalar": sha(cnt, cols), "G_pattern": sha(G.rp, G.ci),
+                        "P_pattern": sha(P.rp, P.ci), "omega_s": info["omega_s"],
+                        "fsai_rounds": info["fsai_rounds"]})
+            if bitwise_values:
+                rec["G_values"] = sha(G.v)
+                rec["P_values"] = sha(P.v)
+            else:
+                rows = sample_rows(info["n"], l)
+                rec["sample_rows"] = rows.tolist()
+                rec["A_rows"] = row_values(A, rows)
+                rec["G_rows"] = row_values(G, rows)
+                rec["P_rows"] = row_values(P, rows)
+        elif not bitwise_values:
+            rows = sample_rows(info["n"], l)
+            rec["sample_rows"] = rows.tolist()
+            rec["A_rows"] = row_values(A, rows)
+        out.append(rec)
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def git_rev() -> str:
+    try:
+        return subprocess.check_output(["git", "-C", ROOT, "rev-parse", "--short=12", "HEAD"], text=True).strip()
+    except (OSError, subprocess.CalledProcessError):
+        return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("config", choices=["c2", "c3"])
+    ap.add_argument("--n-rq", type=int, default=0)
+    ap.add_argument("--iters", type=int, default=10, help="PCG iterations timed per thread count")
+    args = ap.parse_args()
+
+    import oracle
+    from paper_1902_01715_amd import problems as PR
+
+    tmp = tempfile.mkdtemp(prefix="oracle_omp_")
+    lib = oracle.compile_source(os.path.join(HERE, "aspamg_oracle.c"), os.path.join(tmp, "liboracle_omp.so"),
+                                openmp=True)
+    oracle.use_library(lib)
+    ncores = os.cpu_count() or 1
+
+    t0 = time.perf_counter()
+    p = PR.CONFIGS[args.config]()
+    t_gen = time.perf_counter() - t0
+    V0 = p.V0 if args.n_rq == 0 else PR.initial_test_space(p, 10, 11)
+    prm = oracle.default_params(n_rq=args.n_rq)
+    print(f"[oracle {args.config}] inputs {p.n_dof} DOF in {t_gen:.1f} s; setup on {ncores} threads ...", flush=True)
+    oracle.set_threads(ncores)
+    t0 = time.perf_counter()
+    H = oracle.Hierarchy(p.row_ptr, p.col, p.vals, V0, prm)
+    t_setup = time.perf_counter() - t0
+    levels = [H.info(l)["n"] for l in range(H.nlev)]
+    print(f"[oracle {args.config}] setup {t_setup:.1f} s, levels {levels}", flush=True)
+
+    tag = args.config if args.n_rq == 0 else f"{args.config}_srqcg"
+    golden = {"config": args.config, "n_rq": args.n_rq, "n_tv": int(V0.shape[-1]),
+              "test_space": "rigid-body modes" if args.n_rq == 0 else
+              "rigid-body modes + 4 seeded normal columns (initial_test_space(p, 10, 11))",
+              "bitwise_values": args.n_rq == 0, "levels": fingerprint(H, args.n_rq == 0),
+              "written_by": "oracle/fullsize_run.py", "git": git_rev()}
+    gpath = os.path.join(ROOT, "tests", "golden", f"{tag}_hierarchy.json")
+    with open(gpath, "w") as fh:
+        json.dump(golden, fh, indent=1)
+    print(f"[oracle {args.config}] wrote {gpath}", flush=True)
+
+    times = {}
+    for nt in (1, ncores):
+        got = oracle.set_threads(nt)
+        H.pcg(p.f if p.f.ndim == 1 else p.f[:, 0], 0.0, 1)          # warm the vectors
+        t0 = time.perf_counter()
+        u, st = H.pcg(p.f if p.f.ndim == 1 else p.f[:, 0], 0.0, args.iters)
+        dt = time.perf_counter() - t0
+        times[str(got)] = {"threads": got, "iterations": st["iterations"], "seconds": dt,
+                           "s_per_iter": dt / st["iterations"]}
+        print(f"[oracle {args.config}] {got} threads: {st['iterations']} PCG iterations in {dt:.1f} s "
+              f"({dt / st['iterations']:.3f} s/it)", flush=True)
+    rec = {"config": args.config, "n_dof": int(p.n_dof), "n_rq": args.n_rq, "levels": levels,
+           "setup_s": t_setup, "setup_threads": ncores, "pcg": times,
+           "host": {"cpu": cpu_model(), "nproc": ncores, "machine": platform.machine()},
+           "git": git_rev(), "written_by": "oracle/fullsize_run.py",
+           "note": "PCG iterations with rtol 0 (exactly the stated count) on the oracle's own hierarchy; "
+                   "row loops of the block products and vector updates on the stated threads"}
+    ppath = os.path.join(ROOT, "profiles", f"oracle_{tag}_fullsize.json")
+    with open(ppath, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(f"[oracle {args.config}] wrote {ppath}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

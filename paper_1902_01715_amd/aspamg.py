@@ -25,7 +25,8 @@ EXPORTED = [
     "aspamg_solve_batch", "aspamg_vcycle", "aspamg_apply_operator", "aspamg_apply_operator_noalloc",
     "aspamg_level_info",
     "aspamg_level_matrix", "aspamg_level_split", "aspamg_level_test_space", "aspamg_element_gradient", "aspamg_assembler_create",
-    "aspamg_assemble", "aspamg_assembler_destroy", "aspamg_time_kernel", "aspamg_destroy", "aspamg_last_error",
+    "aspamg_assemble", "aspamg_assembler_destroy", "aspamg_time_kernel", "aspamg_time_operator", "aspamg_destroy",
+    "aspamg_last_error",
 ]
 
 
@@ -110,6 +111,8 @@ def lib():
         L.aspamg_assemble.argtypes = [P, P, P]
         L.aspamg_assembler_destroy.argtypes = [P]
         L.aspamg_time_kernel.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.aspamg_time_operator.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_double)]
         L.aspamg_destroy.argtypes = [P]
         L.aspamg_last_error.restype = C.c_char_p
         for nm in EXPORTED:
@@ -258,6 +261,14 @@ class Solver:
         ms, by = C.c_double(), C.c_double()
         self._stream.synchronize()
         _check(lib().aspamg_time_kernel(self.h, which, reps, C.byref(ms), C.byref(by)))
+        return ms.value, by.value
+
+    def time_operator(self, level, op, precision, reps=20):
+        """(average ms per launch, algorithmic bytes per launch) of one V-cycle
+        product of a level (op codes of aspamg_time_operator)."""
+        ms, by = C.c_double(), C.c_double()
+        self._stream.synchronize()
+        _check(lib().aspamg_time_operator(self.h, level, op, precision, reps, C.byref(ms), C.byref(by)))
         return ms.value, by.value
 
     @property

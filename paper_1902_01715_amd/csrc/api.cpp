@@ -546,8 +546,14 @@ static void cycle_level(aspamg_ctx *h, int l, const T *y, T *z, const PcgCtrl *c
   launch_spmv<T, T, T>(O::R(L), W.r, Wn.y, nullptr, 1.0, ctrl, s);
   cycle_level<T>(h, l + 1, Wn.y, Wn.z, ctrl);
   // first post-smoothing step (nu2 >= 1): z += P e and r = (y - A z_pre) - (A P) e
-  // in one stacked product (W.r still holds the pre-smoothing residual)
-  launch_spmv_dual<T, T, T>(O::PAP(L), L.P.n, Wn.z, z, z, 1.0, W.r, W.r, -1.0, ctrl, s);
+  // in one stacked product (W.r still holds the pre-smoothing residual), or
+  // z += P e and then r = y - A z
+  if (L.stacked()) {
+    launch_spmv_dual<T, T, T>(O::PAP(L), L.P.n, Wn.z, z, z, 1.0, W.r, W.r, -1.0, ctrl, s);
+  } else {
+    launch_spmv<T, T, T>(O::P(L), Wn.z, z, z, 1.0, ctrl, s);
+    launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
+  }
   for (int it = 0; it < h->p.nu2; it++) {
     if (it > 0) launch_spmv<T, T, T>(O::A(L), z, W.r, y, -1.0, ctrl, s);
     smooth(W.r, z);
@@ -745,14 +751,15 @@ static double level_bytes(const aspamg_ctx *h, const Level &L) {
   const double nA = (double)L.A.nnzb(), nG = (double)L.G.nnzb(), nP = (double)L.P.nnzb();
   // A: nu1 - 1 pre-smoothing residuals, the restriction residual and nu2 - 1
   // post-smoothing residuals; G and G^T once per smoothing step; R once; the
-  // stacked [P; A P] once (first post-smoothing step, nu2 >= 1)
-  const double usesA = (double)(h->p.nu1 + h->p.nu2 - 1);
+  // stacked [P; A P] once (first post-smoothing step, nu2 >= 1), or P and one
+  // more A
+  const double usesA = (double)(h->p.nu1 + h->p.nu2 - (L.stacked() ? 1 : 0));
   const double nu = (double)(h->p.nu1 + h->p.nu2);
   const bool merged = std::is_same<T, float>::value && L.nnzb_M > 0;
   const double smooth = merged ? (double)L.nnzb_M * block_bytes(O::M(L))
                                : nG * (block_bytes(O::G(L)) + block_bytes(O::GT(L)));
-  return usesA * nA * block_bytes(O::A(L)) + nu * smooth +
-         nP * block_bytes(O::R(L)) + (nP + (double)L.nnzb_AP) * block_bytes(O::PAP(L)) +
+  const double post = L.stacked() ? (nP + (double)L.nnzb_AP) * block_bytes(O::PAP(L)) : nP * block_bytes(O::P(L));
+  return usesA * nA * block_bytes(O::A(L)) + nu * smooth + nP * block_bytes(O::R(L)) + post +
          18.0 * 3.0 * L.A.n * sizeof(T);
 }
 
@@ -1160,7 +1167,7 @@ aspamg_status aspamg_level_info(aspamg_handle h, int32_t level, aspamg_level_inf
     if (M64[k]->col16) o->sell_index16 |= 1 << k;
     if (M32[k]->col16) o->sell_index16 |= 1 << (5 + k);
   }
-  o->sell_stacked = L.PAP64.pack ? -L.PAP64.pack : L.PAP64.lanes;
+  o->sell_stacked = !L.stacked() ? 0 : L.PAP64.pack ? -L.PAP64.pack : L.PAP64.lanes;
   o->nnzb_M = L.nnzb_M;
   if (L.PAP64.col16) o->sell_index16 |= 1 << 10;
   return ASPAMG_OK;
@@ -1339,6 +1346,90 @@ aspamg_status aspamg_time_kernel(aspamg_handle h, int32_t which, int32_t reps, d
     case 4: bytes = cycle_bytes(h, 64); break;
   }
   // inputs: zero-filled vectors are enough for timing (the bytes streamed do not depend on values)
+  run();
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; i++) run();
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
+  *avg_ms = (double)ms / reps;
+  *alg_bytes = bytes;
+  return ASPAMG_OK;
+  ABI_END
+}
+
+aspamg_status aspamg_time_operator(aspamg_handle h, int32_t level, int32_t op, int32_t precision, int32_t reps,
+                                   double *avg_ms, double *alg_bytes) {
+  ABI_BEGIN
+  if (!h || level < 0 || level >= (int32_t)h->lev.size() || op < 0 || op > 7 ||
+      (precision != 32 && precision != 64) || reps < 1 || !avg_ms || !alg_bytes)
+    fail(ASPAMG_EINVAL, "invalid arguments to aspamg_time_operator");
+  const Level &L = h->lev[level];
+  const bool dense = level == h->tail.level || L.coarsest;
+  if (dense != (op == 6)) fail(ASPAMG_EINVAL, "op 6 is the dense operator of the tail or coarsest level, and only it");
+  if (op == 4 && L.nnzb_M == 0) fail(ASPAMG_EINVAL, "this level stores no merged G^T G");
+  if (op == 4 && precision == 64) fail(ASPAMG_EINVAL, "the merged G^T G is applied by the FP32 cycle only");
+  if (op == 5 && !L.stacked()) fail(ASPAMG_EINVAL, "this level applies P and then A (no stacked [P; A P])");
+  hipStream_t s = h->stream;
+  const double n3 = 3.0 * L.A.n, vs = precision == 32 ? 4.0 : 8.0;
+  double bytes = 0.0;
+  std::function<void()> run;
+  auto setup_op = [&](auto tag) {
+    using T = decltype(tag);
+    using O = Ops<T>;
+    const LevelVecs<T> &W = O::V(L);
+    if (op == 6) {
+      const int nd = level == h->tail.level ? h->tail.nd : h->coarse.nd;
+      const double *D = level == h->tail.level ? h->tail.v : h->coarse.inv;
+      run = [=]() { launch_dense_gemv<T>(nd, D, W.y, W.z, nullptr, s); };
+      bytes = (double)nd * nd * 8.0 + 2.0 * nd * vs;
+      return;
+    }
+    const LevelVecs<T> &Wn = O::V(h->lev[level + 1 < (int)h->lev.size() ? level + 1 : level]);
+    const double w = L.omega_s;
+    switch (op) {
+      case 0:   // residual r = y - A z
+        run = [=, &L]() { launch_spmv<T, T, T>(O::A(L), W.z, W.r, W.y, -1.0, nullptr, s); };
+        bytes = (double)L.A.nnzb() * block_bytes(O::A(L)) + 3.0 * n3 * vs;
+        break;
+      case 1:   // t = G r
+        run = [=, &L]() { launch_spmv<T, T, T>(O::G(L), W.r, W.t, nullptr, 1.0, nullptr, s); };
+        bytes = (double)L.G.nnzb() * block_bytes(O::G(L)) + 2.0 * n3 * vs;
+        break;
+      case 2:   // z = z + w G^T t
+        run = [=, &L]() { launch_spmv<T, T, T>(O::GT(L), W.t, W.z, W.z, w, nullptr, s); };
+        bytes = (double)L.G.nnzb() * block_bytes(O::GT(L)) + 3.0 * n3 * vs;
+        break;
+      case 3:   // restriction r_c = R r
+        run = [=, &L]() { launch_spmv<T, T, T>(O::R(L), W.r, Wn.y, nullptr, 1.0, nullptr, s); };
+        bytes = (double)L.P.nnzb() * block_bytes(O::R(L)) + n3 * vs + 3.0 * L.nc * vs;
+        break;
+      case 4:   // z = z + w (G^T G) r, merged
+        run = [=, &L]() { launch_spmv<T, T, T>(O::M(L), W.r, W.z, W.z, w, nullptr, s); };
+        bytes = (double)L.nnzb_M * block_bytes(O::M(L)) + 3.0 * n3 * vs;
+        break;
+      case 5:   // stacked [P; A P] e: z + P e and r - (A P) e
+        run = [=, &L]() {
+          launch_spmv_dual<T, T, T>(O::PAP(L), L.P.n, Wn.z, W.z, W.z, 1.0, W.r, W.r, -1.0, nullptr, s);
+        };
+        bytes = ((double)L.P.nnzb() + (double)L.nnzb_AP) * block_bytes(O::PAP(L)) + 4.0 * n3 * vs + 3.0 * L.nc * vs;
+        break;
+      case 7:   // prolongation z += P e
+        run = [=, &L]() { launch_spmv<T, T, T>(O::P(L), Wn.z, W.z, W.z, 1.0, nullptr, s); };
+        bytes = (double)L.P.nnzb() * block_bytes(O::P(L)) + 2.0 * n3 * vs + 3.0 * L.nc * vs;
+        break;
+    }
+  };
+  if (precision == 32) setup_op(float{});
+  else setup_op(double{});
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
   run();
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipEventRecord(e0, s));

@@ -121,10 +121,12 @@ struct Level {
   Sell<double> A64, G64, GT64, P64, R64;
   Sell<float> A32, G32, GT32, P32, R32;
   // [P; A P] stacked (2 N rows): the first post-smoothing step forms
-  // z + P e and r_pre - (A P) e in one product
+  // z + P e and r_pre - (A P) e in one product.  Only where A P has at most
+  // as many blocks as A (nnzb_AP > 0); elsewhere the step applies P, then A.
   Sell<double> PAP64;
   Sell<float> PAP32;
   int64_t nnzb_AP = 0;
+  bool stacked() const { return nnzb_AP > 0; }
   // M = G^T G as one stored operator on small levels (nnzb_M > 0): each
   // smoothing step of the FP32 cycle is then one product instead of G
   // followed by G^T

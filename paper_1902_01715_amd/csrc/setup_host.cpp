@@ -1363,14 +1363,18 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     L.P32 = derive_fp32(h, L.P64);
     L.R64 = upload_sell<double>(h, transpose(L.P));
     L.R32 = derive_fp32(h, L.R64);
-    {
+    // the stacked [P; A P] replaces the products with P and A of the first
+    // post-smoothing step only where it stores no more blocks than A: the
+    // interpolation of a rich test space can make A P denser than A
+    if (AP.nnzb() <= L.A.nnzb()) {
       L.nnzb_AP = AP.nnzb();
       HostBSR PAP = stack_rows(L.P, AP);
       AP = HostBSR();
       L.PAP64 = upload_sell<double>(h, PAP, 0, true, dPAP);
-      dfree(h, dPAP);
       L.PAP32 = derive_fp32(h, L.PAP64);
     }
+    AP = HostBSR();
+    dfree(h, dPAP);
     clk.tick(l, "upload G P R");
     std::vector<double> Vc((size_t)nc * 3 * ntv);
     for (int32_t i = 0; i < N; i++)

@@ -1,0 +1,91 @@
+"""Full-size hierarchy parity with the oracle through stored fingerprints.
+
+tests/golden/<name>_hierarchy.json is written by oracle/fullsize_run.py, which
+builds the oracle's hierarchy of the full workload once on a CPU host (C2 with
+the six rigid-body modes: several minutes; C3 with the paper's test space:
+longer).  Here the GPU library builds the same hierarchy, in the launch
+configuration bench.py times, and every level is compared:
+  - bit for bit: the C/F split, the scalar interpolation pattern and the block
+    patterns of A, G and P (SHA-256 of the exported arrays);
+  - C2 (n_rq = 0, both sides sum in the same order): the block values of A, G
+    and P bit for bit as well;
+  - C3 with SRQCG (its inner products are summed in different orders on the
+    two sides, so the test spaces agree to rounding only): the values of 48
+    seeded sampled block rows per level, to 1e-8 of the row's largest entry.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1902_01715_amd import problems as PR
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def sha(*arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def load(tag):
+    path = os.path.join(GOLDEN, f"{tag}_hierarchy.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written yet (python -m oracle.fullsize_run)")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("tag", ["c2", "c3_srqcg"])
+def test_fullsize_hierarchy_matches_oracle_fingerprints(tag, cuda):
+    from paper_1902_01715_amd import aspamg
+    g = load(tag)
+    print(f"[case full-size hierarchy {tag}]", flush=True)
+    p = PR.CONFIGS[g["config"]]()
+    V0 = p.V0 if g["n_rq"] == 0 else PR.initial_test_space(p, 10, 11)
+    S = aspamg.Solver(p.row_ptr, p.col, p.vals, V0, aspamg.default_params(n_rq=g["n_rq"]))
+    try:
+        assert S.nlev == len(g["levels"]), (S.nlev, len(g["levels"]))
+        worst = 0.0
+        for rec in g["levels"]:
+            l = rec["level"]
+            li = S.level_info(l)
+            assert (li["n"], li["nnzb_A"]) == (rec["n"], rec["nnzb_A"]), (l, li["n"], li["nnzb_A"])
+            A = S.level_matrix(l, 0)
+            assert sha(A[0], A[1]) == rec["A_pattern"], f"level {l}: Galerkin pattern"
+            if g["bitwise_values"]:
+                assert sha(A[2]) == rec["A_values"], f"level {l}: Galerkin values"
+            mats = {"A": A}
+            if "cf" in rec:
+                assert (li["nnzb_G"], li["nnzb_P"], li["n_coarse"]) == (rec["nnzb_G"], rec["nnzb_P"], rec["n_coarse"])
+                cf, cnt, cols = S.level_split(l)
+                assert sha(cf) == rec["cf"], f"level {l}: C/F split"
+                assert sha(cnt, cols) == rec["P_scalar"], f"level {l}: scalar interpolation pattern"
+                G, P = S.level_matrix(l, 1), S.level_matrix(l, 3)
+                assert sha(G[0], G[1]) == rec["G_pattern"], f"level {l}: FSAI pattern"
+                assert sha(P[0], P[1]) == rec["P_pattern"], f"level {l}: interpolation block pattern"
+                assert li["fsai_rounds"] == rec["fsai_rounds"], l
+                assert abs(li["omega_s"] - rec["omega_s"]) <= 1e-6 * rec["omega_s"], l
+                if g["bitwise_values"]:
+                    assert sha(G[2]) == rec["G_values"], f"level {l}: FSAI values"
+                    assert sha(P[2]) == rec["P_values"], f"level {l}: interpolation weights"
+                mats.update({"G": G, "P": P})
+            if not g["bitwise_values"]:
+                for name, M in mats.items():
+                    rp, v = M[0], M[2]
+                    for i, ref in zip(rec["sample_rows"], rec[f"{name}_rows"]):
+                        got = v[rp[i]:rp[i + 1]].reshape(-1)
+                        ref = np.asarray(ref)
+                        assert got.shape == ref.shape, (l, name, i)
+                        scale = max(np.abs(ref).max(), 1e-300)
+                        d = np.abs(got - ref).max() / scale
+                        worst = max(worst, d)
+                        assert d <= 1e-8, (l, name, i, d)
+        print(f"{tag}: {S.nlev} levels identical; largest sampled value difference {worst:.1e}", flush=True)
+    finally:
+        S.close()
