@@ -1,5 +1,6 @@
 """Edge cases and failure handling of the GPU path: a single-level hierarchy,
-zero and non-finite loads, the iteration cap, a non-SPD matrix, repeatability,
+zero and non-finite loads, the iteration cap, a non-SPD matrix, a singular
+matrix (free body), damping beyond 2/lambda_1 (PCG breakdown), repeatability,
 and an extreme kappa_p that forces one interpolation entry per row (patterns
 still bit-exact against the oracle)."""
 import numpy as np
@@ -102,3 +103,42 @@ def test_kappa_one_patterns_bit_exact(cuda, oracle_lib):
     u_o, _ = H.pcg(p.f, 1e-10, 1000)
     assert np.linalg.norm(u - u_o) / np.linalg.norm(u_o) <= 1e-8
     S.close()
+
+
+def test_damping_beyond_two_over_lambda_breaks_pcg(cuda):
+    """omega lambda_1(G A G^T) > 2 (a safety factor below 1 on the cantilever,
+    whose fine level has lambda_1 = 2.44): the V-cycle is indefinite and the
+    solve must stop with EBREAKDOWN, as the oracle does; the default margin
+    converges."""
+    import torch
+    from paper_1902_01715_amd import aspamg
+    print("[case omega beyond 2/lambda_1, cantilever 40x4x4]", flush=True)
+    p = PR.c2_cantilever(40, 4, 4)
+    f = torch.tensor(p.f, device="cuda")
+    S = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, aspamg.default_params(omega_safety=0.6))
+    li = S.level_info(0)
+    assert li["omega_s"] * li["lambda1"] > 2.0
+    for prec in (64, 32):
+        S.set_precision(prec)
+        with pytest.raises(aspamg.AspamgError) as ei:
+            S.solve(f)
+        assert ei.value.code == aspamg.EBREAKDOWN
+    S.close()
+    S = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0)
+    li = S.level_info(0)
+    assert li["omega_s"] * li["lambda1"] < 2.0
+    S.solve(f)
+    assert S.last_stats["status"] == aspamg.OK
+    S.close()
+
+
+def test_singular_matrix_is_rejected(cuda):
+    """A free body (no Dirichlet rows): K is singular and so is the coarsest
+    Galerkin operator; setup must fail with ENOT_SPD (coarsest Cholesky)."""
+    from paper_1902_01715_amd import aspamg
+    print("[case singular K, free body 5^3]", flush=True)
+    q = PR.unconstrained_box(5, 5, 5, seed=1)
+    with pytest.raises(aspamg.AspamgError) as ei:
+        aspamg.Solver(q.row_ptr, q.col, q.vals, q.V0)
+    assert ei.value.code == aspamg.ENOT_SPD
+    assert "coarsest" in str(ei.value)
