@@ -90,6 +90,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run paper_1902_01715_amd/build.py (hipcc, gfx950) first")
+        # the library and PyTorch must share one HIP runtime (libamdhip64.so.7):
+        # load PyTorch's first so that the library binds to it, not to a second copy
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.aspamg_default_params.argtypes = [C.POINTER(Params)]
