@@ -27,6 +27,7 @@ SOURCES = [
     # (file, is_device, extra flags)
     ("kernels_solve.hip", True, []),
     ("kernels_setup.hip", True, ["-ffp-contract=off"]),
+    ("kernels_coarsen.hip", True, ["-ffp-contract=off"]),
     ("kernels_batch.hip", True, []),
     ("noalloc.hip", True, []),
     ("batch_api.cpp", False, []),

@@ -811,7 +811,7 @@ static std::vector<T> fetch(const T *p, size_t n, hipStream_t s) {
 }
 
 static void check_params(const aspamg_params &p) {
-  if (p.k_g < 0 || p.rho_blocks < 1 || p.rho_blocks > kMaxGrowRho || p.theta < 1 || p.n_max < 1 || p.n_max > kMaxPEntries || p.d_p < 1 ||
+  if (p.k_g < 0 || p.rho_blocks < 1 || p.rho_blocks > kMaxGrowRho || p.theta < 1 || p.theta > kMaxTheta || p.n_max < 1 || p.n_max > kMaxPEntries || p.d_p < 1 ||
       p.lanczos_steps < 1 || p.lanczos_steps > 200 || p.nu1 < 1 || p.nu2 < 1 || p.max_levels < 1 ||
       (p.cycle_precision != 32 && p.cycle_precision != 64) || !(p.rtol >= 0) || p.max_it < 1 ||
       p.quant_bits < 8 || p.quant_bits > 52 || p.check_every < 1 || p.n_tv < 0 || p.n_tv > 64 ||

@@ -30,6 +30,7 @@ constexpr int kDotThreads = ASPAMG_DOT_THREADS;
 constexpr int kMaxFsaiNodes = 32;   // off-diagonal nodes an FSAI row may hold
 constexpr int kMaxGrowRho = 8;      // nodes one aFSAI growth step may add to a row
 constexpr int kMaxPEntries = 8;     // interpolation entries per scalar row (n_max cap)
+constexpr int kMaxTheta = 16;       // strong connections kept per node (theta cap)
 
 // Error raised inside the library; converted to aspamg_status at the ABI.
 struct Error {
@@ -280,6 +281,27 @@ void launch_fsai_grow(const DevBSR &A, int32_t nrows, const int32_t *rows, const
 // of the fine-level test space V (ntv columns): w = (C^T C)^{-1} C^T v.
 void launch_dpls_weights(int32_t nrows, const int32_t *row, const int32_t *cnt, const int32_t *sel,
                          const double *V, int ntv, double *w, hipStream_t s);
+// coarsening on the device (kernels_coarsen.hip): sq_i = sqrt(n_II); the theta
+// strongest connections of every node (keep[i*theta ..], nkeep[i]); the union
+// symmetrisation in three stages (0: counts into cnt; 1: fill the rows bp of
+// `both` through the cursors `at`, then sort and deduplicate each row into
+// len; 2: compact into srp / sci); the independent-set rounds (cf: -1
+// decoupled, 0 F, 1 C, 2 undecided; undecided counts the nodes left)
+void launch_node_norms(int32_t n, const double *V, int ntv, double *sq, hipStream_t s);
+void launch_strong_topk(const DevBSR &A, const int8_t *excl, const double *V, int ntv, const double *sq, int theta,
+                        int qbits, int32_t *keep, int32_t *nkeep, hipStream_t s);
+void launch_union(int32_t n, int theta, const int32_t *keep, const int32_t *nkeep, int stage, int32_t *cnt,
+                  int64_t *bp, int64_t *at, int32_t *both, int32_t *len, const int64_t *srp, int32_t *sci,
+                  hipStream_t s);
+void launch_mis_init(int32_t n, const int8_t *excl, int8_t *cf, hipStream_t s);
+void launch_mis_round(int32_t n, const int64_t *srp, const int32_t *sci, int8_t *cf, int8_t *win, int32_t *undecided,
+                      hipStream_t s);
+// interpolation entries of the fine nodes fnodes[0..nf): pcount[3I+d] and the
+// chosen fine scalar indices psel[(3I+d)*kMaxPEntries ..]; err set when a
+// node's candidates exceed the kernel's limits
+void launch_dpls_rows(int32_t nf, const int32_t *fnodes, const int64_t *srp, const int32_t *sci, const int8_t *cf,
+                      const double *V, int ntv, int d_p, int nmax, double kappa_q, double eps_p, int qbits,
+                      int32_t *pcount, int32_t *psel, int32_t *err, hipStream_t s);
 // RAP numeric phases
 void launch_spgemm_ap(const DevBSR &A, const DevBSR &P, const DevBSR &T, hipStream_t s);
 void launch_spgemm_rt(const DevBSR &R, const DevBSR &T, const DevBSR &Ac, hipStream_t s);

@@ -8,6 +8,7 @@
 // index order with separately rounded products, so the FSAI rows and the
 // Galerkin values are bitwise those of the sequential definition (IEEE
 // binary64 +, -, *, / and sqrt are correctly rounded on the device).
+#include "device_decisions.h"
 #include "internal.h"
 
 namespace aspamg {
@@ -372,27 +373,6 @@ __global__ void __launch_bounds__(256) k_axpy(int64_t n, double a, const double 
 __global__ void __launch_bounds__(256) k_divided(int64_t n, double a, const double *__restrict__ x,
                                                  double *__restrict__ y) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = x[i] / a;
-}
-
-// s rounded to `bits` significant bits, ties to even: the host quantiser of
-// the set-up decisions, for the device (normal values by integer operations on
-// the significand; zero, subnormal and non-finite values by frexp / ldexp).
-__device__ double quantize_dev(double s, int bits) {
-  uint64_t u = (uint64_t)__double_as_longlong(s);
-  const uint64_t ex = (u >> 52) & 0x7FF;
-  if (ex == 0 || ex == 0x7FF) {
-    if (s == 0.0 || !isfinite(s)) return s;
-    int e;
-    const double m = frexp(s, &e);
-    const double r = nearbyint(ldexp(m, bits));
-    return ldexp(r, e - bits);
-  }
-  const int drop = 53 - bits;
-  const uint64_t mask = (1ULL << drop) - 1, half = 1ULL << (drop - 1);
-  const uint64_t rem = u & mask;
-  u &= ~mask;
-  if (rem > half || (rem == half && ((u >> drop) & 1))) u += 1ULL << drop;
-  return __longlong_as_double((long long)u);
 }
 
 // position of column c in row r of A (columns ascending), or -1

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <numeric>
 
 #include "internal.h"
@@ -739,282 +740,111 @@ void srqcg(aspamg_ctx *h, Level &L, int nt, int kmax) {
 // ------------------------------------------------------------------------
 // coarsening (Section 3.4)
 // ------------------------------------------------------------------------
-// n_IJ: squared Frobenius norm of V_I V_J^T (3x3 entries summed over t
-// ascending, squares summed row-major)
-inline double node_affinity(const double *V, int ntv, int32_t I, int32_t J) {
-  double s = 0.0;
-  for (int d = 0; d < 3; d++)
-    for (int e = 0; e < 3; e++) {
-      const double *vi = V + ((size_t)I * 3 + d) * ntv;
-      const double *vj = V + ((size_t)J * 3 + e) * ntv;
-      double m = 0.0;
-      for (int t = 0; t < ntv; t++) m += vi[t] * vj[t];
-      s += m * m;
-    }
-  return s;
-}
-
-inline uint64_t mix64(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ULL;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-  return z ^ (z >> 31);
-}
-
-struct StrongGraph {
-  std::vector<int64_t> rp;
-  std::vector<int32_t> ci;
+// ------------------------------------------------------------------------
+// C/F split on the device (Section 3.4): strong graph S (theta filter of the
+// affinity SoC, union symmetrisation) and its maximal independent set.  The
+// decisions are bitwise those of the sequential rules (kernels_coarsen.hip).
+// ------------------------------------------------------------------------
+struct DevGraph {
+  Scratch rp, ci;
+  DevGraph(size_t n1, size_t nnz) : rp(n1 * 8), ci(nnz * 4) {}
 };
 
-// SoC on A's off-diagonal blocks -> min(theta, deg) strongest per node ->
-// union symmetrisation.
-StrongGraph strong_graph(const Level &L, int ntv, int theta, const Q &q, const std::vector<char> &excl) {
-  const HostBSR &A = L.A;
-  const int32_t n = A.n;
-  std::vector<double> sq(n);
-#pragma omp parallel for schedule(static)
-  for (int32_t i = 0; i < n; i++) sq[i] = std::sqrt(node_affinity(L.V.data(), ntv, i, i));
-  std::vector<int32_t> keep((size_t)n * std::max(theta, 1), -1), nkeep(n, 0);
-#pragma omp parallel
-  {
-    std::vector<std::pair<double, int32_t>> sc;
-#pragma omp for schedule(dynamic, 512)
-    for (int32_t i = 0; i < n; i++) {
-      if (excl[i]) continue;
-      sc.clear();
-      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; k++) {
-        const int32_t j = A.ci[k];
-        if (j == i || excl[j]) continue;
-        const int32_t a = std::min(i, j), c = std::max(i, j);
-        const double den = sq[a] * sq[c];
-        const double s = den > 0.0 ? node_affinity(L.V.data(), ntv, a, c) / den : 0.0;
-        if (s > 0.0) sc.emplace_back(q(s), j);
-      }
-      std::sort(sc.begin(), sc.end(), [](const auto &x, const auto &y) {
-        return x.first != y.first ? x.first > y.first : x.second < y.second;
-      });
-      const int kk = std::min<int>(theta, (int)sc.size());
-      for (int a = 0; a < kk; a++) keep[(size_t)i * theta + a] = sc[a].second;
-      nkeep[i] = kk;
-    }
-  }
-  // union: every kept edge both ways, bucketed by row (counts, then a fill in
-  // row order), each row sorted and deduplicated, then compacted
+std::unique_ptr<DevGraph> strong_graph_device(aspamg_ctx *h, const Level &L, const int8_t *dexcl, const double *dV,
+                                              int ntv) {
+  const aspamg_params &p = h->p;
+  const int32_t n = L.A.n;
+  hipStream_t s = h->stream;
+  const int theta = p.theta;
+  Scratch dsq((size_t)n * 8), dkeep((size_t)n * theta * 4), dnk((size_t)n * 4), dcnt((size_t)n * 4);
+  launch_node_norms(n, dV, ntv, dsq.as<double>(), s);
+  launch_strong_topk(L.dA, dexcl, dV, ntv, dsq.as<double>(), theta, p.quant_bits, dkeep.as<int32_t>(),
+                     dnk.as<int32_t>(), s);
+  HIPCHK(hipMemsetAsync(dcnt.p, 0, (size_t)n * 4, s));
+  launch_union(n, theta, dkeep.as<int32_t>(), dnk.as<int32_t>(), 0, dcnt.as<int32_t>(), nullptr, nullptr, nullptr,
+               nullptr, nullptr, nullptr, s);
+  HIPCHK(hipGetLastError());
+  std::vector<int32_t> cnt(n);
+  to_host(s, cnt.data(), dcnt.as<int32_t>(), n);
   std::vector<int64_t> bp((size_t)n + 1, 0);
-  for (int32_t i = 0; i < n; i++)
-    for (int a = 0; a < nkeep[i]; a++) {
-      bp[(size_t)i + 1]++;
-      bp[(size_t)keep[(size_t)i * theta + a] + 1]++;
-    }
-  for (int32_t i = 0; i < n; i++) bp[(size_t)i + 1] += bp[i];
-  std::vector<int32_t> both(bp[n]);
-  {
-    std::vector<int64_t> at(bp.begin(), bp.end() - 1);
-    for (int32_t i = 0; i < n; i++)
-      for (int a = 0; a < nkeep[i]; a++) {
-        const int32_t j = keep[(size_t)i * theta + a];
-        both[at[i]++] = j;
-        both[at[j]++] = i;
-      }
-  }
-  std::vector<int64_t> len(n);
-#pragma omp parallel for schedule(dynamic, 1024)
-  for (int32_t i = 0; i < n; i++) {
-    auto b = both.begin() + bp[i], e = both.begin() + bp[(size_t)i + 1];
-    std::sort(b, e);
-    len[i] = std::unique(b, e) - b;
-  }
-  StrongGraph S;
-  S.rp.assign(n + 1, 0);
-  for (int32_t i = 0; i < n; i++) S.rp[i + 1] = S.rp[i] + len[i];
-  S.ci.resize(S.rp[n]);
-#pragma omp parallel for schedule(static)
-  for (int32_t i = 0; i < n; i++) std::copy(both.begin() + bp[i], both.begin() + bp[i] + len[i], S.ci.begin() + S.rp[i]);
+  for (int32_t i = 0; i < n; i++) bp[(size_t)i + 1] = bp[i] + cnt[i];
+  Scratch dbp(((size_t)n + 1) * 8), dat(((size_t)n + 1) * 8), dboth((size_t)std::max<int64_t>(bp[n], 1) * 4),
+      dlen((size_t)n * 4);
+  to_device(s, dbp.as<int64_t>(), bp.data(), bp.size());
+  to_device(s, dat.as<int64_t>(), bp.data(), bp.size());
+  launch_union(n, theta, dkeep.as<int32_t>(), dnk.as<int32_t>(), 1, nullptr, dbp.as<int64_t>(), dat.as<int64_t>(),
+               dboth.as<int32_t>(), dlen.as<int32_t>(), nullptr, nullptr, s);
+  HIPCHK(hipGetLastError());
+  std::vector<int32_t> len(n);
+  to_host(s, len.data(), dlen.as<int32_t>(), n);
+  std::vector<int64_t> srp((size_t)n + 1, 0);
+  for (int32_t i = 0; i < n; i++) srp[(size_t)i + 1] = srp[i] + len[i];
+  auto S = std::make_unique<DevGraph>((size_t)n + 1, (size_t)std::max<int64_t>(srp[n], 1));
+  to_device(s, S->rp.as<int64_t>(), srp.data(), srp.size());
+  launch_union(n, theta, nullptr, nullptr, 2, nullptr, dbp.as<int64_t>(), nullptr, dboth.as<int32_t>(), nullptr,
+               S->rp.as<int64_t>(), S->ci.as<int32_t>(), s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
   return S;
 }
 
-// Maximal independent set by rounds of local maxima: an undecided node whose
-// key (|S_I|, mix64(I), -I) exceeds the keys of all undecided S-neighbours
-// becomes C; its undecided neighbours become F.  The fixed point is the set
-// the sequential greedy in descending key order produces.
-void mis(const StrongGraph &S, const std::vector<char> &excl, std::vector<int8_t> &cf) {
-  const int32_t n = (int32_t)excl.size();
-  cf.assign(n, 2);
-  std::vector<uint64_t> hk(n);
-  std::vector<int64_t> deg(n);
-  for (int32_t i = 0; i < n; i++) {
-    if (excl[i]) cf[i] = -1;
-    hk[i] = mix64((uint64_t)i);
-    deg[i] = S.rp[i + 1] - S.rp[i];
+// maximal independent set of S in descending (|S_I|, splitmix64(I), -I): local
+// maximum rounds on the device until every node is decided; L.cf on the host
+void mis_device(aspamg_ctx *h, Level &L, const DevGraph &S, const int8_t *dexcl, int8_t *dcf) {
+  const int32_t n = L.A.n;
+  hipStream_t s = h->stream;
+  Scratch dwin((size_t)n), dund(4);
+  launch_mis_init(n, dexcl, dcf, s);
+  for (int round = 0;; round++) {
+    if (round > n) fail(ASPAMG_EHIP, "independent set: no progress");
+    HIPCHK(hipMemsetAsync(dund.p, 0, 4, s));
+    launch_mis_round(n, S.rp.as<int64_t>(), S.ci.as<int32_t>(), dcf, dwin.as<int8_t>(), dund.as<int32_t>(), s);
+    HIPCHK(hipGetLastError());
+    int32_t und = 0;
+    to_host(s, &und, dund.as<int32_t>(), 1);
+    if (und == 0) break;
   }
-  auto greater = [&](int32_t a, int32_t b) {
-    if (deg[a] != deg[b]) return deg[a] > deg[b];
-    if (hk[a] != hk[b]) return hk[a] > hk[b];
-    return a < b;
-  };
-  std::vector<int32_t> und;
-  for (int32_t i = 0; i < n; i++)
-    if (cf[i] == 2) und.push_back(i);
-  while (!und.empty()) {
-    std::vector<char> win(und.size(), 0);
-#pragma omp parallel for schedule(static)
-    for (int64_t a = 0; a < (int64_t)und.size(); a++) {
-      const int32_t i = und[a];
-      bool best = true;
-      for (int64_t k = S.rp[i]; k < S.rp[i + 1]; k++) {
-        const int32_t j = S.ci[k];
-        if (cf[j] == 2 && greater(j, i)) {
-          best = false;
-          break;
-        }
-      }
-      win[a] = best;
-    }
-    for (size_t a = 0; a < und.size(); a++)
-      if (win[a]) cf[und[a]] = 1;
-    for (size_t a = 0; a < und.size(); a++) {
-      if (!win[a]) continue;
-      const int32_t i = und[a];
-      for (int64_t k = S.rp[i]; k < S.rp[i + 1]; k++)
-        if (cf[S.ci[k]] == 2) cf[S.ci[k]] = 0;
-    }
-    std::vector<int32_t> nx;
-    for (int32_t i : und)
-      if (cf[i] == 2) nx.push_back(i);
-    und.swap(nx);
-  }
+  L.cf.resize(n);
+  to_host(s, L.cf.data(), dcf, n);
 }
 
-// ------------------------------------------------------------------------
-// DPLS interpolation pattern (Section 3.5), Householder form of the greedy:
-// after k accepted columns the residual r and the candidates have been
-// reflected k times, so entries k.. of each vector are its part orthogonal to
-// the chosen columns.  Affinity pi^2 / (rho^2 delta^2) with rho^2 = |r_tail|^2,
-// delta^2 = |c_tail|^2, pi = c_tail . r_tail; the largest quantised affinity
-// (> 0, ties to the lowest candidate) is taken unless max|R_kk| / min|R_kk|
-// would exceed kappa_p.  Stops at n_max, rho^2 <= eps_p^2 v.v, or when no
-// candidate is eligible.  Reflection at step k: alpha = -delta (u_k >= 0) or
-// +delta, h = u_tail with h_k -= alpha, x_tail -= (2 h.x_tail / h.h) h.
-// ------------------------------------------------------------------------
-int dpls_select(const double *v, const double *C, int nca, int ntv, const aspamg_params &p, const Q &q,
-                int32_t *chosen, std::vector<double> &Cw, std::vector<char> &used) {
-  double vv = 0.0;
-  for (int t = 0; t < ntv; t++) vv += v[t] * v[t];
-  if (vv == 0.0) return 0;
-  double r[64], hv[64];
-  std::memcpy(r, v, ntv * sizeof(double));
-  Cw.assign(C, C + (size_t)nca * ntv);
-  used.assign(nca, 0);
-  const double thr = q((p.eps_p * p.eps_p) * vv);
-  const int nmax = std::min(p.n_max, kMaxPEntries);
-  double dmax = 0.0, dmin = 0.0;
-  int K = 0;
-  while (K < nmax && K < ntv) {
-    double rho2 = 0.0;
-    for (int t = K; t < ntv; t++) rho2 += r[t] * r[t];
-    if (!(q(rho2) > thr)) break;
-    int best = -1;
-    double bestq = 0.0, bdel2 = 0.0;
-    for (int a = 0; a < nca; a++) {
-      if (used[a]) continue;
-      const double *c = Cw.data() + (size_t)a * ntv;
-      double del2 = 0.0;
-      for (int t = K; t < ntv; t++) del2 += c[t] * c[t];
-      if (!(del2 > 0.0)) continue;
-      double pi = 0.0;
-      for (int t = K; t < ntv; t++) pi += c[t] * r[t];
-      const double qa = q((pi * pi) / (rho2 * del2));
-      if (qa > bestq) {
-        best = a;
-        bestq = qa;
-        bdel2 = del2;
-      }
-    }
-    if (best < 0) break;
-    const double del = std::sqrt(bdel2);
-    const double mx = K ? std::max(dmax, del) : del;
-    const double mn = K ? std::min(dmin, del) : del;
-    if (q(mx / mn) > q(p.kappa_p)) break;
-    const double *u = Cw.data() + (size_t)best * ntv;
-    const double alpha = u[K] >= 0.0 ? -del : del;
-    for (int t = K; t < ntv; t++) hv[t] = u[t];
-    hv[K] = u[K] - alpha;
-    double sh = hv[K] * hv[K];
-    for (int t = K + 1; t < ntv; t++) sh += hv[t] * hv[t];
-    auto reflect = [&](double *x) {
-      double tau = 0.0;
-      for (int t = K; t < ntv; t++) tau += hv[t] * x[t];
-      const double fct = (2.0 * tau) / sh;
-      for (int t = K; t < ntv; t++) x[t] = x[t] - fct * hv[t];
-    };
-    for (int a = 0; a < nca; a++)
-      if (!used[a] && a != best) reflect(Cw.data() + (size_t)a * ntv);
-    reflect(r);
-    dmax = mx;
-    dmin = mn;
-    chosen[K] = best;
-    used[best] = 1;
-    K++;
-  }
-  return K;
-}
-
-void build_prolongation(aspamg_ctx *h, Level &L, const StrongGraph &S) {
+void build_prolongation(aspamg_ctx *h, Level &L, const DevGraph &S, const int8_t *dcf, const double *dV) {
   const aspamg_params &p = h->p;
   const Q q{p.quant_bits};
   const int32_t n = L.A.n;
   const int ntv = h->ntv;
   const int nmax = std::min(p.n_max, kMaxPEntries);
+  hipStream_t s = h->stream;
   L.pcount.assign((size_t)n * 3, 0);
   L.pcols.assign((size_t)n * 3 * p.n_max, -1);
-  // fine scalar row of each chosen entry (for the weight kernel)
+  // interpolation entries of every fine scalar row, chosen on the device
+  std::vector<int32_t> fnodes;
+  for (int32_t I = 0; I < n; I++)
+    if (L.cf[I] == 0) fnodes.push_back(I);
   std::vector<int32_t> selfine((size_t)n * 3 * kMaxPEntries, 0);
-#pragma omp parallel
   {
-    std::vector<int32_t> dist(n, -1), frontier, cn;
-    std::vector<double> Cm, Cw;
-    std::vector<char> used;
-    std::vector<int32_t> visited;
-#pragma omp for schedule(dynamic, 256)
-    for (int32_t I = 0; I < n; I++) {
-      if (L.cf[I] != 0) continue;
-      // C nodes within S-distance d_p
-      frontier.clear();
-      cn.clear();
-      frontier.push_back(I);
-      dist[I] = 0;
-      for (size_t head = 0; head < frontier.size(); head++) {
-        const int32_t u = frontier[head];
-        if (dist[u] >= p.d_p) continue;
-        for (int64_t k = S.rp[u]; k < S.rp[u + 1]; k++) {
-          const int32_t w = S.ci[k];
-          if (dist[w] >= 0) continue;
-          dist[w] = dist[u] + 1;
-          frontier.push_back(w);
-          if (L.cf[w] == 1) cn.push_back(w);
-        }
-      }
-      for (int32_t u : frontier) dist[u] = -1;
-      std::sort(cn.begin(), cn.end());
-      const int nca = (int)cn.size() * 3;
-      Cm.resize((size_t)std::max(nca, 1) * ntv);
-      for (size_t c = 0; c < cn.size(); c++)
-        for (int e = 0; e < 3; e++)
-          std::memcpy(Cm.data() + (c * 3 + e) * ntv, L.V.data() + ((size_t)cn[c] * 3 + e) * ntv, ntv * sizeof(double));
-      for (int d = 0; d < 3; d++) {
-        int32_t chosen[kMaxPEntries];
-        const int K = dpls_select(L.V.data() + ((size_t)I * 3 + d) * ntv, Cm.data(), nca, ntv, p, q, chosen, Cw, used);
-        const size_t r = (size_t)I * 3 + d;
-        L.pcount[r] = K;
-        for (int k = 0; k < K; k++) {
-          const int32_t J = cn[chosen[k] / 3], e = chosen[k] % 3;
-          L.pcols[r * p.n_max + k] = L.cidx[J] * 3 + e;
-          selfine[r * kMaxPEntries + k] = J * 3 + e;
-        }
-      }
-    }
+    Scratch dfn(fnodes.size() * 4), dcnt((size_t)n * 3 * 4), dsel(selfine.size() * 4), derr(4);
+    to_device(s, dfn.as<int32_t>(), fnodes.data(), fnodes.size());
+    HIPCHK(hipMemsetAsync(dcnt.p, 0, (size_t)n * 3 * 4, s));
+    HIPCHK(hipMemsetAsync(dsel.p, 0, selfine.size() * 4, s));
+    HIPCHK(hipMemsetAsync(derr.p, 0, 4, s));
+    launch_dpls_rows((int32_t)fnodes.size(), dfn.as<int32_t>(), S.rp.as<int64_t>(), S.ci.as<int32_t>(), dcf, dV, ntv,
+                     p.d_p, nmax, q(p.kappa_p), p.eps_p, p.quant_bits, dcnt.as<int32_t>(), dsel.as<int32_t>(),
+                     derr.as<int32_t>(), s);
+    HIPCHK(hipGetLastError());
+    int32_t err = 0;
+    to_host(s, &err, derr.as<int32_t>(), 1);
+    if (err)
+      fail(ASPAMG_EINVAL, "DPLS: a fine node has more interpolation candidates than the device selection holds "
+                          "(1024 nodes within distance d_p, 320 coarse ones, 5120 candidate values)");
+    to_host(s, L.pcount.data(), dcnt.as<int32_t>(), (size_t)n * 3);
+    to_host(s, selfine.data(), dsel.as<int32_t>(), selfine.size());
   }
-  (void)nmax;
+  for (size_t r = 0; r < (size_t)n * 3; r++)
+    for (int k = 0; k < L.pcount[r]; k++) {
+      const int32_t f = selfine[r * kMaxPEntries + k];
+      L.pcols[r * p.n_max + k] = L.cidx[f / 3] * 3 + f % 3;
+    }
   // weights on the GPU: normal equations of the chosen columns
   std::vector<int32_t> rows, cnt, sel;
   for (int64_t r = 0; r < (int64_t)n * 3; r++) {
@@ -1025,14 +855,12 @@ void build_prolongation(aspamg_ctx *h, Level &L, const StrongGraph &S) {
   }
   std::vector<double> w((size_t)rows.size() * kMaxPEntries, 0.0);
   if (!rows.empty()) {
-    Scratch dr(rows.size() * 4), dc(cnt.size() * 4), ds(sel.size() * 4), dV(L.V.size() * 8),
-        dw(w.size() * 8);
+    Scratch dr(rows.size() * 4), dc(cnt.size() * 4), ds(sel.size() * 4), dw(w.size() * 8);
     to_device(h->stream, dr.as<int32_t>(), rows.data(), rows.size());
     to_device(h->stream, dc.as<int32_t>(), cnt.data(), cnt.size());
     to_device(h->stream, ds.as<int32_t>(), sel.data(), sel.size());
-    to_device(h->stream, dV.as<double>(), L.V.data(), L.V.size());
-    launch_dpls_weights((int32_t)rows.size(), dr.as<int32_t>(), dc.as<int32_t>(), ds.as<int32_t>(), dV.as<double>(),
-                        ntv, dw.as<double>(), h->stream);
+    launch_dpls_weights((int32_t)rows.size(), dr.as<int32_t>(), dc.as<int32_t>(), ds.as<int32_t>(), dV, ntv,
+                        dw.as<double>(), h->stream);
     HIPCHK(hipGetLastError());
     to_host(h->stream, w.data(), dw.as<double>(), w.size());
     for (size_t i = 0; i < rows.size(); i++)
@@ -1332,10 +1160,13 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
       clk.tick(l, "test space");
     }
     orthonormalize(L.V, (int64_t)N * 3, ntv);
-    std::vector<char> excl(N);
+    std::vector<int8_t> excl(N);
     for (int32_t i = 0; i < N; i++) excl[i] = is_decoupled(L.A, i);
-    StrongGraph S = strong_graph(L, ntv, p.theta, q, excl);
-    mis(S, excl, L.cf);
+    Scratch dexcl((size_t)N), dV(L.V.size() * 8), dcf((size_t)N);
+    to_device(h->stream, dexcl.as<int8_t>(), excl.data(), excl.size());
+    to_device(h->stream, dV.as<double>(), L.V.data(), L.V.size());
+    std::unique_ptr<DevGraph> S = strong_graph_device(h, L, dexcl.as<int8_t>(), dV.as<double>(), ntv);
+    mis_device(h, L, *S, dexcl.as<int8_t>(), dcf.as<int8_t>());
     clk.tick(l, "coarsening");
     L.cidx.assign(N, -1);
     int32_t nc = 0, nF = 0;
@@ -1349,7 +1180,8 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
       L.coarsest = true;
       break;
     }
-    build_prolongation(h, L, S);
+    build_prolongation(h, L, *S, dcf.as<int8_t>(), dV.as<double>());
+    S.reset();
     clk.tick(l, "DPLS");
     HostBSR AP;              // pattern of A P
     double *dPAP = nullptr;  // [P; A P] block values, on the device
