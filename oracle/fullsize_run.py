@@ -9,10 +9,13 @@ Writes
       the block patterns of A, G and P; of the block values of A, G and P when
       both implementations compute them in the same order (n_rq = 0); with the
       SRQCG test space (inner products summed in different orders on the two
-      sides) the values of 48 seeded sampled block rows per level instead;
+      sides) the leading values of 8 seeded sampled block rows per level
+      instead;
   profiles/oracle_<name>_fullsize.json  the oracle's setup time and the time of
       its PCG iterations on this hierarchy, single-threaded and with its OpenMP
-      row loops on every host core (host CPU, core count, git revision).
+      row loops on every host core (host CPU, core count, git revision), and the
+      same timing of the benchmark's bounded sample on this host
+      (oracle/baseline_sample.py), which relates the benchmark host to this one.
 Only oracle/ and the seeded input generator are called; nothing here reads a
 GPU result.
 """
@@ -35,7 +38,9 @@ ROOT = os.path.dirname(HERE)
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-N_SAMPLE_ROWS = 48
+N_SAMPLE_DRAW = 48       # rows drawn per level (seeded) ...
+SAMPLE_STRIDE = 6        # ... of which every sixth is stored
+MAX_ROW_BLOCKS = 24      # leading blocks of a stored row
 
 
 def sha(*arrays) -> str:
@@ -47,11 +52,26 @@ def sha(*arrays) -> str:
 
 def sample_rows(n: int, level: int) -> np.ndarray:
     rng = np.random.default_rng(1000 + level)
-    return np.sort(rng.choice(n, size=min(n, N_SAMPLE_ROWS), replace=False))
+    return np.sort(rng.choice(n, size=min(n, N_SAMPLE_DRAW), replace=False))[::SAMPLE_STRIDE]
 
 
 def row_values(M, rows):
-    return [M.v[M.rp[i]:M.rp[i + 1]].reshape(-1).tolist() for i in rows]
+    return [M.v[M.rp[i]:min(M.rp[i + 1], M.rp[i] + MAX_ROW_BLOCKS)].reshape(-1).tolist() for i in rows]
+
+
+def shrink(golden):
+    """Reduce a record written with every drawn row and whole rows to the
+    stored form (every SAMPLE_STRIDE-th drawn row, MAX_ROW_BLOCKS leading
+    blocks)."""
+    for rec in golden["levels"]:
+        if "sample_rows" not in rec or len(rec["sample_rows"]) <= N_SAMPLE_DRAW // SAMPLE_STRIDE:
+            continue
+        rec["sample_rows"] = rec["sample_rows"][::SAMPLE_STRIDE]
+        for key in ("A_rows", "G_rows", "P_rows"):
+            if key in rec:
+                rec[key] = [r[:9 * MAX_ROW_BLOCKS] for r in rec[key][::SAMPLE_STRIDE]]
+    golden["max_row_blocks"] = MAX_ROW_BLOCKS
+    return golden
 
 
 def fingerprint(H, bitwise_values: bool) -> list:
@@ -108,7 +128,27 @@ def main():
     ap.add_argument("config", choices=["c2", "c3"])
     ap.add_argument("--n-rq", type=int, default=0)
     ap.add_argument("--iters", type=int, default=10, help="PCG iterations timed per thread count")
+    ap.add_argument("--sample-only", action="store_true",
+                    help="only time the benchmark's bounded sample on this host and add it to the record")
+    ap.add_argument("--shrink", action="store_true",
+                    help="only reduce an existing fingerprint record to the stored form")
     args = ap.parse_args()
+    tag = args.config if args.n_rq == 0 else f"{args.config}_srqcg"
+    ppath = os.path.join(ROOT, "profiles", f"oracle_{tag}_fullsize.json")
+    gpath = os.path.join(ROOT, "tests", "golden", f"{tag}_hierarchy.json")
+    if args.shrink:
+        golden = shrink(json.load(open(gpath)))
+        with open(gpath, "w") as fh:
+            json.dump(golden, fh, indent=1)
+        return
+    if args.sample_only:
+        from oracle.baseline_sample import time_sample
+        rec = json.load(open(ppath))
+        rec["sample"] = time_sample(args.config, args.n_rq)
+        with open(ppath, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec["sample"]), flush=True)
+        return
 
     import oracle
     from paper_1902_01715_amd import problems as PR
@@ -132,13 +172,11 @@ def main():
     levels = [H.info(l)["n"] for l in range(H.nlev)]
     print(f"[oracle {args.config}] setup {t_setup:.1f} s, levels {levels}", flush=True)
 
-    tag = args.config if args.n_rq == 0 else f"{args.config}_srqcg"
     golden = {"config": args.config, "n_rq": args.n_rq, "n_tv": int(V0.shape[-1]),
               "test_space": "rigid-body modes" if args.n_rq == 0 else
               "rigid-body modes + 4 seeded normal columns (initial_test_space(p, 10, 11))",
               "bitwise_values": args.n_rq == 0, "levels": fingerprint(H, args.n_rq == 0),
-              "written_by": "oracle/fullsize_run.py", "git": git_rev()}
-    gpath = os.path.join(ROOT, "tests", "golden", f"{tag}_hierarchy.json")
+              "max_row_blocks": MAX_ROW_BLOCKS, "written_by": "oracle/fullsize_run.py", "git": git_rev()}
     with open(gpath, "w") as fh:
         json.dump(golden, fh, indent=1)
     print(f"[oracle {args.config}] wrote {gpath}", flush=True)
@@ -160,7 +198,10 @@ def main():
            "git": git_rev(), "written_by": "oracle/fullsize_run.py",
            "note": "PCG iterations with rtol 0 (exactly the stated count) on the oracle's own hierarchy; "
                    "row loops of the block products and vector updates on the stated threads"}
-    ppath = os.path.join(ROOT, "profiles", f"oracle_{tag}_fullsize.json")
+    del H
+    oracle.use_library(None)
+    from oracle.baseline_sample import time_sample
+    rec["sample"] = time_sample(args.config, args.n_rq)
     with open(ppath, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(f"[oracle {args.config}] wrote {ppath}", flush=True)

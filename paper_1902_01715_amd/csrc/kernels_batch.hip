@@ -380,6 +380,25 @@ static int spmm_wgs(int32_t n, int kb, int split, int cpt, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(groups, cap));
 }
 
+// Workgroups of one instantiation that the device holds at once (its compute
+// units times the occupancy the kernel's LDS and registers allow), looked up
+// once per instantiation.  A grid of exactly that many workgroups walks each
+// XCD's row groups as one contiguous front; more workgroups than fit would
+// each jump through the range in strides of the grid and scatter the rows in
+// flight, whose gathered x rows then miss L2.
+template <typename T, bool HAS_W, bool DOT, int KB, int S>
+static int spmm_resident() {
+  static int cached = 0;
+  if (!cached) {
+    int dev = 0, cus = 0, per = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsr_spmm<T, HAS_W, DOT, KB, S>, 256, 0));
+    cached = std::max(8, cus * std::max(per, 1));
+  }
+  return cached;
+}
+
 template <typename T, bool HAS_W, bool DOT, int KB, int S>
 static void spmm_ks(const DevBSRT<T> &A, const T *X, T *Y, const T *W, int ld, double alpha, double *part,
                     const BatchCtrl *c, hipStream_t s) {
@@ -387,7 +406,8 @@ static void spmm_ks(const DevBSRT<T> &A, const T *X, T *Y, const T *W, int ld, d
   // every lane loads and stores CPT columns as one 16-byte vector
   const uintptr_t mis = (uintptr_t)X | (uintptr_t)Y | (uintptr_t)W;
   if ((mis & 15) != 0 || ld % CPT != 0) fail(ASPAMG_EINVAL, "SpMM operands must be 16-byte aligned column tiles");
-  dim3 grid((unsigned)spmm_wgs(A.n, KB, S, CPT, DOT ? kBatchParts : 4096), ld / KB);
+  const int cap = std::min(DOT ? kBatchParts : 4096, spmm_resident<T, HAS_W, DOT, KB, S>() / (ld / KB));
+  dim3 grid((unsigned)spmm_wgs(A.n, KB, S, CPT, std::max(cap, 8)), ld / KB);
   hipLaunchKernelGGL((k_bsr_spmm<T, HAS_W, DOT, KB, S>), grid, dim3(256), 0, s, A.n, A.rp, A.ci, A.v, X, Y, W, ld,
                      (T)alpha, part, c);
 }
@@ -434,9 +454,31 @@ void launch_spmm_dot(const DevBSRT<double> &A, const double *X, double *Y, int l
   kb = kb > ld ? ld : kb;
   spmm_any<double, false, true>(A, X, Y, nullptr, ld, kb, 1.0, part, c, s);
 }
+// workgroups (= partial slots) of launch_spmm_dot's grid, as spmm_ks sizes it
+template <int KB, int S>
+static int dot_grid(const DevBSRT<double> &A, int ld) {
+  const int cap = std::min(kBatchParts, spmm_resident<double, false, true, KB, S>() / (ld / KB));
+  return spmm_wgs(A.n, KB, S, 16 / (int)sizeof(double), std::max(cap, 8));
+}
+template <int KB>
+static int dot_grid_k(const DevBSRT<double> &A, int ld) {
+  switch (A.split) {
+    case 1: return dot_grid<KB, 1>(A, ld);
+    case 2: return dot_grid<KB, 2>(A, ld);
+    case 4: return dot_grid<KB, 4>(A, ld);
+    case 8: return dot_grid<KB, 8>(A, ld);
+  }
+  fail(ASPAMG_EINVAL, "SpMM row split must be 1, 2, 4 or 8");
+}
 int spmm_dot_parts(const DevBSRT<double> &A, int ld, int kb) {
   kb = kb > ld ? ld : kb;
-  return spmm_wgs(A.n, kb, A.split, 16 / (int)sizeof(double), kBatchParts);
+  switch (kb) {
+    case 4: return dot_grid_k<4>(A, ld);
+    case 8: return dot_grid_k<8>(A, ld);
+    case 16: return dot_grid_k<16>(A, ld);
+    case 32: return dot_grid_k<32>(A, ld);
+  }
+  fail(ASPAMG_EINVAL, "SpMM tile must be 4, 8, 16 or 32 columns");
 }
 
 template <typename T>

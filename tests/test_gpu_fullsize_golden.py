@@ -10,8 +10,9 @@ configuration bench.py times, and every level is compared:
   - C2 (n_rq = 0, both sides sum in the same order): the block values of A, G
     and P bit for bit as well;
   - C3 with SRQCG (its inner products are summed in different orders on the
-    two sides, so the test spaces agree to rounding only): the values of 48
-    seeded sampled block rows per level, to 1e-8 of the row's largest entry.
+    two sides, so the test spaces agree to rounding only): the leading values
+    of 8 seeded sampled block rows per level, to 1e-8 of the row's largest
+    stored entry.
 """
 import hashlib
 import json
@@ -78,8 +79,9 @@ def test_fullsize_hierarchy_matches_oracle_fingerprints(tag, cuda):
             if not g["bitwise_values"]:
                 for name, M in mats.items():
                     rp, v = M[0], M[2]
+                    nb = g.get("max_row_blocks", 1 << 30)
                     for i, ref in zip(rec["sample_rows"], rec[f"{name}_rows"]):
-                        got = v[rp[i]:rp[i + 1]].reshape(-1)
+                        got = v[rp[i]:min(rp[i + 1], rp[i] + nb)].reshape(-1)
                         ref = np.asarray(ref)
                         assert got.shape == ref.shape, (l, name, i)
                         scale = max(np.abs(ref).max(), 1e-300)
