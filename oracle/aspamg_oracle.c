@@ -216,6 +216,22 @@ static double dot(const double *a, const double *b, int64_t n) {
   return s;
 }
 
+/* The inner products of the test-space iteration in one fixed order: the
+ * entries in consecutive blocks of 256, each block summed from its first
+ * entry, then the block sums from the first block on.  x and y are read with
+ * strides sx, sy (columns of a row-major multi-vector). */
+#define ODOT_BLOCK 256
+static double dotb(const double *x, int64_t sx, const double *y, int64_t sy, int64_t n) {
+  double s = 0.0;
+  for (int64_t b0 = 0; b0 < n; b0 += ODOT_BLOCK) {
+    const int64_t b1 = b0 + ODOT_BLOCK < n ? b0 + ODOT_BLOCK : n;
+    double t = 0.0;
+    for (int64_t i = b0; i < b1; i++) t += x[i * sx] * y[i * sy];
+    s += t;
+  }
+  return s;
+}
+
 /* ------------------------------------------------------------------------- */
 /* small dense Cholesky, left-looking, sums in ascending k:                    */
 /*   L_jj = sqrt(M_jj - sum_{k<j} L_jk^2),  L_ij = (M_ij - sum_{k<j} L_ik L_jk)/L_jj */
@@ -599,6 +615,8 @@ static int orthonormalize(double *V, int64_t nrows, int ntv) {
 /*     it enters as G^{-T} V0: Z0 = (I - S) G^{-T} V0.  On an unconstrained K   */
 /*     with V0 the rigid-body modes, S G^{-T} V0 = G A V0 = 0 and the modes      */
 /*     come back unchanged;                                                    */
+/*   - every inner product is summed in the fixed order of dotb (blocks of 256  */
+/*     entries), the same order the device uses;                               */
 /*   - q is the Rayleigh quotient z^T S z / z^T z; f_i starts at 1 and is set   */
 /*     to z_i^T z_i after each update of column i (not after a projection);     */
 /*   - S Z is formed by products at every projection and then carried:         */
@@ -696,13 +714,8 @@ static int ritz_vectors(const double *Z, const double *SZ, int64_t nr, int nt, d
   double Ms[64 * 64], Mz[64 * 64], L[64 * 64], C[64 * 64], T[64 * 64], X[64 * 64], w[64];
   for (int a = 0; a < nt; a++)
     for (int c = 0; c < nt; c++) {
-      double s1 = 0.0, s2 = 0.0;
-      for (int64_t i = 0; i < nr; i++) {
-        s1 += Z[i * nt + a] * SZ[i * nt + c];
-        s2 += Z[i * nt + a] * Z[i * nt + c];
-      }
-      Ms[a * nt + c] = s1;
-      Mz[a * nt + c] = s2;
+      Ms[a * nt + c] = dotb(Z + a, nt, SZ + c, nt, nr);
+      Mz[a * nt + c] = dotb(Z + a, nt, Z + c, nt, nr);
     }
   for (int a = 0; a < nt; a++)          /* symmetric parts */
     for (int c = 0; c < a; c++) {
@@ -771,7 +784,7 @@ static int srqcg(const obsr *A, const obsr *G, double *V, int nt, int kmax, int 
   for (int c = 0; c < nt; c++) {
     for (int64_t i = 0; i < nr; i++) x[i] = Z[i * nt + c];
     apply_gagt(A, G, &GT, x, y, t1, t2);
-    double e = dot(x, y, nr), ff = dot(x, x, nr);
+    double e = dotb(x, 1, y, 1, nr), ff = dotb(x, 1, x, 1, nr);
     double q = ff > 0.0 ? e / ff : 0.0;
     for (int64_t i = 0; i < nr; i++) {
       SZ[i * nt + c] = y[i];
@@ -806,45 +819,31 @@ static int srqcg(const obsr *A, const obsr *G, double *V, int nt, int kmax, int 
       /* column c: z = Z_c, p = P_c, sz = (S Z)_c, sp = S p */
       for (int64_t i = 0; i < nr; i++) x[i] = Pd[i * nt + c];
       apply_gagt(A, G, &GT, x, sp, t1, t2);
-      double a = 0.0, b = 0.0, cc = 0.0, d = 0.0, e = 0.0;
-      for (int64_t i = 0; i < nr; i++) {
-        const double pi = Pd[i * nt + c], zi = Z[i * nt + c], szi = SZ[i * nt + c];
-        a += pi * szi;
-        b += pi * sp[i];
-        cc += pi * zi;
-        d += pi * pi;
-        e += zi * szi;
-      }
+      const double *pc = Pd + c, *zc = Z + c, *szc = SZ + c;
+      const double a = dotb(pc, nt, szc, nt, nr), b = dotb(pc, nt, sp, 1, nr), cc = dotb(pc, nt, zc, nt, nr),
+                   d = dotb(pc, nt, pc, nt, nr), e = dotb(zc, nt, szc, nt, nr);
       const double fi = f[c];
       const double den = 2.0 * (b * cc - a * d);
       const double u1 = d * e - b * fi;
       const double delta = u1 * u1 - 4.0 * (b * cc - a * d) * (a * fi - cc * e);
       if (!(den != 0.0) || !(delta >= 0.0)) continue;
       const double alpha = (u1 + sqrt(delta)) / den;   /* minimiser of the quotient on z + alpha p */
-      double zz = 0.0, zsz = 0.0;
       for (int64_t i = 0; i < nr; i++) {
         Z[i * nt + c] += alpha * Pd[i * nt + c];
         SZ[i * nt + c] += alpha * sp[i];
       }
-      for (int64_t i = 0; i < nr; i++) {
-        zz += Z[i * nt + c] * Z[i * nt + c];
-        zsz += Z[i * nt + c] * SZ[i * nt + c];
-      }
+      const double zz = dotb(Z + c, nt, Z + c, nt, nr), zsz = dotb(Z + c, nt, SZ + c, nt, nr);
       f[c] = zz;
       const double q = zsz / zz;
       /* gradient of the quotient, g = 2 (S z - q z) / f, and the new direction */
       for (int64_t i = 0; i < nr; i++) g[i] = 2.0 * (SZ[i * nt + c] - q * Z[i * nt + c]) / zz;
-      const double beta = -dot(g, sp, nr) / b;
+      const double beta = -dotb(g, 1, sp, 1, nr) / b;
       for (int64_t i = 0; i < nr; i++) Pd[i * nt + c] = g[i] + beta * Pd[i * nt + c];
     }
   }
   if (rq)
     for (int c = 0; c < nt; c++) {
-      double zz = 0.0, zsz = 0.0;
-      for (int64_t i = 0; i < nr; i++) {
-        zz += Z[i * nt + c] * Z[i * nt + c];
-        zsz += Z[i * nt + c] * SZ[i * nt + c];
-      }
+      const double zz = dotb(Z + c, nt, Z + c, nt, nr), zsz = dotb(Z + c, nt, SZ + c, nt, nr);
       rq[c] = zz > 0.0 ? zsz / zz : 0.0;
     }
   /* V = G^T Z */

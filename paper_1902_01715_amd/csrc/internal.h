@@ -315,6 +315,11 @@ void launch_divided(int64_t n, double a, const double *x, double *y, hipStream_t
 // test-space iteration: out = 2 (sz - q z) / f; y = x + b y; Y = X U (columns of n entries, U nt x nt row-major)
 void launch_rq_gradient(int64_t n, double q, double f, const double *sz, const double *z, double *out, hipStream_t s);
 void launch_xpby(int64_t n, const double *x, double b, double *y, hipStream_t s);
+// inner-product partials of 256-entry blocks (dot256_parts of them), each
+// summed sequentially; y = M x with each row summed sequentially in stored order
+int dot256_parts(int64_t n);
+void launch_dot256(int64_t n, const double *a, const double *b, double *part, hipStream_t s);
+void launch_bsr_mv_seq(const DevBSR &M, const double *x, double *y, hipStream_t s);
 void launch_combine_columns(int64_t n, int nt, const double *X, const double *U, double *Y, hipStream_t s);
 // layout values: slot i takes the 9 values of block map[i] of v (zeros when map[i] < 0)
 template <typename T>

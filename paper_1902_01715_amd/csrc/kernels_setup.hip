@@ -533,6 +533,46 @@ __global__ void __launch_bounds__(256) k_rq_gradient(int64_t n, double q, double
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     out[i] = 2.0 * (sz[i] - q * z[i]) / f;
 }
+// Partial inner products in the test-space iteration's fixed order: entry
+// block b (256 consecutive entries) summed from its first entry by one
+// thread; the host adds the block sums from the first block on.
+__global__ void __launch_bounds__(256) k_dot256(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                                               double *__restrict__ part) {
+  const int64_t blk = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i0 = blk * 256;
+  if (i0 >= n) return;
+  const int64_t i1 = i0 + 256 < n ? i0 + 256 : n;
+  double s = 0.0;
+  for (int64_t i = i0; i < i1; i++) s += a[i] * b[i];
+  part[blk] = s;
+}
+
+// y = M x on a plain block CSR, one thread per block row, each row's
+// components summed over its blocks in stored order (the sequential product)
+__global__ void __launch_bounds__(256) k_bsr_mv_seq(int32_t n, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                   const double *__restrict__ x, double *__restrict__ y) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+    const double *B = v + (size_t)k * 9;
+    const double *xx = x + (size_t)ci[k] * 3;
+    a0 += B[0] * xx[0];
+    a0 += B[1] * xx[1];
+    a0 += B[2] * xx[2];
+    a1 += B[3] * xx[0];
+    a1 += B[4] * xx[1];
+    a1 += B[5] * xx[2];
+    a2 += B[6] * xx[0];
+    a2 += B[7] * xx[1];
+    a2 += B[8] * xx[2];
+  }
+  y[(size_t)i * 3] = a0;
+  y[(size_t)i * 3 + 1] = a1;
+  y[(size_t)i * 3 + 2] = a2;
+}
+
 // y = x + b y
 __global__ void __launch_bounds__(256) k_xpby(int64_t n, const double *__restrict__ x, double b,
                                               double *__restrict__ y) {
@@ -598,6 +638,15 @@ void launch_divided(int64_t n, double a, const double *x, double *y, hipStream_t
 void launch_rq_gradient(int64_t n, double q, double f, const double *sz, const double *z, double *out,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_rq_gradient, dim3(setup_vec_blocks(n)), dim3(256), 0, s, n, q, f, sz, z, out);
+}
+int dot256_parts(int64_t n) { return (int)((n + 255) / 256); }
+void launch_dot256(int64_t n, const double *a, const double *b, double *part, hipStream_t s) {
+  const int64_t nb = dot256_parts(n);
+  hipLaunchKernelGGL(k_dot256, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, n, a, b, part);
+}
+void launch_bsr_mv_seq(const DevBSR &M, const double *x, double *y, hipStream_t s) {
+  if (M.n == 0) return;
+  hipLaunchKernelGGL(k_bsr_mv_seq, dim3((M.n + 255) / 256), dim3(256), 0, s, M.n, M.rp, M.ci, M.v, x, y);
 }
 void launch_xpby(int64_t n, const double *x, double b, double *y, hipStream_t s) {
   hipLaunchKernelGGL(k_xpby, dim3(setup_vec_blocks(n)), dim3(256), 0, s, n, x, b, y);

@@ -623,23 +623,46 @@ void srqcg(aspamg_ctx *h, Level &L, int nt, int kmax) {
   const int64_t n = (int64_t)L.A.n * 3;
   const size_t cols = (size_t)n * nt;
   hipStream_t s = h->stream;
-  const int nb = vec_blocks(n);
+  // inner products in the fixed order of 256-entry blocks and products summed
+  // row by row in stored order, as the sequential definition sums them: the
+  // test space, and every decision that depends on it, is then bitwise the
+  // sequential one
+  const int nb = dot256_parts(n);
   Scratch dZ(cols * 8), dSZ(cols * 8), dP(cols * 8), dW(cols * 8), dsp(n * 8), dg(n * 8), dt1(n * 8), dt2(n * 8),
       dU((size_t)nt * nt * 8), dpart((size_t)nb * std::max(5, 2 * nt * nt) * 8);
   double *Z = dZ.as<double>(), *SZ = dSZ.as<double>(), *Pd = dP.as<double>(), *W = dW.as<double>();
   double *sp = dsp.as<double>(), *g = dg.as<double>(), *part = dpart.as<double>();
   auto C = [n](double *M, int c) { return M + (size_t)c * n; };
+  // plain block-CSR copies of G and G^T for the sequential products (A's is L.dA)
+  const HostBSR GT = transpose(L.G);
+  struct Plain {
+    Scratch rp, ci, v;
+    DevBSR d;
+    Plain(hipStream_t s, const HostBSR &M)
+        : rp(((size_t)M.n + 1) * 4), ci(std::max<size_t>(M.ci.size(), 1) * 4), v(std::max<size_t>(M.v.size(), 1) * 8) {
+      std::vector<int32_t> rp32(M.rp.begin(), M.rp.end());
+      to_device(s, rp.as<int32_t>(), rp32.data(), rp32.size());
+      to_device(s, ci.as<int32_t>(), M.ci.data(), M.ci.size());
+      to_device(s, v.as<double>(), M.v.data(), M.v.size());
+      d.n = M.n;
+      d.nc = M.nc;
+      d.nnzb = M.nnzb();
+      d.rp = rp.as<int32_t>();
+      d.ci = ci.as<int32_t>();
+      d.v = v.as<double>();
+    }
+  } pG(s, L.G), pGT(s, GT);
   auto apply_s = [&](const double *x, double *y) {
-    launch_spmv<double, double, double>(L.GT64, x, dt1.as<double>(), nullptr, 1.0, nullptr, s);
-    launch_spmv<double, double, double>(L.A64, dt1.as<double>(), dt2.as<double>(), nullptr, 1.0, nullptr, s);
-    launch_spmv<double, double, double>(L.G64, dt2.as<double>(), y, nullptr, 1.0, nullptr, s);
+    launch_bsr_mv_seq(pGT.d, x, dt1.as<double>(), s);
+    launch_bsr_mv_seq(L.dA, dt1.as<double>(), dt2.as<double>(), s);
+    launch_bsr_mv_seq(pG.d, dt2.as<double>(), y, s);
   };
   std::vector<double> hp;
   using Pair = std::pair<const double *, const double *>;
   const size_t max_pairs = (size_t)std::max(5, 2 * nt * nt);
   auto dots = [&](const std::vector<Pair> &pr) {
     if (pr.size() > max_pairs) fail(ASPAMG_EINVAL, "srqcg: too many inner products in one batch");
-    for (size_t k = 0; k < pr.size(); k++) launch_dot(n, pr[k].first, pr[k].second, part + k * nb, nullptr, s);
+    for (size_t k = 0; k < pr.size(); k++) launch_dot256(n, pr[k].first, pr[k].second, part + k * nb, s);
     HIPCHK(hipGetLastError());
     hp.resize(pr.size() * nb);
     to_host(s, hp.data(), part, pr.size() * nb);
@@ -732,7 +755,7 @@ void srqcg(aspamg_ctx *h, Level &L, int nt, int kmax) {
     }
   }
   // V = G^T Z
-  for (int c = 0; c < nt; c++) launch_spmv<double, double, double>(L.GT64, C(Z, c), C(W, c), nullptr, 1.0, nullptr, s);
+  for (int c = 0; c < nt; c++) launch_bsr_mv_seq(pGT.d, C(Z, c), C(W, c), s);
   HIPCHK(hipGetLastError());
   to_rows(W, L.V);
 }
