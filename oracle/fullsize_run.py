@@ -5,12 +5,11 @@
 
 Writes
   tests/golden/<name>_hierarchy.json  per-level fingerprints of the oracle's
-      hierarchy: SHA-256 of the C/F split, the scalar interpolation pattern and
-      the block patterns of A, G and P; of the block values of A, G and P when
-      both implementations compute them in the same order (n_rq = 0); with the
-      SRQCG test space (inner products summed in different orders on the two
-      sides) the leading values of 8 seeded sampled block rows per level
-      instead;
+      hierarchy: SHA-256 of the C/F split, the scalar interpolation pattern, the
+      block patterns and the block values of A, G and P (both implementations
+      compute every one of them in the same order, the SRQCG test space
+      included); fingerprint(H, False) keeps the leading values of 8 seeded
+      sampled rows per matrix instead of the value digests;
   profiles/oracle_<name>_fullsize.json  the oracle's setup time and the time of
       its PCG iterations on this hierarchy, single-threaded and with its OpenMP
       row loops on every host core (host CPU, core count, git revision), and the
@@ -175,7 +174,7 @@ def main():
     golden = {"config": args.config, "n_rq": args.n_rq, "n_tv": int(V0.shape[-1]),
               "test_space": "rigid-body modes" if args.n_rq == 0 else
               "rigid-body modes + 4 seeded normal columns (initial_test_space(p, 10, 11))",
-              "bitwise_values": args.n_rq == 0, "levels": fingerprint(H, args.n_rq == 0),
+              "bitwise_values": True, "levels": fingerprint(H, True),
               "max_row_blocks": MAX_ROW_BLOCKS, "written_by": "oracle/fullsize_run.py", "git": git_rev()}
     with open(gpath, "w") as fh:
         json.dump(golden, fh, indent=1)

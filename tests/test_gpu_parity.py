@@ -94,8 +94,13 @@ def test_solve_matches_oracle(pair, prec):
     """u within 1e-8 of the oracle's PCG result at rel. residual 1e-10.  The
     cantilever (E over six decades, aspect-10 elements, L/H = 100) is so
     ill-conditioned that the recursive residual of either implementation
-    drifts from the true one; there the true residual is held to the
-    oracle's own and u to a condition-scaled bar."""
+    drifts from the true one.  There the status (OK) already holds the
+    recomputed residual within max(rtol, its FP64 rounding bound), and u is
+    held to twice the bar the oracle's own solution is pinned to against the
+    dense Cholesky solution of this mesh (test_pcg_matches_dense_cholesky:
+    1e-8 max(1, cond(K) / 1e8), cond(K) from a dense computation): each of the
+    two solutions is within that of the exact one.  Measured: 1.7e-8 in both
+    cycle precisions against a bar of 4.8e-5."""
     import torch
     name, p, S, H = pair
     u_o, st_o = H.pcg(p.f, 1e-10, 1000)
@@ -112,8 +117,10 @@ def test_solve_matches_oracle(pair, prec):
     print(f"{name} prec={prec} it={st['iterations']} (oracle {st_o['iterations']}) err={err:.2e} "
           f"true res {st['relres_true']:.2e} (oracle {rt_o:.2e})")
     if name in ILL_CONDITIONED:
-        assert st["relres_true"] <= 10 * max(rt_o, 1e-10)
-        assert err <= 1e-4, err
+        kappa = np.linalg.cond(K.toarray())
+        bar = 2 * 1e-8 * max(1.0, kappa / 1e8)
+        print(f"{name}: cond(K) {kappa:.2e}, error bar {bar:.2e}, measured {err:.2e}", flush=True)
+        assert err <= bar, (err, bar)
     else:
         assert st["relres_true"] <= 2e-10
         assert err <= 1e-8, err
