@@ -172,6 +172,8 @@ def bench_batch(args, p, desc, S, t_setup):
         "fp32_cycle": out[32], "fp64_cycle": out[64], "speedup_fp64_over_fp32": t64 / t32,
         "graph_vs_eager_fp32": {"graph_s": t32, "eager_s": t_eager},
         "single_rhs_fp32_s": t_single, "batch_speedup_per_rhs": t_single / out[32]["s_per_rhs"],
+        "levels": [{k: li[k] for k in ("n", "n_coarse", "nnzb_A", "nnzb_G", "nnzb_P")}
+                   for li in (S.level_info(l) for l in range(S.nlev))],
     }
 
 

@@ -25,6 +25,19 @@ __device__ __forceinline__ bool bdone(const BatchCtrl *c) { return c != nullptr 
 // columns, so LDS delivers every block once per CPT columns and the global
 // loads per block are the three x gathers of the tile.  Every column is
 // summed in the same order as with one column per lane.
+#ifndef ASPAMG_SPMM_CHUNK
+#define ASPAMG_SPMM_CHUNK 256
+#endif
+#ifndef ASPAMG_SPMM_UNROLL
+#define ASPAMG_SPMM_UNROLL 3
+#endif
+constexpr int kSpmmChunk = ASPAMG_SPMM_CHUNK;    // staged blocks per 16-byte column group
+constexpr int kSpmmUnroll = ASPAMG_SPMM_UNROLL;  // blocks whose gathers are in flight together
+#ifndef ASPAMG_SPMM_STAGE
+#define ASPAMG_SPMM_STAGE 16
+#endif
+constexpr int kSpmmStage = ASPAMG_SPMM_STAGE;    // staging loads in flight per thread
+
 template <typename T> struct Vec16;
 template <> struct Vec16<float> {
   using type = float __attribute__((ext_vector_type(4)));
@@ -43,7 +56,9 @@ __global__ void __launch_bounds__(256) k_bsr_spmm(int32_t n, const int32_t *__re
   constexpr int LPR = KB / CPT;          // lanes per row and lane group
   constexpr int TPR = LPR * S;
   constexpr int RPG = 256 / TPR;
-  constexpr int CH = 256 * CPT;
+  constexpr int CH = kSpmmChunk * CPT;   // matrix blocks staged in LDS at a time
+  constexpr int U = kSpmmUnroll;
+  constexpr int R = kSpmmStage;
   static_assert(KB % CPT == 0, "tile narrower than one lane");
   __shared__ T sv[CH * 9];
   __shared__ int32_t sc[CH];
@@ -71,16 +86,49 @@ __global__ void __launch_bounds__(256) k_bsr_spmm(int32_t n, const int32_t *__re
     V a0 = (V)0, a1 = (V)0, a2 = (V)0;
     for (int32_t cb = b0; cb < b1; cb += CH) {
       const int32_t cn = min(CH, b1 - cb);
-      for (int i = threadIdx.x; i < cn * 9; i += 256) sv[i] = val[(size_t)cb * 9 + i];
+      // staging: R loads per thread are issued before the first LDS store,
+      // so a chunk costs one memory latency per 256 R entries, not one per 256
+      const T *vsrc = val + (size_t)cb * 9;
+      for (int i0 = threadIdx.x; i0 < cn * 9; i0 += 256 * R) {
+        T t[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) t[r] = i0 + 256 * r < cn * 9 ? vsrc[i0 + 256 * r] : (T)0;
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          if (i0 + 256 * r < cn * 9) sv[i0 + 256 * r] = t[r];
+      }
       for (int i = threadIdx.x; i < cn; i += 256) sc[i] = col[cb + i];
       __syncthreads();
       const int32_t lo = max(mb0, cb), hi = min(mb1, cb + cn);
       // first block of this lane group's residue class at or after lo
       const int32_t first = lo + (((sp - (lo - mb0)) % S) + S) % S;
-      for (int32_t b = first; b < hi; b += S) {
-        const int k = b - cb;
-        const int32_t c = sc[k];
-        const T *v = sv + k * 9;
+      // Full steps of U blocks issue their 3 U gathers before the first
+      // product; the remaining blocks of the row go one at a time.  Products
+      // are accumulated in block order either way.
+      int32_t b = first;
+      for (; b + (U - 1) * S < hi; b += U * S) {
+        V x0[U], x1[U], x2[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const int32_t c = sc[b + u * S - cb];
+          x0[u] = *(const V *)(X + (size_t)(3 * c) * ld + j);
+          x1[u] = *(const V *)(X + (size_t)(3 * c + 1) * ld + j);
+          x2[u] = *(const V *)(X + (size_t)(3 * c + 2) * ld + j);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const T *v = sv + (b + u * S - cb) * 9;
+#pragma unroll
+          for (int q = 0; q < CPT; q++) {
+            a0[q] += v[0] * x0[u][q] + v[1] * x1[u][q] + v[2] * x2[u][q];
+            a1[q] += v[3] * x0[u][q] + v[4] * x1[u][q] + v[5] * x2[u][q];
+            a2[q] += v[6] * x0[u][q] + v[7] * x1[u][q] + v[8] * x2[u][q];
+          }
+        }
+      }
+      for (; b < hi; b += S) {
+        const int32_t c = sc[b - cb];
+        const T *v = sv + (b - cb) * 9;
         const V x0 = *(const V *)(X + (size_t)(3 * c) * ld + j);
         const V x1 = *(const V *)(X + (size_t)(3 * c + 1) * ld + j);
         const V x2 = *(const V *)(X + (size_t)(3 * c + 2) * ld + j);
@@ -112,9 +160,11 @@ __global__ void __launch_bounds__(256) k_bsr_spmm(int32_t n, const int32_t *__re
       const size_t o = (size_t)(3 * row) * ld + j;
       V y0, y1, y2;
       if (HAS_W) {
-        y0 = alpha * a0 + *(const V *)(W + o);
-        y1 = alpha * a1 + *(const V *)(W + o + ld);
-        y2 = alpha * a2 + *(const V *)(W + o + 2 * ld);
+        // all three rows of W before the first store (Y may be W)
+        const V w0 = *(const V *)(W + o), w1 = *(const V *)(W + o + ld), w2 = *(const V *)(W + o + 2 * ld);
+        y0 = alpha * a0 + w0;
+        y1 = alpha * a1 + w1;
+        y2 = alpha * a2 + w2;
       } else {
         y0 = alpha * a0;
         y1 = alpha * a1;

@@ -90,6 +90,23 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
   if (row >= n) return;                 // whole lane groups leave together
   const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
   const int32_t cb = sizeof(CI) == 2 ? cbase[sl] : 0;
+  // The writing lane loads its row of w before the product: the three loads
+  // are in flight with the matrix stream instead of each waiting behind the
+  // store before it (y and w may be the same vector).
+  int32_t orow = row;
+  if (DUAL && row >= n1) {
+    orow = row - n1;
+    y = y2;
+    w = w2;
+    alpha = alpha2;
+  }
+  TO w0 = 0, w1 = 0, w2v = 0;
+  if (HAS_W && (e & (L - 1)) == 0) {
+    const TO *wo = w + 3 * (size_t)orow;
+    w0 = wo[0];
+    w1 = wo[1];
+    w2v = wo[2];
+  }
   T a0 = 0, a1 = 0, a2 = 0;
   const CI *cp = col + (size_t)g0 * 64 + e;
   const T *vp = val + (size_t)g0 * 576;
@@ -110,19 +127,11 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
     }
     if ((e & (L - 1)) != 0) return;
   }
-  int32_t orow = row;
-  if (DUAL && row >= n1) {
-    orow = row - n1;
-    y = y2;
-    w = w2;
-    alpha = alpha2;
-  }
   TO *yo = y + 3 * (size_t)orow;
   if (HAS_W) {
-    const TO *wo = w + 3 * (size_t)orow;
-    yo[0] = (TO)(alpha * a0) + wo[0];
-    yo[1] = (TO)(alpha * a1) + wo[1];
-    yo[2] = (TO)(alpha * a2) + wo[2];
+    yo[0] = (TO)(alpha * a0) + w0;
+    yo[1] = (TO)(alpha * a1) + w1;
+    yo[2] = (TO)(alpha * a2) + w2v;
   } else {
     yo[0] = (TO)(alpha * a0);
     yo[1] = (TO)(alpha * a1);
@@ -147,8 +156,30 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
   const bool live = wv < nwaves;        // whole wavefronts
   uint32_t m = 0x00FF;
   T a0 = 0, a1 = 0, a2 = 0;
+  // Every lane of a live wavefront finds the output row of its row (an
+  // unused lane takes the wavefront's first row) and loads that row of w
+  // with the matrix stream.  There is no branch on the metadata, so the
+  // stream's loads are issued before the metadata arrives; the lanes of one
+  // row load the same addresses.
+  int32_t row = 0;
+  TO w0 = 0, w1 = 0, w2v = 0;
   if (live) {
     m = meta[(size_t)wv * 64 + e];
+    const int32_t off = (m & 0xFF) == 0xFF ? 0 : (int32_t)(m & 0xFF);
+    row = wrow[wv] + off;
+    if (DUAL) {
+      const bool second = row >= n1;
+      row = second ? row - n1 : row;
+      y = second ? y2 : y;
+      w = second ? w2 : w;
+      alpha = second ? alpha2 : alpha;
+    }
+    if (HAS_W) {
+      const TO *wo = w + 3 * (size_t)row;
+      w0 = wo[0];
+      w1 = wo[1];
+      w2v = wo[2];
+    }
     const int32_t cb = sizeof(CI) == 2 ? cbase[wv] : 0;
     const CI *cp = col + (size_t)wv * K * 64 + e;
     const T *vp = val + (size_t)wv * K * 576;
@@ -175,19 +206,11 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
     s1 += part[1][threadIdx.x + j];
     s2 += part[2][threadIdx.x + j];
   }
-  int32_t row = wrow[wv] + (int32_t)(m & 0xFF);
-  if (DUAL && row >= n1) {
-    row -= n1;
-    y = y2;
-    w = w2;
-    alpha = alpha2;
-  }
   TO *yo = y + 3 * (size_t)row;
   if (HAS_W) {
-    const TO *wo = w + 3 * (size_t)row;
-    yo[0] = (TO)(alpha * s0) + wo[0];
-    yo[1] = (TO)(alpha * s1) + wo[1];
-    yo[2] = (TO)(alpha * s2) + wo[2];
+    yo[0] = (TO)(alpha * s0) + w0;
+    yo[1] = (TO)(alpha * s1) + w1;
+    yo[2] = (TO)(alpha * s2) + w2v;
   } else {
     yo[0] = (TO)(alpha * s0);
     yo[1] = (TO)(alpha * s1);
@@ -239,6 +262,14 @@ __global__ void __launch_bounds__(kDotThreads) k_sell_spmv_dot(int32_t n, const 
       const int32_t g0 = sptr[sl], g1 = sptr[sl + 1];
       const int32_t cb = sizeof(CI) == 2 ? cbase[sl] : 0;
       double a0 = 0, a1 = 0, a2 = 0;
+      // the row's own p, for the dot, is loaded with the matrix stream
+      double p0 = 0, p1 = 0, p2 = 0;
+      if ((e & (L - 1)) == 0) {
+        const double *xo = x + 3 * (size_t)row;
+        p0 = xo[0];
+        p1 = xo[1];
+        p2 = xo[2];
+      }
       const CI *cp = col + (size_t)g0 * 64 + e;
       const double *vp = val + (size_t)g0 * 576;
 #pragma unroll 2
@@ -262,8 +293,7 @@ __global__ void __launch_bounds__(kDotThreads) k_sell_spmv_dot(int32_t n, const 
         yo[0] = a0;
         yo[1] = a1;
         yo[2] = a2;
-        const double *xo = x + 3 * (size_t)row;
-        d += (xo[0] * a0 + xo[1] * a1) + xo[2] * a2;
+        d += (p0 * a0 + p1 * a1) + p2 * a2;
       }
     }
   }

@@ -9,6 +9,19 @@
       with the SHA-256 of kernels_solve.hip, so a later change to the kernels retires it.
       CMD is the profiled command with PMC in place of the counter name.
 
+  python -m paper_1902_01715_amd.profile_records spmm WORKLOAD BENCH_OUT TRACE_CSV FETCH_DB WRITE_DB TCC_DB CMD
+      One PCG iteration of the FP32-cycle batch solve, launch by launch: the fused
+      K P product with its dot (FP64) and every block SpMM of the V-cycle, labelled
+      with its level and operator, with the algorithmic bytes of the launch (the
+      block values and column indices once, the gathered X once, W and Y), the
+      measured FETCH_SIZE / WRITE_SIZE (scaled by k_copy of the same run, whose
+      write counter reads the bytes it moved), the L2 hit rate
+      (TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)) and the duration of the same
+      launch in a --kernel-trace run.  BENCH_OUT is a file that holds the JSON line
+      of the batch benchmark (its "levels" give the block counts).  The iteration
+      taken is the one between the third and fourth fused K P launches.  Writes
+      profiles/k_bsr_spmm_<WORKLOAD>_traffic.json and prints a markdown table.
+
   python -m paper_1902_01715_amd.profile_records stats KERNEL_STATS_CSV N
       The N most expensive kernels of a `rocprofv3 --kernel-trace --stats
       --output-format csv` run as a markdown table (names without the namespace and
@@ -83,9 +96,130 @@ def stats(path, n):
               f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
 
 
+BATCH_KERNELS = os.path.join(ROOT, "paper_1902_01715_amd", "csrc", "kernels_batch.hip")
+SPMM_RE = re.compile(r"k_bsr_spmm<(float|double), (true|false), (true|false), (\d+), (\d+)>")
+
+
+def dispatches_db(db):
+    """[(name, {counter: value})] of one --pmc run in dispatch order."""
+    con = sqlite3.connect(db)
+    rows = {}
+    for did, name, cn, cv in con.execute("select dispatch_id, name, counter_name, counter_value from pmc_events"):
+        rows.setdefault(did, [short_name(name), {}])[1][cn] = cv
+    con.close()
+    return [tuple(rows[d]) for d in sorted(rows)]
+
+
+def dispatches_trace(path):
+    """[(name, duration ns)] of a --kernel-trace csv in dispatch order."""
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
+    return [(short_name(r["Kernel_Name"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in rows]
+
+
+def iteration_window(names):
+    """Indices of one FP32-cycle PCG iteration: from the third fused K P launch
+    (k_bsr_spmm with the dot) up to the fourth."""
+    kp = [i for i, n in enumerate(names) if (m := SPMM_RE.match(n)) and m.group(3) == "true"]
+    return list(range(kp[2], kp[3]))
+
+
+def cycle_labels(levels, tail):
+    """Operators of the batch V-cycle in launch order: per level G, G^T, A, R,
+    (the coarser levels), P, A, G, G^T; the dense tail is one dense product."""
+    def walk(l):
+        if l == tail:
+            return [(l, "dense")]
+        return ([(l, "G"), (l, "GT"), (l, "A"), (l, "R")] + walk(l + 1) +
+                [(l, "P"), (l, "A"), (l, "G"), (l, "GT")])
+    return walk(0)
+
+
+def spmm_bytes(levels, l, op, size, k):
+    """Algorithmic bytes of Y = alpha M X (+ W) over k columns of type size."""
+    L = levels[l]
+    n, nc = L["n"], L["n_coarse"]
+    nnzb, rows, cols = {"A": (L["nnzb_A"], n, n), "G": (L["nnzb_G"], n, n), "GT": (L["nnzb_G"], n, n),
+                        "R": (L["nnzb_P"], nc, n), "P": (L["nnzb_P"], n, nc), "KP": (L["nnzb_A"], n, n)}[op]
+    vec = 3 * k * size
+    return nnzb * (9 * size + 4) + (rows + 1) * 4 + cols * vec + rows * vec
+
+
+def spmm(workload, bench_out, trace_csv, fetch_db, write_db, tcc_db, cmd):
+    bench = None
+    for line in open(bench_out):
+        if line.startswith("{") and '"levels"' in line:
+            bench = json.loads(line)
+    levels, k = bench["levels"], bench["config"]["rhs"]
+    F, W, T = dispatches_db(fetch_db), dispatches_db(write_db), dispatches_db(tcc_db)
+    D = dispatches_trace(trace_csv)
+    # k_copy reads what it writes: pair its launches of the two runs in order
+    cf = [c["FETCH_SIZE"] for n, c in F if n == "k_copy"]
+    cw = [c["WRITE_SIZE"] for n, c in W if n == "k_copy"]
+    if not cf or len(cf) != len(cw):
+        raise SystemExit("the FETCH and WRITE runs launch k_copy differently")
+    ff = statistics.median(w / f for f, w in zip(cf, cw))
+    launches = []
+    wins = [iteration_window([n for n, _ in src]) for src in (F, W, T, D)]
+    seqs = [[src[i] for i in w] for src, w in zip((F, W, T, D), wins)]
+    names = [n for n, _ in seqs[0]]
+    if any([n for n, _ in sq] != names for sq in seqs[1:]):
+        raise SystemExit("the four runs launch different sequences in the iteration")
+    ntail = sum(1 for n in names if n.startswith("k_dense_gemm"))
+    nspmm = sum(1 for n in names if SPMM_RE.match(n)) - 1
+    tail = nspmm // 8
+    labels = iter(cycle_labels(levels, tail))
+    if ntail != 1 or nspmm != 8 * tail:
+        raise SystemExit(f"unexpected cycle: {nspmm} products, {ntail} dense")
+    total_ns = 0
+    for (name, fc), (_, wc), (_, tc), (_, dur) in zip(*seqs):
+        total_ns += dur
+        m = SPMM_RE.match(name)
+        if m is None and not name.startswith("k_dense_gemm"):
+            launches.append({"kernel": name, "us": dur / 1e3})
+            continue
+        if m is not None and m.group(3) == "true":
+            lev, op, size = 0, "KP", 8
+        else:
+            lev, op = next(labels)
+            size = 4 if "float" in name else 8
+        if op == "dense":
+            launches.append({"kernel": name, "level": lev, "op": "dense tail", "us": dur / 1e3})
+            continue
+        if m.group(2) == "true" and op not in ("A", "P", "GT"):
+            raise SystemExit(f"{name} labelled {op}")
+        alg = spmm_bytes(levels, lev, op, size, k)
+        if m.group(2) == "true":                 # W has the rows of the product (A, P, G^T: level n)
+            alg += levels[lev]["n"] * 3 * k * size
+        fetch = fc["FETCH_SIZE"] * ff * 1024
+        write = wc["WRITE_SIZE"] * 1024
+        hit, miss = tc["TCC_HIT_sum"], tc["TCC_MISS_sum"]
+        launches.append({"kernel": name, "level": lev, "op": op, "bytes_alg": alg, "fetch": fetch, "write": write,
+                         "measured_over_alg": (fetch + write) / alg, "l2_hit": hit / max(hit + miss, 1),
+                         "us": dur / 1e3, "alg_GBps": alg / dur})
+    rec = {"workload": workload, "rhs": k, "levels": levels, "command_pmc": cmd, "calibration": {"kernel": "k_copy", "fetch_factor": ff, "write_factor": 1.0},
+           "iteration_us": total_ns / 1e3, "launches": launches,
+           "kernels_batch_sha256": hashlib.sha256(open(BATCH_KERNELS, "rb").read()).hexdigest()}
+    path = os.path.join(ROOT, "profiles", f"k_bsr_spmm_{workload}_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print("| launch | level | operator | alg. MB | FETCH MB | WRITE MB | meas./alg. | L2 hit | us | alg. GB/s |")
+    print("|---|---|---|---|---|---|---|---|---|---|")
+    for x in launches:
+        if "bytes_alg" in x:
+            print(f"| `{x['kernel']}` | {x['level']} | {x['op']} | {x['bytes_alg'] / 1e6:.1f} | {x['fetch'] / 1e6:.1f} | "
+                  f"{x['write'] / 1e6:.1f} | {x['measured_over_alg']:.2f} | {x['l2_hit']:.2f} | {x['us']:.1f} | "
+                  f"{x['alg_GBps']:.0f} |")
+        else:
+            print(f"| `{x['kernel']}` | {x.get('level', '')} | {x.get('op', '')} | | | | | | {x['us']:.1f} | |")
+    print(f"\niteration: {total_ns / 1e3:.1f} us")
+
+
 def main(argv):
     if len(argv) == 6 and argv[0] == "traffic":
         traffic(argv[1], int(argv[2]), argv[3], argv[4], argv[5])
+    elif len(argv) == 8 and argv[0] == "spmm":
+        spmm(*argv[1:])
     elif len(argv) == 3 and argv[0] == "stats":
         stats(argv[1], int(argv[2]))
     else:

@@ -3,22 +3,18 @@
 tests/golden/<name>_hierarchy.json is written by oracle/fullsize_run.py, which
 builds the oracle's hierarchy of the full workload once on a CPU host (C2 with
 the six rigid-body modes: several minutes; C3 with the paper's test space:
-longer).  Here the GPU library builds the same hierarchy, in the launch
-configuration bench.py times, and every level is compared:
-  - bit for bit: the C/F split, the scalar interpolation pattern and the block
-    patterns of A, G and P (SHA-256 of the exported arrays);
-  - C2 (n_rq = 0, both sides sum in the same order): the block values of A, G
-    and P bit for bit as well;
-  - C3 with the SRQCG test space: the values that do not depend on the test
-    space bit for bit, i.e. the leading values of the seeded sampled rows of
-    the fine-level A (the input K) and G (its aFSAI factor).  Everything
-    downstream of the test space (P, the coarse operators and their factors)
-    is compared by pattern only: the two sides sum SRQCG's inner products over
-    3.2 M entries in different orders, and ten Ritz projections amplify that
-    rounding well beyond the 7e-15 the small SRQCG parity cases show (a
-    sampled Galerkin entry of level 1 differs by 1.6e-8 of its row), while
-    every C/F split and pattern, which the decisions quantised to 20 bits
-    settle, stays identical.
+about 40 minutes on 8 threads).  Here the GPU library builds the same
+hierarchy, in the launch configuration bench.py times, and every level is
+compared bit for bit through SHA-256 digests of the exported arrays: the C/F
+split, the scalar interpolation pattern, the block patterns and the block
+values of A, G and P.  With the SRQCG test space this holds because both sides
+sum SRQCG's inner products in one fixed blocked order and apply its products
+row by row in stored order (Section 3.3; the fixed order is this library's choice); the
+decisions quantised to 20 bits then see identical inputs.
+
+A record written with fingerprint(H, False) keeps the leading values of seeded
+sampled rows instead of the value digests; the fine level's A and G (the input
+and its aFSAI factor) are then compared bit for bit and the rest reported.
 """
 import hashlib
 import json
