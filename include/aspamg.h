@@ -13,6 +13,10 @@
  *   - DOF index = 3 * node + component.  Vectors are float64, node-major.
  *   - Block matrices: row_ptr int32 [n+1], col int32 [nnzb] sorted ascending in
  *     each row, vals float64 [nnzb][3][3] row-major blocks.
+ *   - With params.block_size = 1 the same calls take a scalar CSR matrix (a
+ *     "node" is one unknown, vals [nnz], V0 [n][n_tv]) and run the paper's
+ *     point-wise method; every size stated below in units of 3 is then in
+ *     units of 1.
  *   - A block row holding only its diagonal block is a constrained (Dirichlet)
  *     or decoupled node: it is never coarse and gets no interpolation.
  *   - A handle runs its device work on a private non-blocking stream (default
@@ -95,6 +99,12 @@ typedef struct {
                            *       operator and applied as one product; 0 keeps every level
                            *       sparse.  At most 8192.  The operator is the same; only the
                            *       rounding differs. */
+  int32_t block_size;     /* 3     unknowns per node: 3 takes K as 3x3-block CSR (nodal
+                           *       blocks, elasticity); 1 takes K as scalar CSR and runs
+                           *       the paper's point-wise rules (Sections 3.1-3.5 with
+                           *       1x1 blocks), row_ptr / col / vals then being plain CSR
+                           *       and V0 [n][n_tv].  solve_batch, the assembler and the
+                           *       no-allocation entry point need 3. */
 } aspamg_params;
 
 typedef struct {

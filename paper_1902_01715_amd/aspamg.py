@@ -40,6 +40,7 @@ class Params(C.Structure):
         ("nu1", C.c_int32), ("nu2", C.c_int32), ("cycle_precision", C.c_int32), ("rtol", C.c_double),
         ("max_it", C.c_int32), ("quant_bits", C.c_int32), ("dense_max_dof", C.c_int32),
         ("check_every", C.c_int32), ("use_graph", C.c_int32), ("layout", C.c_int32), ("dense_tail_dof", C.c_int32),
+        ("block_size", C.c_int32),
     ]
 
 
@@ -158,16 +159,20 @@ def _stream_ptr(stream):
 
 
 class Solver:
-    """aSP-AMG preconditioned CG for a 3x3-block SPD matrix.
+    """aSP-AMG preconditioned CG for an SPD matrix in b x b block CSR
+    (params.block_size: 3, nodal blocks of elasticity; 1, scalar CSR and the
+    paper's point-wise rules).
 
-    row_ptr/col/vals: BSR of K (numpy host arrays or torch device tensors),
-    V0: near-null space [n_nodes, 3, n_tv] (rigid-body modes)."""
+    row_ptr/col/vals: block CSR of K (numpy host arrays or torch device
+    tensors; vals [nnzb, b, b]), V0: near-null space [n_nodes, b, n_tv]
+    (rigid-body modes for elasticity)."""
 
     def __init__(self, row_ptr, col, vals, V0, params: Params | None = None, stream=None):
         import torch
         self.params = params if params is not None else default_params()
         self.n = int(len(row_ptr) - 1)
         self.nnzb = int(row_ptr[-1])
+        self.b = int(self.params.block_size)
         def host_or_device(a, dtype, tdtype):
             if isinstance(a, np.ndarray):
                 return np.ascontiguousarray(a, dtype=dtype)
@@ -204,9 +209,9 @@ class Solver:
         self.precision = bits
 
     def solve(self, f, u=None, check=True):
-        """u = K^{-1} f by PCG; f, u float64 CUDA tensors of 3 n entries."""
+        """u = K^{-1} f by PCG; f, u float64 CUDA tensors of b n entries."""
         import torch
-        assert f.is_cuda and f.dtype == torch.float64 and f.numel() == 3 * self.n
+        assert f.is_cuda and f.dtype == torch.float64 and f.numel() == self.b * self.n
         f = f.contiguous()
         if u is None:
             u = torch.empty_like(f)
@@ -219,9 +224,9 @@ class Solver:
         return u
 
     def solve_batch(self, F, U=None):
-        """Columns of F [3n, k] solved together; float64 CUDA tensors."""
+        """Columns of F [3n, k] solved together; float64 CUDA tensors (block size 3)."""
         import torch
-        assert F.is_cuda and F.dtype == torch.float64 and F.shape[0] == 3 * self.n
+        assert F.is_cuda and F.dtype == torch.float64 and F.shape[0] == self.b * self.n
         F = F.contiguous()
         k = F.shape[1]
         if U is None:
@@ -246,7 +251,7 @@ class Solver:
         import torch
         info = self.level_info(level)
         if out_rows is None:
-            out_rows = 3 * (info["n_coarse"] if which == 4 else info["n"])
+            out_rows = self.b * (info["n_coarse"] if which == 4 else info["n"])
         y = torch.empty(out_rows, dtype=torch.float64, device=x.device)
         self._stream.synchronize()
         _check(lib().aspamg_apply_operator(self.h, level, which, precision, _ptr(x.contiguous()), _ptr(y)))
@@ -289,12 +294,12 @@ class Solver:
         return li.as_dict()
 
     def level_matrix(self, level, which):
-        """(row_ptr int64, col int32, vals [nnzb,3,3]) of A (0), G (1) or P (3)."""
+        """(row_ptr int64, col int32, vals [nnzb,b,b]) of A (0), G (1) or P (3)."""
         li = self.level_info(level)
         nnz = {0: li["nnzb_A"], 1: li["nnzb_G"], 3: li["nnzb_P"]}[which]
         rp = np.zeros(li["n"] + 1, dtype=np.int64)
         ci = np.zeros(max(nnz, 1), dtype=np.int32)
-        v = np.zeros((max(nnz, 1), 3, 3))
+        v = np.zeros((max(nnz, 1), self.b, self.b))
         _check(lib().aspamg_level_matrix(self.h, level, which, _ptr(rp), _ptr(ci), _ptr(v)))
         return rp, ci[:nnz], v[:nnz]
 
@@ -302,15 +307,15 @@ class Solver:
         li = self.level_info(level)
         n = li["n"]
         cf = np.zeros(n, dtype=np.int8)
-        cnt = np.zeros(3 * n, dtype=np.int32)
-        cols = np.zeros((3 * n, self.params.n_max), dtype=np.int32)
+        cnt = np.zeros(self.b * n, dtype=np.int32)
+        cols = np.zeros((self.b * n, self.params.n_max), dtype=np.int32)
         _check(lib().aspamg_level_split(self.h, level, _ptr(cf), _ptr(cnt), _ptr(cols)))
         return cf, cnt, cols
 
     def level_test_space(self, level):
-        """The level's orthonormalised test space, [n, 3, n_tv]."""
+        """The level's orthonormalised test space, [n, b, n_tv]."""
         n = self.level_info(level)["n"]
-        V = np.zeros((n, 3, self.n_tv))
+        V = np.zeros((n, self.b, self.n_tv))
         _check(lib().aspamg_level_test_space(self.h, level, _ptr(V)))
         return V
 

@@ -40,6 +40,7 @@ HostBSR transpose(const HostBSR &M) {
   HostBSR T;
   T.n = M.nc;
   T.nc = M.n;
+  T.b = M.b;
   T.rp.assign(T.n + 1, 0);
   const int64_t nnz = M.nnzb();
   for (int64_t k = 0; k < nnz; k++) T.rp[M.ci[k] + 1]++;
@@ -53,11 +54,12 @@ HostBSR transpose(const HostBSR &M) {
       T.ci[q] = i;
       src[q] = k;
     }
-  T.v.resize((size_t)nnz * 9);
+  const int b = M.b, bb = b * b;
+  T.v.resize((size_t)nnz * bb);
 #pragma omp parallel for schedule(static)
   for (int64_t q = 0; q < nnz; q++)
-    for (int d = 0; d < 3; d++)
-      for (int e = 0; e < 3; e++) T.v[(size_t)q * 9 + e * 3 + d] = M.v[(size_t)src[q] * 9 + d * 3 + e];
+    for (int d = 0; d < b; d++)
+      for (int e = 0; e < b; e++) T.v[(size_t)q * bb + e * b + d] = M.v[(size_t)src[q] * bb + d * b + e];
   return T;
 }
 
@@ -184,10 +186,10 @@ static void upload_arrays(aspamg_ctx *h, Sell<T> &S, const std::vector<int32_t> 
     HIPCHK(hipMemcpyAsync(S.meta, meta.data(), meta.size() * 2, hipMemcpyHostToDevice, h->stream));
   }
   const int64_t nslots = (int64_t)map.size();
-  S.val = dalloc<T>(h, (size_t)S.ngroups * 576);
+  S.val = dalloc<T>(h, (size_t)std::max<int64_t>(S.values(), 1));
   int32_t *dmap = dalloc<int32_t>(h, std::max<size_t>(map.size(), 1));
   HIPCHK(hipMemcpyAsync(dmap, map.data(), map.size() * 4, hipMemcpyHostToDevice, h->stream));
-  launch_scatter_values<T>(nslots, dmap, dv, S.val, h->stream);
+  launch_scatter_values<T>(nslots, dmap, dv, S.val, S.b, h->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(h->stream));
   dfree(h, dmap);
@@ -199,6 +201,7 @@ static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::
   Sell<T> S;
   S.n = M.n;
   S.nc = M.nc;
+  S.b = M.b;
   S.nnzb = M.nnzb();
   S.lanes = 0;
   S.pack = K;
@@ -274,6 +277,7 @@ static Sell<T> upload_sliced(aspamg_ctx *h, const HostBSR &M, int L, const std::
   Sell<T> S;
   S.n = M.n;
   S.nc = M.nc;
+  S.b = M.b;
   S.nnzb = M.nnzb();
   S.lanes = L;
   const int rps = kSell / L;
@@ -402,9 +406,9 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
   Sell<T> S = upload_sliced<T>(h, M, L, sptr, dv.v);
   Sell<T> Q = upload_packed<T>(h, M, bestK, bestw, dv.v);
   T *x = nullptr, *y = nullptr;
-  HIPCHK(hipMalloc(&x, sizeof(T) * 3 * (size_t)M.nc));
-  HIPCHK(hipMalloc(&y, sizeof(T) * 3 * (size_t)M.n));
-  HIPCHK(hipMemsetAsync(x, 0, sizeof(T) * 3 * (size_t)M.nc, h->stream));
+  HIPCHK(hipMalloc(&x, sizeof(T) * M.b * (size_t)M.nc));
+  HIPCHK(hipMalloc(&y, sizeof(T) * M.b * (size_t)M.n));
+  HIPCHK(hipMemsetAsync(x, 0, sizeof(T) * M.b * (size_t)M.nc, h->stream));
   float ts = 0, tq = 0;
   try {
     time_products(h, S, Q, x, y, ts, tq);
@@ -428,6 +432,7 @@ Sell<float> derive_fp32(aspamg_ctx *h, const Sell<double> &S) {
   Sell<float> F;
   F.n = S.n;
   F.nc = S.nc;
+  F.b = S.b;
   F.nslices = S.nslices;
   F.lanes = S.lanes;
   F.pack = S.pack;
@@ -438,9 +443,9 @@ Sell<float> derive_fp32(aspamg_ctx *h, const Sell<double> &S) {
   F.col16 = S.col16;
   F.cbase = S.cbase;
   F.meta = S.meta;
-  const int64_t nv = S.ngroups * 576;
+  const int64_t nv = S.values();
   F.val = dalloc<float>(h, (size_t)std::max<int64_t>(nv, 1));
-  if (nv > 0) launch_narrow_values(S.ngroups * 64, S.val, F.val, h->stream);
+  if (nv > 0) launch_narrow_values(S.ngroups * 64, S.val, F.val, S.b, h->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(h->stream));
   return F;
@@ -455,6 +460,7 @@ DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M) {
   DevBSR d;
   d.n = M.n;
   d.nc = M.nc;
+  d.b = M.b;
   d.nnzb = M.nnzb();
   if (d.nnzb >= (int64_t)INT32_MAX) fail(ASPAMG_EINVAL, "operator too large for int32 block indices");
   std::vector<int32_t> rp32(M.rp.begin(), M.rp.end());
@@ -609,9 +615,9 @@ static void build_tail(aspamg_ctx *h) {
   const int lc = (int)h->lev.size() - 1;
   if (h->p.dense_tail_dof <= 0 || lc < 1) return;
   int t = lc;
-  while (t > 0 && 3 * (int64_t)h->lev[t - 1].A.n <= h->p.dense_tail_dof) t--;
+  while (t > 0 && (int64_t)h->b * h->lev[t - 1].A.n <= h->p.dense_tail_dof) t--;
   if (t == lc) return;
-  const int32_t nd = 3 * h->lev[t].A.n;
+  const int32_t nd = h->b * h->lev[t].A.n;
   std::vector<ColumnLevel> C(lc - t + 1);
   std::vector<void *> tmp;
   auto vec = [&](int32_t rows) {
@@ -627,7 +633,7 @@ static void build_tail(aspamg_ctx *h) {
   for (int l = t; l <= lc; l++) {
     const Level &L = h->lev[l];
     ColumnLevel &W = C[l - t];
-    const int32_t rows = 3 * L.A.n;
+    const int32_t rows = h->b * L.A.n;
     W.y = vec(rows);
     W.z = vec(rows);
     if (L.coarsest) continue;
@@ -652,7 +658,7 @@ static void build_tail(aspamg_ctx *h) {
 
 // z = M^{-1} r for FP64 vectors r, z of the fine level
 static void precondition(aspamg_ctx *h, const double *r, double *z, const PcgCtrl *ctrl, bool fp32) {
-  const int64_t n = (int64_t)h->n * 3;
+  const int64_t n = (int64_t)h->n * h->b;
   if (fp32) {
     const Level &L0 = h->lev[0];
     launch_cast<double, float>(n, r, L0.v32.y, ctrl, h->stream);
@@ -671,7 +677,7 @@ static void precondition(aspamg_ctx *h, const double *r, double *z, const PcgCtr
 // host polling window.
 static void pcg_iteration(aspamg_ctx *h, bool fp32) {
   hipStream_t s = h->stream;
-  const int64_t n = (int64_t)h->n * 3;
+  const int64_t n = (int64_t)h->n * h->b;
   const Level &L0 = h->lev[0];
   PcgCtrl *c = h->ctrl;
   // partial regions: [0] p.q, [1] r.r and [2] r.z_old (update), [3] r.z
@@ -696,7 +702,7 @@ static void pcg_iteration(aspamg_ctx *h, bool fp32) {
 
 static void alloc_level_vectors(aspamg_ctx *h) {
   for (auto &L : h->lev) {
-    const size_t n = (size_t)L.A.n * 3;
+    const size_t n = (size_t)L.A.n * h->b;
     L.v64.y = dalloc<double>(h, n);
     L.v64.z = dalloc<double>(h, n);
     L.v64.r = dalloc<double>(h, n);
@@ -706,7 +712,7 @@ static void alloc_level_vectors(aspamg_ctx *h) {
     L.v32.r = dalloc<float>(h, n);
     L.v32.t = dalloc<float>(h, n);
   }
-  const size_t n = (size_t)h->n * 3;
+  const size_t n = (size_t)h->n * h->b;
   h->vu = dalloc<double>(h, n);
   h->vr = dalloc<double>(h, n);
   h->vp = dalloc<double>(h, n);
@@ -723,9 +729,10 @@ static void compute_complexities(aspamg_ctx *h) {
     sn += L.A.n;
     sa += (double)L.A.nnzb();
     if (!L.coarsest) {
-      // scalar nonzeros: off-diagonal blocks 9, diagonal block 6
-      sg += (double)(L.G.nnzb() - L.G.n) * 9.0 + 6.0 * L.G.n;
-      sga += (double)L.A.nnzb() * 9.0;
+      // scalar nonzeros: off-diagonal blocks b^2, diagonal block b(b+1)/2
+      const double bb = (double)h->b * h->b, bd = h->b * (h->b + 1) / 2.0;
+      sg += (double)(L.G.nnzb() - L.G.n) * bb + bd * L.G.n;
+      sga += (double)L.A.nnzb() * bb;
     }
   }
   h->c_gd = sn / h->lev[0].A.n;
@@ -742,7 +749,7 @@ static void compute_complexities(aspamg_ctx *h) {
 // an FP64 cycle and 88 B with an FP32 one.
 template <typename T>
 static double block_bytes(const Sell<T> &S) {
-  return 9.0 * sizeof(T) + S.index_bytes();
+  return (double)S.b * S.b * sizeof(T) + S.index_bytes();
 }
 
 template <typename T>
@@ -760,7 +767,7 @@ static double level_bytes(const aspamg_ctx *h, const Level &L) {
                                : nG * (block_bytes(O::G(L)) + block_bytes(O::GT(L)));
   const double post = L.stacked() ? (nP + (double)L.nnzb_AP) * block_bytes(O::PAP(L)) : nP * block_bytes(O::P(L));
   return usesA * nA * block_bytes(O::A(L)) + nu * smooth + nP * block_bytes(O::R(L)) + post +
-         18.0 * 3.0 * L.A.n * sizeof(T);
+         18.0 * h->b * L.A.n * sizeof(T);
 }
 
 static double cycle_bytes(const aspamg_ctx *h, int prec) {
@@ -778,12 +785,12 @@ static double cycle_bytes(const aspamg_ctx *h, int prec) {
   return B;
 }
 
-static double kp_block_bytes(const aspamg_ctx *h) { return 72.0 + h->lev[0].A64.index_bytes(); }
+static double kp_block_bytes(const aspamg_ctx *h) { return 8.0 * h->b * h->b + h->lev[0].A64.index_bytes(); }
 
 static double iter_bytes(const aspamg_ctx *h, int prec) {
   const Level &L0 = h->lev[0];
   const double per_dof = prec == 32 ? 88.0 : 96.0;
-  return (double)L0.A.nnzb() * kp_block_bytes(h) + 3.0 * L0.A.n * (16.0 + per_dof) + cycle_bytes(h, prec);
+  return (double)L0.A.nnzb() * kp_block_bytes(h) + (double)h->b * L0.A.n * (16.0 + per_dof) + cycle_bytes(h, prec);
 }
 
 template <typename T>
@@ -817,6 +824,7 @@ static void check_params(const aspamg_params &p) {
       p.quant_bits < 8 || p.quant_bits > 52 || p.check_every < 1 || p.n_tv < 0 || p.n_tv > 64 ||
       p.n_rq < 0 || p.n_rq > 1000 ||
       p.layout < 0 || p.layout > 3 || p.dense_tail_dof < 0 || p.dense_tail_dof > kMaxTailDof ||
+      (p.block_size != 1 && p.block_size != 3) ||
       !(p.kappa_p > 0) || !(p.omega_safety > 0))
     fail(ASPAMG_EINVAL, "invalid parameter value");
 }
@@ -829,7 +837,7 @@ double residual_gamma(const aspamg_ctx *h) {
   const HostBSR &A = h->lev[0].A;
   int64_t m = 0;
   for (int32_t i = 0; i < A.n; i++) m = std::max(m, A.rp[i + 1] - A.rp[i]);
-  const double k = (double)(3 * m + 1), u = std::ldexp(1.0, -53);
+  const double k = (double)(h->b * m + 1), u = std::ldexp(1.0, -53);
   return k * u / (1.0 - k * u);
 }
 
@@ -889,6 +897,7 @@ aspamg_status aspamg_default_params(aspamg_params *o) {
   o->use_graph = 1;
   o->layout = 0;
   o->dense_tail_dof = 4096;
+  o->block_size = 3;
   return ASPAMG_OK;
 }
 
@@ -937,15 +946,18 @@ static aspamg_status setup_impl(const aspamg_params *pp, int32_t n_nodes, int64_
   if (user) HIPCHK(hipStreamSynchronize(user));
   h->ntv = n_tv;
   h->n = n_nodes;
+  h->b = p.block_size;
+  const int bb = h->b * h->b;
   HostBSR A;
   A.n = A.nc = n_nodes;
+  A.b = h->b;
   {
     std::vector<int32_t> rp = fetch(row_ptr, (size_t)n_nodes + 1, h->stream);
     if (rp[0] != 0 || rp[n_nodes] != nnzb) fail(ASPAMG_EINVAL, "row_ptr inconsistent with nnzb");
     A.rp.assign(rp.begin(), rp.end());
   }
   A.ci = fetch(col, (size_t)nnzb, h->stream);
-  A.v = fetch(vals, (size_t)nnzb * 9, h->stream);
+  A.v = fetch(vals, (size_t)nnzb * bb, h->stream);
   for (int32_t i = 0; i < n_nodes; i++) {
     if (A.rp[i + 1] < A.rp[i]) fail(ASPAMG_EINVAL, "row_ptr not monotone");
     bool diag = false;
@@ -958,7 +970,7 @@ static aspamg_status setup_impl(const aspamg_params *pp, int32_t n_nodes, int64_
   }
   for (double x : A.v)
     if (!std::isfinite(x)) fail(ASPAMG_EINVAL, "non-finite matrix value");
-  std::vector<double> V = n_tv ? fetch(V0, (size_t)n_nodes * 3 * n_tv, h->stream) : std::vector<double>();
+  std::vector<double> V = n_tv ? fetch(V0, (size_t)n_nodes * h->b * n_tv, h->stream) : std::vector<double>();
   build_hierarchy(h.get(), std::move(A), std::move(V));
   alloc_level_vectors(h.get());
   build_tail(h.get());
@@ -1016,7 +1028,7 @@ aspamg_status aspamg_solve(aspamg_handle h, const double *f_dev, double *u_dev, 
   ABI_BEGIN
   if (!h || !f_dev || !u_dev) fail(ASPAMG_EINVAL, "invalid arguments to aspamg_solve");
   hipStream_t s = h->stream;
-  const int64_t n = (int64_t)h->n * 3;
+  const int64_t n = (int64_t)h->n * h->b;
   const bool fp32 = h->prec == 32;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1124,7 +1136,7 @@ aspamg_status aspamg_apply_operator(aspamg_handle h, int32_t level, int32_t whic
     launch_spmv<double, double, double>(*M[which], x_dev, y_dev, nullptr, 1.0, nullptr, s);
   } else {
     const Sell<float> *M[6] = {&L.A32, &L.G32, &L.GT32, &L.P32, &L.R32, &L.M32};
-    const int64_t nx = (int64_t)M[which]->nc * 3, ny = (int64_t)M[which]->n * 3;
+    const int64_t nx = (int64_t)M[which]->nc * h->b, ny = (int64_t)M[which]->n * h->b;
     float *xs = nullptr, *ys = nullptr;
     HIPCHK(hipMalloc(&xs, std::max<int64_t>(nx, 1) * 4));
     HIPCHK(hipMalloc(&ys, std::max<int64_t>(ny, 1) * 4));
@@ -1337,11 +1349,11 @@ aspamg_status aspamg_time_kernel(aspamg_handle h, int32_t which, int32_t reps, d
         break;
     }
   };
-  const double nb = (double)L0.A.nnzb();
+  const double nb = (double)L0.A.nnzb(), bsz = h->b;
   switch (which) {
-    case 0: bytes = nb * kp_block_bytes(h) + N * 3.0 * 8.0 * 2.0; break;                          // K, p, q
-    case 1: bytes = nb * (36.0 + h->lev[0].A32.index_bytes()) + N * 3.0 * 4.0 * 3.0; break;      // A32, s, y, r
-    case 2: bytes = nb * kp_block_bytes(h) + N * 3.0 * 8.0 * 3.0; break;
+    case 0: bytes = nb * kp_block_bytes(h) + N * bsz * 8.0 * 2.0; break;                          // K, p, q
+    case 1: bytes = nb * block_bytes(h->lev[0].A32) + N * bsz * 4.0 * 3.0; break;                 // A32, s, y, r
+    case 2: bytes = nb * kp_block_bytes(h) + N * bsz * 8.0 * 3.0; break;
     case 3: bytes = cycle_bytes(h, 32); break;
     case 4: bytes = cycle_bytes(h, 64); break;
   }
@@ -1376,7 +1388,7 @@ aspamg_status aspamg_time_operator(aspamg_handle h, int32_t level, int32_t op, i
   if (op == 4 && precision == 64) fail(ASPAMG_EINVAL, "the merged G^T G is applied by the FP32 cycle only");
   if (op == 5 && !L.stacked()) fail(ASPAMG_EINVAL, "this level applies P and then A (no stacked [P; A P])");
   hipStream_t s = h->stream;
-  const double n3 = 3.0 * L.A.n, vs = precision == 32 ? 4.0 : 8.0;
+  const double n3 = (double)h->b * L.A.n, vs = precision == 32 ? 4.0 : 8.0, bsz = h->b;
   double bytes = 0.0;
   std::function<void()> run;
   auto setup_op = [&](auto tag) {
@@ -1407,7 +1419,7 @@ aspamg_status aspamg_time_operator(aspamg_handle h, int32_t level, int32_t op, i
         break;
       case 3:   // restriction r_c = R r
         run = [=, &L]() { launch_spmv<T, T, T>(O::R(L), W.r, Wn.y, nullptr, 1.0, nullptr, s); };
-        bytes = (double)L.P.nnzb() * block_bytes(O::R(L)) + n3 * vs + 3.0 * L.nc * vs;
+        bytes = (double)L.P.nnzb() * block_bytes(O::R(L)) + n3 * vs + bsz * L.nc * vs;
         break;
       case 4:   // z = z + w (G^T G) r, merged
         run = [=, &L]() { launch_spmv<T, T, T>(O::M(L), W.r, W.z, W.z, w, nullptr, s); };
@@ -1417,11 +1429,11 @@ aspamg_status aspamg_time_operator(aspamg_handle h, int32_t level, int32_t op, i
         run = [=, &L]() {
           launch_spmv_dual<T, T, T>(O::PAP(L), L.P.n, Wn.z, W.z, W.z, 1.0, W.r, W.r, -1.0, nullptr, s);
         };
-        bytes = ((double)L.P.nnzb() + (double)L.nnzb_AP) * block_bytes(O::PAP(L)) + 4.0 * n3 * vs + 3.0 * L.nc * vs;
+        bytes = ((double)L.P.nnzb() + (double)L.nnzb_AP) * block_bytes(O::PAP(L)) + 4.0 * n3 * vs + bsz * L.nc * vs;
         break;
       case 7:   // prolongation z += P e
         run = [=, &L]() { launch_spmv<T, T, T>(O::P(L), Wn.z, W.z, W.z, 1.0, nullptr, s); };
-        bytes = (double)L.P.nnzb() * block_bytes(O::P(L)) + 2.0 * n3 * vs + 3.0 * L.nc * vs;
+        bytes = (double)L.P.nnzb() * block_bytes(O::P(L)) + 2.0 * n3 * vs + bsz * L.nc * vs;
         break;
     }
   };
@@ -1450,6 +1462,7 @@ aspamg_status aspamg_time_operator(aspamg_handle h, int32_t level, int32_t op, i
 aspamg_status aspamg_solve_batch(aspamg_handle h, int32_t k, const double *F_dev, int64_t ldf, double *U_dev,
                                  int64_t ldu, aspamg_stats *st) {
   ABI_BEGIN
+  if (h && h->b != 3) fail(ASPAMG_EINVAL, "solve_batch needs 3x3 blocks (block_size 3)");
   const aspamg_status r = solve_batch_impl(h, k, F_dev, ldf, U_dev, ldu, st);
   if (st)
     for (int j = 0; j < k; j++) st[j].spmm_tile = batch_tile(h, h->prec);

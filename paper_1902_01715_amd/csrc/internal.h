@@ -41,18 +41,22 @@ struct Error {
 void hip_check(hipError_t e, const char *what);
 #define HIPCHK(x) ::aspamg::hip_check((x), #x)
 
-// Host 3x3-block CSR (int64 row pointer).
+// Host b x b block CSR (int64 row pointer); b = 3 (nodal blocks) or 1
+// (scalar CSR, the paper's point-wise method).
 struct HostBSR {
   int32_t n = 0, nc = 0;
+  int32_t b = 3;
   std::vector<int64_t> rp;
   std::vector<int32_t> ci;
-  std::vector<double> v;   // nnzb * 9
+  std::vector<double> v;   // nnzb * b * b
   int64_t nnzb() const { return rp.empty() ? 0 : rp.back(); }
+  int bb() const { return b * b; }
 };
 
 // Device plain BSR (int32 row pointer) used by setup kernels.
 struct DevBSR {
   int32_t n = 0, nc = 0;
+  int32_t b = 3;
   int64_t nnzb = 0;
   int32_t *rp = nullptr;
   int32_t *ci = nullptr;
@@ -79,9 +83,12 @@ struct DevBSR {
 // j*K .. j*K+K-1, so padding is per row rather than per slice.
 // meta[s*64 + e] = (lanes of the row << 8 on its first lane, else 0) | row
 // offset inside the wavefront, or 0x00FF for an idle lane.
+// With b = 1 (scalar operators) a slot holds one value: the group's 64
+// values are val[g*64 + e].
 template <typename T>
 struct Sell {
   int32_t n = 0, nc = 0, nslices = 0;  // nslices = wavefronts of the launch
+  int32_t b = 3;           // block size: values per slot b * b
   int32_t lanes = 1;       // L (sliced)
   int32_t pack = 0;        // K (row-packed), 0 for the sliced layout
   int64_t ngroups = 0;     // slot groups (64 entries each)
@@ -93,6 +100,7 @@ struct Sell {
   T *val = nullptr;
   uint16_t *meta = nullptr;
   int64_t slots() const { return ngroups * 64; }
+  int64_t values() const { return ngroups * 64 * b * b; }
   int index_bytes() const { return col16 ? 2 : 4; }
 };
 
@@ -140,7 +148,7 @@ struct Level {
   std::vector<int8_t> cf;
   std::vector<int32_t> cidx;
   int32_t nc = 0;
-  std::vector<double> V;           // orthonormalised test space, [n][3][ntv]
+  std::vector<double> V;           // orthonormalised test space, [n][b][ntv]
   std::vector<int32_t> pcount, pcols;   // scalar P pattern
   LevelVecs<double> v64;
   LevelVecs<float> v32;
@@ -172,6 +180,7 @@ struct aspamg_ctx {
   int32_t device = 0;                         // device current at setup (the stream's)
   int32_t ntv = 0;
   int32_t n = 0;                              // fine block rows
+  int32_t b = 3;                              // unknowns per node (block size)
   std::vector<aspamg::Level> lev;
   aspamg::Coarse coarse;
   aspamg::DenseTail tail;
@@ -287,7 +296,7 @@ void launch_dpls_weights(int32_t nrows, const int32_t *row, const int32_t *cnt, 
 // `both` through the cursors `at`, then sort and deduplicate each row into
 // len; 2: compact into srp / sci); the independent-set rounds (cf: -1
 // decoupled, 0 F, 1 C, 2 undecided; undecided counts the nodes left)
-void launch_node_norms(int32_t n, const double *V, int ntv, double *sq, hipStream_t s);
+void launch_node_norms(int32_t n, const double *V, int ntv, int b, double *sq, hipStream_t s);
 void launch_strong_topk(const DevBSR &A, const int8_t *excl, const double *V, int ntv, const double *sq, int theta,
                         int qbits, int32_t *keep, int32_t *nkeep, hipStream_t s);
 void launch_union(int32_t n, int theta, const int32_t *keep, const int32_t *nkeep, int stage, int32_t *cnt,
@@ -296,11 +305,11 @@ void launch_union(int32_t n, int theta, const int32_t *keep, const int32_t *nkee
 void launch_mis_init(int32_t n, const int8_t *excl, int8_t *cf, hipStream_t s);
 void launch_mis_round(int32_t n, const int64_t *srp, const int32_t *sci, int8_t *cf, int8_t *win, int32_t *undecided,
                       hipStream_t s);
-// interpolation entries of the fine nodes fnodes[0..nf): pcount[3I+d] and the
-// chosen fine scalar indices psel[(3I+d)*kMaxPEntries ..]; err set when a
+// interpolation entries of the fine nodes fnodes[0..nf): pcount[bI+d] and the
+// chosen fine scalar indices psel[(bI+d)*kMaxPEntries ..]; err set when a
 // node's candidates exceed the kernel's limits
 void launch_dpls_rows(int32_t nf, const int32_t *fnodes, const int64_t *srp, const int32_t *sci, const int8_t *cf,
-                      const double *V, int ntv, int d_p, int nmax, double kappa_q, double eps_p, int qbits,
+                      const double *V, int ntv, int b, int d_p, int nmax, double kappa_q, double eps_p, int qbits,
                       int32_t *pcount, int32_t *psel, int32_t *err, hipStream_t s);
 // RAP numeric phases
 void launch_spgemm_ap(const DevBSR &A, const DevBSR &P, const DevBSR &T, hipStream_t s);
@@ -321,11 +330,11 @@ int dot256_parts(int64_t n);
 void launch_dot256(int64_t n, const double *a, const double *b, double *part, hipStream_t s);
 void launch_bsr_mv_seq(const DevBSR &M, const double *x, double *y, hipStream_t s);
 void launch_combine_columns(int64_t n, int nt, const double *X, const double *U, double *Y, hipStream_t s);
-// layout values: slot i takes the 9 values of block map[i] of v (zeros when map[i] < 0)
+// layout values: slot i takes the b * b values of block map[i] of v (zeros when map[i] < 0)
 template <typename T>
-void launch_scatter_values(int64_t nslots, const int32_t *map, const double *v, T *val, hipStream_t s);
+void launch_scatter_values(int64_t nslots, const int32_t *map, const double *v, T *val, int b, hipStream_t s);
 // FP32 layout values from FP64 ones (same slots)
-void launch_narrow_values(int64_t nslots, const double *v64, float *v32, hipStream_t s);
+void launch_narrow_values(int64_t nslots, const double *v64, float *v32, int b, hipStream_t s);
 void launch_element_gradient(int64_t n_el, const int32_t *conn, const double *Ke0, int64_t ke_stride,
                              const double *lam, const double *u, const double *scale, double *grad,
                              hipStream_t s);

@@ -3,7 +3,7 @@
 // the theta filter and its union symmetrisation into the strong graph S, the
 // maximal independent set (C/F split) as a fixed point of local-maximum rounds,
 // and the greedy least-squares selection of the interpolation entries of every
-// fine scalar row.
+// fine scalar row.  Nodes carry b unknowns (3, or 1 for scalar operators).
 //
 // Compiled with -ffp-contract=off: every decision quantity is the sequential
 // IEEE binary64 sum written here (the host's definition, in the same order),
@@ -18,12 +18,12 @@ namespace {
 
 // n_IJ = sum over (d, e) in row-major order of (V_I,d . V_J,e)^2, each inner
 // product summed over the test vectors in ascending order
-__device__ __forceinline__ double node_affinity(const double *__restrict__ V, int ntv, int32_t I, int32_t J) {
+__device__ __forceinline__ double node_affinity(const double *__restrict__ V, int ntv, int32_t I, int32_t J, int b) {
   double s = 0.0;
-  for (int d = 0; d < 3; d++)
-    for (int e = 0; e < 3; e++) {
-      const double *vi = V + ((size_t)I * 3 + d) * ntv;
-      const double *vj = V + ((size_t)J * 3 + e) * ntv;
+  for (int d = 0; d < b; d++)
+    for (int e = 0; e < b; e++) {
+      const double *vi = V + ((size_t)I * b + d) * ntv;
+      const double *vj = V + ((size_t)J * b + e) * ntv;
       double m = 0.0;
       for (int t = 0; t < ntv; t++) m += vi[t] * vj[t];
       s += m * m;
@@ -31,10 +31,10 @@ __device__ __forceinline__ double node_affinity(const double *__restrict__ V, in
   return s;
 }
 
-__global__ void __launch_bounds__(256) k_node_norms(int32_t n, const double *__restrict__ V, int ntv,
+__global__ void __launch_bounds__(256) k_node_norms(int32_t n, const double *__restrict__ V, int ntv, int b,
                                                     double *__restrict__ sq) {
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) sq[i] = sqrt(node_affinity(V, ntv, i, i));
+  if (i < n) sq[i] = sqrt(node_affinity(V, ntv, i, i, b));
 }
 
 // (q1, j1) ranks before (q2, j2): larger quantised strength, then lower node
@@ -49,8 +49,9 @@ __device__ __forceinline__ bool soc_before(double q1, int32_t j1, double q2, int
 __global__ void __launch_bounds__(256) k_strong_topk(int32_t n, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci,
                                                      const int8_t *__restrict__ excl, const double *__restrict__ V,
-                                                     int ntv, const double *__restrict__ sq, int theta, int qbits,
-                                                     int32_t *__restrict__ keep, int32_t *__restrict__ nkeep) {
+                                                     int ntv, int b, const double *__restrict__ sq, int theta,
+                                                     int qbits, int32_t *__restrict__ keep,
+                                                     int32_t *__restrict__ nkeep) {
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   double bq[kMaxTheta];
@@ -62,7 +63,7 @@ __global__ void __launch_bounds__(256) k_strong_topk(int32_t n, const int32_t *_
       if (j == i || excl[j]) continue;
       const int32_t a = min(i, j), c = max(i, j);
       const double den = sq[a] * sq[c];
-      const double s = den > 0.0 ? node_affinity(V, ntv, a, c) / den : 0.0;
+      const double s = den > 0.0 ? node_affinity(V, ntv, a, c, b) / den : 0.0;
       if (!(s > 0.0)) continue;
       const double qs = quantize_dev(s, qbits);
       int at = nb;
@@ -219,7 +220,7 @@ __device__ __forceinline__ bool dpls_better(double qa, int32_t a, double qb, int
 __global__ void __launch_bounds__(64) k_dpls_rows(int32_t nf, const int32_t *__restrict__ fnodes,
                                                   const int64_t *__restrict__ srp, const int32_t *__restrict__ sci,
                                                   const int8_t *__restrict__ cf, const double *__restrict__ V, int ntv,
-                                                  int d_p, int nmax, double kappa_q, double eps_p, int qbits,
+                                                  int b, int d_p, int nmax, double kappa_q, double eps_p, int qbits,
                                                   int32_t *__restrict__ pcount, int32_t *__restrict__ psel,
                                                   int32_t *__restrict__ err) {
   __shared__ int32_t hset[kHashSlots];
@@ -286,19 +287,19 @@ __global__ void __launch_bounds__(64) k_dpls_rows(int32_t nf, const int32_t *__r
       }
       cn[b] = v;
     }
-    if (ok && 3 * ncn * ntv > kCwMax) ok = 0;
+    if (ok && b * ncn * ntv > kCwMax) ok = 0;
     if (!ok) atomicOr(err, 1);
     s_ncn = ncn;
     s_ok = ok;
   }
   __syncthreads();
   if (!s_ok) return;
-  const int nca = 3 * s_ncn;
-  for (int d = 0; d < 3; d++) {
-    const size_t row = (size_t)I * 3 + d;
+  const int nca = b * s_ncn;
+  for (int d = 0; d < b; d++) {
+    const size_t row = (size_t)I * b + d;
     for (int x = lane; x < nca * ntv; x += 64) {
       const int a = x / ntv, t = x % ntv;
-      Cw[x] = V[((size_t)cn[a / 3] * 3 + a % 3) * ntv + t];
+      Cw[x] = V[((size_t)cn[a / b] * b + a % b) * ntv + t];
     }
     for (int a = lane; a < nca; a += 64) used[a] = 0;
     if (lane < ntv) r[lane] = V[row * ntv + lane];
@@ -392,7 +393,7 @@ __global__ void __launch_bounds__(64) k_dpls_rows(int32_t nf, const int32_t *__r
     }
     if (lane == 0) {
       pcount[row] = K;
-      for (int k = 0; k < K; k++) psel[row * kMaxPEntries + k] = cn[chosen[k] / 3] * 3 + chosen[k] % 3;
+      for (int k = 0; k < K; k++) psel[row * kMaxPEntries + k] = cn[chosen[k] / b] * b + chosen[k] % b;
     }
     __syncthreads();
   }
@@ -400,13 +401,13 @@ __global__ void __launch_bounds__(64) k_dpls_rows(int32_t nf, const int32_t *__r
 
 }  // namespace
 
-void launch_node_norms(int32_t n, const double *V, int ntv, double *sq, hipStream_t s) {
-  hipLaunchKernelGGL(k_node_norms, dim3((n + 255) / 256), dim3(256), 0, s, n, V, ntv, sq);
+void launch_node_norms(int32_t n, const double *V, int ntv, int b, double *sq, hipStream_t s) {
+  hipLaunchKernelGGL(k_node_norms, dim3((n + 255) / 256), dim3(256), 0, s, n, V, ntv, b, sq);
 }
 
 void launch_strong_topk(const DevBSR &A, const int8_t *excl, const double *V, int ntv, const double *sq, int theta,
                         int qbits, int32_t *keep, int32_t *nkeep, hipStream_t s) {
-  hipLaunchKernelGGL(k_strong_topk, dim3((A.n + 255) / 256), dim3(256), 0, s, A.n, A.rp, A.ci, excl, V, ntv, sq,
+  hipLaunchKernelGGL(k_strong_topk, dim3((A.n + 255) / 256), dim3(256), 0, s, A.n, A.rp, A.ci, excl, V, ntv, A.b, sq,
                      theta, qbits, keep, nkeep);
 }
 
@@ -437,10 +438,10 @@ void launch_mis_round(int32_t n, const int64_t *srp, const int32_t *sci, int8_t 
 }
 
 void launch_dpls_rows(int32_t nf, const int32_t *fnodes, const int64_t *srp, const int32_t *sci, const int8_t *cf,
-                      const double *V, int ntv, int d_p, int nmax, double kappa_q, double eps_p, int qbits,
+                      const double *V, int ntv, int b, int d_p, int nmax, double kappa_q, double eps_p, int qbits,
                       int32_t *pcount, int32_t *psel, int32_t *err, hipStream_t s) {
   if (nf == 0) return;
-  hipLaunchKernelGGL(k_dpls_rows, dim3(nf), dim3(64), 0, s, nf, fnodes, srp, sci, cf, V, ntv, d_p, nmax, kappa_q,
+  hipLaunchKernelGGL(k_dpls_rows, dim3(nf), dim3(64), 0, s, nf, fnodes, srp, sci, cf, V, ntv, b, d_p, nmax, kappa_q,
                      eps_p, qbits, pcount, psel, err);
 }
 

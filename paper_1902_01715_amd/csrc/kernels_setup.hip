@@ -41,8 +41,8 @@ __global__ void __launch_bounds__(64) k_fsai_rows(int32_t nrows, const int32_t *
                                                   const int32_t *__restrict__ pat_ptr,
                                                   const int32_t *__restrict__ pat_nodes,
                                                   const int32_t *__restrict__ Arp, const int32_t *__restrict__ Aci,
-                                                  const double *__restrict__ Av, int mmax, double *__restrict__ gout,
-                                                  double *__restrict__ psi, int32_t *fail) {
+                                                  const double *__restrict__ Av, int b, int mmax,
+                                                  double *__restrict__ gout, double *__restrict__ psi, int32_t *fail) {
   extern __shared__ double L[];         // packed lower triangle, m(m+1)/2
   __shared__ int32_t nodes[kMaxFsaiNodes + 1];
   __shared__ int bad;
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(64) k_fsai_rows(int32_t nrows, const int32_t *
   const int lane = threadIdx.x;
   const int32_t I = rows[r];
   const int32_t p0 = pat_ptr[r], nb = pat_ptr[r + 1] - p0;
-  const int m = 3 * nb + 3;
+  const int m = b * nb + b;
   for (int q = lane; q <= nb; q += 64) nodes[q] = q < nb ? pat_nodes[p0 + q] : I;
   if (lane == 0) bad = 0;
   __syncthreads();
@@ -62,11 +62,11 @@ __global__ void __launch_bounds__(64) k_fsai_rows(int32_t nrows, const int32_t *
     if (q > p) continue;
     const int32_t rn = nodes[p], cn = nodes[q];
     const int32_t k = find_col(Aci, Arp[rn], Arp[rn + 1], cn);
-    const double *B = k >= 0 ? Av + (size_t)k * 9 : nullptr;
-    for (int d = 0; d < 3; d++)
-      for (int e = 0; e < 3; e++) {
+    const double *B = k >= 0 ? Av + (size_t)k * b * b : nullptr;
+    for (int d = 0; d < b; d++)
+      for (int e = 0; e < b; e++) {
         if (p == q && e > d) continue;
-        L[tri(p * 3 + d, q * 3 + e)] = B ? B[d * 3 + e] : 0.0;
+        L[tri(p * b + d, q * b + e)] = B ? B[d * b + e] : 0.0;
       }
   }
   __syncthreads();
@@ -91,13 +91,13 @@ __global__ void __launch_bounds__(64) k_fsai_rows(int32_t nrows, const int32_t *
     if (lane == 0) *fail = 1;
     return;
   }
-  if (lane < 3) {
+  if (lane < b) {
     const int d = lane;
-    const int md = 3 * nb + d + 1;
-    // compact output: the scalar rows of chunk row r start at 3 (3 pat_ptr[r]
-    // + 3 r), each 3 nb + 3 entries long (md used, the rest zero)
-    const int rs = 3 * nb + 3;
-    double *g = gout + (size_t)3 * (3 * (size_t)p0 + 3 * (size_t)r) + (size_t)d * rs;
+    const int md = b * nb + d + 1;
+    // compact output: the scalar rows of chunk row r start at b (b pat_ptr[r]
+    // + b r), each b nb + b entries long (md used, the rest zero)
+    const int rs = b * nb + b;
+    double *g = gout + (size_t)b * (b * (size_t)p0 + b * (size_t)r) + (size_t)d * rs;
     const double lmm = L[tri(md - 1, md - 1)];
     g[md - 1] = 1.0 / lmm;
     for (int k = md - 2; k >= 0; k--) {
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(64) k_fsai_rows(int32_t nrows, const int32_t *
       g[k] = -acc / L[tri(k, k)];
     }
     for (int k = md; k < rs; k++) g[k] = 0.0;
-    psi[(size_t)r * 3 + d] = lmm * lmm;
+    psi[(size_t)r * b + d] = lmm * lmm;
   }
 }
 
@@ -164,16 +164,13 @@ __global__ void __launch_bounds__(256) k_dpls_weights(int32_t nrows, const int32
   for (int a = 0; a < K; a++) w[(size_t)i * kMaxPEntries + a] = ww[a];
 }
 
-// acc += X * Y for 3x3 blocks, each entry ((x0 y0 + x1 y1) + x2 y2).
-__device__ __forceinline__ void blk_mac(const double *X, const double *Y, double *acc) {
-#pragma unroll
-  for (int d = 0; d < 3; d++)
-#pragma unroll
-    for (int e = 0; e < 3; e++) {
-      double s = X[d * 3] * Y[e];
-      s += X[d * 3 + 1] * Y[3 + e];
-      s += X[d * 3 + 2] * Y[6 + e];
-      acc[d * 3 + e] += s;
+// acc += X * Y for b x b blocks, each entry ((x0 y0 + x1 y1) + x2 y2) for b = 3.
+__device__ __forceinline__ void blk_mac(const double *X, const double *Y, double *acc, int b) {
+  for (int d = 0; d < b; d++)
+    for (int e = 0; e < b; e++) {
+      double s = X[d * b] * Y[e];
+      for (int k = 1; k < b; k++) s += X[d * b + k] * Y[k * b + e];
+      acc[d * b + e] += s;
     }
 }
 
@@ -195,22 +192,23 @@ __global__ void __launch_bounds__(256) k_spgemm_ap(int32_t n, const int32_t *__r
                                                    const int32_t *__restrict__ Prp, const int32_t *__restrict__ Pci,
                                                    const double *__restrict__ Pv, const int32_t *__restrict__ Trp,
                                                    const int32_t *__restrict__ Tci, double *__restrict__ Tv,
-                                                   int64_t nnzT) {
+                                                   int64_t nnzT, int b) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= nnzT) return;
   const int32_t K = row_of(Trp, n, (int32_t)q);
   const int32_t J = Tci[q];
+  const int bb = b * b;
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int32_t a = Arp[K]; a < Arp[K + 1]; a++) {
     const int32_t Lr = Aci[a];
-    for (int32_t b = Prp[Lr]; b < Prp[Lr + 1]; b++) {
-      if (Pci[b] == J) {
-        blk_mac(Av + (size_t)a * 9, Pv + (size_t)b * 9, acc);
+    for (int32_t t = Prp[Lr]; t < Prp[Lr + 1]; t++) {
+      if (Pci[t] == J) {
+        blk_mac(Av + (size_t)a * bb, Pv + (size_t)t * bb, acc, b);
         break;
       }
     }
   }
-  for (int k = 0; k < 9; k++) Tv[q * 9 + k] = acc[k];
+  for (int k = 0; k < bb; k++) Tv[q * bb + k] = acc[k];
 }
 
 // A_c = R T: block (I, J) sums R_IK T_KJ over the blocks K of R's row I in
@@ -220,18 +218,19 @@ __global__ void __launch_bounds__(256) k_spgemm_rt(int32_t nc, const int32_t *__
                                                    const int32_t *__restrict__ Trp, const int32_t *__restrict__ Tci,
                                                    const double *__restrict__ Tv, const int32_t *__restrict__ Crp,
                                                    const int32_t *__restrict__ Cci, double *__restrict__ Cv,
-                                                   int64_t nnzC) {
+                                                   int64_t nnzC, int b) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= nnzC) return;
   const int32_t I = row_of(Crp, nc, (int32_t)q);
   const int32_t J = Cci[q];
+  const int bb = b * b;
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int32_t a = Rrp[I]; a < Rrp[I + 1]; a++) {
     const int32_t K = Rci[a];
     const int32_t t = find_col(Tci, Trp[K], Trp[K + 1], J);
-    if (t >= 0) blk_mac(Rv + (size_t)a * 9, Tv + (size_t)t * 9, acc);
+    if (t >= 0) blk_mac(Rv + (size_t)a * bb, Tv + (size_t)t * bb, acc, b);
   }
-  for (int k = 0; k < 9; k++) Cv[q * 9 + k] = acc[k];
+  for (int k = 0; k < bb; k++) Cv[q * bb + k] = acc[k];
 }
 
 // grad_e = -scale_e * lam_e^T K_e^0 u_e, one thread per element; a shared
@@ -296,29 +295,28 @@ __global__ void __launch_bounds__(256) k_assemble(int64_t nnzb, const int64_t *_
   for (int k = 0; k < 9; k++) vals[s * 9 + k] = acc[k];
 }
 
-// Y = alpha (M X) + W for a block-sparse M (row-major 3x3 blocks, block CSR)
-// and row-major multi-vectors with nb columns ([3 rows][nb]); one thread per
-// block row and column, blocks summed in stored order.  W may alias Y.
+// Y = alpha (M X) + W for a block-sparse M (row-major b x b blocks, block
+// CSR) and row-major multi-vectors with nb columns ([b rows][nb]); one thread
+// per block row and column, blocks summed in stored order.  W may alias Y.
 __global__ void __launch_bounds__(256) k_bsr_mm(int32_t n, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                 const double *__restrict__ X, double *Y, const double *W,
-                                                double alpha, int32_t nb) {
+                                                double alpha, int32_t nb, int b) {
   const int32_t c = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
   if (c >= nb || i >= n) return;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  double a[3] = {0.0, 0.0, 0.0};
   for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
-    const double *b = v + (size_t)k * 9;
-    const double *xj = X + (size_t)3 * ci[k] * nb + c;
-    const double x0 = xj[0], x1 = xj[nb], x2 = xj[2 * (size_t)nb];
-    a0 += b[0] * x0 + b[1] * x1 + b[2] * x2;
-    a1 += b[3] * x0 + b[4] * x1 + b[5] * x2;
-    a2 += b[6] * x0 + b[7] * x1 + b[8] * x2;
+    const double *blk = v + (size_t)k * b * b;
+    const double *xj = X + (size_t)b * ci[k] * nb + c;
+    for (int d = 0; d < b; d++) {
+      double t = blk[d * b] * xj[0];
+      for (int e = 1; e < b; e++) t += blk[d * b + e] * xj[e * (size_t)nb];
+      a[d] += t;
+    }
   }
-  double *yi = Y + (size_t)3 * i * nb + c;
-  const double *wi = W ? W + (size_t)3 * i * nb + c : nullptr;
-  yi[0] = alpha * a0 + (wi ? wi[0] : 0.0);
-  yi[nb] = alpha * a1 + (wi ? wi[nb] : 0.0);
-  yi[2 * (size_t)nb] = alpha * a2 + (wi ? wi[2 * (size_t)nb] : 0.0);
+  double *yi = Y + (size_t)b * i * nb + c;
+  const double *wi = W ? W + (size_t)b * i * nb + c : nullptr;
+  for (int d = 0; d < b; d++) yi[d * (size_t)nb] = alpha * a[d] + (wi ? wi[d * (size_t)nb] : 0.0);
 }
 
 // Y = D X for a dense row-major nd x nd matrix D and [nd][nb] multi-vectors.
@@ -338,25 +336,33 @@ __global__ void __launch_bounds__(256) k_dense_mm(int32_t nd, const double *__re
 // when src < 0.
 template <typename T>
 __global__ void __launch_bounds__(256) k_scatter_values(int64_t nslots, const int32_t *__restrict__ map,
-                                                        const double *__restrict__ v, T *__restrict__ val) {
+                                                        const double *__restrict__ v, T *__restrict__ val, int b) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= nslots) return;
   const int32_t src = map[i];
+  if (b == 1) {                         // scalar operator: one value per slot
+    val[i] = src >= 0 ? (T)v[src] : (T)0;
+    return;
+  }
   constexpr int W = 16 / sizeof(T);   // values per 16-byte chunk
   T *g = val + (i >> 6) * 576;
   const int e = (int)(i & 63);
-  const double *b = src >= 0 ? v + (int64_t)src * 9 : nullptr;
+  const double *blk = src >= 0 ? v + (int64_t)src * 9 : nullptr;
 #pragma unroll
-  for (int q = 0; q < 8; q++) g[(q / W) * 64 * W + e * W + (q % W)] = b ? (T)b[q] : (T)0;
-  g[512 + e] = b ? (T)b[8] : (T)0;
+  for (int q = 0; q < 8; q++) g[(q / W) * 64 * W + e * W + (q % W)] = blk ? (T)blk[q] : (T)0;
+  g[512 + e] = blk ? (T)blk[8] : (T)0;
 }
 
 // FP32 copy of FP64 layout values: the same slots, each value rounded, moved
 // from the FP64 chunk order (pairs) to the FP32 one (quads).
 __global__ void __launch_bounds__(256) k_narrow_values(int64_t nslots, const double *__restrict__ v64,
-                                                       float *__restrict__ v32) {
+                                                       float *__restrict__ v32, int b) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= nslots) return;
+  if (b == 1) {
+    v32[i] = (float)v64[i];
+    return;
+  }
   const double *g = v64 + (i >> 6) * 576;
   float *o = v32 + (i >> 6) * 576;
   const int e = (int)(i & 63);
@@ -408,7 +414,7 @@ __global__ void __launch_bounds__(64) k_fsai_grow(int32_t nrows, const int32_t *
                                                   const int32_t *__restrict__ pat_ptr,
                                                   const int32_t *__restrict__ pat_nodes, const double *__restrict__ g,
                                                   const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                  const double *__restrict__ v, int rho, int qbits,
+                                                  const double *__restrict__ v, int b, int rho, int qbits,
                                                   int32_t *__restrict__ add) {
   constexpr int GS = 3 * kMaxFsaiNodes + 3;
   __shared__ int32_t K[kMaxFsaiNodes + 1];
@@ -433,11 +439,11 @@ __global__ void __launch_bounds__(64) k_fsai_grow(int32_t nrows, const int32_t *
     }
     off[lane + 1] = lo - rp[Kp];
   }
-  // g' rows (compact layout of k_fsai_rows: rows of 3 nb + 3 entries)
-  const int rs = 3 * nb + 3;
-  const double *gi = g + (size_t)3 * (3 * (size_t)p0 + 3 * (size_t)i);
-  for (int t = lane; t < 3 * rs; t += 64) {
-    const int d = t / rs, k = t % rs, md = 3 * nb + d + 1;
+  // g' rows (compact layout of k_fsai_rows: rows of b nb + b entries)
+  const int rs = b * nb + b;
+  const double *gi = g + (size_t)b * (b * (size_t)p0 + b * (size_t)i);
+  for (int t = lane; t < b * rs; t += 64) {
+    const int d = t / rs, k = t % rs, md = b * nb + d + 1;
     if (k < md) gp[d][k] = gi[d * rs + k] / gi[d * rs + md - 1];
   }
   __syncthreads();
@@ -473,23 +479,18 @@ __global__ void __launch_bounds__(64) k_fsai_grow(int32_t nrows, const int32_t *
     for (int q = p; q <= nb; q++) {
       const int32_t pos = find_col(rp, ci, J, K[q]);    // block (J, K_q)
       if (pos < 0) continue;
-      const double *blk = v + (size_t)pos * 9;
-      for (int d = 0; d < 3; d++) {
-        const int kend = min(3, 3 * nb + d + 1 - 3 * q);
+      const double *blk = v + (size_t)pos * b * b;
+      for (int d = 0; d < b; d++) {
+        const int kend = min(b, b * nb + d + 1 - b * q);
         for (int c = 0; c < kend; c++) {
-          const double gk = gp[d][3 * q + c];
-          h[d * 3 + 0] += blk[c] * gk;
-          h[d * 3 + 1] += blk[3 + c] * gk;
-          h[d * 3 + 2] += blk[6 + c] * gk;
+          const double gk = gp[d][b * q + c];
+          for (int e = 0; e < b; e++) h[d * b + e] += blk[e * b + c] * gk;
         }
       }
     }
     double score = 0.0;
-    for (int d = 0; d < 3; d++) {
-      score += h[d * 3 + 0] * h[d * 3 + 0];
-      score += h[d * 3 + 1] * h[d * 3 + 1];
-      score += h[d * 3 + 2] * h[d * 3 + 2];
-    }
+    for (int d = 0; d < b; d++)
+      for (int e = 0; e < b; e++) score += h[d * b + e] * h[d * b + e];
     if (!(score > 0.0)) continue;
     const double qs = quantize_dev(score, qbits);
     // insert into this lane's sorted best list (at most rho kept)
@@ -551,26 +552,17 @@ __global__ void __launch_bounds__(256) k_dot256(int64_t n, const double *__restr
 // components summed over its blocks in stored order (the sequential product)
 __global__ void __launch_bounds__(256) k_bsr_mv_seq(int32_t n, const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ ci, const double *__restrict__ v,
-                                                   const double *__restrict__ x, double *__restrict__ y) {
+                                                   const double *__restrict__ x, double *__restrict__ y, int b) {
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  double a[3] = {0.0, 0.0, 0.0};
   for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
-    const double *B = v + (size_t)k * 9;
-    const double *xx = x + (size_t)ci[k] * 3;
-    a0 += B[0] * xx[0];
-    a0 += B[1] * xx[1];
-    a0 += B[2] * xx[2];
-    a1 += B[3] * xx[0];
-    a1 += B[4] * xx[1];
-    a1 += B[5] * xx[2];
-    a2 += B[6] * xx[0];
-    a2 += B[7] * xx[1];
-    a2 += B[8] * xx[2];
+    const double *B = v + (size_t)k * b * b;
+    const double *xx = x + (size_t)ci[k] * b;
+    for (int d = 0; d < b; d++)
+      for (int e = 0; e < b; e++) a[d] += B[d * b + e] * xx[e];
   }
-  y[(size_t)i * 3] = a0;
-  y[(size_t)i * 3 + 1] = a1;
-  y[(size_t)i * 3 + 2] = a2;
+  for (int d = 0; d < b; d++) y[(size_t)i * b + d] = a[d];
 }
 
 // y = x + b y
@@ -602,7 +594,7 @@ void launch_bsr_mm(const DevBSR &M, const double *X, double *Y, const double *W,
                    hipStream_t s) {
   if (M.n == 0 || nb == 0) return;
   hipLaunchKernelGGL(k_bsr_mm, dim3((unsigned)((nb + 255) / 256), (unsigned)M.n), dim3(256), 0, s, M.n, M.rp, M.ci,
-                     M.v, X, Y, W, alpha, nb);
+                     M.v, X, Y, W, alpha, nb, M.b);
 }
 
 void launch_dense_mm(int32_t nd, const double *D, const double *X, double *Y, int32_t nb, hipStream_t s) {
@@ -611,17 +603,17 @@ void launch_dense_mm(int32_t nd, const double *D, const double *X, double *Y, in
 }
 
 template <typename T>
-void launch_scatter_values(int64_t nslots, const int32_t *map, const double *v, T *val, hipStream_t s) {
+void launch_scatter_values(int64_t nslots, const int32_t *map, const double *v, T *val, int b, hipStream_t s) {
   if (nslots == 0) return;
   hipLaunchKernelGGL(k_scatter_values<T>, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s, nslots, map, v,
-                     val);
+                     val, b);
 }
-template void launch_scatter_values<double>(int64_t, const int32_t *, const double *, double *, hipStream_t);
-template void launch_scatter_values<float>(int64_t, const int32_t *, const double *, float *, hipStream_t);
+template void launch_scatter_values<double>(int64_t, const int32_t *, const double *, double *, int, hipStream_t);
+template void launch_scatter_values<float>(int64_t, const int32_t *, const double *, float *, int, hipStream_t);
 
-void launch_narrow_values(int64_t nslots, const double *v64, float *v32, hipStream_t s) {
+void launch_narrow_values(int64_t nslots, const double *v64, float *v32, int b, hipStream_t s) {
   if (nslots == 0) return;
-  hipLaunchKernelGGL(k_narrow_values, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s, nslots, v64, v32);
+  hipLaunchKernelGGL(k_narrow_values, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s, nslots, v64, v32, b);
 }
 
 static unsigned setup_vec_blocks(int64_t n) {
@@ -646,7 +638,7 @@ void launch_dot256(int64_t n, const double *a, const double *b, double *part, hi
 }
 void launch_bsr_mv_seq(const DevBSR &M, const double *x, double *y, hipStream_t s) {
   if (M.n == 0) return;
-  hipLaunchKernelGGL(k_bsr_mv_seq, dim3((M.n + 255) / 256), dim3(256), 0, s, M.n, M.rp, M.ci, M.v, x, y);
+  hipLaunchKernelGGL(k_bsr_mv_seq, dim3((M.n + 255) / 256), dim3(256), 0, s, M.n, M.rp, M.ci, M.v, x, y, M.b);
 }
 void launch_xpby(int64_t n, const double *x, double b, double *y, hipStream_t s) {
   hipLaunchKernelGGL(k_xpby, dim3(setup_vec_blocks(n)), dim3(256), 0, s, n, x, b, y);
@@ -667,7 +659,7 @@ int launch_fsai_rows(const DevBSR &A, int32_t nrows, const int32_t *rows, const 
   if (nrows == 0) return 0;
   const size_t lds = (size_t)mmax * (mmax + 1) / 2 * sizeof(double);
   hipLaunchKernelGGL(k_fsai_rows, dim3(nrows), dim3(64), lds, s, nrows, rows, pat_ptr, pat_nodes, A.rp, A.ci, A.v,
-                     mmax, g, psi, fail_flag);
+                     A.b, mmax, g, psi, fail_flag);
   return 0;
 }
 
@@ -675,7 +667,7 @@ void launch_fsai_grow(const DevBSR &A, int32_t nrows, const int32_t *rows, const
                       const int32_t *pat_nodes, const double *g, int rho, int qbits, int32_t *add, hipStream_t s) {
   if (nrows == 0) return;
   hipLaunchKernelGGL(k_fsai_grow, dim3(nrows), dim3(64), 0, s, nrows, rows, pat_ptr, pat_nodes, g, A.rp, A.ci, A.v,
-                     rho, qbits, add);
+                     A.b, rho, qbits, add);
 }
 
 void launch_dpls_weights(int32_t nrows, const int32_t *row, const int32_t *cnt, const int32_t *sel,
@@ -687,13 +679,13 @@ void launch_dpls_weights(int32_t nrows, const int32_t *row, const int32_t *cnt, 
 void launch_spgemm_ap(const DevBSR &A, const DevBSR &P, const DevBSR &T, hipStream_t s) {
   if (T.nnzb == 0) return;
   hipLaunchKernelGGL(k_spgemm_ap, dim3((unsigned)((T.nnzb + 255) / 256)), dim3(256), 0, s, T.n, A.rp, A.ci, A.v,
-                     P.rp, P.ci, P.v, T.rp, T.ci, T.v, T.nnzb);
+                     P.rp, P.ci, P.v, T.rp, T.ci, T.v, T.nnzb, T.b);
 }
 
 void launch_spgemm_rt(const DevBSR &R, const DevBSR &T, const DevBSR &Ac, hipStream_t s) {
   if (Ac.nnzb == 0) return;
   hipLaunchKernelGGL(k_spgemm_rt, dim3((unsigned)((Ac.nnzb + 255) / 256)), dim3(256), 0, s, Ac.n, R.rp, R.ci, R.v,
-                     T.rp, T.ci, T.v, Ac.rp, Ac.ci, Ac.v, Ac.nnzb);
+                     T.rp, T.ci, T.v, Ac.rp, Ac.ci, Ac.v, Ac.nnzb, Ac.b);
 }
 
 void launch_element_gradient(int64_t n_el, const int32_t *conn, const double *Ke0, int64_t ke_stride,

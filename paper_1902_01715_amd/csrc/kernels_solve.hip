@@ -57,6 +57,20 @@ __device__ __forceinline__ void blk_fma(const float *g, int e, float x0, float x
   a2 += c1.z * x0 + c1.w * x1 + v8 * x2;
 }
 
+// One slot of a b x b block operator applied to the gathered x of column c:
+// b = 3, the slot's 3x3 block from its group of 576 values (blk_fma); b = 1,
+// the slot's one value at entry e of its group of 64 (scalar CSR).
+template <int B, typename T, typename TX>
+__device__ __forceinline__ void slot_fma(const T *g, int e, const TX *__restrict__ x, int32_t c, T &a0, T &a1,
+                                         T &a2) {
+  if constexpr (B == 3) {
+    const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
+    blk_fma(g, e, x0, x1, x2, a0, a1, a2);
+  } else {
+    a0 += ld_stream(g + e) * (T)x[c];
+  }
+}
+
 // Deterministic sum over a 256-thread block; the result is valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double *sm) {
 #pragma unroll
@@ -77,7 +91,7 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
 // a row meet in a butterfly and lane j = 0 writes the row.
 // With DUAL, rows r >= n1 write y2[r - n1] = alpha2 (A x)[r] + w2[r - n1].
 // CI is the stored column type: int32, or uint16 offsets from cbase[slice].
-template <typename T, typename TX, typename TO, bool HAS_W, int L, bool DUAL, typename CI>
+template <typename T, typename TX, typename TO, bool HAS_W, int L, bool DUAL, typename CI, int B>
 __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__restrict__ sptr,
                                                    const CI *__restrict__ col, const int32_t *__restrict__ cbase,
                                                    const T *__restrict__ val, const TX *__restrict__ x, TO *y,
@@ -102,54 +116,61 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
   }
   TO w0 = 0, w1 = 0, w2v = 0;
   if (HAS_W && (e & (L - 1)) == 0) {
-    const TO *wo = w + 3 * (size_t)orow;
+    const TO *wo = w + B * (size_t)orow;
     w0 = wo[0];
-    w1 = wo[1];
-    w2v = wo[2];
+    if constexpr (B == 3) {
+      w1 = wo[1];
+      w2v = wo[2];
+    }
   }
   T a0 = 0, a1 = 0, a2 = 0;
   const CI *cp = col + (size_t)g0 * 64 + e;
-  const T *vp = val + (size_t)g0 * 576;
+  const T *vp = val + (size_t)g0 * 64 * B * B;
 #pragma unroll 2
   for (int32_t g = g0; g < g1; ++g) {
     const int32_t c = (int32_t)ld_stream(cp) + cb;
-    const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
-    blk_fma(vp, e, x0, x1, x2, a0, a1, a2);
+    slot_fma<B>(vp, e, x, c, a0, a1, a2);
     cp += 64;
-    vp += 576;
+    vp += 64 * B * B;
   }
   if (L > 1) {
 #pragma unroll
     for (int o = L / 2; o > 0; o >>= 1) {
       a0 += __shfl_xor(a0, o, L);
-      a1 += __shfl_xor(a1, o, L);
-      a2 += __shfl_xor(a2, o, L);
+      if constexpr (B == 3) {
+        a1 += __shfl_xor(a1, o, L);
+        a2 += __shfl_xor(a2, o, L);
+      }
     }
     if ((e & (L - 1)) != 0) return;
   }
-  TO *yo = y + 3 * (size_t)orow;
+  TO *yo = y + B * (size_t)orow;
   if (HAS_W) {
     yo[0] = (TO)(alpha * a0) + w0;
-    yo[1] = (TO)(alpha * a1) + w1;
-    yo[2] = (TO)(alpha * a2) + w2v;
+    if constexpr (B == 3) {
+      yo[1] = (TO)(alpha * a1) + w1;
+      yo[2] = (TO)(alpha * a2) + w2v;
+    }
   } else {
     yo[0] = (TO)(alpha * a0);
-    yo[1] = (TO)(alpha * a1);
-    yo[2] = (TO)(alpha * a2);
+    if constexpr (B == 3) {
+      yo[1] = (TO)(alpha * a1);
+      yo[2] = (TO)(alpha * a2);
+    }
   }
 }
 
 // The same product on the row-packed layout: every lane streams its K slot
 // groups (fully unrolled), parks its three partial sums in LDS, and the first
 // lane of each row adds the row's lanes in lane order and writes the row.
-template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL, typename CI>
+template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL, typename CI, int B>
 __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t *__restrict__ wrow,
                                                    const uint16_t *__restrict__ meta, const CI *__restrict__ col,
                                                    const int32_t *__restrict__ cbase, const T *__restrict__ val,
                                                    const TX *__restrict__ x, TO *y, const TO *w, T alpha,
                                                    const PcgCtrl *ctrl, int32_t n1, TO *y2, const TO *w2,
                                                    T alpha2) {
-  __shared__ T part[3][256];
+  __shared__ T part[B][256];
   if (ctrl_done(ctrl)) return;          // the same for every thread of the grid
   const int32_t t = xcd_block() * 256 + threadIdx.x;
   const int32_t wv = t >> 6, e = t & 63;
@@ -175,26 +196,29 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
       alpha = second ? alpha2 : alpha;
     }
     if (HAS_W) {
-      const TO *wo = w + 3 * (size_t)row;
+      const TO *wo = w + B * (size_t)row;
       w0 = wo[0];
-      w1 = wo[1];
-      w2v = wo[2];
+      if constexpr (B == 3) {
+        w1 = wo[1];
+        w2v = wo[2];
+      }
     }
     const int32_t cb = sizeof(CI) == 2 ? cbase[wv] : 0;
     const CI *cp = col + (size_t)wv * K * 64 + e;
-    const T *vp = val + (size_t)wv * K * 576;
+    const T *vp = val + (size_t)wv * K * 64 * B * B;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int32_t c = (int32_t)ld_stream(cp + 64 * k) + cb;
-      const T x0 = (T)x[3 * c], x1 = (T)x[3 * c + 1], x2 = (T)x[3 * c + 2];
-      blk_fma(vp + 576 * k, e, x0, x1, x2, a0, a1, a2);
+      slot_fma<B>(vp + 64 * B * B * k, e, x, c, a0, a1, a2);
     }
   }
   // the lanes of a row never leave their wavefront, whose LDS operations
   // complete in order: a wavefront-scope barrier suffices
   part[0][threadIdx.x] = a0;
-  part[1][threadIdx.x] = a1;
-  part[2][threadIdx.x] = a2;
+  if constexpr (B == 3) {
+    part[1][threadIdx.x] = a1;
+    part[2][threadIdx.x] = a2;
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -203,18 +227,24 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
   T s0 = 0, s1 = 0, s2 = 0;
   for (int j = 0; j < cnt; ++j) {       // lanes of one row never leave the wavefront
     s0 += part[0][threadIdx.x + j];
-    s1 += part[1][threadIdx.x + j];
-    s2 += part[2][threadIdx.x + j];
+    if constexpr (B == 3) {
+      s1 += part[1][threadIdx.x + j];
+      s2 += part[2][threadIdx.x + j];
+    }
   }
-  TO *yo = y + 3 * (size_t)row;
+  TO *yo = y + B * (size_t)row;
   if (HAS_W) {
     yo[0] = (TO)(alpha * s0) + w0;
-    yo[1] = (TO)(alpha * s1) + w1;
-    yo[2] = (TO)(alpha * s2) + w2v;
+    if constexpr (B == 3) {
+      yo[1] = (TO)(alpha * s1) + w1;
+      yo[2] = (TO)(alpha * s2) + w2v;
+    }
   } else {
     yo[0] = (TO)(alpha * s0);
-    yo[1] = (TO)(alpha * s1);
-    yo[2] = (TO)(alpha * s2);
+    if constexpr (B == 3) {
+      yo[1] = (TO)(alpha * s1);
+      yo[2] = (TO)(alpha * s2);
+    }
   }
 }
 
@@ -243,7 +273,7 @@ __device__ __forceinline__ double block_sum_n(double v, double *sm) {
 // every kDotThreads-thread block.  Block b serves the `per` consecutive groups
 // of kDotThreads lanes b*per .. b*per+per-1 (per = 1 up to kMaxPart blocks; a
 // larger operator keeps kMaxPart partials and gives each block more rows).
-template <typename CI, int L>
+template <typename CI, int L, int B>
 __global__ void __launch_bounds__(kDotThreads) k_sell_spmv_dot(int32_t n, const int32_t *__restrict__ sptr,
                                                         const CI *__restrict__ col,
                                                         const int32_t *__restrict__ cbase,
@@ -265,35 +295,42 @@ __global__ void __launch_bounds__(kDotThreads) k_sell_spmv_dot(int32_t n, const 
       // the row's own p, for the dot, is loaded with the matrix stream
       double p0 = 0, p1 = 0, p2 = 0;
       if ((e & (L - 1)) == 0) {
-        const double *xo = x + 3 * (size_t)row;
+        const double *xo = x + B * (size_t)row;
         p0 = xo[0];
-        p1 = xo[1];
-        p2 = xo[2];
+        if constexpr (B == 3) {
+          p1 = xo[1];
+          p2 = xo[2];
+        }
       }
       const CI *cp = col + (size_t)g0 * 64 + e;
-      const double *vp = val + (size_t)g0 * 576;
+      const double *vp = val + (size_t)g0 * 64 * B * B;
 #pragma unroll 2
       for (int32_t g = g0; g < g1; ++g) {
         const int32_t c = (int32_t)ld_stream(cp) + cb;
-        const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
-        blk_fma(vp, e, x0, x1, x2, a0, a1, a2);
+        slot_fma<B>(vp, e, x, c, a0, a1, a2);
         cp += 64;
-        vp += 576;
+        vp += 64 * B * B;
       }
       if (L > 1) {
 #pragma unroll
         for (int o = L / 2; o > 0; o >>= 1) {
           a0 += __shfl_xor(a0, o, L);
-          a1 += __shfl_xor(a1, o, L);
-          a2 += __shfl_xor(a2, o, L);
+          if constexpr (B == 3) {
+            a1 += __shfl_xor(a1, o, L);
+            a2 += __shfl_xor(a2, o, L);
+          }
         }
       }
       if ((e & (L - 1)) == 0) {
-        double *yo = y + 3 * (size_t)row;
+        double *yo = y + B * (size_t)row;
         yo[0] = a0;
-        yo[1] = a1;
-        yo[2] = a2;
-        d += (p0 * a0 + p1 * a1) + p2 * a2;
+        if constexpr (B == 3) {
+          yo[1] = a1;
+          yo[2] = a2;
+          d += (p0 * a0 + p1 * a1) + p2 * a2;
+        } else {
+          d += p0 * a0;
+        }
       }
     }
   }
@@ -306,7 +343,7 @@ __global__ void __launch_bounds__(kDotThreads) k_sell_spmv_dot(int32_t n, const 
 // f - K u, Higham, "Accuracy and Stability of Numerical Algorithms", Sec. 3.5),
 // and the block partials of sum s_i^2.  Same layout and row mapping as
 // k_sell_spmv_dot.
-template <typename CI, int L>
+template <typename CI, int L, int B>
 __global__ void __launch_bounds__(kDotThreads) k_sell_abs_bound(int32_t n, const int32_t *__restrict__ sptr,
                                                          const CI *__restrict__ col,
                                                          const int32_t *__restrict__ cbase,
@@ -325,26 +362,37 @@ __global__ void __launch_bounds__(kDotThreads) k_sell_abs_bound(int32_t n, const
     double a0 = 0, a1 = 0, a2 = 0;
     for (int32_t g = g0; g < g1; ++g) {
       const int32_t c = (int32_t)col[(size_t)g * 64 + e] + cb;
-      const double x0 = fabs(u[3 * c]), x1 = fabs(u[3 * c + 1]), x2 = fabs(u[3 * c + 2]);
-      const wide_f64 *p = reinterpret_cast<const wide_f64 *>(val + (size_t)g * 576) + e;
-      const wide_f64 c0 = p[0], c1 = p[64], c2 = p[128], c3 = p[192];
-      const double v8 = val[(size_t)g * 576 + 512 + e];
-      a0 += fabs(c0.x) * x0 + fabs(c0.y) * x1 + fabs(c1.x) * x2;
-      a1 += fabs(c1.y) * x0 + fabs(c2.x) * x1 + fabs(c2.y) * x2;
-      a2 += fabs(c3.x) * x0 + fabs(c3.y) * x1 + fabs(v8) * x2;
+      if constexpr (B == 3) {
+        const double x0 = fabs(u[3 * c]), x1 = fabs(u[3 * c + 1]), x2 = fabs(u[3 * c + 2]);
+        const wide_f64 *p = reinterpret_cast<const wide_f64 *>(val + (size_t)g * 576) + e;
+        const wide_f64 c0 = p[0], c1 = p[64], c2 = p[128], c3 = p[192];
+        const double v8 = val[(size_t)g * 576 + 512 + e];
+        a0 += fabs(c0.x) * x0 + fabs(c0.y) * x1 + fabs(c1.x) * x2;
+        a1 += fabs(c1.y) * x0 + fabs(c2.x) * x1 + fabs(c2.y) * x2;
+        a2 += fabs(c3.x) * x0 + fabs(c3.y) * x1 + fabs(v8) * x2;
+      } else {
+        a0 += fabs(val[(size_t)g * 64 + e]) * fabs(u[c]);
+      }
     }
     if (L > 1) {
 #pragma unroll
       for (int o = L / 2; o > 0; o >>= 1) {
         a0 += __shfl_xor(a0, o, L);
-        a1 += __shfl_xor(a1, o, L);
-        a2 += __shfl_xor(a2, o, L);
+        if constexpr (B == 3) {
+          a1 += __shfl_xor(a1, o, L);
+          a2 += __shfl_xor(a2, o, L);
+        }
       }
     }
     if ((e & (L - 1)) == 0) {
-      const double *fo = f + 3 * (size_t)row;
-      const double s0 = fabs(fo[0]) + a0, s1 = fabs(fo[1]) + a1, s2 = fabs(fo[2]) + a2;
-      d += (s0 * s0 + s1 * s1) + s2 * s2;
+      const double *fo = f + B * (size_t)row;
+      if constexpr (B == 3) {
+        const double s0 = fabs(fo[0]) + a0, s1 = fabs(fo[1]) + a1, s2 = fabs(fo[2]) + a2;
+        d += (s0 * s0 + s1 * s1) + s2 * s2;
+      } else {
+        const double s0 = fabs(fo[0]) + a0;
+        d += s0 * s0;
+      }
     }
   }
   const double s = block_sum_n<kDotThreads>(d, sm);
@@ -566,17 +614,24 @@ int vec_blocks(int64_t n) {
   return (int)b;
 }
 
-template <typename T, typename TX, typename TO, bool HAS_W, int L, bool DUAL = false>
-static void launch_l(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
-                     hipStream_t s, int32_t n1 = 0, TO *y2 = nullptr, const TO *w2 = nullptr, double alpha2 = 0) {
+template <typename T, typename TX, typename TO, bool HAS_W, int L, bool DUAL, int B>
+static void launch_lb(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
+                      hipStream_t s, int32_t n1, TO *y2, const TO *w2, double alpha2) {
   const int64_t threads = (int64_t)A.nslices * 64;
   const dim3 grid((unsigned)((threads + 255) / 256));
   if (A.col16)
-    hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, HAS_W, L, DUAL, uint16_t>), grid, dim3(256), 0, s, A.n, A.sptr,
+    hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, HAS_W, L, DUAL, uint16_t, B>), grid, dim3(256), 0, s, A.n, A.sptr,
                        A.col16, A.cbase, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
   else
-    hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, HAS_W, L, DUAL, int32_t>), grid, dim3(256), 0, s, A.n, A.sptr, A.col,
-                       nullptr, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
+    hipLaunchKernelGGL((k_sell_spmv<T, TX, TO, HAS_W, L, DUAL, int32_t, B>), grid, dim3(256), 0, s, A.n, A.sptr,
+                       A.col, nullptr, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
+}
+// the operator's block size picks the kernel: 3 (nodal blocks) or 1 (scalar)
+template <typename T, typename TX, typename TO, bool HAS_W, int L, bool DUAL = false>
+static void launch_l(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
+                     hipStream_t s, int32_t n1 = 0, TO *y2 = nullptr, const TO *w2 = nullptr, double alpha2 = 0) {
+  if (A.b == 1) launch_lb<T, TX, TO, HAS_W, L, DUAL, 1>(A, x, y, w, alpha, ctrl, s, n1, y2, w2, alpha2);
+  else launch_lb<T, TX, TO, HAS_W, L, DUAL, 3>(A, x, y, w, alpha, ctrl, s, n1, y2, w2, alpha2);
 }
 
 template <typename T, typename TX, typename TO, bool HAS_W>
@@ -593,17 +648,23 @@ static void launch_spmv_w(const Sell<T> &A, const TX *x, TO *y, const TO *w, dou
   }
 }
 
-template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL = false>
-static void launch_k(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
-                     hipStream_t s, int32_t n1 = 0, TO *y2 = nullptr, const TO *w2 = nullptr, double alpha2 = 0) {
+template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL, int B>
+static void launch_kb(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
+                      hipStream_t s, int32_t n1, TO *y2, const TO *w2, double alpha2) {
   const int64_t threads = (int64_t)A.nslices * 64;
   const dim3 grid((unsigned)((threads + 255) / 256));
   if (A.col16)
-    hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, HAS_W, K, DUAL, uint16_t>), grid, dim3(256), 0, s, A.nslices, A.sptr,
-                       A.meta, A.col16, A.cbase, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
+    hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, HAS_W, K, DUAL, uint16_t, B>), grid, dim3(256), 0, s, A.nslices,
+                       A.sptr, A.meta, A.col16, A.cbase, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
   else
-    hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, HAS_W, K, DUAL, int32_t>), grid, dim3(256), 0, s, A.nslices, A.sptr,
-                       A.meta, A.col, nullptr, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
+    hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, HAS_W, K, DUAL, int32_t, B>), grid, dim3(256), 0, s, A.nslices,
+                       A.sptr, A.meta, A.col, nullptr, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
+}
+template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL = false>
+static void launch_k(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
+                     hipStream_t s, int32_t n1 = 0, TO *y2 = nullptr, const TO *w2 = nullptr, double alpha2 = 0) {
+  if (A.b == 1) launch_kb<T, TX, TO, HAS_W, K, DUAL, 1>(A, x, y, w, alpha, ctrl, s, n1, y2, w2, alpha2);
+  else launch_kb<T, TX, TO, HAS_W, K, DUAL, 3>(A, x, y, w, alpha, ctrl, s, n1, y2, w2, alpha2);
 }
 
 template <typename T, typename TX, typename TO, bool HAS_W>
@@ -683,17 +744,23 @@ int spmv_dot_blocks(const Sell<double> &A) {
   return (int)((dot_groups(A) + per - 1) / per);
 }
 
-template <int L>
-static void launch_dot_l(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
-                         hipStream_t s) {
+template <int L, int B>
+static void launch_dot_lb(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
+                          hipStream_t s) {
   const dim3 grid((unsigned)spmv_dot_blocks(A));
   const int32_t per = dot_per_block(A);
   if (A.col16)
-    hipLaunchKernelGGL((k_sell_spmv_dot<uint16_t, L>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col16, A.cbase, A.val, x,
-                       y, part, ctrl, per);
+    hipLaunchKernelGGL((k_sell_spmv_dot<uint16_t, L, B>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col16,
+                       A.cbase, A.val, x, y, part, ctrl, per);
   else
-    hipLaunchKernelGGL((k_sell_spmv_dot<int32_t, L>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col, nullptr, A.val, x, y,
-                       part, ctrl, per);
+    hipLaunchKernelGGL((k_sell_spmv_dot<int32_t, L, B>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col, nullptr,
+                       A.val, x, y, part, ctrl, per);
+}
+template <int L>
+static void launch_dot_l(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
+                         hipStream_t s) {
+  if (A.b == 1) launch_dot_lb<L, 1>(A, x, y, part, ctrl, s);
+  else launch_dot_lb<L, 3>(A, x, y, part, ctrl, s);
 }
 
 void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *part, const PcgCtrl *ctrl,
@@ -707,16 +774,21 @@ void launch_spmv_dot(const Sell<double> &A, const double *x, double *y, double *
   }
 }
 
-template <int L>
-static void launch_abs_l(const Sell<double> &A, const double *u, const double *f, double *part, hipStream_t s) {
+template <int L, int B>
+static void launch_abs_lb(const Sell<double> &A, const double *u, const double *f, double *part, hipStream_t s) {
   const dim3 grid((unsigned)spmv_dot_blocks(A));
   const int32_t per = dot_per_block(A);
   if (A.col16)
-    hipLaunchKernelGGL((k_sell_abs_bound<uint16_t, L>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col16, A.cbase,
-                       A.val, u, f, part, per);
+    hipLaunchKernelGGL((k_sell_abs_bound<uint16_t, L, B>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col16,
+                       A.cbase, A.val, u, f, part, per);
   else
-    hipLaunchKernelGGL((k_sell_abs_bound<int32_t, L>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col, nullptr,
+    hipLaunchKernelGGL((k_sell_abs_bound<int32_t, L, B>), grid, dim3(kDotThreads), 0, s, A.n, A.sptr, A.col, nullptr,
                        A.val, u, f, part, per);
+}
+template <int L>
+static void launch_abs_l(const Sell<double> &A, const double *u, const double *f, double *part, hipStream_t s) {
+  if (A.b == 1) launch_abs_lb<L, 1>(A, u, f, part, s);
+  else launch_abs_lb<L, 3>(A, u, f, part, s);
 }
 
 void launch_abs_bound(const Sell<double> &A, const double *u, const double *f, double *part, hipStream_t s) {

@@ -79,7 +79,7 @@ extern "C" aspamg_status aspamg_apply_operator_noalloc(aspamg_handle h, int32_t 
       launch_spmv<double, double, double>(*M[which], x_dev, y_dev, nullptr, 1.0, nullptr, s);
     } else {
       const Sell<float> *M[6] = {&L.A32, &L.G32, &L.GT32, &L.P32, &L.R32, &L.M32};
-      const int64_t nx = (int64_t)M[which]->nc * 3, ny = (int64_t)M[which]->n * 3;
+      const int64_t nx = (int64_t)M[which]->nc * h->b, ny = (int64_t)M[which]->n * h->b;
       const int64_t need = round_up(nx, 64) + ny;
       if (need > kScratchFloats)
         fail(ASPAMG_EINVAL, "aspamg_apply_operator_noalloc: the operator needs " + std::to_string(need) +

@@ -123,11 +123,12 @@ void to_host(hipStream_t s, T *hdst, const T *d, size_t n) {
 // ------------------------------------------------------------------------
 struct FsaiState {
   int32_t n;
+  int b;                          // unknowns per node
   int rho;                        // nodes per growth step
   std::vector<int32_t> nb;        // |B| per row
   std::vector<int32_t> nodes;     // n * kMaxFsaiNodes
-  std::vector<double> g;          // n * 3 * gstride
-  std::vector<double> psi;        // n * 3
+  std::vector<double> g;          // n * b * gstride
+  std::vector<double> psi;        // n * b
   std::vector<int32_t> add;       // n * rho: the next growth of the row's current pattern, -1 padded
   static constexpr int gstride = 3 * kMaxFsaiNodes + 3;
 };
@@ -137,6 +138,7 @@ void fsai_factor(aspamg_ctx *h, const Level &L, FsaiState &F, const std::vector<
   if (rows.empty()) return;
   const int32_t nr = (int32_t)rows.size();
   const int gs = FsaiState::gstride;
+  const int b = F.b;
   // chunk to bound device memory
   const int32_t chunk = 1 << 17;
   for (int32_t c0 = 0; c0 < nr; c0 += chunk) {
@@ -153,14 +155,14 @@ void fsai_factor(aspamg_ctx *h, const Level &L, FsaiState &F, const std::vector<
       const int32_t I = rows[c0 + i];
       std::memcpy(pnodes.data() + pptr[i], F.nodes.data() + (size_t)I * kMaxFsaiNodes, F.nb[I] * sizeof(int32_t));
     }
-    const size_t gn = (size_t)3 * (3 * (size_t)pptr[m] + 3 * (size_t)m);   // compact g entries
-    Scratch drows(m * 4), dptr((m + 1) * 4), dnodes(pnodes.size() * 4), dg(gn * 8), dpsi((size_t)m * 3 * 8),
+    const size_t gn = (size_t)b * (b * (size_t)pptr[m] + b * (size_t)m);   // compact g entries
+    Scratch drows(m * 4), dptr((m + 1) * 4), dnodes(pnodes.size() * 4), dg(gn * 8), dpsi((size_t)m * b * 8),
         dfail(4);
     to_device(h->stream, drows.as<int32_t>(), rows.data() + c0, m);
     to_device(h->stream, dptr.as<int32_t>(), pptr.data(), m + 1);
     to_device(h->stream, dnodes.as<int32_t>(), pnodes.data(), pnodes.size());
     HIPCHK(hipMemsetAsync(dfail.p, 0, 4, h->stream));
-    const int mmax = 3 * maxnb + 3;
+    const int mmax = b * maxnb + b;
     launch_fsai_rows(L.dA, m, drows.as<int32_t>(), dptr.as<int32_t>(), dnodes.as<int32_t>(), mmax, dg.as<double>(),
                      dpsi.as<double>(), dfail.as<int32_t>(), h->stream);
     HIPCHK(hipGetLastError());
@@ -169,7 +171,7 @@ void fsai_factor(aspamg_ctx *h, const Level &L, FsaiState &F, const std::vector<
                      h->p.quant_bits, dadd.as<int32_t>(), h->stream);
     HIPCHK(hipGetLastError());
     double *g = static_cast<double *>(staging(h, gn * 8));
-    std::vector<double> psi((size_t)m * 3);
+    std::vector<double> psi((size_t)m * b);
     std::vector<int32_t> add((size_t)m * F.rho);
     int32_t bad = 0;
     to_host(h->stream, &bad, dfail.as<int32_t>(), 1);
@@ -180,14 +182,14 @@ void fsai_factor(aspamg_ctx *h, const Level &L, FsaiState &F, const std::vector<
 #pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < m; i++) {
       const int32_t I = rows[c0 + i];
-      const int rs = 3 * F.nb[I] + 3;
-      const double *src = g + (size_t)3 * (3 * (size_t)pptr[i] + 3 * (size_t)i);
-      for (int d = 0; d < 3; d++) {
-        double *dst = F.g.data() + ((size_t)I * 3 + d) * gs;
+      const int rs = b * F.nb[I] + b;
+      const double *src = g + (size_t)b * (b * (size_t)pptr[i] + b * (size_t)i);
+      for (int d = 0; d < b; d++) {
+        double *dst = F.g.data() + ((size_t)I * b + d) * gs;
         std::memcpy(dst, src + (size_t)d * rs, rs * sizeof(double));
         std::memset(dst + rs, 0, (gs - rs) * sizeof(double));
       }
-      std::memcpy(F.psi.data() + (size_t)I * 3, psi.data() + (size_t)i * 3, 3 * sizeof(double));
+      std::memcpy(F.psi.data() + (size_t)I * b, psi.data() + (size_t)i * b, b * sizeof(double));
       std::memcpy(F.add.data() + (size_t)I * F.rho, add.data() + (size_t)i * F.rho, F.rho * sizeof(int32_t));
     }
   }
@@ -195,7 +197,7 @@ void fsai_factor(aspamg_ctx *h, const Level &L, FsaiState &F, const std::vector<
 
 inline double psi_sum(const FsaiState &F, int32_t I) {
   double s = 0.0;
-  for (int d = 0; d < 3; d++) s += F.psi[(size_t)I * 3 + d];
+  for (int d = 0; d < F.b; d++) s += F.psi[(size_t)I * F.b + d];
   return s;
 }
 
@@ -221,22 +223,24 @@ HostBSR fsai_assemble(const FsaiState &F) {
   HostBSR G;
   const int32_t n = F.n;
   const int gs = FsaiState::gstride;
+  const int b = F.b, bb = b * b;
   G.n = G.nc = n;
+  G.b = b;
   G.rp.assign(n + 1, 0);
   for (int32_t i = 0; i < n; i++) G.rp[i + 1] = G.rp[i] + F.nb[i] + 1;
   G.ci.resize(G.rp[n]);
-  G.v.assign((size_t)G.rp[n] * 9, 0.0);
+  G.v.assign((size_t)G.rp[n] * bb, 0.0);
 #pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < n; i++) {
     const int nb = F.nb[i];
-    const double *g = F.g.data() + (size_t)i * 3 * gs;
+    const double *g = F.g.data() + (size_t)i * b * gs;
     for (int p = 0; p <= nb; p++) {
       const int64_t q = G.rp[i] + p;
       G.ci[q] = p < nb ? F.nodes[(size_t)i * kMaxFsaiNodes + p] : i;
-      for (int d = 0; d < 3; d++)
-        for (int e = 0; e < 3; e++) {
+      for (int d = 0; d < b; d++)
+        for (int e = 0; e < b; e++) {
           if (p == nb && e > d) continue;
-          G.v[(size_t)q * 9 + d * 3 + e] = g[d * gs + p * 3 + e];
+          G.v[(size_t)q * bb + d * b + e] = g[d * gs + p * b + e];
         }
     }
   }
@@ -246,7 +250,7 @@ HostBSR fsai_assemble(const FsaiState &F) {
 // lambda_1(G A G^T) by plain Lanczos on the GPU (FP64 SELL products), the
 // largest Ritz value by Sturm bisection.
 double lanczos_gagt(aspamg_ctx *h, const Level &L, const Sell<double> &G, const Sell<double> &GT, int steps) {
-  const int64_t n = (int64_t)L.A.n * 3;
+  const int64_t n = (int64_t)L.A.n * L.A.b;
   hipStream_t s = h->stream;
   std::vector<double> w(n);
   for (int64_t i = 0; i < n; i++) {
@@ -335,10 +339,11 @@ void build_fsai(aspamg_ctx *h, Level &L) {
   const int32_t n = L.A.n;
   FsaiState F;
   F.n = n;
+  F.b = L.A.b;
   F.nb.assign(n, 0);
   F.nodes.assign((size_t)n * kMaxFsaiNodes, -1);
-  F.g.assign((size_t)n * 3 * FsaiState::gstride, 0.0);
-  F.psi.assign((size_t)n * 3, 0.0);
+  F.g.assign((size_t)n * F.b * FsaiState::gstride, 0.0);
+  F.psi.assign((size_t)n * F.b, 0.0);
   F.rho = p.rho_blocks;
   F.add.assign((size_t)n * F.rho, -1);
   std::vector<int32_t> active(n);
@@ -590,7 +595,8 @@ bool ritz_basis(const std::vector<double> &Ms, const std::vector<double> &Mz, in
 // divided by g_rr, then g_rk x_r is subtracted from x_k for every k < r of row
 // r; each column sees exactly that sequence of operations.
 static void gt_solve(const HostBSR &G, std::vector<double> &V, int nt) {
-  const int64_t nr = (int64_t)G.n * 3;
+  const int b = G.b, bb = b * b;
+  const int64_t nr = (int64_t)G.n * b;
   std::vector<int64_t> diag(G.n);
   for (int32_t I = 0; I < G.n; I++) {
     int64_t kd = G.rp[I + 1] - 1;
@@ -602,14 +608,14 @@ static void gt_solve(const HostBSR &G, std::vector<double> &V, int nt) {
   for (int c = 0; c < nt; c++) {
     double *x = V.data() + c;
     for (int64_t r = nr - 1; r >= 0; r--) {
-      const int32_t I = (int32_t)(r / 3);
-      const int d = (int)(r % 3);
-      const double xr = x[r * nt] / G.v[diag[I] * 9 + d * 3 + d];
+      const int32_t I = (int32_t)(r / b);
+      const int d = (int)(r % b);
+      const double xr = x[r * nt] / G.v[diag[I] * bb + d * b + d];
       x[r * nt] = xr;
       for (int64_t k = G.rp[I]; k < G.rp[I + 1]; k++) {
         const int32_t J = G.ci[k];
-        const int ne = J < I ? 3 : d;     // in the diagonal block only the columns e < d
-        for (int e = 0; e < ne; e++) x[((int64_t)J * 3 + e) * nt] -= G.v[k * 9 + d * 3 + e] * xr;
+        const int ne = J < I ? b : d;     // in the diagonal block only the columns e < d
+        for (int e = 0; e < ne; e++) x[((int64_t)J * b + e) * nt] -= G.v[k * bb + d * b + e] * xr;
       }
     }
   }
@@ -620,7 +626,7 @@ static void gt_solve(const HostBSR &G, std::vector<double> &V, int nt) {
 // S z = lambda z with v = G^T z, hence V = G^T Z at the end); V0 approximates
 // the near kernel of A, so it enters as G^{-T} V0: Z0 = (I - S) G^{-T} V0.
 void srqcg(aspamg_ctx *h, Level &L, int nt, int kmax) {
-  const int64_t n = (int64_t)L.A.n * 3;
+  const int64_t n = (int64_t)L.A.n * L.A.b;
   const size_t cols = (size_t)n * nt;
   hipStream_t s = h->stream;
   // inner products in the fixed order of 256-entry blocks and products summed
@@ -646,6 +652,7 @@ void srqcg(aspamg_ctx *h, Level &L, int nt, int kmax) {
       to_device(s, v.as<double>(), M.v.data(), M.v.size());
       d.n = M.n;
       d.nc = M.nc;
+      d.b = M.b;
       d.nnzb = M.nnzb();
       d.rp = rp.as<int32_t>();
       d.ci = ci.as<int32_t>();
@@ -780,7 +787,7 @@ std::unique_ptr<DevGraph> strong_graph_device(aspamg_ctx *h, const Level &L, con
   hipStream_t s = h->stream;
   const int theta = p.theta;
   Scratch dsq((size_t)n * 8), dkeep((size_t)n * theta * 4), dnk((size_t)n * 4), dcnt((size_t)n * 4);
-  launch_node_norms(n, dV, ntv, dsq.as<double>(), s);
+  launch_node_norms(n, dV, ntv, L.A.b, dsq.as<double>(), s);
   launch_strong_topk(L.dA, dexcl, dV, ntv, dsq.as<double>(), theta, p.quant_bits, dkeep.as<int32_t>(),
                      dnk.as<int32_t>(), s);
   HIPCHK(hipMemsetAsync(dcnt.p, 0, (size_t)n * 4, s));
@@ -837,22 +844,23 @@ void build_prolongation(aspamg_ctx *h, Level &L, const DevGraph &S, const int8_t
   const int32_t n = L.A.n;
   const int ntv = h->ntv;
   const int nmax = std::min(p.n_max, kMaxPEntries);
+  const int b = L.A.b, bb = b * b;
   hipStream_t s = h->stream;
-  L.pcount.assign((size_t)n * 3, 0);
-  L.pcols.assign((size_t)n * 3 * p.n_max, -1);
+  L.pcount.assign((size_t)n * b, 0);
+  L.pcols.assign((size_t)n * b * p.n_max, -1);
   // interpolation entries of every fine scalar row, chosen on the device
   std::vector<int32_t> fnodes;
   for (int32_t I = 0; I < n; I++)
     if (L.cf[I] == 0) fnodes.push_back(I);
-  std::vector<int32_t> selfine((size_t)n * 3 * kMaxPEntries, 0);
+  std::vector<int32_t> selfine((size_t)n * b * kMaxPEntries, 0);
   {
-    Scratch dfn(fnodes.size() * 4), dcnt((size_t)n * 3 * 4), dsel(selfine.size() * 4), derr(4);
+    Scratch dfn(fnodes.size() * 4), dcnt((size_t)n * b * 4), dsel(selfine.size() * 4), derr(4);
     to_device(s, dfn.as<int32_t>(), fnodes.data(), fnodes.size());
-    HIPCHK(hipMemsetAsync(dcnt.p, 0, (size_t)n * 3 * 4, s));
+    HIPCHK(hipMemsetAsync(dcnt.p, 0, (size_t)n * b * 4, s));
     HIPCHK(hipMemsetAsync(dsel.p, 0, selfine.size() * 4, s));
     HIPCHK(hipMemsetAsync(derr.p, 0, 4, s));
     launch_dpls_rows((int32_t)fnodes.size(), dfn.as<int32_t>(), S.rp.as<int64_t>(), S.ci.as<int32_t>(), dcf, dV, ntv,
-                     p.d_p, nmax, q(p.kappa_p), p.eps_p, p.quant_bits, dcnt.as<int32_t>(), dsel.as<int32_t>(),
+                     b, p.d_p, nmax, q(p.kappa_p), p.eps_p, p.quant_bits, dcnt.as<int32_t>(), dsel.as<int32_t>(),
                      derr.as<int32_t>(), s);
     HIPCHK(hipGetLastError());
     int32_t err = 0;
@@ -860,17 +868,17 @@ void build_prolongation(aspamg_ctx *h, Level &L, const DevGraph &S, const int8_t
     if (err)
       fail(ASPAMG_EINVAL, "DPLS: a fine node has more interpolation candidates than the device selection holds "
                           "(1024 nodes within distance d_p, 320 coarse ones, 5120 candidate values)");
-    to_host(s, L.pcount.data(), dcnt.as<int32_t>(), (size_t)n * 3);
+    to_host(s, L.pcount.data(), dcnt.as<int32_t>(), (size_t)n * b);
     to_host(s, selfine.data(), dsel.as<int32_t>(), selfine.size());
   }
-  for (size_t r = 0; r < (size_t)n * 3; r++)
+  for (size_t r = 0; r < (size_t)n * b; r++)
     for (int k = 0; k < L.pcount[r]; k++) {
       const int32_t f = selfine[r * kMaxPEntries + k];
-      L.pcols[r * p.n_max + k] = L.cidx[f / 3] * 3 + f % 3;
+      L.pcols[r * p.n_max + k] = L.cidx[f / b] * b + f % b;
     }
   // weights on the GPU: normal equations of the chosen columns
   std::vector<int32_t> rows, cnt, sel;
-  for (int64_t r = 0; r < (int64_t)n * 3; r++) {
+  for (int64_t r = 0; r < (int64_t)n * b; r++) {
     if (L.pcount[r] == 0) continue;
     rows.push_back((int32_t)r);
     cnt.push_back(L.pcount[r]);
@@ -890,13 +898,14 @@ void build_prolongation(aspamg_ctx *h, Level &L, const DevGraph &S, const int8_t
       for (int k = 0; k < cnt[i]; k++)
         if (std::isnan(w[i * kMaxPEntries + k])) fail(ASPAMG_ENOT_SPD, "DPLS: weight Gram matrix not positive definite");
   }
-  std::vector<double> wr((size_t)n * 3 * kMaxPEntries, 0.0);
+  std::vector<double> wr((size_t)n * b * kMaxPEntries, 0.0);
   for (size_t i = 0; i < rows.size(); i++)
     std::memcpy(wr.data() + (size_t)rows[i] * kMaxPEntries, w.data() + i * kMaxPEntries, kMaxPEntries * 8);
   // assemble P: C rows I3 at (I, c(I)); F rows: union of the chosen coarse nodes
   HostBSR &P = L.P;
   P.n = n;
   P.nc = L.nc;
+  P.b = b;
   P.rp.assign(n + 1, 0);
   // coarse nodes of each row, sorted and unique (at most 3 kMaxPEntries)
   constexpr int kRowMax = 3 * kMaxPEntries;
@@ -907,9 +916,9 @@ void build_prolongation(aspamg_ctx *h, Level &L, const DevGraph &S, const int8_t
     int m = 0;
     if (L.cf[I] == 1) rc[m++] = L.cidx[I];
     else if (L.cf[I] == 0) {
-      for (int d = 0; d < 3; d++) {
-        const size_t r = (size_t)I * 3 + d;
-        for (int k = 0; k < L.pcount[r]; k++) rc[m++] = L.pcols[r * p.n_max + k] / 3;
+      for (int d = 0; d < b; d++) {
+        const size_t r = (size_t)I * b + d;
+        for (int k = 0; k < L.pcount[r]; k++) rc[m++] = L.pcols[r * p.n_max + k] / b;
       }
       std::sort(rc, rc + m);
       m = (int)(std::unique(rc, rc + m) - rc);
@@ -918,22 +927,22 @@ void build_prolongation(aspamg_ctx *h, Level &L, const DevGraph &S, const int8_t
   }
   for (int32_t I = 0; I < n; I++) P.rp[I + 1] = P.rp[I] + nrc[I];
   P.ci.resize(P.rp[n]);
-  P.v.assign((size_t)P.rp[n] * 9, 0.0);
+  P.v.assign((size_t)P.rp[n] * bb, 0.0);
 #pragma omp parallel for schedule(static)
   for (int32_t I = 0; I < n; I++) {
     const int64_t base = P.rp[I];
     const int32_t *rc = rowc.data() + (size_t)I * kRowMax;
     std::copy(rc, rc + nrc[I], P.ci.begin() + base);
     if (L.cf[I] == 1) {
-      for (int d = 0; d < 3; d++) P.v[(size_t)base * 9 + d * 4] = 1.0;
+      for (int d = 0; d < b; d++) P.v[(size_t)base * bb + d * (b + 1)] = 1.0;
     } else if (L.cf[I] == 0) {
-      for (int d = 0; d < 3; d++) {
-        const size_t r = (size_t)I * 3 + d;
+      for (int d = 0; d < b; d++) {
+        const size_t r = (size_t)I * b + d;
         for (int k = 0; k < L.pcount[r]; k++) {
           const int32_t sc = L.pcols[r * p.n_max + k];
-          const int32_t cnod = sc / 3, e = sc % 3;
+          const int32_t cnod = sc / b, e = sc % b;
           const int64_t qpos = base + (std::lower_bound(rc, rc + nrc[I], cnod) - rc);
-          P.v[(size_t)qpos * 9 + d * 3 + e] = wr[r * kMaxPEntries + k];
+          P.v[(size_t)qpos * bb + d * b + e] = wr[r * kMaxPEntries + k];
         }
       }
     }
@@ -947,6 +956,7 @@ HostBSR spgemm_pattern(const HostBSR &X, const HostBSR &Y, bool host_values = tr
   HostBSR Z;
   Z.n = X.n;
   Z.nc = Y.nc;
+  Z.b = X.b;
   Z.rp.assign(X.n + 1, 0);
   // two passes over the product structure: row lengths, then the columns of
   // each row written in place and sorted
@@ -990,7 +1000,7 @@ HostBSR spgemm_pattern(const HostBSR &X, const HostBSR &Y, bool host_values = tr
       std::sort(Z.ci.begin() + Z.rp[i], Z.ci.begin() + Z.rp[i + 1]);
     }
   }
-  if (host_values) Z.v.assign((size_t)Z.rp[X.n] * 9, 0.0);
+  if (host_values) Z.v.assign((size_t)Z.rp[X.n] * Z.bb(), 0.0);
   return Z;
 }
 
@@ -1000,6 +1010,7 @@ struct DevTmp {
     DevBSR d;
     d.n = M.n;
     d.nc = M.nc;
+    d.b = M.b;
     d.nnzb = M.nnzb();
     if (d.nnzb >= (int64_t)INT32_MAX) fail(ASPAMG_EINVAL, "operator too large for int32 block indices");
     std::vector<int32_t> rp32(M.rp.begin(), M.rp.end());
@@ -1007,7 +1018,7 @@ struct DevTmp {
     d.rp = s.back()->as<int32_t>();
     s.push_back(new Scratch(std::max<size_t>(M.ci.size(), 1) * 4));
     d.ci = s.back()->as<int32_t>();
-    s.push_back(new Scratch(std::max<size_t>(M.v.size(), 1) * 8));
+    s.push_back(new Scratch(std::max<size_t>((size_t)M.nnzb() * M.bb(), 1) * 8));
     d.v = s.back()->as<double>();
     to_device(st, d.rp, rp32.data(), rp32.size());
     to_device(st, d.ci, M.ci.data(), M.ci.size());
@@ -1028,12 +1039,13 @@ HostBSR galerkin(aspamg_ctx *h, const Level &L, HostBSR *AP, double **dPAP) {
   HostBSR T = spgemm_pattern(L.A, L.P, false);
   HostBSR Ac = spgemm_pattern(R, T);
   const int64_t nP = L.P.nnzb(), nT = T.nnzb();
-  double *stack = dalloc<double>(h, (size_t)std::max<int64_t>(nP + nT, 1) * 9);
+  const int bb = L.P.bb();
+  double *stack = dalloc<double>(h, (size_t)std::max<int64_t>(nP + nT, 1) * bb);
   DevTmp tmp;
   DevBSR dP = tmp.make(L.P, h->stream, true), dR = tmp.make(R, h->stream, true);
   DevBSR dT = tmp.make(T, h->stream, false), dC = tmp.make(Ac, h->stream, false);
-  dT.v = stack + (size_t)nP * 9;
-  if (nP > 0) HIPCHK(hipMemcpyAsync(stack, dP.v, (size_t)nP * 72, hipMemcpyDeviceToDevice, h->stream));
+  dT.v = stack + (size_t)nP * bb;
+  if (nP > 0) HIPCHK(hipMemcpyAsync(stack, dP.v, (size_t)nP * bb * 8, hipMemcpyDeviceToDevice, h->stream));
   launch_spgemm_ap(L.dA, dP, dT, h->stream);
   launch_spgemm_rt(dR, dT, dC, h->stream);
   HIPCHK(hipGetLastError());
@@ -1049,6 +1061,7 @@ HostBSR stack_rows(const HostBSR &P, const HostBSR &AP) {
   HostBSR S;
   S.n = P.n + AP.n;
   S.nc = P.nc;
+  S.b = P.b;
   S.rp.resize((size_t)S.n + 1);
   for (int32_t i = 0; i <= P.n; i++) S.rp[i] = P.rp[i];
   for (int32_t i = 1; i <= AP.n; i++) S.rp[P.n + i] = P.rp[P.n] + AP.rp[i];
@@ -1059,13 +1072,14 @@ HostBSR stack_rows(const HostBSR &P, const HostBSR &AP) {
 
 // dense coarsest factor and explicit inverse (L^{-T} L^{-1})
 void build_coarse(aspamg_ctx *h, const HostBSR &A) {
-  const int32_t nd = A.n * 3;
+  const int b = A.b, bb = b * b;
+  const int32_t nd = A.n * b;
   if (nd > h->p.dense_max_dof) fail(ASPAMG_EINVAL, "coarsest level too large for a dense factorisation");
   std::vector<double> M((size_t)nd * nd, 0.0), Lm((size_t)nd * nd, 0.0);
   for (int32_t i = 0; i < A.n; i++)
     for (int64_t k = A.rp[i]; k < A.rp[i + 1]; k++)
-      for (int d = 0; d < 3; d++)
-        for (int e = 0; e < 3; e++) M[(size_t)(i * 3 + d) * nd + A.ci[k] * 3 + e] = A.v[(size_t)k * 9 + d * 3 + e];
+      for (int d = 0; d < b; d++)
+        for (int e = 0; e < b; e++) M[(size_t)(i * b + d) * nd + A.ci[k] * b + e] = A.v[(size_t)k * bb + d * b + e];
   // left-looking Cholesky, column by column, in one parallel region.  spd is
   // written only inside the single and read only after its barrier, so every
   // thread leaves the loop at the same column.
@@ -1124,8 +1138,8 @@ void build_coarse(aspamg_ctx *h, const HostBSR &A) {
 void merge_smoother(aspamg_ctx *h, Level &L) {
   const HostBSR GT = transpose(L.G);
   HostBSR M = spgemm_pattern(GT, L.G, false);
-  if ((double)M.nnzb() * 38.0 > kMergeMaxBytes) return;
-  double *dM = dalloc<double>(h, (size_t)std::max<int64_t>(M.nnzb(), 1) * 9);
+  if ((double)M.nnzb() * (4.0 * M.bb() + 2.0) > kMergeMaxBytes) return;   // FP32 values + 16-bit columns
+  double *dM = dalloc<double>(h, (size_t)std::max<int64_t>(M.nnzb(), 1) * M.bb());
   {
     DevTmp tmp;
     DevBSR dGT = tmp.make(GT, h->stream, true), dG = tmp.make(L.G, h->stream, true);
@@ -1172,7 +1186,8 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     L.A64 = upload_sell<double>(h, L.A, l == 0 ? kKpLanes : 0, true, L.dA.v);
     L.A32 = derive_fp32(h, L.A64);
     clk.tick(l, "upload A");
-    if ((int64_t)N * 3 <= p.coarse_max_dof || l == p.max_levels - 1 || l == 31 || ntv == 0) {
+    const int b = L.A.b;
+    if ((int64_t)N * b <= p.coarse_max_dof || l == p.max_levels - 1 || l == 31 || ntv == 0) {
       L.coarsest = true;
       break;
     }
@@ -1182,7 +1197,7 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
       srqcg(h, L, ntv, p.n_rq);
       clk.tick(l, "test space");
     }
-    orthonormalize(L.V, (int64_t)N * 3, ntv);
+    orthonormalize(L.V, (int64_t)N * b, ntv);
     std::vector<int8_t> excl(N);
     for (int32_t i = 0; i < N; i++) excl[i] = is_decoupled(L.A, i);
     Scratch dexcl((size_t)N), dV(L.V.size() * 8), dcf((size_t)N);
@@ -1231,10 +1246,10 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     AP = HostBSR();
     dfree(h, dPAP);
     clk.tick(l, "upload G P R");
-    std::vector<double> Vc((size_t)nc * 3 * ntv);
+    std::vector<double> Vc((size_t)nc * b * ntv);
     for (int32_t i = 0; i < N; i++)
       if (L.cidx[i] >= 0)
-        std::memcpy(Vc.data() + (size_t)L.cidx[i] * 3 * ntv, L.V.data() + (size_t)i * 3 * ntv, 3 * ntv * sizeof(double));
+        std::memcpy(Vc.data() + (size_t)L.cidx[i] * b * ntv, L.V.data() + (size_t)i * b * ntv, b * ntv * sizeof(double));
     h->lev.emplace_back();
     h->lev[l + 1].A = std::move(Ac);
     h->lev[l + 1].V = std::move(Vc);

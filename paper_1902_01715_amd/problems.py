@@ -516,3 +516,140 @@ CONFIGS = {
     "c4": c4_multiload,
     "c5": c5_simp,
 }
+
+
+# ----------------------------------------------------------------------------
+# Scalar (point-wise) inputs on linear tetrahedra (P1), the element family of
+# most of the paper's test matrices (Section 4, Table "Test matrices"), in
+# plain CSR for the block size b = 1.
+# ----------------------------------------------------------------------------
+# the six tetrahedra of a hexahedron sharing its diagonal 0-6 (local hex node
+# numbers as above); neighbouring hexahedra split their shared faces alike
+_HEX_TETS = np.array([[0, 1, 2, 6], [0, 2, 3, 6], [0, 3, 7, 6], [0, 7, 4, 6], [0, 4, 5, 6], [0, 5, 1, 6]])
+
+
+@dataclasses.dataclass
+class ScalarProblem:
+    """A synthetic SPD system in scalar CSR (block size 1)."""
+    name: str
+    coords: np.ndarray      # (N, 3) nodes of the mesh
+    tets: np.ndarray        # (n_el, 4) int64
+    row_ptr: np.ndarray     # (n+1,) int32
+    col: np.ndarray         # (nnz,) int32, ascending per row
+    vals: np.ndarray        # (nnz, 1, 1) float64
+    f: np.ndarray           # (n,) float64
+    V0: np.ndarray          # (n, 1, n_tv) near-null space of the operator without constraints
+    dirichlet: np.ndarray   # (n,) bool: decoupled unknowns (identity rows)
+
+    @property
+    def n(self) -> int:
+        return self.row_ptr.size - 1
+
+    @property
+    def n_dof(self) -> int:
+        return self.n
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.vals.reshape(-1), self.col, self.row_ptr), shape=(self.n, self.n))
+
+
+def tet_mesh(nx, ny, nz, jitter=0.2, seed=0):
+    """Unit box in nx*ny*nz hexahedra, six tetrahedra each, interior nodes
+    moved by U[-jitter h, jitter h] per axis (seeded)."""
+    coords = structured_nodes(nx, ny, nz, 1.0, 1.0, 1.0)
+    hexes = structured_conn(nx, ny, nz).astype(np.int64)
+    if jitter > 0:
+        h = np.array([1.0 / nx, 1.0 / ny, 1.0 / nz])
+        move = np.random.default_rng(seed).uniform(-jitter, jitter, coords.shape) * h
+        inner = ~boundary_node_mask(nx, ny, nz)
+        coords = coords + np.where(inner[:, None], move, 0.0)
+    tets = hexes[:, _HEX_TETS].reshape(-1, 4)
+    # positive orientation
+    X = coords[tets]
+    vol = np.einsum("ij,ij->i", np.cross(X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]), X[:, 3] - X[:, 0])
+    flip = vol < 0
+    tets[flip] = tets[flip][:, [0, 2, 1, 3]]
+    return coords, tets
+
+
+def _tet_gradients(X):
+    """Gradients of the four P1 shape functions and the volumes of tetrahedra X (n_el, 4, 3)."""
+    J = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)   # columns: edges
+    vol = np.linalg.det(J) / 6.0
+    Jinv = np.linalg.inv(J)                     # rows: gradients of barycentric coordinates 1..3
+    g = np.empty((X.shape[0], 4, 3))
+    g[:, 1:] = Jinv
+    g[:, 0] = -Jinv.sum(axis=1)
+    return g, vol
+
+
+def _csr_with_identity_rows(rows, cols, vals, n, fixed):
+    """Assembled CSR with the fixed unknowns decoupled: their rows and
+    columns dropped and a unit diagonal in their place."""
+    import scipy.sparse as sp
+    keep = ~(fixed[rows] | fixed[cols])
+    A = sp.coo_matrix((vals[keep], (rows[keep], cols[keep])), shape=(n, n)).tocsr()
+    A = A + sp.diags(fixed.astype(np.float64))
+    A = A.tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
+def tet_diffusion(nx, ny, nz, contrast=1e3, layers=4, jitter=0.2, seed=0):
+    """-div(kappa grad u) = 1 on P1 tetrahedra, u = 0 on z = 0, kappa = 1 and
+    `contrast` in alternating layers along z.  Test space: the constant."""
+    coords, tets = tet_mesh(nx, ny, nz, jitter, seed)
+    g, vol = _tet_gradients(coords[tets])
+    zc = coords[tets][:, :, 2].mean(axis=1)
+    kappa = np.where((np.floor(zc * layers) % 2) == 1, contrast, 1.0)
+    Ke = (kappa * vol)[:, None, None] * np.einsum("eak,ebk->eab", g, g)
+    n = coords.shape[0]
+    rows = np.repeat(tets, 4, axis=1).reshape(-1)
+    cols = np.tile(tets, (1, 4)).reshape(-1)
+    fixed = np.isclose(coords[:, 2], 0.0)
+    A = _csr_with_identity_rows(rows, cols, Ke.reshape(-1), n, fixed)
+    f = np.zeros(n)
+    np.add.at(f, tets.reshape(-1), np.repeat(vol / 4.0, 4))
+    f[fixed] = 0.0
+    V0 = np.ones((n, 1, 1))
+    return ScalarProblem(f"tetdiff{nx}x{ny}x{nz}", coords, tets, A.indptr.astype(np.int32),
+                         A.indices.astype(np.int32), A.data.reshape(-1, 1, 1).copy(), f, V0, fixed)
+
+
+def tet_elasticity(nx, ny, nz, E=1.0, nu=0.3, jitter=0.2, seed=0):
+    """Linear elasticity on P1 tetrahedra taken point-wise (one unknown per
+    displacement component, DOF = 3 node + component), clamped at z = 0,
+    uniform body force (0, 0, -1).  Test space: the six rigid-body modes, one
+    row per scalar unknown."""
+    coords, tets = tet_mesh(nx, ny, nz, jitter, seed)
+    g, vol = _tet_gradients(coords[tets])
+    lam, mu = lame(E, nu)
+    D = np.zeros((6, 6))
+    D[:3, :3] = lam
+    D[np.arange(3), np.arange(3)] += 2 * mu
+    D[np.arange(3, 6), np.arange(3, 6)] = mu
+    n_el = tets.shape[0]
+    B = np.zeros((n_el, 6, 12))
+    for a in range(4):
+        gx, gy, gz = g[:, a, 0], g[:, a, 1], g[:, a, 2]
+        B[:, 0, 3 * a] = gx
+        B[:, 1, 3 * a + 1] = gy
+        B[:, 2, 3 * a + 2] = gz
+        B[:, 3, 3 * a + 1], B[:, 3, 3 * a + 2] = gz, gy
+        B[:, 4, 3 * a], B[:, 4, 3 * a + 2] = gz, gx
+        B[:, 5, 3 * a], B[:, 5, 3 * a + 1] = gy, gx
+    Ke = vol[:, None, None] * np.einsum("eki,kl,elj->eij", B, D, B)
+    dofs = (3 * tets[:, :, None] + np.arange(3)).reshape(n_el, 12)
+    n = 3 * coords.shape[0]
+    rows = np.repeat(dofs, 12, axis=1).reshape(-1)
+    cols = np.tile(dofs, (1, 12)).reshape(-1)
+    fixed = np.repeat(np.isclose(coords[:, 2], 0.0), 3)
+    A = _csr_with_identity_rows(rows, cols, Ke.reshape(-1), n, fixed)
+    f = np.zeros(n)
+    np.add.at(f, dofs[:, 2::3].reshape(-1), -np.repeat(vol / 4.0, 4))
+    f[fixed] = 0.0
+    V0 = rigid_body_modes(coords).reshape(n, 1, 6)
+    return ScalarProblem(f"tetelast{nx}x{ny}x{nz}", coords, tets, A.indptr.astype(np.int32),
+                         A.indices.astype(np.int32), A.data.reshape(-1, 1, 1).copy(), f, V0, fixed)

@@ -1,0 +1,120 @@
+"""Block size 1: the library's scalar (point-wise) path against the oracle's
+b = 1 on linear tetrahedra (the element family of most of the paper's test
+matrices, Section 4, Table "Test matrices"), in plain CSR.
+
+Every rule of Sections 3.1-3.5 then acts on single unknowns: FSAI rows, the
+affinity of two unknowns, the C/F split of unknowns, DPLS entries.  As for the
+nodal path, index work and the sequential sums (FSAI rows, weights, Galerkin
+values) must match the oracle bit for bit, the V-cycle to 1e-11 and the solve
+to 1e-8 of the oracle's u at relative residual 1e-10."""
+import numpy as np
+import pytest
+
+from paper_1902_01715_amd import problems as PR
+
+pytestmark = pytest.mark.gpu
+
+COMMON = {"coarse_max_dof": 200, "rho_blocks": 4}
+
+
+def _v0_with_random(p, extra, seed):
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(np.concatenate([p.V0, rng.standard_normal((p.n, 1, extra))], axis=2))
+
+
+CASES = {
+    # diffusion with a 1e3 coefficient jump in four layers, constant test vector
+    "tetdiff14": (lambda: PR.tet_diffusion(14, 14, 14, contrast=1e3, layers=4, seed=1), 0, {}),
+    # elasticity taken point-wise (the paper's treatment), rigid-body modes
+    "tetelast7": (lambda: PR.tet_elasticity(7, 7, 7, seed=2), 0, {}),
+    # the paper's test space: the constant padded with random vectors, SRQCG
+    "tetdiff10_srqcg": (lambda: PR.tet_diffusion(10, 10, 10, contrast=1e2, layers=2, seed=3), 5, {"n_rq": 5}),
+}
+
+
+def _setup(p, V0, oracle_lib, **kw):
+    from paper_1902_01715_amd import aspamg
+    S = aspamg.Solver(p.row_ptr, p.col, p.vals, V0, aspamg.default_params(block_size=1, **COMMON, **kw))
+    okw = {k: v for k, v in {**COMMON, **kw}.items() if hasattr(oracle_lib.Params, k)}
+    okw["rho_b"] = COMMON["rho_blocks"]
+    H = oracle_lib.Hierarchy(p.row_ptr.astype(np.int64), p.col, p.vals, V0, oracle_lib.default_params(b=1, **okw))
+    return S, H
+
+
+@pytest.fixture(scope="module", params=[(c, t) for c in CASES for t in ("sparse", "tail")],
+                ids=lambda ct: f"{ct[0]}-{ct[1]}")
+def pair(request, cuda, oracle_lib):
+    name, tail = request.param
+    print(f"[case b=1 {name} {tail}]", flush=True)
+    make, extra, kw = CASES[name]
+    p = make()
+    V0 = _v0_with_random(p, extra, 17) if extra else p.V0
+    S, H = _setup(p, V0, oracle_lib, **kw, **({"dense_tail_dof": 0} if tail == "sparse" else {}))
+    yield name, p, S, H
+    S.close()
+
+
+def test_scalar_hierarchy_bit_exact(pair):
+    name, p, S, H = pair
+    assert H.nlev >= 3, H.nlev
+    assert S.nlev == H.nlev, (S.nlev, H.nlev)
+    for l in range(H.nlev):
+        oi, gi = H.info(l), S.level_info(l)
+        assert gi["n"] == oi["n"] and gi["nnzb_A"] == oi["nnzb_A"], l
+        A_o, A_g = H.A(l), S.level_matrix(l, 0)
+        assert np.array_equal(A_o.rp, A_g[0]) and np.array_equal(A_o.ci, A_g[1]), f"level {l}: Galerkin pattern"
+        assert np.array_equal(A_o.v, A_g[2]), f"level {l}: Galerkin values (max {np.abs(A_o.v - A_g[2]).max()})"
+        if not oi["has_G"]:
+            continue
+        G_o, G_g = H.G(l), S.level_matrix(l, 1)
+        assert np.array_equal(G_o.rp, G_g[0]) and np.array_equal(G_o.ci, G_g[1]), f"level {l}: G pattern"
+        assert np.array_equal(G_o.v, G_g[2]), f"level {l}: FSAI values (max {np.abs(G_o.v - G_g[2]).max()})"
+        cf_g, cnt_g, cols_g = S.level_split(l)
+        assert np.array_equal(H.cf(l), cf_g), f"level {l}: C/F split"
+        cnt_o, cols_o = H.P_scalar(l)
+        assert np.array_equal(cnt_o, cnt_g) and np.array_equal(cols_o, cols_g), f"level {l}: P pattern"
+        P_o, P_g = H.P(l), S.level_matrix(l, 3)
+        assert np.array_equal(P_o.rp, P_g[0]) and np.array_equal(P_o.ci, P_g[1])
+        assert np.array_equal(P_g[2], P_o.v), f"level {l}: weights (max {np.abs(P_g[2] - P_o.v).max()})"
+        assert abs(gi["omega_q"] - oi["omega_q"]) <= 1e-9 * oi["omega_q"]
+        assert gi["fsai_rounds"] == oi["fsai_rounds"]
+
+
+def test_scalar_vcycle_matches_oracle(pair):
+    import torch
+    name, p, S, H = pair
+    y = np.random.default_rng(11).standard_normal(p.n)
+    y[p.dirichlet] = 0.0
+    z_o = H.vcycle(y)
+    S.set_precision(64)
+    z_g = S.vcycle(torch.tensor(y, device="cuda")).cpu().numpy()
+    err = np.linalg.norm(z_g - z_o) / np.linalg.norm(z_o)
+    assert err <= 1e-11, err
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_scalar_solve_matches_oracle(pair, prec):
+    import torch
+    name, p, S, H = pair
+    u_o, st_o = H.pcg(p.f, 1e-10, 1000)
+    assert st_o["status"] == 0
+    S.set_precision(prec)
+    u = S.solve(torch.tensor(p.f, device="cuda")).cpu().numpy()
+    st = S.last_stats
+    err = np.linalg.norm(u - u_o) / np.linalg.norm(u_o)
+    print(f"b=1 {name} prec={prec} it={st['iterations']} (oracle {st_o['iterations']}) err={err:.2e} "
+          f"true res {st['relres_true']:.2e}", flush=True)
+    assert st["status"] == 0, st
+    assert st["relres_true"] <= 2e-10
+    assert err <= 1e-8, err
+    if prec == 64:
+        assert abs(st["iterations"] - st_o["iterations"]) <= 1
+
+
+def test_scalar_batch_is_refused(pair):
+    import torch
+    from paper_1902_01715_amd import aspamg
+    name, p, S, H = pair
+    F = torch.zeros((p.n, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(aspamg.AspamgError):
+        S.solve_batch(F)

@@ -82,3 +82,51 @@ def test_cantilever_tip_deflection_beam_theory():
     G = E / 2.0
     w_ref = P * L ** 3 / (3 * E * I) + P * L / ((5.0 / 6.0) * G * H * H)
     assert abs(w - w_ref) / w_ref < 0.05, (w, w_ref)
+
+
+# ----------------------------------------------------------------------------- P1 tetrahedra (block size 1)
+def test_tet_mesh_fills_the_box_with_positive_volumes():
+    coords, tets = PR.tet_mesh(3, 4, 2, jitter=0.25, seed=5)
+    g, vol = PR._tet_gradients(coords[tets])
+    assert tets.shape == (6 * 3 * 4 * 2, 4)
+    assert (vol > 0).all() and abs(vol.sum() - 1.0) < 1e-13
+    # every interior face is shared by exactly two tetrahedra, boundary faces by one
+    faces = np.sort(tets[:, [[0, 1, 2], [0, 1, 3], [0, 2, 3], [1, 2, 3]]].reshape(-1, 3), axis=1)
+    _, counts = np.unique(faces, axis=0, return_counts=True)
+    assert set(counts.tolist()) <= {1, 2}
+    # barycentric gradients: sum to zero, and reproduce linear fields exactly
+    assert np.abs(g.sum(axis=1)).max() < 1e-12
+    lin = coords @ np.array([0.3, -1.2, 2.0])
+    assert np.allclose(np.einsum("ea,eak->ek", lin[tets], g), [0.3, -1.2, 2.0], atol=1e-12)
+
+
+def test_tet_diffusion_is_spd_with_constant_kernel_and_total_load():
+    p = PR.tet_diffusion(4, 4, 3, contrast=1e2, layers=2, seed=1)
+    A = p.to_scipy().toarray()
+    assert np.abs(A - A.T).max() <= 1e-12 * np.abs(A).max()
+    assert np.linalg.eigvalsh(A).min() > 0
+    assert np.allclose(p.vals.shape[1:], (1, 1))
+    free = ~p.dirichlet
+    # rows away from the clamped face annihilate the constant (the kernel of the Neumann operator)
+    far = free & (p.coords[:, 2] > 0.4)
+    assert np.abs((A @ np.ones(p.n))[far]).max() <= 1e-12 * np.abs(A).max()
+    # f = integral of the unit source over the box, minus the clamped nodes' share
+    assert 0.0 < p.f.sum() < 1.0 and np.all(p.f[p.dirichlet] == 0.0)
+
+
+def test_tet_elasticity_rigid_modes_and_patch():
+    p = PR.tet_elasticity(3, 3, 3, seed=2)
+    K = p.to_scipy().toarray()
+    assert np.abs(K - K.T).max() <= 1e-12 * np.abs(K).max()
+    assert np.linalg.eigvalsh(K).min() > 0
+    # rows whose element neighbourhood avoids the clamped face annihilate the rigid-body modes
+    nodes_far = p.coords[:, 2] > 0.5
+    rows = np.repeat(nodes_far, 3)
+    V = p.V0.reshape(p.n, 6)
+    assert np.abs((K @ V)[rows]).max() <= 1e-11 * np.abs(K).max()
+    # a linear displacement field has the same strain in every tetrahedron
+    Gm = np.array([[0.1, 0.0, -0.2], [0.3, 0.2, 0.0], [0.0, -0.1, 0.4]])
+    u_lin = p.coords @ Gm                              # u_i = sum_k x_k Gm[k, i]
+    g, _ = PR._tet_gradients(p.coords[p.tets])
+    grad = np.einsum("eai,eak->eik", u_lin[p.tets], g)  # du_i / dx_k per element
+    assert np.allclose(grad, Gm.T[None], atol=1e-12)
