@@ -64,6 +64,8 @@ def make_problem(name):
         return PR.c5_simp(), "SIMP cube 48^3 Q1 (352,947 DOF), E=rho^3, compliance gradient"
     if name == "c1":
         return PR.c1_cube(), "unit cube 10^3 Q1 (3,993 DOF)"
+    if name == "t1":
+        return PR.t1_tet_elasticity(), "point-wise elasticity on 64^3 x 6 P1 tetrahedra (823,875 unknowns), scalar CSR"
     raise SystemExit(f"unknown config {name}")
 
 
@@ -81,7 +83,7 @@ def cpu_baseline(problem_name, gpu_iters, n_rq=0):
     oracle.build(force=False)
     tag = problem_name if n_rq == 0 else f"{problem_name}_srqcg"
     path = os.path.join(ROOT, "profiles", f"oracle_{tag}_fullsize.json")
-    if not os.path.exists(path) or problem_name not in ("c2", "c3"):
+    if not os.path.exists(path) or problem_name not in ("c2", "c3", "t1"):
         return None
     rec = json.load(open(path))
     if "sample" not in rec:
@@ -113,6 +115,13 @@ def test_space_label(args):
     if args.n_rq == 0:
         return "rigid-body modes (n_tv = 6)"
     return f"SRQCG, n_tv = 10 (rigid-body modes + 4 seeded random), n_rq = {args.n_rq}"
+
+
+def scalar_config(name):
+    """Block size and the parameters that differ for a scalar workload: one
+    unknown per node, and 4 unknowns added to an FSAI row per step (the
+    paper's rho_g = 4 scalar entries)."""
+    return {"block_size": 1, "rho_blocks": 4} if name == "t1" else {}
 
 
 def bench_batch(args, p, desc, S, t_setup):
@@ -315,7 +324,7 @@ def main():
         print(json.dumps(bench_adjoint(args, p, desc)), flush=True)
         return
     prm = aspamg.default_params(max_it=args.max_it, coarse_max_dof=args.coarse_max_dof, n_rq=args.n_rq,
-                                layout=args.layout)
+                                layout=args.layout, **scalar_config(args.config))
     V0 = p.V0 if args.n_rq == 0 else PR.initial_test_space(p, 10, 11)
     t0 = time.perf_counter()
     S = aspamg.Solver(p.row_ptr, p.col, p.vals, V0, prm)

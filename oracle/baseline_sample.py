@@ -4,7 +4,7 @@ benchmark times the oracle, and the OpenMP timing build it uses.
 A sample is a small instance of the benchmark workload's own recipe (same
 element size, materials, test space and parameters): the layered block
 32x32x16 for the layered workload, the 20x32x32 leading slab for the
-cantilever.  time_sample() builds the oracle's hierarchy for it and times a
+cantilever, 20^3 tetrahedra for the scalar workload.  time_sample() builds the oracle's hierarchy for it and times a
 fixed number of PCG iterations on one thread and on all host cores.  The same
 function runs on the host where oracle/fullsize_run.py measured the full-size
 workload, so the ratio between the two hosts scales that measurement.
@@ -44,6 +44,9 @@ def sample_problem(config):
         return PR.c3_layered_distorted(32, 32, 16), "layered block 32x32x16 (55,539 DOF), the C3 recipe"
     if config == "c2":
         return PR.c2_cantilever(20, 32, 32), "20x32x32 leading slab of the cantilever (68,607 DOF)"
+    if config == "t1":
+        return PR.tet_elasticity(20, 20, 20, jitter=0.2, seed=6), \
+            "point-wise elasticity on 20^3 x 6 tetrahedra (27,783 unknowns), the t1 recipe"
     raise ValueError(config)
 
 
@@ -57,7 +60,8 @@ def time_sample(config, n_rq, iters=20):
     nt = host_threads()
     oracle.set_threads(nt)
     t0 = time.perf_counter()
-    H = oracle.Hierarchy(p.row_ptr, p.col, p.vals, V0, oracle.default_params(n_rq=n_rq))
+    from oracle.fullsize_run import scalar_params
+    H = oracle.Hierarchy(p.row_ptr, p.col, p.vals, V0, oracle.default_params(n_rq=n_rq, **scalar_params(config)))
     setup = time.perf_counter() - t0
     out = {"desc": desc, "n_dof": int(p.n_dof), "setup_s": setup, "iterations": iters, "pcg": {}}
     for threads in sorted({1, nt}):

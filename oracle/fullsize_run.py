@@ -2,6 +2,7 @@
 
     python -m oracle.fullsize_run c2            # six rigid-body modes, every value bitwise
     python -m oracle.fullsize_run c3 --n-rq 10  # the paper's default test space
+    python -m oracle.fullsize_run t1 --n-rq 10  # scalar (b = 1) tetrahedral workload
 
 Writes
   tests/golden/<name>_hierarchy.json  per-level fingerprints of the oracle's
@@ -105,6 +106,12 @@ def fingerprint(H, bitwise_values: bool) -> list:
     return out
 
 
+def scalar_params(config) -> dict:
+    """Oracle parameters of a scalar workload: block size 1 and 4 unknowns
+    per aFSAI growth step (the paper's rho_g = 4)."""
+    return {"b": 1, "rho_b": 4} if config == "t1" else {}
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -124,7 +131,7 @@ def git_rev() -> str:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["c2", "c3"])
+    ap.add_argument("config", choices=["c2", "c3", "t1"])
     ap.add_argument("--n-rq", type=int, default=0)
     ap.add_argument("--iters", type=int, default=10, help="PCG iterations timed per thread count")
     ap.add_argument("--sample-only", action="store_true",
@@ -162,7 +169,7 @@ def main():
     p = PR.CONFIGS[args.config]()
     t_gen = time.perf_counter() - t0
     V0 = p.V0 if args.n_rq == 0 else PR.initial_test_space(p, 10, 11)
-    prm = oracle.default_params(n_rq=args.n_rq)
+    prm = oracle.default_params(n_rq=args.n_rq, **scalar_params(args.config))
     print(f"[oracle {args.config}] inputs {p.n_dof} DOF in {t_gen:.1f} s; setup on {ncores} threads ...", flush=True)
     oracle.set_threads(ncores)
     t0 = time.perf_counter()
@@ -174,6 +181,7 @@ def main():
     golden = {"config": args.config, "n_rq": args.n_rq, "n_tv": int(V0.shape[-1]),
               "test_space": "rigid-body modes" if args.n_rq == 0 else
               "rigid-body modes + 4 seeded normal columns (initial_test_space(p, 10, 11))",
+              "params": scalar_params(args.config),
               "bitwise_values": True, "levels": fingerprint(H, True),
               "max_row_blocks": MAX_ROW_BLOCKS, "written_by": "oracle/fullsize_run.py", "git": git_rev()}
     with open(gpath, "w") as fh:

@@ -315,13 +315,14 @@ def rigid_body_modes(coords):
 
 
 def initial_test_space(p, n_tv, seed):
-    """Initial test space [N, 3, n_tv]: the six rigid-body modes of p, then
-    n_tv - 6 columns of seeded standard normal entries (the random padding of
-    the test space is an input)."""
-    if n_tv < 6:
-        raise ValueError("n_tv must be at least 6")
-    N = p.n_nodes
-    extra = np.random.default_rng(seed).standard_normal((N, 3, n_tv - 6))
+    """Initial test space [N, b, n_tv]: the near-null space of p (the six
+    rigid-body modes, or the constant of a scalar problem), then columns of
+    seeded standard normal entries up to n_tv (the random padding of the test
+    space is an input)."""
+    k = p.V0.shape[2]
+    if n_tv < k:
+        raise ValueError(f"n_tv must be at least {k}")
+    extra = np.random.default_rng(seed).standard_normal((p.V0.shape[0], p.V0.shape[1], n_tv - k))
     return np.ascontiguousarray(np.concatenate([p.V0, extra], axis=2))
 
 
@@ -588,8 +589,10 @@ def _csr_with_identity_rows(rows, cols, vals, n, fixed):
     """Assembled CSR with the fixed unknowns decoupled: their rows and
     columns dropped and a unit diagonal in their place."""
     import scipy.sparse as sp
-    keep = ~(fixed[rows] | fixed[cols])
-    A = sp.coo_matrix((vals[keep], (rows[keep], cols[keep])), shape=(n, n)).tocsr()
+    keep = np.logical_not(fixed[rows])
+    keep &= np.logical_not(fixed[cols])
+    idx = np.flatnonzero(keep)
+    A = sp.coo_matrix((vals[idx], (rows[idx], cols[idx])), shape=(n, n)).tocsr()
     A = A + sp.diags(fixed.astype(np.float64))
     A = A.tocsr()
     A.sum_duplicates()
@@ -640,8 +643,8 @@ def tet_elasticity(nx, ny, nz, E=1.0, nu=0.3, jitter=0.2, seed=0):
         B[:, 3, 3 * a + 1], B[:, 3, 3 * a + 2] = gz, gy
         B[:, 4, 3 * a], B[:, 4, 3 * a + 2] = gz, gx
         B[:, 5, 3 * a], B[:, 5, 3 * a + 1] = gy, gx
-    Ke = vol[:, None, None] * np.einsum("eki,kl,elj->eij", B, D, B)
-    dofs = (3 * tets[:, :, None] + np.arange(3)).reshape(n_el, 12)
+    Ke = vol[:, None, None] * np.matmul(B.transpose(0, 2, 1), np.matmul(D, B))
+    dofs = (3 * tets[:, :, None] + np.arange(3)).reshape(n_el, 12).astype(np.int32)
     n = 3 * coords.shape[0]
     rows = np.repeat(dofs, 12, axis=1).reshape(-1)
     cols = np.tile(dofs, (1, 12)).reshape(-1)
@@ -653,3 +656,13 @@ def tet_elasticity(nx, ny, nz, E=1.0, nu=0.3, jitter=0.2, seed=0):
     V0 = rigid_body_modes(coords).reshape(n, 1, 6)
     return ScalarProblem(f"tetelast{nx}x{ny}x{nz}", coords, tets, A.indptr.astype(np.int32),
                          A.indices.astype(np.int32), A.data.reshape(-1, 1, 1).copy(), f, V0, fixed)
+
+
+def t1_tet_elasticity(n=64, seed=6):
+    """Point-wise elasticity on n^3 x 6 P1 tetrahedra (3 (n+1)^3 unknowns,
+    823,875 for n = 64), interior jitter U[-0.2h, 0.2h], clamped at z = 0,
+    body force: the scalar (block size 1) workload."""
+    return tet_elasticity(n, n, n, jitter=0.2, seed=seed)
+
+
+CONFIGS["t1"] = t1_tet_elasticity

@@ -3,7 +3,8 @@
 tests/golden/<name>_hierarchy.json is written by oracle/fullsize_run.py, which
 builds the oracle's hierarchy of the full workload once on a CPU host (C2 with
 the six rigid-body modes: several minutes; C3 with the paper's test space:
-about 40 minutes on 8 threads).  Here the GPU library builds the same
+about 40 minutes on 8 threads; the scalar tetrahedral workload T1 at block
+size 1).  Here the GPU library builds the same
 hierarchy, in the launch configuration bench.py times, and every level is
 compared bit for bit through SHA-256 digests of the exported arrays: the C/F
 split, the scalar interpolation pattern, the block patterns and the block
@@ -44,14 +45,19 @@ def load(tag):
     return json.load(open(path))
 
 
-@pytest.mark.parametrize("tag", ["c2", "c3", "c3_srqcg"])
+# the oracle's parameter names for the ones the scalar workload sets
+ORACLE_TO_LIB = {"b": "block_size", "rho_b": "rho_blocks"}
+
+
+@pytest.mark.parametrize("tag", ["c2", "c3", "c3_srqcg", "t1_srqcg"])
 def test_fullsize_hierarchy_matches_oracle_fingerprints(tag, cuda):
     from paper_1902_01715_amd import aspamg
     g = load(tag)
     print(f"[case full-size hierarchy {tag}]", flush=True)
     p = PR.CONFIGS[g["config"]]()
     V0 = p.V0 if g["n_rq"] == 0 else PR.initial_test_space(p, 10, 11)
-    S = aspamg.Solver(p.row_ptr, p.col, p.vals, V0, aspamg.default_params(n_rq=g["n_rq"]))
+    extra = {ORACLE_TO_LIB[k]: v for k, v in g.get("params", {}).items()}
+    S = aspamg.Solver(p.row_ptr, p.col, p.vals, V0, aspamg.default_params(n_rq=g["n_rq"], **extra))
     try:
         assert S.nlev == len(g["levels"]), (S.nlev, len(g["levels"]))
         worst = 0.0
