@@ -247,6 +247,11 @@ static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::
   return S;
 }
 
+#ifndef ASPAMG_SCALAR_MIN_PACK
+#define ASPAMG_SCALAR_MIN_PACK 4
+#endif
+constexpr int kScalarMinPack = ASPAMG_SCALAR_MIN_PACK;   // slot groups per lane, scalar row-packed
+
 // Lanes per row of the sliced copy: force_lanes, or the smallest L that keeps
 // kMinThreads lanes busy and then the L (up to 64) with the fewest padded
 // slots, a larger L having to save at least 5%.  Returns L; *sptr receives
@@ -384,6 +389,9 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
   bool span16 = true;
   for (int32_t r = 0; r < M.n && span16; r++) span16 = hi[r] - lo[r] <= 65535;
   for (int K : {1, 2, 4, 8}) {
+    // a scalar slot is one value: with fewer than kScalarMinPack per lane the
+    // lane's share of a row is dominated by the in-row reduction
+    if (M.b == 1 && K < kScalarMinPack) continue;
     std::vector<int32_t> w0 = packed_waves(M, K, lo, hi, span16);
     if (w0.empty()) continue;
     const int64_t sl = (int64_t)(w0.size() - 1) * 64 * K;

@@ -57,6 +57,15 @@ __device__ __forceinline__ void blk_fma(const float *g, int e, float x0, float x
   a2 += c1.z * x0 + c1.w * x1 + v8 * x2;
 }
 
+// Slots per unrolled step of a lane's slot loop: a 3x3 block brings 72 bytes
+// (FP64) per gather, a scalar slot 8, so the scalar loop keeps more slots'
+// loads in flight per step.
+#ifndef ASPAMG_SCALAR_UNROLL
+#define ASPAMG_SCALAR_UNROLL 8
+#endif
+template <int B>
+constexpr int kSlotUnroll = B == 1 ? ASPAMG_SCALAR_UNROLL : 2;
+
 // One slot of a b x b block operator applied to the gathered x of column c:
 // b = 3, the slot's 3x3 block from its group of 576 values (blk_fma); b = 1,
 // the slot's one value at entry e of its group of 64 (scalar CSR).
@@ -126,7 +135,8 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
   T a0 = 0, a1 = 0, a2 = 0;
   const CI *cp = col + (size_t)g0 * 64 + e;
   const T *vp = val + (size_t)g0 * 64 * B * B;
-#pragma unroll 2
+  constexpr int UNR = kSlotUnroll<B>;
+#pragma unroll UNR
   for (int32_t g = g0; g < g1; ++g) {
     const int32_t c = (int32_t)ld_stream(cp) + cb;
     slot_fma<B>(vp, e, x, c, a0, a1, a2);
@@ -304,7 +314,8 @@ __global__ void __launch_bounds__(kDotThreads) k_sell_spmv_dot(int32_t n, const 
       }
       const CI *cp = col + (size_t)g0 * 64 + e;
       const double *vp = val + (size_t)g0 * 64 * B * B;
-#pragma unroll 2
+      constexpr int UNR = kSlotUnroll<B>;
+#pragma unroll UNR
       for (int32_t g = g0; g < g1; ++g) {
         const int32_t c = (int32_t)ld_stream(cp) + cb;
         slot_fma<B>(vp, e, x, c, a0, a1, a2);
