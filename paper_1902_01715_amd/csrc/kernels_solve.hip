@@ -63,8 +63,13 @@ __device__ __forceinline__ void blk_fma(const float *g, int e, float x0, float x
 #ifndef ASPAMG_SCALAR_UNROLL
 #define ASPAMG_SCALAR_UNROLL 8
 #endif
+// For 3x3 blocks, 4 instead of 2 measured on the layered block: FP64 cycle
+// 2.7% faster, FP32 cycle unchanged, q = K p 1.3% slower; 2 is kept.
+#ifndef ASPAMG_BLOCK_UNROLL
+#define ASPAMG_BLOCK_UNROLL 2
+#endif
 template <int B>
-constexpr int kSlotUnroll = B == 1 ? ASPAMG_SCALAR_UNROLL : 2;
+constexpr int kSlotUnroll = B == 1 ? ASPAMG_SCALAR_UNROLL : ASPAMG_BLOCK_UNROLL;
 
 // One slot of a b x b block operator applied to the gathered x of column c:
 // b = 3, the slot's 3x3 block from its group of 576 values (blk_fma); b = 1,
