@@ -165,8 +165,13 @@ __global__ void __launch_bounds__(256) k_dpls_weights(int32_t nrows, const int32
 }
 
 // acc += X * Y for b x b blocks, each entry ((x0 y0 + x1 y1) + x2 y2) for b = 3.
-__device__ __forceinline__ void blk_mac(const double *X, const double *Y, double *acc, int b) {
+// The block size is a template argument in the kernels below: their small
+// accumulator arrays then stay in registers.
+template <int b>
+__device__ __forceinline__ void blk_mac(const double *X, const double *Y, double *acc) {
+#pragma unroll
   for (int d = 0; d < b; d++)
+#pragma unroll
     for (int e = 0; e < b; e++) {
       double s = X[d * b] * Y[e];
       for (int k = 1; k < b; k++) s += X[d * b + k] * Y[k * b + e];
@@ -187,49 +192,53 @@ __device__ __forceinline__ int32_t row_of(const int32_t *rp, int32_t n, int32_t 
 
 // T = A P with the pattern of T fixed: block (K, J) sums A_KL P_LJ over the
 // blocks L of A's row K in ascending order.  One thread per block of T.
+template <int b>
 __global__ void __launch_bounds__(256) k_spgemm_ap(int32_t n, const int32_t *__restrict__ Arp,
                                                    const int32_t *__restrict__ Aci, const double *__restrict__ Av,
                                                    const int32_t *__restrict__ Prp, const int32_t *__restrict__ Pci,
                                                    const double *__restrict__ Pv, const int32_t *__restrict__ Trp,
                                                    const int32_t *__restrict__ Tci, double *__restrict__ Tv,
-                                                   int64_t nnzT, int b) {
+                                                   int64_t nnzT) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= nnzT) return;
   const int32_t K = row_of(Trp, n, (int32_t)q);
   const int32_t J = Tci[q];
-  const int bb = b * b;
+  constexpr int bb = b * b;
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int32_t a = Arp[K]; a < Arp[K + 1]; a++) {
     const int32_t Lr = Aci[a];
     for (int32_t t = Prp[Lr]; t < Prp[Lr + 1]; t++) {
       if (Pci[t] == J) {
-        blk_mac(Av + (size_t)a * bb, Pv + (size_t)t * bb, acc, b);
+        blk_mac<b>(Av + (size_t)a * bb, Pv + (size_t)t * bb, acc);
         break;
       }
     }
   }
+#pragma unroll
   for (int k = 0; k < bb; k++) Tv[q * bb + k] = acc[k];
 }
 
 // A_c = R T: block (I, J) sums R_IK T_KJ over the blocks K of R's row I in
 // ascending order.  One thread per block of A_c.
+template <int b>
 __global__ void __launch_bounds__(256) k_spgemm_rt(int32_t nc, const int32_t *__restrict__ Rrp,
                                                    const int32_t *__restrict__ Rci, const double *__restrict__ Rv,
                                                    const int32_t *__restrict__ Trp, const int32_t *__restrict__ Tci,
                                                    const double *__restrict__ Tv, const int32_t *__restrict__ Crp,
                                                    const int32_t *__restrict__ Cci, double *__restrict__ Cv,
-                                                   int64_t nnzC, int b) {
+                                                   int64_t nnzC) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= nnzC) return;
   const int32_t I = row_of(Crp, nc, (int32_t)q);
   const int32_t J = Cci[q];
-  const int bb = b * b;
+  constexpr int bb = b * b;
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int32_t a = Rrp[I]; a < Rrp[I + 1]; a++) {
     const int32_t K = Rci[a];
     const int32_t t = find_col(Tci, Trp[K], Trp[K + 1], J);
-    if (t >= 0) blk_mac(Rv + (size_t)a * bb, Tv + (size_t)t * bb, acc, b);
+    if (t >= 0) blk_mac<b>(Rv + (size_t)a * bb, Tv + (size_t)t * bb, acc);
   }
+#pragma unroll
   for (int k = 0; k < bb; k++) Cv[q * bb + k] = acc[k];
 }
 
@@ -298,24 +307,28 @@ __global__ void __launch_bounds__(256) k_assemble(int64_t nnzb, const int64_t *_
 // Y = alpha (M X) + W for a block-sparse M (row-major b x b blocks, block
 // CSR) and row-major multi-vectors with nb columns ([b rows][nb]); one thread
 // per block row and column, blocks summed in stored order.  W may alias Y.
+template <int b>
 __global__ void __launch_bounds__(256) k_bsr_mm(int32_t n, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                 const double *__restrict__ X, double *Y, const double *W,
-                                                double alpha, int32_t nb, int b) {
+                                                double alpha, int32_t nb) {
   const int32_t c = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
   if (c >= nb || i >= n) return;
   double a[3] = {0.0, 0.0, 0.0};
   for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
     const double *blk = v + (size_t)k * b * b;
     const double *xj = X + (size_t)b * ci[k] * nb + c;
+#pragma unroll
     for (int d = 0; d < b; d++) {
       double t = blk[d * b] * xj[0];
+#pragma unroll
       for (int e = 1; e < b; e++) t += blk[d * b + e] * xj[e * (size_t)nb];
       a[d] += t;
     }
   }
   double *yi = Y + (size_t)b * i * nb + c;
   const double *wi = W ? W + (size_t)b * i * nb + c : nullptr;
+#pragma unroll
   for (int d = 0; d < b; d++) yi[d * (size_t)nb] = alpha * a[d] + (wi ? wi[d * (size_t)nb] : 0.0);
 }
 
@@ -410,11 +423,12 @@ __device__ __forceinline__ bool grow_before(double a, int32_t ja, double b, int3
 // (score descending, J ascending) are written to add[i*rho ..], -1 padded;
 // nothing is added when |B| + rho exceeds kMaxFsaiNodes.  A candidate reached
 // from several pattern nodes is scored once, by the pair of its first one.
+template <int b>
 __global__ void __launch_bounds__(64) k_fsai_grow(int32_t nrows, const int32_t *__restrict__ rows,
                                                   const int32_t *__restrict__ pat_ptr,
                                                   const int32_t *__restrict__ pat_nodes, const double *__restrict__ g,
                                                   const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                  const double *__restrict__ v, int b, int rho, int qbits,
+                                                  const double *__restrict__ v, int rho, int qbits,
                                                   int32_t *__restrict__ add) {
   constexpr int GS = 3 * kMaxFsaiNodes + 3;
   __shared__ int32_t K[kMaxFsaiNodes + 1];
@@ -480,16 +494,22 @@ __global__ void __launch_bounds__(64) k_fsai_grow(int32_t nrows, const int32_t *
       const int32_t pos = find_col(rp, ci, J, K[q]);    // block (J, K_q)
       if (pos < 0) continue;
       const double *blk = v + (size_t)pos * b * b;
+#pragma unroll
       for (int d = 0; d < b; d++) {
         const int kend = min(b, b * nb + d + 1 - b * q);
-        for (int c = 0; c < kend; c++) {
+#pragma unroll
+        for (int c = 0; c < b; c++) {
+          if (c >= kend) break;
           const double gk = gp[d][b * q + c];
+#pragma unroll
           for (int e = 0; e < b; e++) h[d * b + e] += blk[e * b + c] * gk;
         }
       }
     }
     double score = 0.0;
+#pragma unroll
     for (int d = 0; d < b; d++)
+#pragma unroll
       for (int e = 0; e < b; e++) score += h[d * b + e] * h[d * b + e];
     if (!(score > 0.0)) continue;
     const double qs = quantize_dev(score, qbits);
@@ -550,18 +570,22 @@ __global__ void __launch_bounds__(256) k_dot256(int64_t n, const double *__restr
 
 // y = M x on a plain block CSR, one thread per block row, each row's
 // components summed over its blocks in stored order (the sequential product)
+template <int b>
 __global__ void __launch_bounds__(256) k_bsr_mv_seq(int32_t n, const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ ci, const double *__restrict__ v,
-                                                   const double *__restrict__ x, double *__restrict__ y, int b) {
+                                                   const double *__restrict__ x, double *__restrict__ y) {
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   double a[3] = {0.0, 0.0, 0.0};
   for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
     const double *B = v + (size_t)k * b * b;
     const double *xx = x + (size_t)ci[k] * b;
+#pragma unroll
     for (int d = 0; d < b; d++)
+#pragma unroll
       for (int e = 0; e < b; e++) a[d] += B[d * b + e] * xx[e];
   }
+#pragma unroll
   for (int d = 0; d < b; d++) y[(size_t)i * b + d] = a[d];
 }
 
@@ -593,8 +617,9 @@ __global__ void __launch_bounds__(256) k_eye(int64_t nd, double *__restrict__ X)
 void launch_bsr_mm(const DevBSR &M, const double *X, double *Y, const double *W, double alpha, int32_t nb,
                    hipStream_t s) {
   if (M.n == 0 || nb == 0) return;
-  hipLaunchKernelGGL(k_bsr_mm, dim3((unsigned)((nb + 255) / 256), (unsigned)M.n), dim3(256), 0, s, M.n, M.rp, M.ci,
-                     M.v, X, Y, W, alpha, nb, M.b);
+  const dim3 grid((unsigned)((nb + 255) / 256), (unsigned)M.n);
+  if (M.b == 1) hipLaunchKernelGGL(k_bsr_mm<1>, grid, dim3(256), 0, s, M.n, M.rp, M.ci, M.v, X, Y, W, alpha, nb);
+  else hipLaunchKernelGGL(k_bsr_mm<3>, grid, dim3(256), 0, s, M.n, M.rp, M.ci, M.v, X, Y, W, alpha, nb);
 }
 
 void launch_dense_mm(int32_t nd, const double *D, const double *X, double *Y, int32_t nb, hipStream_t s) {
@@ -638,7 +663,9 @@ void launch_dot256(int64_t n, const double *a, const double *b, double *part, hi
 }
 void launch_bsr_mv_seq(const DevBSR &M, const double *x, double *y, hipStream_t s) {
   if (M.n == 0) return;
-  hipLaunchKernelGGL(k_bsr_mv_seq, dim3((M.n + 255) / 256), dim3(256), 0, s, M.n, M.rp, M.ci, M.v, x, y, M.b);
+  const dim3 grid((M.n + 255) / 256);
+  if (M.b == 1) hipLaunchKernelGGL(k_bsr_mv_seq<1>, grid, dim3(256), 0, s, M.n, M.rp, M.ci, M.v, x, y);
+  else hipLaunchKernelGGL(k_bsr_mv_seq<3>, grid, dim3(256), 0, s, M.n, M.rp, M.ci, M.v, x, y);
 }
 void launch_xpby(int64_t n, const double *x, double b, double *y, hipStream_t s) {
   hipLaunchKernelGGL(k_xpby, dim3(setup_vec_blocks(n)), dim3(256), 0, s, n, x, b, y);
@@ -666,8 +693,12 @@ int launch_fsai_rows(const DevBSR &A, int32_t nrows, const int32_t *rows, const 
 void launch_fsai_grow(const DevBSR &A, int32_t nrows, const int32_t *rows, const int32_t *pat_ptr,
                       const int32_t *pat_nodes, const double *g, int rho, int qbits, int32_t *add, hipStream_t s) {
   if (nrows == 0) return;
-  hipLaunchKernelGGL(k_fsai_grow, dim3(nrows), dim3(64), 0, s, nrows, rows, pat_ptr, pat_nodes, g, A.rp, A.ci, A.v,
-                     A.b, rho, qbits, add);
+  if (A.b == 1)
+    hipLaunchKernelGGL(k_fsai_grow<1>, dim3(nrows), dim3(64), 0, s, nrows, rows, pat_ptr, pat_nodes, g, A.rp, A.ci,
+                       A.v, rho, qbits, add);
+  else
+    hipLaunchKernelGGL(k_fsai_grow<3>, dim3(nrows), dim3(64), 0, s, nrows, rows, pat_ptr, pat_nodes, g, A.rp, A.ci,
+                       A.v, rho, qbits, add);
 }
 
 void launch_dpls_weights(int32_t nrows, const int32_t *row, const int32_t *cnt, const int32_t *sel,
@@ -678,14 +709,24 @@ void launch_dpls_weights(int32_t nrows, const int32_t *row, const int32_t *cnt, 
 
 void launch_spgemm_ap(const DevBSR &A, const DevBSR &P, const DevBSR &T, hipStream_t s) {
   if (T.nnzb == 0) return;
-  hipLaunchKernelGGL(k_spgemm_ap, dim3((unsigned)((T.nnzb + 255) / 256)), dim3(256), 0, s, T.n, A.rp, A.ci, A.v,
-                     P.rp, P.ci, P.v, T.rp, T.ci, T.v, T.nnzb, T.b);
+  const dim3 grid((unsigned)((T.nnzb + 255) / 256));
+  if (T.b == 1)
+    hipLaunchKernelGGL(k_spgemm_ap<1>, grid, dim3(256), 0, s, T.n, A.rp, A.ci, A.v, P.rp, P.ci, P.v, T.rp, T.ci, T.v,
+                       T.nnzb);
+  else
+    hipLaunchKernelGGL(k_spgemm_ap<3>, grid, dim3(256), 0, s, T.n, A.rp, A.ci, A.v, P.rp, P.ci, P.v, T.rp, T.ci, T.v,
+                       T.nnzb);
 }
 
 void launch_spgemm_rt(const DevBSR &R, const DevBSR &T, const DevBSR &Ac, hipStream_t s) {
   if (Ac.nnzb == 0) return;
-  hipLaunchKernelGGL(k_spgemm_rt, dim3((unsigned)((Ac.nnzb + 255) / 256)), dim3(256), 0, s, Ac.n, R.rp, R.ci, R.v,
-                     T.rp, T.ci, T.v, Ac.rp, Ac.ci, Ac.v, Ac.nnzb, Ac.b);
+  const dim3 grid((unsigned)((Ac.nnzb + 255) / 256));
+  if (Ac.b == 1)
+    hipLaunchKernelGGL(k_spgemm_rt<1>, grid, dim3(256), 0, s, Ac.n, R.rp, R.ci, R.v, T.rp, T.ci, T.v, Ac.rp, Ac.ci,
+                       Ac.v, Ac.nnzb);
+  else
+    hipLaunchKernelGGL(k_spgemm_rt<3>, grid, dim3(256), 0, s, Ac.n, R.rp, R.ci, R.v, T.rp, T.ci, T.v, Ac.rp, Ac.ci,
+                       Ac.v, Ac.nnzb);
 }
 
 void launch_element_gradient(int64_t n_el, const int32_t *conn, const double *Ke0, int64_t ke_stride,
