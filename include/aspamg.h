@@ -103,8 +103,8 @@ typedef struct {
                            *       blocks, elasticity); 1 takes K as scalar CSR and runs
                            *       the paper's point-wise rules (Sections 3.1-3.5 with
                            *       1x1 blocks), row_ptr / col / vals then being plain CSR
-                           *       and V0 [n][n_tv].  solve_batch, the assembler and the
-                           *       no-allocation entry point need 3. */
+                           *       and V0 [n][n_tv].  solve_batch and the assembler need
+                           *       3. */
 } aspamg_params;
 
 typedef struct {

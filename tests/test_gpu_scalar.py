@@ -118,3 +118,24 @@ def test_scalar_batch_is_refused(pair):
     F = torch.zeros((p.n, 4), dtype=torch.float64, device="cuda")
     with pytest.raises(aspamg.AspamgError):
         S.solve_batch(F)
+
+
+@pytest.mark.parametrize("which", [0, 1, 2, 3, 4])
+def test_scalar_operators_through_both_entry_points(pair, which):
+    """Level-0 products of the scalar hierarchy in FP64 against the oracle's
+    matrices, and the no-allocation entry point against the allocating one
+    in FP32 (the same kernels: bit for bit)."""
+    import torch
+    name, p, S, H = pair
+    M = {0: H.A(0), 1: H.G(0), 2: H.G(0), 3: H.P(0), 4: H.P(0)}[which].to_scipy().tocsr()
+    if which in (2, 4):
+        M = M.T.tocsr()
+    x = np.random.default_rng(5 + which).standard_normal(M.shape[1])
+    xt = torch.tensor(x, device="cuda")
+    y = S.apply(0, which, xt, precision=64, out_rows=M.shape[0]).cpu().numpy()
+    ref = M @ x
+    scale = abs(M).max() * np.abs(x).max() * max(1, M.getnnz(axis=1).max())
+    assert np.abs(y - ref).max() <= 1e-14 * scale
+    y32 = S.apply(0, which, xt, precision=32, out_rows=M.shape[0])
+    y32n = S.apply_noalloc(0, which, xt, torch.empty_like(y32), precision=32)
+    assert torch.equal(y32, y32n)
