@@ -226,7 +226,10 @@ OP_NAMES = {0: "residual A", 1: "G", 2: "G^T", 3: "restriction R", 4: "merged G^
             6: "dense", 7: "prolongation P"}
 
 
-def level_table(S, levels, reps=50):
+LEVEL_TABLE_REPS = 50
+
+
+def level_table(S, levels, reps):
     """Every product of the V-cycle per level and precision: average launch
     time (HIP events, 50 launches), algorithmic bytes and GB/s, and how many
     times one cycle launches it (V(1,1): A once, G and G^T twice, R and the
@@ -295,7 +298,8 @@ def main():
                          "seeded random columns): the paper's defaults; 0 keeps the six rigid-body modes alone "
                          "(c2, c3, c4)")
     ap.add_argument("--layout", type=int, default=0,
-                    help="operator layout policy (0 timed choice, 1 by stored slots, 2 sliced only, 3 row-packed only)")
+                    help="operator layout policy (0 timed choice, 1 by stored slots, 2 sliced only, 3 row-packed in "
+                         "workgroup units only, 4 row-packed in wavefront units only)")
     ap.add_argument("--level-table", action="store_true",
                     help="also time every V-cycle product per level and precision (aspamg_time_operator) and add "
                          "the table to the JSON line")
@@ -405,7 +409,8 @@ def main():
                     "residual_fp64_GBps": r64_b / (r64_ms * 1e-3) / 1e9},
         "levels": [{k: li[k] for k in ("n", "n_coarse", "nnzb_A", "nnzb_G", "nnzb_P", "sell_slots_A", "sell_slots_G",
                                       "sell_slots_GT", "sell_lanes64", "sell_lanes32", "sell_stacked", "sell_index16",
-                                      "omega_s", "fsai_rounds")}
+                                      "sell_unit64", "sell_unit32", "sell_stacked32", "sell_stacked_unit64",
+                                      "sell_stacked_unit32", "omega_s", "fsai_rounds")}
                    for li in levels],
         "roofline": {"bound": "hbm", "kernel": "k_sell_spmv_dot (q = K p, FP64, sliced ELL with one lane per row)",
                      "achieved": kp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kp_gbs / HBM_PEAK_GBS,
@@ -413,7 +418,8 @@ def main():
                      "alg_bytes_per_launch": kp_b},
     }
     if args.level_table:
-        out["level_table"] = level_table(S, levels)
+        out["level_table"] = level_table(S, levels, LEVEL_TABLE_REPS)
+        out["level_table_reps"] = LEVEL_TABLE_REPS
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.config, st32["iterations"], args.n_rq)

@@ -86,13 +86,17 @@ typedef struct {
   int32_t dense_max_dof;  /* 16384 refuse a larger dense coarsest system                */
   int32_t check_every;    /* 4     PCG iterations per host convergence poll             */
   int32_t use_graph;      /* 1     replay the PCG iteration as a captured HIP graph     */
-  int32_t layout;         /* 0     device layout of the stored operators: 0 time both
-                           *       layouts on the device for the larger operators; 1 pick
-                           *       by stored slots only (the same choice on every run); 2
-                           *       sliced ELL only; 3 row-packed only.  The fine-level FP64
-                           *       operator of q = K p is sliced with one lane per row in
-                           *       every case.  Results do not depend on the layout beyond
-                           *       the order of floating-point sums within a row. */
+  int32_t layout;         /* 0     device layout of the stored operators: 0 time the
+                           *       candidate layouts on the device for the larger operators,
+                           *       separately for the FP64 and FP32 copies; 1 pick by stored
+                           *       slots only (the same choice on every run); 2 sliced ELL
+                           *       only; 3 row-packed only, rows packed into units of a
+                           *       256-thread workgroup; 4 row-packed only, units of one
+                           *       wavefront.  The fine-level FP64 operator of q = K p is
+                           *       sliced with one lane per row in every case, and the FP32
+                           *       copy of the fine-level K shares its layout.  Results do
+                           *       not depend on the layout beyond the order of
+                           *       floating-point sums within a row. */
   int32_t dense_tail_dof; /* 4096  the V-cycle from the highest level whose unknowns, and
                            *       those of every level below it, number at most this
                            *       (above the coarsest) is formed at setup as one dense FP64
@@ -137,22 +141,30 @@ typedef struct {
   double  lambda1, omega_q, omega_s;
   int64_t sell_slots_A, sell_slots_G, sell_slots_GT; /* stored block slots (padding incl.) */
   /* device layout of the stored operators A, G, G^T, P, R (index = `which` of
-   * aspamg_apply_operator), FP64 and FP32 copies: L > 0 for the sliced layout
-   * with L lanes per row, -K for the row-packed layout with K slot groups per
-   * wavefront */
+   * aspamg_apply_operator), FP64 and FP32 copies (each chosen for its own
+   * precision): L > 0 for the sliced layout with L lanes per row, -K for the
+   * row-packed layout with K slot groups per lane (its packing unit in
+   * sell_unit64 / sell_unit32) */
   int32_t sell_lanes64[5], sell_lanes32[5];
   /* bit k (FP64 copy) and bit 5 + k (FP32 copy) set when operator k stores its
    * columns as 16-bit offsets from a per-slice base; bit 10 the same for the
    * row-stacked [P; A P] operator of the coarse-grid correction */
   int32_t sell_index16;
-  /* layout of the row-stacked [P; A P] operator (same encoding as sell_lanes64;
-   * its FP32 copy shares it); 0 on the coarsest level and where A P has more
+  /* layout of the FP64 copy of the row-stacked [P; A P] operator (same
+   * encoding as sell_lanes64); 0 on the coarsest level and where A P has more
    * blocks than A (there the first post-smoothing step applies P, then A) */
   int32_t sell_stacked;
   /* blocks of M = G^T G when the FP32 cycle's smoothing applies it as one
    * stored operator (small levels above the dense tail), else 0 (G, then G^T;
    * the FP64 cycle always applies G, then G^T) */
   int64_t nnzb_M;
+  /* lanes per packing unit of the row-packed copies of A, G, G^T, P, R: 64
+   * (rows packed per wavefront) or 256 (per 256-thread workgroup, a row's
+   * lanes possibly in different wavefronts); 0 for the sliced layout */
+  int32_t sell_unit64[5], sell_unit32[5];
+  /* the row-stacked operator's FP32 copy (encoded as sell_stacked) and the
+   * packing units of its two copies (as sell_unit64) */
+  int32_t sell_stacked32, sell_stacked_unit64, sell_stacked_unit32;
 } aspamg_level_info_t;
 
 /* Fill *out with the defaults.  out: caller-owned. */

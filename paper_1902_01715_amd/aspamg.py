@@ -66,6 +66,8 @@ class LevelInfo(C.Structure):
         ("sell_slots_A", C.c_int64), ("sell_slots_G", C.c_int64), ("sell_slots_GT", C.c_int64),
         ("sell_lanes64", C.c_int32 * 5), ("sell_lanes32", C.c_int32 * 5),
         ("sell_index16", C.c_int32), ("sell_stacked", C.c_int32), ("nnzb_M", C.c_int64),
+        ("sell_unit64", C.c_int32 * 5), ("sell_unit32", C.c_int32 * 5),
+        ("sell_stacked32", C.c_int32), ("sell_stacked_unit64", C.c_int32), ("sell_stacked_unit32", C.c_int32),
     ]
 
     def as_dict(self):

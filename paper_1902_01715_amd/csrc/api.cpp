@@ -15,7 +15,7 @@
 // sizes mirrored by the Python binding
 static_assert(sizeof(aspamg_params) == 160, "aspamg_params layout changed");
 static_assert(sizeof(aspamg_stats) == 104, "aspamg_stats layout changed");
-static_assert(sizeof(aspamg_level_info_t) == 144, "aspamg_level_info_t layout changed");
+static_assert(sizeof(aspamg_level_info_t) == 200, "aspamg_level_info_t layout changed");
 
 namespace aspamg {
 
@@ -91,24 +91,28 @@ static void row_spans(const HostBSR &M, std::vector<int32_t> &lo, std::vector<in
     }
 }
 
-// Row-packed layout with K slot groups per wavefront: rows in matrix order,
-// max(1, ceil(len/K)) lanes each, a new wavefront whenever a row does not fit.
-// When every row on its own spans at most 65,536 columns, a new wavefront also
-// starts where the next row would widen the wavefront's span beyond that, so
-// a jump in the column numbering (the seam of a row-stacked operator) does not
-// cost the whole operator its 16-bit column offsets.  Returns the first row of
-// every wavefront (plus n at the end), or an empty vector when a row needs
-// more than 64 lanes.
-static std::vector<int32_t> packed_waves(const HostBSR &M, int K, const std::vector<int32_t> &lo,
+// Row-packed layout with K slot groups per lane, packed into units of `unit`
+// lanes (64: one wavefront; 256: the four of one workgroup): rows in matrix
+// order, max(1, ceil(len/K)) lanes each, a new unit whenever a row does not
+// fit.  In a 256-lane unit a row may cross wavefronts (its lanes meet in LDS
+// behind a workgroup barrier), so the unit leaves fewer lanes unused than a
+// single wavefront would.  When every row on its own spans at most 65,536
+// columns, a new unit also starts where the next row would widen the unit's
+// span beyond that, so a jump in the column numbering (the seam of a
+// row-stacked operator) does not cost the whole operator its 16-bit column
+// offsets.  Returns the first row of every unit (plus n at the end), or an
+// empty vector when a row needs more than min(unit, kPackMaxLanes) lanes.
+static std::vector<int32_t> packed_units(const HostBSR &M, int K, int unit, const std::vector<int32_t> &lo,
                                          const std::vector<int32_t> &hi, bool span16) {
   std::vector<int32_t> w0;
-  int used = 64;
+  const int maxl = std::min(unit, kPackMaxLanes);
+  int used = unit;
   int32_t wlo = INT32_MAX, whi = -1;
   for (int32_t r = 0; r < M.n; r++) {
     const int64_t len = M.rp[r + 1] - M.rp[r];
     const int64_t lr = std::max<int64_t>(1, (len + K - 1) / K);
-    if (lr > 64) return {};
-    bool fresh = used + lr > 64;
+    if (lr > maxl) return {};
+    bool fresh = used + lr > unit;
     if (!fresh && span16 && hi[r] >= 0 && whi >= 0)
       fresh = (int64_t)std::max(whi, hi[r]) - std::min(wlo, lo[r]) > 65535;
     if (fresh) {
@@ -196,8 +200,9 @@ static void upload_arrays(aspamg_ctx *h, Sell<T> &S, const std::vector<int32_t> 
 }
 
 template <typename T>
-static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::vector<int32_t> &w0,
+static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, int unit, const std::vector<int32_t> &w0,
                              const double *dv) {
+  const int kWaves = unit / 64;
   Sell<T> S;
   S.n = M.n;
   S.nc = M.nc;
@@ -205,41 +210,45 @@ static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, const std::
   S.nnzb = M.nnzb();
   S.lanes = 0;
   S.pack = K;
-  S.nslices = (int32_t)w0.size() - 1;
+  S.unit = unit;
+  const int32_t nunits = (int32_t)w0.size() - 1;
+  S.nslices = nunits * kWaves;
   S.ngroups = (int64_t)S.nslices * K;
   std::vector<int32_t> col((size_t)S.ngroups * 64), map((size_t)S.ngroups * 64);
-  std::vector<uint16_t> meta((size_t)S.nslices * 64);
+  std::vector<uint16_t> meta((size_t)S.nslices * 64, 0);   // unused lanes: no row to write, offset 0
 #pragma omp parallel for schedule(dynamic, 64)
-  for (int32_t s = 0; s < S.nslices; s++) {
-    // lane e of wavefront s serves blocks j K .. j K + K - 1 of row lrow[e]
-    int32_t lrow[64], lj[64];
+  for (int32_t u = 0; u < nunits; u++) {
+    // lane e of unit u serves blocks j K .. j K + K - 1 of row lrow[e]
+    int32_t lrow[256], lj[256];
     int e = 0;
-    for (int32_t r = w0[s]; r < w0[s + 1]; r++) {
+    for (int32_t r = w0[u]; r < w0[u + 1]; r++) {
       const int64_t len = M.rp[r + 1] - M.rp[r];
       const int lr = (int)std::max<int64_t>(1, (len + K - 1) / K);
       for (int j = 0; j < lr; j++, e++) {
-        meta[(size_t)s * 64 + e] = (uint16_t)(((j == 0 ? lr : 0) << 8) | (r - w0[s]));
+        meta[(size_t)u * unit + e] = (uint16_t)(((j == 0 ? lr : 0) << 8) | (r - w0[u]));
         lrow[e] = r;
         lj[e] = j;
       }
     }
-    for (int f = e; f < 64; f++) {
-      meta[(size_t)s * 64 + f] = 0x00FF;
+    for (int f = e; f < unit; f++) {
       lrow[f] = -1;
       lj[f] = 0;
     }
-    for (int k = 0; k < K; k++) {
-      const size_t g = (size_t)s * K + k;
-      for (int f = 0; f < 64; f++) {
-        int32_t src = -1;
-        if (lrow[f] >= 0) {
-          const int64_t b = (int64_t)lj[f] * K + k;
-          if (b < M.rp[lrow[f] + 1] - M.rp[lrow[f]]) src = (int32_t)(M.rp[lrow[f]] + b);
+    // slot group k of the unit's wavefront wv holds entry k of lanes 64 wv .. 64 wv + 63
+    for (int wv = 0; wv < kWaves; wv++)
+      for (int k = 0; k < K; k++) {
+        const size_t g = ((size_t)u * kWaves + wv) * K + k;
+        for (int f = 0; f < 64; f++) {
+          const int ln = wv * 64 + f;
+          int32_t src = -1;
+          if (lrow[ln] >= 0) {
+            const int64_t b = (int64_t)lj[ln] * K + k;
+            if (b < M.rp[lrow[ln] + 1] - M.rp[lrow[ln]]) src = (int32_t)(M.rp[lrow[ln]] + b);
+          }
+          map[g * 64 + f] = src;
+          col[g * 64 + f] = src >= 0 ? M.ci[src] : -1;
         }
-        map[g * 64 + f] = src;
-        col[g * 64 + f] = src >= 0 ? M.ci[src] : -1;
       }
-    }
   }
   const int64_t Kp = K;
   std::vector<int32_t> base = settle_columns(col, S.nslices, [Kp](int32_t s) { return (int64_t)s * Kp; });
@@ -325,41 +334,52 @@ void free_sell(aspamg_ctx *h, Sell<T> &S) {
   S = Sell<T>();
 }
 
-// Median times of y = S x and y = Q x over 7 launches each, the two
-// alternating (after one warm-up launch each), on the handle's stream.
+// Median launch times of y = C x for each candidate layout C over 7 rounds in
+// which the candidates take turns (after one warm-up launch each), on the
+// handle's stream.
 template <typename T>
-static void time_products(aspamg_ctx *h, const Sell<T> &S, const Sell<T> &Q, const T *x, T *y, float &ts,
-                          float &tq) {
-  hipEvent_t e[4];
-  for (auto &ev : e) HIPCHK(hipEventCreate(&ev));
+static std::vector<float> time_layouts(aspamg_ctx *h, const std::vector<Sell<T>> &C, const T *x, T *y) {
+  const size_t n = C.size();
   constexpr int kReps = 7;
-  float a[kReps], b[kReps];
-  launch_spmv<T, T, T>(S, x, y, nullptr, 1.0, nullptr, h->stream);
-  launch_spmv<T, T, T>(Q, x, y, nullptr, 1.0, nullptr, h->stream);
-  for (int i = 0; i < kReps; i++) {
-    HIPCHK(hipEventRecord(e[0], h->stream));
-    launch_spmv<T, T, T>(S, x, y, nullptr, 1.0, nullptr, h->stream);
-    HIPCHK(hipEventRecord(e[1], h->stream));
-    launch_spmv<T, T, T>(Q, x, y, nullptr, 1.0, nullptr, h->stream);
-    HIPCHK(hipEventRecord(e[2], h->stream));
-    HIPCHK(hipEventSynchronize(e[2]));
-    HIPCHK(hipEventElapsedTime(&a[i], e[0], e[1]));
-    HIPCHK(hipEventElapsedTime(&b[i], e[1], e[2]));
+  std::vector<hipEvent_t> e(n + 1, nullptr);
+  for (auto &ev : e) HIPCHK(hipEventCreate(&ev));
+  std::vector<std::vector<float>> t(n, std::vector<float>(kReps, 0.f));
+  try {
+    for (const Sell<T> &c : C) launch_spmv<T, T, T>(c, x, y, nullptr, 1.0, nullptr, h->stream);
+    for (int i = 0; i < kReps; i++) {
+      HIPCHK(hipEventRecord(e[0], h->stream));
+      for (size_t j = 0; j < n; j++) {
+        launch_spmv<T, T, T>(C[j], x, y, nullptr, 1.0, nullptr, h->stream);
+        HIPCHK(hipEventRecord(e[j + 1], h->stream));
+      }
+      HIPCHK(hipEventSynchronize(e[n]));
+      for (size_t j = 0; j < n; j++) HIPCHK(hipEventElapsedTime(&t[j][i], e[j], e[j + 1]));
+    }
+  } catch (...) {
+    for (auto &ev : e) (void)hipEventDestroy(ev);
+    throw;
   }
   for (auto &ev : e) (void)hipEventDestroy(ev);
-  std::sort(a, a + kReps);
-  std::sort(b, b + kReps);
-  ts = a[kReps / 2];
-  tq = b[kReps / 2];
+  std::vector<float> med(n);
+  for (size_t j = 0; j < n; j++) {
+    std::sort(t[j].begin(), t[j].end());
+    med[j] = t[j][kReps / 2];
+  }
+  return med;
 }
 
-// Device copy of M used by the products of the solve phase.  With
-// force_lanes the sliced layout with that many lanes per row; otherwise the
-// sliced layout and the row-packed one with the fewest slots (if it stores at
-// most 1.5 times the sliced slots) are both built and timed on this device,
-// and the faster one is kept (the row-packed one must win by 5%).  Operators
-// under kTimedSlots slots, or all of them without `timed`, keep the
-// row-packed layout when it stores 10% fewer slots.
+// Device copy of M used by the products of the solve phase, in the precision
+// T it is applied in.  With force_lanes the sliced layout with that many lanes
+// per row.  Otherwise the candidates are the sliced layout and the row-packed
+// ones with units of one wavefront and of one workgroup, each with its K of
+// fewest slots.  Those storing at most 1.5 times the sliced slots are built
+// and timed on this device in T, and the fastest is kept (a row-packed one
+// must beat the sliced one by 5%).  Operators under kTimedSlots slots, or all
+// of them without `timed`, take the wavefront-unit packing unless the
+// workgroup unit stores 10% fewer slots, and keep it when it stores 10% fewer
+// slots than the sliced layout.  Policy 2 forces the sliced
+// layout, 3 and 4 the row-packed one with units of a workgroup and of a
+// wavefront (sliced where a row needs more lanes than a unit holds).
 template <typename T>
 Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed, const double *dvals) {
   const int policy = h->p.layout;
@@ -382,44 +402,61 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
   }
   if (force_lanes || M.n == 0 || M.nc == 0 || policy == 2) return upload_sliced<T>(h, M, L, sptr, dv.v);
   if (policy != 0) timed = false;
-  int bestK = 0;
-  int64_t best = 0;
-  std::vector<int32_t> bestw, lo, hi;
+  struct Plan {
+    int K = 0, unit = 0;
+    int64_t slots = 0;
+    std::vector<int32_t> w0;
+  } pk[2];
+  std::vector<int32_t> lo, hi;
   row_spans(M, lo, hi);
   bool span16 = true;
   for (int32_t r = 0; r < M.n && span16; r++) span16 = hi[r] - lo[r] <= 65535;
-  for (int K : {1, 2, 4, 8}) {
-    // a scalar slot is one value: with fewer than kScalarMinPack per lane the
-    // lane's share of a row is dominated by the in-row reduction
-    if (M.b == 1 && K < kScalarMinPack) continue;
-    std::vector<int32_t> w0 = packed_waves(M, K, lo, hi, span16);
-    if (w0.empty()) continue;
-    const int64_t sl = (int64_t)(w0.size() - 1) * 64 * K;
-    if (!bestK || sl < best) {
-      best = sl;
-      bestK = K;
-      bestw.swap(w0);
+  const int units[2] = {64, 256};
+  for (int u = 0; u < 2; u++) {
+    pk[u].unit = units[u];
+    for (int K : {1, 2, 4, 8}) {
+      // a scalar slot is one value: with fewer than kScalarMinPack per lane the
+      // lane's share of a row is dominated by the in-row reduction
+      if (M.b == 1 && K < kScalarMinPack) continue;
+      std::vector<int32_t> w0 = packed_units(M, K, units[u], lo, hi, span16);
+      if (w0.empty()) continue;
+      const int64_t sl = (int64_t)(w0.size() - 1) * units[u] * K;
+      if (!pk[u].K || sl < pk[u].slots) {
+        pk[u].K = K;
+        pk[u].slots = sl;
+        pk[u].w0.swap(w0);
+      }
     }
   }
-  if (!bestK) return upload_sliced<T>(h, M, L, sptr, dv.v);   // a row needs more than 64 lanes
-  if (policy == 3) return upload_packed<T>(h, M, bestK, bestw, dv.v);
-  const int64_t sliced = (int64_t)sptr.back() * 64;
-  const double ratio = (double)best / (double)sliced;
-  // small operators sit at the launch-latency floor either way: no timing
-  if (!timed || std::max<int64_t>(best, sliced) < kTimedSlots) {
-    if (ratio >= 0.9) return upload_sliced<T>(h, M, L, sptr, dv.v);
-    return upload_packed<T>(h, M, bestK, bestw, dv.v);
+  auto packed = [&](const Plan &q) { return upload_packed<T>(h, M, q.K, q.unit, q.w0, dv.v); };
+  if (policy == 3 || policy == 4) {
+    const Plan &q = pk[policy == 3 ? 1 : 0];
+    return q.K ? packed(q) : upload_sliced<T>(h, M, L, sptr, dv.v);
   }
-  if (ratio > 1.5) return upload_sliced<T>(h, M, L, sptr, dv.v);
-  Sell<T> S = upload_sliced<T>(h, M, L, sptr, dv.v);
-  Sell<T> Q = upload_packed<T>(h, M, bestK, bestw, dv.v);
+  // untimed choice: the wavefront unit unless the workgroup unit stores 10%
+  // fewer slots (its barrier costs the most where the product is short)
+  const Plan *best = pk[0].K ? &pk[0] : nullptr;
+  if (pk[1].K && (!best || (double)pk[1].slots < 0.9 * (double)best->slots)) best = &pk[1];
+  if (!best) return upload_sliced<T>(h, M, L, sptr, dv.v);   // a row needs more than kPackMaxLanes lanes
+  const int64_t sliced = (int64_t)sptr.back() * 64;
+  // small operators sit at the launch-latency floor either way: no timing
+  const int64_t fewest = pk[0].K && pk[1].K ? std::min(pk[0].slots, pk[1].slots) : best->slots;
+  if (!timed || std::max<int64_t>(fewest, sliced) < kTimedSlots) {
+    if ((double)best->slots >= 0.9 * (double)sliced) return upload_sliced<T>(h, M, L, sptr, dv.v);
+    return packed(*best);
+  }
+  std::vector<Sell<T>> cand;
+  cand.push_back(upload_sliced<T>(h, M, L, sptr, dv.v));
+  for (const Plan &q : pk)
+    if (q.K && (double)q.slots <= 1.5 * (double)sliced) cand.push_back(packed(q));
+  if (cand.size() == 1) return cand[0];
   T *x = nullptr, *y = nullptr;
   HIPCHK(hipMalloc(&x, sizeof(T) * M.b * (size_t)M.nc));
   HIPCHK(hipMalloc(&y, sizeof(T) * M.b * (size_t)M.n));
-  HIPCHK(hipMemsetAsync(x, 0, sizeof(T) * M.b * (size_t)M.nc, h->stream));
-  float ts = 0, tq = 0;
+  std::vector<float> t;
   try {
-    time_products(h, S, Q, x, y, ts, tq);
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(T) * M.b * (size_t)M.nc, h->stream));
+    t = time_layouts(h, cand, x, y);
   } catch (...) {
     (void)hipFree(x);
     (void)hipFree(y);
@@ -427,12 +464,12 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
   }
   (void)hipFree(x);
   (void)hipFree(y);
-  if (tq < 0.95f * ts) {
-    free_sell(h, S);
-    return Q;
-  }
-  free_sell(h, Q);
-  return S;
+  size_t pick = 0;
+  for (size_t j = 1; j < cand.size(); j++)
+    if (t[j] < 0.95f * t[0] && (pick == 0 || t[j] < t[pick])) pick = j;
+  for (size_t j = 0; j < cand.size(); j++)
+    if (j != pick) free_sell(h, cand[j]);
+  return cand[pick];
 }
 // FP32 copy of S in the same layout: the index arrays are shared with S (so
 // the copy is never freed on its own), the values converted on the device.
@@ -444,6 +481,7 @@ Sell<float> derive_fp32(aspamg_ctx *h, const Sell<double> &S) {
   F.nslices = S.nslices;
   F.lanes = S.lanes;
   F.pack = S.pack;
+  F.unit = S.unit;
   F.ngroups = S.ngroups;
   F.nnzb = S.nnzb;
   F.sptr = S.sptr;
@@ -831,7 +869,7 @@ static void check_params(const aspamg_params &p) {
       (p.cycle_precision != 32 && p.cycle_precision != 64) || !(p.rtol >= 0) || p.max_it < 1 ||
       p.quant_bits < 8 || p.quant_bits > 52 || p.check_every < 1 || p.n_tv < 0 || p.n_tv > 64 ||
       p.n_rq < 0 || p.n_rq > 1000 ||
-      p.layout < 0 || p.layout > 3 || p.dense_tail_dof < 0 || p.dense_tail_dof > kMaxTailDof ||
+      p.layout < 0 || p.layout > 4 || p.dense_tail_dof < 0 || p.dense_tail_dof > kMaxTailDof ||
       (p.block_size != 1 && p.block_size != 3) ||
       !(p.kappa_p > 0) || !(p.omega_safety > 0))
     fail(ASPAMG_EINVAL, "invalid parameter value");
@@ -1187,7 +1225,16 @@ aspamg_status aspamg_level_info(aspamg_handle h, int32_t level, aspamg_level_inf
     if (M64[k]->col16) o->sell_index16 |= 1 << k;
     if (M32[k]->col16) o->sell_index16 |= 1 << (5 + k);
   }
-  o->sell_stacked = !L.stacked() ? 0 : L.PAP64.pack ? -L.PAP64.pack : L.PAP64.lanes;
+  for (int k = 0; k < 5; k++) {
+    o->sell_unit64[k] = M64[k]->pack ? M64[k]->unit : 0;
+    o->sell_unit32[k] = M32[k]->pack ? M32[k]->unit : 0;
+  }
+  if (L.stacked()) {
+    o->sell_stacked = L.PAP64.pack ? -L.PAP64.pack : L.PAP64.lanes;
+    o->sell_stacked32 = L.PAP32.pack ? -L.PAP32.pack : L.PAP32.lanes;
+    o->sell_stacked_unit64 = L.PAP64.pack ? L.PAP64.unit : 0;
+    o->sell_stacked_unit32 = L.PAP32.pack ? L.PAP32.unit : 0;
+  }
   o->nnzb_M = L.nnzb_M;
   if (L.PAP64.col16) o->sell_index16 |= 1 << 10;
   return ASPAMG_OK;

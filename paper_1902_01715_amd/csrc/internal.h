@@ -13,6 +13,10 @@
 namespace aspamg {
 
 constexpr int kSell = 64;           // rows per SELL slice = one wavefront
+// row-packed layout: rows are packed into units of one wavefront (64 lanes)
+// or of one 256-thread workgroup; a row's lane count is kept in 8 bits of the
+// lane metadata
+constexpr int kPackMaxLanes = 255;
 constexpr int64_t kMinThreads = 262144;  // lanes per row grow until n * L reaches this
 constexpr int64_t kTimedSlots = 1 << 20;  // layouts of larger operators are chosen by timing
 // q = K p: lanes per row of the fine-level FP64 copy and workgroup size (one
@@ -91,6 +95,7 @@ struct Sell {
   int32_t b = 3;           // block size: values per slot b * b
   int32_t lanes = 1;       // L (sliced)
   int32_t pack = 0;        // K (row-packed), 0 for the sliced layout
+  int32_t unit = 0;        // lanes per packing unit (row-packed): 64 or 256
   int64_t ngroups = 0;     // slot groups (64 entries each)
   int64_t nnzb = 0;        // real blocks
   int32_t *sptr = nullptr;

@@ -176,10 +176,14 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int32_t n, const int32_t *__r
 }
 
 // The same product on the row-packed layout: every lane streams its K slot
-// groups (fully unrolled), parks its three partial sums in LDS, and the first
-// lane of each row adds the row's lanes in lane order and writes the row.
+// groups (fully unrolled) and parks its three partial sums in LDS; the first
+// lane of each row then adds the row's lanes in lane order and writes the row.
+// Rows are packed into units of 64 << ushift lanes (ushift 0: one wavefront,
+// 2: the workgroup's four) whose rows start at wrow[unit]; within a unit a
+// row's lanes may lie in different wavefronts, and the sums wait for a
+// workgroup barrier instead of a wavefront one.
 template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL, typename CI, int B>
-__global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t *__restrict__ wrow,
+__global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, int32_t ushift, const int32_t *__restrict__ wrow,
                                                    const uint16_t *__restrict__ meta, const CI *__restrict__ col,
                                                    const int32_t *__restrict__ cbase, const T *__restrict__ val,
                                                    const TX *__restrict__ x, TO *y, const TO *w, T alpha,
@@ -190,10 +194,10 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
   const int32_t t = xcd_block() * 256 + threadIdx.x;
   const int32_t wv = t >> 6, e = t & 63;
   const bool live = wv < nwaves;        // whole wavefronts
-  uint32_t m = 0x00FF;
+  uint32_t m = 0;
   T a0 = 0, a1 = 0, a2 = 0;
   // Every lane of a live wavefront finds the output row of its row (an
-  // unused lane takes the wavefront's first row) and loads that row of w
+  // unused lane has offset 0: the unit's first row) and loads that row of w
   // with the matrix stream.  There is no branch on the metadata, so the
   // stream's loads are issued before the metadata arrives; the lanes of one
   // row load the same addresses.
@@ -201,8 +205,7 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
   TO w0 = 0, w1 = 0, w2v = 0;
   if (live) {
     m = meta[(size_t)wv * 64 + e];
-    const int32_t off = (m & 0xFF) == 0xFF ? 0 : (int32_t)(m & 0xFF);
-    row = wrow[wv] + off;
+    row = wrow[wv >> ushift] + (int32_t)(m & 0xFF);
     if (DUAL) {
       const bool second = row >= n1;
       row = second ? row - n1 : row;
@@ -227,20 +230,24 @@ __global__ void __launch_bounds__(256) k_pack_spmv(int32_t nwaves, const int32_t
       slot_fma<B>(vp + 64 * B * B * k, e, x, c, a0, a1, a2);
     }
   }
-  // the lanes of a row never leave their wavefront, whose LDS operations
-  // complete in order: a wavefront-scope barrier suffices
   part[0][threadIdx.x] = a0;
   if constexpr (B == 3) {
     part[1][threadIdx.x] = a1;
     part[2][threadIdx.x] = a2;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (ushift == 0) {
+    // the lanes of a row never leave their wavefront, whose LDS operations
+    // complete in order: a wavefront-scope barrier suffices
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();                    // ushift is the same for the whole grid
+  }
   const int cnt = (int)(m >> 8);
   if (!live || cnt == 0) return;
   T s0 = 0, s1 = 0, s2 = 0;
-  for (int j = 0; j < cnt; ++j) {       // lanes of one row never leave the wavefront
+  for (int j = 0; j < cnt; ++j) {       // lanes of one row never leave their unit
     s0 += part[0][threadIdx.x + j];
     if constexpr (B == 3) {
       s1 += part[1][threadIdx.x + j];
@@ -667,14 +674,18 @@ static void launch_spmv_w(const Sell<T> &A, const TX *x, TO *y, const TO *w, dou
 template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL, int B>
 static void launch_kb(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,
                       hipStream_t s, int32_t n1, TO *y2, const TO *w2, double alpha2) {
-  const int64_t threads = (int64_t)A.nslices * 64;
-  const dim3 grid((unsigned)((threads + 255) / 256));
+  // units of one wavefront (ushift 0) or of the workgroup's four (ushift 2),
+  // which then fill whole workgroups
+  const int ushift = A.unit == 256 ? 2 : 0;
+  if ((A.unit != 64 && A.unit != 256) || (ushift == 2 && A.nslices % 4 != 0))
+    fail(ASPAMG_EINVAL, "row-packed layout with an unsupported packing unit");
+  const dim3 grid((unsigned)((A.nslices + 3) / 4));
   if (A.col16)
     hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, HAS_W, K, DUAL, uint16_t, B>), grid, dim3(256), 0, s, A.nslices,
-                       A.sptr, A.meta, A.col16, A.cbase, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
+                       ushift, A.sptr, A.meta, A.col16, A.cbase, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
   else
     hipLaunchKernelGGL((k_pack_spmv<T, TX, TO, HAS_W, K, DUAL, int32_t, B>), grid, dim3(256), 0, s, A.nslices,
-                       A.sptr, A.meta, A.col, nullptr, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
+                       ushift, A.sptr, A.meta, A.col, nullptr, A.val, x, y, w, (T)alpha, ctrl, n1, y2, w2, (T)alpha2);
 }
 template <typename T, typename TX, typename TO, bool HAS_W, int K, bool DUAL = false>
 static void launch_k(const Sell<T> &A, const TX *x, TO *y, const TO *w, double alpha, const PcgCtrl *ctrl,

@@ -1150,8 +1150,8 @@ void merge_smoother(aspamg_ctx *h, Level &L) {
     HIPCHK(hipStreamSynchronize(h->stream));
   }
   L.M64 = upload_sell<double>(h, M, 0, true, dM);
+  L.M32 = upload_sell<float>(h, M, 0, true, dM);
   dfree(h, dM);
-  L.M32 = derive_fp32(h, L.M64);
   L.nnzb_M = M.nnzb();
 }
 
@@ -1184,7 +1184,9 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     L.dA = upload_bsr(h, L.A);
     // lanes per fine row of q = K p; the layouts scatter from the block values of dA
     L.A64 = upload_sell<double>(h, L.A, l == 0 ? kKpLanes : 0, true, L.dA.v);
-    L.A32 = derive_fp32(h, L.A64);
+    // the fine level's FP32 residual product streams K at the device's practical
+    // rate in the q = K p layout; coarser levels choose a layout for FP32 too
+    L.A32 = l == 0 ? derive_fp32(h, L.A64) : upload_sell<float>(h, L.A, 0, true, L.dA.v);
     clk.tick(l, "upload A");
     const int b = L.A.b;
     if ((int64_t)N * b <= p.coarse_max_dof || l == p.max_levels - 1 || l == 31 || ntv == 0) {
@@ -1225,14 +1227,18 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     double *dPAP = nullptr;  // [P; A P] block values, on the device
     HostBSR Ac = galerkin(h, L, &AP, &dPAP);
     clk.tick(l, "Galerkin");
-    // device operators of this level
-    // (G64 and GT64 come from build_fsai); FP32 copies share the layouts
-    L.G32 = derive_fp32(h, L.G64);
-    L.GT32 = derive_fp32(h, L.GT64);
-    L.P64 = upload_sell<double>(h, L.P);
-    L.P32 = derive_fp32(h, L.P64);
-    L.R64 = upload_sell<double>(h, transpose(L.P));
-    L.R32 = derive_fp32(h, L.R64);
+    // device operators of this level (G64 and GT64 come from build_fsai); the
+    // FP32 copies choose their layouts in FP32, where the narrower values
+    // shift the balance between the matrix stream and the row reductions
+    {
+      const HostBSR GT = transpose(L.G), R = transpose(L.P);
+      L.G32 = upload_sell<float>(h, L.G);
+      L.GT32 = upload_sell<float>(h, GT);
+      L.P64 = upload_sell<double>(h, L.P);
+      L.P32 = upload_sell<float>(h, L.P);
+      L.R64 = upload_sell<double>(h, R);
+      L.R32 = upload_sell<float>(h, R);
+    }
     // the stacked [P; A P] replaces the products with P and A of the first
     // post-smoothing step only where it stores no more blocks than A: the
     // interpolation of a rich test space can make A P denser than A
@@ -1241,7 +1247,7 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
       HostBSR PAP = stack_rows(L.P, AP);
       AP = HostBSR();
       L.PAP64 = upload_sell<double>(h, PAP, 0, true, dPAP);
-      L.PAP32 = derive_fp32(h, L.PAP64);
+      L.PAP32 = upload_sell<float>(h, PAP, 0, true, dPAP);
     }
     AP = HostBSR();
     dfree(h, dPAP);

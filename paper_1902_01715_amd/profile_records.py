@@ -22,6 +22,19 @@
       taken is the one between the third and fourth fused K P launches.  Writes
       profiles/k_bsr_spmm_<WORKLOAD>_traffic.json and prints a markdown table.
 
+  python -m paper_1902_01715_amd.profile_records levels WORKLOAD COPY_DOUBLES BENCH_OUT TRACE_CSV FETCH_DB WRITE_DB TCC_DB CMD
+      Every V-cycle product per level and precision as `bench.py --level-table`
+      launches it (aspamg_time_operator: one warm-up launch, then the timed ones),
+      in four runs of the same command: --kernel-trace, FETCH_SIZE, WRITE_SIZE and
+      TCC_HIT_sum/TCC_MISS_sum.  The table's launches are the last ones of each run;
+      each product gets the median over its timed launches of the duration and of
+      the counters (FETCH and WRITE scaled by k_copy of COPY_DOUBLES doubles, as
+      for `traffic`), its algorithmic bytes from the benchmark line and the kernel
+      each run launched (the layouts are chosen by timing at set-up, so a run may
+      pick another layout for a product near a tie; such rows are flagged).
+      Writes profiles/k_sell_spmv_<WORKLOAD>_levels_traffic.json and prints a
+      markdown table.
+
   python -m paper_1902_01715_amd.profile_records stats KERNEL_STATS_CSV N
       The N most expensive kernels of a `rocprofv3 --kernel-trace --stats
       --output-format csv` run as a markdown table (names without the namespace and
@@ -215,11 +228,68 @@ def spmm(workload, bench_out, trace_csv, fetch_db, write_db, tcc_db, cmd):
     print(f"\niteration: {total_ns / 1e3:.1f} us")
 
 
+def levels_traffic(workload, copy_doubles, bench_out, trace_csv, fetch_db, write_db, tcc_db, cmd):
+    bench = None
+    for line in open(bench_out):
+        if line.startswith("{") and '"level_table"' in line:
+            bench = json.loads(line)
+    rows, reps = bench["level_table"], bench["level_table_reps"]
+    per_row = reps + 1
+    need = len(rows) * per_row
+    F, W, T = dispatches_db(fetch_db), dispatches_db(write_db), dispatches_db(tcc_db)
+    D = dispatches_trace(trace_csv)
+    copy_kib = copy_doubles * 8 / 1024
+    ff = copy_kib / statistics.median(c["FETCH_SIZE"] for n, c in F if n == "k_copy")
+    wf = copy_kib / statistics.median(c["WRITE_SIZE"] for n, c in W if n == "k_copy")
+    srcs = [F[-need:], W[-need:], T[-need:], D[-need:]]
+    if any(len(x) != need for x in srcs):
+        raise SystemExit("a run has fewer launches than the level table")
+    out = []
+    for i, row in enumerate(rows):
+        parts = [x[i * per_row:(i + 1) * per_row] for x in srcs]
+        names = [{n for n, _ in part} for part in parts]
+        kind = "k_dense_gemv" if row["op"] == "dense" else "spmv"
+        for ns in names:
+            if len(ns) != 1 or kind not in next(iter(ns)):
+                raise SystemExit(f"row {i} ({row['level']}, {row['prec']}, {row['op']}): launches {sorted(ns)}")
+        kern = [next(iter(ns)) for ns in names]
+        timed = [part[1:] for part in parts]
+        fetch = statistics.median(c["FETCH_SIZE"] for _, c in timed[0]) * ff * 1024
+        write = statistics.median(c["WRITE_SIZE"] for _, c in timed[1]) * wf * 1024
+        hit = statistics.median(c["TCC_HIT_sum"] for _, c in timed[2])
+        miss = statistics.median(c["TCC_MISS_sum"] for _, c in timed[2])
+        us = statistics.median(d for _, d in timed[3]) / 1e3
+        rec = {"level": row["level"], "prec": row["prec"], "op": row["op"], "per_cycle": row["per_cycle"],
+               "kernel": kern[3], "bytes_alg": row["bytes"], "fetch": fetch, "write": write,
+               "measured_over_alg": (fetch + write) / row["bytes"], "l2_hit": hit / max(hit + miss, 1),
+               "us": us, "alg_GBps": row["bytes"] / (us * 1e3)}
+        if len(set(kern)) != 1:
+            rec["kernel_by_run"] = {"fetch": kern[0], "write": kern[1], "tcc": kern[2], "trace": kern[3]}
+        out.append(rec)
+    rec = {"workload": workload, "command_pmc": cmd, "reps": reps,
+           "calibration": {"kernel": "k_copy", "bytes": copy_doubles * 8, "fetch_factor": ff, "write_factor": wf},
+           "levels": bench["levels"], "products": out,
+           "kernels_solve_sha256": hashlib.sha256(open(KERNELS, "rb").read()).hexdigest()}
+    path = os.path.join(ROOT, "profiles", f"k_sell_spmv_{workload}_levels_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print("| level | prec | product | per cycle | kernel | alg. MB | FETCH MB | WRITE MB | meas./alg. | L2 hit | us | alg. GB/s |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|")
+    for x in out:
+        flag = " (layout differs between runs)" if "kernel_by_run" in x else ""
+        print(f"| {x['level']} | {x['prec']} | {x['op']} | {x['per_cycle']} | `{x['kernel']}`{flag} | "
+              f"{x['bytes_alg'] / 1e6:.1f} | {x['fetch'] / 1e6:.1f} | {x['write'] / 1e6:.1f} | "
+              f"{x['measured_over_alg']:.2f} | {x['l2_hit']:.2f} | {x['us']:.1f} | {x['alg_GBps']:.0f} |")
+
+
 def main(argv):
     if len(argv) == 6 and argv[0] == "traffic":
         traffic(argv[1], int(argv[2]), argv[3], argv[4], argv[5])
     elif len(argv) == 8 and argv[0] == "spmm":
         spmm(*argv[1:])
+    elif len(argv) == 9 and argv[0] == "levels":
+        levels_traffic(argv[1], int(argv[2]), *argv[3:])
     elif len(argv) == 3 and argv[0] == "stats":
         stats(argv[1], int(argv[2]))
     else:

@@ -32,7 +32,7 @@ def test_default_params_and_struct_layout():
     # the ctypes mirrors have the C struct sizes (asserted at compile time in the library)
     assert ctypes.sizeof(aspamg.Params) == 160
     assert ctypes.sizeof(aspamg.Stats) == 104
-    assert ctypes.sizeof(aspamg.LevelInfo) == 144
+    assert ctypes.sizeof(aspamg.LevelInfo) == 200
 
 
 def test_last_error_is_a_string():

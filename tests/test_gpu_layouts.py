@@ -1,5 +1,6 @@
 """Both device layouts of the stored operators (sliced ELL with L lanes per row
-and row-packed with K slot groups per wavefront), forced through the `layout`
+and row-packed with K slot groups per lane in units of four wavefronts, where a
+row's lanes may lie in different wavefronts), forced through the `layout`
 parameter: every operator of every level against the oracle's matrices, the
 solve against the oracle, and the slot-count policy giving the same layouts and
 bitwise the same solution on two setups.  A randomly renumbered mesh, whose
@@ -11,7 +12,7 @@ from paper_1902_01715_amd import problems as PR
 
 pytestmark = pytest.mark.gpu
 
-POLICY = {"sliced": 2, "packed": 3}
+POLICY = {"sliced": 2, "packed": 3, "packed64": 4}     # row-packed in workgroup / wavefront units
 
 
 @pytest.fixture(scope="module")
@@ -34,17 +35,20 @@ def test_forced_layout_operators_and_solve(cuda, problem, form, product_bound):
         li = S.level_info(l)
         if li["sell_stacked"] != 0:     # 0: P, then A (A P denser than A)
             assert (li["sell_stacked"] > 0) == (form == "sliced")
-        if form == "packed" and li["sell_stacked"] != 0:   # the seam between P and A P starts a wavefront
+        if form != "sliced" and li["sell_stacked"] != 0:   # the seam between P and A P starts a unit
             assert li["sell_index16"] & (1 << 10)
-        for prec, lanes in ((64, li["sell_lanes64"]), (32, li["sell_lanes32"])):
+            assert li["sell_stacked_unit64"] == li["sell_stacked_unit32"] == (256 if form == "packed" else 64)
+        for prec, lanes, units in ((64, li["sell_lanes64"], li["sell_unit64"]),
+                                   (32, li["sell_lanes32"], li["sell_unit32"])):
             for which in range(5):
                 fixed = l == 0 and which == 0     # q = K p copy (and its FP32 twin): sliced, one lane
                 if fixed:
-                    assert lanes[which] == 1
+                    assert lanes[which] == 1 and units[which] == 0
                 elif form == "sliced":
-                    assert lanes[which] > 0, (l, which, prec)
+                    assert lanes[which] > 0 and units[which] == 0, (l, which, prec)
                 else:
                     assert lanes[which] < 0, (l, which, prec)
+                    assert units[which] == (256 if form == "packed" else 64), (l, which, prec)
                 M = {0: H.A(l), 1: H.G(l), 2: H.G(l), 3: H.P(l), 4: H.P(l)}[which].to_scipy().tocsr()
                 if which in (2, 4):
                     M = M.T.tocsr()
@@ -70,6 +74,41 @@ def test_forced_layout_operators_and_solve(cuda, problem, form, product_bound):
         assert st["relres_true"] <= 10 * max(rt_o, 1e-10)
         assert err <= 1e-8, err
     S.close()
+
+
+def _crossing_rows(lens, K):
+    """Rows whose lanes straddle a wavefront boundary inside a 256-lane unit of
+    the row-packed plan (rows in order, max(1, ceil(len / K)) lanes each, a new
+    unit when a row does not fit; no column-span break below 65,536 columns)."""
+    used, cross = 256, 0
+    for n in lens:
+        lr = max(1, -(-int(n) // K))
+        if used + lr > 256:
+            used = 0
+        cross += used // 64 != (used + lr - 1) // 64
+        used += lr
+    return cross
+
+
+def test_packed_rows_cross_wavefronts(cuda, problem):
+    """The forced row-packed layout of the problem above has rows whose lanes
+    lie in two wavefronts (their partial sums meet across the workgroup), so the
+    operator checks of test_forced_layout_operators_and_solve cover them."""
+    from paper_1902_01715_amd import aspamg
+    p, _ = problem
+    assert p.n_nodes < 65536                   # every unit's columns fit 16-bit offsets
+    S = aspamg.Solver(p.row_ptr, p.col, p.vals, p.V0, aspamg.default_params(layout=POLICY["packed"]))
+    try:
+        total = 0
+        for l in range(S.nlev - 1):
+            li = S.level_info(l)
+            for which in (1, 3):               # G and P: row lengths from the level's matrices
+                K = -li["sell_lanes64"][which]
+                rp = S.level_matrix(l, which)[0]
+                total += _crossing_rows(np.diff(rp), K)
+        assert total > 0
+    finally:
+        S.close()
 
 
 def test_slot_policy_is_reproducible(cuda, problem):

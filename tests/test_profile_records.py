@@ -116,3 +116,87 @@ def test_spmm_record_labels_one_iteration(tmp_path, monkeypatch, capsys):
     # A with the fused axpy: the matrix, row pointers, x, y and w
     assert a["bytes_alg"] == 50 * 40 + 11 * 4 + 3 * 10 * 48
     assert rec["iteration_us"] == 14 * 0.5
+
+
+def test_levels_record_takes_the_table_launches(tmp_path, monkeypatch, capsys):
+    ns = "void aspamg::(anonymous namespace)::"
+    sell, pack = ns + "k_sell_spmv<float, float, float, 4>(int)", ns + "k_pack_spmv<float, float, float, 2>(int)"
+    dense, copy = ns + "k_dense_gemv<float>(int)", ns + "k_copy(long, double const*, double*)"
+    rows = [{"level": 0, "prec": 32, "op": "residual A", "per_cycle": 1, "ms": 0.1, "bytes": 4.0e6, "GBps": 40.0},
+            {"level": 0, "prec": 32, "op": "G", "per_cycle": 2, "ms": 0.05, "bytes": 2.0e6, "GBps": 40.0},
+            {"level": 1, "prec": 32, "op": "dense", "per_cycle": 1, "ms": 0.01, "bytes": 1.0e5, "GBps": 10.0}]
+    reps = 3
+    # set-up and solve launches first (k_copy among them), then warm-up + reps per row
+    head = [copy, sell, copy, pack]
+    table = [sell] * (reps + 1) + [pack] * (reps + 1) + [dense] * (reps + 1)
+    seq = head + table
+    def db(path, counters):
+        con = sqlite3.connect(path)
+        con.execute("create table pmc_events (dispatch_id int, name text, counter_name text, counter_value real)")
+        for i, name in enumerate(seq):
+            for c, v in counters(i, name).items():
+                con.execute("insert into pmc_events values (?, ?, ?, ?)", (i + 1, name, c, v))
+        con.commit()
+        con.close()
+    kib = 8e6 / 1024                      # k_copy of 1,000,000 doubles
+    # the warm-up launch of each row reads a cold cache: 10x the counts, ignored by the median
+    warm = {len(head) + r * (reps + 1) for r in range(3)}
+    db(tmp_path / "f.db", lambda i, n: {"FETCH_SIZE": kib / 2 if "k_copy" in n else (1000.0 if i in warm else 100.0 + i % 2)})
+    db(tmp_path / "w.db", lambda i, n: {"WRITE_SIZE": kib if "k_copy" in n else 20.0})
+    db(tmp_path / "t.db", lambda i, n: {"TCC_HIT_sum": 9.0, "TCC_MISS_sum": 1.0})
+    with open(tmp_path / "trace.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for i, name in enumerate(seq):
+            # the trace run chose the sliced layout for G
+            name = sell if name == pack and i >= len(head) else name
+            w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Start_Timestamp": 10000 * i,
+                        "End_Timestamp": 10000 * i + 2000})
+    (tmp_path / "bench.out").write_text("[bench] x\n" + json.dumps({"levels": [{"n": 1}], "level_table": rows,
+                                                                    "level_table_reps": reps}) + "\n")
+    monkeypatch.setattr(pr, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    pr.main(["levels", "t", "1000000", str(tmp_path / "bench.out"), str(tmp_path / "trace.csv"),
+             str(tmp_path / "f.db"), str(tmp_path / "w.db"), str(tmp_path / "t.db"), "cmd PMC"])
+    rec = json.load(open(tmp_path / "profiles" / "k_sell_spmv_t_levels_traffic.json"))
+    a, g, d = rec["products"]
+    assert abs(rec["calibration"]["fetch_factor"] - 2.0) < 1e-12 and abs(rec["calibration"]["write_factor"] - 1.0) < 1e-12
+    # median of the timed launches only (the warm-up's 1000 KiB left out)
+    assert a["fetch"] in (100.0 * 2 * 1024, 101.0 * 2 * 1024) and a["write"] == 20.0 * 1024
+    assert abs(a["measured_over_alg"] - (a["fetch"] + a["write"]) / 4.0e6) < 1e-12
+    assert a["l2_hit"] == 0.9 and a["us"] == 2.0 and a["alg_GBps"] == 4.0e6 / 2000
+    assert "kernel_by_run" not in a and a["kernel"].startswith("k_sell_spmv")
+    assert g["kernel_by_run"]["fetch"].startswith("k_pack_spmv") and g["kernel_by_run"]["trace"].startswith("k_sell_spmv")
+    assert d["op"] == "dense" and d["kernel"].startswith("k_dense_gemv")
+    assert "layout differs between runs" in capsys.readouterr().out
+
+
+def test_levels_record_rejects_a_misaligned_run(tmp_path, monkeypatch):
+    ns = "void aspamg::(anonymous namespace)::"
+    sell, dense = ns + "k_sell_spmv<float, float, float, 4>(int)", ns + "k_dense_gemv<float>(int)"
+    copy = ns + "k_copy(long, double const*, double*)"
+    rows = [{"level": 0, "prec": 32, "op": "G", "per_cycle": 2, "ms": 0.05, "bytes": 2.0e6, "GBps": 40.0},
+            {"level": 1, "prec": 32, "op": "dense", "per_cycle": 1, "ms": 0.01, "bytes": 1.0e5, "GBps": 10.0}]
+    seq = [copy] + [sell] * 2 + [dense] * 3          # one launch short in the first row: misaligned by one
+    con = sqlite3.connect(tmp_path / "x.db")
+    con.execute("create table pmc_events (dispatch_id int, name text, counter_name text, counter_value real)")
+    for i, name in enumerate(seq):
+        for c in ("FETCH_SIZE", "WRITE_SIZE", "TCC_HIT_sum", "TCC_MISS_sum"):
+            con.execute("insert into pmc_events values (?, ?, ?, ?)", (i + 1, name, c, 1.0))
+    con.commit()
+    con.close()
+    with open(tmp_path / "trace.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for i, name in enumerate(seq):
+            w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Start_Timestamp": 0, "End_Timestamp": 1})
+    (tmp_path / "b.out").write_text(json.dumps({"levels": [], "level_table": rows, "level_table_reps": 2}) + "\n")
+    monkeypatch.setattr(pr, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    db = str(tmp_path / "x.db")
+    try:
+        pr.levels_traffic("t", 1000, str(tmp_path / "b.out"), str(tmp_path / "trace.csv"), db, db, db, "cmd")
+    except SystemExit as e:
+        assert "row 0" in str(e)
+    else:
+        raise AssertionError("a misaligned run was accepted")
