@@ -372,9 +372,10 @@ static std::vector<float> time_layouts(aspamg_ctx *h, const std::vector<Sell<T>>
 // T it is applied in.  With force_lanes the sliced layout with that many lanes
 // per row.  Otherwise the candidates are the sliced layout and the row-packed
 // ones with units of one wavefront and of one workgroup, each with its K of
-// fewest slots.  Those storing at most 1.5 times the sliced slots are built
-// and timed on this device in T, and the fastest is kept (a row-packed one
-// must beat the sliced one by 5%).  Operators under kTimedSlots slots, or all
+// fewest slots and with the next smaller K where that stores at most 10% more.
+// Those storing at most 1.5 times the sliced slots are built and timed on this
+// device in T, and the fastest is kept (a row-packed one must beat the sliced
+// one by 5%).  Operators under kTimedSlots slots, or all
 // of them without `timed`, take the wavefront-unit packing unless the
 // workgroup unit stores 10% fewer slots, and keep it when it stores 10% fewer
 // slots than the sliced layout.  Policy 2 forces the sliced
@@ -406,27 +407,39 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
     int K = 0, unit = 0;
     int64_t slots = 0;
     std::vector<int32_t> w0;
-  } pk[2];
+  };
+  // per unit (64, 256) and K (1, 2, 4, 8): the row-packed plan, K = 0 where a
+  // row needs more lanes than the unit holds
+  Plan all[2][4];
   std::vector<int32_t> lo, hi;
   row_spans(M, lo, hi);
   bool span16 = true;
   for (int32_t r = 0; r < M.n && span16; r++) span16 = hi[r] - lo[r] <= 65535;
-  const int units[2] = {64, 256};
-  for (int u = 0; u < 2; u++) {
-    pk[u].unit = units[u];
-    for (int K : {1, 2, 4, 8}) {
+  const int units[2] = {64, 256}, ks[4] = {1, 2, 4, 8};
+  for (int u = 0; u < 2; u++)
+    for (int i = 0; i < 4; i++) {
       // a scalar slot is one value: with fewer than kScalarMinPack per lane the
       // lane's share of a row is dominated by the in-row reduction
-      if (M.b == 1 && K < kScalarMinPack) continue;
-      std::vector<int32_t> w0 = packed_units(M, K, units[u], lo, hi, span16);
+      if (M.b == 1 && ks[i] < kScalarMinPack) continue;
+      std::vector<int32_t> w0 = packed_units(M, ks[i], units[u], lo, hi, span16);
       if (w0.empty()) continue;
-      const int64_t sl = (int64_t)(w0.size() - 1) * units[u] * K;
-      if (!pk[u].K || sl < pk[u].slots) {
-        pk[u].K = K;
-        pk[u].slots = sl;
-        pk[u].w0.swap(w0);
-      }
+      Plan &q = all[u][i];
+      q.K = ks[i];
+      q.unit = units[u];
+      q.slots = (int64_t)(w0.size() - 1) * units[u] * ks[i];
+      q.w0.swap(w0);
     }
+  // pk[u]: the plan of fewest slots in unit u; alt[u]: the next smaller K when it
+  // stores at most 10% more slots (more lanes per row, shorter lane chains)
+  Plan pk[2], alt[2];
+  for (int u = 0; u < 2; u++) {
+    int bi = -1;
+    for (int i = 0; i < 4; i++)
+      if (all[u][i].K && (bi < 0 || all[u][i].slots < all[u][bi].slots)) bi = i;
+    if (bi < 0) continue;
+    if (bi > 0 && all[u][bi - 1].K && (double)all[u][bi - 1].slots <= 1.1 * (double)all[u][bi].slots)
+      alt[u] = std::move(all[u][bi - 1]);
+    pk[u] = std::move(all[u][bi]);
   }
   auto packed = [&](const Plan &q) { return upload_packed<T>(h, M, q.K, q.unit, q.w0, dv.v); };
   if (policy == 3 || policy == 4) {
@@ -447,8 +460,8 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
   }
   std::vector<Sell<T>> cand;
   cand.push_back(upload_sliced<T>(h, M, L, sptr, dv.v));
-  for (const Plan &q : pk)
-    if (q.K && (double)q.slots <= 1.5 * (double)sliced) cand.push_back(packed(q));
+  for (const Plan *q : {&pk[0], &alt[0], &pk[1], &alt[1]})
+    if (q->K && (double)q->slots <= 1.5 * (double)sliced) cand.push_back(packed(*q));
   if (cand.size() == 1) return cand[0];
   T *x = nullptr, *y = nullptr;
   HIPCHK(hipMalloc(&x, sizeof(T) * M.b * (size_t)M.nc));
