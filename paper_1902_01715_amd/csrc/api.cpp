@@ -372,7 +372,7 @@ static std::vector<float> time_layouts(aspamg_ctx *h, const std::vector<Sell<T>>
 // T it is applied in.  With force_lanes the sliced layout with that many lanes
 // per row.  Otherwise the candidates are the sliced layout and the row-packed
 // ones with units of one wavefront and of one workgroup, each with its K of
-// fewest slots and with the next smaller K where that stores at most 10% more.
+// fewest slots and with every smaller K that stores at most 10% more.
 // Those storing at most 1.5 times the sliced slots are built and timed on this
 // device in T, and the fastest is kept (a row-packed one must beat the sliced
 // one by 5%).  Operators under kTimedSlots slots, or all
@@ -429,16 +429,18 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
       q.slots = (int64_t)(w0.size() - 1) * units[u] * ks[i];
       q.w0.swap(w0);
     }
-  // pk[u]: the plan of fewest slots in unit u; alt[u]: the next smaller K when it
-  // stores at most 10% more slots (more lanes per row, shorter lane chains)
-  Plan pk[2], alt[2];
+  // pk[u]: the plan of fewest slots in unit u; alt[u]: the smaller K that store
+  // at most 10% more slots (more lanes per row, shorter lane chains)
+  Plan pk[2];
+  std::vector<Plan> alt[2];
   for (int u = 0; u < 2; u++) {
     int bi = -1;
     for (int i = 0; i < 4; i++)
       if (all[u][i].K && (bi < 0 || all[u][i].slots < all[u][bi].slots)) bi = i;
     if (bi < 0) continue;
-    if (bi > 0 && all[u][bi - 1].K && (double)all[u][bi - 1].slots <= 1.1 * (double)all[u][bi].slots)
-      alt[u] = std::move(all[u][bi - 1]);
+    for (int i = bi - 1; i >= 0; i--)
+      if (all[u][i].K && (double)all[u][i].slots <= 1.1 * (double)all[u][bi].slots)
+        alt[u].push_back(std::move(all[u][i]));
     pk[u] = std::move(all[u][bi]);
   }
   auto packed = [&](const Plan &q) { return upload_packed<T>(h, M, q.K, q.unit, q.w0, dv.v); };
@@ -460,8 +462,11 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
   }
   std::vector<Sell<T>> cand;
   cand.push_back(upload_sliced<T>(h, M, L, sptr, dv.v));
-  for (const Plan *q : {&pk[0], &alt[0], &pk[1], &alt[1]})
-    if (q->K && (double)q->slots <= 1.5 * (double)sliced) cand.push_back(packed(*q));
+  for (int u = 0; u < 2; u++) {
+    if (pk[u].K && (double)pk[u].slots <= 1.5 * (double)sliced) cand.push_back(packed(pk[u]));
+    for (const Plan &q : alt[u])
+      if ((double)q.slots <= 1.5 * (double)sliced) cand.push_back(packed(q));
+  }
   if (cand.size() == 1) return cand[0];
   T *x = nullptr, *y = nullptr;
   HIPCHK(hipMalloc(&x, sizeof(T) * M.b * (size_t)M.nc));
