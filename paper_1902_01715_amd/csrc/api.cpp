@@ -372,7 +372,7 @@ static std::vector<float> time_layouts(aspamg_ctx *h, const std::vector<Sell<T>>
 // T it is applied in.  With force_lanes the sliced layout with that many lanes
 // per row.  Otherwise the candidates are the sliced layout and the row-packed
 // ones with units of one wavefront and of one workgroup, each with its K of
-// fewest slots and with every smaller K that stores at most 10% more.
+// fewest slots and with every other K that stores at most 10% more.
 // Those storing at most 1.5 times the sliced slots are built and timed on this
 // device in T, and the fastest is kept (a row-packed one must beat the sliced
 // one by 5%).  Operators under kTimedSlots slots, or all
@@ -429,8 +429,9 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
       q.slots = (int64_t)(w0.size() - 1) * units[u] * ks[i];
       q.w0.swap(w0);
     }
-  // pk[u]: the plan of fewest slots in unit u; alt[u]: the smaller K that store
-  // at most 10% more slots (more lanes per row, shorter lane chains)
+  // pk[u]: the plan of fewest slots in unit u; alt[u]: the other K that store at
+  // most 10% more slots (a smaller K gives a row more lanes and each lane a
+  // shorter chain, a larger one each lane more work per row sum)
   Plan pk[2];
   std::vector<Plan> alt[2];
   for (int u = 0; u < 2; u++) {
@@ -438,8 +439,8 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
     for (int i = 0; i < 4; i++)
       if (all[u][i].K && (bi < 0 || all[u][i].slots < all[u][bi].slots)) bi = i;
     if (bi < 0) continue;
-    for (int i = bi - 1; i >= 0; i--)
-      if (all[u][i].K && (double)all[u][i].slots <= 1.1 * (double)all[u][bi].slots)
+    for (int i = 0; i < 4; i++)
+      if (i != bi && all[u][i].K && (double)all[u][i].slots <= 1.1 * (double)all[u][bi].slots)
         alt[u].push_back(std::move(all[u][i]));
     pk[u] = std::move(all[u][bi]);
   }
