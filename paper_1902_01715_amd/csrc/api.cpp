@@ -156,14 +156,24 @@ static std::vector<int32_t> settle_columns(std::vector<int32_t> &col, int32_t no
   return base;
 }
 
-// Device arrays of a layout: slice/wavefront pointers, columns (16-bit
+// One candidate layout of an operator on the device: its index arrays (in a
+// Sell whose values are not set) and the per-slot source map that scatters
+// the operator's block values into any precision's copy.
+struct Candidate {
+  Sell<double> idx;
+  int32_t *map = nullptr;
+  int64_t nslots = 0;
+};
+
+// Device index arrays of a layout: slice/unit pointers, columns (16-bit
 // offsets when `base` is not empty), the lane metadata of the row-packed
-// layout, and the values, scattered on the device from the block values `dv`
-// of the source matrix (device copy) by the per-slot source map.
-template <typename T>
-static void upload_arrays(aspamg_ctx *h, Sell<T> &S, const std::vector<int32_t> &sptr, const std::vector<int32_t> &col,
-                          const std::vector<int32_t> &base, const std::vector<int32_t> &map, const double *dv,
-                          const std::vector<uint16_t> &meta) {
+// layout, and the per-slot source map.
+static Candidate upload_index(aspamg_ctx *h, const Sell<double> &shape, const std::vector<int32_t> &sptr,
+                              const std::vector<int32_t> &col, const std::vector<int32_t> &base,
+                              const std::vector<int32_t> &map, const std::vector<uint16_t> &meta) {
+  Candidate c;
+  c.idx = shape;
+  Sell<double> &S = c.idx;
   S.sptr = dalloc<int32_t>(h, sptr.size());
   HIPCHK(hipMemcpyAsync(S.sptr, sptr.data(), sptr.size() * 4, hipMemcpyHostToDevice, h->stream));
   std::vector<uint16_t> c16;
@@ -189,21 +199,59 @@ static void upload_arrays(aspamg_ctx *h, Sell<T> &S, const std::vector<int32_t> 
     S.meta = dalloc<uint16_t>(h, meta.size());
     HIPCHK(hipMemcpyAsync(S.meta, meta.data(), meta.size() * 2, hipMemcpyHostToDevice, h->stream));
   }
-  const int64_t nslots = (int64_t)map.size();
-  S.val = dalloc<T>(h, (size_t)std::max<int64_t>(S.values(), 1));
-  int32_t *dmap = dalloc<int32_t>(h, std::max<size_t>(map.size(), 1));
-  HIPCHK(hipMemcpyAsync(dmap, map.data(), map.size() * 4, hipMemcpyHostToDevice, h->stream));
-  launch_scatter_values<T>(nslots, dmap, dv, S.val, S.b, h->stream);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(h->stream));
-  dfree(h, dmap);
+  c.nslots = (int64_t)map.size();
+  c.map = dalloc<int32_t>(h, std::max<size_t>(map.size(), 1));
+  HIPCHK(hipMemcpyAsync(c.map, map.data(), map.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));   // the host arrays go out of scope
+  return c;
 }
 
+// A Sell<T> with the layout fields and index arrays of S (shared, not copied)
+// and no values.
+template <typename T, typename U>
+static Sell<T> same_index(const Sell<U> &S) {
+  Sell<T> F;
+  F.n = S.n;
+  F.nc = S.nc;
+  F.b = S.b;
+  F.nslices = S.nslices;
+  F.lanes = S.lanes;
+  F.pack = S.pack;
+  F.unit = S.unit;
+  F.ngroups = S.ngroups;
+  F.nnzb = S.nnzb;
+  F.sptr = S.sptr;
+  F.col = S.col;
+  F.col16 = S.col16;
+  F.cbase = S.cbase;
+  F.meta = S.meta;
+  return F;
+}
+
+// The candidate's copy in precision T: its index arrays, and values scattered
+// from the operator's block values dv (device copy).
 template <typename T>
-static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, int unit, const std::vector<int32_t> &w0,
-                             const double *dv) {
+static Sell<T> with_values(aspamg_ctx *h, const Candidate &c, const double *dv) {
+  Sell<T> S = same_index<T>(c.idx);
+  S.val = dalloc<T>(h, (size_t)std::max<int64_t>(S.values(), 1));
+  launch_scatter_values<T>(c.nslots, c.map, dv, S.val, S.b, h->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return S;
+}
+
+static void free_index(aspamg_ctx *h, Candidate &c) {
+  dfree(h, c.idx.sptr);
+  dfree(h, c.idx.col);
+  dfree(h, c.idx.col16);
+  dfree(h, c.idx.cbase);
+  dfree(h, c.idx.meta);
+  c.idx = Sell<double>();
+}
+
+static Candidate packed_layout(aspamg_ctx *h, const HostBSR &M, int K, int unit, const std::vector<int32_t> &w0) {
   const int kWaves = unit / 64;
-  Sell<T> S;
+  Sell<double> S;
   S.n = M.n;
   S.nc = M.nc;
   S.b = M.b;
@@ -252,8 +300,7 @@ static Sell<T> upload_packed(aspamg_ctx *h, const HostBSR &M, int K, int unit, c
   }
   const int64_t Kp = K;
   std::vector<int32_t> base = settle_columns(col, S.nslices, [Kp](int32_t s) { return (int64_t)s * Kp; });
-  upload_arrays(h, S, w0, col, base, map, dv, meta);
-  return S;
+  return upload_index(h, S, w0, col, base, map, meta);
 }
 
 #ifndef ASPAMG_SCALAR_MIN_PACK
@@ -285,10 +332,8 @@ static int sliced_plan(const HostBSR &M, int force_lanes, std::vector<int32_t> *
   return L;
 }
 
-template <typename T>
-static Sell<T> upload_sliced(aspamg_ctx *h, const HostBSR &M, int L, const std::vector<int32_t> &sptr,
-                             const double *dv) {
-  Sell<T> S;
+static Candidate sliced_layout(aspamg_ctx *h, const HostBSR &M, int L, const std::vector<int32_t> &sptr) {
+  Sell<double> S;
   S.n = M.n;
   S.nc = M.nc;
   S.b = M.b;
@@ -312,8 +357,7 @@ static Sell<T> upload_sliced(aspamg_ctx *h, const HostBSR &M, int L, const std::
     }
   }
   std::vector<int32_t> base = settle_columns(col, S.nslices, [&sptr](int32_t s) { return (int64_t)sptr[s]; });
-  upload_arrays(h, S, sptr, col, base, map, dv, {});
-  return S;
+  return upload_index(h, S, sptr, col, base, map, {});
 }
 
 void dfree(aspamg_ctx *h, void *p) {
@@ -325,12 +369,14 @@ void dfree(aspamg_ctx *h, void *p) {
 
 template <typename T>
 void free_sell(aspamg_ctx *h, Sell<T> &S) {
-  dfree(h, S.sptr);
-  dfree(h, S.col);
-  dfree(h, S.col16);
-  dfree(h, S.cbase);
+  if (S.own_index) {
+    dfree(h, S.sptr);
+    dfree(h, S.col);
+    dfree(h, S.col16);
+    dfree(h, S.cbase);
+    dfree(h, S.meta);
+  }
   dfree(h, S.val);
-  dfree(h, S.meta);
   S = Sell<T>();
 }
 
@@ -368,40 +414,28 @@ static std::vector<float> time_layouts(aspamg_ctx *h, const std::vector<Sell<T>>
   return med;
 }
 
-// Device copy of M used by the products of the solve phase, in the precision
-// T it is applied in.  With force_lanes the sliced layout with that many lanes
-// per row.  Otherwise the candidates are the sliced layout and the row-packed
-// ones with units of one wavefront and of one workgroup, each with its K of
-// fewest slots and with every other K that stores at most 10% more.
-// Those storing at most 1.5 times the sliced slots are built and timed on this
-// device in T, and the fastest is kept (a row-packed one must beat the sliced
-// one by 5%).  Operators under kTimedSlots slots, or all
-// of them without `timed`, take the wavefront-unit packing unless the
-// workgroup unit stores 10% fewer slots, and keep it when it stores 10% fewer
-// slots than the sliced layout.  Policy 2 forces the sliced
-// layout, 3 and 4 the row-packed one with units of a workgroup and of a
-// wavefront (sliced where a row needs more lanes than a unit holds).
-template <typename T>
-Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed, const double *dvals) {
+// Candidate layouts of M for the products of the solve phase, the sliced one
+// first.  With force_lanes the sliced layout with that many lanes per row.
+// Otherwise, for the timed choice, the sliced layout and the row-packed ones
+// with units of one wavefront and of one workgroup, each with its K of fewest
+// slots and every other K that stores at most 10% more, those storing at most
+// 1.5 times the sliced slots; each precision's copy then times them on the
+// device (keep_fastest).  Operators under kTimedSlots slots, or all of them
+// without `timed`, get one layout: the wavefront-unit packing unless the
+// workgroup unit stores 10% fewer slots, kept when it stores 10% fewer slots
+// than the sliced layout.  Policy 2 forces the sliced layout, 3 and 4 the
+// row-packed one with units of a workgroup and of a wavefront (sliced where a
+// row needs more lanes than a unit holds).
+static std::vector<Candidate> candidates(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed) {
   const int policy = h->p.layout;
   if (M.nnzb() >= (int64_t)INT32_MAX) fail(ASPAMG_EINVAL, "operator too large for int32 block indices");
   std::vector<int32_t> sptr;
   const int L = sliced_plan(M, force_lanes, &sptr);
-  // the block values on the device once; every layout built below scatters from them
-  struct Values {
-    aspamg_ctx *h;
-    double *v;
-    bool own;
-    ~Values() {
-      if (own) dfree(h, v);
-    }
-  } dv{h, const_cast<double *>(dvals), dvals == nullptr};
-  if (!dvals) {
-    dv.v = dalloc<double>(h, std::max<size_t>(M.v.size(), 1));
-    if (!M.v.empty())
-      HIPCHK(hipMemcpyAsync(dv.v, M.v.data(), M.v.size() * 8, hipMemcpyHostToDevice, h->stream));
+  std::vector<Candidate> C;
+  if (force_lanes || M.n == 0 || M.nc == 0 || policy == 2) {
+    C.push_back(sliced_layout(h, M, L, sptr));
+    return C;
   }
-  if (force_lanes || M.n == 0 || M.nc == 0 || policy == 2) return upload_sliced<T>(h, M, L, sptr, dv.v);
   if (policy != 0) timed = false;
   struct Plan {
     int K = 0, unit = 0;
@@ -444,70 +478,130 @@ Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed
         alt[u].push_back(std::move(all[u][i]));
     pk[u] = std::move(all[u][bi]);
   }
-  auto packed = [&](const Plan &q) { return upload_packed<T>(h, M, q.K, q.unit, q.w0, dv.v); };
+  auto packed = [&](const Plan &q) { C.push_back(packed_layout(h, M, q.K, q.unit, q.w0)); };
   if (policy == 3 || policy == 4) {
     const Plan &q = pk[policy == 3 ? 1 : 0];
-    return q.K ? packed(q) : upload_sliced<T>(h, M, L, sptr, dv.v);
+    if (q.K) packed(q);
+    else C.push_back(sliced_layout(h, M, L, sptr));
+    return C;
   }
   // untimed choice: the wavefront unit unless the workgroup unit stores 10%
   // fewer slots (its barrier costs the most where the product is short)
   const Plan *best = pk[0].K ? &pk[0] : nullptr;
   if (pk[1].K && (!best || (double)pk[1].slots < 0.9 * (double)best->slots)) best = &pk[1];
-  if (!best) return upload_sliced<T>(h, M, L, sptr, dv.v);   // a row needs more than kPackMaxLanes lanes
   const int64_t sliced = (int64_t)sptr.back() * 64;
+  if (!best) {                    // a row needs more than kPackMaxLanes lanes
+    C.push_back(sliced_layout(h, M, L, sptr));
+    return C;
+  }
   // small operators sit at the launch-latency floor either way: no timing
   const int64_t fewest = pk[0].K && pk[1].K ? std::min(pk[0].slots, pk[1].slots) : best->slots;
   if (!timed || std::max<int64_t>(fewest, sliced) < kTimedSlots) {
-    if ((double)best->slots >= 0.9 * (double)sliced) return upload_sliced<T>(h, M, L, sptr, dv.v);
-    return packed(*best);
+    if ((double)best->slots >= 0.9 * (double)sliced) C.push_back(sliced_layout(h, M, L, sptr));
+    else packed(*best);
+    return C;
   }
-  std::vector<Sell<T>> cand;
-  cand.push_back(upload_sliced<T>(h, M, L, sptr, dv.v));
+  C.push_back(sliced_layout(h, M, L, sptr));
   for (int u = 0; u < 2; u++) {
-    if (pk[u].K && (double)pk[u].slots <= 1.5 * (double)sliced) cand.push_back(packed(pk[u]));
+    if (pk[u].K && (double)pk[u].slots <= 1.5 * (double)sliced) packed(pk[u]);
     for (const Plan &q : alt[u])
-      if ((double)q.slots <= 1.5 * (double)sliced) cand.push_back(packed(q));
+      if ((double)q.slots <= 1.5 * (double)sliced) packed(q);
   }
-  if (cand.size() == 1) return cand[0];
-  T *x = nullptr, *y = nullptr;
-  HIPCHK(hipMalloc(&x, sizeof(T) * M.b * (size_t)M.nc));
-  HIPCHK(hipMalloc(&y, sizeof(T) * M.b * (size_t)M.n));
-  std::vector<float> t;
-  try {
-    HIPCHK(hipMemsetAsync(x, 0, sizeof(T) * M.b * (size_t)M.nc, h->stream));
-    t = time_layouts(h, cand, x, y);
-  } catch (...) {
+  return C;
+}
+
+// The block values of M on the device: dvals when given, else uploaded here
+// (and freed with this object).
+struct DeviceValues {
+  aspamg_ctx *h;
+  double *v;
+  bool own;
+  DeviceValues(aspamg_ctx *hh, const HostBSR &M, const double *dvals)
+      : h(hh), v(const_cast<double *>(dvals)), own(dvals == nullptr) {
+    if (own) {
+      v = dalloc<double>(h, std::max<size_t>(M.v.size(), 1));
+      if (!M.v.empty()) HIPCHK(hipMemcpyAsync(v, M.v.data(), M.v.size() * 8, hipMemcpyHostToDevice, h->stream));
+    }
+  }
+  ~DeviceValues() {
+    if (own) dfree(h, v);
+  }
+  DeviceValues(const DeviceValues &) = delete;
+  DeviceValues &operator=(const DeviceValues &) = delete;
+};
+
+// The copies of every candidate in precision T; with more than one, each is
+// timed on the device (7 rounds of turns, medians) and the fastest kept, a
+// row-packed one having to beat the sliced one (first) by 5%.  The values of
+// the others are freed; returns the kept copy, its candidate's index in *picked.
+template <typename T>
+static Sell<T> keep_fastest(aspamg_ctx *h, const HostBSR &M, const std::vector<Candidate> &C, const double *dv,
+                            size_t *picked) {
+  std::vector<Sell<T>> v;
+  for (const Candidate &c : C) v.push_back(with_values<T>(h, c, dv));
+  size_t pick = 0;
+  if (v.size() > 1) {
+    const size_t nx = (size_t)M.b * std::max<int32_t>(M.nc, 1), ny = (size_t)M.b * std::max<int32_t>(M.n, 1);
+    T *x = nullptr, *y = nullptr;
+    HIPCHK(hipMalloc(&x, sizeof(T) * nx));
+    HIPCHK(hipMalloc(&y, sizeof(T) * ny));
+    std::vector<float> t;
+    try {
+      HIPCHK(hipMemsetAsync(x, 0, sizeof(T) * nx, h->stream));
+      t = time_layouts(h, v, x, y);
+    } catch (...) {
+      (void)hipFree(x);
+      (void)hipFree(y);
+      throw;
+    }
     (void)hipFree(x);
     (void)hipFree(y);
-    throw;
+    for (size_t j = 1; j < v.size(); j++)
+      if (t[j] < 0.95f * t[0] && (pick == 0 || t[j] < t[pick])) pick = j;
   }
-  (void)hipFree(x);
-  (void)hipFree(y);
-  size_t pick = 0;
-  for (size_t j = 1; j < cand.size(); j++)
-    if (t[j] < 0.95f * t[0] && (pick == 0 || t[j] < t[pick])) pick = j;
-  for (size_t j = 0; j < cand.size(); j++)
-    if (j != pick) free_sell(h, cand[j]);
-  return cand[pick];
+  for (size_t j = 0; j < v.size(); j++)
+    if (j != pick) dfree(h, v[j].val);
+  *picked = pick;
+  return v[pick];
 }
-// FP32 copy of S in the same layout: the index arrays are shared with S (so
-// the copy is never freed on its own), the values converted on the device.
+
+// Device copy of M used by the products of the solve phase, in precision T,
+// in the layout chosen among candidates() (timed in T where there are several).
+template <typename T>
+Sell<T> upload_sell(aspamg_ctx *h, const HostBSR &M, int force_lanes, bool timed, const double *dvals) {
+  DeviceValues dv(h, M, dvals);
+  std::vector<Candidate> C = candidates(h, M, force_lanes, timed);
+  size_t pick = 0;
+  Sell<T> S = keep_fastest<T>(h, M, C, dv.v, &pick);
+  for (size_t j = 0; j < C.size(); j++) {
+    dfree(h, C[j].map);
+    if (j != pick) free_index(h, C[j]);
+  }
+  return S;
+}
+
+// The FP64 and FP32 copies of M, each in the layout timed in its own
+// precision.  The candidates' index arrays are built once for both; when the
+// two copies pick the same candidate, the FP32 copy shares the FP64 copy's
+// index arrays.
+void upload_sell_pair(aspamg_ctx *h, const HostBSR &M, const double *dvals, Sell<double> &d64, Sell<float> &d32) {
+  DeviceValues dv(h, M, dvals);
+  std::vector<Candidate> C = candidates(h, M, 0, true);
+  size_t p64 = 0, p32 = 0;
+  d64 = keep_fastest<double>(h, M, C, dv.v, &p64);
+  d32 = keep_fastest<float>(h, M, C, dv.v, &p32);
+  d32.own_index = p32 != p64;
+  for (size_t j = 0; j < C.size(); j++) {
+    dfree(h, C[j].map);
+    if (j != p64 && j != p32) free_index(h, C[j]);
+  }
+}
+
+// FP32 copy of S in the same layout: the index arrays are shared with S (the
+// copy does not own them), the values converted on the device.
 Sell<float> derive_fp32(aspamg_ctx *h, const Sell<double> &S) {
-  Sell<float> F;
-  F.n = S.n;
-  F.nc = S.nc;
-  F.b = S.b;
-  F.nslices = S.nslices;
-  F.lanes = S.lanes;
-  F.pack = S.pack;
-  F.unit = S.unit;
-  F.ngroups = S.ngroups;
-  F.nnzb = S.nnzb;
-  F.sptr = S.sptr;
-  F.col = S.col;
-  F.col16 = S.col16;
-  F.cbase = S.cbase;
-  F.meta = S.meta;
+  Sell<float> F = same_index<float>(S);
+  F.own_index = false;
   const int64_t nv = S.values();
   F.val = dalloc<float>(h, (size_t)std::max<int64_t>(nv, 1));
   if (nv > 0) launch_narrow_values(S.ngroups * 64, S.val, F.val, S.b, h->stream);

@@ -104,6 +104,7 @@ struct Sell {
   int32_t *cbase = nullptr;
   T *val = nullptr;
   uint16_t *meta = nullptr;
+  bool own_index = true;   // false where the index arrays belong to another copy
   int64_t slots() const { return ngroups * 64; }
   int64_t values() const { return ngroups * 64 * b * b; }
   int index_bytes() const { return col16 ? 2 : 4; }
@@ -240,6 +241,9 @@ template <typename T>
 void free_sell(aspamg_ctx *h, Sell<T> &S);   // releases the device arrays of S
 // FP32 copy in the same layout, sharing S's index arrays (never freed on its own)
 Sell<float> derive_fp32(aspamg_ctx *h, const Sell<double> &S);
+// FP64 and FP32 copies of M, each in the layout timed in its own precision
+// (index arrays built once; shared when both copies pick the same layout)
+void upload_sell_pair(aspamg_ctx *h, const HostBSR &M, const double *dvals, Sell<double> &d64, Sell<float> &d32);
 DevBSR upload_bsr(aspamg_ctx *h, const HostBSR &M);
 
 // ---- solve-path kernel launchers (kernels_solve.hip) ----

@@ -376,12 +376,14 @@ void build_fsai(aspamg_ctx *h, Level &L) {
   clk.tick(-1, "fsai assemble");
   L.fsai_rounds = 0;
   for (;;) {
-    // device copies of G and G^T (kept as the level's operators when the
-    // outer loop stops here)
-    L.G64 = upload_sell<double>(h, L.G);
-    L.GT64 = upload_sell<double>(h, transpose(L.G));
+    // device copies of G and G^T for the Lanczos estimate, in the layouts
+    // chosen by stored slots (no timing: the loop may run many rounds)
+    Sell<double> g = upload_sell<double>(h, L.G, 0, false);
+    Sell<double> gt = upload_sell<double>(h, transpose(L.G), 0, false);
     clk.tick(-1, "fsai G upload");
-    L.lambda1 = lanczos_gagt(h, L, L.G64, L.GT64, p.lanczos_steps);
+    L.lambda1 = lanczos_gagt(h, L, g, gt, p.lanczos_steps);
+    free_sell(h, g);
+    free_sell(h, gt);
     clk.tick(-1, "lanczos");
     L.omega_q = 2.0 / L.lambda1;
     if (!p.outer_fsai) break;
@@ -393,13 +395,16 @@ void build_fsai(aspamg_ctx *h, Level &L) {
     std::vector<int32_t> rows;
     for (int32_t I = 0; I < n; I++)
       if (grew[I]) rows.push_back(I);
-    if (rows.empty()) break;            // G unchanged: its device copies stay
-    free_sell(h, L.G64);
-    free_sell(h, L.GT64);
+    if (rows.empty()) break;            // G unchanged
     fsai_factor(h, L, F, rows);
     L.G = fsai_assemble(F);
     L.fsai_rounds++;
   }
+  // the level's operators: G and G^T of the final round, FP64 and FP32 copies
+  // in the layouts timed on the device
+  upload_sell_pair(h, L.G, nullptr, L.G64, L.G32);
+  upload_sell_pair(h, transpose(L.G), nullptr, L.GT64, L.GT32);
+  clk.tick(-1, "fsai G upload");
   const double w = 2.0 / (p.omega_safety * L.lambda1);
   L.omega_s = w < 1.0 ? w : 1.0;
 }
@@ -1149,8 +1154,7 @@ void merge_smoother(aspamg_ctx *h, Level &L) {
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
   }
-  L.M64 = upload_sell<double>(h, M, 0, true, dM);
-  L.M32 = upload_sell<float>(h, M, 0, true, dM);
+  upload_sell_pair(h, M, dM, L.M64, L.M32);
   dfree(h, dM);
   L.nnzb_M = M.nnzb();
 }
@@ -1183,10 +1187,14 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     const int32_t N = L.A.n;
     L.dA = upload_bsr(h, L.A);
     // lanes per fine row of q = K p; the layouts scatter from the block values of dA
-    L.A64 = upload_sell<double>(h, L.A, l == 0 ? kKpLanes : 0, true, L.dA.v);
     // the fine level's FP32 residual product streams K at the device's practical
     // rate in the q = K p layout; coarser levels choose a layout for FP32 too
-    L.A32 = l == 0 ? derive_fp32(h, L.A64) : upload_sell<float>(h, L.A, 0, true, L.dA.v);
+    if (l == 0) {
+      L.A64 = upload_sell<double>(h, L.A, kKpLanes, true, L.dA.v);
+      L.A32 = derive_fp32(h, L.A64);
+    } else {
+      upload_sell_pair(h, L.A, L.dA.v, L.A64, L.A32);
+    }
     clk.tick(l, "upload A");
     const int b = L.A.b;
     if ((int64_t)N * b <= p.coarse_max_dof || l == p.max_levels - 1 || l == 31 || ntv == 0) {
@@ -1227,18 +1235,11 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
     double *dPAP = nullptr;  // [P; A P] block values, on the device
     HostBSR Ac = galerkin(h, L, &AP, &dPAP);
     clk.tick(l, "Galerkin");
-    // device operators of this level (G64 and GT64 come from build_fsai); the
+    // device operators of this level (G and G^T come from build_fsai); the
     // FP32 copies choose their layouts in FP32, where the narrower values
     // shift the balance between the matrix stream and the row reductions
-    {
-      const HostBSR GT = transpose(L.G), R = transpose(L.P);
-      L.G32 = upload_sell<float>(h, L.G);
-      L.GT32 = upload_sell<float>(h, GT);
-      L.P64 = upload_sell<double>(h, L.P);
-      L.P32 = upload_sell<float>(h, L.P);
-      L.R64 = upload_sell<double>(h, R);
-      L.R32 = upload_sell<float>(h, R);
-    }
+    upload_sell_pair(h, L.P, nullptr, L.P64, L.P32);
+    upload_sell_pair(h, transpose(L.P), nullptr, L.R64, L.R32);
     // the stacked [P; A P] replaces the products with P and A of the first
     // post-smoothing step only where it stores no more blocks than A: the
     // interpolation of a rich test space can make A P denser than A
@@ -1246,8 +1247,7 @@ void build_hierarchy(aspamg_ctx *h, HostBSR &&A0, std::vector<double> &&V0) {
       L.nnzb_AP = AP.nnzb();
       HostBSR PAP = stack_rows(L.P, AP);
       AP = HostBSR();
-      L.PAP64 = upload_sell<double>(h, PAP, 0, true, dPAP);
-      L.PAP32 = upload_sell<float>(h, PAP, 0, true, dPAP);
+      upload_sell_pair(h, PAP, dPAP, L.PAP64, L.PAP32);
     }
     AP = HostBSR();
     dfree(h, dPAP);
