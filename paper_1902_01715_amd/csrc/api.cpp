@@ -91,46 +91,6 @@ static void row_spans(const HostBSR &M, std::vector<int32_t> &lo, std::vector<in
     }
 }
 
-// Row-packed layout with K slot groups per lane, packed into units of `unit`
-// lanes (64: one wavefront; 256: the four of one workgroup): rows in matrix
-// order, max(1, ceil(len/K)) lanes each, a new unit whenever a row does not
-// fit.  In a 256-lane unit a row may cross wavefronts (its lanes meet in LDS
-// behind a workgroup barrier), so the unit leaves fewer lanes unused than a
-// single wavefront would.  When every row on its own spans at most 65,536
-// columns, a new unit also starts where the next row would widen the unit's
-// span beyond that, so a jump in the column numbering (the seam of a
-// row-stacked operator) does not cost the whole operator its 16-bit column
-// offsets.  Returns the first row of every unit (plus n at the end), or an
-// empty vector when a row needs more than min(unit, kPackMaxLanes) lanes.
-static std::vector<int32_t> packed_units(const HostBSR &M, int K, int unit, const std::vector<int32_t> &lo,
-                                         const std::vector<int32_t> &hi, bool span16) {
-  std::vector<int32_t> w0;
-  const int maxl = std::min(unit, kPackMaxLanes);
-  int used = unit;
-  int32_t wlo = INT32_MAX, whi = -1;
-  for (int32_t r = 0; r < M.n; r++) {
-    const int64_t len = M.rp[r + 1] - M.rp[r];
-    const int64_t lr = std::max<int64_t>(1, (len + K - 1) / K);
-    if (lr > maxl) return {};
-    bool fresh = used + lr > unit;
-    if (!fresh && span16 && hi[r] >= 0 && whi >= 0)
-      fresh = (int64_t)std::max(whi, hi[r]) - std::min(wlo, lo[r]) > 65535;
-    if (fresh) {
-      w0.push_back(r);
-      used = 0;
-      wlo = INT32_MAX;
-      whi = -1;
-    }
-    used += (int)lr;
-    if (hi[r] >= 0) {
-      wlo = std::min(wlo, lo[r]);
-      whi = std::max(whi, hi[r]);
-    }
-  }
-  w0.push_back(M.n);
-  return w0;
-}
-
 // Padding entries (column -1 on entry) take the smallest real column of their
 // owner (slice or wavefront: entries [first[s]*64, first[s+1]*64)); returns the
 // per-owner bases when every owner spans at most 65,536 columns, else empty.
@@ -250,7 +210,6 @@ static void free_index(aspamg_ctx *h, Candidate &c) {
 }
 
 static Candidate packed_layout(aspamg_ctx *h, const HostBSR &M, int K, int unit, const std::vector<int32_t> &w0) {
-  const int kWaves = unit / 64;
   Sell<double> S;
   S.n = M.n;
   S.nc = M.nc;
@@ -259,45 +218,11 @@ static Candidate packed_layout(aspamg_ctx *h, const HostBSR &M, int K, int unit,
   S.lanes = 0;
   S.pack = K;
   S.unit = unit;
-  const int32_t nunits = (int32_t)w0.size() - 1;
-  S.nslices = nunits * kWaves;
+  S.nslices = ((int32_t)w0.size() - 1) * (unit / 64);
   S.ngroups = (int64_t)S.nslices * K;
-  std::vector<int32_t> col((size_t)S.ngroups * 64), map((size_t)S.ngroups * 64);
-  std::vector<uint16_t> meta((size_t)S.nslices * 64, 0);   // unused lanes: no row to write, offset 0
-#pragma omp parallel for schedule(dynamic, 64)
-  for (int32_t u = 0; u < nunits; u++) {
-    // lane e of unit u serves blocks j K .. j K + K - 1 of row lrow[e]
-    int32_t lrow[256], lj[256];
-    int e = 0;
-    for (int32_t r = w0[u]; r < w0[u + 1]; r++) {
-      const int64_t len = M.rp[r + 1] - M.rp[r];
-      const int lr = (int)std::max<int64_t>(1, (len + K - 1) / K);
-      for (int j = 0; j < lr; j++, e++) {
-        meta[(size_t)u * unit + e] = (uint16_t)(((j == 0 ? lr : 0) << 8) | (r - w0[u]));
-        lrow[e] = r;
-        lj[e] = j;
-      }
-    }
-    for (int f = e; f < unit; f++) {
-      lrow[f] = -1;
-      lj[f] = 0;
-    }
-    // slot group k of the unit's wavefront wv holds entry k of lanes 64 wv .. 64 wv + 63
-    for (int wv = 0; wv < kWaves; wv++)
-      for (int k = 0; k < K; k++) {
-        const size_t g = ((size_t)u * kWaves + wv) * K + k;
-        for (int f = 0; f < 64; f++) {
-          const int ln = wv * 64 + f;
-          int32_t src = -1;
-          if (lrow[ln] >= 0) {
-            const int64_t b = (int64_t)lj[ln] * K + k;
-            if (b < M.rp[lrow[ln] + 1] - M.rp[lrow[ln]]) src = (int32_t)(M.rp[lrow[ln]] + b);
-          }
-          map[g * 64 + f] = src;
-          col[g * 64 + f] = src >= 0 ? M.ci[src] : -1;
-        }
-      }
-  }
+  std::vector<int32_t> col, map;
+  std::vector<uint16_t> meta;
+  packed_slots(M.rp.data(), M.ci.data(), K, unit, w0, col, map, meta);
   const int64_t Kp = K;
   std::vector<int32_t> base = settle_columns(col, S.nslices, [Kp](int32_t s) { return (int64_t)s * Kp; });
   return upload_index(h, S, w0, col, base, map, meta);
@@ -455,7 +380,7 @@ static std::vector<Candidate> candidates(aspamg_ctx *h, const HostBSR &M, int fo
       // a scalar slot is one value: with fewer than kScalarMinPack per lane the
       // lane's share of a row is dominated by the in-row reduction
       if (M.b == 1 && ks[i] < kScalarMinPack) continue;
-      std::vector<int32_t> w0 = packed_units(M, ks[i], units[u], lo, hi, span16);
+      std::vector<int32_t> w0 = packed_units(M.rp.data(), M.n, ks[i], units[u], lo.data(), hi.data(), span16);
       if (w0.empty()) continue;
       Plan &q = all[u][i];
       q.K = ks[i];

@@ -9,14 +9,11 @@
 #include <vector>
 
 #include "aspamg.h"
+#include "layout_plan.h"
 
 namespace aspamg {
 
 constexpr int kSell = 64;           // rows per SELL slice = one wavefront
-// row-packed layout: rows are packed into units of one wavefront (64 lanes)
-// or of one 256-thread workgroup; a row's lane count is kept in 8 bits of the
-// lane metadata
-constexpr int kPackMaxLanes = 255;
 constexpr int64_t kMinThreads = 262144;  // lanes per row grow until n * L reaches this
 constexpr int64_t kTimedSlots = 1 << 20;  // layouts of larger operators are chosen by timing
 // q = K p: lanes per row of the fine-level FP64 copy and workgroup size (one
