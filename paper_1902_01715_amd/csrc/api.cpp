@@ -65,16 +65,8 @@ HostBSR transpose(const HostBSR &M) {
 
 // slot groups of the sliced layout with L lanes per row
 static std::vector<int32_t> sliced_ptr(const HostBSR &M, int L) {
-  const int rps = kSell / L;
-  const int32_t ns = (M.n + rps - 1) / rps;
-  std::vector<int32_t> sptr(ns + 1, 0);
-  for (int32_t s = 0; s < ns; s++) {
-    int64_t w = 0;
-    for (int32_t r = s * rps; r < std::min(M.n, (s + 1) * rps); r++)
-      w = std::max<int64_t>(w, (M.rp[r + 1] - M.rp[r] + L - 1) / L);
-    if ((int64_t)sptr[s] + w >= (int64_t)INT32_MAX / 64) fail(ASPAMG_EINVAL, "operator too large for the sliced layout");
-    sptr[s + 1] = sptr[s] + (int32_t)w;
-  }
+  std::vector<int32_t> sptr = sliced_ptr(M.rp.data(), M.n, L);
+  if (sptr.empty()) fail(ASPAMG_EINVAL, "operator too large for the sliced layout");
   return sptr;
 }
 
@@ -89,31 +81,6 @@ static void row_spans(const HostBSR &M, std::vector<int32_t> &lo, std::vector<in
       if (lo[r] < 0 || c < lo[r]) lo[r] = c;
       if (c > hi[r]) hi[r] = c;
     }
-}
-
-// Padding entries (column -1 on entry) take the smallest real column of their
-// owner (slice or wavefront: entries [first[s]*64, first[s+1]*64)); returns the
-// per-owner bases when every owner spans at most 65,536 columns, else empty.
-static std::vector<int32_t> settle_columns(std::vector<int32_t> &col, int32_t nowners,
-                                           const std::function<int64_t(int32_t)> &first) {
-  std::vector<int32_t> base(nowners, 0);
-  bool fits = true;
-#pragma omp parallel for schedule(static) reduction(&& : fits)
-  for (int32_t s = 0; s < nowners; s++) {
-    int32_t lo = INT32_MAX, hi = -1;
-    for (int64_t i = first(s) * 64; i < first(s + 1) * 64; i++)
-      if (col[i] >= 0) {
-        lo = std::min(lo, col[i]);
-        hi = std::max(hi, col[i]);
-      }
-    if (hi < 0) lo = hi = 0;
-    for (int64_t i = first(s) * 64; i < first(s + 1) * 64; i++)
-      if (col[i] < 0) col[i] = lo;
-    base[s] = lo;
-    fits = fits && hi - lo <= 65535;
-  }
-  if (!fits) base.clear();
-  return base;
 }
 
 // One candidate layout of an operator on the device: its index arrays (in a
@@ -264,23 +231,10 @@ static Candidate sliced_layout(aspamg_ctx *h, const HostBSR &M, int L, const std
   S.b = M.b;
   S.nnzb = M.nnzb();
   S.lanes = L;
-  const int rps = kSell / L;
   S.nslices = (int32_t)sptr.size() - 1;
   S.ngroups = sptr.back();
-  std::vector<int32_t> col((size_t)S.ngroups * 64), map((size_t)S.ngroups * 64);
-#pragma omp parallel for schedule(dynamic, 64)
-  for (int32_t s = 0; s < S.nslices; s++) {
-    for (int32_t g = sptr[s]; g < sptr[s + 1]; g++) {
-      for (int e = 0; e < kSell; e++) {
-        const int32_t r = s * rps + e / L;
-        const int64_t k = (int64_t)(g - sptr[s]) * L + e % L;
-        const int64_t len = r < M.n ? M.rp[r + 1] - M.rp[r] : 0;
-        const int32_t src = k < len ? (int32_t)(M.rp[r] + k) : -1;
-        map[(size_t)g * 64 + e] = src;
-        col[(size_t)g * 64 + e] = src >= 0 ? M.ci[src] : -1;
-      }
-    }
-  }
+  std::vector<int32_t> col, map;
+  sliced_slots(M.rp.data(), M.ci.data(), M.n, L, sptr, col, map);
   std::vector<int32_t> base = settle_columns(col, S.nslices, [&sptr](int32_t s) { return (int64_t)sptr[s]; });
   return upload_index(h, S, sptr, col, base, map, {});
 }

@@ -13,7 +13,6 @@
 
 namespace aspamg {
 
-constexpr int kSell = 64;           // rows per SELL slice = one wavefront
 constexpr int64_t kMinThreads = 262144;  // lanes per row grow until n * L reaches this
 constexpr int64_t kTimedSlots = 1 << 20;  // layouts of larger operators are chosen by timing
 // q = K p: lanes per row of the fine-level FP64 copy and workgroup size (one

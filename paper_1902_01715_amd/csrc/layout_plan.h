@@ -1,14 +1,88 @@
-// Host planning of the row-packed operator layout, free of device code: which
-// rows form each packing unit, and for every slot the source block and its
-// column, for every lane its row and lane count.  The device arrays are built
-// from these vectors (api.cpp); the kernel that reads them is k_pack_spmv.
+// Host planning of the two operator layouts, free of device code: for the
+// sliced layout the slot groups of every slice, for the row-packed layout
+// which rows form each packing unit and every lane's row and lane count; for
+// both, every slot's source block and column, and the per-owner column bases
+// of the 16-bit offsets.  The device arrays are built from these vectors
+// (api.cpp); the kernels that read them are k_sell_spmv and k_pack_spmv.
 #pragma once
 
 #include <algorithm>
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 namespace aspamg {
+
+constexpr int kSell = 64;           // rows per SELL slice = one wavefront
+
+// Slot-group pointers of the sliced layout with L lanes per row (L a power of
+// two, 1-64): slice s holds rows s*64/L .. (s+1)*64/L - 1 and as many slot
+// groups as its longest row needs (ceil(len / L)).  rp has n + 1 entries.
+// Returns the n_slices + 1 pointers, or an empty vector when the slot groups
+// would not fit int32 entry indices.
+inline std::vector<int32_t> sliced_ptr(const int64_t *rp, int32_t n, int L) {
+  const int rps = kSell / L;
+  const int32_t ns = (n + rps - 1) / rps;
+  std::vector<int32_t> sptr(ns + 1, 0);
+  for (int32_t s = 0; s < ns; s++) {
+    int64_t w = 0;
+    for (int32_t r = s * rps; r < std::min(n, (s + 1) * rps); r++) w = std::max<int64_t>(w, (rp[r + 1] - rp[r] + L - 1) / L);
+    if ((int64_t)sptr[s] + w >= (int64_t)INT32_MAX / 64) return {};
+    sptr[s + 1] = sptr[s] + (int32_t)w;
+  }
+  return sptr;
+}
+
+// The slots of the sliced layout: entry e of slot group g of slice s belongs
+// to row s*64/L + e/L and holds that row's block (g - sptr[s]) L + e % L.
+// map[slot] is the source block (index into ci, -1 for padding), col[slot]
+// its column (-1 for padding).  The vectors are resized here.
+inline void sliced_slots(const int64_t *rp, const int32_t *ci, int32_t n, int L, const std::vector<int32_t> &sptr,
+                         std::vector<int32_t> &col, std::vector<int32_t> &map) {
+  const int rps = kSell / L;
+  const int32_t nslices = (int32_t)sptr.size() - 1;
+  col.assign((size_t)sptr.back() * 64, -1);
+  map.assign((size_t)sptr.back() * 64, -1);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int32_t s = 0; s < nslices; s++) {
+    for (int32_t g = sptr[s]; g < sptr[s + 1]; g++) {
+      for (int e = 0; e < kSell; e++) {
+        const int32_t r = s * rps + e / L;
+        const int64_t k = (int64_t)(g - sptr[s]) * L + e % L;
+        const int64_t len = r < n ? rp[r + 1] - rp[r] : 0;
+        const int32_t src = k < len ? (int32_t)(rp[r] + k) : -1;
+        map[(size_t)g * 64 + e] = src;
+        col[(size_t)g * 64 + e] = src >= 0 ? ci[src] : -1;
+      }
+    }
+  }
+}
+
+// Padding entries (column -1 on entry) take the smallest real column of their
+// owner (slice or wavefront: entries [first(s)*64, first(s+1)*64)), 0 in an
+// owner without real entries; returns the per-owner bases (that smallest
+// column) when every owner spans at most 65,536 columns, else empty.
+inline std::vector<int32_t> settle_columns(std::vector<int32_t> &col, int32_t nowners,
+                                           const std::function<int64_t(int32_t)> &first) {
+  std::vector<int32_t> base(nowners, 0);
+  bool fits = true;
+#pragma omp parallel for schedule(static) reduction(&& : fits)
+  for (int32_t s = 0; s < nowners; s++) {
+    int32_t lo = INT32_MAX, hi = -1;
+    for (int64_t i = first(s) * 64; i < first(s + 1) * 64; i++)
+      if (col[i] >= 0) {
+        lo = std::min(lo, col[i]);
+        hi = std::max(hi, col[i]);
+      }
+    if (hi < 0) lo = hi = 0;
+    for (int64_t i = first(s) * 64; i < first(s + 1) * 64; i++)
+      if (col[i] < 0) col[i] = lo;
+    base[s] = lo;
+    fits = fits && hi - lo <= 65535;
+  }
+  if (!fits) base.clear();
+  return base;
+}
 
 // a row's lane count is kept in 8 bits of the lane metadata
 constexpr int kPackMaxLanes = 255;

@@ -33,3 +33,27 @@ int plan_packed(const int64_t *rp, const int32_t *ci, int32_t n, int K, int unit
   return (int)w0.size() - 1;
 }
 }
+
+extern "C" {
+
+// Plans the sliced layout with L lanes per row and settles its padding
+// columns.  Returns the number of slices, -1 when the slot groups overflow,
+// -2 when the caller's buffers are too small.  *nbase receives the number of
+// 16-bit column bases (0 when some slice spans more than 65,536 columns).
+int plan_sliced(const int64_t *rp, const int32_t *ci, int32_t n, int L, int32_t *sptr_out, int64_t sptr_cap,
+                int32_t *col_out, int32_t *map_out, int64_t slot_cap, int32_t *base_out, int32_t *nbase) {
+  std::vector<int32_t> sptr = aspamg::sliced_ptr(rp, n, L);
+  if (sptr.empty()) return -1;
+  std::vector<int32_t> col, map;
+  aspamg::sliced_slots(rp, ci, n, L, sptr, col, map);
+  const int32_t ns = (int32_t)sptr.size() - 1;
+  std::vector<int32_t> base = aspamg::settle_columns(col, ns, [&sptr](int32_t s) { return (int64_t)sptr[s]; });
+  if ((int64_t)sptr.size() > sptr_cap || (int64_t)col.size() > slot_cap) return -2;
+  std::memcpy(sptr_out, sptr.data(), sptr.size() * sizeof(int32_t));
+  std::memcpy(col_out, col.data(), col.size() * sizeof(int32_t));
+  std::memcpy(map_out, map.data(), map.size() * sizeof(int32_t));
+  std::memcpy(base_out, base.data(), base.size() * sizeof(int32_t));
+  *nbase = (int32_t)base.size();
+  return ns;
+}
+}

@@ -1,6 +1,8 @@
-"""The row-packed layout planner on the host (csrc/layout_plan.h, built here
-with g++ into a small test library; no GPU): the packing units, the per-slot
-source blocks and columns, and the per-lane metadata that k_pack_spmv reads.
+"""The layout planners on the host (csrc/layout_plan.h, built here with g++
+into a small test library; no GPU): for the row-packed layout the packing
+units, the per-slot source blocks and columns, and the per-lane metadata that
+k_pack_spmv reads; for the sliced layout the slot groups per slice, the slots
+and the settled padding columns with their 16-bit bases.
 
 Checked against the layout's definition on seeded random patterns: every
 stored block lands in exactly one slot and every slot of a lane belongs to
@@ -8,7 +10,10 @@ that lane's row; a lane serves K consecutive blocks of its row; the first
 lane of a row carries the row's lane count and every lane its row's offset in
 the unit; a unit's rows fit its lanes, and a unit is closed only when the
 next row does not fit (or would widen its columns beyond 16-bit offsets);
-rows needing more lanes than a unit or the 8-bit count holds are refused."""
+rows needing more lanes than a unit or the 8-bit count holds are refused.  A
+slice holds as many slot groups as its longest row needs, lane j of a row its
+blocks j, j + L, ...; padding takes its slice's smallest real column, and the
+bases are given only when every slice spans at most 65,536 columns."""
 import ctypes
 import os
 import subprocess
@@ -30,6 +35,8 @@ def planner(tmp_path_factory):
     lib.plan_packed.argtypes = [P, P, ctypes.c_int32, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int64,
                                 P, P, ctypes.c_int64, P, ctypes.c_int64]
     lib.plan_packed.restype = ctypes.c_int
+    lib.plan_sliced.argtypes = [P, P, ctypes.c_int32, ctypes.c_int, P, ctypes.c_int64, P, P, ctypes.c_int64, P, P]
+    lib.plan_sliced.restype = ctypes.c_int
 
     def plan(rp, ci, K, unit, span16):
         n = len(rp) - 1
@@ -47,6 +54,25 @@ def planner(tmp_path_factory):
         if nu < 0:
             return None
         return w0[:nu + 1], col[:nu * unit * K], mp[:nu * unit * K], meta[:nu * unit]
+
+    def sliced(rp, ci, L):
+        n = len(rp) - 1
+        ns_cap = n // (64 // L) + 2
+        lens = np.diff(rp)
+        slots = int(-(-lens // L).sum() * 64 + 64 * ns_cap) * (64 // L)
+        sptr = np.zeros(ns_cap + 1, np.int32)
+        col = np.zeros(slots, np.int32)
+        mp = np.zeros(slots, np.int32)
+        base = np.zeros(ns_cap, np.int32)
+        nb = ctypes.c_int32(0)
+        rp = np.ascontiguousarray(rp, np.int64)
+        ci = np.ascontiguousarray(ci, np.int32)
+        ns = lib.plan_sliced(rp.ctypes.data, ci.ctypes.data, n, L, sptr.ctypes.data, len(sptr), col.ctypes.data,
+                             mp.ctypes.data, len(col), base.ctypes.data, ctypes.byref(nb))
+        assert ns >= 0
+        g = sptr[ns]
+        return sptr[:ns + 1], col[:g * 64], mp[:g * 64], base[:nb.value]
+    plan.sliced = sliced
     return plan
 
 
@@ -172,3 +198,53 @@ def test_empty_rows_take_one_lane(planner):
     assert list(w0) == [0, 4]
     assert list(meta[:5] >> 8) == [1, 1, 1, 1, 0]
     _check(rp, ci, 2, 64, True, (w0, col, mp, meta))
+
+
+@pytest.mark.parametrize("L", [1, 2, 4, 8, 16, 32, 64])
+def test_sliced_plan_matches_its_definition(planner, L):
+    rng = np.random.default_rng(50 + L)
+    rp, ci = _pattern(rng, 333, 0, 90, 20000, 900)
+    sptr, col, mp, base = planner.sliced(rp, ci, L)
+    n, rps = len(rp) - 1, 64 // L
+    lens = np.diff(rp)
+    assert len(sptr) - 1 == -(-n // rps) and sptr[0] == 0
+    seen = np.zeros(len(ci), np.int64)
+    spans = []
+    for s in range(len(sptr) - 1):
+        rows = np.arange(s * rps, min(n, (s + 1) * rps))
+        assert sptr[s + 1] - sptr[s] == (-(-lens[rows] // L)).max()    # the longest row's groups
+        real = []
+        for g in range(sptr[s], sptr[s + 1]):
+            for e in range(64):
+                r, k = s * rps + e // L, (g - sptr[s]) * L + e % L
+                src, c = mp[g * 64 + e], col[g * 64 + e]
+                if r < n and k < lens[r]:
+                    assert src == rp[r] + k and c == ci[src]                # lane e % L of row r: blocks j, j + L, ...
+                    seen[src] += 1
+                    real.append(c)
+                else:
+                    assert src == -1
+        pad = [col[g * 64 + e] for g in range(sptr[s], sptr[s + 1]) for e in range(64)
+               if mp[g * 64 + e] < 0]
+        lo = min(real) if real else 0
+        assert all(c == lo for c in pad)                                # padding: the slice's smallest column
+        spans.append((lo, max(real) - lo if real else 0))
+    assert np.all(seen == 1)
+    if all(sp <= 65535 for _, sp in spans):
+        assert list(base) == [lo for lo, _ in spans]
+    else:
+        assert len(base) == 0
+
+
+def test_sliced_plan_wide_spans_drop_the_bases(planner):
+    # one slice's rows reach columns 0 and 70,000: no 16-bit offsets anywhere
+    rp = np.array([0, 2, 3, 4], np.int64)
+    ci = np.array([0, 70000, 5, 6], np.int32)
+    sptr, col, mp, base = planner.sliced(rp, ci, 1)
+    assert len(base) == 0 and list(sptr) == [0, 2]
+    ci = np.array([100, 65635, 100, 101], np.int32)                     # span exactly 65,535: fits
+    sptr, col, mp, base = planner.sliced(rp, ci, 1)
+    assert list(base) == [100]
+    # padding slots of rows 1 and 2 (one block each) and of the absent rows
+    # take the slice's smallest column
+    assert col[64 + 1] == 100 and col[64 + 2] == 100 and col[3] == 100 and col[64 + 63] == 100
